@@ -1,0 +1,313 @@
+"""CPU oracle for warm-start APSP -- TEST INFRASTRUCTURE ONLY.
+
+Only `tests/`, `__graft_entry__.smoke()` and the benchmark's `cpu_baseline`
+leg may import this module.  It shares no code with the HIP library and never
+imports it.  Every routine here computes a *plain definition* from the paper,
+slowly and visibly:
+
+* ``fw`` / ``dijkstra_rows`` -- the cold APSP matrix (paper, Section 1;
+  notation table: SPD with SPD(i,i) = 0 and the matrix M_G) by textbook
+  Floyd-Warshall and dense Dijkstra, in C (``apsp_oracle.c``).
+* ``brute_force_apsp`` / ``all_shortest_simple_paths`` -- enumeration of
+  simple paths, straight from the definition of a path (the notation table's
+  loop-free sequence Psi and the set Theta of all i->j paths); tiny n only.
+* ``remove_mask`` -- the need_update_list of a node removal (Section 2.2,
+  built with Theorem "theorem_spd_4" / Corollary "corollary3"): pair (i,j)
+  is listed when M[i][k] + M[k][j] equals M[i][j].
+* ``remove_cost`` -- Definition "def:cost_defi": Phi / (N - 1).
+* ``edge_mask`` -- the same criterion applied to an edge (u,v): the pairs
+  whose shortest distance can use the edge (see DESIGN for this reading).
+* ``canonical_path`` -- the lexicographically smallest shortest simple path,
+  taken greedily among Algorithm 7's candidates (correct when w >= 1).
+* ``apply_update`` -- the updated graph G' of the notation table (G + p,
+  G - G_k, or one edge re-weighted), as a plain adjacency edit.
+
+All distances are int32 with INF = 2**30 and saturating sums computed in
+int64 then clamped (the same value as the uint32 form of the C routines).
+Matrices are in "compact" order: position a holds the a-th live id in
+ascending order.
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import os
+import subprocess
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+INF = 1 << 30
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "apsp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (OpenMP).  Portable x86-64-v2 code so the
+    library built here also runs on another host."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-shared",
+                               "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        i32, p = ctypes.c_int32, ctypes.c_void_p
+        lib.oracle_fw_init.argtypes = [i32, p, p]
+        lib.oracle_fw_pivots.argtypes = [i32, p, i32, i32, ctypes.c_int]
+        lib.oracle_dijkstra_rows.argtypes = [i32, p, p, i32, p, ctypes.c_int]
+        lib.oracle_max_threads.argtypes = []
+        for f in (lib.oracle_fw_init, lib.oracle_fw_pivots, lib.oracle_dijkstra_rows,
+                  lib.oracle_max_threads):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check_adj(A: np.ndarray) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.int32)
+    assert A.ndim == 2 and A.shape[0] == A.shape[1]
+    return A
+
+
+def oplus(a, b):
+    """Saturating concatenation a (+) b = min(a + b, INF) on int arrays."""
+    return np.minimum(np.asarray(a, dtype=np.int64) + np.asarray(b, dtype=np.int64), INF)
+
+
+# ---------------------------------------------------------------------------
+# cold APSP
+# ---------------------------------------------------------------------------
+
+def fw_init(A: np.ndarray) -> np.ndarray:
+    A = _check_adj(A)
+    n = A.shape[0]
+    D = np.empty_like(A)
+    if _load().oracle_fw_init(n, _ptr(A), _ptr(D)) != 0:
+        raise ValueError("adjacency weights must lie in [0, INF]")
+    return D
+
+
+def fw_pivots(D: np.ndarray, k0: int, k1: int, threads: int = 0) -> None:
+    """Apply Floyd-Warshall pivots k0..k1-1 to D in place."""
+    assert D.flags.c_contiguous and D.dtype == np.int32
+    if _load().oracle_fw_pivots(D.shape[0], _ptr(D), k0, k1, threads) != 0:
+        raise ValueError("bad pivot range")
+
+
+def fw(A: np.ndarray, threads: int = 0) -> np.ndarray:
+    """Cold APSP by textbook Floyd-Warshall."""
+    D = fw_init(A)
+    fw_pivots(D, 0, D.shape[0], threads)
+    return D
+
+
+def dijkstra_rows(A: np.ndarray, srcs: Sequence[int], threads: int = 0) -> np.ndarray:
+    """Rows srcs of the APSP matrix, one dense Dijkstra per source."""
+    A = _check_adj(A)
+    s = np.ascontiguousarray(np.asarray(srcs, dtype=np.int32).reshape(-1))
+    out = np.empty((s.size, A.shape[0]), dtype=np.int32)
+    if _load().oracle_dijkstra_rows(A.shape[0], _ptr(A), _ptr(s), s.size, _ptr(out), threads) != 0:
+        raise ValueError("bad source")
+    return out
+
+
+def dijkstra_cols(A: np.ndarray, dsts: Sequence[int], threads: int = 0) -> np.ndarray:
+    """Columns dsts of the APSP matrix (Dijkstra on the reversed graph);
+    result[r][i] = SPD(i, dsts[r])."""
+    return dijkstra_rows(np.ascontiguousarray(np.asarray(A).T), dsts, threads)
+
+
+# ---------------------------------------------------------------------------
+# brute force (n <= 8): the definition of a path, enumerated
+# ---------------------------------------------------------------------------
+
+def _simple_paths(A: np.ndarray, i: int, j: int):
+    """Every simple path i -> j over present edges, with its length."""
+    n = A.shape[0]
+    if i == j:
+        yield (i,), 0
+        return
+    others = [t for t in range(n) if t != i and t != j]
+    for r in range(len(others) + 1):
+        for mid in itertools.permutations(others, r):
+            seq = (i,) + mid + (j,)
+            total = 0
+            ok = True
+            for a, b in zip(seq[:-1], seq[1:]):
+                w = int(A[a, b])
+                if w >= INF:
+                    ok = False
+                    break
+                total += w
+            if ok:
+                yield seq, min(total, INF)
+
+
+def brute_force_apsp(A: np.ndarray) -> np.ndarray:
+    """SPD(i,j) = min over all simple i->j paths of the summed weight (INF if
+    none), SPD(i,i) = 0."""
+    A = _check_adj(A)
+    n = A.shape[0]
+    assert n <= 8, "brute force is for tiny graphs"
+    D = np.full((n, n), INF, dtype=np.int64)
+    for i in range(n):
+        for j in range(n):
+            for _, L in _simple_paths(A, i, j):
+                D[i, j] = min(D[i, j], L)
+    return D.astype(np.int32)
+
+
+def all_shortest_simple_paths(A: np.ndarray, i: int, j: int) -> List[Tuple[int, ...]]:
+    """All simple i->j paths of minimum length, lexicographically sorted."""
+    A = _check_adj(A)
+    paths = list(_simple_paths(A, i, j))
+    if not paths:
+        return []
+    best = min(L for _, L in paths)
+    if best >= INF:
+        return []
+    return sorted(p for p, L in paths if L == best)
+
+
+# ---------------------------------------------------------------------------
+# masks, cost, query
+# ---------------------------------------------------------------------------
+
+def remove_mask(D: np.ndarray, k: int) -> np.ndarray:
+    """need_update_list of removing compact node k, as a boolean matrix:
+    F[i][j] is True when i != j, k not in {i, j}, D[i][j] < INF and
+    D[i][k] (+) D[k][j] == D[i][j]  (equality form of Corollary 'corollary3';
+    for distances '>=' and '==' coincide)."""
+    D = np.asarray(D, dtype=np.int64)
+    n = D.shape[0]
+    F = (oplus(D[:, k][:, None], D[k, :][None, :]) == D) & (D < INF)
+    F[np.arange(n), np.arange(n)] = False
+    F[k, :] = False
+    F[:, k] = False
+    return F
+
+
+def remove_cost(F: np.ndarray, n_before: int) -> Tuple[int, float]:
+    """Definition 'def:cost_defi': Phi = number of non-empty need_update_list
+    rows, Cost = Phi / (N - 1) with N the node count before the removal."""
+    phi = int(np.count_nonzero(F.any(axis=1)))
+    cost = 0.0 if n_before <= 1 else phi / (n_before - 1)
+    return phi, cost
+
+
+def edge_mask(D: np.ndarray, u: int, v: int, w_old: int, undirected: bool) -> np.ndarray:
+    """Pairs whose shortest distance can use edge u->v of weight w_old:
+    i != j, D[i][j] < INF and D[i][u] (+) w_old (+) D[v][j] == D[i][j]; for an
+    undirected graph also the v->u direction."""
+    D = np.asarray(D, dtype=np.int64)
+    n = D.shape[0]
+    F = oplus(oplus(D[:, u][:, None], w_old), D[v, :][None, :]) == D
+    if undirected:
+        F |= oplus(oplus(D[:, v][:, None], w_old), D[u, :][None, :]) == D
+    F &= D < INF
+    F[np.arange(n), np.arange(n)] = False
+    return F
+
+
+def edge_scope(col_u, col_v, row_u, row_v, w: int) -> Tuple[int, int]:
+    """|R| and |C| of edge u->v with weight w, from column u, column v, row u and
+    row v of the APSP matrix: R = {i: D[i][u] (+) w == D[i][v] < INF},
+    C = {j: w (+) D[v][j] == D[u][j] < INF}.  |R|*|C| bounds the number of pairs
+    whose shortest path the edge can carry."""
+    col_u, col_v = np.asarray(col_u, np.int64), np.asarray(col_v, np.int64)
+    row_u, row_v = np.asarray(row_u, np.int64), np.asarray(row_v, np.int64)
+    R = int(np.count_nonzero((oplus(col_u, w) == col_v) & (col_v < INF)))
+    C = int(np.count_nonzero((oplus(w, row_v) == row_u) & (row_u < INF)))
+    return R, C
+
+
+def canonical_path(A: np.ndarray, D: np.ndarray, i: int, j: int) -> List[int]:
+    """Lexicographically smallest shortest simple i->j path (compact indices).
+
+    Candidates are Algorithm 7's: t with D[i][t] (+) D[t][j] == D[i][j]
+    (Theorem 'al_correct': they contain every shortest path).  From cur, the
+    next node is the smallest b != cur with A[cur][b] < INF and
+    A[cur][b] (+) D[b][j] == D[cur][j].  With w >= 1 each step lowers
+    D[.][j], so the walk is simple and ends at j.  Returns [] if unreachable.
+    """
+    A = np.asarray(A, dtype=np.int64)
+    D = np.asarray(D, dtype=np.int64)
+    if i == j:
+        return [i]
+    if D[i, j] >= INF:
+        return []
+    n = D.shape[0]
+    cand = [t for t in range(n) if t in (i, j) or oplus(D[i, t], D[t, j]) == D[i, j]]
+    path = [i]
+    cur = i
+    while cur != j:
+        nxt = None
+        for b in cand:  # ascending
+            if b == cur or A[cur, b] >= INF:
+                continue
+            if oplus(A[cur, b], D[b, j]) == D[cur, j]:
+                nxt = b
+                break
+        if nxt is None or len(path) > n:
+            raise RuntimeError("no canonical successor (zero-weight cycle?)")
+        path.append(nxt)
+        cur = nxt
+    return path
+
+
+# ---------------------------------------------------------------------------
+# the updated graph G'
+# ---------------------------------------------------------------------------
+
+def apply_update(A: np.ndarray, ids: List[int], kind: str, *, u: int = -1, v: int = -1,
+                 w: int = 0, w_out=None, w_in=None, undirected: bool = False):
+    """Return (A', ids') for one update, in compact ascending-id order.
+
+    add:      G + p -- p gets id max(ids)+1 (or 0), appended last; row p is
+              w_out, column p is w_in (w_in = w_out if undirected).
+    remove:   G - G_k -- row and column of id u deleted.
+    edge:     (kinds 'decrease' / 'increase' / 'edge') weight of u->v set to
+              w (and v->u if undirected).
+    """
+    A = np.asarray(A, dtype=np.int32)
+    n = A.shape[0]
+    if kind == "add":
+        w_out = np.asarray(w_out, dtype=np.int32).reshape(n)
+        w_in = w_out if (w_in is None or undirected) else np.asarray(w_in, dtype=np.int32).reshape(n)
+        B = np.empty((n + 1, n + 1), dtype=np.int32)
+        B[:n, :n] = A
+        B[n, :n] = w_out
+        B[:n, n] = w_in
+        B[n, n] = 0
+        return B, list(ids) + [(max(ids) + 1) if ids else 0]
+    if kind == "remove":
+        a = ids.index(u)
+        keep = [x for x in range(n) if x != a]
+        return np.ascontiguousarray(A[np.ix_(keep, keep)]), [x for x in ids if x != u]
+    if kind in ("decrease", "increase", "edge"):
+        a, b = ids.index(u), ids.index(v)
+        B = A.copy()
+        B[a, b] = w
+        if undirected:
+            B[b, a] = w
+        return B, list(ids)
+    raise ValueError(kind)

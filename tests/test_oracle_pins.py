@@ -1,0 +1,330 @@
+"""Pins of the CPU oracle to things other than itself.
+
+Each test checks the oracle against what the paper or the mathematics fixes:
+brute-force enumeration of simple paths, an external library (scipy's
+Floyd-Warshall), the Bellman optimality equations (unique solution for
+positive weights), the paper's add-node theorems rebuilt in plain loops, and
+the paper's printed worked example.  A plausible slip in the oracle (dropped
+term, swapped index, wrong comparison) fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2412_15122_amd import workloads as W
+
+INF = O.INF
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_graph(rng, n, wmax, *, undirected=False, density=1.0, zero=0.0):
+    return W.random_graph(n, 1, wmax, undirected=undirected, density=density,
+                          seed=int(rng.integers(1 << 31)), zero_frac=zero)
+
+
+# ---------------------------------------------------------------------------
+# cold APSP: three independent routes agree
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 7])
+@pytest.mark.parametrize("undirected", [False, True])
+def test_fw_equals_brute_force(n, undirected):
+    rng = np.random.default_rng(100 + n + 10 * undirected)
+    for trial in range(6):
+        density = [1.0, 0.6, 0.3][trial % 3]
+        wmax = [3, 20, 1000][trial % 3]            # [1,3] forces heavy ties
+        zero = 0.2 if trial == 4 else 0.0           # zero-weight edges are allowed
+        A = rand_graph(rng, n, wmax, undirected=undirected, density=density, zero=zero)
+        assert np.array_equal(O.fw(A), O.brute_force_apsp(A))
+
+
+@pytest.mark.parametrize("n", [2, 17, 64, 150])
+def test_fw_equals_scipy(n):
+    from scipy.sparse.csgraph import floyd_warshall
+    rng = np.random.default_rng(7 + n)
+    for density in (1.0, 0.4, 0.05):
+        A = rand_graph(rng, n, 50, density=density)
+        Af = np.where(A >= INF, np.inf, A.astype(np.float64))
+        np.fill_diagonal(Af, 0.0)
+        ref = floyd_warshall(Af, directed=True)
+        ref = np.where(np.isinf(ref), INF, ref).astype(np.int64)
+        assert np.array_equal(O.fw(A).astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("threads", [1, 3])
+def test_dijkstra_rows_equal_fw(threads):
+    rng = np.random.default_rng(3)
+    for n, density in ((1, 1.0), (40, 0.3), (200, 1.0), (257, 0.9)):
+        A = rand_graph(rng, n, 100, density=density)
+        D = O.fw(A, threads=threads)
+        srcs = np.arange(n)
+        assert np.array_equal(O.dijkstra_rows(A, srcs, threads=threads), D)
+        assert np.array_equal(O.dijkstra_cols(A, srcs, threads=threads), D.T)
+
+
+def test_fw_pivot_ranges_compose():
+    rng = np.random.default_rng(4)
+    A = rand_graph(rng, 90, 30, density=0.5)
+    D = O.fw_init(A)
+    for k0 in range(0, 90, 17):
+        O.fw_pivots(D, k0, min(90, k0 + 17), threads=2)
+    assert np.array_equal(D, O.fw(A))
+
+
+def test_fw_rejects_out_of_range_weights():
+    A = np.zeros((3, 3), dtype=np.int32)
+    A[0, 1] = -1
+    with pytest.raises(ValueError):
+        O.fw(A)
+    A[0, 1] = INF + 1
+    with pytest.raises(ValueError):
+        O.fw(A)
+
+
+def bfs_reachable(A):
+    n = A.shape[0]
+    R = np.zeros((n, n), dtype=bool)
+    for s in range(n):
+        seen = {s}
+        stack = [s]
+        while stack:
+            x = stack.pop()
+            for y in range(n):
+                if A[x, y] < INF and y not in seen:
+                    seen.add(y)
+                    stack.append(y)
+        R[s, list(seen)] = True
+    return R
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_fw_invariants_bellman_unique(undirected):
+    """With w >= 1 the Bellman equations D[i][i] = 0,
+    D[i][j] = min_t A[i][t] (+) D[t][j] have exactly one solution (the APSP
+    matrix), so checking them pins every entry.  Reachability comes from an
+    independent graph search."""
+    rng = np.random.default_rng(11)
+    for n, density, wmax in ((60, 1.0, 10), (80, 0.1, 1000), (45, 0.03, 5)):
+        A = rand_graph(rng, n, wmax, undirected=undirected, density=density)
+        D = O.fw(A).astype(np.int64)
+        A64 = A.astype(np.int64)
+        assert np.all(np.diag(D) == 0)
+        off = ~np.eye(n, dtype=bool)
+        assert np.all(D[off] <= A64[off])
+        # triangle inequality
+        for k in range(n):
+            assert np.all(D <= O.oplus(D[:, k][:, None], D[k, :][None, :]))
+        # Bellman optimality (first hop)
+        best = np.full((n, n), INF, dtype=np.int64)
+        for t in range(n):
+            best = np.minimum(best, O.oplus(A64[:, t][:, None], D[t, :][None, :]))
+        assert np.array_equal(D[off], best[off])
+        assert np.array_equal(D < INF, bfs_reachable(A))
+        if undirected:
+            assert np.array_equal(D, D.T)
+
+
+# ---------------------------------------------------------------------------
+# the paper's add-node theorems, written out, reproduce the oracle
+# ---------------------------------------------------------------------------
+
+def apsp_by_repeated_add(A):
+    """Cold APSP by adding nodes one at a time (the recursion the paper's
+    Algorithm 1 rests on): the new row by Theorem 'theorem2', the new column
+    by Theorem 'theo_2_back', old pairs by Theorem 'theorem3'.  Plain loops,
+    no shared code with the oracle."""
+    n = A.shape[0]
+    M = [[0]]
+    for m in range(1, n):
+        out = []
+        for r in range(m):      # SPD(new, r) = min_t d(new, t) + SPD(t, r)
+            out.append(min(min(int(A[m, t]) + M[t][r] for t in range(m)), INF))
+        inn = []
+        for r in range(m):      # SPD(r, new) = min_t SPD(r, t) + d(t, new)
+            inn.append(min(min(M[r][t] + int(A[t, m]) for t in range(m)), INF))
+        for i in range(m):      # SPD'(i, j) = min(SPD(i, j), t1 + t2)
+            for j in range(m):
+                M[i][j] = min(M[i][j], inn[i] + out[j])
+        for i in range(m):
+            M[i].append(inn[i])
+        M.append(out + [0])
+    return np.array(M, dtype=np.int64).reshape(n, n) if n else np.zeros((0, 0), np.int64)
+
+
+@pytest.mark.parametrize("n", [1, 2, 9, 33])
+def test_repeated_add_node_equals_fw(n):
+    rng = np.random.default_rng(21 + n)
+    for density in (1.0, 0.3):
+        A = rand_graph(rng, n, 40, density=density)
+        assert np.array_equal(apsp_by_repeated_add(A), O.fw(A).astype(np.int64))
+
+
+# ---------------------------------------------------------------------------
+# the paper's worked example (printed need_update_lists)
+# ---------------------------------------------------------------------------
+
+def load_fixture():
+    with open(os.path.join(GOLDEN, "paper_remove_example.json")) as f:
+        fx = json.load(f)
+    names = fx["nodes"]
+    idx = {c: i for i, c in enumerate(names)}
+    n = len(names)
+    A = np.full((n, n), INF, dtype=np.int32)
+    np.fill_diagonal(A, 0)
+    for a, b, w in fx["undirected_edges"]:
+        A[idx[a], idx[b]] = A[idx[b], idx[a]] = w
+    return fx, names, idx, A
+
+
+def test_paper_worked_example_need_update_lists():
+    fx, names, idx, A = load_fixture()
+    D = O.fw(A)
+    for removed, exp in fx["remove"].items():
+        k = idx[removed]
+        F = O.remove_mask(D, k)
+        got = {names[i]: [[names[i], names[j]] for j in range(len(names)) if F[i, j]]
+               for i in range(len(names)) if i != k}
+        assert got == exp["need_update_list"]
+        A2, ids2 = O.apply_update(A, list(range(4)), "remove", u=k, undirected=True)
+        D2 = O.fw(A2)
+        pos = {i: p for p, i in enumerate(ids2)}
+        for a, b in exp["equal"]:
+            assert D[idx[a], idx[b]] == D2[pos[idx[a]], pos[idx[b]]]
+        for a, b in exp["not_equal"]:
+            assert D[idx[a], idx[b]] != D2[pos[idx[a]], pos[idx[b]]]
+
+
+def test_paper_worked_example_cost():
+    fx, names, idx, A = load_fixture()
+    D = O.fw(A)
+    assert O.remove_cost(O.remove_mask(D, idx["C"]), 4) == (0, 0.0)
+    assert O.remove_cost(O.remove_mask(D, idx["B"]), 4) == (3, 1.0)
+
+
+# ---------------------------------------------------------------------------
+# masks: exact contents by brute force, soundness by cold recompute
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_remove_mask_is_node_on_some_shortest_path(undirected):
+    """For w >= 1, D[i][k] + D[k][j] == D[i][j] exactly when k lies on some
+    shortest simple i->j path (enumerated)."""
+    rng = np.random.default_rng(31)
+    for trial in range(8):
+        n = 6
+        A = rand_graph(rng, n, [2, 9][trial % 2], undirected=undirected,
+                       density=[1.0, 0.5][trial % 2 == 1 and trial > 3])
+        D = O.fw(A)
+        for k in range(n):
+            F = O.remove_mask(D, k)
+            for i in range(n):
+                for j in range(n):
+                    on = (i != j and k not in (i, j) and
+                          any(k in p for p in O.all_shortest_simple_paths(A, i, j)))
+                    assert F[i, j] == on, (trial, k, i, j)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_edge_mask_is_edge_on_some_shortest_path(undirected):
+    rng = np.random.default_rng(41)
+    for trial in range(8):
+        n = 6
+        A = rand_graph(rng, n, [2, 9][trial % 2], undirected=undirected)
+        D = O.fw(A)
+        for u in range(n):
+            for v in range(n):
+                if u == v:
+                    continue
+                F = O.edge_mask(D, u, v, int(A[u, v]), undirected)
+                for i in range(n):
+                    for j in range(n):
+                        on = False
+                        if i != j:
+                            for p in O.all_shortest_simple_paths(A, i, j):
+                                hops = list(zip(p[:-1], p[1:]))
+                                if (u, v) in hops or (undirected and (v, u) in hops):
+                                    on = True
+                        assert F[i, j] == on, (trial, u, v, i, j)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_masks_cover_every_changed_pair(undirected):
+    """Corollary 'corollary3' (soundness): pairs outside the mask keep their
+    distance.  Checked against a cold recompute, with ties and zero weights."""
+    rng = np.random.default_rng(51)
+    for trial in range(12):
+        n = int(rng.integers(2, 40))
+        A = rand_graph(rng, n, [3, 50][trial % 2], undirected=undirected,
+                       density=[1.0, 0.4][trial % 3 == 0], zero=0.1 if trial % 4 == 1 else 0.0)
+        D = O.fw(A)
+        ids = list(range(n))
+        k = int(rng.integers(n))
+        F = O.remove_mask(D, k)
+        A2, ids2 = O.apply_update(A, ids, "remove", u=k, undirected=undirected)
+        D2 = O.fw(A2)
+        keep = [x for x in range(n) if x != k]
+        changed = D[np.ix_(keep, keep)] != D2
+        assert not np.any(changed & ~F[np.ix_(keep, keep)])
+        u, v = rng.choice(n, size=2, replace=False)
+        if A[u, v] < INF:
+            w_new = int(A[u, v]) + int(rng.integers(1, 100))
+            Fe = O.edge_mask(D, u, v, int(A[u, v]), undirected)
+            A3, _ = O.apply_update(A, ids, "increase", u=u, v=v, w=w_new, undirected=undirected)
+            assert not np.any((O.fw(A3) != D) & ~Fe)
+
+
+# ---------------------------------------------------------------------------
+# query
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_canonical_path_is_lexicographic_minimum(undirected):
+    rng = np.random.default_rng(61)
+    for trial in range(10):
+        n = int(rng.integers(1, 8))
+        A = rand_graph(rng, n, [2, 30][trial % 2], undirected=undirected,
+                       density=[1.0, 0.5][trial % 3 == 0])
+        D = O.fw(A)
+        for i in range(n):
+            for j in range(n):
+                paths = O.all_shortest_simple_paths(A, i, j)
+                got = O.canonical_path(A, D, i, j)
+                if not paths:
+                    assert got == [] and D[i, j] == INF
+                else:
+                    assert tuple(got) == paths[0]
+
+
+def test_edge_scope_counts():
+    rng = np.random.default_rng(71)
+    A = rand_graph(rng, 30, 5, undirected=True)
+    D = O.fw(A)
+    for (u, v) in ((0, 1), (3, 7), (10, 2)):
+        w = int(A[u, v])
+        R, C = O.edge_scope(D[:, u], D[:, v], D[u, :], D[v, :], w)
+        assert R == sum(1 for i in range(30) if min(D[i, u] + w, INF) == D[i, v] < INF)
+        assert C == sum(1 for j in range(30) if min(w + D[v, j], INF) == D[u, j] < INF)
+        # |F_e| never exceeds |R| * |C| in either direction
+        Fe = O.edge_mask(D, u, v, w, False)
+        assert Fe.sum() <= R * C
+
+
+# ---------------------------------------------------------------------------
+# the updated graph G'
+# ---------------------------------------------------------------------------
+
+def test_apply_update_semantics():
+    A = np.array([[0, 5, INF], [2, 0, 7], [1, INF, 0]], dtype=np.int32)
+    ids = [0, 4, 9]
+    B, ids2 = O.apply_update(A, ids, "add", w_out=[3, 4, 5], w_in=[6, 7, 8])
+    assert ids2 == [0, 4, 9, 10]
+    assert B[3, :3].tolist() == [3, 4, 5] and B[:3, 3].tolist() == [6, 7, 8] and B[3, 3] == 0
+    C, ids3 = O.apply_update(B, ids2, "remove", u=4)
+    assert ids3 == [0, 9, 10]
+    assert C.tolist() == [[0, INF, 6], [1, 0, 8], [3, 5, 0]]
+    E, _ = O.apply_update(C, ids3, "decrease", u=9, v=0, w=0, undirected=True)
+    assert E[1, 0] == 0 and E[0, 1] == 0
+    assert O.apply_update(np.zeros((0, 0), np.int32), [], "add", w_out=[], w_in=[])[1] == [0]
