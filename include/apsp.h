@@ -1,0 +1,239 @@
+/*
+ * apsp.h -- C ABI of the warm-start all-pairs shortest-path library (gfx950).
+ *
+ * The library keeps the APSP matrix of a dense weighted graph resident on
+ * one GPU and updates it exactly after a minor change, following the paper
+ * "Solving the all pairs shortest path problem after minor update of a
+ * large dense graph" (Liu, arXiv 2412.15122):
+ *
+ *   apsp_cold          cold APSP (Floyd-Warshall; Section 1)
+ *   apsp_add_node      G + p   (Theorems theorem2, theo_2_back, theorem3 and
+ *                               Corollaries corollary1, corollary2; Sec. 2.1)
+ *   apsp_remove_node   G - G_k (need_update_list by Theorem theorem_spd_4 /
+ *                               Corollary corollary3, then recompute of the
+ *                               listed pairs; Section 2.2, Algorithm 5)
+ *   apsp_update_edge   one edge raised or lowered (Section 2.3, Algorithm 6;
+ *                               done directly, see each call)
+ *   apsp_query         warm single-pair shortest path (Section 3, Alg. 7)
+ *
+ * Values.  Weights and distances are int32 in [0, APSP_INF]; APSP_INF
+ * (2^30) means "no edge" / "unreachable".  Path lengths saturate at
+ * APSP_INF.  The diagonal of an adjacency matrix is ignored and taken as 0.
+ * Every result is bit-exact: it equals the cold APSP matrix of the updated
+ * graph.
+ *
+ * Ids.  A graph created with n nodes has ids 0..n-1.  apsp_add_node gives
+ * the new node id max_id + 1 (the paper appends node N + 1); a removed id is
+ * never reused.  Vectors indexed by node and matrices read back are in
+ * ascending-id order (the paper's index order).
+ *
+ * Memory.  The caller owns all device memory: one buffer of
+ * apsp_required_bytes(capacity, kind) bytes, 256-byte aligned, passed to
+ * apsp_cold and kept alive until apsp_graph_destroy.  The library carves
+ * the distance matrix, the adjacency (and its transpose for directed
+ * graphs), an index of light in-edges and its workspace out of it; it never
+ * allocates or frees device memory itself.  Pointers whose name ends in
+ * _dev are device pointers; all others are host pointers.
+ *
+ * Streams.  Every call enqueues on the graph's HIP stream (given to
+ * apsp_cold, changeable with apsp_set_stream) and returns without waiting,
+ * except the calls documented as synchronous.
+ *
+ * Errors.  Calls return an apsp_status; nothing is thrown across the ABI.
+ * Arguments are checked before anything is enqueued, so a call that returns
+ * an error leaves the graph unchanged.  Values that live in device memory
+ * (adjacency entries, weight vectors) are checked on the device: an entry
+ * outside [0, APSP_INF] is treated as an absent edge and the graph records
+ * a sticky error that apsp_sync returns (once) as APSP_E_VALUE.  APSP_E_DEVICE means a HIP
+ * call failed and the device state is undefined; rebuild with apsp_cold.
+ * apsp_last_error() gives a message for the last failing call on the
+ * calling thread.
+ *
+ * Threads.  A graph handle must not be used by two threads at once.
+ */
+#ifndef APSP_H
+#define APSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define APSP_INF 1073741824
+#define APSP_ABI_VERSION 1
+/* Largest capacity (node slots) of one graph. */
+#define APSP_MAX_CAPACITY 38912
+
+typedef enum {
+    APSP_OK = 0,
+    APSP_E_INVALID = -1,   /* bad argument; nothing enqueued */
+    APSP_E_NOT_FOUND = -2, /* id is not live */
+    APSP_E_CAPACITY = -3,  /* no free slot, buffer too small, or output too short */
+    APSP_E_DEVICE = -5,    /* HIP failure; device state undefined */
+    APSP_E_VALUE = -7      /* sticky: a device-resident weight was out of range */
+} apsp_status;
+
+typedef enum { APSP_DIRECTED = 0, APSP_UNDIRECTED = 1 } apsp_kind;
+
+/* What apsp_remove_node and an edge increase do after building the mask
+ * (Algorithm 5 switches to Floyd-Warshall when Cost exceeds delta). */
+typedef enum {
+    APSP_FALLBACK_NEVER = 0,  /* always recompute the masked pairs (default) */
+    APSP_FALLBACK_COST = 1,   /* Algorithm 5: cold FW on G' when Cost > delta;
+                                 the decision reads Phi back (synchronous) */
+    APSP_FALLBACK_ALWAYS = 2  /* always cold FW on G' */
+} apsp_fallback;
+
+typedef struct apsp_graph apsp_graph;
+
+/* Per-update statistics of the last update (apsp_last_stats). */
+typedef struct {
+    int64_t flagged;     /* |F|: pairs in the need_update mask */
+    int32_t rows;        /* Phi: rows with at least one flagged pair */
+    int32_t n_before;    /* live node count before the update */
+    double cost;         /* Definition def:cost_defi: Phi / (N - 1) */
+    int32_t kind;        /* 0 none, 1 add, 2 remove, 3 decrease, 4 increase */
+    int32_t noop;        /* 1 when D provably did not change (O(1) path) */
+    int32_t fallback;    /* 1 when cold Floyd-Warshall ran instead */
+    int32_t full_scans;  /* in-edge scans that went past the light-edge index */
+    int32_t sweeps;      /* largest number of relaxation sweeps of one row */
+    int32_t rows_relaxed;/* rows touched by an add-node / decrease relaxation */
+} apsp_update_stats;
+
+/* ---- sizing ------------------------------------------------------------ */
+
+/* Bytes of device memory a graph of `capacity` node slots needs.
+ * Returns 0 for an invalid capacity or kind.  Host only. */
+size_t apsp_required_bytes(int32_t capacity, int32_t kind);
+
+/* ---- construction ------------------------------------------------------ */
+
+/* Cold start: build a graph from the n x n adjacency matrix adj_dev
+ * (row-major, leading dimension adj_ld >= n, row i = edges out of node i)
+ * and compute its APSP matrix by blocked Floyd-Warshall.
+ *   kind       APSP_DIRECTED or APSP_UNDIRECTED (adjacency must be
+ *              symmetric; asymmetric pairs take the smaller weight and set
+ *              the sticky error)
+ *   capacity   node slots, n <= capacity <= APSP_MAX_CAPACITY, >= 1
+ *   dev_buf    caller-owned device buffer of dev_buf_bytes >=
+ *              apsp_required_bytes(capacity, kind), 256-byte aligned
+ *   hip_stream hipStream_t to enqueue on (NULL = default stream)
+ *   out        receives the handle (host memory owned by the library)
+ * n = 0 gives an empty graph.  adj_dev is only read during the call's
+ * kernels; it may be freed after the stream has passed them. */
+apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t kind,
+                      int32_t capacity, void *dev_buf, size_t dev_buf_bytes,
+                      void *hip_stream, apsp_graph **out);
+
+/* Recompute D from the current adjacency by cold Floyd-Warshall (the
+ * fallback of Algorithm 5, and recovery).  Asynchronous. */
+apsp_status apsp_recompute_cold(apsp_graph *g);
+
+/* Release the handle.  Does not touch the caller's device buffer.  Waits
+ * for the graph's stream. */
+apsp_status apsp_graph_destroy(apsp_graph *g);
+
+/* ---- updates (asynchronous) ---------------------------------------------- */
+
+/* Add node p (paper: G + p, Section 2.1).  w_out_dev[t] is the weight of
+ * p -> t and w_in_dev[t] the weight of t -> p, for the t-th live node in
+ * ascending-id order (length = live count before the call).  For an
+ * undirected graph w_in_dev may be NULL (it equals w_out_dev).  New row:
+ * SPD(p, r) = min_t d(p,t) + SPD(t,r) (Corollary corollary1); new column:
+ * SPD(r, p) = min_t SPD(r,t) + d(t,p) (Corollary corollary2); old pairs:
+ * min(SPD(i,j), SPD(i,p) + SPD(p,j)) (Theorem theorem3).  *new_id (host)
+ * receives max_id + 1.  Returns APSP_E_CAPACITY when every slot is used. */
+apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t *w_in_dev,
+                          int32_t *new_id);
+
+/* Remove node `id` (paper: G - G_k, Section 2.2, Algorithm 5).  Pairs (i,j)
+ * with D[i][k] + D[k][j] == D[i][j] form the need_update mask (Corollary
+ * corollary3: all others keep their distance); the masked pairs are
+ * recomputed exactly on G - G_k, or cold Floyd-Warshall runs, per the
+ * fallback policy.  The id is retired. */
+apsp_status apsp_remove_node(apsp_graph *g, int32_t id);
+
+/* Set the weight of edge u -> v (and v -> u for an undirected graph) to w,
+ * 0 <= w <= APSP_INF (APSP_INF deletes the edge).  u != v, both live.
+ * The paper (Algorithm 6) removes one endpoint and adds it back; this call
+ * gets the same D directly: a decrease below D[u][v] relaxes every pair
+ * through the new edge (Theorem theorem3 with a relay node on the edge), an
+ * increase of an edge with D[u][v] == w_old recomputes the pairs whose
+ * shortest distance can use it (Corollary corollary3 applied to that relay
+ * node); any other change leaves D as it is.  The choice is made on the
+ * device: the call never waits. */
+apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w);
+
+/* ---- queries (synchronous) ------------------------------------------------ */
+
+/* Shortest path from i to j (Algorithm 7, Section 3): *dist = D[i][j]; the
+ * path is the lexicographically smallest shortest simple path over ids,
+ * found among Algorithm 7's candidates {t : D[i][t] + D[t][j] == D[i][j]}
+ * (Theorem al_correct).  With zero-weight edges any shortest simple path
+ * may be returned.  path_ids (host, path_cap entries) receives the ids from
+ * i to j; *path_len its length (1 when i == j, 0 when unreachable, in which
+ * case *dist = APSP_INF).  If path_cap < *path_len, returns
+ * APSP_E_CAPACITY with *dist and *path_len set.  path_ids may be NULL when
+ * path_cap is 0. */
+apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
+                       int32_t *path_ids, int32_t path_cap, int32_t *path_len);
+
+/* Copy the live distance matrix (ascending-id order) into out_dev
+ * (n x n, leading dimension out_ld >= n).  Asynchronous. */
+apsp_status apsp_read_matrix(apsp_graph *g, int32_t *out_dev, int64_t out_ld);
+
+/* Same for the adjacency matrix (diagonal 0). */
+apsp_status apsp_read_adjacency(apsp_graph *g, int32_t *out_dev, int64_t out_ld);
+
+/* Live node count (host bookkeeping; never waits). */
+apsp_status apsp_node_count(const apsp_graph *g, int32_t *n);
+
+/* Live ids in ascending order into ids (host, cap entries); *n receives the
+ * count.  APSP_E_CAPACITY when cap is too small (with *n set). */
+apsp_status apsp_node_ids(const apsp_graph *g, int32_t *ids, int32_t cap, int32_t *n);
+
+/* |R| and |C| of edge u -> v at its current weight w: R = {i : D[i][u] + w
+ * == D[i][v] < INF}, C = {j : w + D[v][j] == D[u][j] < INF}.  |R| * |C|
+ * bounds how many pairs route through the edge.  Synchronous. */
+apsp_status apsp_edge_scope(apsp_graph *g, int32_t u, int32_t v, int32_t *r_count,
+                            int32_t *c_count);
+
+/* Statistics of the last update.  Synchronous. */
+apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out);
+
+/* ---- control --------------------------------------------------------------- */
+
+/* Wait for the graph's stream; returns the sticky device error if any
+ * (and clears it). */
+apsp_status apsp_sync(apsp_graph *g);
+
+apsp_status apsp_set_stream(apsp_graph *g, void *hip_stream);
+
+/* Fallback policy of removals and edge increases; delta is Algorithm 5's
+ * threshold on Cost (used by APSP_FALLBACK_COST). */
+apsp_status apsp_set_fallback(apsp_graph *g, int32_t policy, double delta);
+
+/* Use only the first `limit` entries (1..64) of each node's light in-edge
+ * index; entries beyond it are treated as unindexed.  Results do not
+ * change; a small limit exercises the exhaustive-scan path.  Default 64. */
+apsp_status apsp_set_index_limit(apsp_graph *g, int32_t limit);
+
+/* Per-kernel timing with HIP events on the graph's stream.  kernel_mask has
+ * bit k set for every kernel id k (0..apsp_kernel_count()-1) to time; -1
+ * times all, 0 stops.  The call waits for the stream and clears the totals.
+ * apsp_profile_read waits for the stream and returns, for kernel `kernel`,
+ * the number of timed launches and their summed duration in ms. */
+apsp_status apsp_profile(apsp_graph *g, int64_t kernel_mask);
+apsp_status apsp_profile_read(apsp_graph *g, int32_t kernel, int64_t *launches, double *total_ms);
+int32_t apsp_kernel_count(void);
+const char *apsp_kernel_name(int32_t kernel);
+
+const char *apsp_last_error(void);
+int32_t apsp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APSP_H */

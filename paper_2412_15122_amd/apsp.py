@@ -1,0 +1,188 @@
+"""Python face of the HIP library: a device-resident graph with its APSP matrix.
+
+Every method marshals arguments and calls the C ABI (include/apsp.h); all
+arithmetic runs in the library's gfx950 kernels.  torch supplies the device
+buffer and the stream only.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _native as N
+
+INF = N.APSP_INF
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _device_int32(x):
+    """A contiguous int32 CUDA tensor holding x (numpy, list or tensor)."""
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        t = x
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.int32)))
+    return t.to(device="cuda", dtype=torch.int32).contiguous()
+
+
+class Graph:
+    """A dense weighted graph whose APSP matrix lives on the GPU.
+
+    Graph(adj, undirected=False, capacity=None) runs the cold start
+    (apsp_cold).  `adj` is an n x n int32 matrix (numpy or torch), absent
+    edges APSP_INF, diagonal ignored.  Ids are 0..n-1; added nodes get
+    max_id + 1.
+    """
+
+    def __init__(self, adj, *, undirected: bool = False, capacity: Optional[int] = None):
+        torch = _torch()
+        self._lib = N.load()
+        A = _device_int32(adj)
+        if A.dim() != 2 or A.shape[0] != A.shape[1]:
+            raise ValueError("adjacency must be square")
+        n = int(A.shape[0])
+        cap = int(capacity if capacity is not None else max(n, 1))
+        self.kind = N.APSP_UNDIRECTED if undirected else N.APSP_DIRECTED
+        self.undirected = bool(undirected)
+        nbytes = int(self._lib.apsp_required_bytes(cap, self.kind))
+        if nbytes == 0:
+            raise ValueError(f"invalid capacity {cap}")
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._buf.data_ptr()
+        self._ptr = (base + 255) & ~255
+        self._nbytes = nbytes
+        self.capacity = cap
+        self._stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = self._lib.apsp_cold(A.data_ptr() if n else None, n, A.stride(0) if n else 0, self.kind, cap,
+                                 self._ptr, nbytes, self._stream.cuda_stream, ctypes.byref(h))
+        N.check(st, "apsp_cold")
+        self._h = h
+        self._keep = []
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.apsp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- updates --------------------------------------------------------------
+    def add_node(self, w_out, w_in=None) -> int:
+        """Add a node; w_out[t] / w_in[t] are the weights to / from the t-th
+        live node in ascending-id order.  Returns the new id."""
+        n = self.num_nodes()
+        wo = _device_int32(w_out).reshape(-1) if n else None
+        wi = None
+        if n and not self.undirected:
+            if w_in is None:
+                raise ValueError("w_in is required for a directed graph")
+            wi = _device_int32(w_in).reshape(-1)
+        if n and (wo.numel() != n or (wi is not None and wi.numel() != n)):
+            raise ValueError(f"weight vectors must have {n} entries")
+        return self.add_node_device(wo.data_ptr() if n else None, wi.data_ptr() if wi is not None else None)
+
+    def add_node_device(self, w_out_ptr, w_in_ptr) -> int:
+        """add_node with device pointers (length = live count)."""
+        nid = ctypes.c_int32()
+        N.check(self._lib.apsp_add_node(self._h, w_out_ptr, w_in_ptr, ctypes.byref(nid)), "apsp_add_node")
+        return int(nid.value)
+
+    def remove_node(self, node_id: int) -> None:
+        N.check(self._lib.apsp_remove_node(self._h, int(node_id)), "apsp_remove_node")
+
+    def update_edge(self, u: int, v: int, w: int) -> None:
+        N.check(self._lib.apsp_update_edge(self._h, int(u), int(v), int(w)), "apsp_update_edge")
+
+    def recompute_cold(self) -> None:
+        N.check(self._lib.apsp_recompute_cold(self._h), "apsp_recompute_cold")
+
+    # -- reads ------------------------------------------------------------------
+    def num_nodes(self) -> int:
+        n = ctypes.c_int32()
+        N.check(self._lib.apsp_node_count(self._h, ctypes.byref(n)), "apsp_node_count")
+        return int(n.value)
+
+    def ids(self) -> List[int]:
+        n = self.num_nodes()
+        buf = (ctypes.c_int32 * max(n, 1))()
+        cnt = ctypes.c_int32()
+        N.check(self._lib.apsp_node_ids(self._h, buf, n, ctypes.byref(cnt)), "apsp_node_ids")
+        return list(buf[: cnt.value])
+
+    def matrix_device(self, which: str = "D"):
+        torch = _torch()
+        n = self.num_nodes()
+        out = torch.empty((n, n), dtype=torch.int32, device="cuda")
+        fn = self._lib.apsp_read_matrix if which == "D" else self._lib.apsp_read_adjacency
+        N.check(fn(self._h, out.data_ptr() if n else None, max(n, 1)), "apsp_read")
+        return out
+
+    def matrix(self) -> np.ndarray:
+        """Distance matrix in ascending-id order (host copy)."""
+        return self.matrix_device("D").cpu().numpy()
+
+    def adjacency(self) -> np.ndarray:
+        return self.matrix_device("A").cpu().numpy()
+
+    def query(self, i: int, j: int) -> Tuple[int, List[int]]:
+        """(distance, shortest path as ids) from i to j."""
+        cap = self.num_nodes()
+        buf = (ctypes.c_int32 * max(cap, 1))()
+        dist = ctypes.c_int32()
+        ln = ctypes.c_int32()
+        N.check(self._lib.apsp_query(self._h, int(i), int(j), ctypes.byref(dist), buf, cap, ctypes.byref(ln)),
+                "apsp_query")
+        return int(dist.value), list(buf[: ln.value])
+
+    def edge_scope(self, u: int, v: int) -> Tuple[int, int]:
+        r = ctypes.c_int32()
+        c = ctypes.c_int32()
+        N.check(self._lib.apsp_edge_scope(self._h, int(u), int(v), ctypes.byref(r), ctypes.byref(c)),
+                "apsp_edge_scope")
+        return int(r.value), int(c.value)
+
+    def stats(self) -> dict:
+        s = N.UpdateStats()
+        N.check(self._lib.apsp_last_stats(self._h, ctypes.byref(s)), "apsp_last_stats")
+        return s.as_dict()
+
+    # -- control ----------------------------------------------------------------
+    def sync(self) -> None:
+        N.check(self._lib.apsp_sync(self._h), "apsp_sync")
+
+    def set_fallback(self, policy: int, delta: float = 0.5) -> None:
+        N.check(self._lib.apsp_set_fallback(self._h, int(policy), float(delta)), "apsp_set_fallback")
+
+    def set_index_limit(self, limit: int) -> None:
+        N.check(self._lib.apsp_set_index_limit(self._h, int(limit)), "apsp_set_index_limit")
+
+    def profile(self, mask: int) -> None:
+        N.check(self._lib.apsp_profile(self._h, int(mask)), "apsp_profile")
+
+    def profile_read(self, kernel: int) -> Tuple[int, float]:
+        c = ctypes.c_int64()
+        ms = ctypes.c_double()
+        N.check(self._lib.apsp_profile_read(self._h, int(kernel), ctypes.byref(c), ctypes.byref(ms)),
+                "apsp_profile_read")
+        return int(c.value), float(ms.value)
+
+
+def kernel_names() -> List[str]:
+    lib = N.load()
+    return [lib.apsp_kernel_name(k).decode() for k in range(lib.apsp_kernel_count())]
+
+
+def kernel_id(name: str) -> int:
+    return kernel_names().index(name)

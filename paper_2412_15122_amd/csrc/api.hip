@@ -1,0 +1,681 @@
+// Host side of the C ABI: argument checks, the id <-> slot map, buffer
+// carving, and the order in which each update enqueues its kernels.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <set>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "apsp_internal.h"
+
+using namespace apsp;
+
+namespace {
+
+thread_local std::string g_err;
+
+apsp_status fail(apsp_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int32_t padded(int32_t cap) { return ((cap + TILE - 1) / TILE) * TILE; }
+
+struct Layout {
+    size_t D, A, AT, nin, nin_cnt, nin_beta, id_of_slot, vec, plist, rank_a, rank_b, qbuf, qscratch, fscratch,
+        ctl, total;
+};
+
+constexpr int NVEC = 8;  // wo, wi, out, in, colu, colv, rowu, rowv
+
+Layout make_layout(int32_t cap, int32_t kind) {
+    Layout L{};
+    const size_t P = (size_t)padded(cap);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t mat = P * P * sizeof(int32_t);
+    L.D = take(mat);
+    L.A = take(mat);
+    L.AT = kind == APSP_DIRECTED ? take(mat) : (size_t)-1;
+    L.nin = take(P * NIN_L * sizeof(int2));
+    L.nin_cnt = take(P * 4);
+    L.nin_beta = take(P * 4);
+    L.id_of_slot = take(P * 4);
+    L.vec = take((size_t)NVEC * P * 4);
+    L.plist = take(NIN_L * sizeof(int2) + 256);
+    L.rank_a = take(P * 4);
+    L.rank_b = take(P * 4);
+    L.qbuf = take((P + 8) * 4);
+    L.qscratch = take(4 * P * 4);
+    L.fscratch = take((size_t)FUSED_GRID * 2 * P * 4);
+    L.ctl = take(sizeof(Ctl));
+    L.total = off;
+    return L;
+}
+
+enum UpdateKind { UK_NONE = 0, UK_ADD = 1, UK_REMOVE = 2, UK_DECREASE = 3, UK_INCREASE = 4 };
+
+struct ProfImpl {
+    hipStream_t stream = nullptr;
+    int64_t mask = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec {
+        int32_t kid;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    int32_t cur_kid = -1;
+    hipEvent_t cur_a = nullptr;
+    int64_t count[KID_COUNT] = {};
+    double ms[KID_COUNT] = {};
+
+    hipEvent_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void collect() {
+        for (auto &r : recs) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                count[r.kid] += 1;
+                ms[r.kid] += t;
+            }
+        }
+        recs.clear();
+        used = 0;
+    }
+    ~ProfImpl() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+namespace apsp {
+void Prof::begin(int32_t kid) {
+    auto *p = static_cast<ProfImpl *>(impl);
+    if (!on || !p || !((p->mask >> kid) & 1)) {
+        if (p) p->cur_kid = -1;
+        return;
+    }
+    hipEvent_t e = p->take();
+    if (!e) return;
+    (void)hipEventRecord(e, p->stream);
+    p->cur_kid = kid;
+    p->cur_a = e;
+}
+void Prof::end() {
+    auto *p = static_cast<ProfImpl *>(impl);
+    if (!on || !p || p->cur_kid < 0) return;
+    hipEvent_t e = p->take();
+    if (!e) return;
+    (void)hipEventRecord(e, p->stream);
+    p->recs.push_back({p->cur_kid, p->cur_a, e});
+    p->cur_kid = -1;
+}
+}  // namespace apsp
+
+struct apsp_graph {
+    int32_t cap = 0, P = 0, kind = 0;
+    hipStream_t stream = nullptr;
+    char *base = nullptr;
+    DevGraph dg{};
+    int32_t *vec[NVEC] = {};
+    int2 *plist = nullptr;
+    int32_t *plist_cnt = nullptr, *plist_beta = nullptr;
+    int32_t *rank_cur = nullptr, *rank_other = nullptr;
+    int32_t *qbuf = nullptr, *qscratch = nullptr, *fscratch = nullptr;
+    // host bookkeeping
+    int32_t n_live = 0, max_id = -1;
+    std::vector<int32_t> live_ids;  // ascending
+    std::unordered_map<int32_t, int32_t> slot_of_id;
+    std::set<int32_t> free_slots;
+    int32_t policy = APSP_FALLBACK_NEVER;
+    double delta = 0.5;
+    int32_t last_kind = UK_NONE, last_n_before = 0, last_fallback = 0;
+    Ctl *ctl_h = nullptr;   // pinned
+    int32_t *qbuf_h = nullptr;  // pinned
+    ProfImpl prof_impl;
+    Prof prof;
+};
+
+namespace {
+
+bool hip_ok(hipError_t e, const char *what) {
+    if (e == hipSuccess) return true;
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+}
+
+apsp_status check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(APSP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return APSP_OK;
+}
+
+int32_t *&wo(apsp_graph *g) { return g->vec[0]; }
+int32_t *&wi(apsp_graph *g) { return g->vec[1]; }
+int32_t *&vout(apsp_graph *g) { return g->vec[2]; }
+int32_t *&vin(apsp_graph *g) { return g->vec[3]; }
+int32_t *&colu(apsp_graph *g) { return g->vec[4]; }
+int32_t *&colv(apsp_graph *g) { return g->vec[5]; }
+int32_t *&rowu(apsp_graph *g) { return g->vec[6]; }
+int32_t *&rowv(apsp_graph *g) { return g->vec[7]; }
+
+int32_t rank_of(const apsp_graph *g, int32_t id) {
+    auto it = std::lower_bound(g->live_ids.begin(), g->live_ids.end(), id);
+    if (it == g->live_ids.end() || *it != id) return -1;
+    return (int32_t)(it - g->live_ids.begin());
+}
+
+bool lookup(const apsp_graph *g, int32_t id, int32_t *slot) {
+    auto it = g->slot_of_id.find(id);
+    if (it == g->slot_of_id.end()) return false;
+    *slot = it->second;
+    return true;
+}
+
+apsp_status read_ctl(apsp_graph *g) {
+    if (!hip_ok(hipMemcpyAsync(g->ctl_h, g->dg.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream), "read ctl"))
+        return APSP_E_DEVICE;
+    if (!hip_ok(hipStreamSynchronize(g->stream), "stream sync")) return APSP_E_DEVICE;
+    return APSP_OK;
+}
+
+apsp_status set_count_only(apsp_graph *g, int32_t v) {
+    launch_fill(&g->dg.ctl->count_only, 1, v, g->stream);
+    return check_launch("count_only");
+}
+
+// D := cold Floyd-Warshall of the current adjacency over the used slots.
+apsp_status run_cold(apsp_graph *g) {
+    const int32_t n = g->dg.n_slots;
+    g->prof.begin(KID_MISC);
+    launch_copy_square(g->dg.D, g->dg.A, g->dg.ld, n, g->stream);
+    g->prof.end();
+    launch_fw(g->dg, n, g->stream, &g->prof);
+    return check_launch("cold Floyd-Warshall");
+}
+
+// Algorithm 5's decision for the pending mask (rows/flags counted on the
+// device): returns 1 when cold Floyd-Warshall should run.
+apsp_status decide_fallback(apsp_graph *g, const FusedArgs &fa, int32_t n_before, int32_t *fallback) {
+    *fallback = 0;
+    if (g->policy == APSP_FALLBACK_ALWAYS) {
+        *fallback = 1;
+        return APSP_OK;
+    }
+    if (g->policy != APSP_FALLBACK_COST) return APSP_OK;
+    apsp_status st = set_count_only(g, 1);
+    if (st) return st;
+    launch_fused(g->dg, fa, g->stream);
+    if ((st = check_launch("mask count"))) return st;
+    if ((st = set_count_only(g, 0))) return st;
+    if ((st = read_ctl(g))) return st;
+    const double cost = n_before > 1 ? (double)g->ctl_h->rows / (double)(n_before - 1) : 0.0;
+    *fallback = cost > g->delta;
+    return APSP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int32_t apsp_abi_version(void) { return APSP_ABI_VERSION; }
+
+const char *apsp_last_error(void) { return g_err.c_str(); }
+
+int32_t apsp_kernel_count(void) { return KID_COUNT; }
+
+const char *apsp_kernel_name(int32_t k) {
+    static const char *names[KID_COUNT] = {
+        "fw_pivot", "fw_panel", "fw_tiles", "nin_build", "nin_update", "add_out", "add_in", "add_relax",
+        "add_place", "gather", "mask_recompute", "tombstone", "edge_begin", "dec_relax", "query", "misc"};
+    if (k < 0 || k >= KID_COUNT) return "";
+    return names[k];
+}
+
+size_t apsp_required_bytes(int32_t capacity, int32_t kind) {
+    if (capacity < 1 || capacity > APSP_MAX_CAPACITY) return 0;
+    if (kind != APSP_DIRECTED && kind != APSP_UNDIRECTED) return 0;
+    return make_layout(capacity, kind).total;
+}
+
+apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t kind, int32_t capacity,
+                      void *dev_buf, size_t dev_buf_bytes, void *hip_stream, apsp_graph **out) {
+    if (!out) return fail(APSP_E_INVALID, "apsp_cold: out is NULL");
+    *out = nullptr;
+    if (kind != APSP_DIRECTED && kind != APSP_UNDIRECTED) return fail(APSP_E_INVALID, "apsp_cold: bad kind");
+    if (capacity < 1 || capacity > APSP_MAX_CAPACITY)
+        return fail(APSP_E_INVALID, "apsp_cold: capacity must be in [1, APSP_MAX_CAPACITY]");
+    if (n < 0 || n > capacity) return fail(APSP_E_INVALID, "apsp_cold: n must be in [0, capacity]");
+    if (n > 0 && (!adj_dev || adj_ld < n)) return fail(APSP_E_INVALID, "apsp_cold: bad adjacency pointer or ld");
+    if (!dev_buf) return fail(APSP_E_INVALID, "apsp_cold: dev_buf is NULL");
+    if (((uintptr_t)dev_buf & 255) != 0) return fail(APSP_E_INVALID, "apsp_cold: dev_buf not 256-byte aligned");
+    const Layout L = make_layout(capacity, kind);
+    if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, "apsp_cold: dev_buf smaller than apsp_required_bytes");
+
+    apsp_graph *g = new (std::nothrow) apsp_graph();
+    if (!g) return fail(APSP_E_INVALID, "apsp_cold: out of host memory");
+    g->cap = capacity;
+    g->P = padded(capacity);
+    g->kind = kind;
+    g->stream = (hipStream_t)hip_stream;
+    g->base = (char *)dev_buf;
+    if (!hip_ok(hipHostMalloc((void **)&g->ctl_h, sizeof(Ctl), 0), "pinned alloc") ||
+        !hip_ok(hipHostMalloc((void **)&g->qbuf_h, (size_t)(g->P + 8) * 4, 0), "pinned alloc")) {
+        apsp_graph_destroy(g);
+        return APSP_E_DEVICE;
+    }
+    char *b = g->base;
+    DevGraph &d = g->dg;
+    d.D = (int32_t *)(b + L.D);
+    d.A = (int32_t *)(b + L.A);
+    d.AT = kind == APSP_DIRECTED ? (int32_t *)(b + L.AT) : nullptr;
+    d.nin = (int2 *)(b + L.nin);
+    d.nin_cnt = (int32_t *)(b + L.nin_cnt);
+    d.nin_beta = (int32_t *)(b + L.nin_beta);
+    d.id_of_slot = (int32_t *)(b + L.id_of_slot);
+    d.ctl = (Ctl *)(b + L.ctl);
+    d.ld = g->P;
+    d.P = g->P;
+    d.n_slots = 0;
+    d.undirected = kind == APSP_UNDIRECTED;
+    d.lim = NIN_L;
+    for (int v = 0; v < NVEC; ++v) g->vec[v] = (int32_t *)(b + L.vec) + (size_t)v * g->P;
+    g->plist = (int2 *)(b + L.plist);
+    g->plist_cnt = (int32_t *)(b + L.plist + NIN_L * sizeof(int2));
+    g->plist_beta = g->plist_cnt + 1;
+    g->rank_cur = (int32_t *)(b + L.rank_a);
+    g->rank_other = (int32_t *)(b + L.rank_b);
+    g->qbuf = (int32_t *)(b + L.qbuf);
+    g->qscratch = (int32_t *)(b + L.qscratch);
+    g->fscratch = (int32_t *)(b + L.fscratch);
+    g->prof_impl.stream = g->stream;
+    g->prof.impl = &g->prof_impl;
+
+    configure_kernels();
+    hipStream_t s = g->stream;
+    const int64_t PP = (int64_t)g->P * g->P;
+    launch_fill(d.D, PP, (int32_t)INF, s);
+    launch_fill(d.A, PP, (int32_t)INF, s);
+    if (d.AT) launch_fill(d.AT, PP, (int32_t)INF, s);
+    launch_fill(d.id_of_slot, g->P, -1, s);
+    launch_fill(d.nin_cnt, g->P, 0, s);
+    launch_fill(d.nin_beta, g->P, (int32_t)INF, s);
+    launch_fill((int32_t *)d.ctl, sizeof(Ctl) / 4, 0, s);
+    launch_load_adj(d, adj_dev, adj_ld, n, s);
+    if (d.AT) launch_transpose(d.A, d.AT, d.ld, n, s);
+    d.n_slots = n;
+    launch_iota(d.id_of_slot, n, s);
+    launch_iota(g->rank_cur, n, s);
+    apsp_status st = run_cold(g);
+    if (st) {
+        apsp_graph_destroy(g);
+        return st;
+    }
+    launch_nin_build(d, 0, n, 0, s);
+    if ((st = check_launch("index build"))) {
+        apsp_graph_destroy(g);
+        return st;
+    }
+    g->n_live = n;
+    g->max_id = n - 1;
+    g->live_ids.resize(n);
+    for (int32_t i = 0; i < n; ++i) {
+        g->live_ids[i] = i;
+        g->slot_of_id[i] = i;
+    }
+    *out = g;
+    return APSP_OK;
+}
+
+apsp_status apsp_recompute_cold(apsp_graph *g) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_recompute_cold: NULL graph");
+    return run_cold(g);
+}
+
+apsp_status apsp_graph_destroy(apsp_graph *g) {
+    if (!g) return APSP_OK;
+    (void)hipStreamSynchronize(g->stream);
+    if (g->ctl_h) (void)hipHostFree(g->ctl_h);
+    if (g->qbuf_h) (void)hipHostFree(g->qbuf_h);
+    delete g;
+    return APSP_OK;
+}
+
+apsp_status apsp_set_stream(apsp_graph *g, void *hip_stream) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_set_stream: NULL graph");
+    g->stream = (hipStream_t)hip_stream;
+    g->prof_impl.stream = g->stream;
+    return APSP_OK;
+}
+
+apsp_status apsp_set_fallback(apsp_graph *g, int32_t policy, double delta) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_set_fallback: NULL graph");
+    if (policy < APSP_FALLBACK_NEVER || policy > APSP_FALLBACK_ALWAYS)
+        return fail(APSP_E_INVALID, "apsp_set_fallback: bad policy");
+    if (!(delta >= 0.0)) return fail(APSP_E_INVALID, "apsp_set_fallback: delta must be >= 0");
+    g->policy = policy;
+    g->delta = delta;
+    return APSP_OK;
+}
+
+apsp_status apsp_set_index_limit(apsp_graph *g, int32_t limit) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_set_index_limit: NULL graph");
+    if (limit < 1 || limit > NIN_L) return fail(APSP_E_INVALID, "apsp_set_index_limit: limit must be in [1, 64]");
+    g->dg.lim = limit;
+    return APSP_OK;
+}
+
+apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t *w_in_dev, int32_t *new_id) {
+    if (!g || !new_id) return fail(APSP_E_INVALID, "apsp_add_node: NULL argument");
+    const bool und = g->kind == APSP_UNDIRECTED;
+    if (g->n_live > 0 && (!w_out_dev || (!und && !w_in_dev)))
+        return fail(APSP_E_INVALID, "apsp_add_node: weight vector is NULL");
+    int32_t p;
+    if (!g->free_slots.empty()) p = *g->free_slots.begin();
+    else if (g->dg.n_slots < g->cap) p = g->dg.n_slots;
+    else return fail(APSP_E_CAPACITY, "apsp_add_node: every slot is in use");
+    const int32_t nid = g->max_id + 1;
+    hipStream_t s = g->stream;
+    DevGraph &d = g->dg;
+    const int32_t n_before = g->n_live;
+    d.n_slots = std::max(d.n_slots, p + 1);
+    launch_reset_stats(d, s);
+    launch_scatter_weights(d, w_out_dev, w_in_dev, g->rank_cur, n_before, wo(g), und ? wo(g) : wi(g), s);
+    int32_t *wi_s = und ? wo(g) : wi(g);
+    int2 *pin = d.nin + (int64_t)p * NIN_L;
+    g->prof.begin(KID_NIN_BUILD);
+    launch_select_vec(wi_s, d.n_slots, p, pin, d.nin_cnt + p, d.nin_beta + p, s);
+    if (!und) launch_select_vec(wo(g), d.n_slots, p, g->plist, g->plist_cnt, g->plist_beta, s);
+    g->prof.end();
+    const int2 *ol = und ? pin : g->plist;
+    const int32_t *oc = und ? d.nin_cnt + p : g->plist_cnt;
+    const int32_t *ob = und ? d.nin_beta + p : g->plist_beta;
+    g->prof.begin(KID_ADD_OUT);
+    launch_add_out(d, ol, oc, ob, wo(g), vout(g), s);
+    g->prof.end();
+    int32_t *in = vout(g);
+    if (!und) {
+        g->prof.begin(KID_ADD_IN);
+        launch_add_in(d, p, wi_s, vin(g), s);
+        g->prof.end();
+        in = vin(g);
+    }
+    g->prof.begin(KID_ADD_RELAX);
+    launch_add_relax(d, in, vout(g), s);
+    g->prof.end();
+    g->prof.begin(KID_ADD_PLACE);
+    launch_add_place(d, p, nid, n_before, g->rank_cur, in, vout(g), wo(g), wi_s, s);
+    g->prof.end();
+    g->prof.begin(KID_NIN_UPDATE);
+    launch_nin_insert_node(d, p, wo(g), s);
+    g->prof.end();
+    apsp_status st = check_launch("apsp_add_node");
+    if (st) return st;
+    g->free_slots.erase(p);
+    g->max_id = nid;
+    g->live_ids.push_back(nid);
+    g->slot_of_id[nid] = p;
+    g->n_live += 1;
+    g->last_kind = UK_ADD;
+    g->last_n_before = n_before;
+    g->last_fallback = 0;
+    *new_id = nid;
+    return APSP_OK;
+}
+
+apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_remove_node: NULL graph");
+    int32_t k;
+    if (!lookup(g, id, &k)) return fail(APSP_E_NOT_FOUND, "apsp_remove_node: id is not live");
+    const int32_t r = rank_of(g, id);
+    hipStream_t s = g->stream;
+    DevGraph &d = g->dg;
+    const int32_t n_before = g->n_live;
+    launch_reset_stats(d, s);
+    g->prof.begin(KID_GATHER);
+    launch_gather_rc(d, k, k, colu(g), nullptr, rowu(g), nullptr, 0, s);
+    g->prof.end();
+    FusedArgs fa{};
+    fa.mode = FUSED_REMOVE;
+    fa.k = k;
+    fa.col1 = colu(g);
+    fa.row1 = rowu(g);
+    fa.scratch = g->fscratch;
+    int32_t fallback = 0;
+    apsp_status st = decide_fallback(g, fa, n_before, &fallback);
+    if (st) return st;
+    // a cost pass counted the mask already; the recompute counts it again
+    if (!fallback && g->policy == APSP_FALLBACK_COST) launch_reset_stats(d, s);
+    if (!fallback) {
+        g->prof.begin(KID_FUSED);
+        launch_fused(d, fa, s);
+        g->prof.end();
+    }
+    g->prof.begin(KID_TOMBSTONE);
+    launch_tombstone(d, k, s);
+    g->prof.end();
+    g->prof.begin(KID_NIN_UPDATE);
+    launch_nin_purge(d, k, s);
+    g->prof.end();
+    if (fallback) {
+        if ((st = run_cold(g))) return st;
+    }
+    g->prof.begin(KID_NIN_BUILD);
+    launch_nin_build(d, 0, d.n_slots, 1, s);
+    g->prof.end();
+    launch_rank_remove(g->rank_cur, g->rank_other, r, n_before, s);
+    if ((st = check_launch("apsp_remove_node"))) return st;
+    std::swap(g->rank_cur, g->rank_other);
+    g->live_ids.erase(g->live_ids.begin() + r);
+    g->slot_of_id.erase(id);
+    g->free_slots.insert(k);
+    g->n_live -= 1;
+    g->last_kind = UK_REMOVE;
+    g->last_n_before = n_before;
+    g->last_fallback = fallback;
+    return APSP_OK;
+}
+
+apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_update_edge: NULL graph");
+    if (w < 0 || (uint32_t)w > INF) return fail(APSP_E_INVALID, "apsp_update_edge: weight outside [0, APSP_INF]");
+    if (u == v) return fail(APSP_E_INVALID, "apsp_update_edge: u == v");
+    int32_t su, sv;
+    if (!lookup(g, u, &su) || !lookup(g, v, &sv)) return fail(APSP_E_NOT_FOUND, "apsp_update_edge: id is not live");
+    hipStream_t s = g->stream;
+    DevGraph &d = g->dg;
+    const int32_t n_before = g->n_live;
+    g->prof.begin(KID_EDGE_BEGIN);
+    launch_edge_begin(d, su, sv, w, s);
+    g->prof.end();
+    g->prof.begin(KID_GATHER);
+    launch_gather_rc(d, su, sv, colu(g), colv(g), rowu(g), rowv(g), 1, s);
+    g->prof.end();
+    g->prof.begin(KID_DEC_RELAX);
+    launch_dec_relax(d, colu(g), colv(g), rowu(g), rowv(g), w, s);
+    g->prof.end();
+    FusedArgs fa{};
+    fa.mode = FUSED_INCREASE;
+    fa.k = -1;
+    fa.col1 = colu(g);
+    fa.col2 = colv(g);
+    fa.row1 = rowv(g);
+    fa.row2 = rowu(g);
+    fa.scratch = g->fscratch;
+    int32_t fallback = 0;
+    apsp_status st;
+    if (g->policy != APSP_FALLBACK_NEVER) {
+        if ((st = read_ctl(g))) return st;
+        if (g->ctl_h->edge_mode == EDGE_INCREASE) {
+            if ((st = decide_fallback(g, fa, n_before, &fallback))) return st;
+        }
+    }
+    if (fallback) {
+        if ((st = run_cold(g))) return st;
+    } else {
+        if (g->policy == APSP_FALLBACK_COST) launch_reset_stats(d, s);
+        g->prof.begin(KID_FUSED);
+        launch_fused(d, fa, s);
+        g->prof.end();
+    }
+    g->prof.begin(KID_NIN_BUILD);
+    launch_nin_build(d, sv, 1, 1, s);
+    if (g->kind == APSP_UNDIRECTED) launch_nin_build(d, su, 1, 1, s);
+    g->prof.end();
+    if ((st = check_launch("apsp_update_edge"))) return st;
+    g->last_n_before = n_before;
+    g->last_fallback = fallback;
+    g->last_kind = -1;  // the device picked the path; apsp_last_stats reads it back
+    return APSP_OK;
+}
+
+apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32_t *path_ids, int32_t path_cap,
+                       int32_t *path_len) {
+    if (!g || !dist || !path_len) return fail(APSP_E_INVALID, "apsp_query: NULL argument");
+    if (path_cap < 0 || (path_cap > 0 && !path_ids)) return fail(APSP_E_INVALID, "apsp_query: bad path buffer");
+    int32_t si, sj;
+    if (!lookup(g, i, &si) || !lookup(g, j, &sj)) return fail(APSP_E_NOT_FOUND, "apsp_query: id is not live");
+    hipStream_t s = g->stream;
+    g->prof.begin(KID_QUERY);
+    launch_query(g->dg, si, sj, g->qbuf, g->qscratch, s);
+    g->prof.end();
+    apsp_status st = check_launch("apsp_query");
+    if (st) return st;
+    const size_t words = 3 + (size_t)std::min(g->n_live, std::max(path_cap, 1));
+    if (!hip_ok(hipMemcpyAsync(g->qbuf_h, g->qbuf, words * 4, hipMemcpyDeviceToHost, s), "query copy") ||
+        !hip_ok(hipStreamSynchronize(s), "query sync"))
+        return APSP_E_DEVICE;
+    if (g->qbuf_h[2] != 0) return fail(APSP_E_DEVICE, "apsp_query: no shortest path found on the device");
+    *dist = g->qbuf_h[0];
+    *path_len = g->qbuf_h[1];
+    if (*path_len > path_cap) return fail(APSP_E_CAPACITY, "apsp_query: path_cap too small");
+    for (int32_t t = 0; t < *path_len; ++t) path_ids[t] = g->qbuf_h[3 + t];
+    return APSP_OK;
+}
+
+apsp_status apsp_read_matrix(apsp_graph *g, int32_t *out_dev, int64_t out_ld) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_read_matrix: NULL graph");
+    if (g->n_live > 0 && (!out_dev || out_ld < g->n_live)) return fail(APSP_E_INVALID, "apsp_read_matrix: bad output");
+    launch_gather_compact(g->dg.D, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->stream);
+    return check_launch("apsp_read_matrix");
+}
+
+apsp_status apsp_read_adjacency(apsp_graph *g, int32_t *out_dev, int64_t out_ld) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_read_adjacency: NULL graph");
+    if (g->n_live > 0 && (!out_dev || out_ld < g->n_live))
+        return fail(APSP_E_INVALID, "apsp_read_adjacency: bad output");
+    launch_gather_compact(g->dg.A, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->stream);
+    return check_launch("apsp_read_adjacency");
+}
+
+apsp_status apsp_node_count(const apsp_graph *g, int32_t *n) {
+    if (!g || !n) return fail(APSP_E_INVALID, "apsp_node_count: NULL argument");
+    *n = g->n_live;
+    return APSP_OK;
+}
+
+apsp_status apsp_node_ids(const apsp_graph *g, int32_t *ids, int32_t cap, int32_t *n) {
+    if (!g || !n || cap < 0 || (cap > 0 && !ids)) return fail(APSP_E_INVALID, "apsp_node_ids: bad argument");
+    *n = g->n_live;
+    if (cap < g->n_live) return fail(APSP_E_CAPACITY, "apsp_node_ids: cap too small");
+    std::copy(g->live_ids.begin(), g->live_ids.end(), ids);
+    return APSP_OK;
+}
+
+apsp_status apsp_edge_scope(apsp_graph *g, int32_t u, int32_t v, int32_t *r_count, int32_t *c_count) {
+    if (!g || !r_count || !c_count) return fail(APSP_E_INVALID, "apsp_edge_scope: NULL argument");
+    if (u == v) return fail(APSP_E_INVALID, "apsp_edge_scope: u == v");
+    int32_t su, sv;
+    if (!lookup(g, u, &su) || !lookup(g, v, &sv)) return fail(APSP_E_NOT_FOUND, "apsp_edge_scope: id is not live");
+    launch_fill(&g->dg.ctl->scope_r, 2, 0, g->stream);
+    launch_edge_scope(g->dg, su, sv, g->stream);
+    apsp_status st = check_launch("apsp_edge_scope");
+    if (st) return st;
+    if ((st = read_ctl(g))) return st;
+    *r_count = g->ctl_h->scope_r;
+    *c_count = g->ctl_h->scope_c;
+    return APSP_OK;
+}
+
+apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
+    if (!g || !out) return fail(APSP_E_INVALID, "apsp_last_stats: NULL argument");
+    apsp_status st = read_ctl(g);
+    if (st) return st;
+    const Ctl &c = *g->ctl_h;
+    std::memset(out, 0, sizeof(*out));
+    out->flagged = (int64_t)c.flagged;
+    out->rows = c.rows;
+    out->n_before = g->last_n_before;
+    out->full_scans = c.full_scans;
+    out->sweeps = c.sweeps;
+    out->rows_relaxed = c.rows_relaxed;
+    out->fallback = g->last_fallback;
+    int32_t kind = g->last_kind;
+    if (kind == -1) {  // edge update: the device chose the path
+        kind = c.edge_mode == EDGE_INCREASE ? UK_INCREASE : (c.edge_mode == EDGE_DECREASE ? UK_DECREASE : UK_NONE);
+        out->noop = c.edge_mode == EDGE_NOOP;
+    }
+    out->kind = kind;
+    if (kind == UK_REMOVE || kind == UK_INCREASE)
+        out->cost = g->last_n_before > 1 ? (double)c.rows / (double)(g->last_n_before - 1) : 0.0;
+    if (kind == UK_REMOVE) out->noop = c.flagged == 0 && !g->last_fallback;
+    return APSP_OK;
+}
+
+apsp_status apsp_sync(apsp_graph *g) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_sync: NULL graph");
+    apsp_status st = read_ctl(g);
+    if (st) return st;
+    if (g->ctl_h->err) {
+        launch_fill(&g->dg.ctl->err, 1, 0, g->stream);
+        if (!hip_ok(hipStreamSynchronize(g->stream), "stream sync")) return APSP_E_DEVICE;
+        return fail(APSP_E_VALUE, "a device-resident weight was outside [0, APSP_INF]; it was treated as an absent edge");
+    }
+    return APSP_OK;
+}
+
+apsp_status apsp_profile(apsp_graph *g, int64_t kernel_mask) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_profile: NULL graph");
+    if (!hip_ok(hipStreamSynchronize(g->stream), "stream sync")) return APSP_E_DEVICE;
+    g->prof_impl.collect();
+    for (int k = 0; k < KID_COUNT; ++k) {
+        g->prof_impl.count[k] = 0;
+        g->prof_impl.ms[k] = 0.0;
+    }
+    g->prof_impl.mask = kernel_mask;
+    g->prof.on = kernel_mask != 0;
+    return APSP_OK;
+}
+
+apsp_status apsp_profile_read(apsp_graph *g, int32_t kernel, int64_t *launches, double *total_ms) {
+    if (!g || !launches || !total_ms) return fail(APSP_E_INVALID, "apsp_profile_read: NULL argument");
+    if (kernel < 0 || kernel >= KID_COUNT) return fail(APSP_E_INVALID, "apsp_profile_read: bad kernel id");
+    if (!hip_ok(hipStreamSynchronize(g->stream), "stream sync")) return APSP_E_DEVICE;
+    g->prof_impl.collect();
+    *launches = g->prof_impl.count[kernel];
+    *total_ms = g->prof_impl.ms[kernel];
+    return APSP_OK;
+}
+
+}  // extern "C"

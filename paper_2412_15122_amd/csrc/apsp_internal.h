@@ -1,0 +1,150 @@
+// Internal declarations shared by the library's translation units.
+//
+// Storage (all slot-indexed, row-major, leading dimension ld = P, where P is
+// the capacity rounded up to a multiple of 128):
+//   D   distance matrix            D[i][j] = SPD(i, j)
+//   A   adjacency                  A[i][j] = d(i, j); A[s][s] = 0 for a live
+//                                  slot s, APSP_INF for a dead or unused one
+//   AT  transpose of A (directed graphs only), so in-edges are a row
+//   light in-edge index: for each slot y up to 64 entries (x, w) of in-edges
+//   x -> y sorted by ascending w, a count, and a bound beta[y] such that
+//   every in-edge of y that is not listed weighs at least beta[y].
+// Dead and unused slots hold APSP_INF in their whole row and column of D and
+// A, including the diagonal, which makes them inert in every kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/apsp.h"
+
+namespace apsp {
+
+constexpr uint32_t INF = 1u << 30;
+constexpr int TILE = 128;        // Floyd-Warshall block / matrix padding
+constexpr int NIN_L = 64;        // light in-edge index entries per node
+constexpr int FUSED_GRID = 512;  // resident work-groups of the mask+recompute kernel
+constexpr int FUSED_THREADS = 256;
+
+enum EdgeMode : int32_t { EDGE_NOOP = 0, EDGE_DECREASE = 1, EDGE_INCREASE = 2 };
+enum FusedMode : int32_t { FUSED_REMOVE = 0, FUSED_INCREASE = 1 };
+enum ErrBits : int32_t { ERR_VALUE = 1 };
+
+// Device control block: per-update decisions and statistics.
+struct Ctl {
+    int32_t edge_mode;
+    int32_t w_old;
+    int32_t duv;
+    int32_t err;          // sticky error bits
+    unsigned long long flagged;
+    int32_t rows;
+    int32_t full_scans;
+    int32_t sweeps;
+    int32_t rows_relaxed;
+    int32_t scope_r;
+    int32_t scope_c;
+    int32_t count_only;   // set by the host for the Algorithm 5 cost pass
+    int32_t pad[3];
+};
+
+// Device view of one graph, passed to kernels by value.
+struct DevGraph {
+    int32_t *D;
+    int32_t *A;
+    int32_t *AT;          // nullptr for undirected graphs
+    int2 *nin;            // [P][NIN_L] (x, w)
+    int32_t *nin_cnt;     // [P]
+    int32_t *nin_beta;    // [P]
+    int32_t *id_of_slot;  // [P], -1 for dead
+    Ctl *ctl;
+    int64_t ld;
+    int32_t P;
+    int32_t n_slots;      // slots [0, n_slots) may be live
+    int32_t undirected;
+    int32_t lim;          // usable index entries (1..NIN_L)
+};
+
+// Row y of the in-edge matrix: Min[y][x] = A[x][y].
+__host__ __device__ inline const int32_t *in_matrix(const DevGraph &g) {
+    return g.undirected ? g.A : g.AT;
+}
+
+// ---- launchers (defined next to their kernels) -----------------------------
+
+void launch_fill(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+void launch_load_adj(const DevGraph &g, const int32_t *adj, int64_t adj_ld, int32_t n, hipStream_t s);
+void launch_transpose(const int32_t *src, int32_t *dst, int64_t ld, int32_t n, hipStream_t s);
+void launch_copy_square(int32_t *dst, const int32_t *src, int64_t ld, int32_t n, hipStream_t s);
+void launch_iota(int32_t *p, int32_t n, hipStream_t s);
+
+// Floyd-Warshall over slots [0, n): three launches per 128-wide round.
+struct Prof;
+void launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof);
+
+// Light in-edge index.
+void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t only_short, hipStream_t s);
+void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
+                       int32_t *beta, hipStream_t s);
+void launch_nin_insert_node(const DevGraph &g, int32_t p, const int32_t *w_row, hipStream_t s);
+void launch_nin_purge(const DevGraph &g, int32_t k, hipStream_t s);
+
+// Add node.
+void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32_t *w_in,
+                            const int32_t *slot_of_rank, int32_t n_live, int32_t *wo, int32_t *wi,
+                            hipStream_t s);
+void launch_add_out(const DevGraph &g, const int2 *plist, const int32_t *pcnt, const int32_t *pbeta,
+                    const int32_t *wo, int32_t *out, hipStream_t s);
+void launch_add_in(const DevGraph &g, int32_t p, const int32_t *wi, int32_t *in, hipStream_t s);
+void launch_add_relax(const DevGraph &g, const int32_t *in, const int32_t *out, hipStream_t s);
+void launch_add_place(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
+                      const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi,
+                      hipStream_t s);
+
+// Remove node / edge increase: mask + exact recompute of the masked pairs.
+struct FusedArgs {
+    int32_t mode;         // FusedMode
+    int32_t k;            // removed slot (FUSED_REMOVE)
+    int32_t w_old;        // FUSED_INCREASE: read from ctl on the device
+    const int32_t *col1;  // per-row vectors (see kernel)
+    const int32_t *col2;
+    const int32_t *row1;
+    const int32_t *row2;
+    int32_t *scratch;     // FUSED_GRID * 2 * P ints
+};
+void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, int32_t *colb,
+                      int32_t *rowa, int32_t *rowb, int32_t gate_on_edge, hipStream_t s);
+void launch_fused(const DevGraph &g, const FusedArgs &fa, hipStream_t s);
+void launch_tombstone(const DevGraph &g, int32_t k, hipStream_t s);
+void launch_rank_remove(const int32_t *src, int32_t *dst, int32_t r, int32_t n_live, hipStream_t s);
+void launch_reset_stats(const DevGraph &g, hipStream_t s);
+
+// Edge update.
+void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, hipStream_t s);
+void launch_dec_relax(const DevGraph &g, const int32_t *colu, const int32_t *colv, const int32_t *rowu,
+                      const int32_t *rowv, int32_t w, hipStream_t s);
+
+// Query / read-out.
+void launch_query(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch, hipStream_t s);
+void launch_gather_compact(const int32_t *src, int64_t ld, int32_t *dst, int64_t dst_ld,
+                           const int32_t *slot_of_rank, int32_t n, hipStream_t s);
+void launch_edge_scope(const DevGraph &g, int32_t su, int32_t sv, hipStream_t s);
+
+size_t fused_lds_bytes(int32_t P);
+size_t nin_build_lds_bytes(int32_t P);
+void configure_kernels();  // raise dynamic-LDS limits once per process
+
+// Kernel ids for per-kernel timing (apsp_profile).
+enum KernelId : int32_t {
+    KID_FW_PIVOT = 0, KID_FW_PANEL, KID_FW_TILE, KID_NIN_BUILD, KID_NIN_UPDATE,
+    KID_ADD_OUT, KID_ADD_IN, KID_ADD_RELAX, KID_ADD_PLACE, KID_GATHER, KID_FUSED,
+    KID_TOMBSTONE, KID_EDGE_BEGIN, KID_DEC_RELAX, KID_QUERY, KID_MISC, KID_COUNT
+};
+
+// Event-based timing hooks (implemented in the host API unit).
+struct Prof {
+    void begin(int32_t kid);
+    void end();
+    bool on = false;
+    void *impl = nullptr;
+};
+
+}  // namespace apsp

@@ -1,0 +1,871 @@
+// Warm-start updates: add node, remove node, edge decrease / increase, and the
+// light in-edge index they share.
+//
+// Notation: a (+) b = min(a + b, INF), INF = 2^30, evaluated in uint32 (sums
+// of two values <= INF stay below 2^32, and a min against a value <= INF
+// needs no clamp).
+#include "apsp_internal.h"
+
+namespace apsp {
+
+// ---------------------------------------------------------------------------
+// wave / block helpers (wave64)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Block-wide reductions for 256 threads; `red` holds >= 4 words of LDS.
+__device__ uint32_t block_min256(uint32_t v, uint32_t *red) {
+    v = wave_min(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t r = min(min(red[0], red[1]), min(red[2], red[3]));
+    return r;
+}
+
+__device__ int block_sum256(int v, uint32_t *red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = (uint32_t)v;
+    __syncthreads();
+    return (int)(red[0] + red[1] + red[2] + red[3]);
+}
+
+// Exclusive prefix sum over the 256 threads of a block; returns this thread's
+// offset and writes the total to *total.  `red` holds >= 8 words.
+__device__ int block_exscan256(int v, uint32_t *red, int *total) {
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    __syncthreads();
+    if (lane == 63) red[wid] = (uint32_t)incl;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wid; ++w) base += (int)red[w];
+    *total = (int)(red[0] + red[1] + red[2] + red[3]);
+    return base + incl - v;
+}
+
+// ---------------------------------------------------------------------------
+// light in-edge index
+// ---------------------------------------------------------------------------
+// For node y the index lists up to NIN_L in-edges (x, w) with the smallest
+// weights, ascending, and a bound beta[y] <= the weight of every unlisted
+// in-edge (INF when every in-edge is listed).  Scans that stop at
+// min(cnt, lim) entries use beta_eff = (cnt > lim) ? list[lim].w : beta.
+
+struct SelectShared {
+    uint32_t hist[256];
+    uint32_t red[16];
+    int bin, kk;
+    unsigned long long keys[NIN_L];
+};
+
+// Select the NIN_L smallest entries of vals[0..n) other than index `excl`
+// and other than INF (absent edges), ordered by (w, x).  One 256-thread block.
+__device__ void select_light(const int32_t *__restrict__ vals, int32_t n, int32_t excl, int2 *list,
+                             int32_t *cnt_out, int32_t *beta_out, SelectShared &sh) {
+    const int tid = threadIdx.x;
+    int valid = 0;
+    for (int32_t x = tid; x < n; x += 256) {
+        uint32_t v = (uint32_t)vals[x];
+        valid += (x != excl && v < INF);
+    }
+    int total = block_sum256(valid, sh.red);
+    uint32_t tau = INF;  // entries < tau are all taken
+    int need_eq = 0;     // plus this many entries == tau, lowest index first
+    if (total > NIN_L) {
+        uint32_t prefix = 0, mask = 0;
+        int kk = NIN_L;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            sh.hist[tid] = 0;
+            __syncthreads();
+            for (int32_t x = tid; x < n; x += 256) {
+                uint32_t v = (uint32_t)vals[x];
+                if (x != excl && v < INF && (v & mask) == prefix) atomicAdd(&sh.hist[(v >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int cum = 0, b = 0;
+                for (; b < 255; ++b) {
+                    if (cum + (int)sh.hist[b] >= kk) break;
+                    cum += (int)sh.hist[b];
+                }
+                sh.bin = b;
+                sh.kk = kk - cum;
+            }
+            __syncthreads();
+            prefix |= (uint32_t)sh.bin << shift;
+            mask |= 255u << shift;
+            kk = sh.kk;
+            __syncthreads();
+        }
+        tau = prefix;
+        need_eq = kk;
+    }
+    // ordered collection over contiguous segments
+    const int32_t seg = (n + 255) / 256;
+    const int32_t x0 = min(n, tid * seg), x1 = min(n, x0 + seg);
+    int c_less = 0, c_eq = 0;
+    for (int32_t x = x0; x < x1; ++x) {
+        uint32_t v = (uint32_t)vals[x];
+        if (x == excl || v >= INF) continue;
+        c_less += (v < tau);
+        c_eq += (v == tau);
+    }
+    int tot_less, tot_eq;
+    int off_less = block_exscan256(c_less, sh.red, &tot_less);
+    int off_eq = block_exscan256(c_eq, sh.red + 8, &tot_eq);
+    for (int32_t x = x0; x < x1; ++x) {
+        uint32_t v = (uint32_t)vals[x];
+        if (x == excl || v >= INF) continue;
+        if (v < tau) {
+            sh.keys[off_less++] = ((unsigned long long)v << 32) | (uint32_t)x;
+        } else if (v == tau) {
+            if (off_eq < need_eq) sh.keys[tot_less + off_eq] = ((unsigned long long)v << 32) | (uint32_t)x;
+            ++off_eq;
+        }
+    }
+    __syncthreads();
+    const int m = min(total, NIN_L);
+    if (tid < 64) {  // bitonic sort of 64 keys in one wave
+        const int lane = tid;
+        unsigned long long key = lane < m ? sh.keys[lane] : ~0ull;
+        for (int k = 2; k <= 64; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+                uint32_t olo = (uint32_t)__shfl_xor((int)lo, j), ohi = (uint32_t)__shfl_xor((int)hi, j);
+                unsigned long long other = ((unsigned long long)ohi << 32) | olo;
+                bool up = (lane & k) == 0;
+                bool lower = (lane & j) == 0;
+                unsigned long long mn = key < other ? key : other;
+                unsigned long long mx = key < other ? other : key;
+                key = (lower == up) ? mn : mx;
+            }
+        }
+        int2 ent;
+        if (lane < m) {
+            ent.x = (int32_t)(uint32_t)key;
+            ent.y = (int32_t)(uint32_t)(key >> 32);
+        } else {
+            ent.x = 0;
+            ent.y = (int32_t)INF;
+        }
+        list[lane] = ent;
+        if (lane == 0) {
+            *cnt_out = m;
+            *beta_out = (int32_t)(total > NIN_L ? tau : INF);
+        }
+    }
+}
+
+// Build the index of nodes first .. first+count-1 from row y of the in-edge
+// matrix.  only_short: rebuild only lists that have shrunk below NIN_L/2
+// while unlisted in-edges exist.
+__global__ __launch_bounds__(256) void k_nin_build(DevGraph g, int32_t first, int32_t only_short) {
+    __shared__ SelectShared sh;
+    const int32_t y = first + blockIdx.x;
+    if (y >= g.n_slots) return;
+    int32_t *cnt = g.nin_cnt + y, *beta = g.nin_beta + y;
+    if (only_short && !(*cnt < NIN_L / 2 && (uint32_t)*beta < INF)) return;
+    int2 *list = g.nin + (int64_t)y * NIN_L;
+    if (g.A[(int64_t)y * g.ld + y] != 0) {  // dead slot
+        if (threadIdx.x == 0) { *cnt = 0; *beta = (int32_t)INF; }
+        return;
+    }
+    select_light(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, list, cnt, beta, sh);
+}
+
+void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t only_short, hipStream_t s) {
+    if (count <= 0) return;
+    k_nin_build<<<count, 256, 0, s>>>(g, first, only_short);
+}
+
+__global__ __launch_bounds__(256) void k_select_vec(const int32_t *vals, int32_t n, int32_t excl, int2 *list,
+                                                    int32_t *cnt, int32_t *beta) {
+    __shared__ SelectShared sh;
+    select_light(vals, n, excl, list, cnt, beta, sh);
+}
+
+void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
+                       int32_t *beta, hipStream_t s) {
+    k_select_vec<<<1, 256, 0, s>>>(vals, n, exclude, list, cnt, beta);
+}
+
+// Wave-level list edits (one wave owns list y).
+__device__ void wave_list_purge(const DevGraph &g, int32_t y, int32_t x) {
+    const int lane = lane_id();
+    int2 *L = g.nin + (int64_t)y * NIN_L;
+    const int cnt = g.nin_cnt[y];
+    int2 ent = lane < cnt ? L[lane] : make_int2(0, (int)INF);
+    unsigned long long m = __ballot(lane < cnt && ent.x == x);
+    if (m == 0) return;
+    const int pos = __ffsll((long long)m) - 1;
+    int nx = __shfl_down(ent.x, 1), ny = __shfl_down(ent.y, 1);
+    if (lane >= pos && lane < cnt - 1) L[lane] = make_int2(nx, ny);
+    if (lane == cnt - 1) L[lane] = make_int2(0, (int)INF);
+    if (lane == 0) g.nin_cnt[y] = cnt - 1;
+}
+
+// Insert in-edge (x, w) into list y if w < beta (dropping the heaviest entry
+// when full and lowering beta to it).  Caller guarantees x is not listed.
+__device__ void wave_list_insert(const DevGraph &g, int32_t y, int32_t x, uint32_t w) {
+    const int lane = lane_id();
+    int2 *L = g.nin + (int64_t)y * NIN_L;
+    const int cnt = g.nin_cnt[y];
+    const uint32_t beta = (uint32_t)g.nin_beta[y];
+    if (w >= INF || w >= beta) return;
+    int2 ent = lane < cnt ? L[lane] : make_int2(0, (int)INF);
+    const int pos = __popcll(__ballot(lane < cnt && (uint32_t)ent.y <= w));
+    int px = __shfl_up(ent.x, 1), py = __shfl_up(ent.y, 1);
+    const int ncnt = min(cnt + 1, NIN_L);
+    uint32_t dropped = INF;
+    if (cnt == NIN_L) dropped = (pos < NIN_L) ? (uint32_t)__shfl(ent.y, NIN_L - 1) : w;
+    int2 ne = lane < pos ? ent : (lane == pos ? make_int2(x, (int)w) : make_int2(px, py));
+    if (lane < ncnt) L[lane] = ne;
+    if (lane == 0) {
+        g.nin_cnt[y] = ncnt;
+        if (cnt == NIN_L) g.nin_beta[y] = (int32_t)min(beta, dropped);
+    }
+}
+
+// New node p: its out-edges p -> y (weights w_row[y]) are in-edges of y.
+__global__ __launch_bounds__(256) void k_nin_insert_node(DevGraph g, int32_t p, const int32_t *w_row) {
+    const int32_t y = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (y >= g.n_slots || y == p || g.id_of_slot[y] < 0) return;
+    wave_list_insert(g, y, p, (uint32_t)w_row[y]);
+}
+
+void launch_nin_insert_node(const DevGraph &g, int32_t p, const int32_t *w_row, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_nin_insert_node<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, p, w_row);
+}
+
+// Node k is gone: drop it from every list; its own list empties.
+__global__ __launch_bounds__(256) void k_nin_purge(DevGraph g, int32_t k) {
+    const int32_t y = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (y >= g.n_slots) return;
+    if (y == k) {
+        if (lane_id() == 0) { g.nin_cnt[y] = 0; g.nin_beta[y] = (int32_t)INF; }
+        return;
+    }
+    wave_list_purge(g, y, k);
+}
+
+void launch_nin_purge(const DevGraph &g, int32_t k, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_nin_purge<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, k);
+}
+
+// ---------------------------------------------------------------------------
+// add node (Section 2.1)
+// ---------------------------------------------------------------------------
+
+// wo[s] / wi[s]: the new node's out- / in-weight towards slot s (INF for
+// dead slots); weights outside [0, INF] become INF and set the sticky error.
+__global__ void k_scatter_weights(DevGraph g, const int32_t *__restrict__ w_out, const int32_t *__restrict__ w_in,
+                                  const int32_t *__restrict__ slot_of_rank, int32_t n_live, int32_t *wo,
+                                  int32_t *wi) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_live) return;
+    int32_t s = slot_of_rank[r];
+    int32_t a = w_out[r];
+    int32_t b = w_in ? w_in[r] : a;
+    int bad = 0;
+    if (a < 0 || (uint32_t)a > INF) { a = (int32_t)INF; bad = 1; }
+    if (b < 0 || (uint32_t)b > INF) { b = (int32_t)INF; bad = 1; }
+    wo[s] = a;
+    wi[s] = b;
+    if (bad) atomicOr(&g.ctl->err, (int32_t)ERR_VALUE);
+}
+
+void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32_t *w_in,
+                            const int32_t *slot_of_rank, int32_t n_live, int32_t *wo, int32_t *wi,
+                            hipStream_t s) {
+    launch_fill(wo, g.n_slots, (int32_t)INF, s);
+    if (wi != wo) launch_fill(wi, g.n_slots, (int32_t)INF, s);
+    if (n_live <= 0) return;
+    k_scatter_weights<<<(n_live + 255) / 256, 256, 0, s>>>(g, w_out, g.undirected ? nullptr : w_in,
+                                                          slot_of_rank, n_live, wo, wi);
+}
+
+// out[c] = min_t wo[t] (+) D[t][c]  (Corollary corollary1: SPD(p, c)).
+// The new node's lightest out-edges come first (plist, ascending weight): a
+// column stops once the next weight reaches its current value (distances
+// are >= 0), and every unlisted t has wo[t] >= beta, so a column whose
+// value is <= beta is final.  Columns above beta (or unreachable) take an
+// exhaustive scan.  One block = 256 columns; its 4 waves split the list.
+__global__ __launch_bounds__(256) void k_add_out(DevGraph g, const int2 *__restrict__ plist,
+                                                 const int32_t *__restrict__ pcnt, const int32_t *__restrict__ pbeta,
+                                                 const int32_t *__restrict__ wo, int32_t *__restrict__ out) {
+    __shared__ uint32_t part[4][256];
+    __shared__ uint32_t red[8];
+    const int n = g.n_slots;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int32_t cbase = blockIdx.x * 256;
+    const int32_t c0 = cbase + lane * 4;
+    bool live[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) live[e] = (c0 + e < n) && g.id_of_slot[c0 + e] >= 0;
+    uint32_t acc[4] = {INF, INF, INF, INF};
+    const int cnt = *pcnt;
+    const int lim = min(cnt, g.lim);
+    const uint32_t beta_eff = cnt > g.lim ? (uint32_t)plist[g.lim].y : (uint32_t)*pbeta;
+    if (c0 < n) {
+        for (int e = wv; e < lim; e += 4) {
+            int2 ent = plist[e];
+            uint32_t mx = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (live[q]) mx = max(mx, acc[q]);
+            if ((uint32_t)ent.y >= mx) break;
+            int4 v = *reinterpret_cast<const int4 *>(g.D + (int64_t)ent.x * g.ld + c0);
+            acc[0] = min(acc[0], (uint32_t)ent.y + (uint32_t)v.x);
+            acc[1] = min(acc[1], (uint32_t)ent.y + (uint32_t)v.y);
+            acc[2] = min(acc[2], (uint32_t)ent.y + (uint32_t)v.z);
+            acc[3] = min(acc[3], (uint32_t)ent.y + (uint32_t)v.w);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[wv][lane * 4 + q] = acc[q];
+    __syncthreads();
+    const int32_t c = cbase + tid;  // one column per thread from here on
+    uint32_t fin = min(min(part[0][tid], part[1][tid]), min(part[2][tid], part[3][tid]));
+    const bool live_c = c < n && g.id_of_slot[c] >= 0;
+    int need = live_c && fin > beta_eff;
+    need = block_sum256(need, red);
+    if (need) {
+        if (c < n) {
+            for (int32_t t = 0; t < n; ++t)
+                fin = min(fin, (uint32_t)wo[t] + (uint32_t)g.D[(int64_t)t * g.ld + c]);
+        }
+    }
+    if (c < n) out[c] = (int32_t)min(fin, INF);
+}
+
+void launch_add_out(const DevGraph &g, const int2 *plist, const int32_t *pcnt, const int32_t *pbeta,
+                    const int32_t *wo, int32_t *out, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_add_out<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, plist, pcnt, pbeta, wo, out);
+}
+
+// in[i] = min_r D[i][r] (+) wi[r]  (Corollary corollary2: SPD(i, p)), one wave
+// per row over the new node's light in-edges (its own index list, built
+// from wi), exhaustive when the row's value exceeds beta.  Directed only;
+// for an undirected graph in = out.
+__global__ __launch_bounds__(256) void k_add_in(DevGraph g, int32_t p, const int32_t *__restrict__ wi,
+                                                int32_t *__restrict__ in) {
+    const int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (i >= g.n_slots) return;
+    if (g.id_of_slot[i] < 0) {
+        if (lane == 0) in[i] = (int32_t)INF;
+        return;
+    }
+    const int2 *L = g.nin + (int64_t)p * NIN_L;
+    const int cnt = g.nin_cnt[p];
+    const int lim = min(cnt, g.lim);
+    const uint32_t beta_eff = cnt > g.lim ? (uint32_t)L[g.lim].y : (uint32_t)g.nin_beta[p];
+    const int32_t *Di = g.D + (int64_t)i * g.ld;
+    uint32_t best = INF;
+    if (lane < lim) {
+        int2 ent = L[lane];
+        best = (uint32_t)ent.y + (uint32_t)Di[ent.x];
+    }
+    best = wave_min(best);
+    if (best > beta_eff) {
+        for (int32_t r = lane; r < g.n_slots; r += 64) best = min(best, (uint32_t)Di[r] + (uint32_t)wi[r]);
+        best = wave_min(best);
+    }
+    if (lane == 0) in[i] = (int32_t)min(best, INF);
+}
+
+void launch_add_in(const DevGraph &g, int32_t p, const int32_t *wi, int32_t *in, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_add_in<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, p, wi, in);
+}
+
+// Theorem theorem3: D[i][j] = min(D[i][j], in[i] + out[j]) over the old
+// slots.  Block = 1024 columns x 8 rows; a row with in[i] = INF cannot change.
+constexpr int RELAX_ROWS = 8;
+
+__global__ __launch_bounds__(256) void k_add_relax(DevGraph g, const int32_t *__restrict__ in,
+                                                   const int32_t *__restrict__ out) {
+    const int n = g.n_slots;
+    const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    const int32_t r0 = blockIdx.y * RELAX_ROWS;
+    if (c0 >= n) return;
+    uint4 o = *reinterpret_cast<const uint4 *>(out + c0);
+    if (c0 + 1 >= n) o.y = INF;
+    if (c0 + 2 >= n) o.z = INF;
+    if (c0 + 3 >= n) o.w = INF;
+    int rows = 0;
+#pragma unroll 4
+    for (int r = 0; r < RELAX_ROWS; ++r) {
+        const int32_t i = r0 + r;
+        if (i >= n) break;
+        const uint32_t a = (uint32_t)in[i];
+        if (a >= INF) continue;
+        ++rows;
+        uint4 *dp = reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0);
+        uint4 d = *dp;
+        uint4 t = make_uint4(a + o.x, a + o.y, a + o.z, a + o.w);
+        if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
+            d.x = min(d.x, t.x);
+            d.y = min(d.y, t.y);
+            d.z = min(d.z, t.z);
+            d.w = min(d.w, t.w);
+            *dp = d;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && rows) atomicAdd(&g.ctl->rows_relaxed, rows);
+}
+
+void launch_add_relax(const DevGraph &g, const int32_t *in, const int32_t *out, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + RELAX_ROWS - 1) / RELAX_ROWS);
+    k_add_relax<<<grid, 256, 0, s>>>(g, in, out);
+}
+
+// Write the new node's row and column of D and A (and A^T) and register it.
+__global__ void k_add_place(DevGraph g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
+                            const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n_slots) return;
+    const int64_t ld = g.ld;
+    if (s == p) {
+        g.D[(int64_t)p * ld + p] = 0;
+        g.A[(int64_t)p * ld + p] = 0;
+        if (!g.undirected) g.AT[(int64_t)p * ld + p] = 0;
+        g.id_of_slot[p] = new_id;
+        slot_of_rank[rank] = p;
+        return;
+    }
+    g.D[(int64_t)p * ld + s] = out[s];
+    g.D[(int64_t)s * ld + p] = in[s];
+    g.A[(int64_t)p * ld + s] = wo[s];
+    g.A[(int64_t)s * ld + p] = wi[s];
+    if (!g.undirected) {
+        g.AT[(int64_t)s * ld + p] = wo[s];
+        g.AT[(int64_t)p * ld + s] = wi[s];
+    }
+}
+
+void launch_add_place(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
+                      const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi,
+                      hipStream_t s) {
+    k_add_place<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, p, new_id, rank, slot_of_rank, in, out, wo, wi);
+}
+
+// ---------------------------------------------------------------------------
+// gathers, tombstones, bookkeeping
+// ---------------------------------------------------------------------------
+
+// Zero the per-update counters (the edge decision is written by k_edge_begin).
+__global__ void k_reset_stats(DevGraph g) {
+    Ctl *c = g.ctl;
+    c->flagged = 0;
+    c->rows = 0;
+    c->full_scans = 0;
+    c->sweeps = 0;
+    c->rows_relaxed = 0;
+    c->scope_r = 0;
+    c->scope_c = 0;
+}
+
+void launch_reset_stats(const DevGraph &g, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(g); }
+
+// cola[i] = D[i][a], colb[i] = D[i][b], rowa[j] = D[a][j], rowb[j] = D[b][j].
+__global__ void k_gather_rc(DevGraph g, int32_t a, int32_t b, int32_t *cola, int32_t *colb, int32_t *rowa,
+                            int32_t *rowb, int32_t gate_on_edge) {
+    if (gate_on_edge && g.ctl->edge_mode == EDGE_NOOP) return;
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n_slots) return;
+    const int64_t ld = g.ld;
+    cola[i] = g.D[(int64_t)i * ld + a];
+    rowa[i] = g.D[(int64_t)a * ld + i];
+    if (colb) colb[i] = g.D[(int64_t)i * ld + b];
+    if (rowb) rowb[i] = g.D[(int64_t)b * ld + i];
+}
+
+void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, int32_t *colb, int32_t *rowa,
+                      int32_t *rowb, int32_t gate_on_edge, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_gather_rc<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, a, b, cola, colb, rowa, rowb, gate_on_edge);
+}
+
+// G - G_k: row and column k of D, A (and A^T) become INF, diagonal included.
+__global__ void k_tombstone(DevGraph g, int32_t k) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n_slots) return;
+    const int64_t ld = g.ld;
+    const int32_t I = (int32_t)INF;
+    g.D[(int64_t)k * ld + s] = I;
+    g.D[(int64_t)s * ld + k] = I;
+    g.A[(int64_t)k * ld + s] = I;
+    g.A[(int64_t)s * ld + k] = I;
+    if (!g.undirected) {
+        g.AT[(int64_t)k * ld + s] = I;
+        g.AT[(int64_t)s * ld + k] = I;
+    }
+    if (s == k) g.id_of_slot[k] = -1;
+}
+
+void launch_tombstone(const DevGraph &g, int32_t k, hipStream_t s) {
+    k_tombstone<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, k);
+}
+
+__global__ void k_rank_remove(const int32_t *src, int32_t *dst, int32_t r, int32_t n_live) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_live - 1) dst[t] = src[t < r ? t : t + 1];
+}
+
+void launch_rank_remove(const int32_t *src, int32_t *dst, int32_t r, int32_t n_live, hipStream_t s) {
+    if (n_live <= 1) return;
+    k_rank_remove<<<(n_live + 255) / 256, 256, 0, s>>>(src, dst, r, n_live);
+}
+
+// ---------------------------------------------------------------------------
+// edge update (Section 2.3), decided on the device
+// ---------------------------------------------------------------------------
+
+__device__ void wave_list_set_edge(const DevGraph &g, int32_t y, int32_t x, uint32_t w) {
+    wave_list_purge(g, y, x);
+    wave_list_insert(g, y, x, w);
+}
+
+// One wave: read the old weight and D[u][v], pick the path, write A, fix the
+// index lists of v (and u).
+//   w == w_old                      -> nothing changes
+//   w <  w_old and w <  D[u][v]     -> decrease relaxation
+//   w <  w_old and w >= D[u][v]     -> nothing changes in D
+//   w >  w_old and w_old == D[u][v] -> increase: mask + recompute
+//   w >  w_old and w_old >  D[u][v] -> the edge is on no shortest path
+__global__ __launch_bounds__(64) void k_edge_begin(DevGraph g, int32_t su, int32_t sv, int32_t w) {
+    const int lane = lane_id();
+    const int64_t ld = g.ld;
+    const uint32_t w_old = (uint32_t)g.A[(int64_t)su * ld + sv];
+    const uint32_t duv = (uint32_t)g.D[(int64_t)su * ld + sv];
+    const uint32_t wn = (uint32_t)w;
+    int32_t mode = EDGE_NOOP;
+    if (wn < w_old) mode = (wn < duv) ? EDGE_DECREASE : EDGE_NOOP;
+    else if (wn > w_old) mode = (w_old == duv && duv < INF) ? EDGE_INCREASE : EDGE_NOOP;
+    __syncthreads();
+    if (lane == 0) {
+        Ctl *c = g.ctl;
+        c->edge_mode = mode;
+        c->w_old = (int32_t)w_old;
+        c->duv = (int32_t)duv;
+        c->flagged = 0;
+        c->rows = 0;
+        c->full_scans = 0;
+        c->sweeps = 0;
+        c->rows_relaxed = 0;
+        g.A[(int64_t)su * ld + sv] = w;
+        if (g.undirected) g.A[(int64_t)sv * ld + su] = w;
+        else g.AT[(int64_t)sv * ld + su] = w;
+    }
+    wave_list_set_edge(g, sv, su, wn);
+    if (g.undirected) wave_list_set_edge(g, su, sv, wn);
+}
+
+void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, hipStream_t s) {
+    k_edge_begin<<<1, 64, 0, s>>>(g, su, sv, w);
+}
+
+// Decrease of u -> v to w (< D[u][v]).  Inserting a relay node on the edge
+// and applying Theorem theorem3 gives
+//   D'[i][j] = min(D[i][j], D[i][u] + w + D[v][j])   (and v -> u if undirected).
+// Only rows with D[i][u] + w < D[i][v] can change.  The column / row vectors
+// were gathered before this launch, so in-place writes do not feed back.
+__global__ __launch_bounds__(256) void k_dec_relax(DevGraph g, const int32_t *__restrict__ colu,
+                                                   const int32_t *__restrict__ colv, const int32_t *__restrict__ rowu,
+                                                   const int32_t *__restrict__ rowv, int32_t w) {
+    if (g.ctl->edge_mode != EDGE_DECREASE) return;
+    const int n = g.n_slots;
+    const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    const int32_t r0 = blockIdx.y * RELAX_ROWS;
+    if (c0 >= n) return;
+    const uint32_t wn = (uint32_t)w;
+    uint4 bv = *reinterpret_cast<const uint4 *>(rowv + c0);
+    uint4 bu = make_uint4(INF, INF, INF, INF);
+    if (g.undirected) bu = *reinterpret_cast<const uint4 *>(rowu + c0);
+    if (c0 + 1 >= n) { bv.y = INF; bu.y = INF; }
+    if (c0 + 2 >= n) { bv.z = INF; bu.z = INF; }
+    if (c0 + 3 >= n) { bv.w = INF; bu.w = INF; }
+    int rows = 0;
+    for (int r = 0; r < RELAX_ROWS; ++r) {
+        const int32_t i = r0 + r;
+        if (i >= n) break;
+        const uint32_t du = (uint32_t)colu[i], dv = (uint32_t)colv[i];
+        const uint32_t a1 = du + wn, a2 = dv + wn;
+        const bool t1 = a1 < dv;
+        const bool t2 = g.undirected && a2 < du;
+        if (!t1 && !t2) continue;
+        ++rows;
+        const uint32_t x1 = t1 ? a1 : INF, x2 = t2 ? a2 : INF;
+        uint4 *dp = reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0);
+        uint4 d = *dp;
+        uint4 t = make_uint4(min(x1 + bv.x, x2 + bu.x), min(x1 + bv.y, x2 + bu.y), min(x1 + bv.z, x2 + bu.z),
+                             min(x1 + bv.w, x2 + bu.w));
+        if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
+            d.x = min(d.x, t.x);
+            d.y = min(d.y, t.y);
+            d.z = min(d.z, t.z);
+            d.w = min(d.w, t.w);
+            *dp = d;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && rows) atomicAdd(&g.ctl->rows_relaxed, rows);
+}
+
+void launch_dec_relax(const DevGraph &g, const int32_t *colu, const int32_t *colv, const int32_t *rowu,
+                      const int32_t *rowv, int32_t w, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + RELAX_ROWS - 1) / RELAX_ROWS);
+    k_dec_relax<<<grid, 256, 0, s>>>(g, colu, colv, rowu, rowv, w);
+}
+
+// ---------------------------------------------------------------------------
+// mask + exact recompute (node removal, edge increase)
+// ---------------------------------------------------------------------------
+// One block per affected row i (blocks stride over rows).
+//   1. Stream row i once, flag column j when a pair test holds
+//        remove k:   D[i][k] + D[k][j] == D[i][j]          (Corollary corollary3)
+//        increase:   D[i][u] + w_old + D[v][j] == D[i][j]  (and v -> u if undirected)
+//      with j != i, D[i][j] < INF (j != k for a removal).  Unflagged entries
+//      keep their value in G' (Theorem theorem_spd_4); flagged ones start at
+//      INF in an LDS copy `cur` of the row, as does column k.
+//   2. Recompute the flagged entries on G' by Bellman-Ford relaxation
+//        cur[y] = min_x cur[x] (+) A'[x][y]
+//      restricted to the flagged y.  The unflagged x already hold exact
+//      values, so the fixed point is the exact row of G'.  Each y scans its
+//      light in-edge list in ascending weight and stops when the weight
+//      reaches cur[y]; a y whose value stays above its list bound beta takes
+//      an exhaustive scan of its in-edges.  Sweeps repeat until nothing
+//      changes.
+//   3. Write the flagged entries back.
+// Every value written is the length of a real walk in G' and the final row
+// satisfies every edge inequality of G', so it equals SPD in G' exactly.
+
+size_t fused_lds_bytes(int32_t P) {
+    return ((size_t)P + 2 * (size_t)((P + 31) / 32) + 64) * sizeof(uint32_t);
+}
+
+__global__ __launch_bounds__(FUSED_THREADS) void k_fused(DevGraph g, FusedArgs fa) {
+    extern __shared__ uint32_t sm[];
+    const int n = g.n_slots;
+    const int nw = (n + 31) >> 5;
+    uint32_t *cur = sm;
+    uint32_t *fl = sm + g.P;
+    uint32_t *red = fl + 2 * ((g.P + 31) >> 5);  // 64 words
+    uint32_t *flag_changed = red + 32;
+    uint32_t *flag_nfs = red + 33;
+    const int tid = threadIdx.x;
+    uint32_t w_old = 0;
+    if (fa.mode == FUSED_INCREASE) {
+        if (g.ctl->edge_mode != EDGE_INCREASE) return;
+        w_old = (uint32_t)g.ctl->w_old;
+    }
+    const bool count_only = g.ctl->count_only != 0;
+    const int32_t *Min = in_matrix(g);
+    int32_t *list = fa.scratch + (int64_t)blockIdx.x * 2 * g.P;
+    int32_t *fsl = list + g.P;
+    unsigned long long my_flagged = 0;
+    int my_rows = 0, my_fs = 0, my_sweeps = 0;
+
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        bool t1 = false, t2 = false;
+        uint32_t a1 = 0, a2 = 0;
+        if (fa.mode == FUSED_REMOVE) {
+            const uint32_t dik = (uint32_t)fa.col1[i];
+            t1 = (i != fa.k) && dik < INF;
+            a1 = dik;
+        } else {
+            const uint32_t cu = (uint32_t)fa.col1[i], cv = (uint32_t)fa.col2[i];
+            t1 = cv < INF && cu + w_old == cv;
+            a1 = cv;
+            if (g.undirected) {
+                t2 = cu < INF && cv + w_old == cu;
+                a2 = cu;
+            }
+        }
+        if (!t1 && !t2) continue;
+
+        // 1. mask
+        for (int w = tid; w < nw; w += FUSED_THREADS) fl[w] = 0;
+        __syncthreads();
+        const int32_t *Drow = g.D + (int64_t)i * g.ld;
+        int cnt = 0;
+        for (int q = tid; q * 4 < n; q += FUSED_THREADS) {
+            const int j0 = q * 4;
+            uint4 d = *reinterpret_cast<const uint4 *>(Drow + j0);
+            uint4 r1 = make_uint4(0, 0, 0, 0), r2 = make_uint4(0, 0, 0, 0);
+            if (t1) r1 = *reinterpret_cast<const uint4 *>(fa.row1 + j0);
+            if (t2) r2 = *reinterpret_cast<const uint4 *>(fa.row2 + j0);
+            const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
+            const uint32_t v1[4] = {r1.x, r1.y, r1.z, r1.w};
+            const uint32_t v2[4] = {r2.x, r2.y, r2.z, r2.w};
+            uint32_t bits = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = j0 + e;
+                uint32_t dj = dv[e];
+                bool f = false;
+                if (j < n && j != i && dj < INF) f = (t1 && a1 + v1[e] == dj) || (t2 && a2 + v2[e] == dj);
+                if (fa.mode == FUSED_REMOVE && j == fa.k) {
+                    f = false;
+                    dj = INF;
+                }
+                if (f) bits |= 1u << e;
+                if (!count_only) cur[j] = f ? INF : dj;
+            }
+            if (bits) {
+                atomicOr(&fl[j0 >> 5], bits << (j0 & 31));
+                cnt += __popc(bits);
+            }
+        }
+        const int total = block_sum256(cnt, red);
+        if (total == 0) continue;
+        if (tid == 0) {
+            my_flagged += (unsigned long long)total;
+            ++my_rows;
+        }
+        if (count_only) {
+            __syncthreads();
+            continue;
+        }
+
+        // flagged columns -> list (ascending)
+        {
+            const int per = (nw + FUSED_THREADS - 1) / FUSED_THREADS;
+            const int w0 = min(nw, tid * per), w1 = min(nw, w0 + per);
+            int c = 0;
+            for (int w = w0; w < w1; ++w) c += __popc(fl[w]);
+            int tot;
+            int off = block_exscan256(c, red, &tot);
+            for (int w = w0; w < w1; ++w) {
+                uint32_t bits = fl[w];
+                while (bits) {
+                    const int b = __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    list[off++] = w * 32 + b;
+                }
+            }
+        }
+        __syncthreads();
+
+        // 2. recompute
+        int sweeps = 0;
+        for (;;) {
+            for (;;) {  // light-index sweeps until stable
+                __syncthreads();
+                if (tid == 0) *flag_changed = 0;
+                __syncthreads();
+                for (int e = tid; e < total; e += FUSED_THREADS) {
+                    const int32_t y = list[e];
+                    uint32_t best = cur[y];
+                    const int lim = min(g.nin_cnt[y], g.lim);
+                    const int2 *L = g.nin + (int64_t)y * NIN_L;
+                    for (int t = 0; t < lim; ++t) {
+                        const int2 ent = L[t];
+                        if ((uint32_t)ent.y >= best) break;
+                        best = min(best, cur[ent.x] + (uint32_t)ent.y);
+                    }
+                    if (best < cur[y]) {
+                        cur[y] = best;
+                        *flag_changed = 1;
+                    }
+                }
+                __syncthreads();
+                ++sweeps;
+                if (*flag_changed == 0) break;
+            }
+            // entries still above their list bound need every in-edge
+            __syncthreads();
+            if (tid == 0) *flag_nfs = 0;
+            __syncthreads();
+            for (int e = tid; e < total; e += FUSED_THREADS) {
+                const int32_t y = list[e];
+                const int c = g.nin_cnt[y];
+                const uint32_t beta_eff = c > g.lim ? (uint32_t)g.nin[(int64_t)y * NIN_L + g.lim].y
+                                                    : (uint32_t)g.nin_beta[y];
+                if (cur[y] > beta_eff) fsl[atomicAdd(flag_nfs, 1u)] = y;
+            }
+            __syncthreads();
+            const int nfs = (int)*flag_nfs;
+            if (nfs == 0) break;
+            if (tid == 0) *flag_changed = 0;
+            for (int f = 0; f < nfs; ++f) {
+                const int32_t y = fsl[f];
+                const int32_t *col = Min + (int64_t)y * g.ld;
+                uint32_t best = INF;
+                for (int32_t x = tid; x < n; x += FUSED_THREADS) best = min(best, cur[x] + (uint32_t)col[x]);
+                best = block_min256(best, red);
+                if (tid == 0 && best < cur[y]) {
+                    cur[y] = best;
+                    *flag_changed = 1;
+                }
+                __syncthreads();
+            }
+            my_fs += nfs;
+            __syncthreads();
+            if (*flag_changed == 0) break;
+        }
+
+        // 3. write back
+        for (int e = tid; e < total; e += FUSED_THREADS) {
+            const int32_t y = list[e];
+            const_cast<int32_t *>(Drow)[y] = (int32_t)cur[y];
+        }
+        if (tid == 0) my_sweeps = max(my_sweeps, sweeps);
+        __syncthreads();
+    }
+    if (tid == 0 && (my_rows || my_fs)) {
+        atomicAdd(&g.ctl->flagged, my_flagged);
+        atomicAdd(&g.ctl->rows, my_rows);
+        atomicAdd(&g.ctl->full_scans, my_fs);
+        atomicMax(&g.ctl->sweeps, my_sweeps);
+    }
+}
+
+void launch_fused(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    const int grid = g.n_slots < FUSED_GRID ? g.n_slots : FUSED_GRID;
+    k_fused<<<grid, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
+}
+
+size_t nin_build_lds_bytes(int32_t) { return 0; }
+
+void configure_kernels() {
+    static bool done = false;
+    if (done) return;
+    done = true;
+    (void)hipFuncSetAttribute((const void *)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)fused_lds_bytes(((APSP_MAX_CAPACITY + TILE - 1) / TILE) * TILE));
+}
+
+}  // namespace apsp

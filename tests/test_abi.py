@@ -1,0 +1,89 @@
+"""The C ABI library loads and exports every symbol the header declares.
+
+Host-only calls (sizing, argument checks that fail before any device work,
+names, version) run without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "apsp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(apsp_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2412_15122_amd import _native as N
+    return N.load()
+
+
+def test_header_declares_the_north_star_calls():
+    names = declared_functions()
+    for required in ("apsp_cold", "apsp_add_node", "apsp_remove_node", "apsp_update_edge", "apsp_query"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2412_15122_amd import _native as N
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in N.SIGNATURES, f"binding lacks {name}"
+
+
+def test_constants_match_header(lib):
+    from paper_2412_15122_amd import _native as N
+    text = open(HEADER).read()
+    assert int(re.search(r"#define APSP_INF (\d+)", text).group(1)) == N.APSP_INF == 1 << 30
+    assert int(re.search(r"#define APSP_MAX_CAPACITY (\d+)", text).group(1)) == N.APSP_MAX_CAPACITY
+    assert lib.apsp_abi_version() == int(re.search(r"#define APSP_ABI_VERSION (\d+)", text).group(1))
+    for name in ("APSP_OK", "APSP_E_INVALID", "APSP_E_NOT_FOUND", "APSP_E_CAPACITY", "APSP_E_DEVICE", "APSP_E_VALUE"):
+        m = re.search(name + r"\s*=\s*(-?\d+)", text)
+        assert int(m.group(1)) == getattr(N, name)
+
+
+def test_required_bytes(lib):
+    from paper_2412_15122_amd import _native as N
+    assert lib.apsp_required_bytes(0, 0) == 0
+    assert lib.apsp_required_bytes(N.APSP_MAX_CAPACITY + 1, 0) == 0
+    assert lib.apsp_required_bytes(10, 7) == 0
+    und = lib.apsp_required_bytes(16384, N.APSP_UNDIRECTED)
+    dire = lib.apsp_required_bytes(16384, N.APSP_DIRECTED)
+    mat = 16384 * 16384 * 4
+    assert 2 * mat <= und < 2 * mat + (256 << 20)     # D + A + index + workspace
+    assert dire - und >= mat                          # plus the transpose
+    assert lib.apsp_required_bytes(100, 0) % 256 == 0
+
+
+def test_cold_argument_checks_fail_before_device_work(lib):
+    from paper_2412_15122_amd import _native as N
+    h = ctypes.c_void_p()
+    assert lib.apsp_cold(None, 4, 4, 0, 8, None, 0, None, None) == N.APSP_E_INVALID
+    assert lib.apsp_cold(None, 4, 4, 0, 8, None, 0, None, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert b"adjacency" in lib.apsp_last_error()
+    assert lib.apsp_cold(None, 0, 0, 3, 8, None, 0, None, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert lib.apsp_cold(None, 9, 9, 0, 8, None, 0, None, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert lib.apsp_cold(None, 0, 0, 0, 8, ctypes.c_void_p(256), 16, None, ctypes.byref(h)) == N.APSP_E_CAPACITY
+    assert lib.apsp_cold(None, 0, 0, 0, 8, ctypes.c_void_p(257), 1 << 40, None, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert h.value is None
+
+
+def test_null_handle_checks(lib):
+    from paper_2412_15122_amd import _native as N
+    assert lib.apsp_remove_node(None, 0) == N.APSP_E_INVALID
+    assert lib.apsp_update_edge(None, 0, 1, 5) == N.APSP_E_INVALID
+    assert lib.apsp_add_node(None, None, None, None) == N.APSP_E_INVALID
+    assert lib.apsp_graph_destroy(None) == N.APSP_OK
+
+
+def test_kernel_names(lib):
+    names = [lib.apsp_kernel_name(k).decode() for k in range(lib.apsp_kernel_count())]
+    assert "mask_recompute" in names and "add_relax" in names and "fw_tiles" in names
+    assert lib.apsp_kernel_name(-1) == b""
