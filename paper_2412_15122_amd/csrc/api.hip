@@ -207,8 +207,11 @@ apsp_status run_cold(apsp_graph *g) {
     g->prof.begin(KID_MISC);
     launch_copy_square(g->dg.D, g->dg.A, g->dg.ld, n, g->stream);
     g->prof.end();
-    launch_fw(g->dg, n, g->stream, &g->prof);
-    return check_launch("cold Floyd-Warshall");
+    apsp_status st = check_launch("cold start copy");
+    if (st) return st;
+    if (const char *bad = launch_fw(g->dg, n, g->stream, &g->prof))
+        return fail(APSP_E_DEVICE, std::string("Floyd-Warshall launch failed: ") + bad);
+    return APSP_OK;
 }
 
 // Algorithm 5's decision for the pending mask (rows/flags counted on the
@@ -312,7 +315,10 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
     g->prof_impl.stream = g->stream;
     g->prof.impl = &g->prof_impl;
 
-    configure_kernels();
+    if (hipError_t e = configure_kernels(); e != hipSuccess) {
+        apsp_graph_destroy(g);
+        return fail(APSP_E_DEVICE, std::string("configuring kernels: ") + hipGetErrorString(e));
+    }
     hipStream_t s = g->stream;
     const int64_t PP = (int64_t)g->P * g->P;
     launch_fill(d.D, PP, (int32_t)INF, s);
@@ -322,12 +328,21 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
     launch_fill(d.nin_cnt, g->P, 0, s);
     launch_fill(d.nin_beta, g->P, (int32_t)INF, s);
     launch_fill((int32_t *)d.ctl, sizeof(Ctl) / 4, 0, s);
+    apsp_status st = check_launch("cold start fill");
+    if (st) {
+        apsp_graph_destroy(g);
+        return st;
+    }
     launch_load_adj(d, adj_dev, adj_ld, n, s);
     if (d.AT) launch_transpose(d.A, d.AT, d.ld, n, s);
     d.n_slots = n;
     launch_iota(d.id_of_slot, n, s);
     launch_iota(g->rank_cur, n, s);
-    apsp_status st = run_cold(g);
+    if ((st = check_launch("cold start load"))) {
+        apsp_graph_destroy(g);
+        return st;
+    }
+    st = run_cold(g);
     if (st) {
         apsp_graph_destroy(g);
         return st;

@@ -78,7 +78,8 @@ void launch_iota(int32_t *p, int32_t n, hipStream_t s);
 
 // Floyd-Warshall over slots [0, n): three launches per 128-wide round.
 struct Prof;
-void launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof);
+// Returns the name of a kernel whose launch failed, or nullptr.
+const char *launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof);
 
 // Light in-edge index.
 void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t only_short, hipStream_t s);
@@ -130,7 +131,7 @@ void launch_edge_scope(const DevGraph &g, int32_t su, int32_t sv, hipStream_t s)
 
 size_t fused_lds_bytes(int32_t P);
 size_t nin_build_lds_bytes(int32_t P);
-void configure_kernels();  // raise dynamic-LDS limits once per process
+hipError_t configure_kernels();  // raise dynamic-LDS limits once per process
 
 // Kernel ids for per-kernel timing (apsp_profile).
 enum KernelId : int32_t {

@@ -282,22 +282,26 @@ __global__ __launch_bounds__(256) void k_fw_tiles(int32_t *D, int64_t ld, int32_
     minplus_tile(Ap, Bp, C, ld, As, Bs);
 }
 
-void launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof) {
-    if (n <= 0) return;
+const char *launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof) {
+    if (n <= 0) return nullptr;
     const int32_t nb = (n + TILE - 1) / TILE;
     for (int32_t r = 0; r < nb; ++r) {
         if (prof) prof->begin(KID_FW_PIVOT);
         k_fw_pivot<<<1, 1024, 0, s>>>(g.D, g.ld, r);
         if (prof) prof->end();
+        if (hipGetLastError() != hipSuccess) return "fw_pivot";
         if (nb > 1) {
             if (prof) prof->begin(KID_FW_PANEL);
             k_fw_panel<<<2 * (nb - 1), 256, 0, s>>>(g.D, g.ld, r, nb);
             if (prof) prof->end();
+            if (hipGetLastError() != hipSuccess) return "fw_panel";
             if (prof) prof->begin(KID_FW_TILE);
             k_fw_tiles<<<(nb - 1) * (nb - 1), 256, 0, s>>>(g.D, g.ld, r, nb);
             if (prof) prof->end();
+            if (hipGetLastError() != hipSuccess) return "fw_tiles";
         }
     }
+    return nullptr;
 }
 
 }  // namespace apsp

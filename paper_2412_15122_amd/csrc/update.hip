@@ -860,12 +860,19 @@ void launch_fused(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
 
 size_t nin_build_lds_bytes(int32_t) { return 0; }
 
-void configure_kernels() {
-    static bool done = false;
-    if (done) return;
-    done = true;
-    (void)hipFuncSetAttribute((const void *)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)fused_lds_bytes(((APSP_MAX_CAPACITY + TILE - 1) / TILE) * TILE));
+// The mask + recompute kernel keeps a whole row in LDS; APSP_MAX_CAPACITY is
+// the largest capacity whose row (plus flags) fits the 160 KiB of one CU.
+static_assert(APSP_MAX_CAPACITY % TILE == 0, "capacity limit must be a tile multiple");
+static_assert(((size_t)APSP_MAX_CAPACITY + 2 * (APSP_MAX_CAPACITY / 32) + 64) * 4 <= 163840,
+              "a row of the largest graph must fit in LDS");
+
+hipError_t configure_kernels() {
+    static hipError_t status = hipErrorNotReady;
+    if (status != hipErrorNotReady) return status;
+    status = hipFuncSetAttribute((const void *)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)fused_lds_bytes(APSP_MAX_CAPACITY));
+    (void)hipGetLastError();  // do not leave the status for an unrelated launch check
+    return status;
 }
 
 }  // namespace apsp

@@ -185,7 +185,7 @@ def _draw_weights(rng, m: int, wmin: int, wmax: int, density: float) -> np.ndarr
 def make_update(rng, st: GraphState, kind: str, *, wmin: int, wmax: int,
                 inc_max: int, density: float = 1.0) -> Update:
     """Draw one update of `kind` against the current state and apply it to the
-    bookkeeping.  Decrease: new weight uniform on [1, old]; increase: uniform on
+    bookkeeping.  Decrease: new weight uniform on [1, old] (0 stays 0); increase: uniform on
     [old, max(old, inc_max)]."""
     if kind == ADD:
         m = len(st.live)
@@ -199,7 +199,7 @@ def make_update(rng, st: GraphState, kind: str, *, wmin: int, wmax: int,
         return Update(REMOVE, u=k)
     u, v, old = _pick_edge(rng, st)
     if kind == DECREASE:
-        w = int(rng.integers(1, old + 1))
+        w = int(rng.integers(min(1, old), old + 1))   # a zero-weight edge stays 0
     elif kind == INCREASE:
         w = int(rng.integers(old, max(old, inc_max) + 1))
     else:
