@@ -1,0 +1,352 @@
+"""Benchmark: warm-start APSP updates on one MI355X.
+
+Workload: undirected complete graph, n = 16384, symmetric int32 weights
+U[1, 10000] (D = 1 GiB).  One step = 1000 updates applied in sequence
+(300 add-node / 200 remove-node / 250 edge decrease / 250 edge increase,
+seeded shuffle; the first is the worst-case increase of the step: among the
+64 lightest edges, the one with the largest |R| * |C|, raised to 20000).
+Every input (graph, add-node weight vectors) is resident in HBM before the
+timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384]
+                  [--no-cpu-baseline] [--no-verify]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
+N_DEFAULT = 16384
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=N_DEFAULT)
+    ap.add_argument("--updates", type=int, default=1000, help="updates per step (multiple of 20)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--cold-reps", type=int, default=3)
+    ap.add_argument("--trace", action="store_true", help="log per-update mask statistics during warmup")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# algorithmic bytes per launch of the sweep kernels
+# ---------------------------------------------------------------------------
+# add_relax reads every live row of D once (the new pair distances need every
+# old entry); mask_recompute reads every row it visits once.  Writes are the
+# changed / recomputed entries only and are not counted (they are a small,
+# data-dependent fraction).
+
+def algorithmic_bytes(kind, n_live, stats):
+    if kind == "add_relax":
+        return 4 * n_live * n_live
+    if kind == "mask_recompute":
+        if stats["kind"] == 2:                      # removal: every live row but k
+            return 4 * (n_live - 1) * n_live
+        if stats["kind"] == 4:                      # increase: rows of R only
+            return 4 * stats.get("rows_visited", 0) * n_live
+        return 0
+    return 0
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2412_15122_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2412_15122_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(kernel)
+    if not ent or ent.get("source_hash") != source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle's cold Floyd-Warshall, sampled
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(adj, budget_s=12.0):
+    from oracle import oracle as O
+    n = adj.shape[0]
+    D = O.fw_init(adj)
+    threads = O.max_threads()
+    done = 0
+    t0 = time.perf_counter()
+    chunk = 4
+    while done < n and time.perf_counter() - t0 < budget_s:
+        k1 = min(n, done + chunk)
+        O.fw_pivots(D, done, k1, threads)
+        done = k1
+        chunk = min(64, chunk * 2)
+    el = time.perf_counter() - t0
+    per_pivot = el / done
+    full = per_pivot * n
+    return {
+        "value": 1.0 / full,
+        "unit": "updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"textbook Floyd-Warshall (the oracle's cold recompute of one updated graph) at n={n}: "
+                   f"pivots 0..{done - 1} of {n} timed ({el:.1f} s, {per_pivot * 1e3:.1f} ms/pivot), "
+                   f"extrapolated to the full {n} pivots = {full:.0f} s per update"),
+    }
+
+
+# ---------------------------------------------------------------------------
+# main
+# ---------------------------------------------------------------------------
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the hot path is single-GPU by design "
+              "(multi-GPU sharding is described, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2412_15122_amd import workloads as W
+    from paper_2412_15122_amd.apsp import Graph, kernel_names
+    from paper_2412_15122_amd import _native as N
+
+    torch.cuda.set_device(0)
+    n = args.n
+    steps_total = args.warmup + args.steps
+    per = args.updates
+    counts = {W.ADD: per * 3 // 10, W.REMOVE: per * 2 // 10, W.DECREASE: per // 4, W.INCREASE: per // 4}
+    counts[W.INCREASE] = per - counts[W.ADD] - counts[W.REMOVE] - counts[W.DECREASE]
+    growth = counts[W.ADD] - counts[W.REMOVE]
+    cap = n + max(growth, 0) * steps_total + 256
+
+    t = time.perf_counter()
+    adj = W.config3_graph(n)
+    log(f"[bench] graph n={n} generated in {time.perf_counter() - t:.1f}s")
+    g = Graph(adj, undirected=True, capacity=cap)
+    torch.cuda.synchronize()
+    log("[bench] cold start done")
+    names = kernel_names()
+    kid = {nm: i for i, nm in enumerate(names)}
+
+    # GPU cold blocked Floyd-Warshall at n (median of reps)
+    cold_ms = []
+    for _ in range(args.cold_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.recompute_cold()
+        e1.record()
+        torch.cuda.synchronize()
+        cold_ms.append(e0.elapsed_time(e1))
+    cold_med = float(np.median(cold_ms))
+    log(f"[bench] GPU cold FW n={n}: {cold_med:.1f} ms (reps {['%.1f' % c for c in cold_ms]})")
+
+    stream = W.Config3Stream(adj, counts=counts)
+    cand_base = W.lightest_edges(adj, 64, True)
+
+    def worst_case_edge():
+        live = set(g.ids())
+        best, best_key = None, None
+        for (u, v, _) in cand_base:
+            if u not in live or v not in live:
+                continue
+            r, c = g.edge_scope(u, v)
+            key = (-(r * c), u, v)
+            if best_key is None or key < best_key:
+                best, best_key = (u, v), key
+        return (best[0], best[1], 20000)
+
+    def stage(block):
+        """Upload every add-node weight vector of the block (inputs resident
+        in HBM before timing)."""
+        vecs = [u.w_out for u in block if u.kind == W.ADD]
+        flat = np.concatenate(vecs) if vecs else np.zeros(1, np.int32)
+        dev = torch.from_numpy(np.ascontiguousarray(flat, dtype=np.int32)).cuda()
+        ptrs, off = [], 0
+        for u in block:
+            if u.kind == W.ADD:
+                ptrs.append(dev.data_ptr() + 4 * off)
+                off += u.w_out.size
+            else:
+                ptrs.append(None)
+        return dev, ptrs
+
+    def run_block(block, ptrs, events, trace=None):
+        for i, u in enumerate(block):
+            if u.kind == W.ADD:
+                g.add_node_device(ptrs[i], ptrs[i])
+            elif u.kind == W.REMOVE:
+                g.remove_node(u.u)
+            else:
+                g.update_edge(u.u, u.v, u.w)
+            if events is not None:
+                events[i].record()
+            if trace is not None and u.kind in (W.REMOVE, W.INCREASE, W.ADD):
+                trace.append((u.kind, g.stats()))
+
+    lat_ms = []
+    kinds_all = []
+    timed_ms = 0.0
+    prof_kernel = None
+    prof_totals = {}
+    alg_bytes_total = 0
+    stats_all = []
+    for step in range(steps_total):
+        timed = step >= args.warmup
+        worst = worst_case_edge()
+        block = stream.next_block(worst=worst)
+        dev, ptrs = stage(block)
+        torch.cuda.synchronize()
+        if step == 0:
+            g.profile(-1)          # every kernel: find the dominant one
+        elif timed and prof_kernel is not None:
+            g.profile(1 << kid[prof_kernel])
+        events = [torch.cuda.Event(enable_timing=True) for _ in block] if timed else None
+        start = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record()
+        trace = [] if (args.trace and not timed) else None
+        run_block(block, ptrs, events, trace)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if trace:
+            for kind in (W.REMOVE, W.INCREASE, W.ADD):
+                ss = [st for k, st in trace if k == kind and not st["noop"]]
+                if not ss:
+                    continue
+                keys = ("flagged", "rows", "sweeps", "full_scans", "rows_relaxed")
+                log(f"[bench] trace {kind}: {len(ss)} non-noop; " + ", ".join(
+                    f"{k} mean {np.mean([st[k] for st in ss]):.1f} max {max(st[k] for st in ss)}" for k in keys))
+        if step == 0:
+            tot = {nm: g.profile_read(kid[nm]) for nm in names}
+            prof_totals = {nm: v for nm, v in tot.items() if v[0]}
+            sweep = {nm: v[1] for nm, v in prof_totals.items() if nm in ("add_relax", "mask_recompute")}
+            prof_kernel = max(sweep, key=sweep.get) if sweep else None
+            g.profile(0)
+            log("[bench] kernel totals (step 0): " +
+                ", ".join(f"{nm}={v[1]:.1f}ms/{v[0]}" for nm, v in sorted(prof_totals.items(), key=lambda x: -x[1][1])))
+        log(f"[bench] step {step} ({'timed' if timed else 'warmup'}): {1e3 * (t1 - t0):.1f} ms for {len(block)} updates")
+        if timed:
+            timed_ms += 1e3 * (t1 - t0)
+            prev = start
+            for ev in events:
+                lat_ms.append(prev.elapsed_time(ev))
+                prev = ev
+            kinds_all += [u.kind for u in block]
+            if prof_kernel is not None:
+                c, ms = g.profile_read(kid[prof_kernel])
+                prof_totals.setdefault("timed", [0, 0.0])
+                prof_totals["timed"][0] += c
+                prof_totals["timed"][1] += ms
+                g.profile(0)
+        del dev
+
+    # algorithmic bytes of the dominant kernel over the timed steps: replay the
+    # live counts (every add / remove changes n by one)
+    live = n + growth * args.warmup
+    removes_bytes = adds_bytes = 0
+    launches = {"add_relax": 0, "mask_recompute": 0}
+    for k in kinds_all:
+        if k == W.ADD:
+            adds_bytes += 4 * live * live
+            launches["add_relax"] += 1
+            live += 1
+        elif k == W.REMOVE:
+            removes_bytes += 4 * (live - 1) * live
+            launches["mask_recompute"] += 1
+            live -= 1
+        elif k == W.INCREASE:
+            launches["mask_recompute"] += 1
+    roofline = None
+    if prof_kernel and "timed" in prof_totals and prof_totals["timed"][1] > 0:
+        c, ms = prof_totals["timed"]
+        alg = adds_bytes if prof_kernel == "add_relax" else removes_bytes
+        achieved = alg / (ms * 1e-3) / 1e9
+        tb = traffic_from_profiles(prof_kernel)
+        roofline = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
+            "kernel": prof_kernel, "launches": c, "avg_launch_ms": round(ms / max(c, 1), 4),
+            "algorithmic_bytes_per_launch": round(alg / max(c, 1)),
+        }
+
+    verify = None
+    if not args.no_verify:
+        # warm result == GPU cold Floyd-Warshall of the final graph
+        A_final = g.matrix_device("A")
+        D_warm = g.matrix_device("D")
+        g2 = Graph(A_final, undirected=True, capacity=A_final.shape[0])
+        verify = bool(torch.equal(D_warm, g2.matrix_device("D")))
+        g2.close()
+        del A_final, D_warm
+        log(f"[bench] warm == GPU cold on the final graph: {verify}")
+
+    K = args.steps
+    ms_per_step = timed_ms / K
+    value = per / (ms_per_step * 1e-3)
+    lat = np.array(lat_ms)
+    by_kind = {}
+    for k in (W.ADD, W.REMOVE, W.DECREASE, W.INCREASE):
+        sel = np.array([kk == k for kk in kinds_all])
+        if sel.any():
+            by_kind[k] = round(float(lat[sel].mean()), 4)
+    out = {
+        "metric": "warm-start APSP updates/s (n=16384, 1 GPU)",
+        "value": round(value, 2),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"undirected complete graph n={n}, symmetric weights U[1,10000], "
+                         f"{per} sequential updates per step ({counts[W.ADD]} add / {counts[W.REMOVE]} remove / "
+                         f"{counts[W.DECREASE]} decrease / {counts[W.INCREASE]} increase incl. one worst-case increase)"),
+            "n": n, "updates_per_step": per, "parallelism": "none (1 GPU)",
+        },
+        "cold_fw_ms": round(cold_med, 2),
+        "cold_updates_per_s": round(1e3 / cold_med, 3),
+        "warm_vs_cold_speedup": round(cold_med / (ms_per_step / per), 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                       "mean_by_kind": by_kind},
+        "verified_vs_gpu_cold": verify,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle Floyd-Warshall, sampled)")
+        out["cpu_baseline"] = cpu_baseline(adj)
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,7 +64,7 @@ extern "C" {
 #define APSP_INF 1073741824
 #define APSP_ABI_VERSION 1
 /* Largest capacity (node slots) of one graph. */
-#define APSP_MAX_CAPACITY 38400
+#define APSP_MAX_CAPACITY 38272
 
 typedef enum {
     APSP_OK = 0,

@@ -24,7 +24,7 @@ APSP_UNDIRECTED = 1
 APSP_FALLBACK_NEVER = 0
 APSP_FALLBACK_COST = 1
 APSP_FALLBACK_ALWAYS = 2
-APSP_MAX_CAPACITY = 38400
+APSP_MAX_CAPACITY = 38272
 
 STATUS_NAMES = {
     APSP_OK: "APSP_OK", APSP_E_INVALID: "APSP_E_INVALID", APSP_E_NOT_FOUND: "APSP_E_NOT_FOUND",

@@ -28,7 +28,7 @@ int32_t padded(int32_t cap) { return ((cap + TILE - 1) / TILE) * TILE; }
 
 struct Layout {
     size_t D, A, AT, nin, nin_cnt, nin_beta, id_of_slot, vec, plist, rank_a, rank_b, qbuf, qscratch, fscratch,
-        ctl, total;
+        nin_queue, heavy_rows, heavy_epoch, ctl, total;
 };
 
 constexpr int NVEC = 8;  // wo, wi, out, in, colu, colv, rowu, rowv
@@ -57,6 +57,9 @@ Layout make_layout(int32_t cap, int32_t kind) {
     L.qbuf = take((P + 8) * 4);
     L.qscratch = take(4 * P * 4);
     L.fscratch = take((size_t)FUSED_GRID * 2 * P * 4);
+    L.nin_queue = take(P * 4);
+    L.heavy_rows = take(P * 4);
+    L.heavy_epoch = take(P * 4);
     L.ctl = take(sizeof(Ctl));
     L.total = off;
     return L;
@@ -138,7 +141,9 @@ struct apsp_graph {
     int2 *plist = nullptr;
     int32_t *plist_cnt = nullptr, *plist_beta = nullptr;
     int32_t *rank_cur = nullptr, *rank_other = nullptr;
-    int32_t *qbuf = nullptr, *qscratch = nullptr, *fscratch = nullptr;
+    int32_t *qbuf = nullptr, *qscratch = nullptr, *fscratch = nullptr, *nin_queue = nullptr;
+    int32_t *heavy_rows = nullptr, *heavy_epoch = nullptr;
+    int32_t epoch = 0;
     // host bookkeeping
     int32_t n_live = 0, max_id = -1;
     std::vector<int32_t> live_ids;  // ascending
@@ -312,6 +317,9 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
     g->qbuf = (int32_t *)(b + L.qbuf);
     g->qscratch = (int32_t *)(b + L.qscratch);
     g->fscratch = (int32_t *)(b + L.fscratch);
+    g->nin_queue = (int32_t *)(b + L.nin_queue);
+    g->heavy_rows = (int32_t *)(b + L.heavy_rows);
+    g->heavy_epoch = (int32_t *)(b + L.heavy_epoch);
     g->prof_impl.stream = g->stream;
     g->prof.impl = &g->prof_impl;
 
@@ -327,6 +335,7 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
     launch_fill(d.id_of_slot, g->P, -1, s);
     launch_fill(d.nin_cnt, g->P, 0, s);
     launch_fill(d.nin_beta, g->P, (int32_t)INF, s);
+    launch_fill(g->heavy_epoch, g->P, 0, s);
     launch_fill((int32_t *)d.ctl, sizeof(Ctl) / 4, 0, s);
     apsp_status st = check_launch("cold start fill");
     if (st) {
@@ -477,6 +486,9 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     fa.col1 = colu(g);
     fa.row1 = rowu(g);
     fa.scratch = g->fscratch;
+    fa.heavy_rows = g->heavy_rows;
+    fa.heavy_epoch = g->heavy_epoch;
+    fa.epoch = ++g->epoch;
     int32_t fallback = 0;
     apsp_status st = decide_fallback(g, fa, n_before, &fallback);
     if (st) return st;
@@ -491,13 +503,13 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     launch_tombstone(d, k, s);
     g->prof.end();
     g->prof.begin(KID_NIN_UPDATE);
-    launch_nin_purge(d, k, s);
+    launch_nin_purge(d, k, g->nin_queue, s);
     g->prof.end();
     if (fallback) {
         if ((st = run_cold(g))) return st;
     }
     g->prof.begin(KID_NIN_BUILD);
-    launch_nin_build(d, 0, d.n_slots, 1, s);
+    launch_nin_rebuild_queue(d, g->nin_queue, s);
     g->prof.end();
     launch_rank_remove(g->rank_cur, g->rank_other, r, n_before, s);
     if ((st = check_launch("apsp_remove_node"))) return st;
@@ -538,6 +550,9 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     fa.row1 = rowv(g);
     fa.row2 = rowu(g);
     fa.scratch = g->fscratch;
+    fa.heavy_rows = g->heavy_rows;
+    fa.heavy_epoch = g->heavy_epoch;
+    fa.epoch = ++g->epoch;
     int32_t fallback = 0;
     apsp_status st;
     if (g->policy != APSP_FALLBACK_NEVER) {

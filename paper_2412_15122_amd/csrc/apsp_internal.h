@@ -43,7 +43,9 @@ struct Ctl {
     int32_t scope_r;
     int32_t scope_c;
     int32_t count_only;   // set by the host for the Algorithm 5 cost pass
-    int32_t pad[3];
+    int32_t short_count;  // index lists queued for a rebuild
+    int32_t heavy_count;  // rows deferred to the heavy-row pass
+    int32_t pad[1];
 };
 
 // Device view of one graph, passed to kernels by value.
@@ -86,7 +88,10 @@ void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t o
 void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
                        int32_t *beta, hipStream_t s);
 void launch_nin_insert_node(const DevGraph &g, int32_t p, const int32_t *w_row, hipStream_t s);
-void launch_nin_purge(const DevGraph &g, int32_t k, hipStream_t s);
+// Drop node k from every list; lists that fall below NIN_L/2 while unlisted
+// in-edges exist are queued in `queue` and rebuilt by launch_nin_rebuild_queue.
+void launch_nin_purge(const DevGraph &g, int32_t k, int32_t *queue, hipStream_t s);
+void launch_nin_rebuild_queue(const DevGraph &g, const int32_t *queue, hipStream_t s);
 
 // Add node.
 void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32_t *w_in,
@@ -110,6 +115,9 @@ struct FusedArgs {
     const int32_t *row1;
     const int32_t *row2;
     int32_t *scratch;     // FUSED_GRID * 2 * P ints
+    int32_t *heavy_rows;  // [P] rows deferred to the heavy-row pass
+    int32_t *heavy_epoch; // [P] heavy_epoch[i] == epoch marks row i heavy
+    int32_t epoch;        // distinct for every mask pass
 };
 void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, int32_t *colb,
                       int32_t *rowa, int32_t *rowb, int32_t gate_on_edge, hipStream_t s);

@@ -264,20 +264,44 @@ void launch_nin_insert_node(const DevGraph &g, int32_t p, const int32_t *w_row, 
     k_nin_insert_node<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, p, w_row);
 }
 
-// Node k is gone: drop it from every list; its own list empties.
-__global__ __launch_bounds__(256) void k_nin_purge(DevGraph g, int32_t k) {
+// Node k is gone: drop it from every list; its own list empties.  A list
+// left with fewer than NIN_L/2 entries while unlisted in-edges remain is
+// queued for a rebuild.
+__global__ __launch_bounds__(256) void k_nin_purge(DevGraph g, int32_t k, int32_t *queue) {
     const int32_t y = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (y >= g.n_slots) return;
     if (y == k) {
+        g.nin[(int64_t)y * NIN_L + lane_id()] = make_int2(0, (int)INF);
         if (lane_id() == 0) { g.nin_cnt[y] = 0; g.nin_beta[y] = (int32_t)INF; }
         return;
     }
+    const int before = g.nin_cnt[y];
     wave_list_purge(g, y, k);
+    if (lane_id() == 0 && before >= NIN_L / 2 && before - 1 < NIN_L / 2 && (uint32_t)g.nin_beta[y] < INF &&
+        g.id_of_slot[y] >= 0) {
+        queue[atomicAdd(&g.ctl->short_count, 1)] = y;
+    }
 }
 
-void launch_nin_purge(const DevGraph &g, int32_t k, hipStream_t s) {
+void launch_nin_purge(const DevGraph &g, int32_t k, int32_t *queue, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_nin_purge<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, k);
+    k_nin_purge<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, k, queue);
+}
+
+__global__ __launch_bounds__(256) void k_nin_rebuild_queue(DevGraph g, const int32_t *queue) {
+    __shared__ SelectShared sh;
+    const int count = g.ctl->short_count;
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int32_t y = queue[idx];
+        select_light(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, g.nin + (int64_t)y * NIN_L, g.nin_cnt + y,
+                     g.nin_beta + y, sh);
+        __syncthreads();
+    }
+}
+
+void launch_nin_rebuild_queue(const DevGraph &g, const int32_t *queue, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_nin_rebuild_queue<<<32, 256, 0, s>>>(g, queue);
 }
 
 // ---------------------------------------------------------------------------
@@ -494,6 +518,8 @@ __global__ void k_reset_stats(DevGraph g) {
     c->rows_relaxed = 0;
     c->scope_r = 0;
     c->scope_c = 0;
+    c->short_count = 0;
+    c->heavy_count = 0;
 }
 
 void launch_reset_stats(const DevGraph &g, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(g); }
@@ -584,6 +610,7 @@ __global__ __launch_bounds__(64) void k_edge_begin(DevGraph g, int32_t su, int32
         c->full_scans = 0;
         c->sweeps = 0;
         c->rows_relaxed = 0;
+        c->heavy_count = 0;
         g.A[(int64_t)su * ld + sv] = w;
         if (g.undirected) g.A[(int64_t)sv * ld + su] = w;
         else g.AT[(int64_t)sv * ld + su] = w;
@@ -671,19 +698,241 @@ void launch_dec_relax(const DevGraph &g, const int32_t *colu, const int32_t *col
 // Every value written is the length of a real walk in G' and the final row
 // satisfies every edge inequality of G', so it equals SPD in G' exactly.
 
-size_t fused_lds_bytes(int32_t P) {
-    return ((size_t)P + 2 * (size_t)((P + 31) / 32) + 64) * sizeof(uint32_t);
+// Minimum over a group of 16 lanes (xor offsets below 16 stay in the group).
+__device__ __forceinline__ uint32_t group16_min(uint32_t v) {
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 16));
+    return v;
 }
 
+constexpr int FUSED_UNROLL = 8;  // int4 loads in flight per thread and row
+constexpr int LDS_LIST = 128;    // flagged columns kept in LDS; also the heavy-row threshold
+
+// LDS words: cur[P] | two flag bitmaps | list[LDS_LIST] | 64 scratch words.
+size_t fused_lds_bytes(int32_t P) {
+    return ((size_t)P + 2 * (size_t)((P + 31) / 32) + LDS_LIST + 64) * sizeof(uint32_t);
+}
+
+struct FusedShared {
+    uint32_t *cur, *fl, *fl2, *red, *flag_changed, *flag_nfs;
+    int32_t *list_lds;
+};
+
+__device__ FusedShared fused_shared(const DevGraph &g, uint32_t *sm) {
+    FusedShared f;
+    const int nwp = (g.P + 31) >> 5;
+    f.cur = sm;
+    f.fl = sm + g.P;
+    f.fl2 = f.fl + nwp;
+    f.list_lds = (int32_t *)(f.fl2 + nwp);
+    f.red = (uint32_t *)(f.list_lds + LDS_LIST);
+    f.flag_changed = f.red + 32;
+    f.flag_nfs = f.red + 33;
+    return f;
+}
+
+// The pair tests of row i (block-uniform).
+struct RowTests {
+    bool t1, t2;
+    uint32_t a1, a2;
+};
+
+__device__ RowTests row_tests(const DevGraph &g, const FusedArgs &fa, int32_t i, uint32_t w_old) {
+    RowTests r{false, false, 0, 0};
+    if (fa.mode == FUSED_REMOVE) {
+        const uint32_t dik = (uint32_t)fa.col1[i];
+        r.t1 = (i != fa.k) && dik < INF;
+        r.a1 = dik;
+    } else {
+        const uint32_t cu = (uint32_t)fa.col1[i], cv = (uint32_t)fa.col2[i];
+        r.t1 = cv < INF && cu + w_old == cv;
+        r.a1 = cv;
+        if (g.undirected) {
+            r.t2 = cu < INF && cv + w_old == cu;
+            r.a2 = cu;
+        }
+    }
+    return r;
+}
+
+// Mask pass over row i.  Each lane tests 4 consecutive columns; 8 lanes
+// assemble a 32-bit flag word with shuffles (no clearing, no atomics).
+//   fill == 0: cur[j] = INF for flagged j, D[i][j] otherwise (fl = flags)
+//   fill == 1: (heavy-row pass) flagged j whose row is light takes the
+//              mirrored D[j][i]; flagged j whose row is heavy (heavy[j] ==
+//              epoch) is INF and goes to fl2; fl = all flags.
+// Returns this thread's flag count.
+__device__ int mask_row(const DevGraph &g, const FusedArgs &fa, int32_t i, const RowTests &rt, FusedShared &sh,
+                        bool write_cur, int fill) {
+    const int n = g.n_slots;
+    const int tid = threadIdx.x, lane = lane_id();
+    const int32_t *Drow = g.D + (int64_t)i * g.ld;
+    int cnt = 0;
+    // the trip count is block-uniform: the shuffles below need every lane
+    for (int b = 0; b * 4 < n; b += FUSED_THREADS * FUSED_UNROLL) {
+        const int q0 = b + tid;
+        uint4 d[FUSED_UNROLL], r1[FUSED_UNROLL], r2[FUSED_UNROLL];
+#pragma unroll
+        for (int u = 0; u < FUSED_UNROLL; ++u) {
+            const int j0 = (q0 + u * FUSED_THREADS) * 4;
+            d[u] = make_uint4(INF, INF, INF, INF);
+            r1[u] = r2[u] = make_uint4(0, 0, 0, 0);
+            if (j0 < n) {
+                d[u] = *reinterpret_cast<const uint4 *>(Drow + j0);
+                if (rt.t1) r1[u] = *reinterpret_cast<const uint4 *>(fa.row1 + j0);
+                if (rt.t2) r2[u] = *reinterpret_cast<const uint4 *>(fa.row2 + j0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < FUSED_UNROLL; ++u) {
+            const int j0 = (q0 + u * FUSED_THREADS) * 4;
+            const uint32_t dv[4] = {d[u].x, d[u].y, d[u].z, d[u].w};
+            const uint32_t v1[4] = {r1[u].x, r1[u].y, r1[u].z, r1[u].w};
+            const uint32_t v2[4] = {r2[u].x, r2[u].y, r2[u].z, r2[u].w};
+            uint32_t bits = 0, hbits = 0;
+            uint32_t cv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = j0 + e;
+                uint32_t dj = dv[e];
+                bool f = false;
+                if (j < n && j != i && dj < INF) f = (rt.t1 && rt.a1 + v1[e] == dj) || (rt.t2 && rt.a2 + v2[e] == dj);
+                if (fa.mode == FUSED_REMOVE && j == fa.k) {
+                    f = false;
+                    dj = INF;
+                }
+                bits |= (uint32_t)f << e;
+                cv[e] = dj;
+                if (f) {
+                    if (fill == 1 && fa.heavy_epoch[j] != fa.epoch) {
+                        cv[e] = (uint32_t)g.D[(int64_t)j * g.ld + i];
+                    } else {
+                        cv[e] = INF;
+                        hbits |= 1u << e;
+                    }
+                }
+            }
+            cnt += __popc(bits);
+            uint32_t word = bits << ((lane & 7) * 4);
+            uint32_t hword = hbits << ((lane & 7) * 4);
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                word |= (uint32_t)__shfl_xor((int)word, o);
+                hword |= (uint32_t)__shfl_xor((int)hword, o);
+            }
+            if (j0 < n) {
+                if (write_cur) *reinterpret_cast<uint4 *>(sh.cur + j0) = make_uint4(cv[0], cv[1], cv[2], cv[3]);
+                if ((lane & 7) == 0) {
+                    sh.fl[j0 >> 5] = word;
+                    if (fill == 1) sh.fl2[j0 >> 5] = hword;
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+// Bitmap words -> ascending column list (block-wide); returns the count.
+__device__ int compact_bits(const uint32_t *bm, int nw, int32_t *list, uint32_t *red) {
+    const int tid = threadIdx.x;
+    const int per = (nw + FUSED_THREADS - 1) / FUSED_THREADS;
+    const int w0 = min(nw, tid * per), w1 = min(nw, w0 + per);
+    int c = 0;
+    for (int w = w0; w < w1; ++w) c += __popc(bm[w]);
+    int tot;
+    int off = block_exscan256(c, red, &tot);
+    for (int w = w0; w < w1; ++w) {
+        uint32_t bits = bm[w];
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            list[off++] = w * 32 + b;
+        }
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Bellman-Ford relaxation of the columns list[0..total) of the LDS row cur:
+//   cur[y] = min_x cur[x] (+) A'[x][y]
+// Sweeps scan each y's light in-edges (16 lanes per y, 16 entries per
+// load, stopping once an entry is at least the current value; unused
+// entries are (0, INF) sentinels).  When the sweeps are stable, every y
+// above its index bound beta gets an exhaustive scan of its in-edges, and
+// the sweeps resume if that changed anything.
+__device__ void row_bellman_ford(const DevGraph &g, FusedShared &sh, const int32_t *list, int total, int32_t *fsl,
+                                 int &sweeps, int &nfs_total) {
+    const int n = g.n_slots;
+    const int tid = threadIdx.x;
+    const int grp = tid >> 4, gl = tid & 15;
+    const int lim = g.lim;
+    const int32_t *Min = in_matrix(g);
+    uint32_t *cur = sh.cur;
+    for (;;) {
+        for (;;) {
+            __syncthreads();
+            if (tid == 0) *sh.flag_changed = 0;
+            __syncthreads();
+            for (int e = grp; e < total; e += FUSED_THREADS / 16) {
+                const int32_t y = list[e];
+                uint32_t best = cur[y];
+                const int2 *L = g.nin + (int64_t)y * NIN_L;
+                for (int c0 = 0; c0 < lim; c0 += 16) {
+                    const int e2 = c0 + gl;
+                    const int2 ent = e2 < lim ? L[e2] : make_int2(0, (int)INF);
+                    const uint32_t cand = (uint32_t)ent.y < best ? cur[ent.x] + (uint32_t)ent.y : INF;
+                    best = min(best, group16_min(cand));
+                    const uint32_t wlast = (uint32_t)__shfl(ent.y, 15, 16);
+                    if (wlast >= best) break;  // every later entry is at least as heavy
+                }
+                if (gl == 0 && best < cur[y]) {
+                    cur[y] = best;
+                    *sh.flag_changed = 1;
+                }
+            }
+            __syncthreads();
+            ++sweeps;
+            if (*sh.flag_changed == 0) break;
+        }
+        __syncthreads();
+        if (tid == 0) *sh.flag_nfs = 0;
+        __syncthreads();
+        for (int e = tid; e < total; e += FUSED_THREADS) {
+            const int32_t y = list[e];
+            uint32_t beta_eff = (uint32_t)g.nin_beta[y];
+            if (lim < NIN_L) beta_eff = min(beta_eff, (uint32_t)g.nin[(int64_t)y * NIN_L + lim].y);
+            if (cur[y] > beta_eff) fsl[atomicAdd(sh.flag_nfs, 1u)] = y;
+        }
+        __syncthreads();
+        const int nfs = (int)*sh.flag_nfs;
+        if (nfs == 0) break;
+        if (tid == 0) *sh.flag_changed = 0;
+        for (int f = 0; f < nfs; ++f) {
+            const int32_t y = fsl[f];
+            const int32_t *col = Min + (int64_t)y * g.ld;
+            uint32_t best = INF;
+            for (int32_t x = tid; x < n; x += FUSED_THREADS) best = min(best, cur[x] + (uint32_t)col[x]);
+            best = block_min256(best, sh.red);
+            if (tid == 0 && best < cur[y]) {
+                cur[y] = best;
+                *sh.flag_changed = 1;
+            }
+            __syncthreads();
+        }
+        nfs_total += nfs;
+        __syncthreads();
+        if (*sh.flag_changed == 0) break;
+    }
+}
+
+// Pass A: every affected row.  Undirected graphs defer rows with more than
+// LDS_LIST flagged columns ("heavy" rows) to pass B: there, D' being
+// symmetric, a flagged (i, j) whose row j is light is copied from D'[j][i].
 __global__ __launch_bounds__(FUSED_THREADS) void k_fused(DevGraph g, FusedArgs fa) {
     extern __shared__ uint32_t sm[];
+    FusedShared sh = fused_shared(g, sm);
     const int n = g.n_slots;
     const int nw = (n + 31) >> 5;
-    uint32_t *cur = sm;
-    uint32_t *fl = sm + g.P;
-    uint32_t *red = fl + 2 * ((g.P + 31) >> 5);  // 64 words
-    uint32_t *flag_changed = red + 32;
-    uint32_t *flag_nfs = red + 33;
     const int tid = threadIdx.x;
     uint32_t w_old = 0;
     if (fa.mode == FUSED_INCREASE) {
@@ -691,64 +940,16 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused(DevGraph g, FusedArgs f
         w_old = (uint32_t)g.ctl->w_old;
     }
     const bool count_only = g.ctl->count_only != 0;
-    const int32_t *Min = in_matrix(g);
-    int32_t *list = fa.scratch + (int64_t)blockIdx.x * 2 * g.P;
-    int32_t *fsl = list + g.P;
+    const bool defer = g.undirected && !count_only;
+    int32_t *glist = fa.scratch + (int64_t)blockIdx.x * 2 * g.P;
+    int32_t *fsl = glist + g.P;
     unsigned long long my_flagged = 0;
     int my_rows = 0, my_fs = 0, my_sweeps = 0;
 
     for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        bool t1 = false, t2 = false;
-        uint32_t a1 = 0, a2 = 0;
-        if (fa.mode == FUSED_REMOVE) {
-            const uint32_t dik = (uint32_t)fa.col1[i];
-            t1 = (i != fa.k) && dik < INF;
-            a1 = dik;
-        } else {
-            const uint32_t cu = (uint32_t)fa.col1[i], cv = (uint32_t)fa.col2[i];
-            t1 = cv < INF && cu + w_old == cv;
-            a1 = cv;
-            if (g.undirected) {
-                t2 = cu < INF && cv + w_old == cu;
-                a2 = cu;
-            }
-        }
-        if (!t1 && !t2) continue;
-
-        // 1. mask
-        for (int w = tid; w < nw; w += FUSED_THREADS) fl[w] = 0;
-        __syncthreads();
-        const int32_t *Drow = g.D + (int64_t)i * g.ld;
-        int cnt = 0;
-        for (int q = tid; q * 4 < n; q += FUSED_THREADS) {
-            const int j0 = q * 4;
-            uint4 d = *reinterpret_cast<const uint4 *>(Drow + j0);
-            uint4 r1 = make_uint4(0, 0, 0, 0), r2 = make_uint4(0, 0, 0, 0);
-            if (t1) r1 = *reinterpret_cast<const uint4 *>(fa.row1 + j0);
-            if (t2) r2 = *reinterpret_cast<const uint4 *>(fa.row2 + j0);
-            const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
-            const uint32_t v1[4] = {r1.x, r1.y, r1.z, r1.w};
-            const uint32_t v2[4] = {r2.x, r2.y, r2.z, r2.w};
-            uint32_t bits = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = j0 + e;
-                uint32_t dj = dv[e];
-                bool f = false;
-                if (j < n && j != i && dj < INF) f = (t1 && a1 + v1[e] == dj) || (t2 && a2 + v2[e] == dj);
-                if (fa.mode == FUSED_REMOVE && j == fa.k) {
-                    f = false;
-                    dj = INF;
-                }
-                if (f) bits |= 1u << e;
-                if (!count_only) cur[j] = f ? INF : dj;
-            }
-            if (bits) {
-                atomicOr(&fl[j0 >> 5], bits << (j0 & 31));
-                cnt += __popc(bits);
-            }
-        }
-        const int total = block_sum256(cnt, red);
+        const RowTests rt = row_tests(g, fa, i, w_old);
+        if (!rt.t1 && !rt.t2) continue;
+        const int total = block_sum256(mask_row(g, fa, i, rt, sh, !count_only, 0), sh.red);
         if (total == 0) continue;
         if (tid == 0) {
             my_flagged += (unsigned long long)total;
@@ -758,88 +959,22 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused(DevGraph g, FusedArgs f
             __syncthreads();
             continue;
         }
-
-        // flagged columns -> list (ascending)
-        {
-            const int per = (nw + FUSED_THREADS - 1) / FUSED_THREADS;
-            const int w0 = min(nw, tid * per), w1 = min(nw, w0 + per);
-            int c = 0;
-            for (int w = w0; w < w1; ++w) c += __popc(fl[w]);
-            int tot;
-            int off = block_exscan256(c, red, &tot);
-            for (int w = w0; w < w1; ++w) {
-                uint32_t bits = fl[w];
-                while (bits) {
-                    const int b = __ffs(bits) - 1;
-                    bits &= bits - 1;
-                    list[off++] = w * 32 + b;
-                }
+        if (defer && total > LDS_LIST) {
+            if (tid == 0) {
+                fa.heavy_epoch[i] = fa.epoch;
+                fa.heavy_rows[atomicAdd(&g.ctl->heavy_count, 1)] = i;
             }
+            __syncthreads();
+            continue;
         }
-        __syncthreads();
-
-        // 2. recompute
+        int32_t *list = total <= LDS_LIST ? sh.list_lds : glist;
+        compact_bits(sh.fl, nw, list, sh.red);
         int sweeps = 0;
-        for (;;) {
-            for (;;) {  // light-index sweeps until stable
-                __syncthreads();
-                if (tid == 0) *flag_changed = 0;
-                __syncthreads();
-                for (int e = tid; e < total; e += FUSED_THREADS) {
-                    const int32_t y = list[e];
-                    uint32_t best = cur[y];
-                    const int lim = min(g.nin_cnt[y], g.lim);
-                    const int2 *L = g.nin + (int64_t)y * NIN_L;
-                    for (int t = 0; t < lim; ++t) {
-                        const int2 ent = L[t];
-                        if ((uint32_t)ent.y >= best) break;
-                        best = min(best, cur[ent.x] + (uint32_t)ent.y);
-                    }
-                    if (best < cur[y]) {
-                        cur[y] = best;
-                        *flag_changed = 1;
-                    }
-                }
-                __syncthreads();
-                ++sweeps;
-                if (*flag_changed == 0) break;
-            }
-            // entries still above their list bound need every in-edge
-            __syncthreads();
-            if (tid == 0) *flag_nfs = 0;
-            __syncthreads();
-            for (int e = tid; e < total; e += FUSED_THREADS) {
-                const int32_t y = list[e];
-                const int c = g.nin_cnt[y];
-                const uint32_t beta_eff = c > g.lim ? (uint32_t)g.nin[(int64_t)y * NIN_L + g.lim].y
-                                                    : (uint32_t)g.nin_beta[y];
-                if (cur[y] > beta_eff) fsl[atomicAdd(flag_nfs, 1u)] = y;
-            }
-            __syncthreads();
-            const int nfs = (int)*flag_nfs;
-            if (nfs == 0) break;
-            if (tid == 0) *flag_changed = 0;
-            for (int f = 0; f < nfs; ++f) {
-                const int32_t y = fsl[f];
-                const int32_t *col = Min + (int64_t)y * g.ld;
-                uint32_t best = INF;
-                for (int32_t x = tid; x < n; x += FUSED_THREADS) best = min(best, cur[x] + (uint32_t)col[x]);
-                best = block_min256(best, red);
-                if (tid == 0 && best < cur[y]) {
-                    cur[y] = best;
-                    *flag_changed = 1;
-                }
-                __syncthreads();
-            }
-            my_fs += nfs;
-            __syncthreads();
-            if (*flag_changed == 0) break;
-        }
-
-        // 3. write back
+        row_bellman_ford(g, sh, list, total, fsl, sweeps, my_fs);
+        int32_t *Drow = g.D + (int64_t)i * g.ld;
         for (int e = tid; e < total; e += FUSED_THREADS) {
             const int32_t y = list[e];
-            const_cast<int32_t *>(Drow)[y] = (int32_t)cur[y];
+            Drow[y] = (int32_t)sh.cur[y];
         }
         if (tid == 0) my_sweeps = max(my_sweeps, sweeps);
         __syncthreads();
@@ -852,10 +987,49 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused(DevGraph g, FusedArgs f
     }
 }
 
+// Pass B (undirected): heavy rows.  Light flagged entries are mirrored; the
+// heavy-heavy ones are recomputed by Bellman-Ford against the now exact
+// remainder of the row.
+__global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, FusedArgs fa) {
+    extern __shared__ uint32_t sm[];
+    FusedShared sh = fused_shared(g, sm);
+    const int n = g.n_slots;
+    const int nw = (n + 31) >> 5;
+    const int tid = threadIdx.x;
+    uint32_t w_old = 0;
+    if (fa.mode == FUSED_INCREASE) {
+        if (g.ctl->edge_mode != EDGE_INCREASE) return;
+        w_old = (uint32_t)g.ctl->w_old;
+    }
+    const int count = g.ctl->heavy_count;
+    int32_t *glist = fa.scratch + (int64_t)blockIdx.x * 2 * g.P;
+    int32_t *fsl = glist + g.P;
+    int my_fs = 0, my_sweeps = 0;
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int32_t i = fa.heavy_rows[idx];
+        const RowTests rt = row_tests(g, fa, i, w_old);
+        block_sum256(mask_row(g, fa, i, rt, sh, true, 1), sh.red);
+        const int hh = compact_bits(sh.fl2, nw, glist, sh.red);
+        int sweeps = 0;
+        if (hh > 0) row_bellman_ford(g, sh, glist, hh, fsl, sweeps, my_fs);
+        const int all = compact_bits(sh.fl, nw, glist, sh.red);
+        int32_t *Drow = g.D + (int64_t)i * g.ld;
+        for (int e = tid; e < all; e += FUSED_THREADS) {
+            const int32_t y = glist[e];
+            Drow[y] = (int32_t)sh.cur[y];
+        }
+        if (tid == 0) my_sweeps = max(my_sweeps, sweeps);
+        __syncthreads();
+    }
+    if (tid == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
+    if (tid == 0 && my_sweeps) atomicMax(&g.ctl->sweeps, my_sweeps);
+}
+
 void launch_fused(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
     if (g.n_slots <= 0) return;
     const int grid = g.n_slots < FUSED_GRID ? g.n_slots : FUSED_GRID;
     k_fused<<<grid, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
+    if (g.undirected) k_fused_heavy<<<FUSED_GRID / 2, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
 }
 
 size_t nin_build_lds_bytes(int32_t) { return 0; }
@@ -863,7 +1037,7 @@ size_t nin_build_lds_bytes(int32_t) { return 0; }
 // The mask + recompute kernel keeps a whole row in LDS; APSP_MAX_CAPACITY is
 // the largest capacity whose row (plus flags) fits the 160 KiB of one CU.
 static_assert(APSP_MAX_CAPACITY % TILE == 0, "capacity limit must be a tile multiple");
-static_assert(((size_t)APSP_MAX_CAPACITY + 2 * (APSP_MAX_CAPACITY / 32) + 64) * 4 <= 163840,
+static_assert(((size_t)APSP_MAX_CAPACITY + 2 * (APSP_MAX_CAPACITY / 32) + LDS_LIST + 64) * 4 <= 163840,
               "a row of the largest graph must fit in LDS");
 
 hipError_t configure_kernels() {
@@ -871,6 +1045,9 @@ hipError_t configure_kernels() {
     if (status != hipErrorNotReady) return status;
     status = hipFuncSetAttribute((const void *)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)fused_lds_bytes(APSP_MAX_CAPACITY));
+    if (status == hipSuccess)
+        status = hipFuncSetAttribute((const void *)k_fused_heavy, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)fused_lds_bytes(APSP_MAX_CAPACITY));
     (void)hipGetLastError();  // do not leave the status for an unrelated launch check
     return status;
 }

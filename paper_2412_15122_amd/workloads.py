@@ -64,16 +64,20 @@ def random_graph(n: int, wmin: int, wmax: int, *, undirected: bool = False,
 
 
 def symmetric_complete_graph(n: int, wmin: int, wmax: int, seed) -> np.ndarray:
-    """Undirected complete graph with symmetric uniform weights, built in place
-    so that n = 16384 (1 GiB) needs about two matrices of host memory."""
+    """Undirected complete graph with symmetric uniform weights: the upper
+    triangle is drawn, the lower one mirrors it block by block (so n = 16384,
+    1 GiB, needs little more than one matrix of host memory)."""
     rng = np.random.default_rng(seed)
     a = rng.integers(wmin, wmax + 1, size=(n, n), dtype=np.int32)
-    # mirror the strict upper triangle onto the lower one, a row block at a time
-    blk = 1024
+    blk = 2048
     for r0 in range(0, n, blk):
         r1 = min(n, r0 + blk)
-        for r in range(r0, r1):
-            a[r, :r] = a[:r, r]
+        d = a[r0:r1, r0:r1]
+        low = np.tril_indices(r1 - r0, -1)
+        d[low] = d.T[low]
+        for c0 in range(0, r0, blk):
+            c1 = min(n, c0 + blk)
+            a[r0:r1, c0:c1] = a[c0:c1, r0:r1].T
     np.fill_diagonal(a, 0)
     return a
 
@@ -119,9 +123,18 @@ class GraphState:
         self.live: List[int] = list(range(self.n0))
         self.max_id = self.n0 - 1
         self.edits: Dict[Tuple[int, int], int] = {}
-        # added node id -> (dict out-weights by id, dict in-weights by id)
-        self.added_out: Dict[int, Dict[int, int]] = {}
-        self.added_in: Dict[int, Dict[int, int]] = {}
+        # added node id -> (ids live when it was added (ascending), out-weights, in-weights)
+        self.added: Dict[int, Tuple[np.ndarray, np.ndarray, np.ndarray]] = {}
+
+    def _added_weight(self, node: int, other: int, out: bool) -> Optional[int]:
+        rec = self.added.get(node)
+        if rec is None:
+            return None
+        ids, w_out, w_in = rec
+        pos = int(np.searchsorted(ids, other))
+        if pos < ids.size and ids[pos] == other:
+            return int((w_out if out else w_in)[pos])
+        return None
 
     def weight(self, u: int, v: int) -> int:
         if u == v:
@@ -131,11 +144,12 @@ class GraphState:
             return self.edits[key]
         # an edge touching an added node was drawn when the younger endpoint
         # was added: it sits in that node's out- or in-weights
-        if u in self.added_out and v in self.added_out[u]:
-            return self.added_out[u][v]
-        if v in self.added_in and u in self.added_in[v]:
-            return self.added_in[v][u]
-        return int(self.base[u, v])
+        w = self._added_weight(u, v, True)
+        if w is None:
+            w = self._added_weight(v, u, False)
+        if w is None:
+            w = int(self.base[u, v])
+        return w
 
     def set_weight(self, u: int, v: int, w: int) -> None:
         self.edits[(u, v)] = int(w)
@@ -145,8 +159,7 @@ class GraphState:
     def add(self, w_out: np.ndarray, w_in: np.ndarray) -> int:
         nid = self.max_id + 1
         self.max_id = nid
-        self.added_out[nid] = {t: int(x) for t, x in zip(self.live, w_out)}
-        self.added_in[nid] = {t: int(x) for t, x in zip(self.live, w_in)}
+        self.added[nid] = (np.asarray(self.live, dtype=np.int64), np.asarray(w_out), np.asarray(w_in))
         self.live.append(nid)
         return nid
 
