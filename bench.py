@@ -49,20 +49,10 @@ def parse():
 # algorithmic bytes per launch of the sweep kernels
 # ---------------------------------------------------------------------------
 # add_relax reads every live row of D once (the new pair distances need every
-# old entry); mask_recompute reads every row it visits once.  Writes are the
-# changed / recomputed entries only and are not counted (they are a small,
-# data-dependent fraction).
-
-def algorithmic_bytes(kind, n_live, stats):
-    if kind == "add_relax":
-        return 4 * n_live * n_live
-    if kind == "mask_recompute":
-        if stats["kind"] == 2:                      # removal: every live row but k
-            return 4 * (n_live - 1) * n_live
-        if stats["kind"] == 4:                      # increase: rows of R only
-            return 4 * stats.get("rows_visited", 0) * n_live
-        return 0
-    return 0
+# old entry); mask_detect reads every row that can hold a flag once (for a
+# removal every live row but k; an increase reads only the rows of R, counted
+# as 0 here).  Writes are the changed / recomputed entries only and are not
+# counted (a small, data-dependent fraction).
 
 
 def source_hash():
@@ -244,7 +234,7 @@ def main():
         if step == 0:
             tot = {nm: g.profile_read(kid[nm]) for nm in names}
             prof_totals = {nm: v for nm, v in tot.items() if v[0]}
-            sweep = {nm: v[1] for nm, v in prof_totals.items() if nm in ("add_relax", "mask_recompute")}
+            sweep = {nm: v[1] for nm, v in prof_totals.items() if nm in ("add_relax", "mask_detect")}
             prof_kernel = max(sweep, key=sweep.get) if sweep else None
             g.profile(0)
             log("[bench] kernel totals (step 0): " +
@@ -269,7 +259,7 @@ def main():
     # live counts (every add / remove changes n by one)
     live = n + growth * args.warmup
     removes_bytes = adds_bytes = 0
-    launches = {"add_relax": 0, "mask_recompute": 0}
+    launches = {"add_relax": 0, "mask_detect": 0}
     for k in kinds_all:
         if k == W.ADD:
             adds_bytes += 4 * live * live
@@ -277,10 +267,10 @@ def main():
             live += 1
         elif k == W.REMOVE:
             removes_bytes += 4 * (live - 1) * live
-            launches["mask_recompute"] += 1
+            launches["mask_detect"] += 1
             live -= 1
         elif k == W.INCREASE:
-            launches["mask_recompute"] += 1
+            launches["mask_detect"] += 1
     roofline = None
     if prof_kernel and "timed" in prof_totals and prof_totals["timed"][1] > 0:
         c, ms = prof_totals["timed"]

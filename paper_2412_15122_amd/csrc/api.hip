@@ -28,7 +28,7 @@ int32_t padded(int32_t cap) { return ((cap + TILE - 1) / TILE) * TILE; }
 
 struct Layout {
     size_t D, A, AT, nin, nin_cnt, nin_beta, id_of_slot, vec, plist, rank_a, rank_b, qbuf, qscratch, fscratch,
-        nin_queue, heavy_rows, heavy_epoch, ctl, total;
+        nin_queue, heavy_rows, heavy_epoch, flag_bits, row_bits, ctl, total;
 };
 
 constexpr int NVEC = 8;  // wo, wi, out, in, colu, colv, rowu, rowv
@@ -60,6 +60,8 @@ Layout make_layout(int32_t cap, int32_t kind) {
     L.nin_queue = take(P * 4);
     L.heavy_rows = take(P * 4);
     L.heavy_epoch = take(P * 4);
+    L.flag_bits = take(P * ((P + 31) / 32) * 4);
+    L.row_bits = take(((P + 31) / 32) * 4);
     L.ctl = take(sizeof(Ctl));
     L.total = off;
     return L;
@@ -143,6 +145,7 @@ struct apsp_graph {
     int32_t *rank_cur = nullptr, *rank_other = nullptr;
     int32_t *qbuf = nullptr, *qscratch = nullptr, *fscratch = nullptr, *nin_queue = nullptr;
     int32_t *heavy_rows = nullptr, *heavy_epoch = nullptr;
+    uint32_t *flag_bits = nullptr, *row_bits = nullptr;
     int32_t epoch = 0;
     // host bookkeeping
     int32_t n_live = 0, max_id = -1;
@@ -201,11 +204,6 @@ apsp_status read_ctl(apsp_graph *g) {
     return APSP_OK;
 }
 
-apsp_status set_count_only(apsp_graph *g, int32_t v) {
-    launch_fill(&g->dg.ctl->count_only, 1, v, g->stream);
-    return check_launch("count_only");
-}
-
 // D := cold Floyd-Warshall of the current adjacency over the used slots.
 apsp_status run_cold(apsp_graph *g) {
     const int32_t n = g->dg.n_slots;
@@ -219,24 +217,36 @@ apsp_status run_cold(apsp_graph *g) {
     return APSP_OK;
 }
 
-// Algorithm 5's decision for the pending mask (rows/flags counted on the
-// device): returns 1 when cold Floyd-Warshall should run.
-apsp_status decide_fallback(apsp_graph *g, const FusedArgs &fa, int32_t n_before, int32_t *fallback) {
+// Algorithm 5's switch, after the mask has been detected (Phi and |F| are in
+// the control block): 1 when cold Floyd-Warshall should replace the masked
+// recompute.  Only the cost policy reads the counts back (synchronous).
+apsp_status decide_fallback(apsp_graph *g, const FusedArgs *fa, int32_t n_before, int32_t *fallback) {
     *fallback = 0;
     if (g->policy == APSP_FALLBACK_ALWAYS) {
         *fallback = 1;
         return APSP_OK;
     }
     if (g->policy != APSP_FALLBACK_COST) return APSP_OK;
-    apsp_status st = set_count_only(g, 1);
+    launch_count_flag_rows(g->dg, *fa, g->stream);
+    apsp_status st = read_ctl(g);
     if (st) return st;
-    launch_fused(g->dg, fa, g->stream);
-    if ((st = check_launch("mask count"))) return st;
-    if ((st = set_count_only(g, 0))) return st;
-    if ((st = read_ctl(g))) return st;
     const double cost = n_before > 1 ? (double)g->ctl_h->rows / (double)(n_before - 1) : 0.0;
     *fallback = cost > g->delta;
-    return APSP_OK;
+    launch_fill(&g->dg.ctl->rows, 1, 0, g->stream);  // the recompute counts Phi again
+    return check_launch("cost decision");
+}
+
+FusedArgs fused_args(apsp_graph *g, int32_t mode) {
+    FusedArgs fa{};
+    fa.mode = mode;
+    fa.k = -1;
+    fa.scratch = g->fscratch;
+    fa.heavy_rows = g->heavy_rows;
+    fa.heavy_epoch = g->heavy_epoch;
+    fa.flag_bits = g->flag_bits;
+    fa.row_bits = g->row_bits;
+    fa.epoch = ++g->epoch;
+    return fa;
 }
 
 }  // namespace
@@ -256,7 +266,8 @@ int32_t apsp_kernel_count(void) { return KID_COUNT; }
 const char *apsp_kernel_name(int32_t k) {
     static const char *names[KID_COUNT] = {
         "fw_pivot", "fw_panel", "fw_tiles", "nin_build", "nin_update", "add_out", "add_in", "add_relax",
-        "add_place", "gather", "mask_recompute", "tombstone", "edge_begin", "dec_relax", "query", "misc"};
+        "add_place", "gather", "mask_recompute", "tombstone", "edge_begin", "dec_relax", "query", "misc",
+        "mask_detect"};
     if (k < 0 || k >= KID_COUNT) return "";
     return names[k];
 }
@@ -320,6 +331,8 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
     g->nin_queue = (int32_t *)(b + L.nin_queue);
     g->heavy_rows = (int32_t *)(b + L.heavy_rows);
     g->heavy_epoch = (int32_t *)(b + L.heavy_epoch);
+    g->flag_bits = (uint32_t *)(b + L.flag_bits);
+    g->row_bits = (uint32_t *)(b + L.row_bits);
     g->prof_impl.stream = g->stream;
     g->prof.impl = &g->prof_impl;
 
@@ -336,6 +349,7 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
     launch_fill(d.nin_cnt, g->P, 0, s);
     launch_fill(d.nin_beta, g->P, (int32_t)INF, s);
     launch_fill(g->heavy_epoch, g->P, 0, s);
+    launch_fill((int32_t *)g->row_bits, (g->P + 31) / 32, 0, s);
     launch_fill((int32_t *)d.ctl, sizeof(Ctl) / 4, 0, s);
     apsp_status st = check_launch("cold start fill");
     if (st) {
@@ -480,25 +494,19 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     g->prof.begin(KID_GATHER);
     launch_gather_rc(d, k, k, colu(g), nullptr, rowu(g), nullptr, 0, s);
     g->prof.end();
-    FusedArgs fa{};
-    fa.mode = FUSED_REMOVE;
+    FusedArgs fa = fused_args(g, FUSED_REMOVE);
     fa.k = k;
     fa.col1 = colu(g);
     fa.row1 = rowu(g);
-    fa.scratch = g->fscratch;
-    fa.heavy_rows = g->heavy_rows;
-    fa.heavy_epoch = g->heavy_epoch;
-    fa.epoch = ++g->epoch;
+    g->prof.begin(KID_MASK);
+    launch_mask_detect(d, fa, s);
+    g->prof.end();
     int32_t fallback = 0;
-    apsp_status st = decide_fallback(g, fa, n_before, &fallback);
+    apsp_status st = decide_fallback(g, &fa, n_before, &fallback);
     if (st) return st;
-    // a cost pass counted the mask already; the recompute counts it again
-    if (!fallback && g->policy == APSP_FALLBACK_COST) launch_reset_stats(d, s);
-    if (!fallback) {
-        g->prof.begin(KID_FUSED);
-        launch_fused(d, fa, s);
-        g->prof.end();
-    }
+    g->prof.begin(KID_FUSED);
+    launch_mask_recompute(d, fa, fallback, s);
+    g->prof.end();
     g->prof.begin(KID_TOMBSTONE);
     launch_tombstone(d, k, s);
     g->prof.end();
@@ -542,33 +550,24 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     g->prof.begin(KID_DEC_RELAX);
     launch_dec_relax(d, colu(g), colv(g), rowu(g), rowv(g), w, s);
     g->prof.end();
-    FusedArgs fa{};
-    fa.mode = FUSED_INCREASE;
-    fa.k = -1;
+    FusedArgs fa = fused_args(g, FUSED_INCREASE);
     fa.col1 = colu(g);
     fa.col2 = colv(g);
     fa.row1 = rowv(g);
     fa.row2 = rowu(g);
-    fa.scratch = g->fscratch;
-    fa.heavy_rows = g->heavy_rows;
-    fa.heavy_epoch = g->heavy_epoch;
-    fa.epoch = ++g->epoch;
+    g->prof.begin(KID_MASK);
+    launch_mask_detect(d, fa, s);
+    g->prof.end();
     int32_t fallback = 0;
     apsp_status st;
     if (g->policy != APSP_FALLBACK_NEVER) {
         if ((st = read_ctl(g))) return st;
-        if (g->ctl_h->edge_mode == EDGE_INCREASE) {
-            if ((st = decide_fallback(g, fa, n_before, &fallback))) return st;
-        }
+        if (g->ctl_h->edge_mode == EDGE_INCREASE && (st = decide_fallback(g, &fa, n_before, &fallback))) return st;
     }
-    if (fallback) {
-        if ((st = run_cold(g))) return st;
-    } else {
-        if (g->policy == APSP_FALLBACK_COST) launch_reset_stats(d, s);
-        g->prof.begin(KID_FUSED);
-        launch_fused(d, fa, s);
-        g->prof.end();
-    }
+    g->prof.begin(KID_FUSED);
+    launch_mask_recompute(d, fa, fallback, s);
+    g->prof.end();
+    if (fallback && (st = run_cold(g))) return st;
     g->prof.begin(KID_NIN_BUILD);
     launch_nin_build(d, sv, 1, 1, s);
     if (g->kind == APSP_UNDIRECTED) launch_nin_build(d, su, 1, 1, s);

@@ -24,6 +24,7 @@ constexpr int TILE = 128;        // Floyd-Warshall block / matrix padding
 constexpr int NIN_L = 64;        // light in-edge index entries per node
 constexpr int FUSED_GRID = 512;  // resident work-groups of the mask+recompute kernel
 constexpr int FUSED_THREADS = 256;
+constexpr int ROW_CAP = 64;      // flagged columns listed per row (more: a "heavy" row)
 
 enum EdgeMode : int32_t { EDGE_NOOP = 0, EDGE_DECREASE = 1, EDGE_INCREASE = 2 };
 enum FusedMode : int32_t { FUSED_REMOVE = 0, FUSED_INCREASE = 1 };
@@ -42,7 +43,7 @@ struct Ctl {
     int32_t rows_relaxed;
     int32_t scope_r;
     int32_t scope_c;
-    int32_t count_only;   // set by the host for the Algorithm 5 cost pass
+    int32_t reserved;
     int32_t short_count;  // index lists queued for a rebuild
     int32_t heavy_count;  // rows deferred to the heavy-row pass
     int32_t pad[1];
@@ -117,11 +118,18 @@ struct FusedArgs {
     int32_t *scratch;     // FUSED_GRID * 2 * P ints
     int32_t *heavy_rows;  // [P] rows deferred to the heavy-row pass
     int32_t *heavy_epoch; // [P] heavy_epoch[i] == epoch marks row i heavy
+    uint32_t *flag_bits;  // [P][P/32] flag bitmap of the tested rows
+    uint32_t *row_bits;   // [P/32] rows holding a flag; zero between updates
     int32_t epoch;        // distinct for every mask pass
 };
 void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, int32_t *colb,
                       int32_t *rowa, int32_t *rowb, int32_t gate_on_edge, hipStream_t s);
-void launch_fused(const DevGraph &g, const FusedArgs &fa, hipStream_t s);
+// Mask + recompute in two steps: detection (|F| lands in ctl->flagged), then
+// the recompute (Phi in ctl->rows) -- or, with reset_only, just the clearing
+// of the row marks when cold Floyd-Warshall replaces the recompute.
+void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s);
+void launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s);
+void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s);  // Phi -> ctl->rows
 void launch_tombstone(const DevGraph &g, int32_t k, hipStream_t s);
 void launch_rank_remove(const int32_t *src, int32_t *dst, int32_t r, int32_t n_live, hipStream_t s);
 void launch_reset_stats(const DevGraph &g, hipStream_t s);
@@ -145,7 +153,7 @@ hipError_t configure_kernels();  // raise dynamic-LDS limits once per process
 enum KernelId : int32_t {
     KID_FW_PIVOT = 0, KID_FW_PANEL, KID_FW_TILE, KID_NIN_BUILD, KID_NIN_UPDATE,
     KID_ADD_OUT, KID_ADD_IN, KID_ADD_RELAX, KID_ADD_PLACE, KID_GATHER, KID_FUSED,
-    KID_TOMBSTONE, KID_EDGE_BEGIN, KID_DEC_RELAX, KID_QUERY, KID_MISC, KID_COUNT
+    KID_TOMBSTONE, KID_EDGE_BEGIN, KID_DEC_RELAX, KID_QUERY, KID_MISC, KID_MASK, KID_COUNT
 };
 
 // Event-based timing hooks (implemented in the host API unit).

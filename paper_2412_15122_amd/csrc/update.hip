@@ -4,6 +4,8 @@
 // Notation: a (+) b = min(a + b, INF), INF = 2^30, evaluated in uint32 (sums
 // of two values <= INF stay below 2^32, and a min against a value <= INF
 // needs no clamp).
+#include <algorithm>
+
 #include "apsp_internal.h"
 
 namespace apsp {
@@ -85,63 +87,102 @@ struct SelectShared {
 };
 
 // Select the NIN_L smallest entries of vals[0..n) other than index `excl`
-// and other than INF (absent edges), ordered by (w, x).  One 256-thread block.
+// and other than INF (absent edges), ordered by (w, x).  One 256-thread
+// block; `stage` is LDS for n words (the values are read from memory once).
 __device__ void select_light(const int32_t *__restrict__ vals, int32_t n, int32_t excl, int2 *list,
-                             int32_t *cnt_out, int32_t *beta_out, SelectShared &sh) {
+                             int32_t *cnt_out, int32_t *beta_out, SelectShared &sh, uint32_t *stage) {
     const int tid = threadIdx.x;
     int valid = 0;
     for (int32_t x = tid; x < n; x += 256) {
         uint32_t v = (uint32_t)vals[x];
-        valid += (x != excl && v < INF);
+        if (x == excl) v = INF;
+        stage[x] = v;
+        valid += v < INF;
     }
     int total = block_sum256(valid, sh.red);
     uint32_t tau = INF;  // entries < tau are all taken
     int need_eq = 0;     // plus this many entries == tau, lowest index first
-    if (total > NIN_L) {
-        uint32_t prefix = 0, mask = 0;
-        int kk = NIN_L;
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            sh.hist[tid] = 0;
-            __syncthreads();
-            for (int32_t x = tid; x < n; x += 256) {
-                uint32_t v = (uint32_t)vals[x];
-                if (x != excl && v < INF && (v & mask) == prefix) atomicAdd(&sh.hist[(v >> shift) & 255u], 1u);
+    // Finds the bin holding rank kk of sh.hist; writes sh.bin and sh.kk.
+    auto find_bin = [&](int kk) {
+        if (tid < 64) {
+            const uint32_t h0 = sh.hist[4 * tid], h1 = sh.hist[4 * tid + 1], h2 = sh.hist[4 * tid + 2],
+                           h3 = sh.hist[4 * tid + 3];
+            const int own = (int)(h0 + h1 + h2 + h3);
+            int incl = own;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(incl, o);
+                if (tid >= o) incl += t;
             }
-            __syncthreads();
-            if (tid == 0) {
-                int cum = 0, b = 0;
-                for (; b < 255; ++b) {
-                    if (cum + (int)sh.hist[b] >= kk) break;
-                    cum += (int)sh.hist[b];
+            const int before = incl - own;
+            if (before < kk && kk <= incl) {
+                int cum = before, b = 4 * tid;
+                const uint32_t hh[4] = {h0, h1, h2, h3};
+                for (int q = 0; q < 3; ++q, ++b) {
+                    if (cum + (int)hh[q] >= kk) break;
+                    cum += (int)hh[q];
                 }
                 sh.bin = b;
                 sh.kk = kk - cum;
             }
-            __syncthreads();
-            prefix |= (uint32_t)sh.bin << shift;
-            mask |= 255u << shift;
-            kk = sh.kk;
-            __syncthreads();
+            if (tid == 63 && incl < kk) sh.bin = -1;  // rank beyond the histogram
         }
-        tau = prefix;
-        need_eq = kk;
+        __syncthreads();
+    };
+    if (total > NIN_L) {
+        // light weights are usually packed near the minimum: try the 256
+        // values [vmin, vmin + 256) first (one histogram, few collisions)
+        uint32_t vmin = INF;
+        for (int32_t x = tid; x < n; x += 256) vmin = min(vmin, stage[x]);
+        vmin = block_min256(vmin, sh.red);
+        sh.hist[tid] = 0;
+        __syncthreads();
+        for (int32_t x = tid; x < n; x += 256) {
+            const uint32_t w = stage[x];
+            if (w < INF && w - vmin < 256u) atomicAdd(&sh.hist[w - vmin], 1u);
+        }
+        __syncthreads();
+        find_bin(NIN_L);
+        if (sh.bin >= 0) {
+            tau = vmin + (uint32_t)sh.bin;
+            need_eq = sh.kk;
+        } else {
+            uint32_t prefix = 0, mask = 0;
+            int kk = NIN_L;
+            for (int shift = 24; shift >= 0; shift -= 8) {
+                __syncthreads();
+                sh.hist[tid] = 0;
+                __syncthreads();
+                for (int32_t x = tid; x < n; x += 256) {
+                    const uint32_t v = stage[x];
+                    if (v < INF && (v & mask) == prefix) atomicAdd(&sh.hist[(v >> shift) & 255u], 1u);
+                }
+                __syncthreads();
+                find_bin(kk);
+                prefix |= (uint32_t)sh.bin << shift;
+                mask |= 255u << shift;
+                kk = sh.kk;
+            }
+            tau = prefix;
+            need_eq = kk;
+        }
+        __syncthreads();
     }
-    // ordered collection over contiguous segments
+    // ordered collection over contiguous segments of the staged values
     const int32_t seg = (n + 255) / 256;
     const int32_t x0 = min(n, tid * seg), x1 = min(n, x0 + seg);
     int c_less = 0, c_eq = 0;
     for (int32_t x = x0; x < x1; ++x) {
-        uint32_t v = (uint32_t)vals[x];
-        if (x == excl || v >= INF) continue;
+        const uint32_t v = stage[x];
         c_less += (v < tau);
-        c_eq += (v == tau);
+        c_eq += (v == tau && v < INF);
     }
     int tot_less, tot_eq;
     int off_less = block_exscan256(c_less, sh.red, &tot_less);
     int off_eq = block_exscan256(c_eq, sh.red + 8, &tot_eq);
     for (int32_t x = x0; x < x1; ++x) {
-        uint32_t v = (uint32_t)vals[x];
-        if (x == excl || v >= INF) continue;
+        const uint32_t v = stage[x];
+        if (v >= INF) continue;
         if (v < tau) {
             sh.keys[off_less++] = ((unsigned long long)v << 32) | (uint32_t)x;
         } else if (v == tau) {
@@ -180,6 +221,7 @@ __device__ void select_light(const int32_t *__restrict__ vals, int32_t n, int32_
             *beta_out = (int32_t)(total > NIN_L ? tau : INF);
         }
     }
+    __syncthreads();
 }
 
 // Build the index of nodes first .. first+count-1 from row y of the in-edge
@@ -187,6 +229,7 @@ __device__ void select_light(const int32_t *__restrict__ vals, int32_t n, int32_
 // while unlisted in-edges exist.
 __global__ __launch_bounds__(256) void k_nin_build(DevGraph g, int32_t first, int32_t only_short) {
     __shared__ SelectShared sh;
+    extern __shared__ uint32_t stage[];
     const int32_t y = first + blockIdx.x;
     if (y >= g.n_slots) return;
     int32_t *cnt = g.nin_cnt + y, *beta = g.nin_beta + y;
@@ -196,23 +239,26 @@ __global__ __launch_bounds__(256) void k_nin_build(DevGraph g, int32_t first, in
         if (threadIdx.x == 0) { *cnt = 0; *beta = (int32_t)INF; }
         return;
     }
-    select_light(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, list, cnt, beta, sh);
+    select_light(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, list, cnt, beta, sh, stage);
 }
+
+size_t nin_build_lds_bytes(int32_t P) { return (size_t)P * sizeof(uint32_t); }
 
 void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t only_short, hipStream_t s) {
     if (count <= 0) return;
-    k_nin_build<<<count, 256, 0, s>>>(g, first, only_short);
+    k_nin_build<<<count, 256, nin_build_lds_bytes(g.P), s>>>(g, first, only_short);
 }
 
 __global__ __launch_bounds__(256) void k_select_vec(const int32_t *vals, int32_t n, int32_t excl, int2 *list,
                                                     int32_t *cnt, int32_t *beta) {
     __shared__ SelectShared sh;
-    select_light(vals, n, excl, list, cnt, beta, sh);
+    extern __shared__ uint32_t stage[];
+    select_light(vals, n, excl, list, cnt, beta, sh, stage);
 }
 
 void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
                        int32_t *beta, hipStream_t s) {
-    k_select_vec<<<1, 256, 0, s>>>(vals, n, exclude, list, cnt, beta);
+    k_select_vec<<<1, 256, (size_t)(n > 0 ? n : 1) * sizeof(uint32_t), s>>>(vals, n, exclude, list, cnt, beta);
 }
 
 // Wave-level list edits (one wave owns list y).
@@ -290,18 +336,18 @@ void launch_nin_purge(const DevGraph &g, int32_t k, int32_t *queue, hipStream_t 
 
 __global__ __launch_bounds__(256) void k_nin_rebuild_queue(DevGraph g, const int32_t *queue) {
     __shared__ SelectShared sh;
+    extern __shared__ uint32_t stage[];
     const int count = g.ctl->short_count;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int32_t y = queue[idx];
         select_light(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, g.nin + (int64_t)y * NIN_L, g.nin_cnt + y,
-                     g.nin_beta + y, sh);
-        __syncthreads();
+                     g.nin_beta + y, sh, stage);
     }
 }
 
 void launch_nin_rebuild_queue(const DevGraph &g, const int32_t *queue, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_nin_rebuild_queue<<<32, 256, 0, s>>>(g, queue);
+    k_nin_rebuild_queue<<<32, 256, nin_build_lds_bytes(g.P), s>>>(g, queue);
 }
 
 // ---------------------------------------------------------------------------
@@ -925,71 +971,244 @@ __device__ void row_bellman_ford(const DevGraph &g, FusedShared &sh, const int32
     }
 }
 
-// Pass A: every affected row.  Undirected graphs defer rows with more than
-// LDS_LIST flagged columns ("heavy" rows) to pass B: there, D' being
-// symmetric, a flagged (i, j) whose row j is light is copied from D'[j][i].
-__global__ __launch_bounds__(FUSED_THREADS) void k_fused(DevGraph g, FusedArgs fa) {
-    extern __shared__ uint32_t sm[];
-    FusedShared sh = fused_shared(g, sm);
+// Pass A, in two kernels.
+//   detect: stream D in tiles of 8 rows x 1024 columns (the pair-test row
+//     slice stays in registers) and write the flags of every tested row into a
+//     bitmap (32 columns per word, assembled by 8 lanes, plain stores: every
+//     word of a tested row is rewritten, so nothing needs clearing).  A row
+//     with a flag sets its bit in row_bits (no return value waited on).
+//   recompute: one wavefront per flagged row.  The row's flagged columns are
+//     read from the bitmap; the row of D itself is `cur`: flagged entries (and
+//     column k of a removal) are set to INF and relaxed in place by
+//     Bellman-Ford over the light in-edge index.  Rows with more than ROW_CAP
+//     flags ("heavy") are left untouched and queued for pass B.
+constexpr int DETECT_ROWS = 8;
+constexpr int RECOMPUTE_BLOCKS = 2048;  // 4 waves each
+
+__device__ __forceinline__ unsigned long long lanes_below() {
+    return (1ull << lane_id()) - 1ull;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
+    __shared__ uint32_t red[8];
     const int n = g.n_slots;
-    const int nw = (n + 31) >> 5;
-    const int tid = threadIdx.x;
     uint32_t w_old = 0;
-    if (fa.mode == FUSED_INCREASE) {
+    if (MODE == FUSED_INCREASE) {
         if (g.ctl->edge_mode != EDGE_INCREASE) return;
         w_old = (uint32_t)g.ctl->w_old;
     }
-    const bool count_only = g.ctl->count_only != 0;
-    const bool defer = g.undirected && !count_only;
-    int32_t *glist = fa.scratch + (int64_t)blockIdx.x * 2 * g.P;
-    int32_t *fsl = glist + g.P;
-    unsigned long long my_flagged = 0;
-    int my_rows = 0, my_fs = 0, my_sweeps = 0;
-
-    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const RowTests rt = row_tests(g, fa, i, w_old);
-        if (!rt.t1 && !rt.t2) continue;
-        const int total = block_sum256(mask_row(g, fa, i, rt, sh, !count_only, 0), sh.red);
-        if (total == 0) continue;
-        if (tid == 0) {
-            my_flagged += (unsigned long long)total;
-            ++my_rows;
-        }
-        if (count_only) {
-            __syncthreads();
-            continue;
-        }
-        if (defer && total > LDS_LIST) {
-            if (tid == 0) {
-                fa.heavy_epoch[i] = fa.epoch;
-                fa.heavy_rows[atomicAdd(&g.ctl->heavy_count, 1)] = i;
-            }
-            __syncthreads();
-            continue;
-        }
-        int32_t *list = total <= LDS_LIST ? sh.list_lds : glist;
-        compact_bits(sh.fl, nw, list, sh.red);
-        int sweeps = 0;
-        row_bellman_ford(g, sh, list, total, fsl, sweeps, my_fs);
-        int32_t *Drow = g.D + (int64_t)i * g.ld;
-        for (int e = tid; e < total; e += FUSED_THREADS) {
-            const int32_t y = list[e];
-            Drow[y] = (int32_t)sh.cur[y];
-        }
-        if (tid == 0) my_sweeps = max(my_sweeps, sweeps);
-        __syncthreads();
+    const int lane = lane_id();
+    const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    const int32_t r0 = blockIdx.y * DETECT_ROWS;
+    const int64_t nwp = (g.P + 31) / 32;
+    uint4 v1 = make_uint4(0, 0, 0, 0), v2 = v1;
+    if (c0 < n) {
+        v1 = *reinterpret_cast<const uint4 *>(fa.row1 + c0);
+        if (MODE == FUSED_INCREASE) v2 = *reinterpret_cast<const uint4 *>(fa.row2 + c0);
     }
-    if (tid == 0 && (my_rows || my_fs)) {
-        atomicAdd(&g.ctl->flagged, my_flagged);
-        atomicAdd(&g.ctl->rows, my_rows);
-        atomicAdd(&g.ctl->full_scans, my_fs);
-        atomicMax(&g.ctl->sweeps, my_sweeps);
+    const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w};
+    const uint32_t w2[4] = {v2.x, v2.y, v2.z, v2.w};
+    const int kx = MODE == FUSED_REMOVE ? fa.k : -1;
+    int found = 0;
+    uint4 d[DETECT_ROWS];
+    uint32_t a1[DETECT_ROWS], a2[DETECT_ROWS];
+    bool tested[DETECT_ROWS];
+#pragma unroll
+    for (int r = 0; r < DETECT_ROWS; ++r) {
+        const int32_t i = r0 + r;
+        d[r] = make_uint4(INF, INF, INF, INF);
+        a1[r] = a2[r] = 0x80000000u;  // disabled: a + v exceeds every finite entry
+        tested[r] = false;
+        if (i < n) {
+            const RowTests rt = row_tests(g, fa, i, w_old);
+            if (rt.t1) a1[r] = rt.a1;
+            if (rt.t2) a2[r] = rt.a2;
+            tested[r] = rt.t1 || rt.t2;
+            if (tested[r] && c0 < n) d[r] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)i * g.ld + c0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < DETECT_ROWS; ++r) {
+        if (!tested[r]) continue;  // block-uniform
+        const int32_t i = r0 + r;
+        const uint32_t dv[4] = {d[r].x, d[r].y, d[r].z, d[r].w};
+        uint32_t bits = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int32_t j = c0 + e;
+            bool f = a1[r] + w1[e] == dv[e];
+            if (MODE == FUSED_INCREASE) f = f || (a2[r] + w2[e] == dv[e]);
+            f = f && dv[e] < INF && j != i && j != kx;
+            bits |= (uint32_t)f << e;
+        }
+        found += __popc(bits);
+        uint32_t word = bits << ((lane & 7) * 4);
+        word |= (uint32_t)__shfl_xor((int)word, 1);
+        word |= (uint32_t)__shfl_xor((int)word, 2);
+        word |= (uint32_t)__shfl_xor((int)word, 4);
+        if ((lane & 7) == 0 && c0 < n) fa.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
+        if (__ballot(bits != 0) != 0 && lane == 0) atomicOr(&fa.row_bits[i >> 5], 1u << (i & 31));
+    }
+    found = block_sum256(found, red);
+    if (threadIdx.x == 0 && found) atomicAdd(&g.ctl->flagged, (unsigned long long)found);
+}
+
+// Phi of the pending mask (Algorithm 5's cost needs it before the recompute).
+__global__ __launch_bounds__(256) void k_count_flag_rows(DevGraph g, FusedArgs fa) {
+    __shared__ uint32_t red[8];
+    int c = 0;
+    for (int w = threadIdx.x; w < (g.n_slots + 31) / 32; w += 256) c += __popc(fa.row_bits[w]);
+    c = block_sum256(c, red);
+    if (threadIdx.x == 0) g.ctl->rows = c;
+}
+
+// Bellman-Ford over the flagged columns list[0..cnt) of row Drow (in place),
+// one wavefront: 16 groups of 4 lanes, each group one column at a time,
+// reading 16 index entries per load and stopping once an entry is at least
+// the current value.  Columns left above their index bound get exhaustive
+// in-edge scans, and the sweeps resume if that changed anything.
+__device__ void wave_bellman_ford(const DevGraph &g, int32_t *Drow, const int32_t *list, int cnt, int32_t *fsl,
+                                  int &sweeps, int &nfs_total) {
+    const int lane = lane_id();
+    const int g4 = lane >> 2, l4 = lane & 3;
+    const int lim = g.lim;
+    const int n = g.n_slots;
+    const int32_t *Min = in_matrix(g);
+    for (;;) {
+        for (;;) {
+            bool changed = false;
+            for (int e = g4; e < cnt; e += 16) {
+                const int32_t y = list[e];
+                uint32_t best = (uint32_t)Drow[y];
+                const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
+                for (int c0 = 0; c0 < lim; c0 += 16) {
+                    // lane l4 of the group holds entries c0 + 4*l4 .. +3
+                    const int e0 = c0 + 4 * l4;
+                    int4 pa = make_int4(0, (int)INF, 0, (int)INF), pb = pa;
+                    if (e0 < lim) pa = L4[e0 >> 1];
+                    if (e0 + 2 < lim) pb = L4[(e0 >> 1) + 1];
+                    if (e0 + 1 >= lim) pa.w = (int)INF;
+                    if (e0 + 3 >= lim) pb.w = (int)INF;
+                    uint32_t cm = INF;
+                    if ((uint32_t)pa.y < best) cm = min(cm, (uint32_t)Drow[pa.x] + (uint32_t)pa.y);
+                    if ((uint32_t)pa.w < best) cm = min(cm, (uint32_t)Drow[pa.z] + (uint32_t)pa.w);
+                    if ((uint32_t)pb.y < best) cm = min(cm, (uint32_t)Drow[pb.x] + (uint32_t)pb.y);
+                    if ((uint32_t)pb.w < best) cm = min(cm, (uint32_t)Drow[pb.z] + (uint32_t)pb.w);
+                    cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
+                    cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
+                    best = min(best, cm);
+                    const uint32_t wlast = (uint32_t)__shfl(pb.w, 3, 4);
+                    if (wlast >= best) break;  // every later entry is at least as heavy
+                }
+                if (l4 == 0 && best < (uint32_t)Drow[y]) {
+                    Drow[y] = (int32_t)best;
+                    changed = true;
+                }
+            }
+            __threadfence_block();
+            ++sweeps;
+            if (!__any(changed)) break;
+        }
+        int nfs = 0;
+        for (int b = 0; b < cnt; b += 64) {
+            const int e = b + lane;
+            bool need = false;
+            int32_t y = 0;
+            if (e < cnt) {
+                y = list[e];
+                uint32_t beta_eff = (uint32_t)g.nin_beta[y];
+                if (lim < NIN_L) beta_eff = min(beta_eff, (uint32_t)g.nin[(int64_t)y * NIN_L + lim].y);
+                need = (uint32_t)Drow[y] > beta_eff;
+            }
+            const unsigned long long m = __ballot(need);
+            if (need) fsl[nfs + __popcll(m & lanes_below())] = y;
+            nfs += __popcll(m);
+        }
+        if (nfs == 0) break;
+        bool changed = false;
+        for (int f = 0; f < nfs; ++f) {
+            const int32_t y = fsl[f];
+            const int32_t *col = Min + (int64_t)y * g.ld;
+            uint32_t best = INF;
+            for (int32_t x = lane; x < n; x += 64) best = min(best, (uint32_t)Drow[x] + (uint32_t)col[x]);
+            best = wave_min(best);
+            if (best < (uint32_t)Drow[y]) {
+                changed = true;
+                if (lane == 0) Drow[y] = (int32_t)best;
+            }
+            __threadfence_block();
+        }
+        nfs_total += nfs;
+        if (!changed) break;
     }
 }
 
-// Pass B (undirected): heavy rows.  Light flagged entries are mirrored; the
-// heavy-heavy ones are recomputed by Bellman-Ford against the now exact
-// remainder of the row.
+// reset_only: only clear the flagged rows' bits (after a cold fallback).
+__global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa, int32_t reset_only) {
+    __shared__ int32_t lists[4][ROW_CAP];
+    __shared__ int32_t fsls[4][ROW_CAP];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    int32_t *list = lists[wv];
+    int32_t *fsl = fsls[wv];
+    if (fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE) return;
+    const int n = g.n_slots;
+    const int nw = (n + 31) / 32;
+    const int64_t nwp = (g.P + 31) / 32;
+    int my_rows = 0, my_fs = 0, my_sweeps = 0;
+    for (int32_t i = blockIdx.x * 4 + wv; i < n; i += gridDim.x * 4) {
+        if (((fa.row_bits[i >> 5] >> (i & 31)) & 1u) == 0) continue;
+        ++my_rows;
+        if (lane == 0) atomicAnd(&fa.row_bits[i >> 5], ~(1u << (i & 31)));
+        if (reset_only) continue;
+        // flagged columns of row i -> list (at most ROW_CAP kept)
+        const uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
+        int cnt = 0;
+        for (int b = 0; b < nw; b += 64) {  // wave-uniform
+            const int w = b + lane;
+            uint32_t bits = w < nw ? fw[w] : 0u;
+            const int c = __popc(bits);
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(incl, o);
+                if (lane >= o) incl += t;
+            }
+            int pos = cnt + incl - c;
+            while (bits) {
+                const int bt = __ffs(bits) - 1;
+                bits &= bits - 1;
+                if (pos < ROW_CAP) list[pos] = w * 32 + bt;
+                ++pos;
+            }
+            cnt += __shfl(incl, 63);
+        }
+        if (cnt > ROW_CAP) {
+            if (lane == 0) {
+                fa.heavy_epoch[i] = fa.epoch;
+                fa.heavy_rows[atomicAdd(&g.ctl->heavy_count, 1)] = i;
+            }
+            continue;
+        }
+        int32_t *Drow = g.D + (int64_t)i * g.ld;
+        __threadfence_block();
+        for (int e = lane; e < cnt; e += 64) Drow[list[e]] = (int32_t)INF;
+        if (fa.mode == FUSED_REMOVE && lane == 0) Drow[fa.k] = (int32_t)INF;
+        __threadfence_block();
+        int sweeps = 0;
+        wave_bellman_ford(g, Drow, list, cnt, fsl, sweeps, my_fs);
+        my_sweeps = max(my_sweeps, sweeps);
+    }
+    if (lane == 0 && my_rows) atomicAdd(&g.ctl->rows, my_rows);
+    if (lane == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
+    if (lane == 0 && my_sweeps) atomicMax(&g.ctl->sweeps, my_sweeps);
+}
+
+// Pass B: the heavy rows, one block each with the row in LDS.
+//   undirected: D' is symmetric, so a flagged (i, j) whose row j was light
+//   is copied from D'[j][i]; the heavy-heavy entries are recomputed by
+//   Bellman-Ford against the now exact remainder of the row.
+//   directed: every flagged entry is recomputed by Bellman-Ford.
 __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, FusedArgs fa) {
     extern __shared__ uint32_t sm[];
     FusedShared sh = fused_shared(g, sm);
@@ -1002,17 +1221,18 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, Fused
         w_old = (uint32_t)g.ctl->w_old;
     }
     const int count = g.ctl->heavy_count;
+    const int fill = g.undirected ? 1 : 0;
     int32_t *glist = fa.scratch + (int64_t)blockIdx.x * 2 * g.P;
     int32_t *fsl = glist + g.P;
     int my_fs = 0, my_sweeps = 0;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int32_t i = fa.heavy_rows[idx];
         const RowTests rt = row_tests(g, fa, i, w_old);
-        block_sum256(mask_row(g, fa, i, rt, sh, true, 1), sh.red);
-        const int hh = compact_bits(sh.fl2, nw, glist, sh.red);
+        block_sum256(mask_row(g, fa, i, rt, sh, true, fill), sh.red);
+        const int todo = compact_bits(fill ? sh.fl2 : sh.fl, nw, glist, sh.red);
         int sweeps = 0;
-        if (hh > 0) row_bellman_ford(g, sh, glist, hh, fsl, sweeps, my_fs);
-        const int all = compact_bits(sh.fl, nw, glist, sh.red);
+        if (todo > 0) row_bellman_ford(g, sh, glist, todo, fsl, sweeps, my_fs);
+        const int all = fill ? compact_bits(sh.fl, nw, glist, sh.red) : todo;
         int32_t *Drow = g.D + (int64_t)i * g.ld;
         for (int e = tid; e < all; e += FUSED_THREADS) {
             const int32_t y = glist[e];
@@ -1025,17 +1245,25 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, Fused
     if (tid == 0 && my_sweeps) atomicMax(&g.ctl->sweeps, my_sweeps);
 }
 
-void launch_fused(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    const int grid = g.n_slots < FUSED_GRID ? g.n_slots : FUSED_GRID;
-    k_fused<<<grid, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
-    if (g.undirected) k_fused_heavy<<<FUSED_GRID / 2, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
+    dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS);
+    if (fa.mode == FUSED_REMOVE) k_mask_detect<FUSED_REMOVE><<<grid, 256, 0, s>>>(g, fa);
+    else k_mask_detect<FUSED_INCREASE><<<grid, 256, 0, s>>>(g, fa);
 }
 
-size_t nin_build_lds_bytes(int32_t) { return 0; }
+void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
+    k_count_flag_rows<<<1, 256, 0, s>>>(g, fa);
+}
 
-// The mask + recompute kernel keeps a whole row in LDS; APSP_MAX_CAPACITY is
-// the largest capacity whose row (plus flags) fits the 160 KiB of one CU.
+void launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_recompute_rows<<<RECOMPUTE_BLOCKS, 256, 0, s>>>(g, fa, reset_only);
+    if (!reset_only) k_fused_heavy<<<FUSED_GRID, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
+}
+
 static_assert(APSP_MAX_CAPACITY % TILE == 0, "capacity limit must be a tile multiple");
 static_assert(((size_t)APSP_MAX_CAPACITY + 2 * (APSP_MAX_CAPACITY / 32) + LDS_LIST + 64) * 4 <= 163840,
               "a row of the largest graph must fit in LDS");
@@ -1043,11 +1271,15 @@ static_assert(((size_t)APSP_MAX_CAPACITY + 2 * (APSP_MAX_CAPACITY / 32) + LDS_LI
 hipError_t configure_kernels() {
     static hipError_t status = hipErrorNotReady;
     if (status != hipErrorNotReady) return status;
-    status = hipFuncSetAttribute((const void *)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+    status = hipFuncSetAttribute((const void *)k_fused_heavy, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)fused_lds_bytes(APSP_MAX_CAPACITY));
+    const int sel = (int)(nin_build_lds_bytes(APSP_MAX_CAPACITY) + sizeof(SelectShared));
     if (status == hipSuccess)
-        status = hipFuncSetAttribute((const void *)k_fused_heavy, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)fused_lds_bytes(APSP_MAX_CAPACITY));
+        status = hipFuncSetAttribute((const void *)k_nin_build, hipFuncAttributeMaxDynamicSharedMemorySize, sel);
+    if (status == hipSuccess)
+        status = hipFuncSetAttribute((const void *)k_select_vec, hipFuncAttributeMaxDynamicSharedMemorySize, sel);
+    if (status == hipSuccess)
+        status = hipFuncSetAttribute((const void *)k_nin_rebuild_queue, hipFuncAttributeMaxDynamicSharedMemorySize, sel);
     (void)hipGetLastError();  // do not leave the status for an unrelated launch check
     return status;
 }
