@@ -42,6 +42,14 @@ def parse():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--cold-reps", type=int, default=3)
     ap.add_argument("--trace", action="store_true", help="log per-update mask statistics during warmup")
+    ap.add_argument("--mix", default="all", choices=["all", "add", "remove", "decrease", "increase"],
+                    help="update kinds of a step (profiling runs of one kind); 'all' is the benchmark mix")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (counter calibration)")
+    ap.add_argument("--workload", default="updates", choices=["updates", "batched"],
+                    help="updates: the n=16384 update stream (default); batched: 512 graphs with 8 queued "
+                         "updates each, one persistent launch vs one call per update")
+    ap.add_argument("--graphs", type=int, default=512, help="batched: number of graphs")
     return ap.parse_args()
 
 
@@ -113,23 +121,170 @@ def cpu_baseline(adj, budget_s=12.0):
 # main
 # ---------------------------------------------------------------------------
 
+def batch_items(wls, W):
+    items = []
+    for gi, w in enumerate(wls):
+        for up in w.updates:
+            if up.kind == W.ADD:
+                items.append(("add", gi, up.w_out, up.w_in))
+            elif up.kind == W.REMOVE:
+                items.append(("remove", gi, up.u))
+            else:
+                items.append(("edge", gi, up.u, up.v, up.w))
+    return items
+
+
+def bench_batched(args):
+    """512 directed complete graphs (n log-uniform in [128, 2048]), 8 queued
+    updates each: one autotuned, graph-replayed persistent launch against the
+    plain path (one library call, i.e. one set of kernel launches, per
+    update).  Each timed run starts from fresh device copies of the same
+    cold-started graphs; the two paths' final matrices are compared."""
+    import torch
+    from paper_2412_15122_amd import workloads as W
+    from paper_2412_15122_amd.apsp import Graph
+    from paper_2412_15122_amd.batch import Batch
+    from paper_2412_15122_amd import autotune
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    wls = W.config4(graphs=args.graphs)
+    log(f"[bench] {len(wls)} graphs generated in {time.perf_counter() - t:.1f}s")
+    base = [Graph(w.adj, undirected=False, capacity=w.adj.shape[0] + 8) for w in wls]
+    torch.cuda.synchronize()
+    items = batch_items(wls, W)
+    n_upd = len(items)
+    ns = np.array([w.adj.shape[0] for w in wls])
+    log(f"[bench] cold starts done; {n_upd} updates; sum n^2 = {int((ns.astype(np.int64) ** 2).sum())}")
+    tuned = autotune.tune(base, items, reps=2, force=True)
+    cfg = tuned["config"]
+    log(f"[bench] autotuned config {cfg} ({tuned['ms']} ms); table: " +
+        ", ".join(f"g{r['grid']}/o{r['order']}/v{r['variant']}={r['ms']}" for r in tuned["table"]))
+    b = Batch(len(base), n_upd, **cfg)
+    prep = b.prepare(base, items)
+
+    # staged device weights for the plain path (resident before timing)
+    dev_w = []
+    for it in items:
+        if it[0] == "add":
+            dev_w.append((torch.from_numpy(np.ascontiguousarray(it[2])).cuda(),
+                          torch.from_numpy(np.ascontiguousarray(it[3])).cuda()))
+        else:
+            dev_w.append(None)
+
+    def plain(gs):
+        for t, it in enumerate(items):
+            g = gs[it[1]]
+            if it[0] == "add":
+                g.add_node_device(dev_w[t][0].data_ptr(), dev_w[t][1].data_ptr())
+            elif it[0] == "remove":
+                g.remove_node(it[2])
+            else:
+                g.update_edge(it[2], it[3], it[4])
+
+    batched_ms, plain_ms, verify = [], [], True
+    for rep in range(args.warmup + args.steps):
+        ga = [g.clone() for g in base]
+        gb = [g.clone() for g in base]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        b.submit(prep, graphs=ga)
+        e1.record()
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) * 1e3
+        st_us, en_us = b.graph_times(len(base))
+        dur = en_us - st_us
+        big = int(np.argmax(ns))
+        spans = {"makespan_us": round(float(en_us.max()), 1), "max_graph_us": round(float(dur.max()), 1),
+                 "mean_graph_us": round(float(dur.mean()), 1), "largest_graph_us": round(float(dur[big]), 1),
+                 "largest_graph_n": int(ns[big]), "last_start_us": round(float(st_us.max()), 1)}
+        log(f"[bench] per-graph spans: {spans}")
+        t0 = time.perf_counter()
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2.record()
+        plain(gb)
+        e3.record()
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) * 1e3
+        same = all(torch.equal(x.matrix_device("D"), y.matrix_device("D")) for x, y in zip(ga, gb))
+        verify = verify and same
+        log(f"[bench] rep {rep}: batched {tb:.2f} ms wall ({e0.elapsed_time(e1):.2f} ms events), "
+            f"plain {tp:.1f} ms wall ({e2.elapsed_time(e3):.1f} ms events), equal={same}")
+        if rep >= args.warmup:
+            batched_ms.append(tb)
+            plain_ms.append(tp)
+        for x in ga + gb:
+            x.close()
+    bt, pt = float(np.median(batched_ms)), float(np.median(plain_ms))
+    # algorithmic bytes: one read of D per add (relaxation) and per removal
+    # (mask); live counts replayed per graph
+    alg = 0
+    for gi, w in enumerate(wls):
+        live = w.adj.shape[0]
+        for up in w.updates:
+            if up.kind == W.ADD:
+                alg += 4 * live * live
+                live += 1
+            elif up.kind == W.REMOVE:
+                alg += 4 * (live - 1) * live
+                live -= 1
+    achieved = alg / (bt * 1e-3) / 1e9
+    out = {
+        "metric": "batched warm-start APSP updates/s (512 graphs x 8 updates, 1 GPU)",
+        "value": round(n_upd / (bt * 1e-3), 1),
+        "unit": "updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(bt, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": (f"{len(wls)} directed complete graphs, n log-uniform in [128, 2048], weights "
+                                f"U[1,5000], {n_upd} queued updates (8 per graph), one persistent launch"),
+                   "graphs": len(wls), "updates_per_step": n_upd, "parallelism": "none (1 GPU)",
+                   "launch": cfg},
+        "plain_path": {"ms_per_step": round(pt, 2), "updates_per_s": round(n_upd / (pt * 1e-3), 1),
+                       "what": "one library call (its kernel launches) per update, same updates"},
+        "batched_vs_plain_speedup": round(pt / bt, 2),
+        "per_graph_spans": spans,
+        "verified_vs_plain": verify,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_batch (whole launch)",
+                     "algorithmic_bytes_per_launch": alg},
+        "autotune": {"key": tuned["key"], "table": tuned["table"]},
+    }
+    b.close()
+    for g in base:
+        g.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path is single-GPU by design "
               "(multi-GPU sharding is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
     import torch
     from paper_2412_15122_amd import workloads as W
     from paper_2412_15122_amd.apsp import Graph, kernel_names
     from paper_2412_15122_amd import _native as N
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = args.n
     steps_total = args.warmup + args.steps
     per = args.updates
     counts = {W.ADD: per * 3 // 10, W.REMOVE: per * 2 // 10, W.DECREASE: per // 4, W.INCREASE: per // 4}
     counts[W.INCREASE] = per - counts[W.ADD] - counts[W.REMOVE] - counts[W.DECREASE]
+    if args.mix != "all":
+        counts = {k: (per if k == args.mix else 0) for k in counts}
     growth = counts[W.ADD] - counts[W.REMOVE]
     cap = n + max(growth, 0) * steps_total + 256
 
@@ -206,7 +361,7 @@ def main():
     stats_all = []
     for step in range(steps_total):
         timed = step >= args.warmup
-        worst = worst_case_edge()
+        worst = worst_case_edge() if counts[W.INCREASE] > 0 else None
         block = stream.next_block(worst=worst)
         dev, ptrs = stage(block)
         torch.cuda.synchronize()

@@ -230,6 +230,76 @@ apsp_status apsp_profile_read(apsp_graph *g, int32_t kernel, int64_t *launches, 
 int32_t apsp_kernel_count(void);
 const char *apsp_kernel_name(int32_t kernel);
 
+/* ---- copies of a graph ------------------------------------------------- */
+
+/* A second handle with the same state as g (matrices, index, ids), in the
+ * caller's buffer dev_buf of apsp_required_bytes(capacity of g, kind of g)
+ * bytes, enqueued on hip_stream after waiting for g's stream.  The copy is
+ * independent of g from then on.  Errors as apsp_cold. */
+apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes, void *hip_stream,
+                             apsp_graph **out);
+
+/* ---- batched updates --------------------------------------------------- */
+
+/* Many graphs and their queued updates run in one persistent launch: every
+ * work-group takes one graph at a time (by default the graph with the most
+ * work first) and applies that graph's items in the order they appear in
+ * the item array, with the same semantics, and bit for bit the same
+ * matrices, as the single calls above (apsp_add_node, apsp_remove_node,
+ * apsp_update_edge, apsp_query).  Graphs of a batch need capacity <=
+ * APSP_BATCH_MAX_CAPACITY.  The fallback policy is not applied inside a
+ * batch: removals and increases always take the masked recompute. */
+#define APSP_BATCH_MAX_CAPACITY 32768
+
+typedef enum {
+    APSP_OP_ADD_NODE = 1,    /* w_out_dev, w_in_dev as apsp_add_node */
+    APSP_OP_REMOVE_NODE = 2, /* u = id */
+    APSP_OP_UPDATE_EDGE = 3, /* u -> v gets weight w */
+    APSP_OP_QUERY = 4        /* u -> v; the result goes to out_dev */
+} apsp_batch_op;
+
+typedef struct {
+    int32_t graph;            /* index into the graphs array of apsp_batch_run */
+    int32_t op;               /* apsp_batch_op */
+    int32_t u, v, w;
+    int32_t out_cap;          /* query: int32 slots at out_dev, >= 3 + live nodes */
+    const int32_t *w_out_dev; /* add: out-edge weights, one per live node, ascending ids */
+    const int32_t *w_in_dev;  /* add, directed graphs: in-edge weights */
+    int32_t *out_dev;         /* query: [distance, path length, status (0 ok), path ids...] */
+} apsp_batch_item;
+
+typedef struct apsp_batch apsp_batch;
+
+/* Device workspace for batches of up to max_graphs graphs and max_items items. */
+size_t apsp_batch_workspace_bytes(int32_t max_graphs, int32_t max_items);
+/* ws_dev: caller-owned device buffer of apsp_batch_workspace_bytes bytes,
+ * 256-byte aligned, alive until apsp_batch_destroy. */
+apsp_status apsp_batch_create(void *ws_dev, size_t ws_bytes, int32_t max_graphs, int32_t max_items,
+                              apsp_batch **out);
+apsp_status apsp_batch_destroy(apsp_batch *b);
+/* grid: work-groups of the persistent launch (0: two per compute unit, at
+ * most one per graph); order: 0 most work first, 1 array order; variant:
+ * loads in flight per thread in the streaming loops (0: one, 1: two);
+ * use_graph: 1 records the launch once in a HIP graph and replays it. */
+apsp_status apsp_batch_set_config(apsp_batch *b, int32_t grid, int32_t order, int32_t variant,
+                                  int32_t use_graph);
+/* Runs items[0..num_items) on graphs[0..num_graphs) (distinct handles) on
+ * hip_stream.  Work queued earlier for a graph on another stream must have
+ * completed.  Every item is checked first; if one is invalid, nothing runs,
+ * no graph changes, and the status names the first bad item.  new_ids
+ * (host, num_items, may be NULL) receives the id of each added node and -1
+ * for other items.  Returns once the launch is enqueued; query results are
+ * in out_dev when the stream reaches that point. */
+apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num_graphs,
+                           const apsp_batch_item *items, int32_t num_items, void *hip_stream,
+                           int32_t *new_ids);
+/* Per-graph timing of the last apsp_batch_run, read from the device wall
+ * clock (synchronous: waits for that run's stream).  start_us[i] / end_us[i]
+ * are when a work-group took graphs[i] and finished its items, in
+ * microseconds from the earliest start; -1 for graphs without items.
+ * num_graphs must equal that run's. */
+apsp_status apsp_batch_graph_times(apsp_batch *b, double *start_us, double *end_us, int32_t num_graphs);
+
 const char *apsp_last_error(void);
 int32_t apsp_abi_version(void);
 

@@ -25,6 +25,11 @@ APSP_FALLBACK_NEVER = 0
 APSP_FALLBACK_COST = 1
 APSP_FALLBACK_ALWAYS = 2
 APSP_MAX_CAPACITY = 38272
+APSP_BATCH_MAX_CAPACITY = 32768
+APSP_OP_ADD_NODE = 1
+APSP_OP_REMOVE_NODE = 2
+APSP_OP_UPDATE_EDGE = 3
+APSP_OP_QUERY = 4
 
 STATUS_NAMES = {
     APSP_OK: "APSP_OK", APSP_E_INVALID: "APSP_E_INVALID", APSP_E_NOT_FOUND: "APSP_E_NOT_FOUND",
@@ -48,6 +53,20 @@ class UpdateStats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("graph", ctypes.c_int32),
+        ("op", ctypes.c_int32),
+        ("u", ctypes.c_int32),
+        ("v", ctypes.c_int32),
+        ("w", ctypes.c_int32),
+        ("out_cap", ctypes.c_int32),
+        ("w_out_dev", ctypes.c_void_p),
+        ("w_in_dev", ctypes.c_void_p),
+        ("out_dev", ctypes.c_void_p),
+    ]
 
 
 _lib = None
@@ -82,6 +101,13 @@ SIGNATURES = {
     "apsp_set_index_limit": (_I32, [_P, _I32]),
     "apsp_profile": (_I32, [_P, _I64]),
     "apsp_profile_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
+    "apsp_graph_clone": (_I32, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "apsp_batch_workspace_bytes": (ctypes.c_size_t, [_I32, _I32]),
+    "apsp_batch_create": (_I32, [_P, ctypes.c_size_t, _I32, _I32, ctypes.POINTER(_P)]),
+    "apsp_batch_destroy": (_I32, [_P]),
+    "apsp_batch_set_config": (_I32, [_P, _I32, _I32, _I32, _I32]),
+    "apsp_batch_run": (_I32, [_P, ctypes.POINTER(_P), _I32, ctypes.POINTER(BatchItem), _I32, _P, _PI32]),
+    "apsp_batch_graph_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _I32]),
 }
 
 

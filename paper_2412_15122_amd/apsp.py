@@ -66,6 +66,32 @@ class Graph:
         self._h = h
         self._keep = []
 
+    @classmethod
+    def _from_handle(cls, lib, h, buf, ptr, nbytes, cap, kind, stream):
+        g = cls.__new__(cls)
+        g._lib = lib
+        g._h = h
+        g._buf = buf
+        g._ptr = ptr
+        g._nbytes = nbytes
+        g.capacity = cap
+        g.kind = kind
+        g.undirected = kind == N.APSP_UNDIRECTED
+        g._stream = stream
+        g._keep = []
+        return g
+
+    def clone(self) -> "Graph":
+        """An independent copy of this graph (apsp_graph_clone)."""
+        torch = _torch()
+        buf = torch.empty(self._nbytes + 256, dtype=torch.uint8, device="cuda")
+        ptr = (buf.data_ptr() + 255) & ~255
+        stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        N.check(self._lib.apsp_graph_clone(self._h, ptr, self._nbytes, stream.cuda_stream, ctypes.byref(h)),
+                "apsp_graph_clone")
+        return Graph._from_handle(self._lib, h, buf, ptr, self._nbytes, self.capacity, self.kind, stream)
+
     # -- lifetime ------------------------------------------------------------
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -13,106 +13,15 @@
 
 using namespace apsp;
 
-namespace {
+#include "host_graph.h"
 
-thread_local std::string g_err;
+using namespace apsp_host;
 
-apsp_status fail(apsp_status st, const std::string &msg) {
-    g_err = msg;
-    return st;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-int32_t padded(int32_t cap) { return ((cap + TILE - 1) / TILE) * TILE; }
-
-struct Layout {
-    size_t D, A, AT, nin, nin_cnt, nin_beta, id_of_slot, vec, plist, rank_a, rank_b, qbuf, qscratch, fscratch,
-        nin_queue, heavy_rows, heavy_epoch, flag_bits, row_bits, ctl, total;
-};
-
-constexpr int NVEC = 8;  // wo, wi, out, in, colu, colv, rowu, rowv
-
-Layout make_layout(int32_t cap, int32_t kind) {
-    Layout L{};
-    const size_t P = (size_t)padded(cap);
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off = align256(off + bytes);
-        return o;
-    };
-    const size_t mat = P * P * sizeof(int32_t);
-    L.D = take(mat);
-    L.A = take(mat);
-    L.AT = kind == APSP_DIRECTED ? take(mat) : (size_t)-1;
-    L.nin = take(P * NIN_L * sizeof(int2));
-    L.nin_cnt = take(P * 4);
-    L.nin_beta = take(P * 4);
-    L.id_of_slot = take(P * 4);
-    L.vec = take((size_t)NVEC * P * 4);
-    L.plist = take(NIN_L * sizeof(int2) + 256);
-    L.rank_a = take(P * 4);
-    L.rank_b = take(P * 4);
-    L.qbuf = take((P + 8) * 4);
-    L.qscratch = take(4 * P * 4);
-    L.fscratch = take((size_t)FUSED_GRID * 2 * P * 4);
-    L.nin_queue = take(P * 4);
-    L.heavy_rows = take(P * 4);
-    L.heavy_epoch = take(P * 4);
-    L.flag_bits = take(P * ((P + 31) / 32) * 4);
-    L.row_bits = take(((P + 31) / 32) * 4);
-    L.ctl = take(sizeof(Ctl));
-    L.total = off;
-    return L;
-}
-
-enum UpdateKind { UK_NONE = 0, UK_ADD = 1, UK_REMOVE = 2, UK_DECREASE = 3, UK_INCREASE = 4 };
-
-struct ProfImpl {
-    hipStream_t stream = nullptr;
-    int64_t mask = 0;
-    std::vector<hipEvent_t> pool;
-    size_t used = 0;
-    struct Rec {
-        int32_t kid;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> recs;
-    int32_t cur_kid = -1;
-    hipEvent_t cur_a = nullptr;
-    int64_t count[KID_COUNT] = {};
-    double ms[KID_COUNT] = {};
-
-    hipEvent_t take() {
-        if (used == pool.size()) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            pool.push_back(e);
-        }
-        return pool[used++];
-    }
-    void collect() {
-        for (auto &r : recs) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
-                count[r.kid] += 1;
-                ms[r.kid] += t;
-            }
-        }
-        recs.clear();
-        used = 0;
-    }
-    ~ProfImpl() {
-        for (auto e : pool) (void)hipEventDestroy(e);
-    }
-};
-
-}  // namespace
+thread_local std::string apsp_host::g_err;
 
 namespace apsp {
 void Prof::begin(int32_t kid) {
-    auto *p = static_cast<ProfImpl *>(impl);
+    auto *p = static_cast<apsp_host::ProfImpl *>(impl);
     if (!on || !p || !((p->mask >> kid) & 1)) {
         if (p) p->cur_kid = -1;
         return;
@@ -124,7 +33,7 @@ void Prof::begin(int32_t kid) {
     p->cur_a = e;
 }
 void Prof::end() {
-    auto *p = static_cast<ProfImpl *>(impl);
+    auto *p = static_cast<apsp_host::ProfImpl *>(impl);
     if (!on || !p || p->cur_kid < 0) return;
     hipEvent_t e = p->take();
     if (!e) return;
@@ -134,68 +43,7 @@ void Prof::end() {
 }
 }  // namespace apsp
 
-struct apsp_graph {
-    int32_t cap = 0, P = 0, kind = 0;
-    hipStream_t stream = nullptr;
-    char *base = nullptr;
-    DevGraph dg{};
-    int32_t *vec[NVEC] = {};
-    int2 *plist = nullptr;
-    int32_t *plist_cnt = nullptr, *plist_beta = nullptr;
-    int32_t *rank_cur = nullptr, *rank_other = nullptr;
-    int32_t *qbuf = nullptr, *qscratch = nullptr, *fscratch = nullptr, *nin_queue = nullptr;
-    int32_t *heavy_rows = nullptr, *heavy_epoch = nullptr;
-    uint32_t *flag_bits = nullptr, *row_bits = nullptr;
-    int32_t epoch = 0;
-    // host bookkeeping
-    int32_t n_live = 0, max_id = -1;
-    std::vector<int32_t> live_ids;  // ascending
-    std::unordered_map<int32_t, int32_t> slot_of_id;
-    std::set<int32_t> free_slots;
-    int32_t policy = APSP_FALLBACK_NEVER;
-    double delta = 0.5;
-    int32_t last_kind = UK_NONE, last_n_before = 0, last_fallback = 0;
-    Ctl *ctl_h = nullptr;   // pinned
-    int32_t *qbuf_h = nullptr;  // pinned
-    ProfImpl prof_impl;
-    Prof prof;
-};
-
 namespace {
-
-bool hip_ok(hipError_t e, const char *what) {
-    if (e == hipSuccess) return true;
-    g_err = std::string(what) + ": " + hipGetErrorString(e);
-    return false;
-}
-
-apsp_status check_launch(const char *what) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(APSP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-    return APSP_OK;
-}
-
-int32_t *&wo(apsp_graph *g) { return g->vec[0]; }
-int32_t *&wi(apsp_graph *g) { return g->vec[1]; }
-int32_t *&vout(apsp_graph *g) { return g->vec[2]; }
-int32_t *&vin(apsp_graph *g) { return g->vec[3]; }
-int32_t *&colu(apsp_graph *g) { return g->vec[4]; }
-int32_t *&colv(apsp_graph *g) { return g->vec[5]; }
-int32_t *&rowu(apsp_graph *g) { return g->vec[6]; }
-int32_t *&rowv(apsp_graph *g) { return g->vec[7]; }
-
-int32_t rank_of(const apsp_graph *g, int32_t id) {
-    auto it = std::lower_bound(g->live_ids.begin(), g->live_ids.end(), id);
-    if (it == g->live_ids.end() || *it != id) return -1;
-    return (int32_t)(it - g->live_ids.begin());
-}
-
-bool lookup(const apsp_graph *g, int32_t id, int32_t *slot) {
-    auto it = g->slot_of_id.find(id);
-    if (it == g->slot_of_id.end()) return false;
-    *slot = it->second;
-    return true;
-}
 
 apsp_status read_ctl(apsp_graph *g) {
     if (!hip_ok(hipMemcpyAsync(g->ctl_h, g->dg.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream), "read ctl"))
@@ -234,6 +82,58 @@ apsp_status decide_fallback(apsp_graph *g, const FusedArgs *fa, int32_t n_before
     *fallback = cost > g->delta;
     launch_fill(&g->dg.ctl->rows, 1, 0, g->stream);  // the recompute counts Phi again
     return check_launch("cost decision");
+}
+
+// A handle over the caller's buffer: pinned host mirrors and the carving of
+// dev_buf by make_layout; nothing is enqueued.
+apsp_status make_handle(int32_t capacity, int32_t kind, void *dev_buf, hipStream_t stream, apsp_graph **out) {
+    const Layout L = make_layout(capacity, kind);
+    apsp_graph *g = new (std::nothrow) apsp_graph();
+    if (!g) return fail(APSP_E_INVALID, "out of host memory");
+    g->cap = capacity;
+    g->P = padded(capacity);
+    g->kind = kind;
+    g->stream = stream;
+    g->base = (char *)dev_buf;
+    if (!hip_ok(hipHostMalloc((void **)&g->ctl_h, sizeof(Ctl), 0), "pinned alloc") ||
+        !hip_ok(hipHostMalloc((void **)&g->qbuf_h, (size_t)(g->P + 8) * 4, 0), "pinned alloc")) {
+        apsp_graph_destroy(g);
+        return APSP_E_DEVICE;
+    }
+    char *b = g->base;
+    DevGraph &d = g->dg;
+    d.D = (int32_t *)(b + L.D);
+    d.A = (int32_t *)(b + L.A);
+    d.AT = kind == APSP_DIRECTED ? (int32_t *)(b + L.AT) : nullptr;
+    d.nin = (int2 *)(b + L.nin);
+    d.nin_cnt = (int32_t *)(b + L.nin_cnt);
+    d.nin_beta = (int32_t *)(b + L.nin_beta);
+    d.id_of_slot = (int32_t *)(b + L.id_of_slot);
+    d.ctl = (Ctl *)(b + L.ctl);
+    d.ld = g->P;
+    d.P = g->P;
+    d.n_slots = 0;
+    d.undirected = kind == APSP_UNDIRECTED;
+    d.lim = NIN_L;
+    for (int v = 0; v < NVEC; ++v) g->vec[v] = (int32_t *)(b + L.vec) + (size_t)v * g->P;
+    g->plist = (int2 *)(b + L.plist);
+    g->plist_cnt = (int32_t *)(b + L.plist + NIN_L * sizeof(int2));
+    g->plist_beta = g->plist_cnt + 1;
+    g->rank_cur = (int32_t *)(b + L.rank_a);
+    g->rank_other = (int32_t *)(b + L.rank_b);
+    g->qbuf = (int32_t *)(b + L.qbuf);
+    g->qscratch = (int32_t *)(b + L.qscratch);
+    g->fscratch = (int32_t *)(b + L.fscratch);
+    g->nin_queue = (int32_t *)(b + L.nin_queue);
+    g->heavy_rows = (int32_t *)(b + L.heavy_rows);
+    g->heavy_epoch = (int32_t *)(b + L.heavy_epoch);
+    g->flag_bits = (uint32_t *)(b + L.flag_bits);
+    g->row_bits = (uint32_t *)(b + L.row_bits);
+    g->prof_impl.stream = g->stream;
+    g->prof.impl = &g->prof_impl;
+
+    *out = g;
+    return APSP_OK;
 }
 
 FusedArgs fused_args(apsp_graph *g, int32_t mode) {
@@ -292,50 +192,10 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
     const Layout L = make_layout(capacity, kind);
     if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, "apsp_cold: dev_buf smaller than apsp_required_bytes");
 
-    apsp_graph *g = new (std::nothrow) apsp_graph();
-    if (!g) return fail(APSP_E_INVALID, "apsp_cold: out of host memory");
-    g->cap = capacity;
-    g->P = padded(capacity);
-    g->kind = kind;
-    g->stream = (hipStream_t)hip_stream;
-    g->base = (char *)dev_buf;
-    if (!hip_ok(hipHostMalloc((void **)&g->ctl_h, sizeof(Ctl), 0), "pinned alloc") ||
-        !hip_ok(hipHostMalloc((void **)&g->qbuf_h, (size_t)(g->P + 8) * 4, 0), "pinned alloc")) {
-        apsp_graph_destroy(g);
-        return APSP_E_DEVICE;
-    }
-    char *b = g->base;
+    apsp_graph *g = nullptr;
+    apsp_status st0 = make_handle(capacity, kind, dev_buf, (hipStream_t)hip_stream, &g);
+    if (st0) return st0;
     DevGraph &d = g->dg;
-    d.D = (int32_t *)(b + L.D);
-    d.A = (int32_t *)(b + L.A);
-    d.AT = kind == APSP_DIRECTED ? (int32_t *)(b + L.AT) : nullptr;
-    d.nin = (int2 *)(b + L.nin);
-    d.nin_cnt = (int32_t *)(b + L.nin_cnt);
-    d.nin_beta = (int32_t *)(b + L.nin_beta);
-    d.id_of_slot = (int32_t *)(b + L.id_of_slot);
-    d.ctl = (Ctl *)(b + L.ctl);
-    d.ld = g->P;
-    d.P = g->P;
-    d.n_slots = 0;
-    d.undirected = kind == APSP_UNDIRECTED;
-    d.lim = NIN_L;
-    for (int v = 0; v < NVEC; ++v) g->vec[v] = (int32_t *)(b + L.vec) + (size_t)v * g->P;
-    g->plist = (int2 *)(b + L.plist);
-    g->plist_cnt = (int32_t *)(b + L.plist + NIN_L * sizeof(int2));
-    g->plist_beta = g->plist_cnt + 1;
-    g->rank_cur = (int32_t *)(b + L.rank_a);
-    g->rank_other = (int32_t *)(b + L.rank_b);
-    g->qbuf = (int32_t *)(b + L.qbuf);
-    g->qscratch = (int32_t *)(b + L.qscratch);
-    g->fscratch = (int32_t *)(b + L.fscratch);
-    g->nin_queue = (int32_t *)(b + L.nin_queue);
-    g->heavy_rows = (int32_t *)(b + L.heavy_rows);
-    g->heavy_epoch = (int32_t *)(b + L.heavy_epoch);
-    g->flag_bits = (uint32_t *)(b + L.flag_bits);
-    g->row_bits = (uint32_t *)(b + L.row_bits);
-    g->prof_impl.stream = g->stream;
-    g->prof.impl = &g->prof_impl;
-
     if (hipError_t e = configure_kernels(); e != hipSuccess) {
         apsp_graph_destroy(g);
         return fail(APSP_E_DEVICE, std::string("configuring kernels: ") + hipGetErrorString(e));
@@ -397,6 +257,50 @@ apsp_status apsp_graph_destroy(apsp_graph *g) {
     if (g->ctl_h) (void)hipHostFree(g->ctl_h);
     if (g->qbuf_h) (void)hipHostFree(g->qbuf_h);
     delete g;
+    return APSP_OK;
+}
+
+apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes, void *hip_stream,
+                             apsp_graph **out) {
+    if (!out) return fail(APSP_E_INVALID, "apsp_graph_clone: out is NULL");
+    *out = nullptr;
+    if (!g) return fail(APSP_E_INVALID, "apsp_graph_clone: NULL graph");
+    if (!dev_buf) return fail(APSP_E_INVALID, "apsp_graph_clone: dev_buf is NULL");
+    if (((uintptr_t)dev_buf & 255) != 0) return fail(APSP_E_INVALID, "apsp_graph_clone: dev_buf not 256-byte aligned");
+    const Layout L = make_layout(g->cap, g->kind);
+    if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, "apsp_graph_clone: dev_buf smaller than apsp_required_bytes");
+    if ((char *)dev_buf < g->base + L.total && g->base < (char *)dev_buf + L.total)
+        return fail(APSP_E_INVALID, "apsp_graph_clone: dev_buf overlaps the source graph");
+    apsp_graph *c = nullptr;
+    apsp_status st = make_handle(g->cap, g->kind, dev_buf, (hipStream_t)hip_stream, &c);
+    if (st) return st;
+    hipEvent_t ev = nullptr;
+    bool ok = hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event") &&
+              hip_ok(hipEventRecord(ev, g->stream), "event record") &&
+              hip_ok(hipStreamWaitEvent(c->stream, ev, 0), "stream wait") &&
+              hip_ok(hipMemcpyAsync(c->base, g->base, L.total, hipMemcpyDeviceToDevice, c->stream), "clone copy");
+    if (ev) (void)hipEventDestroy(ev);
+    if (!ok) {
+        apsp_graph_destroy(c);
+        return APSP_E_DEVICE;
+    }
+    const int64_t ro = (char *)g->rank_cur - g->base;
+    c->rank_cur = (int32_t *)(c->base + ro);
+    c->rank_other = (int32_t *)(c->base + ((char *)g->rank_other - g->base));
+    c->dg.n_slots = g->dg.n_slots;
+    c->dg.lim = g->dg.lim;
+    c->epoch = g->epoch;
+    c->n_live = g->n_live;
+    c->max_id = g->max_id;
+    c->live_ids = g->live_ids;
+    c->slot_of_id = g->slot_of_id;
+    c->free_slots = g->free_slots;
+    c->policy = g->policy;
+    c->delta = g->delta;
+    c->last_kind = g->last_kind;
+    c->last_n_before = g->last_n_before;
+    c->last_fallback = g->last_fallback;
+    *out = c;
     return APSP_OK;
 }
 

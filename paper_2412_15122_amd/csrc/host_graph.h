@@ -1,0 +1,177 @@
+// Host-side state of a graph handle and the helpers the C ABI's units share:
+// the device buffer layout, the id <-> slot map, and error reporting.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <set>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "apsp_internal.h"
+
+namespace apsp_host {
+
+using namespace apsp;
+
+extern thread_local std::string g_err;
+
+inline apsp_status fail(apsp_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline int32_t padded(int32_t cap) { return ((cap + TILE - 1) / TILE) * TILE; }
+
+struct Layout {
+    size_t D, A, AT, nin, nin_cnt, nin_beta, id_of_slot, vec, plist, rank_a, rank_b, qbuf, qscratch, fscratch,
+        nin_queue, heavy_rows, heavy_epoch, flag_bits, row_bits, ctl, total;
+};
+
+constexpr int NVEC = 8;  // wo, wi, out, in, colu, colv, rowu, rowv
+
+inline Layout make_layout(int32_t cap, int32_t kind) {
+    Layout L{};
+    const size_t P = (size_t)padded(cap);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t mat = P * P * sizeof(int32_t);
+    L.D = take(mat);
+    L.A = take(mat);
+    L.AT = kind == APSP_DIRECTED ? take(mat) : (size_t)-1;
+    L.nin = take(P * NIN_L * sizeof(int2));
+    L.nin_cnt = take(P * 4);
+    L.nin_beta = take(P * 4);
+    L.id_of_slot = take(P * 4);
+    L.vec = take((size_t)NVEC * P * 4);
+    L.plist = take(NIN_L * sizeof(int2) + 256);
+    L.rank_a = take(P * 4);
+    L.rank_b = take(P * 4);
+    L.qbuf = take((P + 8) * 4);
+    L.qscratch = take(4 * P * 4);
+    L.fscratch = take((size_t)FUSED_GRID * 2 * P * 4);
+    L.nin_queue = take(P * 4);
+    L.heavy_rows = take(P * 4);
+    L.heavy_epoch = take(P * 4);
+    L.flag_bits = take(P * ((P + 31) / 32) * 4);
+    L.row_bits = take(((P + 31) / 32) * 4);
+    L.ctl = take(sizeof(Ctl));
+    L.total = off;
+    return L;
+}
+
+enum UpdateKind { UK_NONE = 0, UK_ADD = 1, UK_REMOVE = 2, UK_DECREASE = 3, UK_INCREASE = 4 };
+
+struct ProfImpl {
+    hipStream_t stream = nullptr;
+    int64_t mask = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec {
+        int32_t kid;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    int32_t cur_kid = -1;
+    hipEvent_t cur_a = nullptr;
+    int64_t count[KID_COUNT] = {};
+    double ms[KID_COUNT] = {};
+
+    hipEvent_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void collect() {
+        for (auto &r : recs) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                count[r.kid] += 1;
+                ms[r.kid] += t;
+            }
+        }
+        recs.clear();
+        used = 0;
+    }
+    ~ProfImpl() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace apsp_host
+
+struct apsp_graph {
+    using ProfImpl = apsp_host::ProfImpl;
+    int32_t cap = 0, P = 0, kind = 0;
+    hipStream_t stream = nullptr;
+    char *base = nullptr;
+    apsp::DevGraph dg{};
+    int32_t *vec[apsp_host::NVEC] = {};
+    int2 *plist = nullptr;
+    int32_t *plist_cnt = nullptr, *plist_beta = nullptr;
+    int32_t *rank_cur = nullptr, *rank_other = nullptr;
+    int32_t *qbuf = nullptr, *qscratch = nullptr, *fscratch = nullptr, *nin_queue = nullptr;
+    int32_t *heavy_rows = nullptr, *heavy_epoch = nullptr;
+    uint32_t *flag_bits = nullptr, *row_bits = nullptr;
+    int32_t epoch = 0;
+    // host bookkeeping
+    int32_t n_live = 0, max_id = -1;
+    std::vector<int32_t> live_ids;  // ascending
+    std::unordered_map<int32_t, int32_t> slot_of_id;
+    std::set<int32_t> free_slots;
+    int32_t policy = APSP_FALLBACK_NEVER;
+    double delta = 0.5;
+    int32_t last_kind = apsp_host::UK_NONE, last_n_before = 0, last_fallback = 0;
+    apsp::Ctl *ctl_h = nullptr;   // pinned
+    int32_t *qbuf_h = nullptr;  // pinned
+    ProfImpl prof_impl;
+    apsp::Prof prof;
+};
+
+namespace apsp_host {
+
+inline bool hip_ok(hipError_t e, const char *what) {
+    if (e == hipSuccess) return true;
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+}
+
+inline apsp_status check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(APSP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return APSP_OK;
+}
+
+inline int32_t *&wo(apsp_graph *g) { return g->vec[0]; }
+inline int32_t *&wi(apsp_graph *g) { return g->vec[1]; }
+inline int32_t *&vout(apsp_graph *g) { return g->vec[2]; }
+inline int32_t *&vin(apsp_graph *g) { return g->vec[3]; }
+inline int32_t *&colu(apsp_graph *g) { return g->vec[4]; }
+inline int32_t *&colv(apsp_graph *g) { return g->vec[5]; }
+inline int32_t *&rowu(apsp_graph *g) { return g->vec[6]; }
+inline int32_t *&rowv(apsp_graph *g) { return g->vec[7]; }
+
+inline int32_t rank_of(const apsp_graph *g, int32_t id) {
+    auto it = std::lower_bound(g->live_ids.begin(), g->live_ids.end(), id);
+    if (it == g->live_ids.end() || *it != id) return -1;
+    return (int32_t)(it - g->live_ids.begin());
+}
+
+inline bool lookup(const apsp_graph *g, int32_t id, int32_t *slot) {
+    auto it = g->slot_of_id.find(id);
+    if (it == g->slot_of_id.end()) return false;
+    *slot = it->second;
+    return true;
+}
+
+}  // namespace apsp_host

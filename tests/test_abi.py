@@ -87,3 +87,29 @@ def test_kernel_names(lib):
     names = [lib.apsp_kernel_name(k).decode() for k in range(lib.apsp_kernel_count())]
     assert "mask_recompute" in names and "add_relax" in names and "fw_tiles" in names
     assert lib.apsp_kernel_name(-1) == b""
+
+
+def test_batch_and_clone_host_checks(lib):
+    from paper_2412_15122_amd import _native as N
+    assert lib.apsp_batch_workspace_bytes(0, 1) == 0
+    assert lib.apsp_batch_workspace_bytes(1, 0) == 0
+    small = lib.apsp_batch_workspace_bytes(1, 1)
+    big = lib.apsp_batch_workspace_bytes(512, 4096)
+    assert small % 256 == 0 and big % 256 == 0 and big > small
+    assert big < (8 << 20)                      # launch records only: graphs own their buffers
+    h = ctypes.c_void_p()
+    assert lib.apsp_batch_create(None, 1 << 20, 4, 4, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert lib.apsp_batch_create(ctypes.c_void_p(257), 1 << 20, 4, 4, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert lib.apsp_batch_create(ctypes.c_void_p(256), 16, 4, 4, ctypes.byref(h)) == N.APSP_E_CAPACITY
+    assert lib.apsp_batch_create(ctypes.c_void_p(256), 1 << 20, 0, 4, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert h.value is None
+    assert lib.apsp_batch_set_config(None, 0, 0, 0, 1) == N.APSP_E_INVALID
+    assert lib.apsp_batch_run(None, None, 0, None, 0, None, None) == N.APSP_E_INVALID
+    assert lib.apsp_batch_destroy(None) == N.APSP_OK
+    assert lib.apsp_graph_clone(None, ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert lib.apsp_graph_clone(None, None, 0, None, None) == N.APSP_E_INVALID
+    text = open(HEADER).read()
+    assert int(re.search(r"#define APSP_BATCH_MAX_CAPACITY (\d+)", text).group(1)) == N.APSP_BATCH_MAX_CAPACITY
+    for name in ("APSP_OP_ADD_NODE", "APSP_OP_REMOVE_NODE", "APSP_OP_UPDATE_EDGE", "APSP_OP_QUERY"):
+        assert int(re.search(name + r"\s*=\s*(\d+)", text).group(1)) == getattr(N, name)
+    assert ctypes.sizeof(N.BatchItem) == 48
