@@ -200,6 +200,10 @@ def bench_batched(args):
                  "mean_graph_us": round(float(dur.mean()), 1), "largest_graph_us": round(float(dur[big]), 1),
                  "largest_graph_n": int(ns[big]), "last_start_us": round(float(st_us.max()), 1)}
         log(f"[bench] per-graph spans: {spans}")
+        if rep == 0:
+            for gi in np.argsort(-dur)[:6]:
+                log(f"[bench]   slow graph {gi}: n={ns[gi]} {dur[gi]:.0f} us, updates "
+                    + " ".join(u.kind for u in wls[gi].updates))
         t0 = time.perf_counter()
         e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e2.record()

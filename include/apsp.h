@@ -249,7 +249,7 @@ apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes,
  * apsp_update_edge, apsp_query).  Graphs of a batch need capacity <=
  * APSP_BATCH_MAX_CAPACITY.  The fallback policy is not applied inside a
  * batch: removals and increases always take the masked recompute. */
-#define APSP_BATCH_MAX_CAPACITY 32768
+#define APSP_BATCH_MAX_CAPACITY 16384
 
 typedef enum {
     APSP_OP_ADD_NODE = 1,    /* w_out_dev, w_in_dev as apsp_add_node */

@@ -25,7 +25,7 @@ APSP_FALLBACK_NEVER = 0
 APSP_FALLBACK_COST = 1
 APSP_FALLBACK_ALWAYS = 2
 APSP_MAX_CAPACITY = 38272
-APSP_BATCH_MAX_CAPACITY = 32768
+APSP_BATCH_MAX_CAPACITY = 16384
 APSP_OP_ADD_NODE = 1
 APSP_OP_REMOVE_NODE = 2
 APSP_OP_UPDATE_EDGE = 3

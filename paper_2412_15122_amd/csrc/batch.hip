@@ -19,9 +19,52 @@
 
 namespace apsp {
 
+// Visits the 4-column groups of rows [0, n) whose row_ok(i) holds.  Each
+// wavefront takes runs of U 256-column chunks (64 lanes x 4 columns, one row
+// per chunk), so every lane has U independent 16-byte loads of D in flight
+// before it uses any; body(i, c0, ok, d) runs on every lane (ok false where
+// the lane has no group), so it may use cross-lane operations.
+template <int U, class RowOk, class Body>
+__device__ inline void stream_chunks(const DevGraph &g, int32_t n, RowOk row_ok, Body body) {
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int32_t Q = (n + 255) >> 8;
+    const int32_t total = n * Q;
+    for (int32_t base = wv * U; base < total; base += (BATCH_THREADS / 64) * U) {
+        uint4 d[U];
+        int32_t ri[U], rc[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t k = base + u;
+            const int32_t i = k / Q;
+            const int32_t c0 = (k - i * Q) * 256 + lane * 4;
+            ri[u] = i;
+            rc[u] = c0;
+            ok[u] = k < total && c0 < n && row_ok(i);
+            d[u] = make_uint4(INF, INF, INF, INF);
+            if (ok[u]) d[u] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)i * g.ld + c0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) body(ri[u], rc[u], ok[u], d[u]);
+    }
+}
+
+// stage[0..n) = a[0..n) and stage[P..P+n) = b[0..n) (b may be null), padded
+// with INF to a multiple of 4.
+__device__ inline void stage_rows(uint32_t *stage, int32_t P, int32_t n, const int32_t *a, const int32_t *b) {
+    const int32_t n4 = (n + 3) & ~3;
+    for (int32_t c = threadIdx.x; c < n4; c += BATCH_THREADS) {
+        stage[c] = c < n ? (uint32_t)a[c] : INF;
+        if (b) stage[P + c] = c < n ? (uint32_t)b[c] : INF;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // add node
 // ---------------------------------------------------------------------------
+constexpr int PREF = 8;  // index entries whose loads are issued together
+
 template <int U>
 __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
                           uint32_t *stage) {
@@ -61,7 +104,17 @@ __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchIt
         for (int32_t c = tid; c < n; c += BATCH_THREADS) {
             uint32_t acc = INF;
             if (g.id_of_slot[c] >= 0) {
-                for (int e = 0; e < lim; ++e) {
+                // the first PREF entries' loads are issued together; an entry
+                // never examined weighs at least the last one examined
+                uint32_t pv[PREF];
+#pragma unroll
+                for (int e = 0; e < PREF; ++e) {
+                    const int2 ent = e < lim ? ol[e] : make_int2(0, (int)INF);
+                    pv[e] = e < lim ? (uint32_t)ent.y + (uint32_t)g.D[(int64_t)ent.x * g.ld + c] : INF;
+                }
+#pragma unroll
+                for (int e = 0; e < PREF; ++e) acc = min(acc, pv[e]);
+                for (int e = PREF; e < lim; ++e) {
                     const int2 ent = ol[e];
                     if ((uint32_t)ent.y >= acc) break;
                     acc = min(acc, (uint32_t)ent.y + (uint32_t)g.D[(int64_t)ent.x * g.ld + c]);
@@ -81,7 +134,15 @@ __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchIt
             uint32_t best = INF;
             if (g.id_of_slot[r] >= 0) {
                 const int32_t *Dr = g.D + (int64_t)r * g.ld;
-                for (int e = 0; e < lim; ++e) {
+                uint32_t pv[PREF];
+#pragma unroll
+                for (int e = 0; e < PREF; ++e) {
+                    const int2 ent = e < lim ? pin[e] : make_int2(0, (int)INF);
+                    pv[e] = e < lim ? (uint32_t)ent.y + (uint32_t)Dr[ent.x] : INF;
+                }
+#pragma unroll
+                for (int e = 0; e < PREF; ++e) best = min(best, pv[e]);
+                for (int e = PREF; e < lim; ++e) {
                     const int2 ent = pin[e];
                     if ((uint32_t)ent.y >= best) break;
                     best = min(best, (uint32_t)ent.y + (uint32_t)Dr[ent.x]);
@@ -95,28 +156,23 @@ __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchIt
     __syncthreads();
     const int32_t *in = und ? bg.vout : bg.vin;
     const int32_t *out = bg.vout;
-    // Theorem theorem3 over all old pairs, (row, 4-column) cells spread over the block
-    const int nc4 = (n + 3) / 4;
-    const int64_t cells = (int64_t)n * nc4;
-#pragma unroll U
-    for (int64_t x = tid; x < cells; x += BATCH_THREADS) {
-        const int32_t i = (int32_t)(x / nc4);
-        const int32_t c0 = (int32_t)(x - (int64_t)i * nc4) * 4;
-        const uint32_t a = (uint32_t)in[i];
-        if (a >= INF) continue;
-        uint4 *dp = reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0);
-        uint4 d = *dp;
-        const uint32_t o[4] = {(uint32_t)out[c0], c0 + 1 < n ? (uint32_t)out[c0 + 1] : INF,
-                               c0 + 2 < n ? (uint32_t)out[c0 + 2] : INF, c0 + 3 < n ? (uint32_t)out[c0 + 3] : INF};
-        const uint4 t = make_uint4(a + o[0], a + o[1], a + o[2], a + o[3]);
-        if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
-            d.x = min(d.x, t.x);
-            d.y = min(d.y, t.y);
-            d.z = min(d.z, t.z);
-            d.w = min(d.w, t.w);
-            *dp = d;
-        }
-    }
+    // Theorem theorem3 over all old pairs; the new row `out` sits in LDS
+    stage_rows(stage, g.P, n, out, nullptr);
+    stream_chunks<U>(
+        g, n, [&](int32_t i) { return (uint32_t)in[i] < INF; },
+        [&](int32_t i, int32_t c0, bool ok, uint4 d) {
+            if (!ok) return;
+            const uint32_t a = (uint32_t)in[i];
+            const uint4 o = *reinterpret_cast<const uint4 *>(stage + c0);
+            const uint4 t = make_uint4(a + o.x, a + o.y, a + o.z, a + o.w);
+            if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
+                d.x = min(d.x, t.x);
+                d.y = min(d.y, t.y);
+                d.z = min(d.z, t.z);
+                d.w = min(d.w, t.w);
+                *reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0) = d;
+            }
+        });
     __syncthreads();
     // place row / column p
     const int64_t ld = g.ld;
@@ -140,8 +196,18 @@ __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchIt
     }
     __syncthreads();
     // p's out-edges are in-edges of every other node
-    for (int32_t y = tid >> 6; y < n; y += BATCH_THREADS / 64)
-        if (y != p && g.id_of_slot[y] >= 0) wave_list_insert(g, y, p, (uint32_t)wo[y]);
+    // (lanes screen 64 lists at a time: an edge at or above a list's bound
+    // is not listed)
+    for (int32_t y0 = (tid >> 6) * 64; y0 < n; y0 += BATCH_THREADS) {
+        const int32_t y = y0 + lane_id();
+        const bool cand = y < n && y != p && g.id_of_slot[y] >= 0 && (uint32_t)wo[y] < (uint32_t)g.nin_beta[y];
+        unsigned long long m = __ballot(cand);
+        while (m) {
+            const int b = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            wave_list_insert(g, y0 + b, p, (uint32_t)wo[y0 + b]);
+        }
+    }
     __syncthreads();
 }
 
@@ -152,52 +218,56 @@ __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchIt
 // one wavefront per flagged row runs the Bellman-Ford recompute in place.
 template <int U>
 __device__ void batch_mask_recompute(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa, uint32_t w_old,
-                                     int32_t *wlists) {
+                                     uint32_t *stage, int32_t *wlists) {
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int n = g.n_slots;
     const int nw = (n + 31) / 32;
     const int64_t nwp = (g.P + 31) / 32;
-    const int64_t cells = (int64_t)n * nw;
-#pragma unroll U
-    for (int64_t x = tid; x < cells; x += BATCH_THREADS) {
-        const int32_t i = (int32_t)(x / nw);
-        const int32_t w = (int32_t)(x - (int64_t)i * nw);
-        const RowTests rt = row_tests(g, fa, i, w_old);
-        if (!rt.t1 && !rt.t2) continue;
-        const uint32_t a1 = rt.t1 ? rt.a1 : 0x80000000u, a2 = rt.t2 ? rt.a2 : 0x80000000u;
-        const int32_t *Dr = g.D + (int64_t)i * g.ld + w * 32;
-        const int32_t *R1 = fa.row1 + w * 32;
-        const int32_t *R2 = fa.row2 ? fa.row2 + w * 32 : R1;
-        uint32_t word = 0;
+    // the pair test's row vectors in LDS; rows stream through in chunks and
+    // 8 lanes assemble each 32-column flag word with shuffles
+    stage_rows(stage, g.P, n, fa.row1, fa.row2);
+    const uint32_t *S1 = stage, *S2 = stage + g.P;
+    stream_chunks<U>(
+        g, n,
+        [&](int32_t i) {
+            const RowTests rt = row_tests(g, fa, i, w_old);
+            return rt.t1 || rt.t2;
+        },
+        [&](int32_t i, int32_t c0, bool ok, uint4 d) {
+            uint32_t bits = 0;
+            if (ok) {
+                const RowTests rt = row_tests(g, fa, i, w_old);
+                const uint4 v1 = *reinterpret_cast<const uint4 *>(S1 + c0);
+                const uint4 v2 = fa.row2 ? *reinterpret_cast<const uint4 *>(S2 + c0) : v1;
+                const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
+                const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w};
+                const uint32_t w2[4] = {v2.x, v2.y, v2.z, v2.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint4 d = *reinterpret_cast<const uint4 *>(Dr + 4 * q);
-            const uint4 v1 = *reinterpret_cast<const uint4 *>(R1 + 4 * q);
-            const uint4 v2 = *reinterpret_cast<const uint4 *>(R2 + 4 * q);
-            const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
-            const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w};
-            const uint32_t w2[4] = {v2.x, v2.y, v2.z, v2.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const bool f = dv[e] < INF && (a1 + w1[e] == dv[e] || a2 + w2[e] == dv[e]);
-                word |= (uint32_t)f << (4 * q + e);
+                for (int e = 0; e < 4; ++e) {
+                    const int32_t j = c0 + e;
+                    const bool f = j < n && j != i && !(fa.mode == FUSED_REMOVE && j == fa.k) && dv[e] < INF &&
+                                   ((rt.t1 && rt.a1 + w1[e] == dv[e]) || (rt.t2 && rt.a2 + w2[e] == dv[e]));
+                    bits |= (uint32_t)f << e;
+                }
             }
-        }
-        const int32_t j0 = w * 32;
-        if ((unsigned)(i - j0) < 32u) word &= ~(1u << (i - j0));
-        if (fa.mode == FUSED_REMOVE && (unsigned)(fa.k - j0) < 32u) word &= ~(1u << (fa.k - j0));
-        if (j0 + 32 > n) word &= (n - j0 >= 32) ? ~0u : ((1u << (n - j0)) - 1u);
-        bg.flag_bits[(int64_t)i * nwp + w] = word;
-        if (word) atomicOr(&bg.row_bits[i >> 5], 1u << (i & 31));
-    }
+            uint32_t word = bits << ((lane & 7) * 4);
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) word |= (uint32_t)__shfl_xor((int)word, o);
+            if (ok && (lane & 7) == 0) bg.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
+            if (__ballot(ok && word != 0) != 0 && lane == 0) atomicOr(&bg.row_bits[i >> 5], 1u << (i & 31));
+        });
     __syncthreads();
     int my_flagged = 0, my_rows = 0, my_fs = 0, my_sweeps = 0;
     int32_t *list = wlists + wv * 2 * ROW_CAP;
     int32_t *fsl = list + ROW_CAP;
     int32_t *glist = bg.scratch + (int64_t)wv * 2 * g.P;  // rows with more than ROW_CAP flags
     int32_t *gfsl = glist + g.P;
-    for (int32_t i = wv; i < n; i += BATCH_THREADS / 64) {
-        if (((bg.row_bits[i >> 5] >> (i & 31)) & 1u) == 0) continue;
+    for (int32_t i0 = wv * 64; i0 < n; i0 += BATCH_THREADS) {
+      const int32_t ii = i0 + lane;
+      unsigned long long rows = __ballot(ii < n && ((bg.row_bits[ii >> 5] >> (ii & 31)) & 1u));
+      while (rows) {
+        const int32_t i = i0 + __ffsll((long long)rows) - 1;
+        rows &= rows - 1;
         const uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
         int cnt = 0;
         for (int b = 0; b < nw; b += 64) {
@@ -243,6 +313,7 @@ __device__ void batch_mask_recompute(const DevGraph &g, const BatchGraph &bg, co
         my_sweeps = max(my_sweeps, sweeps);
         my_flagged += cnt;
         ++my_rows;
+      }
     }
     __syncthreads();
     for (int w = tid; w < (n + 31) / 32; w += BATCH_THREADS) bg.row_bits[w] = 0;
@@ -279,7 +350,33 @@ __device__ void batch_remove(const DevGraph &g, const BatchGraph &bg, const Batc
     fa.col1 = bg.colu;
     fa.row1 = bg.rowu;
     fa.row2 = nullptr;
-    batch_mask_recompute<U>(g, bg, fa, 0, wlists);
+    batch_mask_recompute<U>(g, bg, fa, 0, stage, wlists);
+    // drop k from every index list (lanes screen 64 lists at a time: k can
+    // be listed in y only if its edge is no heavier than y's last entry);
+    // k's own list empties
+    for (int32_t y0 = (tid >> 6) * 64; y0 < n; y0 += BATCH_THREADS) {
+        const int32_t y = y0 + lane_id();
+        bool cand = false;
+        if (y < n && y != k) {
+            const int c = g.nin_cnt[y];
+            const uint32_t wk = (uint32_t)g.A[(int64_t)k * g.ld + y];
+            cand = c > 0 && wk < INF && wk <= (uint32_t)g.nin[(int64_t)y * NIN_L + c - 1].y;
+        }
+        unsigned long long m = __ballot(cand);
+        while (m) {
+            const int b = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            wave_list_purge(g, y0 + b, k);
+        }
+    }
+    if (tid < 64) {
+        g.nin[(int64_t)k * NIN_L + tid] = make_int2(0, (int)INF);
+        if (tid == 0) {
+            g.nin_cnt[k] = 0;
+            g.nin_beta[k] = (int32_t)INF;
+        }
+    }
+    __syncthreads();
     // tombstone
     const int64_t ld = g.ld;
     for (int32_t s = tid; s < n; s += BATCH_THREADS) {
@@ -292,17 +389,7 @@ __device__ void batch_remove(const DevGraph &g, const BatchGraph &bg, const Batc
             g.AT[(int64_t)s * ld + k] = (int32_t)INF;
         }
     }
-    __syncthreads();
     if (tid == 0) g.id_of_slot[k] = -1;
-    // drop k from every index list; k's own list empties
-    for (int32_t y = tid >> 6; y < n; y += BATCH_THREADS / 64) {
-        if (y == k) {
-            g.nin[(int64_t)y * NIN_L + lane_id()] = make_int2(0, (int)INF);
-            if (lane_id() == 0) { g.nin_cnt[y] = 0; g.nin_beta[y] = (int32_t)INF; }
-        } else {
-            wave_list_purge(g, y, k);
-        }
-    }
     __syncthreads();
     // rebuild the lists that fell below half (rare)
     __shared__ int32_t s_cnt;
@@ -339,26 +426,36 @@ __device__ void batch_edge(const DevGraph &g, const BatchGraph &bg, const BatchI
         __syncthreads();
     }
     if (mode == EDGE_DECREASE) {
+        // relaxation through the new edge: D[i][j] vs D[i][u] + w + D[v][j]
+        // (and D[i][v] + w + D[u][j] when undirected), rows filtered first
         const bool und = g.undirected != 0;
         const uint32_t wn = (uint32_t)w;
-        const int nc4 = (n + 3) / 4;
-        const int64_t cells = (int64_t)n * nc4;
-#pragma unroll U
-        for (int64_t x = tid; x < cells; x += BATCH_THREADS) {
-            const int32_t i = (int32_t)(x / nc4);
-            const int32_t c0 = (int32_t)(x - (int64_t)i * nc4) * 4;
-            const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
-            const uint32_t a1 = du + wn, a2 = dv + wn;
-            const bool t1 = a1 < dv, t2 = und && a2 < du;
-            if (!t1 && !t2) continue;
-            const uint32_t x1 = t1 ? a1 : INF, x2 = t2 ? a2 : INF;
-            int32_t *Dr = g.D + (int64_t)i * g.ld;
-            for (int e = 0; e < 4 && c0 + e < n; ++e) {
-                const int32_t j = c0 + e;
-                const uint32_t t = min(x1 + (uint32_t)bg.rowv[j], und ? x2 + (uint32_t)bg.rowu[j] : INF);
-                if (t < (uint32_t)Dr[j]) Dr[j] = (int32_t)t;
-            }
-        }
+        stage_rows(stage, g.P, n, bg.rowv, und ? bg.rowu : nullptr);
+        const uint32_t *SV = stage, *SU = stage + g.P;
+        stream_chunks<U>(
+            g, n,
+            [&](int32_t i) {
+                const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
+                return du + wn < dv || (und && dv + wn < du);
+            },
+            [&](int32_t i, int32_t c0, bool ok, uint4 d) {
+                if (!ok) return;
+                const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
+                const uint32_t x1 = du + wn < dv ? du + wn : INF;
+                const uint32_t x2 = und && dv + wn < du ? dv + wn : INF;
+                const uint4 rv = *reinterpret_cast<const uint4 *>(SV + c0);
+                uint4 ru = make_uint4(INF, INF, INF, INF);
+                if (und) ru = *reinterpret_cast<const uint4 *>(SU + c0);
+                const uint4 t = make_uint4(min(x1 + rv.x, x2 + ru.x), min(x1 + rv.y, x2 + ru.y),
+                                           min(x1 + rv.z, x2 + ru.z), min(x1 + rv.w, x2 + ru.w));
+                if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
+                    d.x = min(d.x, t.x);
+                    d.y = min(d.y, t.y);
+                    d.z = min(d.z, t.z);
+                    d.w = min(d.w, t.w);
+                    *reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0) = d;
+                }
+            });
         __syncthreads();
     } else if (mode == EDGE_INCREASE) {
         FusedArgs fa{};
@@ -368,7 +465,7 @@ __device__ void batch_edge(const DevGraph &g, const BatchGraph &bg, const BatchI
         fa.col2 = bg.colv;
         fa.row1 = bg.rowv;
         fa.row2 = g.undirected ? bg.rowu : nullptr;
-        batch_mask_recompute<U>(g, bg, fa, w_old, wlists);
+        batch_mask_recompute<U>(g, bg, fa, w_old, stage, wlists);
     }
     batch_rebuild_if_short(g, sv, ssh, stage);
     if (g.undirected) batch_rebuild_if_short(g, su, ssh, stage);
@@ -381,7 +478,7 @@ __device__ void batch_edge(const DevGraph &g, const BatchGraph &bg, const BatchI
 template <int U>
 __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch(BatchHeader *hdr, const BatchGraph *graphs,
                                                          const int32_t *order, const BatchItem *items) {
-    extern __shared__ uint32_t stage[];  // select staging (P words), then 4 wave lists of 2 ROW_CAP
+    extern __shared__ uint32_t stage[];  // 2 P words of row vectors / select staging, then 4 wave lists of 2 ROW_CAP
     __shared__ SelectShared ssh;
     __shared__ int32_t s_next;
     const int32_t num_graphs = hdr->num_graphs;
@@ -392,7 +489,7 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch(BatchHeader *hdr, co
         const int32_t idx = s_next;
         if (idx >= num_graphs) break;
         const BatchGraph &bg = graphs[order[idx]];
-        int32_t *wlists = reinterpret_cast<int32_t *>(stage) + bg.g.P;
+        int32_t *wlists = reinterpret_cast<int32_t *>(stage) + 2 * bg.g.P;
         if (threadIdx.x == 0) hdr->times[2 * bg.index] = wall_clock64();
         for (int32_t t = bg.item_begin; t < bg.item_end; ++t) {
             const BatchItem it = items[t];
@@ -418,15 +515,15 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch(BatchHeader *hdr, co
     }
 }
 
-size_t batch_lds_bytes(int32_t P_max) { return ((size_t)P_max + 4 * 2 * ROW_CAP) * sizeof(uint32_t); }
+size_t batch_lds_bytes(int32_t P_max) { return (2 * (size_t)P_max + 4 * 2 * ROW_CAP) * sizeof(uint32_t); }
 
 hipError_t configure_batch() {
     static hipError_t status = hipErrorNotReady;
     if (status != hipErrorNotReady) return status;
     const int lds = (int)batch_lds_bytes(BATCH_MAX_CAPACITY);
-    status = hipFuncSetAttribute((const void *)k_batch<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    status = hipFuncSetAttribute((const void *)k_batch<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (status == hipSuccess)
-        status = hipFuncSetAttribute((const void *)k_batch<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        status = hipFuncSetAttribute((const void *)k_batch<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipGetLastError();
     return status;
 }
@@ -436,8 +533,8 @@ hipError_t launch_batch(BatchHeader *hdr, const BatchGraph *graphs, const int32_
     if (P_max > BATCH_MAX_CAPACITY || grid < 1) return hipErrorInvalidValue;
     launch_fill(&hdr->counter, 1, 0, s);
     const size_t lds = batch_lds_bytes(P_max);
-    if (variant == 0) k_batch<1><<<grid, BATCH_THREADS, lds, s>>>(hdr, graphs, order, items);
-    else k_batch<2><<<grid, BATCH_THREADS, lds, s>>>(hdr, graphs, order, items);
+    if (variant == 0) k_batch<4><<<grid, BATCH_THREADS, lds, s>>>(hdr, graphs, order, items);
+    else k_batch<8><<<grid, BATCH_THREADS, lds, s>>>(hdr, graphs, order, items);
     return hipGetLastError();
 }
 
