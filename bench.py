@@ -46,10 +46,13 @@ def parse():
                     help="update kinds of a step (profiling runs of one kind); 'all' is the benchmark mix")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration)")
-    ap.add_argument("--workload", default="updates", choices=["updates", "batched"],
+    ap.add_argument("--workload", default="updates", choices=["updates", "batched", "serving"],
                     help="updates: the n=16384 update stream (default); batched: 512 graphs with 8 queued "
                          "updates each, one persistent launch vs one call per update")
-    ap.add_argument("--graphs", type=int, default=512, help="batched: number of graphs")
+    ap.add_argument("--graphs", type=int, default=None, help="batched / serving: number of graphs (512 / 64)")
+    ap.add_argument("--rates", default="1000,3000,10000,30000,100000",
+                    help="serving: Poisson arrival rates (requests/s) to sweep")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
     return ap.parse_args()
 
 
@@ -57,15 +60,20 @@ def parse():
 # algorithmic bytes per launch of the sweep kernels
 # ---------------------------------------------------------------------------
 # add_relax reads every live row of D once (the new pair distances need every
-# old entry); mask_detect reads every row that can hold a flag once (for a
-# removal every live row but k; an increase reads only the rows of R, counted
-# as 0 here).  Writes are the changed / recomputed entries only and are not
-# counted (a small, data-dependent fraction).
+# old entry): 4 n^2 bytes per added node, n the live count before the add.
+# mask_detect (a removal; an edge increase is timed separately as
+# mask_detect_inc) reads every live row but k once: 4 (n - 1) n bytes.  Writes
+# (changed entries, the flag bitmap) are not counted.
+
+
+KERNEL_SOURCES = ("update.hip", "device_common.h")   # where add_relax and mask_detect live
 
 
 def source_hash():
+    """Hash of the sweep kernels' sources: counter figures taken on other
+    sources are not reported."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2412_15122_amd", "csrc"))):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2412_15122_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -147,7 +155,7 @@ def bench_batched(args):
     from paper_2412_15122_amd import autotune
     torch.cuda.set_device(0)
     t = time.perf_counter()
-    wls = W.config4(graphs=args.graphs)
+    wls = W.config4(graphs=args.graphs or 512)
     log(f"[bench] {len(wls)} graphs generated in {time.perf_counter() - t:.1f}s")
     base = [Graph(w.adj, undirected=False, capacity=w.adj.shape[0] + 8) for w in wls]
     torch.cuda.synchronize()
@@ -261,6 +269,68 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(args):
+    """64 resident directed complete graphs (n uniform in [1024, 8192]),
+    Poisson requests (45% increase, 45% decrease, 2.5% add, 2.5% remove, 5%
+    query) swept over arrival rates: the continuous-batching server against
+    the plain path (one library call per request, no batching).  Graphs are
+    cold-started before each timed run; every request's latency is its
+    completion time (event observed) minus its arrival time."""
+    import torch
+    from paper_2412_15122_amd import workloads as W
+    from paper_2412_15122_amd import serve
+    from paper_2412_15122_amd.apsp import Graph
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    adjs = W.config5_graphs(graphs=args.graphs or 64)
+    ns = [a.shape[0] for a in adjs]
+    log(f"[bench] {len(adjs)} graphs generated in {time.perf_counter() - t:.1f}s; n {min(ns)}..{max(ns)}")
+    rates = [float(x) for x in args.rates.split(",")]
+    rows = []
+    for rate in rates:
+        gen = W.Config5Requests(adjs)
+        reqs = serve.requests_from_stream(gen, rate, args.requests)
+        srv = serve.Server(adjs, streams=4)
+        srv.preload()
+        s = srv.run(reqs)
+        s["stats"] = dict(srv.stats)
+        srv.close()
+        del srv
+        torch.cuda.empty_cache()
+        gs = [Graph(a, capacity=a.shape[0] + 64) for a in adjs]
+        torch.cuda.synchronize()
+        p = serve.serve_plain(gs, reqs)
+        for g in gs:
+            g.close()
+        del gs
+        torch.cuda.empty_cache()
+        row = {"rate": rate,
+               "served": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()},
+               "plain": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in p.items()}}
+        rows.append(row)
+        log(f"[bench] rate {rate:.0f}/s: served {s['updates_per_s']:.0f} upd/s p50 {s['p50_ms']:.3f} ms "
+            f"p99 {s['p99_ms']:.3f} ms {s['stats']} | plain {p['updates_per_s']:.0f} upd/s p50 {p['p50_ms']:.3f} "
+            f"p99 {p['p99_ms']:.3f} ms")
+    top = rows[-1]
+    out = {
+        "metric": "served warm-start APSP updates/s (64 resident graphs, 1 GPU)",
+        "value": round(top["served"]["updates_per_s"], 1),
+        "unit": "updates/s",
+        "n_gpus": 1, "steps": len(rates), "warmup": 0,
+        "ms_per_step": round(top["served"]["wall_s"] * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": (f"{len(adjs)} directed complete graphs, n uniform in [1024, 8192], weights U[1,10000]; "
+                                f"Poisson requests, {args.requests} per rate: 45% increase, 45% decrease, 2.5% add, "
+                                f"2.5% remove, 5% single-pair query"),
+                   "graphs": len(adjs), "parallelism": "none (1 GPU)", "rates": rates},
+        "latency_ms": {"p50": top["served"]["p50_ms"], "p99": top["served"]["p99_ms"]},
+        "plain_path": {"updates_per_s": round(top["plain"]["updates_per_s"], 1), "p50_ms": top["plain"]["p50_ms"],
+                       "p99_ms": top["plain"]["p99_ms"]},
+        "sweep": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -269,6 +339,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     import torch
     from paper_2412_15122_amd import workloads as W
     from paper_2412_15122_amd.apsp import Graph, kernel_names
@@ -428,8 +500,6 @@ def main():
             removes_bytes += 4 * (live - 1) * live
             launches["mask_detect"] += 1
             live -= 1
-        elif k == W.INCREASE:
-            launches["mask_detect"] += 1
     roofline = None
     if prof_kernel and "timed" in prof_totals and prof_totals["timed"][1] > 0:
         c, ms = prof_totals["timed"]

@@ -239,6 +239,13 @@ const char *apsp_kernel_name(int32_t kernel);
 apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes, void *hip_stream,
                              apsp_graph **out);
 
+/* The caller has copied g's whole buffer (apsp_required_bytes bytes, e.g.
+ * out to host memory and back) into dev_buf; from now on g uses dev_buf and
+ * the old buffer may be freed.  Nothing is enqueued: the caller orders the
+ * copy before g's next call (e.g. on g's stream).  Lets a server move idle
+ * graphs out of HBM and back without a cold start. */
+apsp_status apsp_graph_relocate(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes);
+
 /* ---- batched updates --------------------------------------------------- */
 
 /* Many graphs and their queued updates run in one persistent launch: every

@@ -92,6 +92,48 @@ class Graph:
                 "apsp_graph_clone")
         return Graph._from_handle(self._lib, h, buf, ptr, self._nbytes, self.capacity, self.kind, stream)
 
+    @property
+    def nbytes(self) -> int:
+        """Device bytes the graph holds (apsp_required_bytes)."""
+        return self._nbytes
+
+    @property
+    def resident(self) -> bool:
+        return self._buf is not None and self._buf.is_cuda
+
+    def swap_out(self) -> None:
+        """Copy the graph's device buffer to host memory and release the HBM
+        (the handle keeps the ids and bookkeeping)."""
+        torch = _torch()
+        if not self.resident:
+            return
+        off = self._ptr - self._buf.data_ptr()
+        host = torch.empty(self._nbytes, dtype=torch.uint8, pin_memory=True)
+        with torch.cuda.stream(self._stream):
+            host.copy_(self._buf[off:off + self._nbytes], non_blocking=True)
+        self._stream.synchronize()
+        self._buf = host
+        self._ptr = None
+
+    def swap_in(self) -> None:
+        """Bring a swapped-out graph back into HBM (apsp_graph_relocate)."""
+        torch = _torch()
+        if self.resident:
+            return
+        buf = torch.empty(self._nbytes + 256, dtype=torch.uint8, device="cuda")
+        ptr = (buf.data_ptr() + 255) & ~255
+        off = ptr - buf.data_ptr()
+        with torch.cuda.stream(self._stream):
+            buf[off:off + self._nbytes].copy_(self._buf, non_blocking=True)
+        N.check(self._lib.apsp_graph_relocate(self._h, ptr, self._nbytes), "apsp_graph_relocate")
+        self._stream.synchronize()
+        self._buf = buf
+        self._ptr = ptr
+
+    def set_stream(self, stream) -> None:
+        N.check(self._lib.apsp_set_stream(self._h, stream.cuda_stream), "apsp_set_stream")
+        self._stream = stream
+
     # -- lifetime ------------------------------------------------------------
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -167,7 +167,7 @@ const char *apsp_kernel_name(int32_t k) {
     static const char *names[KID_COUNT] = {
         "fw_pivot", "fw_panel", "fw_tiles", "nin_build", "nin_update", "add_out", "add_in", "add_relax",
         "add_place", "gather", "mask_recompute", "tombstone", "edge_begin", "dec_relax", "query", "misc",
-        "mask_detect"};
+        "mask_detect", "mask_detect_inc"};
     if (k < 0 || k >= KID_COUNT) return "";
     return names[k];
 }
@@ -301,6 +301,39 @@ apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes,
     c->last_n_before = g->last_n_before;
     c->last_fallback = g->last_fallback;
     *out = c;
+    return APSP_OK;
+}
+
+apsp_status apsp_graph_relocate(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_graph_relocate: NULL graph");
+    if (!dev_buf || ((uintptr_t)dev_buf & 255) != 0)
+        return fail(APSP_E_INVALID, "apsp_graph_relocate: dev_buf NULL or not 256-byte aligned");
+    const Layout L = make_layout(g->cap, g->kind);
+    if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, "apsp_graph_relocate: dev_buf smaller than apsp_required_bytes");
+    apsp_graph *t = nullptr;
+    apsp_status st = make_handle(g->cap, g->kind, dev_buf, g->stream, &t);
+    if (st) return st;
+    const int64_t rc = (char *)g->rank_cur - g->base, ro = (char *)g->rank_other - g->base;
+    const int32_t n_slots = g->dg.n_slots, lim = g->dg.lim;
+    g->base = t->base;
+    g->dg = t->dg;
+    g->dg.n_slots = n_slots;
+    g->dg.lim = lim;
+    for (int v = 0; v < NVEC; ++v) g->vec[v] = t->vec[v];
+    g->plist = t->plist;
+    g->plist_cnt = t->plist_cnt;
+    g->plist_beta = t->plist_beta;
+    g->rank_cur = (int32_t *)(g->base + rc);
+    g->rank_other = (int32_t *)(g->base + ro);
+    g->qbuf = t->qbuf;
+    g->qscratch = t->qscratch;
+    g->fscratch = t->fscratch;
+    g->nin_queue = t->nin_queue;
+    g->heavy_rows = t->heavy_rows;
+    g->heavy_epoch = t->heavy_epoch;
+    g->flag_bits = t->flag_bits;
+    g->row_bits = t->row_bits;
+    apsp_graph_destroy(t);
     return APSP_OK;
 }
 
@@ -459,7 +492,7 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     fa.col2 = colv(g);
     fa.row1 = rowv(g);
     fa.row2 = rowu(g);
-    g->prof.begin(KID_MASK);
+    g->prof.begin(KID_MASK_INC);
     launch_mask_detect(d, fa, s);
     g->prof.end();
     int32_t fallback = 0;

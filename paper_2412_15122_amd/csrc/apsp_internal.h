@@ -153,7 +153,7 @@ hipError_t configure_kernels();  // raise dynamic-LDS limits once per process
 enum KernelId : int32_t {
     KID_FW_PIVOT = 0, KID_FW_PANEL, KID_FW_TILE, KID_NIN_BUILD, KID_NIN_UPDATE,
     KID_ADD_OUT, KID_ADD_IN, KID_ADD_RELAX, KID_ADD_PLACE, KID_GATHER, KID_FUSED,
-    KID_TOMBSTONE, KID_EDGE_BEGIN, KID_DEC_RELAX, KID_QUERY, KID_MISC, KID_MASK, KID_COUNT
+    KID_TOMBSTONE, KID_EDGE_BEGIN, KID_DEC_RELAX, KID_QUERY, KID_MISC, KID_MASK, KID_MASK_INC, KID_COUNT
 };
 
 // Event-based timing hooks (implemented in the host API unit).

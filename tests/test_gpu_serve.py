@@ -1,0 +1,129 @@
+"""GPU parity of the serving loop (continuous batching over resident graphs).
+
+A Poisson request stream over several graphs (edge increases and decreases,
+node additions and removals, single-pair queries) is served under an HBM
+budget that holds only a few graphs at once, so requests queue for
+admission and idle graphs move out to host memory and back.  Each graph's
+final matrix, ids and adjacency, each query answer and each new id must
+equal what the same graph gets when its requests run alone, one library
+call each, in arrival order; a few final states are also checked against
+the oracle's cold Floyd-Warshall.  The tolerance is zero.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2412_15122_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+HEADROOM = 64
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def graphs_and_requests(sizes, rate, count, seed):
+    from paper_2412_15122_amd import serve
+    adjs = [W.random_graph(n, 1, 10000, seed=seed * 100 + i) for i, n in enumerate(sizes)]
+    gen = W.Config5Requests(adjs, seed=seed)
+    reqs = serve.requests_from_stream(gen, rate, count)
+    return adjs, gen, reqs
+
+
+def replay_alone(adjs, reqs):
+    """Each graph on its own, its requests in arrival order through the
+    single calls."""
+    from paper_2412_15122_amd.apsp import Graph
+    gs = [Graph(a, capacity=a.shape[0] + HEADROOM) for a in adjs]
+    results = {}
+    for r in sorted(reqs, key=lambda r: r.arrival):
+        g = gs[r.graph]
+        if r.kind == "add":
+            results[r.rid] = g.add_node(r.args[0], r.args[1])
+        elif r.kind == "remove":
+            g.remove_node(r.args[0])
+        elif r.kind == "query":
+            results[r.rid] = g.query(r.args[0], r.args[1])
+        else:
+            g.update_edge(*r.args)
+    return gs, results
+
+
+def check_against_alone(srv, adjs, reqs):
+    import torch
+    alone, results = replay_alone(adjs, reqs)
+    for i in range(len(adjs)):
+        g = srv.graph(i)
+        if g is None:       # never admitted: no request addressed it
+            assert not any(r.graph == i for r in reqs)
+            continue
+        assert g.ids() == alone[i].ids(), i
+        assert torch.equal(g.matrix_device("D"), alone[i].matrix_device("D")), i
+        assert torch.equal(g.matrix_device("A"), alone[i].matrix_device("A")), i
+        g.sync()
+    for r in reqs:
+        if r.kind in ("add", "query"):
+            assert r.result == results[r.rid], (r.rid, r.kind)
+    for g in alone:
+        g.close()
+
+
+def test_mix_equals_alone_under_tiny_budget():
+    from paper_2412_15122_amd import serve
+    sizes = [60, 200, 33, 150, 90, 250, 120, 75]
+    adjs, gen, reqs = graphs_and_requests(sizes, rate=20000.0, count=700, seed=51)
+    from paper_2412_15122_amd import _native as N
+    nbytes = sorted(int(N.load().apsp_required_bytes(a.shape[0] + HEADROOM, 0)) for a in adjs)
+    budget = nbytes[-1] + nbytes[-2] + nbytes[-3]        # about three graphs at a time
+    srv = serve.Server(adjs, budget_bytes=budget, streams=3)
+    summary = srv.run(reqs)
+    log("summary", summary, dict(srv.stats))
+    assert all(r.done is not None for r in reqs)
+    assert srv.stats["evictions"] > 0 and srv.stats["swap_ins"] > 0
+    assert srv.stats["batches"] > 0 and srv.stats["heavy"] > 0
+    # per-graph FIFO: completion times never decrease along a graph's arrivals
+    for i in range(len(adjs)):
+        done = [r.done for r in sorted(reqs, key=lambda r: r.arrival) if r.graph == i]
+        assert all(a <= b for a, b in zip(done, done[1:])), i
+    check_against_alone(srv, adjs, reqs)
+    # the oracle on some final states (the generator's bookkeeping holds them)
+    for i in (0, 2, 4):
+        st = gen.states[i]
+        A = st.dense()
+        assert srv.graph(i).ids() == st.live
+        assert np.array_equal(srv.graph(i).matrix(), O.fw(A, threads=THREADS)), i
+    srv.close()
+
+
+def test_mix_equals_alone_with_everything_resident_and_slow_arrivals():
+    from paper_2412_15122_amd import serve
+    sizes = [300, 140, 64, 500]
+    adjs, gen, reqs = graphs_and_requests(sizes, rate=3000.0, count=300, seed=52)
+    srv = serve.Server(adjs, streams=4)
+    summary = srv.run(reqs)
+    log("summary", summary, dict(srv.stats))
+    assert srv.stats["evictions"] == 0
+    check_against_alone(srv, adjs, reqs)
+    srv.close()
+
+
+def test_plain_server_matches_too():
+    from paper_2412_15122_amd import serve
+    from paper_2412_15122_amd.apsp import Graph
+    import torch
+    sizes = [80, 130]
+    adjs, gen, reqs = graphs_and_requests(sizes, rate=5000.0, count=120, seed=53)
+    gs = [Graph(a, capacity=a.shape[0] + HEADROOM) for a in adjs]
+    summary = serve.serve_plain(gs, reqs)
+    log("plain", summary)
+    alone, results = replay_alone(adjs, reqs)
+    for i in range(2):
+        assert torch.equal(gs[i].matrix_device("D"), alone[i].matrix_device("D"))
+    for r in reqs:
+        if r.kind in ("add", "query"):
+            assert r.result == results[r.rid]
