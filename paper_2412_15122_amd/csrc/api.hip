@@ -129,6 +129,7 @@ apsp_status make_handle(int32_t capacity, int32_t kind, void *dev_buf, hipStream
     g->heavy_epoch = (int32_t *)(b + L.heavy_epoch);
     g->flag_bits = (uint32_t *)(b + L.flag_bits);
     g->row_bits = (uint32_t *)(b + L.row_bits);
+    g->partials = (int32_t *)(b + L.partials);
     g->prof_impl.stream = g->stream;
     g->prof.impl = &g->prof_impl;
 
@@ -145,6 +146,7 @@ FusedArgs fused_args(apsp_graph *g, int32_t mode) {
     fa.heavy_epoch = g->heavy_epoch;
     fa.flag_bits = g->flag_bits;
     fa.row_bits = g->row_bits;
+    fa.partials = g->partials;
     fa.epoch = ++g->epoch;
     return fa;
 }
@@ -333,6 +335,7 @@ apsp_status apsp_graph_relocate(apsp_graph *g, void *dev_buf, size_t dev_buf_byt
     g->heavy_epoch = t->heavy_epoch;
     g->flag_bits = t->flag_bits;
     g->row_bits = t->row_bits;
+    g->partials = t->partials;
     apsp_graph_destroy(t);
     return APSP_OK;
 }

@@ -25,6 +25,7 @@ constexpr int NIN_L = 64;        // light in-edge index entries per node
 constexpr int FUSED_GRID = 512;  // resident work-groups of the mask+recompute kernel
 constexpr int FUSED_THREADS = 256;
 constexpr int ROW_CAP = 64;      // flagged columns listed per row (more: a "heavy" row)
+constexpr int RECOMPUTE_BLOCKS = 2048;  // work-groups of the per-row recompute (4 waves each)
 
 enum EdgeMode : int32_t { EDGE_NOOP = 0, EDGE_DECREASE = 1, EDGE_INCREASE = 2 };
 enum FusedMode : int32_t { FUSED_REMOVE = 0, FUSED_INCREASE = 1 };
@@ -120,6 +121,7 @@ struct FusedArgs {
     int32_t *heavy_epoch; // [P] heavy_epoch[i] == epoch marks row i heavy
     uint32_t *flag_bits;  // [P][P/32] flag bitmap of the tested rows
     uint32_t *row_bits;   // [P/32] rows holding a flag; zero between updates
+    int32_t *partials;    // [RECOMPUTE_BLOCKS][4] per-work-group statistics of the recompute
     int32_t epoch;        // distinct for every mask pass
 };
 void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, int32_t *colb,

@@ -481,11 +481,10 @@ size_t fused_lds_bytes(int32_t P) {
 //     Bellman-Ford over the light in-edge index.  Rows with more than ROW_CAP
 //     flags ("heavy") are left untouched and queued for pass B.
 constexpr int DETECT_ROWS = 8;
-constexpr int RECOMPUTE_BLOCKS = 2048;  // 4 waves each
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
-    __shared__ uint32_t red[8];
+    __shared__ uint32_t s_rows;
     const int n = g.n_slots;
     uint32_t w_old = 0;
     if (MODE == FUSED_INCREASE) {
@@ -493,6 +492,7 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
         w_old = (uint32_t)g.ctl->w_old;
     }
     const int lane = lane_id();
+    if (threadIdx.x == 0) s_rows = 0;
     const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
     const int32_t r0 = blockIdx.y * DETECT_ROWS;
     const int64_t nwp = (g.P + 31) / 32;
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
     const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w};
     const uint32_t w2[4] = {v2.x, v2.y, v2.z, v2.w};
     const int kx = MODE == FUSED_REMOVE ? fa.k : -1;
-    int found = 0;
+    uint32_t row_mask = 0;  // rows of this tile holding a flag (wave-uniform)
     uint4 d[DETECT_ROWS];
     uint32_t a1[DETECT_ROWS], a2[DETECT_ROWS];
     bool tested[DETECT_ROWS];
@@ -536,16 +536,18 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
             f = f && dv[e] < INF && j != i && j != kx;
             bits |= (uint32_t)f << e;
         }
-        found += __popc(bits);
         uint32_t word = bits << ((lane & 7) * 4);
         word |= (uint32_t)__shfl_xor((int)word, 1);
         word |= (uint32_t)__shfl_xor((int)word, 2);
         word |= (uint32_t)__shfl_xor((int)word, 4);
         if ((lane & 7) == 0 && c0 < n) fa.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
-        if (__ballot(bits != 0) != 0 && lane == 0) atomicOr(&fa.row_bits[i >> 5], 1u << (i & 31));
+        if (__ballot(bits != 0) != 0) row_mask |= 1u << r;
     }
-    found = block_sum256(found, red);
-    if (threadIdx.x == 0 && found) atomicAdd(&g.ctl->flagged, (unsigned long long)found);
+    // one row-mark update per tile: its 8 rows share a word of row_bits
+    __syncthreads();
+    if (lane == 0 && row_mask) atomicOr(&s_rows, row_mask);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_rows) atomicOr(&fa.row_bits[r0 >> 5], s_rows << (r0 & 31));
 }
 
 // Phi of the pending mask (Algorithm 5's cost needs it before the recompute).
@@ -561,19 +563,18 @@ __global__ __launch_bounds__(256) void k_count_flag_rows(DevGraph g, FusedArgs f
 __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa, int32_t reset_only) {
     __shared__ int32_t lists[4][ROW_CAP];
     __shared__ int32_t fsls[4][ROW_CAP];
+    __shared__ int32_t stat[4][4];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     int32_t *list = lists[wv];
     int32_t *fsl = fsls[wv];
-    if (fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE) return;
     const int n = g.n_slots;
     const int nw = (n + 31) / 32;
     const int64_t nwp = (g.P + 31) / 32;
-    int my_rows = 0, my_fs = 0, my_sweeps = 0;
-    for (int32_t i = blockIdx.x * 4 + wv; i < n; i += gridDim.x * 4) {
+    int my_rows = 0, my_fs = 0, my_sweeps = 0, my_flagged = 0;
+    const bool active = !(fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE);
+    for (int32_t i = blockIdx.x * 4 + wv; active && i < n; i += gridDim.x * 4) {
         if (((fa.row_bits[i >> 5] >> (i & 31)) & 1u) == 0) continue;
         ++my_rows;
-        if (lane == 0) atomicAnd(&fa.row_bits[i >> 5], ~(1u << (i & 31)));
-        if (reset_only) continue;
         // flagged columns of row i -> list (at most ROW_CAP kept)
         const uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
         int cnt = 0;
@@ -588,7 +589,7 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
                 if (lane >= o) incl += t;
             }
             int pos = cnt + incl - c;
-            while (bits) {
+            while (bits && !reset_only) {
                 const int bt = __ffs(bits) - 1;
                 bits &= bits - 1;
                 if (pos < ROW_CAP) list[pos] = w * 32 + bt;
@@ -596,6 +597,8 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
             }
             cnt += __shfl(incl, 63);
         }
+        my_flagged += cnt;
+        if (reset_only) continue;
         if (cnt > ROW_CAP) {
             if (lane == 0) {
                 fa.heavy_epoch[i] = fa.epoch;
@@ -612,9 +615,49 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
         wave_bellman_ford(g, Drow, list, cnt, fsl, sweeps, my_fs);
         my_sweeps = max(my_sweeps, sweeps);
     }
-    if (lane == 0 && my_rows) atomicAdd(&g.ctl->rows, my_rows);
-    if (lane == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
-    if (lane == 0 && my_sweeps) atomicMax(&g.ctl->sweeps, my_sweeps);
+    // statistics: one partial per work-group, summed by k_mask_finish
+    if (lane == 0) {
+        stat[wv][0] = my_rows;
+        stat[wv][1] = my_flagged;
+        stat[wv][2] = my_fs;
+        stat[wv][3] = my_sweeps;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        int v = q == 3 ? max(max(stat[0][q], stat[1][q]), max(stat[2][q], stat[3][q]))
+                       : stat[0][q] + stat[1][q] + stat[2][q] + stat[3][q];
+        fa.partials[blockIdx.x * 4 + q] = v;
+    }
+}
+
+// After the recompute: sum the work-groups' statistics into the control
+// block and clear the row marks for the next update.
+__global__ __launch_bounds__(256) void k_mask_finish(DevGraph g, FusedArgs fa, int32_t blocks) {
+    __shared__ uint32_t red[8];
+    if (fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE) return;
+    int rows = 0, fs = 0, flagged = 0;
+    uint32_t sw = 0;
+    for (int b = threadIdx.x; b < blocks; b += 256) {
+        rows += fa.partials[b * 4 + 0];
+        flagged += fa.partials[b * 4 + 1];
+        fs += fa.partials[b * 4 + 2];
+        sw = max(sw, (uint32_t)fa.partials[b * 4 + 3]);
+    }
+    for (int w = threadIdx.x; w < (g.n_slots + 31) / 32; w += 256) fa.row_bits[w] = 0;
+    rows = block_sum256(rows, red);
+    flagged = block_sum256(flagged, red);
+    fs = block_sum256(fs, red);
+    sw = wave_max(sw);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = sw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        g.ctl->rows += rows;
+        g.ctl->flagged += (unsigned long long)flagged;
+        g.ctl->full_scans += fs;
+        g.ctl->sweeps = max(g.ctl->sweeps, (int32_t)max(max(red[0], red[1]), max(red[2], red[3])));
+    }
 }
 
 // Pass B: the heavy rows, one block each with the row in LDS.
@@ -671,8 +714,10 @@ void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t 
 
 void launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_recompute_rows<<<RECOMPUTE_BLOCKS, 256, 0, s>>>(g, fa, reset_only);
+    const int blocks = std::min(RECOMPUTE_BLOCKS, (g.n_slots + 3) / 4);
+    k_recompute_rows<<<blocks, 256, 0, s>>>(g, fa, reset_only);
     if (!reset_only) k_fused_heavy<<<FUSED_GRID, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
+    k_mask_finish<<<1, 256, 0, s>>>(g, fa, blocks);
 }
 
 static_assert(APSP_MAX_CAPACITY % TILE == 0, "capacity limit must be a tile multiple");
