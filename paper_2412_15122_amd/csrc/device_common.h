@@ -65,27 +65,76 @@ __device__ inline int block_exscan256(int v, uint32_t *red, int *total) {
     return base + incl - v;
 }
 
+// Block-wide reductions for NT threads (a multiple of 64); `red` holds at
+// least NT / 64 words of LDS.
+template <int NT>
+__device__ inline uint32_t block_min(uint32_t v, uint32_t *red) {
+    v = wave_min(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t r = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) r = min(r, red[w]);
+    return r;
+}
+
+template <int NT>
+__device__ inline int block_sum(int v, uint32_t *red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = (uint32_t)v;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) r += (int)red[w];
+    return r;
+}
+
+template <int NT>
+__device__ inline int block_exscan(int v, uint32_t *red, int *total) {
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    __syncthreads();
+    if (lane == 63) red[wid] = (uint32_t)incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        base += w < wid ? (int)red[w] : 0;
+        tot += (int)red[w];
+    }
+    *total = tot;
+    return base + incl - v;
+}
+
 struct SelectShared {
     uint32_t hist[256];
-    uint32_t red[16];
+    uint32_t red[32];
     int bin, kk;
     unsigned long long keys[NIN_L];
 };
 
 // Select the NIN_L smallest entries of vals[0..n) other than index `excl`
-// and other than INF (absent edges), ordered by (w, x).  One 256-thread
-// block; `stage` is LDS for n words (the values are read from memory once).
+// and other than INF (absent edges), ordered by (w, x).  One block of NT
+// threads; `stage` is LDS for n words (the values are read from memory once).
+template <int NT = 256>
 __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n, int32_t excl, int2 *list,
                              int32_t *cnt_out, int32_t *beta_out, SelectShared &sh, uint32_t *stage) {
     const int tid = threadIdx.x;
     int valid = 0;
-    for (int32_t x = tid; x < n; x += 256) {
+    for (int32_t x = tid; x < n; x += NT) {
         uint32_t v = (uint32_t)vals[x];
         if (x == excl) v = INF;
         stage[x] = v;
         valid += v < INF;
     }
-    int total = block_sum256(valid, sh.red);
+    int total = block_sum<NT>(valid, sh.red);
     uint32_t tau = INF;  // entries < tau are all taken
     int need_eq = 0;     // plus this many entries == tau, lowest index first
     // Finds the bin holding rank kk of sh.hist; writes sh.bin and sh.kk.
@@ -119,11 +168,11 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
         // light weights are usually packed near the minimum: try the 256
         // values [vmin, vmin + 256) first (one histogram, few collisions)
         uint32_t vmin = INF;
-        for (int32_t x = tid; x < n; x += 256) vmin = min(vmin, stage[x]);
-        vmin = block_min256(vmin, sh.red);
-        sh.hist[tid] = 0;
+        for (int32_t x = tid; x < n; x += NT) vmin = min(vmin, stage[x]);
+        vmin = block_min<NT>(vmin, sh.red);
+        if (tid < 256) sh.hist[tid] = 0;
         __syncthreads();
-        for (int32_t x = tid; x < n; x += 256) {
+        for (int32_t x = tid; x < n; x += NT) {
             const uint32_t w = stage[x];
             if (w < INF && w - vmin < 256u) atomicAdd(&sh.hist[w - vmin], 1u);
         }
@@ -137,9 +186,9 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
             int kk = NIN_L;
             for (int shift = 24; shift >= 0; shift -= 8) {
                 __syncthreads();
-                sh.hist[tid] = 0;
+                if (tid < 256) sh.hist[tid] = 0;
                 __syncthreads();
-                for (int32_t x = tid; x < n; x += 256) {
+                for (int32_t x = tid; x < n; x += NT) {
                     const uint32_t v = stage[x];
                     if (v < INF && (v & mask) == prefix) atomicAdd(&sh.hist[(v >> shift) & 255u], 1u);
                 }
@@ -155,7 +204,7 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
         __syncthreads();
     }
     // ordered collection over contiguous segments of the staged values
-    const int32_t seg = (n + 255) / 256;
+    const int32_t seg = (n + NT - 1) / NT;
     const int32_t x0 = min(n, tid * seg), x1 = min(n, x0 + seg);
     int c_less = 0, c_eq = 0;
     for (int32_t x = x0; x < x1; ++x) {
@@ -164,8 +213,8 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
         c_eq += (v == tau && v < INF);
     }
     int tot_less, tot_eq;
-    int off_less = block_exscan256(c_less, sh.red, &tot_less);
-    int off_eq = block_exscan256(c_eq, sh.red + 8, &tot_eq);
+    int off_less = block_exscan<NT>(c_less, sh.red, &tot_less);
+    int off_eq = block_exscan<NT>(c_eq, sh.red + 16, &tot_eq);
     for (int32_t x = x0; x < x1; ++x) {
         const uint32_t v = stage[x];
         if (v >= INF) continue;

@@ -43,16 +43,21 @@ void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t o
     k_nin_build<<<count, 256, nin_build_lds_bytes(g.P), s>>>(g, first, only_short);
 }
 
-__global__ __launch_bounds__(256) void k_select_vec(const int32_t *vals, int32_t n, int32_t excl, int2 *list,
-                                                    int32_t *cnt, int32_t *beta) {
+// A single list on the critical path of an update: one wide block, so that
+// more loads are in flight and the LDS passes take fewer steps.
+constexpr int SELECT_WIDE = 1024;
+
+__global__ __launch_bounds__(SELECT_WIDE) void k_select_vec(const int32_t *vals, int32_t n, int32_t excl, int2 *list,
+                                                            int32_t *cnt, int32_t *beta) {
     __shared__ SelectShared sh;
     extern __shared__ uint32_t stage[];
-    select_light(vals, n, excl, list, cnt, beta, sh, stage);
+    select_light<SELECT_WIDE>(vals, n, excl, list, cnt, beta, sh, stage);
 }
 
 void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
                        int32_t *beta, hipStream_t s) {
-    k_select_vec<<<1, 256, (size_t)(n > 0 ? n : 1) * sizeof(uint32_t), s>>>(vals, n, exclude, list, cnt, beta);
+    k_select_vec<<<1, SELECT_WIDE, (size_t)(n > 0 ? n : 1) * sizeof(uint32_t), s>>>(vals, n, exclude, list, cnt,
+                                                                                    beta);
 }
 
 // New node p: its out-edges p -> y (weights w_row[y]) are in-edges of y.
@@ -91,20 +96,20 @@ void launch_nin_purge(const DevGraph &g, int32_t k, int32_t *queue, hipStream_t 
     k_nin_purge<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, k, queue);
 }
 
-__global__ __launch_bounds__(256) void k_nin_rebuild_queue(DevGraph g, const int32_t *queue) {
+__global__ __launch_bounds__(SELECT_WIDE) void k_nin_rebuild_queue(DevGraph g, const int32_t *queue) {
     __shared__ SelectShared sh;
     extern __shared__ uint32_t stage[];
     const int count = g.ctl->short_count;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int32_t y = queue[idx];
-        select_light(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, g.nin + (int64_t)y * NIN_L, g.nin_cnt + y,
-                     g.nin_beta + y, sh, stage);
+        select_light<SELECT_WIDE>(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, g.nin + (int64_t)y * NIN_L,
+                                  g.nin_cnt + y, g.nin_beta + y, sh, stage);
     }
 }
 
 void launch_nin_rebuild_queue(const DevGraph &g, const int32_t *queue, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_nin_rebuild_queue<<<32, 256, nin_build_lds_bytes(g.P), s>>>(g, queue);
+    k_nin_rebuild_queue<<<32, SELECT_WIDE, nin_build_lds_bytes(g.P), s>>>(g, queue);
 }
 
 // ---------------------------------------------------------------------------
