@@ -100,6 +100,7 @@ typedef struct {
     int32_t full_scans;  /* in-edge scans that went past the light-edge index */
     int32_t sweeps;      /* largest number of relaxation sweeps of one row */
     int32_t rows_relaxed;/* rows touched by an add-node / decrease relaxation */
+    int32_t heavy_rows;  /* rows with more than 64 flagged pairs (one work-group each) */
 } apsp_update_stats;
 
 /* ---- sizing ------------------------------------------------------------ */

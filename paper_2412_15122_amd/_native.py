@@ -49,6 +49,7 @@ class UpdateStats(ctypes.Structure):
         ("full_scans", ctypes.c_int32),
         ("sweeps", ctypes.c_int32),
         ("rows_relaxed", ctypes.c_int32),
+        ("heavy_rows", ctypes.c_int32),
     ]
 
     def as_dict(self):

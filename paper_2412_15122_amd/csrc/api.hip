@@ -599,6 +599,7 @@ apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
     out->full_scans = c.full_scans;
     out->sweeps = c.sweeps;
     out->rows_relaxed = c.rows_relaxed;
+    out->heavy_rows = c.heavy_count;
     out->fallback = g->last_fallback;
     int32_t kind = g->last_kind;
     if (kind == -1) {  // edge update: the device chose the path

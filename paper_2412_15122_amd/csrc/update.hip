@@ -619,6 +619,15 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
         int sweeps = 0;
         wave_bellman_ford(g, Drow, list, cnt, fsl, sweeps, my_fs);
         my_sweeps = max(my_sweeps, sweeps);
+        // undirected: D' is symmetric and so is the mask, so the final
+        // entries of row i are also those of column i.  A heavy row j takes
+        // its entry (j, i) from here; a light row j computes the same value
+        // itself, and any interleaving of the two exact writes is harmless.
+        if (g.undirected)
+            for (int e = lane; e < cnt; e += 64) {
+                const int32_t y = list[e];
+                g.D[(int64_t)y * g.ld + i] = Drow[y];
+            }
     }
     // statistics: one partial per work-group, summed by k_mask_finish
     if (lane == 0) {
@@ -666,9 +675,10 @@ __global__ __launch_bounds__(256) void k_mask_finish(DevGraph g, FusedArgs fa, i
 }
 
 // Pass B: the heavy rows, one block each with the row in LDS.
-//   undirected: D' is symmetric, so a flagged (i, j) whose row j was light
-//   is copied from D'[j][i]; the heavy-heavy entries are recomputed by
-//   Bellman-Ford against the now exact remainder of the row.
+//   undirected: every flagged (i, j) whose row j was light already holds its
+//   final value (written by pass A from D'[j][i]); the heavy-heavy entries
+//   are recomputed by Bellman-Ford against the now exact remainder of the
+//   row.
 //   directed: every flagged entry is recomputed by Bellman-Ford.
 __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, FusedArgs fa) {
     extern __shared__ uint32_t sm[];
@@ -686,6 +696,42 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, Fused
     int32_t *glist = fa.scratch + (int64_t)blockIdx.x * 2 * g.P;
     int32_t *fsl = glist + g.P;
     int my_fs = 0, my_sweeps = 0;
+    if (g.undirected) {
+        if (blockIdx.x >= count) return;
+        const int64_t nwp = (g.P + 31) / 32;
+        // bitmap of the heavy rows (sh.fl), built once per work-group
+        for (int w = tid; w < nw; w += FUSED_THREADS) sh.fl[w] = 0;
+        __syncthreads();
+        for (int q = tid; q < count; q += FUSED_THREADS) {
+            const int32_t r = fa.heavy_rows[q];
+            atomicOr(&sh.fl[r >> 5], 1u << (r & 31));
+        }
+        __syncthreads();
+        for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+            const int32_t i = fa.heavy_rows[idx];
+            int32_t *Drow = g.D + (int64_t)i * g.ld;
+            for (int32_t c = tid * 4; c < n; c += FUSED_THREADS * 4)
+                *reinterpret_cast<uint4 *>(sh.cur + c) = *reinterpret_cast<const uint4 *>(Drow + c);
+            const uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
+            for (int w = tid; w < nw; w += FUSED_THREADS) sh.fl2[w] = fw[w] & sh.fl[w];
+            __syncthreads();
+            const int todo = compact_bits(sh.fl2, nw, glist, sh.red);
+            for (int e = tid; e < todo; e += FUSED_THREADS) sh.cur[glist[e]] = INF;
+            if (fa.mode == FUSED_REMOVE && tid == 0) sh.cur[fa.k] = INF;
+            int sweeps = 0;
+            if (todo > 0) row_bellman_ford(g, sh, glist, todo, fsl, sweeps, my_fs);
+            __syncthreads();
+            for (int e = tid; e < todo; e += FUSED_THREADS) {
+                const int32_t y = glist[e];
+                Drow[y] = (int32_t)sh.cur[y];
+            }
+            if (tid == 0) my_sweeps = max(my_sweeps, sweeps);
+            __syncthreads();
+        }
+        if (tid == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
+        if (tid == 0 && my_sweeps) atomicMax(&g.ctl->sweeps, my_sweeps);
+        return;
+    }
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int32_t i = fa.heavy_rows[idx];
         const RowTests rt = row_tests(g, fa, i, w_old);
