@@ -308,7 +308,7 @@ __device__ __forceinline__ uint32_t group16_min(uint32_t v) {
     return v;
 }
 
-constexpr int FUSED_UNROLL = 8;  // int4 loads in flight per thread and row
+constexpr int FUSED_UNROLL = 4;  // int4 loads in flight per thread and row
 constexpr int LDS_LIST = 128;    // flagged columns a block-per-row recompute keeps in LDS
 
 __device__ __forceinline__ unsigned long long lanes_below() {
@@ -442,7 +442,7 @@ __device__ inline int compact_bits(const uint32_t *bm, int nw, int32_t *list, ui
     int c = 0;
     for (int w = w0; w < w1; ++w) c += __popc(bm[w]);
     int tot;
-    int off = block_exscan256(c, red, &tot);
+    int off = block_exscan<FUSED_THREADS>(c, red, &tot);
     for (int w = w0; w < w1; ++w) {
         uint32_t bits = bm[w];
         while (bits) {
@@ -457,8 +457,8 @@ __device__ inline int compact_bits(const uint32_t *bm, int nw, int32_t *list, ui
 
 // Bellman-Ford relaxation of the columns list[0..total) of the LDS row cur:
 //   cur[y] = min_x cur[x] (+) A'[x][y]
-// Sweeps scan each y's light in-edges (16 lanes per y, 16 entries per
-// load, stopping once an entry is at least the current value; unused
+// Sweeps scan each y's light in-edges (4 lanes per y, 32 entries per round
+// trip, stopping once an entry is at least the current value; unused
 // entries are (0, INF) sentinels).  When the sweeps are stable, every y
 // above its index bound beta gets an exhaustive scan of its in-edges, and
 // the sweeps resume if that changed anything.
@@ -466,7 +466,8 @@ __device__ inline void row_bellman_ford(const DevGraph &g, FusedShared &sh, cons
                                  int &sweeps, int &nfs_total) {
     const int n = g.n_slots;
     const int tid = threadIdx.x;
-    const int grp = tid >> 4, gl = tid & 15;
+    const int grp = tid >> 2, l4 = tid & 3;
+    constexpr int NG = FUSED_THREADS / 4;
     const int lim = g.lim;
     const int32_t *Min = in_matrix(g);
     uint32_t *cur = sh.cur;
@@ -475,23 +476,44 @@ __device__ inline void row_bellman_ford(const DevGraph &g, FusedShared &sh, cons
             __syncthreads();
             if (tid == 0) *sh.flag_changed = 0;
             __syncthreads();
-            for (int e = grp; e < total; e += FUSED_THREADS / 16) {
+            bool changed = false;
+            for (int e = grp; e < total; e += NG) {
                 const int32_t y = list[e];
                 uint32_t best = cur[y];
-                const int2 *L = g.nin + (int64_t)y * NIN_L;
-                for (int c0 = 0; c0 < lim; c0 += 16) {
-                    const int e2 = c0 + gl;
-                    const int2 ent = e2 < lim ? L[e2] : make_int2(0, (int)INF);
-                    const uint32_t cand = (uint32_t)ent.y < best ? cur[ent.x] + (uint32_t)ent.y : INF;
-                    best = min(best, group16_min(cand));
-                    const uint32_t wlast = (uint32_t)__shfl(ent.y, 15, 16);
+                const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
+                for (int c0 = 0; c0 < lim; c0 += 32) {
+                    const int e0 = c0 + 4 * l4, e1 = e0 + 16;
+                    const int4 none = make_int4(0, (int)INF, 0, (int)INF);
+                    int4 pa = none, pb = none, pc = none, pd = none;
+                    if (e0 < lim) pa = L4[e0 >> 1];
+                    if (e0 + 2 < lim) pb = L4[(e0 >> 1) + 1];
+                    if (e1 < lim) pc = L4[e1 >> 1];
+                    if (e1 + 2 < lim) pd = L4[(e1 >> 1) + 1];
+                    if (e0 + 1 >= lim) pa.w = (int)INF;
+                    if (e0 + 3 >= lim) pb.w = (int)INF;
+                    if (e1 + 1 >= lim) pc.w = (int)INF;
+                    if (e1 + 3 >= lim) pd.w = (int)INF;
+                    uint32_t cm = INF;
+                    if ((uint32_t)pa.y < best) cm = min(cm, cur[pa.x] + (uint32_t)pa.y);
+                    if ((uint32_t)pa.w < best) cm = min(cm, cur[pa.z] + (uint32_t)pa.w);
+                    if ((uint32_t)pb.y < best) cm = min(cm, cur[pb.x] + (uint32_t)pb.y);
+                    if ((uint32_t)pb.w < best) cm = min(cm, cur[pb.z] + (uint32_t)pb.w);
+                    if ((uint32_t)pc.y < best) cm = min(cm, cur[pc.x] + (uint32_t)pc.y);
+                    if ((uint32_t)pc.w < best) cm = min(cm, cur[pc.z] + (uint32_t)pc.w);
+                    if ((uint32_t)pd.y < best) cm = min(cm, cur[pd.x] + (uint32_t)pd.y);
+                    if ((uint32_t)pd.w < best) cm = min(cm, cur[pd.z] + (uint32_t)pd.w);
+                    cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
+                    cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
+                    best = min(best, cm);
+                    const uint32_t wlast = (uint32_t)__shfl(pd.w, 3, 4);
                     if (wlast >= best) break;  // every later entry is at least as heavy
                 }
-                if (gl == 0 && best < cur[y]) {
+                if (l4 == 0 && best < cur[y]) {
                     cur[y] = best;
-                    *sh.flag_changed = 1;
+                    changed = true;
                 }
             }
+            if (changed) *sh.flag_changed = 1;
             __syncthreads();
             ++sweeps;
             if (*sh.flag_changed == 0) break;
@@ -514,7 +536,7 @@ __device__ inline void row_bellman_ford(const DevGraph &g, FusedShared &sh, cons
             const int32_t *col = Min + (int64_t)y * g.ld;
             uint32_t best = INF;
             for (int32_t x = tid; x < n; x += FUSED_THREADS) best = min(best, cur[x] + (uint32_t)col[x]);
-            best = block_min256(best, sh.red);
+            best = block_min<FUSED_THREADS>(best, sh.red);
             if (tid == 0 && best < cur[y]) {
                 cur[y] = best;
                 *sh.flag_changed = 1;
@@ -705,23 +727,33 @@ __device__ inline void wave_bellman_ford(const DevGraph &g, int32_t *Drow, const
                 const int32_t y = list[e];
                 uint32_t best = (uint32_t)Drow[y];
                 const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
-                for (int c0 = 0; c0 < lim; c0 += 16) {
-                    // lane l4 of the group holds entries c0 + 4*l4 .. +3
-                    const int e0 = c0 + 4 * l4;
-                    int4 pa = make_int4(0, (int)INF, 0, (int)INF), pb = pa;
+                for (int c0 = 0; c0 < lim; c0 += 32) {
+                    // lane l4 of the group holds entries c0 + 4*l4 .. +3 and
+                    // c0 + 16 + 4*l4 .. +3: 32 entries per round trip
+                    const int e0 = c0 + 4 * l4, e1 = e0 + 16;
+                    const int4 none = make_int4(0, (int)INF, 0, (int)INF);
+                    int4 pa = none, pb = none, pc = none, pd = none;
                     if (e0 < lim) pa = L4[e0 >> 1];
                     if (e0 + 2 < lim) pb = L4[(e0 >> 1) + 1];
+                    if (e1 < lim) pc = L4[e1 >> 1];
+                    if (e1 + 2 < lim) pd = L4[(e1 >> 1) + 1];
                     if (e0 + 1 >= lim) pa.w = (int)INF;
                     if (e0 + 3 >= lim) pb.w = (int)INF;
+                    if (e1 + 1 >= lim) pc.w = (int)INF;
+                    if (e1 + 3 >= lim) pd.w = (int)INF;
                     uint32_t cm = INF;
                     if ((uint32_t)pa.y < best) cm = min(cm, (uint32_t)Drow[pa.x] + (uint32_t)pa.y);
                     if ((uint32_t)pa.w < best) cm = min(cm, (uint32_t)Drow[pa.z] + (uint32_t)pa.w);
                     if ((uint32_t)pb.y < best) cm = min(cm, (uint32_t)Drow[pb.x] + (uint32_t)pb.y);
                     if ((uint32_t)pb.w < best) cm = min(cm, (uint32_t)Drow[pb.z] + (uint32_t)pb.w);
+                    if ((uint32_t)pc.y < best) cm = min(cm, (uint32_t)Drow[pc.x] + (uint32_t)pc.y);
+                    if ((uint32_t)pc.w < best) cm = min(cm, (uint32_t)Drow[pc.z] + (uint32_t)pc.w);
+                    if ((uint32_t)pd.y < best) cm = min(cm, (uint32_t)Drow[pd.x] + (uint32_t)pd.y);
+                    if ((uint32_t)pd.w < best) cm = min(cm, (uint32_t)Drow[pd.z] + (uint32_t)pd.w);
                     cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
                     cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
                     best = min(best, cm);
-                    const uint32_t wlast = (uint32_t)__shfl(pb.w, 3, 4);
+                    const uint32_t wlast = (uint32_t)__shfl(pd.w, 3, 4);
                     if (wlast >= best) break;  // every later entry is at least as heavy
                 }
                 if (l4 == 0 && best < (uint32_t)Drow[y]) {

@@ -583,10 +583,16 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
         // flagged columns of row i -> list (at most ROW_CAP kept)
         const uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
         int cnt = 0;
-        for (int b = 0; b < nw; b += 64) {  // wave-uniform
-            const int w = b + lane;
-            uint32_t bits = w < nw ? fw[w] : 0u;
-            const int c = __popc(bits);
+        for (int b = 0; b < nw; b += 512) {  // wave-uniform; 8 words per lane in flight
+            uint32_t wd[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int w = b + q * 64 + lane;
+                wd[q] = w < nw ? fw[w] : 0u;
+            }
+            int c = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c += __popc(wd[q]);
             int incl = c;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -594,11 +600,16 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
                 if (lane >= o) incl += t;
             }
             int pos = cnt + incl - c;
-            while (bits && !reset_only) {
-                const int bt = __ffs(bits) - 1;
-                bits &= bits - 1;
-                if (pos < ROW_CAP) list[pos] = w * 32 + bt;
-                ++pos;
+            if (!reset_only && cnt + __shfl(incl, 63) <= ROW_CAP) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    uint32_t bits = wd[q];
+                    while (bits) {
+                        const int bt = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        list[pos++] = (b + q * 64 + lane) * 32 + bt;
+                    }
+                }
             }
             cnt += __shfl(incl, 63);
         }
@@ -735,7 +746,7 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, Fused
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int32_t i = fa.heavy_rows[idx];
         const RowTests rt = row_tests(g, fa, i, w_old);
-        block_sum256(mask_row(g, fa, i, rt, sh, true, fill), sh.red);
+        block_sum<FUSED_THREADS>(mask_row(g, fa, i, rt, sh, true, fill), sh.red);
         const int todo = compact_bits(fill ? sh.fl2 : sh.fl, nw, glist, sh.red);
         int sweeps = 0;
         if (todo > 0) row_bellman_ford(g, sh, glist, todo, fsl, sweeps, my_fs);
