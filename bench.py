@@ -50,6 +50,8 @@ def parse():
                     help="updates: the n=16384 update stream (default); batched: 512 graphs with 8 queued "
                          "updates each, one persistent launch vs one call per update")
     ap.add_argument("--graphs", type=int, default=None, help="batched / serving: number of graphs (512 / 64)")
+    ap.add_argument("--batch-config", default=None,
+                    help="batched: grid,order,variant to use instead of autotuning")
     ap.add_argument("--rates", default="1000,3000,10000,30000,100000",
                     help="serving: Poisson arrival rates (requests/s) to sweep")
     ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
@@ -163,7 +165,12 @@ def bench_batched(args):
     n_upd = len(items)
     ns = np.array([w.adj.shape[0] for w in wls])
     log(f"[bench] cold starts done; {n_upd} updates; sum n^2 = {int((ns.astype(np.int64) ** 2).sum())}")
-    tuned = autotune.tune(base, items, reps=2, force=True)
+    if args.batch_config:
+        gr, od, va = (int(x) for x in args.batch_config.split(","))
+        tuned = {"config": {"grid": gr, "order": od, "variant": va, "use_graph": 1}, "ms": None, "table": [],
+                 "key": "fixed"}
+    else:
+        tuned = autotune.tune(base, items, reps=2, force=True)
     cfg = tuned["config"]
     log(f"[bench] autotuned config {cfg} ({tuned['ms']} ms); table: " +
         ", ".join(f"g{r['grid']}/o{r['order']}/v{r['variant']}={r['ms']}" for r in tuned["table"]))
@@ -208,6 +215,14 @@ def bench_batched(args):
                  "mean_graph_us": round(float(dur.mean()), 1), "largest_graph_us": round(float(dur[big]), 1),
                  "largest_graph_n": int(ns[big]), "last_start_us": round(float(st_us.max()), 1)}
         log(f"[bench] per-graph spans: {spans}")
+        if cfg["variant"] >= 2 and rep == 0:
+            ph = b.phase_times()
+            log("[bench] lockstep phase ends (us): " + " ".join(f"{x:.0f}" for x in ph))
+            try:
+                b.status()
+                log("[bench] lockstep barriers: ok")
+            except Exception as exc:  # reported, the run continues
+                log(f"[bench] lockstep barriers: {exc}")
         if rep == 0:
             for gi in np.argsort(-dur)[:6]:
                 log(f"[bench]   slow graph {gi}: n={ns[gi]} {dur[gi]:.0f} us, updates "

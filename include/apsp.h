@@ -285,10 +285,16 @@ size_t apsp_batch_workspace_bytes(int32_t max_graphs, int32_t max_items);
 apsp_status apsp_batch_create(void *ws_dev, size_t ws_bytes, int32_t max_graphs, int32_t max_items,
                               apsp_batch **out);
 apsp_status apsp_batch_destroy(apsp_batch *b);
-/* grid: work-groups of the persistent launch (0: two per compute unit, at
- * most one per graph); order: 0 most work first, 1 array order; variant:
- * loads in flight per thread in the streaming loops (0: one, 1: two);
- * use_graph: 1 records the launch once in a HIP graph and replays it. */
+/* Two schedules.  Work queue (variants 0, 1): every work-group takes one
+ * graph at a time (order: 0 most work first, 1 array order) and runs all of
+ * its items alone.  Lockstep (variants 2, 3): step s applies item s of every
+ * graph, the row sweeps of all graphs spread over the whole grid between
+ * grid barriers (a cooperative launch of the resident grid; the order is
+ * irrelevant).  Even variants keep 4, odd ones 8 loads in flight per lane in
+ * the streaming loops.  grid: work-groups (0: two per compute unit, at most
+ * one per graph for the work queue; all resident ones for lockstep; a
+ * lockstep grid is capped at the resident count).  use_graph: 1 records the
+ * launch once in a HIP graph and replays it. */
 apsp_status apsp_batch_set_config(apsp_batch *b, int32_t grid, int32_t order, int32_t variant,
                                   int32_t use_graph);
 /* Runs items[0..num_items) on graphs[0..num_graphs) (distinct handles) on
@@ -301,12 +307,22 @@ apsp_status apsp_batch_set_config(apsp_batch *b, int32_t grid, int32_t order, in
 apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num_graphs,
                            const apsp_batch_item *items, int32_t num_items, void *hip_stream,
                            int32_t *new_ids);
+/* Waits for the last apsp_batch_run and reports APSP_E_DEVICE if a lockstep
+ * grid barrier timed out (every wait is bounded, so a launch always ends;
+ * the graphs of such a batch are then in an undefined state). */
+apsp_status apsp_batch_status(apsp_batch *b);
 /* Per-graph timing of the last apsp_batch_run, read from the device wall
  * clock (synchronous: waits for that run's stream).  start_us[i] / end_us[i]
  * are when a work-group took graphs[i] and finished its items, in
  * microseconds from the earliest start; -1 for graphs without items.
  * num_graphs must equal that run's. */
 apsp_status apsp_batch_graph_times(apsp_batch *b, double *start_us, double *end_us, int32_t num_graphs);
+/* Diagnostics of the last lockstep apsp_batch_run (synchronous): for each of
+ * its first 32 steps, the wall clock (microseconds from the start of the
+ * first graph) after the grid barriers ending the per-graph phase, the row
+ * sweeps and the recompute (0 where a step had no recompute phase); *count
+ * receives min(cap, 3 * steps).  Zero entries for the work-queue schedule. */
+apsp_status apsp_batch_phase_times(apsp_batch *b, double *us, int32_t cap, int32_t *count);
 
 const char *apsp_last_error(void);
 int32_t apsp_abi_version(void);

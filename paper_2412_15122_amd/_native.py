@@ -109,6 +109,8 @@ SIGNATURES = {
     "apsp_batch_destroy": (_I32, [_P]),
     "apsp_batch_set_config": (_I32, [_P, _I32, _I32, _I32, _I32]),
     "apsp_batch_run": (_I32, [_P, ctypes.POINTER(_P), _I32, ctypes.POINTER(BatchItem), _I32, _P, _PI32]),
+    "apsp_batch_status": (_I32, [_P]),
+    "apsp_batch_phase_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double), _I32, _PI32]),
     "apsp_batch_graph_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _I32]),
 }
 

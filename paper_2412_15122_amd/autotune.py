@@ -1,8 +1,9 @@
 """Autotuner of the batched launch shape.
 
-The batched kernel has three launch knobs (apsp_batch_set_config): the number
-of persistent work-groups, the order in which they take graphs (most work
-first, or as given) and the streaming variant (loads in flight per thread).
+The batched launch has four knobs (apsp_batch_set_config): the schedule
+(one work-group per graph from a work queue, or all graphs in lockstep with
+the whole grid on every row sweep), the number of work-groups, the order in
+which the work queue hands out graphs, and the loads in flight per lane.
 The best choice depends on the spread of graph sizes and the number of
 graphs, so the tuner times every candidate on clones of the caller's graphs
 (the originals are not touched), keeps the fastest, and caches it in a JSON
@@ -39,12 +40,16 @@ def signature(graphs: Sequence[Graph], items: Sequence[tuple]) -> str:
 
 
 def candidates(n_cu: int, n_graphs: int) -> List[Dict[str, int]]:
+    """Work-queue schedule (variants 0, 1): grid x order; lockstep schedule
+    (variants 2, 3): the resident grid (order does not apply)."""
     out = []
     grids = sorted({min(n_graphs, k * n_cu) for k in (1, 2, 4)} | {0})
     for variant in (0, 1):
         for order in (0, 1):
             for grid in grids:
                 out.append({"grid": grid, "order": order, "variant": variant, "use_graph": 1})
+    for variant in (2, 3):
+        out.append({"grid": 0, "order": 0, "variant": variant, "use_graph": 1})
     return out
 
 

@@ -160,6 +160,18 @@ class Batch:
         return results
 
 
+    def status(self) -> None:
+        """Wait for the last run; raises if a lockstep barrier timed out."""
+        N.check(self._lib.apsp_batch_status(self._h), "apsp_batch_status")
+
+    def phase_times(self):
+        """Lockstep diagnostics of the last run: microseconds at the end of
+        each step's phases (see apsp_batch_phase_times)."""
+        buf = (ctypes.c_double * 96)()
+        cnt = ctypes.c_int32()
+        N.check(self._lib.apsp_batch_phase_times(self._h, buf, 96, ctypes.byref(cnt)), "apsp_batch_phase_times")
+        return np.array(buf[:cnt.value])
+
     def graph_times(self, num_graphs: int):
         """(start_us, end_us) per graph of the last run (waits for it)."""
         a = (ctypes.c_double * max(num_graphs, 1))()

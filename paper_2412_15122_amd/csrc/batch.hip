@@ -1,10 +1,6 @@
-// Batched updates over many graphs in one persistent launch.
+// Batched updates over many graphs.
 //
-// Every work-group pops a graph from a shared counter (largest first by
-// default) and applies that graph's queued items in order, so per-graph
-// order holds without any wait between work-groups: a work-group exits as
-// soon as the counter has passed the last graph.  Each update runs the same
-// method as the single-graph kernels, at work-group scope:
+// Each update runs the same method as the single-graph kernels:
 //   add node     Corollaries corollary1 / corollary2 (new row / column over
 //                the new node's light edges) and Theorem theorem3 (relaxation)
 //   remove node  Corollary corollary3 mask, then Bellman-Ford recompute of
@@ -12,6 +8,22 @@
 //   edge update  decrease: relaxation through the new edge; increase: mask
 //                of the pairs that can use the edge, then the same recompute
 //   query        Algorithm 7 (candidates, then the canonical walk)
+// split into phases: a prologue and an epilogue that one work-group runs per
+// graph (list selection, O(n) vectors, placement, index edits), and row
+// sweeps (relaxation, mask, recompute) that any number of work-groups can
+// share by row ranges.
+//
+// Two schedules over the same phases:
+//   work queue  every work-group pops a graph (most work first) and runs all
+//               of its items, every phase, alone; no waiting between
+//               work-groups.  Good for many small graphs.
+//   lockstep    step s applies item s of every graph: graph-parallel
+//               epilogue(s-1) + prologue(s), then the row sweeps of all
+//               graphs spread over the whole grid, with grid barriers between
+//               the phases.  The grid is launched cooperatively (all of it
+//               resident); every barrier wait is bounded and a timeout is
+//               reported instead of hanging.  Good when large graphs would
+//               leave one work-group streaming a whole matrix.
 #include <algorithm>
 
 #include "batch_internal.h"
@@ -19,16 +31,21 @@
 
 namespace apsp {
 
-// Visits the 4-column groups of rows [0, n) whose row_ok(i) holds.  Each
-// wavefront takes runs of U 256-column chunks (64 lanes x 4 columns, one row
-// per chunk), so every lane has U independent 16-byte loads of D in flight
-// before it uses any; body(i, c0, ok, d) runs on every lane (ok false where
-// the lane has no group), so it may use cross-lane operations.
+// ---------------------------------------------------------------------------
+// streaming helpers
+// ---------------------------------------------------------------------------
+
+// Visits the 4-column groups of rows [r0, r1) (columns [0, n)) whose
+// row_ok(i) holds.  Each wavefront takes runs of U 256-column chunks (64
+// lanes x 4 columns, one row per chunk), so every lane has U independent
+// 16-byte loads of D in flight before it uses any; body(i, c0, ok, d) runs
+// on every lane (ok false where the lane has no group), so it may use
+// cross-lane operations.
 template <int U, class RowOk, class Body>
-__device__ inline void stream_chunks(const DevGraph &g, int32_t n, RowOk row_ok, Body body) {
+__device__ inline void stream_chunks(const DevGraph &g, int32_t n, int32_t r0, int32_t r1, RowOk row_ok, Body body) {
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     const int32_t Q = (n + 255) >> 8;
-    const int32_t total = n * Q;
+    const int32_t total = (r1 - r0) * Q;
     for (int32_t base = wv * U; base < total; base += (BATCH_THREADS / 64) * U) {
         uint4 d[U];
         int32_t ri[U], rc[U];
@@ -36,8 +53,8 @@ __device__ inline void stream_chunks(const DevGraph &g, int32_t n, RowOk row_ok,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t k = base + u;
-            const int32_t i = k / Q;
-            const int32_t c0 = (k - i * Q) * 256 + lane * 4;
+            const int32_t i = r0 + k / Q;
+            const int32_t c0 = (k % Q) * 256 + lane * 4;
             ri[u] = i;
             rc[u] = c0;
             ok[u] = k < total && c0 < n && row_ok(i);
@@ -60,17 +77,33 @@ __device__ inline void stage_rows(uint32_t *stage, int32_t P, int32_t n, const i
     __syncthreads();
 }
 
+// 4 consecutive entries of a row vector (columns >= n read as INF).
+__device__ inline uint4 vec4(const uint32_t *v, int32_t c0, int32_t n) {
+    return make_uint4(v[c0], c0 + 1 < n ? v[c0 + 1] : INF, c0 + 2 < n ? v[c0 + 2] : INF, c0 + 3 < n ? v[c0 + 3] : INF);
+}
+
+// D[i][c0..c0+3] := min(D, t), stored only when something changed.
+__device__ inline void store_min4(const DevGraph &g, int32_t i, int32_t c0, uint4 d, uint4 t) {
+    if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
+        d.x = min(d.x, t.x);
+        d.y = min(d.y, t.y);
+        d.z = min(d.z, t.z);
+        d.w = min(d.w, t.w);
+        *reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0) = d;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // add node
 // ---------------------------------------------------------------------------
 constexpr int PREF = 8;  // index entries whose loads are issued together
 
-template <int U>
-__device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
-                          uint32_t *stage) {
+// Weights, the new node's light lists, out[] (new row) and in[] (new column).
+__device__ __forceinline__ void add_prologue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
+                             uint32_t *stage) {
     const int tid = threadIdx.x;
     const int n = g.n_slots;
-    const int32_t p = it.a, new_id = it.b, rank = it.c;
+    const int32_t p = it.a, rank = it.c;
     const bool und = g.undirected != 0;
     int32_t *wo = bg.wo;
     int32_t *wi = und ? bg.wo : bg.wi;
@@ -154,27 +187,35 @@ __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchIt
         }
     }
     __syncthreads();
-    const int32_t *in = und ? bg.vout : bg.vin;
-    const int32_t *out = bg.vout;
-    // Theorem theorem3 over all old pairs; the new row `out` sits in LDS
-    stage_rows(stage, g.P, n, out, nullptr);
+}
+
+// Theorem theorem3 over rows [r0, r1): D[i][j] = min(D[i][j], in[i] + out[j]).
+// outv: the new row (LDS stage or global).
+template <int U>
+__device__ __forceinline__ void add_relax_rows(const DevGraph &g, const BatchGraph &bg, int32_t r0, int32_t r1, const uint32_t *outv) {
+    const int n = g.n_slots;
+    const int32_t *in = g.undirected ? bg.vout : bg.vin;
     stream_chunks<U>(
-        g, n, [&](int32_t i) { return (uint32_t)in[i] < INF; },
+        g, n, r0, r1, [&](int32_t i) { return (uint32_t)in[i] < INF; },
         [&](int32_t i, int32_t c0, bool ok, uint4 d) {
             if (!ok) return;
             const uint32_t a = (uint32_t)in[i];
-            const uint4 o = *reinterpret_cast<const uint4 *>(stage + c0);
-            const uint4 t = make_uint4(a + o.x, a + o.y, a + o.z, a + o.w);
-            if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
-                d.x = min(d.x, t.x);
-                d.y = min(d.y, t.y);
-                d.z = min(d.z, t.z);
-                d.w = min(d.w, t.w);
-                *reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0) = d;
-            }
+            const uint4 o = vec4(outv, c0, n);
+            store_min4(g, i, c0, d, make_uint4(a + o.x, a + o.y, a + o.z, a + o.w));
         });
-    __syncthreads();
-    // place row / column p
+}
+
+// Row and column p of D, A (and A^T), the id, the rank, and p's out-edges in
+// every other node's light list.
+__device__ __forceinline__ void add_epilogue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it) {
+    const int tid = threadIdx.x;
+    const int n = g.n_slots;
+    const int32_t p = it.a, new_id = it.b, rank = it.c;
+    const bool und = g.undirected != 0;
+    const int32_t *wo = bg.wo;
+    const int32_t *wi = und ? bg.wo : bg.wi;
+    const int32_t *in = und ? bg.vout : bg.vin;
+    const int32_t *out = bg.vout;
     const int64_t ld = g.ld;
     for (int32_t s = tid; s < n; s += BATCH_THREADS) {
         if (s == p) continue;
@@ -195,9 +236,8 @@ __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchIt
         it.rank_src[rank] = p;
     }
     __syncthreads();
-    // p's out-edges are in-edges of every other node
-    // (lanes screen 64 lists at a time: an edge at or above a list's bound
-    // is not listed)
+    // lanes screen 64 lists at a time: an edge at or above a list's bound is
+    // not listed
     for (int32_t y0 = (tid >> 6) * 64; y0 < n; y0 += BATCH_THREADS) {
         const int32_t y = y0 + lane_id();
         const bool cand = y < n && y != p && g.id_of_slot[y] >= 0 && (uint32_t)wo[y] < (uint32_t)g.nin_beta[y];
@@ -212,23 +252,41 @@ __device__ void batch_add(const DevGraph &g, const BatchGraph &bg, const BatchIt
 }
 
 // ---------------------------------------------------------------------------
-// mask (removal / increase) and recompute
+// mask and recompute (removal, edge increase)
 // ---------------------------------------------------------------------------
-// Flags into the graph's bitmap, 32 columns per word per thread step, then
-// one wavefront per flagged row runs the Bellman-Ford recompute in place.
+
+__device__ inline FusedArgs remove_args(const BatchGraph &bg, const BatchItem &it) {
+    FusedArgs fa{};
+    fa.mode = FUSED_REMOVE;
+    fa.k = it.a;
+    fa.col1 = bg.colu;
+    fa.row1 = bg.rowu;
+    fa.row2 = nullptr;
+    return fa;
+}
+
+__device__ inline FusedArgs increase_args(const DevGraph &g, const BatchGraph &bg) {
+    FusedArgs fa{};
+    fa.mode = FUSED_INCREASE;
+    fa.k = -1;
+    fa.col1 = bg.colu;
+    fa.col2 = bg.colv;
+    fa.row1 = bg.rowv;
+    fa.row2 = g.undirected ? bg.rowu : nullptr;
+    return fa;
+}
+
+// Flags of rows [r0, r1) into the graph's bitmap (8 lanes assemble each
+// 32-column word with shuffles) and the row marks.  S1 / S2: the pair test's
+// row vectors (LDS stage or global; S2 used only when fa.row2 is set).
 template <int U>
-__device__ void batch_mask_recompute(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa, uint32_t w_old,
-                                     uint32_t *stage, int32_t *wlists) {
-    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+__device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa, uint32_t w_old, int32_t r0,
+                            int32_t r1, const uint32_t *S1, const uint32_t *S2) {
+    const int lane = lane_id();
     const int n = g.n_slots;
-    const int nw = (n + 31) / 32;
     const int64_t nwp = (g.P + 31) / 32;
-    // the pair test's row vectors in LDS; rows stream through in chunks and
-    // 8 lanes assemble each 32-column flag word with shuffles
-    stage_rows(stage, g.P, n, fa.row1, fa.row2);
-    const uint32_t *S1 = stage, *S2 = stage + g.P;
     stream_chunks<U>(
-        g, n,
+        g, n, r0, r1,
         [&](int32_t i) {
             const RowTests rt = row_tests(g, fa, i, w_old);
             return rt.t1 || rt.t2;
@@ -237,8 +295,8 @@ __device__ void batch_mask_recompute(const DevGraph &g, const BatchGraph &bg, co
             uint32_t bits = 0;
             if (ok) {
                 const RowTests rt = row_tests(g, fa, i, w_old);
-                const uint4 v1 = *reinterpret_cast<const uint4 *>(S1 + c0);
-                const uint4 v2 = fa.row2 ? *reinterpret_cast<const uint4 *>(S2 + c0) : v1;
+                const uint4 v1 = vec4(S1, c0, n);
+                const uint4 v2 = fa.row2 ? vec4(S2, c0, n) : v1;
                 const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
                 const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w};
                 const uint32_t w2[4] = {v2.x, v2.y, v2.z, v2.w};
@@ -256,104 +314,217 @@ __device__ void batch_mask_recompute(const DevGraph &g, const BatchGraph &bg, co
             if (ok && (lane & 7) == 0) bg.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
             if (__ballot(ok && word != 0) != 0 && lane == 0) atomicOr(&bg.row_bits[i >> 5], 1u << (i & 31));
         });
-    __syncthreads();
-    int my_flagged = 0, my_rows = 0, my_fs = 0, my_sweeps = 0;
+}
+
+// Bellman-Ford over the flagged columns of row Drow read straight from its
+// flag words fw[0..nw) (no list): 16 groups of 4 lanes take words round
+// robin, a group relaxes the columns of its word one at a time, 32 index
+// entries per round trip, stopping once an entry is at least the current
+// value.  Columns left above their index bound are marked in `need` (nw
+// words of LDS) and get exhaustive scans by the whole wavefront; the sweeps
+// resume if that changed anything.
+__device__ __forceinline__ void wave_bellman_ford_words(const DevGraph &g, int32_t *Drow, const uint32_t *fw, int nw,
+                                                        uint32_t *need) {
+    const int lane = lane_id();
+    const int g4 = lane >> 2, l4 = lane & 3;
+    const int lim = g.lim;
+    const int n = g.n_slots;
+    const int32_t *Min = in_matrix(g);
+    for (;;) {
+        for (;;) {
+            bool changed = false;
+            for (int w = g4; w < nw; w += 16) {
+                uint32_t bits = fw[w];
+                while (bits) {
+                    const int32_t y = w * 32 + __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    uint32_t best = (uint32_t)Drow[y];
+                    const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
+                    for (int c0 = 0; c0 < lim; c0 += 32) {
+                        const int e0 = c0 + 4 * l4, e1 = e0 + 16;
+                        const int4 none = make_int4(0, (int)INF, 0, (int)INF);
+                        int4 pa = none, pb = none, pc = none, pd = none;
+                        if (e0 < lim) pa = L4[e0 >> 1];
+                        if (e0 + 2 < lim) pb = L4[(e0 >> 1) + 1];
+                        if (e1 < lim) pc = L4[e1 >> 1];
+                        if (e1 + 2 < lim) pd = L4[(e1 >> 1) + 1];
+                        if (e0 + 1 >= lim) pa.w = (int)INF;
+                        if (e0 + 3 >= lim) pb.w = (int)INF;
+                        if (e1 + 1 >= lim) pc.w = (int)INF;
+                        if (e1 + 3 >= lim) pd.w = (int)INF;
+                        uint32_t cm = INF;
+                        if ((uint32_t)pa.y < best) cm = min(cm, (uint32_t)Drow[pa.x] + (uint32_t)pa.y);
+                        if ((uint32_t)pa.w < best) cm = min(cm, (uint32_t)Drow[pa.z] + (uint32_t)pa.w);
+                        if ((uint32_t)pb.y < best) cm = min(cm, (uint32_t)Drow[pb.x] + (uint32_t)pb.y);
+                        if ((uint32_t)pb.w < best) cm = min(cm, (uint32_t)Drow[pb.z] + (uint32_t)pb.w);
+                        if ((uint32_t)pc.y < best) cm = min(cm, (uint32_t)Drow[pc.x] + (uint32_t)pc.y);
+                        if ((uint32_t)pc.w < best) cm = min(cm, (uint32_t)Drow[pc.z] + (uint32_t)pc.w);
+                        if ((uint32_t)pd.y < best) cm = min(cm, (uint32_t)Drow[pd.x] + (uint32_t)pd.y);
+                        if ((uint32_t)pd.w < best) cm = min(cm, (uint32_t)Drow[pd.z] + (uint32_t)pd.w);
+                        cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
+                        cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
+                        best = min(best, cm);
+                        const uint32_t wlast = (uint32_t)__shfl(pd.w, 3, 4);
+                        if (wlast >= best) break;
+                    }
+                    if (l4 == 0 && best < (uint32_t)Drow[y]) {
+                        Drow[y] = (int32_t)best;
+                        changed = true;
+                    }
+                }
+            }
+            __threadfence_block();
+            if (!__any(changed)) break;
+        }
+        // columns above their bound -> need (LDS bitmap of this wavefront)
+        for (int w = lane; w < nw; w += 64) need[w] = 0;
+        __threadfence_block();
+        for (int w = g4; w < nw; w += 16) {
+            uint32_t bits = fw[w];
+            uint32_t mark = 0;
+            while (bits) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                const int32_t y = w * 32 + b;
+                uint32_t beta_eff = (uint32_t)g.nin_beta[y];
+                if (lim < NIN_L) beta_eff = min(beta_eff, (uint32_t)g.nin[(int64_t)y * NIN_L + lim].y);
+                if ((uint32_t)Drow[y] > beta_eff) mark |= 1u << b;
+            }
+            if (l4 == 0 && mark) need[w] = mark;
+        }
+        __threadfence_block();
+        bool changed = false;
+        for (int w = 0; w < nw; ++w) {  // wave-uniform: every lane reads the same LDS word
+            uint32_t bits = need[w];
+            while (bits) {
+                const int32_t y = w * 32 + __ffs(bits) - 1;
+                bits &= bits - 1;
+                const int32_t *col = Min + (int64_t)y * g.ld;
+                uint32_t best = INF;
+                for (int32_t x = lane; x < n; x += 64) best = min(best, (uint32_t)Drow[x] + (uint32_t)col[x]);
+                best = wave_min(best);
+                if (best < (uint32_t)Drow[y]) {
+                    changed = true;
+                    if (lane == 0) Drow[y] = (int32_t)best;
+                }
+                __threadfence_block();
+            }
+        }
+        if (!changed) break;
+    }
+}
+
+// Recompute of the flagged rows among [r0, r1): one wavefront per row, rows
+// dealt round robin to the 4 wavefronts.  The row's flagged entries (and
+// column k of a removal) start at INF and are relaxed in place; rows with at
+// most ROW_CAP flags use a list in LDS (wlists: 2 ROW_CAP words per wave);
+// larger ones use a list in global memory (glists: 2 P words per wave) or,
+// without one, read their flag words directly (needs: 4 * ceil(P / 32)
+// words of LDS).
+__device__ __forceinline__ void recompute_rows(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa, int32_t r0, int32_t r1,
+                               int32_t *wlists, int32_t *glists, uint32_t *needs, bool defer_heavy = false) {
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int nw = (g.n_slots + 31) / 32;
+    const int64_t nwp = (g.P + 31) / 32;
     int32_t *list = wlists + wv * 2 * ROW_CAP;
     int32_t *fsl = list + ROW_CAP;
-    int32_t *glist = bg.scratch + (int64_t)wv * 2 * g.P;  // rows with more than ROW_CAP flags
-    int32_t *gfsl = glist + g.P;
-    for (int32_t i0 = wv * 64; i0 < n; i0 += BATCH_THREADS) {
-      const int32_t ii = i0 + lane;
-      unsigned long long rows = __ballot(ii < n && ((bg.row_bits[ii >> 5] >> (ii & 31)) & 1u));
-      while (rows) {
-        const int32_t i = i0 + __ffsll((long long)rows) - 1;
-        rows &= rows - 1;
-        const uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
-        int cnt = 0;
-        for (int b = 0; b < nw; b += 64) {
-            const int w = b + lane;
-            const uint32_t bits0 = w < nw ? fw[w] : 0u;
-            const int c = __popc(bits0);
-            int incl = c;
+    int32_t *glist = glists ? glists + (int64_t)wv * 2 * g.P : nullptr;
+    int nfs = 0;
+    for (int32_t i = r0 + wv; i < r1; i += BATCH_THREADS / 64) {
+        {
+            if (((bg.row_bits[i >> 5] >> (i & 31)) & 1u) == 0) continue;
+            const uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
+            int cnt = 0;
+            for (int b = 0; b < nw; b += 512) {  // wave-uniform; 8 words per lane in flight
+                uint32_t wd[8];
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int t = __shfl_up(incl, o);
-                if (lane >= o) incl += t;
-            }
-            cnt += __shfl(incl, 63);
-        }
-        int32_t *L = cnt <= ROW_CAP ? list : glist;
-        int32_t *F = cnt <= ROW_CAP ? fsl : gfsl;
-        int done = 0;
-        for (int b = 0; b < nw; b += 64) {
-            const int w = b + lane;
-            uint32_t bits = w < nw ? fw[w] : 0u;
-            const int c = __popc(bits);
-            int incl = c;
+                for (int q = 0; q < 8; ++q) {
+                    const int w = b + q * 64 + lane;
+                    wd[q] = w < nw ? fw[w] : 0u;
+                }
+                int c = 0;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int t = __shfl_up(incl, o);
-                if (lane >= o) incl += t;
+                for (int q = 0; q < 8; ++q) c += __popc(wd[q]);
+                int incl = c;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(incl, o);
+                    if (lane >= o) incl += t;
+                }
+                int pos = cnt + incl - c;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    uint32_t bits = wd[q];
+                    while (bits) {
+                        const int bt = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        const int32_t col = (b + q * 64 + lane) * 32 + bt;
+                        if (pos < ROW_CAP) list[pos] = col;
+                        if (glist) glist[pos] = col;
+                        ++pos;
+                    }
+                }
+                cnt += __shfl(incl, 63);
             }
-            int pos = done + incl - c;
-            while (bits) {
-                const int bt = __ffs(bits) - 1;
-                bits &= bits - 1;
-                L[pos++] = w * 32 + bt;
+            if (defer_heavy && cnt > ROW_CAP) {  // one work-group per row later
+                if (lane == 0) bg.heavy_rows[atomicAdd(&g.ctl->heavy_count, 1)] = i;
+                continue;
             }
-            done += __shfl(incl, 63);
+            __threadfence_block();
+            int32_t *Drow = g.D + (int64_t)i * g.ld;
+            if (cnt <= ROW_CAP || glist) {
+                const int32_t *L = cnt <= ROW_CAP ? list : glist;
+                for (int e = lane; e < cnt; e += 64) Drow[L[e]] = (int32_t)INF;
+            } else {
+                for (int w = lane; w < nw; w += 64) {
+                    uint32_t bits = fw[w];
+                    while (bits) {
+                        Drow[w * 32 + __ffs(bits) - 1] = (int32_t)INF;
+                        bits &= bits - 1;
+                    }
+                }
+            }
+            if (fa.mode == FUSED_REMOVE && lane == 0) Drow[fa.k] = (int32_t)INF;
+            __threadfence_block();
+            int sweeps = 0;
+            if (cnt <= ROW_CAP) wave_bellman_ford(g, Drow, list, cnt, fsl, sweeps, nfs);
+            else if (glist) wave_bellman_ford(g, Drow, glist, cnt, glist + g.P, sweeps, nfs);
+            else wave_bellman_ford_words(g, Drow, fw, nw, needs + wv * ((g.P + 31) / 32));
         }
-        __threadfence_block();
-        int32_t *Drow = g.D + (int64_t)i * g.ld;
-        for (int e = lane; e < cnt; e += 64) Drow[L[e]] = (int32_t)INF;
-        if (fa.mode == FUSED_REMOVE && lane == 0) Drow[fa.k] = (int32_t)INF;
-        __threadfence_block();
-        int sweeps = 0;
-        wave_bellman_ford(g, Drow, L, cnt, F, sweeps, my_fs);
-        my_sweeps = max(my_sweeps, sweeps);
-        my_flagged += cnt;
-        ++my_rows;
-      }
     }
-    __syncthreads();
-    for (int w = tid; w < (n + 31) / 32; w += BATCH_THREADS) bg.row_bits[w] = 0;
-    if (lane == 0 && (my_rows || my_fs)) {
-        atomicAdd(&g.ctl->flagged, (unsigned long long)my_flagged);
-        atomicAdd(&g.ctl->rows, my_rows);
-        atomicAdd(&g.ctl->full_scans, my_fs);
-        atomicMax(&g.ctl->sweeps, my_sweeps);
-    }
-    __syncthreads();
+}
+
+__device__ inline void clear_row_marks(const DevGraph &g, const BatchGraph &bg) {
+    for (int w = threadIdx.x; w < (g.n_slots + 31) / 32; w += BATCH_THREADS) bg.row_bits[w] = 0;
 }
 
 // Rebuild the index lists of y when they have shrunk (block-wide select).
-__device__ void batch_rebuild_if_short(const DevGraph &g, int32_t y, SelectShared &ssh, uint32_t *stage) {
+__device__ __forceinline__ void batch_rebuild_if_short(const DevGraph &g, int32_t y, SelectShared &ssh, uint32_t *stage) {
     if (!(g.nin_cnt[y] < NIN_L / 2 && (uint32_t)g.nin_beta[y] < INF && g.id_of_slot[y] >= 0)) return;
     select_light(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, g.nin + (int64_t)y * NIN_L, g.nin_cnt + y,
                  g.nin_beta + y, ssh, stage);
 }
 
-template <int U>
-__device__ void batch_remove(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
-                             uint32_t *stage, int32_t *wlists) {
-    const int tid = threadIdx.x;
-    const int n = g.n_slots;
-    const int32_t k = it.a, rank = it.b, n_live = it.c;
-    for (int32_t i = tid; i < n; i += BATCH_THREADS) {
+__device__ __forceinline__ void remove_prologue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it) {
+    const int32_t k = it.a;
+    if (threadIdx.x == 0) g.ctl->heavy_count = 0;
+    for (int32_t i = threadIdx.x; i < g.n_slots; i += BATCH_THREADS) {
         bg.colu[i] = g.D[(int64_t)i * g.ld + k];
         bg.rowu[i] = g.D[(int64_t)k * g.ld + i];
     }
     __syncthreads();
-    FusedArgs fa{};
-    fa.mode = FUSED_REMOVE;
-    fa.k = k;
-    fa.col1 = bg.colu;
-    fa.row1 = bg.rowu;
-    fa.row2 = nullptr;
-    batch_mask_recompute<U>(g, bg, fa, 0, stage, wlists);
-    // drop k from every index list (lanes screen 64 lists at a time: k can
-    // be listed in y only if its edge is no heavier than y's last entry);
-    // k's own list empties
+}
+
+// Row marks cleared, k dropped from every index list, tombstone, short lists
+// rebuilt, ranks shifted.
+__device__ __forceinline__ void remove_epilogue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
+                                uint32_t *stage) {
+    const int tid = threadIdx.x;
+    const int n = g.n_slots;
+    const int32_t k = it.a, rank = it.b, n_live = it.c;
+    clear_row_marks(g, bg);
+    // lanes screen 64 lists at a time: k can be listed in y only if its edge
+    // is no heavier than y's last entry
     for (int32_t y0 = (tid >> 6) * 64; y0 < n; y0 += BATCH_THREADS) {
         const int32_t y = y0 + lane_id();
         bool cand = false;
@@ -377,7 +548,6 @@ __device__ void batch_remove(const DevGraph &g, const BatchGraph &bg, const Batc
         }
     }
     __syncthreads();
-    // tombstone
     const int64_t ld = g.ld;
     for (int32_t s = tid; s < n; s += BATCH_THREADS) {
         g.D[(int64_t)k * ld + s] = (int32_t)INF;
@@ -401,83 +571,243 @@ __device__ void batch_remove(const DevGraph &g, const BatchGraph &bg, const Batc
     __syncthreads();
     const int nq = s_cnt;
     for (int q = 0; q < nq; ++q) batch_rebuild_if_short(g, bg.queue[q], ssh, stage);
-    // ranks after the removed one move down by one
     for (int32_t t = tid; t < n_live - 1; t += BATCH_THREADS) it.rank_dst[t] = it.rank_src[t < rank ? t : t + 1];
     __syncthreads();
 }
 
-template <int U>
-__device__ void batch_edge(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
-                           uint32_t *stage, int32_t *wlists) {
-    const int tid = threadIdx.x;
-    const int n = g.n_slots;
+// ---------------------------------------------------------------------------
+// edge update
+// ---------------------------------------------------------------------------
+
+// The decision (decrease / increase / nothing, on the device), the new
+// weight in A and the index lists, and the gathers the sweeps need.
+__device__ __forceinline__ void edge_prologue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it) {
     const int32_t su = it.a, sv = it.b, w = it.c;
-    if (tid < 64) edge_begin_wave(g, su, sv, w);
+    if (threadIdx.x < 64) edge_begin_wave(g, su, sv, w);
     __syncthreads();
-    const int32_t mode = g.ctl->edge_mode;
-    const uint32_t w_old = (uint32_t)g.ctl->w_old;
-    if (mode != EDGE_NOOP) {
-        for (int32_t i = tid; i < n; i += BATCH_THREADS) {
+    if (g.ctl->edge_mode != EDGE_NOOP) {
+        for (int32_t i = threadIdx.x; i < g.n_slots; i += BATCH_THREADS) {
             bg.colu[i] = g.D[(int64_t)i * g.ld + su];
             bg.colv[i] = g.D[(int64_t)i * g.ld + sv];
             bg.rowu[i] = g.D[(int64_t)su * g.ld + i];
             bg.rowv[i] = g.D[(int64_t)sv * g.ld + i];
         }
-        __syncthreads();
     }
-    if (mode == EDGE_DECREASE) {
-        // relaxation through the new edge: D[i][j] vs D[i][u] + w + D[v][j]
-        // (and D[i][v] + w + D[u][j] when undirected), rows filtered first
-        const bool und = g.undirected != 0;
-        const uint32_t wn = (uint32_t)w;
-        stage_rows(stage, g.P, n, bg.rowv, und ? bg.rowu : nullptr);
-        const uint32_t *SV = stage, *SU = stage + g.P;
-        stream_chunks<U>(
-            g, n,
-            [&](int32_t i) {
-                const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
-                return du + wn < dv || (und && dv + wn < du);
-            },
-            [&](int32_t i, int32_t c0, bool ok, uint4 d) {
-                if (!ok) return;
-                const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
-                const uint32_t x1 = du + wn < dv ? du + wn : INF;
-                const uint32_t x2 = und && dv + wn < du ? dv + wn : INF;
-                const uint4 rv = *reinterpret_cast<const uint4 *>(SV + c0);
-                uint4 ru = make_uint4(INF, INF, INF, INF);
-                if (und) ru = *reinterpret_cast<const uint4 *>(SU + c0);
-                const uint4 t = make_uint4(min(x1 + rv.x, x2 + ru.x), min(x1 + rv.y, x2 + ru.y),
-                                           min(x1 + rv.z, x2 + ru.z), min(x1 + rv.w, x2 + ru.w));
-                if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
-                    d.x = min(d.x, t.x);
-                    d.y = min(d.y, t.y);
-                    d.z = min(d.z, t.z);
-                    d.w = min(d.w, t.w);
-                    *reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0) = d;
+    __syncthreads();
+}
+
+// Relaxation through the lowered edge over rows [r0, r1): D[i][j] vs
+// D[i][u] + w + D[v][j] (and D[i][v] + w + D[u][j] when undirected), rows
+// that cannot change filtered first.  SV / SU: rows v and u (LDS or global).
+template <int U>
+__device__ __forceinline__ void dec_relax_rows(const DevGraph &g, const BatchGraph &bg, int32_t w, int32_t r0, int32_t r1,
+                               const uint32_t *SV, const uint32_t *SU) {
+    const bool und = g.undirected != 0;
+    const uint32_t wn = (uint32_t)w;
+    const int n = g.n_slots;
+    stream_chunks<U>(
+        g, n, r0, r1,
+        [&](int32_t i) {
+            const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
+            return du + wn < dv || (und && dv + wn < du);
+        },
+        [&](int32_t i, int32_t c0, bool ok, uint4 d) {
+            if (!ok) return;
+            const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
+            const uint32_t x1 = du + wn < dv ? du + wn : INF;
+            const uint32_t x2 = und && dv + wn < du ? dv + wn : INF;
+            const uint4 rv = vec4(SV, c0, n);
+            const uint4 ru = und ? vec4(SU, c0, n) : make_uint4(INF, INF, INF, INF);
+            store_min4(g, i, c0, d,
+                       make_uint4(min(x1 + rv.x, x2 + ru.x), min(x1 + rv.y, x2 + ru.y), min(x1 + rv.z, x2 + ru.z),
+                                  min(x1 + rv.w, x2 + ru.w)));
+        });
+}
+
+__device__ __forceinline__ void edge_epilogue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
+                              uint32_t *stage) {
+    if (g.ctl->edge_mode == EDGE_INCREASE) clear_row_marks(g, bg);
+    batch_rebuild_if_short(g, it.b, ssh, stage);
+    if (g.undirected) batch_rebuild_if_short(g, it.a, ssh, stage);
+    __syncthreads();
+}
+
+// One heavy row with the whole work-group: row i of D in LDS (cur, P words),
+// its flagged entries (from the flag words) set to INF (and column k of a
+// removal), Bellman-Ford with 64 groups of 4 lanes reading cur from LDS,
+// exhaustive scans (marked in need: nw LDS words) by the whole work-group,
+// then the flagged entries written back.
+__device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa, int32_t i,
+                                                uint32_t *cur, uint32_t *need, int *s_flag, uint32_t *red) {
+    const int tid = threadIdx.x, grp = tid >> 2, l4 = tid & 3;
+    const int n = g.n_slots;
+    const int nw = (n + 31) / 32;
+    const int64_t nwp = (g.P + 31) / 32;
+    const int lim = g.lim;
+    const int32_t *Min = in_matrix(g);
+    int32_t *Drow = g.D + (int64_t)i * g.ld;
+    const uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
+    for (int32_t c = tid * 4; c < n; c += BATCH_THREADS * 4)
+        *reinterpret_cast<uint4 *>(cur + c) = *reinterpret_cast<const uint4 *>(Drow + c);
+    __syncthreads();
+    for (int w = tid; w < nw; w += BATCH_THREADS) {
+        uint32_t bits = fw[w];
+        while (bits) {
+            cur[w * 32 + __ffs(bits) - 1] = INF;
+            bits &= bits - 1;
+        }
+    }
+    if (fa.mode == FUSED_REMOVE && tid == 0) cur[fa.k] = INF;
+    for (;;) {
+        for (;;) {
+            __syncthreads();
+            if (tid == 0) *s_flag = 0;
+            __syncthreads();
+            bool changed = false;
+            for (int w = grp; w < nw; w += BATCH_THREADS / 4) {
+                uint32_t bits = fw[w];
+                while (bits) {
+                    const int32_t y = w * 32 + __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    uint32_t best = cur[y];
+                    const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
+                    for (int c0 = 0; c0 < lim; c0 += 32) {
+                        const int e0 = c0 + 4 * l4, e1 = e0 + 16;
+                        const int4 none = make_int4(0, (int)INF, 0, (int)INF);
+                        int4 pa = none, pb = none, pc = none, pd = none;
+                        if (e0 < lim) pa = L4[e0 >> 1];
+                        if (e0 + 2 < lim) pb = L4[(e0 >> 1) + 1];
+                        if (e1 < lim) pc = L4[e1 >> 1];
+                        if (e1 + 2 < lim) pd = L4[(e1 >> 1) + 1];
+                        if (e0 + 1 >= lim) pa.w = (int)INF;
+                        if (e0 + 3 >= lim) pb.w = (int)INF;
+                        if (e1 + 1 >= lim) pc.w = (int)INF;
+                        if (e1 + 3 >= lim) pd.w = (int)INF;
+                        uint32_t cm = INF;
+                        if ((uint32_t)pa.y < best) cm = min(cm, cur[pa.x] + (uint32_t)pa.y);
+                        if ((uint32_t)pa.w < best) cm = min(cm, cur[pa.z] + (uint32_t)pa.w);
+                        if ((uint32_t)pb.y < best) cm = min(cm, cur[pb.x] + (uint32_t)pb.y);
+                        if ((uint32_t)pb.w < best) cm = min(cm, cur[pb.z] + (uint32_t)pb.w);
+                        if ((uint32_t)pc.y < best) cm = min(cm, cur[pc.x] + (uint32_t)pc.y);
+                        if ((uint32_t)pc.w < best) cm = min(cm, cur[pc.z] + (uint32_t)pc.w);
+                        if ((uint32_t)pd.y < best) cm = min(cm, cur[pd.x] + (uint32_t)pd.y);
+                        if ((uint32_t)pd.w < best) cm = min(cm, cur[pd.z] + (uint32_t)pd.w);
+                        cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
+                        cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
+                        best = min(best, cm);
+                        const uint32_t wlast = (uint32_t)__shfl(pd.w, 3, 4);
+                        if (wlast >= best) break;
+                    }
+                    if (l4 == 0 && best < cur[y]) {
+                        cur[y] = best;
+                        changed = true;
+                    }
                 }
-            });
+            }
+            if (changed) *s_flag = 1;
+            __syncthreads();
+            if (*s_flag == 0) break;
+        }
+        for (int w = tid; w < nw; w += BATCH_THREADS) need[w] = 0;
         __syncthreads();
-    } else if (mode == EDGE_INCREASE) {
-        FusedArgs fa{};
-        fa.mode = FUSED_INCREASE;
-        fa.k = -1;
-        fa.col1 = bg.colu;
-        fa.col2 = bg.colv;
-        fa.row1 = bg.rowv;
-        fa.row2 = g.undirected ? bg.rowu : nullptr;
-        batch_mask_recompute<U>(g, bg, fa, w_old, stage, wlists);
+        for (int w = grp; w < nw; w += BATCH_THREADS / 4) {
+            uint32_t bits = fw[w], mark = 0;
+            while (bits) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                const int32_t y = w * 32 + b;
+                uint32_t beta_eff = (uint32_t)g.nin_beta[y];
+                if (lim < NIN_L) beta_eff = min(beta_eff, (uint32_t)g.nin[(int64_t)y * NIN_L + lim].y);
+                if (cur[y] > beta_eff) mark |= 1u << b;
+            }
+            if (l4 == 0 && mark) need[w] = mark;
+        }
+        __syncthreads();
+        if (tid == 0) *s_flag = 0;
+        for (int w = 0; w < nw; ++w) {  // block-uniform: every thread reads the same LDS word
+            uint32_t bits = need[w];
+            while (bits) {
+                const int32_t y = w * 32 + __ffs(bits) - 1;
+                bits &= bits - 1;
+                const int32_t *col = Min + (int64_t)y * g.ld;
+                uint32_t best = INF;
+                for (int32_t x = tid; x < n; x += BATCH_THREADS) best = min(best, cur[x] + (uint32_t)col[x]);
+                best = block_min<BATCH_THREADS>(best, red);
+                if (tid == 0 && best < cur[y]) {
+                    cur[y] = best;
+                    *s_flag = 1;
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        if (*s_flag == 0) break;
     }
-    batch_rebuild_if_short(g, sv, ssh, stage);
-    if (g.undirected) batch_rebuild_if_short(g, su, ssh, stage);
+    for (int w = tid; w < nw; w += BATCH_THREADS) {
+        uint32_t bits = fw[w];
+        while (bits) {
+            const int32_t y = w * 32 + __ffs(bits) - 1;
+            bits &= bits - 1;
+            Drow[y] = (int32_t)cur[y];
+        }
+    }
     __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// the persistent kernel
+// schedule 1: work queue (one work-group per graph, all phases)
 // ---------------------------------------------------------------------------
+
+template <int U>
+__device__ __forceinline__ void run_item_alone(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
+                               uint32_t *stage, int32_t *wlists) {
+    const int n = g.n_slots;
+    switch (it.op) {
+    case BOP_ADD:
+        add_prologue(g, bg, it, ssh, stage);
+        stage_rows(stage, g.P, n, bg.vout, nullptr);
+        add_relax_rows<U>(g, bg, 0, n, stage);
+        __syncthreads();
+        add_epilogue(g, bg, it);
+        break;
+    case BOP_REMOVE: {
+        remove_prologue(g, bg, it);
+        const FusedArgs fa = remove_args(bg, it);
+        stage_rows(stage, g.P, n, fa.row1, nullptr);
+        detect_rows<U>(g, bg, fa, 0, 0, n, stage, stage + g.P);
+        __syncthreads();
+        recompute_rows(g, bg, fa, 0, n, wlists, bg.scratch, stage);
+        __syncthreads();
+        remove_epilogue(g, bg, it, ssh, stage);
+        break;
+    }
+    case BOP_EDGE: {
+        edge_prologue(g, bg, it);
+        const int32_t mode = g.ctl->edge_mode;
+        if (mode == EDGE_DECREASE) {
+            stage_rows(stage, g.P, n, bg.rowv, g.undirected ? bg.rowu : nullptr);
+            dec_relax_rows<U>(g, bg, it.c, 0, n, stage, stage + g.P);
+            __syncthreads();
+        } else if (mode == EDGE_INCREASE) {
+            const FusedArgs fa = increase_args(g, bg);
+            stage_rows(stage, g.P, n, fa.row1, fa.row2);
+            detect_rows<U>(g, bg, fa, (uint32_t)g.ctl->w_old, 0, n, stage, stage + g.P);
+            __syncthreads();
+            recompute_rows(g, bg, fa, 0, n, wlists, bg.scratch, stage);
+            __syncthreads();
+        }
+        edge_epilogue(g, bg, it, ssh, stage);
+        break;
+    }
+    case BOP_QUERY: query_block(g, it.a, it.b, it.out, bg.qscratch); break;
+    default: break;
+    }
+    __syncthreads();
+}
+
 template <int U>
 __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch(BatchHeader *hdr, const BatchGraph *graphs,
-                                                         const int32_t *order, const BatchItem *items) {
+                                                            const int32_t *order, const BatchItem *items) {
     extern __shared__ uint32_t stage[];  // 2 P words of row vectors / select staging, then 4 wave lists of 2 ROW_CAP
     __shared__ SelectShared ssh;
     __shared__ int32_t s_next;
@@ -495,35 +825,234 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch(BatchHeader *hdr, co
             const BatchItem it = items[t];
             DevGraph g = bg.g;
             g.n_slots = it.n_slots;
-            if (threadIdx.x == 0) {
-                g.ctl->flagged = 0;
-                g.ctl->rows = 0;
-                g.ctl->full_scans = 0;
-                g.ctl->sweeps = 0;
-            }
-            __syncthreads();
-            switch (it.op) {
-            case BOP_ADD: batch_add<U>(g, bg, it, ssh, stage); break;
-            case BOP_REMOVE: batch_remove<U>(g, bg, it, ssh, stage, wlists); break;
-            case BOP_EDGE: batch_edge<U>(g, bg, it, ssh, stage, wlists); break;
-            case BOP_QUERY: query_block(g, it.a, it.b, it.out, bg.qscratch); break;
-            default: break;
-            }
-            __syncthreads();
+            run_item_alone<U>(g, bg, it, ssh, stage, wlists);
         }
         if (threadIdx.x == 0) hdr->times[2 * bg.index + 1] = wall_clock64();
     }
 }
 
+// ---------------------------------------------------------------------------
+// schedule 2: lockstep (whole grid on every step's row sweeps)
+// ---------------------------------------------------------------------------
+
+constexpr long BARRIER_SPIN_LIMIT = 1L << 21;  // about a second of polling, then a reported timeout
+
+// Grid barrier in two levels (8 groups of work-groups, then the groups), with
+// release/acquire ordering at device scope.  Every wait is bounded: a timeout
+// sets hdr->err and lets the work-group go on, so the launch always ends.
+__device__ __forceinline__ void grid_barrier(BatchHeader *hdr) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned nb = gridDim.x;
+        const unsigned grp = blockIdx.x & 7u;
+        const unsigned ngroups = nb < 8 ? nb : 8;
+        const unsigned gsize = nb / 8 + (grp < nb % 8 ? 1u : 0u);
+        __threadfence();
+        const unsigned gen = __hip_atomic_load(&hdr->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned a = __hip_atomic_fetch_add(&hdr->bar_group[grp * 32], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (a == gsize - 1) {
+            __hip_atomic_store(&hdr->bar_group[grp * 32], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned b = __hip_atomic_fetch_add(&hdr->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (b == ngroups - 1) {
+                __hip_atomic_store(&hdr->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&hdr->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        // poll with relaxed loads (an acquire per poll would invalidate the
+        // caches the still-working work-groups rely on), then one acquire
+        long it = 0;
+        while (__hip_atomic_load(&hdr->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen &&
+               it < BARRIER_SPIN_LIMIT) {
+            __builtin_amdgcn_s_sleep(2);
+            ++it;
+        }
+        if (it >= BARRIER_SPIN_LIMIT) atomicOr(&hdr->err, 1);
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Chunk c of a step's sweep table -> graph (base: prefix of chunk counts).
+__device__ inline int32_t chunk_graph(const int32_t *base, int32_t num_graphs, int32_t c) {
+    int32_t lo = 0, hi = num_graphs;  // base[lo] <= c < base[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= c) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int U>
+__global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs,
+                                                                     const BatchItem *items, const int32_t *tables) {
+    extern __shared__ uint32_t stage[];  // P words of select staging, then 4 wave lists of 2 ROW_CAP
+    __shared__ SelectShared ssh;
+    __shared__ int32_t s_claim, s_found_g, s_found_j;
+    __shared__ int s_flag;
+    const int32_t G = hdr->num_graphs;
+    const int32_t steps = hdr->steps;
+    const int32_t P_max = hdr->p_max;
+    int32_t *wlists = reinterpret_cast<int32_t *>(stage) + P_max;
+    for (int32_t s = 0; s <= steps; ++s) {
+        // A: per graph, the epilogue of item s-1 and the prologue of item s
+        for (int32_t gi = blockIdx.x; gi < G; gi += gridDim.x) {
+            const BatchGraph &bg = graphs[gi];
+            if (s == 0 && threadIdx.x == 0) hdr->times[2 * bg.index] = wall_clock64();
+            const int32_t cnt = bg.item_end - bg.item_begin;
+            if (s >= 1 && s - 1 < cnt) {
+                const BatchItem it = items[bg.item_begin + s - 1];
+                DevGraph g = bg.g;
+                g.n_slots = it.n_slots;
+                if (it.op == BOP_ADD) add_epilogue(g, bg, it);
+                else if (it.op == BOP_REMOVE) remove_epilogue(g, bg, it, ssh, stage);
+                else if (it.op == BOP_EDGE) edge_epilogue(g, bg, it, ssh, stage);
+                if (s == cnt && threadIdx.x == 0) hdr->times[2 * bg.index + 1] = wall_clock64();
+            }
+            if (s < cnt) {
+                const BatchItem it = items[bg.item_begin + s];
+                DevGraph g = bg.g;
+                g.n_slots = it.n_slots;
+                if (it.op == BOP_ADD) add_prologue(g, bg, it, ssh, stage);
+                else if (it.op == BOP_REMOVE) remove_prologue(g, bg, it);
+                else if (it.op == BOP_EDGE) edge_prologue(g, bg, it);
+                else if (it.op == BOP_QUERY) query_block(g, it.a, it.b, it.out, bg.qscratch);
+                if (s == cnt - 1 && it.op == BOP_QUERY && threadIdx.x == 0)
+                    hdr->times[2 * bg.index + 1] = wall_clock64();
+            }
+            __syncthreads();
+        }
+        if (s == steps) break;
+        grid_barrier(hdr);
+        if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s < BATCH_PHASE_STAMPS) hdr->phase_ts[3 * s] = wall_clock64();
+        // B: row sweeps (relaxation or mask) of every graph, spread over the grid
+        const int32_t *baseB = tables + (int64_t)s * 2 * (G + 1);
+        for (int32_t c = blockIdx.x; c < baseB[G]; c += gridDim.x) {
+            const int32_t gi = chunk_graph(baseB, G, c);
+            const BatchGraph &bg = graphs[gi];
+            const BatchItem it = items[bg.item_begin + s];
+            DevGraph g = bg.g;
+            g.n_slots = it.n_slots;
+            const int32_t rpc = batch_rows_per_chunk(it.n_slots);
+            const int32_t r0 = (c - baseB[gi]) * rpc, r1 = min(r0 + rpc, it.n_slots);
+            if (it.op == BOP_ADD) {
+                add_relax_rows<U>(g, bg, r0, r1, reinterpret_cast<const uint32_t *>(bg.vout));
+            } else if (it.op == BOP_REMOVE) {
+                const FusedArgs fa = remove_args(bg, it);
+                detect_rows<U>(g, bg, fa, 0, r0, r1, reinterpret_cast<const uint32_t *>(fa.row1), nullptr);
+            } else if (it.op == BOP_EDGE) {
+                const int32_t mode = g.ctl->edge_mode;
+                if (mode == EDGE_DECREASE) {
+                    dec_relax_rows<U>(g, bg, it.c, r0, r1, reinterpret_cast<const uint32_t *>(bg.rowv),
+                                      reinterpret_cast<const uint32_t *>(bg.rowu));
+                } else if (mode == EDGE_INCREASE) {
+                    const FusedArgs fa = increase_args(g, bg);
+                    detect_rows<U>(g, bg, fa, (uint32_t)g.ctl->w_old, r0, r1,
+                                   reinterpret_cast<const uint32_t *>(fa.row1),
+                                   reinterpret_cast<const uint32_t *>(fa.row2));
+                }
+            }
+            __syncthreads();
+        }
+        // C: recompute of the flagged rows (removal, edge increase)
+        const int32_t *baseC = baseB + (G + 1);
+        if (baseC[G] > 0) {
+            grid_barrier(hdr);
+            if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s + 1 < BATCH_PHASE_STAMPS)
+                hdr->phase_ts[3 * s + 1] = wall_clock64();
+            for (int32_t c = blockIdx.x; c < baseC[G]; c += gridDim.x) {
+                const int32_t gi = chunk_graph(baseC, G, c);
+                const BatchGraph &bg = graphs[gi];
+                const BatchItem it = items[bg.item_begin + s];
+                DevGraph g = bg.g;
+                g.n_slots = it.n_slots;
+                const int32_t r0 = (c - baseC[gi]) * BATCH_RECOMPUTE_ROWS;
+                const int32_t r1 = min(r0 + BATCH_RECOMPUTE_ROWS, it.n_slots);
+                if (it.op == BOP_REMOVE) {
+                    recompute_rows(g, bg, remove_args(bg, it), r0, r1, wlists, nullptr, stage, true);
+                } else if (it.op == BOP_EDGE && g.ctl->edge_mode == EDGE_INCREASE) {
+                    recompute_rows(g, bg, increase_args(g, bg), r0, r1, wlists, nullptr, stage, true);
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0 && s < BATCH_PHASE_STAMPS)
+                atomicMax(reinterpret_cast<unsigned long long *>(&hdr->work_ts[s]), (unsigned long long)wall_clock64());
+            grid_barrier(hdr);
+            // C2: the deferred heavy rows, one work-group each, taken from a
+            // shared counter; a claim maps to (graph, row) through a
+            // block-wide scan of the graphs' heavy-row counts
+            for (;;) {
+                if (threadIdx.x == 0) s_claim = atomicAdd(&hdr->heavy_claim, 1);
+                __syncthreads();
+                const int32_t t = s_claim;
+                int32_t found_g = -1, found_j = 0, base = 0;
+                for (int32_t g0 = 0; g0 < G && found_g < 0; g0 += BATCH_THREADS) {
+                    const int32_t gi = g0 + threadIdx.x;
+                    int32_t hc = 0;
+                    if (gi < G) {
+                        const BatchGraph &bq = graphs[gi];
+                        const int32_t cnt = bq.item_end - bq.item_begin;
+                        if (s < cnt) {
+                            const int32_t op = items[bq.item_begin + s].op;
+                            if (op == BOP_REMOVE || (op == BOP_EDGE && bq.g.ctl->edge_mode == EDGE_INCREASE))
+                                hc = bq.g.ctl->heavy_count;
+                        }
+                    }
+                    int tot;
+                    const int off = block_exscan<BATCH_THREADS>(hc, ssh.red, &tot);
+                    if (t >= base + off && t < base + off + hc) {
+                        s_found_g = gi;
+                        s_found_j = t - base - off;
+                    }
+                    __syncthreads();
+                    if (t < base + tot) {
+                        found_g = s_found_g;
+                        found_j = s_found_j;
+                    }
+                    base += tot;
+                    __syncthreads();
+                }
+                if (found_g < 0) break;  // block-uniform: every claim beyond the total ends the pass
+                const BatchGraph &bg = graphs[found_g];
+                const BatchItem it = items[bg.item_begin + s];
+                DevGraph g = bg.g;
+                g.n_slots = it.n_slots;
+                const FusedArgs fa = it.op == BOP_REMOVE ? remove_args(bg, it) : increase_args(g, bg);
+                heavy_row_block(g, bg, fa, bg.heavy_rows[found_j], stage, reinterpret_cast<uint32_t *>(wlists),
+                                &s_flag, ssh.red);
+            }
+        }
+        grid_barrier(hdr);
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(&hdr->heavy_claim, 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s + 2 < BATCH_PHASE_STAMPS)
+            hdr->phase_ts[3 * s + 2] = wall_clock64();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+
 size_t batch_lds_bytes(int32_t P_max) { return (2 * (size_t)P_max + 4 * 2 * ROW_CAP) * sizeof(uint32_t); }
+
+size_t batch_lockstep_lds_bytes(int32_t P_max) { return ((size_t)P_max + 4 * 2 * ROW_CAP) * sizeof(uint32_t); }
 
 hipError_t configure_batch() {
     static hipError_t status = hipErrorNotReady;
     if (status != hipErrorNotReady) return status;
     const int lds = (int)batch_lds_bytes(BATCH_MAX_CAPACITY);
+    const int lds2 = (int)batch_lockstep_lds_bytes(BATCH_MAX_CAPACITY);
     status = hipFuncSetAttribute((const void *)k_batch<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (status == hipSuccess)
         status = hipFuncSetAttribute((const void *)k_batch<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (status == hipSuccess)
+        status = hipFuncSetAttribute((const void *)k_batch_lockstep<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     lds2);
+    if (status == hipSuccess)
+        status = hipFuncSetAttribute((const void *)k_batch_lockstep<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     lds2);
     (void)hipGetLastError();
     return status;
 }
@@ -536,6 +1065,33 @@ hipError_t launch_batch(BatchHeader *hdr, const BatchGraph *graphs, const int32_
     if (variant == 0) k_batch<4><<<grid, BATCH_THREADS, lds, s>>>(hdr, graphs, order, items);
     else k_batch<8><<<grid, BATCH_THREADS, lds, s>>>(hdr, graphs, order, items);
     return hipGetLastError();
+}
+
+hipError_t lockstep_grid(int32_t P_max, int32_t variant, int32_t *grid) {
+    const size_t lds = batch_lockstep_lds_bytes(P_max);
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, variant == 2 ? (const void *)k_batch_lockstep<4> : (const void *)k_batch_lockstep<8>,
+        BATCH_THREADS, lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *grid = per_cu * cus;
+    return *grid > 0 ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs, const BatchItem *items,
+                                 const int32_t *tables, int32_t P_max, int32_t grid, int32_t variant, hipStream_t s) {
+    if (P_max > BATCH_MAX_CAPACITY || grid < 1) return hipErrorInvalidValue;
+    launch_fill(reinterpret_cast<int32_t *>(&hdr->bar_count), 1, 0, s);
+    launch_fill(reinterpret_cast<int32_t *>(hdr->bar_group), 8 * 32, 0, s);
+    launch_fill(&hdr->err, 1, 0, s);
+    launch_fill(&hdr->heavy_claim, 1, 0, s);
+    launch_fill(reinterpret_cast<int32_t *>(hdr->work_ts), 2 * BATCH_PHASE_STAMPS, 0, s);
+    const size_t lds = batch_lockstep_lds_bytes(P_max);
+    void *args[] = {(void *)&hdr, (void *)&graphs, (void *)&items, (void *)&tables};
+    const void *fn = variant == 2 ? (const void *)k_batch_lockstep<4> : (const void *)k_batch_lockstep<8>;
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BATCH_THREADS), args, (unsigned)lds, s);
 }
 
 }  // namespace apsp

@@ -18,7 +18,7 @@ using namespace apsp_host;
 namespace {
 
 struct BatchLayout {
-    size_t graphs, order, items, times, total;
+    size_t graphs, order, items, times, tables, total;
 };
 
 BatchLayout batch_layout(int32_t max_graphs, int32_t max_items) {
@@ -32,6 +32,8 @@ BatchLayout batch_layout(int32_t max_graphs, int32_t max_items) {
     off = align256(off + (size_t)max_items * sizeof(BatchItem));
     L.times = off;
     off = align256(off + (size_t)max_graphs * 2 * sizeof(long long));
+    L.tables = off;  // lockstep: per step, sweep and recompute chunk prefixes over the graphs
+    off = align256(off + (size_t)max_items * 2 * ((size_t)max_graphs + 1) * sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -88,8 +90,9 @@ struct apsp_batch {
     int32_t n_cu = 0;
     int32_t clock_khz = 0;
     long long *times_h = nullptr;  // pinned
+    int32_t *err_h = nullptr;      // pinned
     hipStream_t last_stream = nullptr;
-    int32_t last_num_graphs = 0;
+    int32_t last_num_graphs = 0, last_steps = 0;
     std::vector<ExecKey> execs;
     // per-run scratch (host)
     std::vector<int32_t> count, begin, fill, active;
@@ -100,17 +103,28 @@ struct apsp_batch {
 namespace {
 
 apsp_status launch(apsp_batch *b, int32_t n_active, int32_t P_max, hipStream_t s) {
+    const bool lockstep = b->variant >= 2;
     int32_t grid = b->grid > 0 ? b->grid : std::max(1, std::min(n_active, 2 * b->n_cu));
+    if (lockstep) {
+        int32_t cap = 0;
+        if (!hip_ok(lockstep_grid(P_max, b->variant, &cap), "lockstep occupancy")) return APSP_E_DEVICE;
+        grid = b->grid > 0 ? std::min(b->grid, cap) : cap;
+    }
     auto *hdr = reinterpret_cast<BatchHeader *>(b->ws);
     auto *graphs = reinterpret_cast<const BatchGraph *>(b->ws + b->L.graphs);
     auto *order = reinterpret_cast<const int32_t *>(b->ws + b->L.order);
     auto *items = reinterpret_cast<const BatchItem *>(b->ws + b->L.items);
+    auto *tables = reinterpret_cast<const int32_t *>(b->ws + b->L.tables);
+    auto go = [&](hipStream_t st) {
+        return lockstep ? launch_batch_lockstep(hdr, graphs, items, tables, P_max, grid, b->variant, st)
+                        : launch_batch(hdr, graphs, order, items, P_max, grid, b->variant, st);
+    };
     if (!b->use_graph) {
-        hipError_t e = launch_batch(hdr, graphs, order, items, P_max, grid, b->variant, s);
+        hipError_t e = go(s);
         if (e != hipSuccess) return fail(APSP_E_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
         return APSP_OK;
     }
-    const size_t lds = batch_lds_bytes(P_max);
+    const size_t lds = lockstep ? batch_lockstep_lds_bytes(P_max) : batch_lds_bytes(P_max);
     for (auto &x : b->execs) {
         if (x.grid == grid && x.variant == b->variant && x.lds == lds) {
             if (!hip_ok(hipGraphLaunch(x.exec, s), "graph launch")) return APSP_E_DEVICE;
@@ -120,7 +134,7 @@ apsp_status launch(apsp_batch *b, int32_t n_active, int32_t P_max, hipStream_t s
     ExecKey k{grid, b->variant, lds, nullptr, nullptr};
     hipStream_t cs = b->cap_stream;
     if (!hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) return APSP_E_DEVICE;
-    hipError_t e = launch_batch(hdr, graphs, order, items, P_max, grid, b->variant, cs);
+    hipError_t e = go(cs);
     hipError_t e2 = hipStreamEndCapture(cs, &k.graph);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (k.graph) (void)hipGraphDestroy(k.graph);
@@ -175,6 +189,7 @@ apsp_status apsp_batch_create(void *ws_dev, size_t ws_bytes, int32_t max_graphs,
         !hip_ok(hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev), "device attribute") ||
         !hip_ok(hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev), "device attribute") ||
         !hip_ok(hipHostMalloc((void **)&b->times_h, (size_t)max_graphs * 2 * sizeof(long long), 0), "pinned alloc") ||
+        !hip_ok(hipHostMalloc((void **)&b->err_h, sizeof(int32_t), 0), "pinned alloc") ||
         !hip_ok(configure_batch(), "configuring the batched kernel")) {
         apsp_batch_destroy(b);
         return APSP_E_DEVICE;
@@ -197,6 +212,7 @@ apsp_status apsp_batch_destroy(apsp_batch *b) {
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->stage) (void)hipHostFree(b->stage);
     if (b->times_h) (void)hipHostFree(b->times_h);
+    if (b->err_h) (void)hipHostFree(b->err_h);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return APSP_OK;
@@ -204,7 +220,7 @@ apsp_status apsp_batch_destroy(apsp_batch *b) {
 
 apsp_status apsp_batch_set_config(apsp_batch *b, int32_t grid, int32_t order, int32_t variant, int32_t use_graph) {
     if (!b) return fail(APSP_E_INVALID, "apsp_batch_set_config: NULL batch");
-    if (grid < 0 || order < 0 || order > 1 || variant < 0 || variant > 1 || use_graph < 0 || use_graph > 1)
+    if (grid < 0 || order < 0 || order > 1 || variant < 0 || variant > 3 || use_graph < 0 || use_graph > 1)
         return fail(APSP_E_INVALID, "apsp_batch_set_config: value out of range");
     b->grid = grid;
     b->order = order;
@@ -356,6 +372,7 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
         bg.queue = g->nin_queue;
         bg.flag_bits = g->flag_bits;
         bg.row_bits = g->row_bits;
+        bg.heavy_rows = g->heavy_rows;
         bg.item_begin = b->begin[i];
         bg.item_end = b->begin[i + 1];
         bg.index = i;
@@ -372,6 +389,38 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
     hdr->num_graphs = n_active;
     hdr->counter = 0;
     hdr->times = reinterpret_cast<long long *>(b->ws + b->L.times);
+    hdr->p_max = P_max;
+    hdr->steps = 0;
+    size_t table_words = 0;
+    if (b->variant >= 2) {
+        // lockstep: step s applies item s of every graph; per step, the chunk
+        // prefixes of the sweep phase (every kind but a query) and of the
+        // recompute phase (removals and edge updates)
+        int32_t steps = 0;
+        for (int32_t i : b->active) steps = std::max(steps, b->count[i]);
+        auto *tab = reinterpret_cast<int32_t *>(b->stage + b->L.tables);
+        const int32_t G1 = n_active + 1;
+        for (int32_t st = 0; st < steps; ++st) {
+            int32_t *tb = tab + (size_t)st * 2 * G1, *tc = tb + G1;
+            tb[0] = tc[0] = 0;
+            for (int32_t ai = 0; ai < n_active; ++ai) {
+                const int32_t i = b->active[ai];
+                int32_t cb = 0, cc = 0;
+                if (st < b->count[i]) {
+                    const BatchItem &bi = bitems[b->begin[i] + st];
+                    const int32_t rpc = batch_rows_per_chunk(bi.n_slots);
+                    if (bi.op != BOP_QUERY) cb = (bi.n_slots + rpc - 1) / rpc;
+                    if (bi.op == BOP_REMOVE || bi.op == BOP_EDGE)
+                        cc = (bi.n_slots + BATCH_RECOMPUTE_ROWS - 1) / BATCH_RECOMPUTE_ROWS;
+                }
+                tb[ai + 1] = tb[ai] + cb;
+                tc[ai + 1] = tc[ai] + cc;
+            }
+        }
+        hdr->steps = steps;
+        b->last_steps = steps;
+        table_words = (size_t)steps * 2 * G1;
+    }
     // order the batch after earlier work of each graph on its own stream
     std::vector<hipStream_t> others;
     for (int32_t i : b->active)
@@ -388,6 +437,9 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
             return undo_all(log), APSP_E_DEVICE;
     const size_t bytes = b->L.items + (size_t)num_items * sizeof(BatchItem);
     if (!hip_ok(hipMemcpyAsync(b->ws, b->stage, bytes, hipMemcpyHostToDevice, s), "batch upload") ||
+        (table_words && !hip_ok(hipMemcpyAsync(b->ws + b->L.tables, b->stage + b->L.tables,
+                                               table_words * sizeof(int32_t), hipMemcpyHostToDevice, s),
+                                "batch upload")) ||
         !hip_ok(hipEventRecord(b->staged, s), "event record"))
         return undo_all(log), APSP_E_DEVICE;
     b->stage_busy = true;
@@ -436,6 +488,50 @@ apsp_status apsp_batch_graph_times(apsp_batch *b, double *start_us, double *end_
         start_us[i] = ran[i] ? (double)(b->times_h[2 * i] - t0) * us_per_tick : -1.0;
         end_us[i] = ran[i] ? (double)(b->times_h[2 * i + 1] - t0) * us_per_tick : -1.0;
     }
+    return APSP_OK;
+}
+
+apsp_status apsp_batch_status(apsp_batch *b) {
+    if (!b) return fail(APSP_E_INVALID, "apsp_batch_status: NULL batch");
+    if (b->last_num_graphs == 0) return APSP_OK;
+    auto *hdr = reinterpret_cast<BatchHeader *>(b->ws);
+    if (!hip_ok(hipMemcpyAsync(b->err_h, &hdr->err, sizeof(int32_t), hipMemcpyDeviceToHost, b->last_stream), "copy") ||
+        !hip_ok(hipStreamSynchronize(b->last_stream), "stream sync"))
+        return APSP_E_DEVICE;
+    if (b->variant >= 2 && *b->err_h)
+        return fail(APSP_E_DEVICE, "apsp_batch_status: a grid barrier of the lockstep launch timed out; the "
+                                   "batch's graphs are in an undefined state");
+    return APSP_OK;
+}
+
+apsp_status apsp_batch_phase_times(apsp_batch *b, double *us, int32_t cap, int32_t *count) {
+    if (!b || !count || (cap > 0 && !us)) return fail(APSP_E_INVALID, "apsp_batch_phase_times: bad argument");
+    *count = 0;
+    if (b->variant < 2 || b->last_num_graphs == 0) return APSP_OK;
+    auto *hdr = reinterpret_cast<BatchHeader *>(b->ws);
+    std::vector<long long> ts(BATCH_PHASE_STAMPS + 2);
+    long long *stamps = ts.data();
+    if (!hip_ok(hipMemcpyAsync(stamps, hdr->phase_ts, BATCH_PHASE_STAMPS * sizeof(long long), hipMemcpyDeviceToHost,
+                               b->last_stream),
+                "copy") ||
+        !hip_ok(hipMemcpyAsync(b->times_h, b->ws + b->L.times, 2 * sizeof(long long), hipMemcpyDeviceToHost,
+                               b->last_stream),
+                "copy") ||
+        !hip_ok(hipStreamSynchronize(b->last_stream), "stream sync"))
+        return APSP_E_DEVICE;
+    std::vector<long long> work(BATCH_PHASE_STAMPS);
+    if (!hip_ok(hipMemcpy(work.data(), hdr->work_ts, BATCH_PHASE_STAMPS * sizeof(long long), hipMemcpyDeviceToHost),
+                "copy"))
+        return APSP_E_DEVICE;
+    const int32_t n = std::min(cap, std::min(3 * b->last_steps, BATCH_PHASE_STAMPS));
+    const double us_per_tick = 1e3 / (double)std::max(1, b->clock_khz);
+    long long t0 = b->times_h[0];  // start of the first graph
+    for (int32_t k = 0; k < n; ++k) us[k] = (double)(stamps[k] - t0) * us_per_tick;
+    // diagnostics: the latest end of recompute work of step s goes after the
+    // phase ends, when there is room
+    for (int32_t s2 = 0; s2 < b->last_steps && n + s2 < cap && s2 < BATCH_PHASE_STAMPS; ++s2)
+        us[n + s2] = work[s2] ? (double)(work[s2] - t0) * us_per_tick : 0.0;
+    *count = std::min(cap, n + std::min(b->last_steps, BATCH_PHASE_STAMPS));
     return APSP_OK;
 }
 

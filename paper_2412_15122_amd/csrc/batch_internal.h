@@ -35,6 +35,7 @@ struct BatchGraph {
     int32_t *qscratch;  // 4 P: query candidates
     int32_t *queue;     // P: index lists to rebuild
     uint32_t *flag_bits, *row_bits;
+    int32_t *heavy_rows;  // P: lockstep rows deferred to the one-work-group-per-row pass
     int32_t item_begin, item_end;
     int32_t index;      // position in the caller's graphs array
     int32_t pad;
@@ -42,18 +43,46 @@ struct BatchGraph {
 
 struct BatchHeader {
     int32_t num_graphs;
-    int32_t counter;     // next position of `order` to take; cleared before each launch
+    int32_t counter;     // work queue: next position of `order` to take; cleared before each launch
     long long *times;    // [2 * caller's graph count]: wall clock at start / end of each graph
-    int32_t pad[60];
+    int32_t steps;       // lockstep: items per graph at most
+    int32_t p_max;       // lockstep: largest pitch of the batch
+    int32_t err;         // lockstep: set when a grid barrier wait timed out
+    int32_t heavy_claim; // lockstep: next deferred heavy row to take (zero between steps)
+    int32_t pad0[24];
+    unsigned bar_count;  // lockstep grid barrier (each counter on its own 128-byte line)
+    unsigned pad1[31];
+    unsigned bar_gen;
+    unsigned pad2[31];
+    unsigned bar_group[8 * 32];
+    long long phase_ts[96];  // lockstep: wall clock after the barriers of the first 32 steps (diagnostics)
+    long long work_ts[96];   // lockstep: latest end of a work-group's recompute work, per step (diagnostics)
 };
+
+constexpr int BATCH_PHASE_STAMPS = 96;
+constexpr int BATCH_RECOMPUTE_ROWS = 16;  // rows per chunk of the lockstep recompute phase
 
 constexpr int BATCH_THREADS = 256;
 constexpr int BATCH_MAX_CAPACITY = APSP_BATCH_MAX_CAPACITY;  // keeps the select stage in LDS
 
+// Rows per chunk of a lockstep row sweep: about 64K entries (rows of n).
+__host__ __device__ inline int32_t batch_rows_per_chunk(int32_t n) {
+    const int32_t r = n > 0 ? (1 << 16) / n : 1;
+    return r < 1 ? 1 : r;
+}
+
 size_t batch_lds_bytes(int32_t P_max);
+size_t batch_lockstep_lds_bytes(int32_t P_max);
 hipError_t configure_batch();  // raise the dynamic-LDS limit once per process
 // Persistent launch of `grid` work-groups over the graphs listed in `order`.
 hipError_t launch_batch(BatchHeader *hdr, const BatchGraph *graphs, const int32_t *order, const BatchItem *items,
                         int32_t P_max, int32_t grid, int32_t variant, hipStream_t s);
+// Lockstep schedule (variants 2 and 3): the grid that is resident all at
+// once (cooperative launch), and the launch.  tables: per step, two prefix
+// arrays over the graphs (chunks of the sweep phase, chunks of the recompute
+// phase).
+hipError_t lockstep_grid(int32_t P_max, int32_t variant, int32_t *grid);
+hipError_t launch_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs, const BatchItem *items,
+                                 const int32_t *tables, int32_t P_max, int32_t grid, int32_t variant, hipStream_t s);
 
 }  // namespace apsp

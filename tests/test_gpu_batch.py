@@ -115,6 +115,7 @@ def run_and_compare(sizes, config, undirected_every=0, seed=7, check_oracle=True
     b = Batch(len(ga), len(items), **config)
     log("batch", config, "graphs", len(ga), "items", len(items))
     res = b.run(ga, items)
+    b.status()
     torch.cuda.synchronize()
     answers = replay_single(gb, items)
     for gi in range(len(ga)):
@@ -145,7 +146,19 @@ def test_batch_equals_single_calls_graph_replay_both_variants():
     run_and_compare(SIZES, {"use_graph": True, "variant": 0, "order": 1, "grid": 3}, undirected_every=2, seed=12)
 
 
-def test_replayed_graph_stays_correct_across_batches():
+def test_lockstep_schedule_equals_single_calls():
+    run_and_compare(SIZES, {"use_graph": False, "variant": 2}, undirected_every=3, seed=13)
+    run_and_compare(SIZES, {"use_graph": True, "variant": 3}, undirected_every=2, seed=14)
+
+
+def test_lockstep_with_a_tiny_grid_and_uneven_queues():
+    """Grid far below the chunk count (every work-group loops over chunks and
+    graphs) and graphs whose queues end at different steps."""
+    run_and_compare([700, 3, 1, 250, 143, 1200], {"use_graph": True, "variant": 2, "grid": 3}, seed=15)
+
+
+@pytest.mark.parametrize("variant", [0, 3])
+def test_replayed_graph_stays_correct_across_batches(variant):
     """The recorded launch is replayed for later batches with new items."""
     from paper_2412_15122_amd.batch import Batch
     import torch
@@ -153,7 +166,7 @@ def test_replayed_graph_stays_correct_across_batches():
     graphs, _, items1 = make_case(sizes, 0, seed=21)
     ga = build(graphs)
     gb = [g.clone() for g in ga]
-    b = Batch(len(ga), 256, use_graph=True)
+    b = Batch(len(ga), 256, use_graph=True, variant=variant)
     for rnd in range(3):
         if rnd == 0:
             items = items1
@@ -168,6 +181,7 @@ def test_replayed_graph_stays_correct_across_batches():
                 a, c = rng.choice(len(ids), size=2, replace=False)
                 items.append(("query", gi, ids[int(a)], ids[int(c)]))
         res = b.run(ga, items)
+        b.status()
         torch.cuda.synchronize()
         answers = replay_single(gb, items)
         for gi in range(len(ga)):
@@ -221,10 +235,14 @@ def test_config4_shape_sample():
                 items.append(("remove", gi, up.u))
             else:
                 items.append(("edge", gi, up.u, up.v, up.w))
-    b = Batch(len(ga), len(items))
-    b.run(ga, items)
+    gc = [g.clone() for g in ga]
+    for variant, gs in ((0, ga), (3, gc)):
+        b = Batch(len(gs), len(items), variant=variant)
+        b.run(gs, items)
+        b.status()
+        b.close()
     torch.cuda.synchronize()
     replay_single(gb, items)
     for gi in range(len(ga)):
         assert_same(ga[gi], gb[gi], f"graph {gi} n={wls[gi].adj.shape[0]}")
-    b.close()
+        assert_same(gc[gi], gb[gi], f"lockstep graph {gi} n={wls[gi].adj.shape[0]}")
