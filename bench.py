@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--rates", default="1000,3000,10000,30000,100000",
                     help="serving: Poisson arrival rates (requests/s) to sweep")
     ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
+    ap.add_argument("--schedules", default="lockstep,hybrid",
+                    help="serving: server schedules to run (the first is the reported one)")
     return ap.parse_args()
 
 
@@ -301,17 +303,24 @@ def bench_serving(args):
     ns = [a.shape[0] for a in adjs]
     log(f"[bench] {len(adjs)} graphs generated in {time.perf_counter() - t:.1f}s; n {min(ns)}..{max(ns)}")
     rates = [float(x) for x in args.rates.split(",")]
+    schedules = args.schedules.split(",")
     rows = []
     for rate in rates:
-        gen = W.Config5Requests(adjs)
-        reqs = serve.requests_from_stream(gen, rate, args.requests)
-        srv = serve.Server(adjs, streams=4)
-        srv.preload()
-        s = srv.run(reqs)
-        s["stats"] = dict(srv.stats)
-        srv.close()
-        del srv
-        torch.cuda.empty_cache()
+        per = {}
+        for sched in schedules:
+            gen = W.Config5Requests(adjs)
+            reqs = serve.requests_from_stream(gen, rate, args.requests)
+            srv = serve.Server(adjs, streams=4, schedule=sched)
+            srv.preload()
+            r = srv.run(reqs)
+            r["stats"] = dict(srv.stats)
+            srv.close()
+            del srv
+            torch.cuda.empty_cache()
+            per[sched] = r
+            log(f"[bench] rate {rate:.0f}/s {sched}: {r['updates_per_s']:.0f} upd/s p50 {r['p50_ms']:.3f} ms "
+                f"p99 {r['p99_ms']:.3f} ms {r['stats']}")
+        s = per[schedules[0]]
         gs = [Graph(a, capacity=a.shape[0] + 64) for a in adjs]
         torch.cuda.synchronize()
         p = serve.serve_plain(gs, reqs)
@@ -319,12 +328,12 @@ def bench_serving(args):
             g.close()
         del gs
         torch.cuda.empty_cache()
-        row = {"rate": rate,
-               "served": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()},
-               "plain": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in p.items()}}
+        rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+        row = {"rate": rate, "served": rnd(s), "plain": rnd(p)}
+        for sched in schedules[1:]:
+            row[sched] = rnd(per[sched])
         rows.append(row)
-        log(f"[bench] rate {rate:.0f}/s: served {s['updates_per_s']:.0f} upd/s p50 {s['p50_ms']:.3f} ms "
-            f"p99 {s['p99_ms']:.3f} ms {s['stats']} | plain {p['updates_per_s']:.0f} upd/s p50 {p['p50_ms']:.3f} "
+        log(f"[bench] rate {rate:.0f}/s: plain {p['updates_per_s']:.0f} upd/s p50 {p['p50_ms']:.3f} "
             f"p99 {p['p99_ms']:.3f} ms")
     top = rows[-1]
     out = {
@@ -337,7 +346,8 @@ def bench_serving(args):
         "config": {"workload": (f"{len(adjs)} directed complete graphs, n uniform in [1024, 8192], weights U[1,10000]; "
                                 f"Poisson requests, {args.requests} per rate: 45% increase, 45% decrease, 2.5% add, "
                                 f"2.5% remove, 5% single-pair query"),
-                   "graphs": len(adjs), "parallelism": "none (1 GPU)", "rates": rates},
+                   "graphs": len(adjs), "parallelism": "none (1 GPU)", "rates": rates,
+                   "schedule": schedules[0]},
         "latency_ms": {"p50": top["served"]["p50_ms"], "p99": top["served"]["p99_ms"]},
         "plain_path": {"updates_per_s": round(top["plain"]["updates_per_s"], 1), "p50_ms": top["plain"]["p50_ms"],
                        "p99_ms": top["plain"]["p99_ms"]},

@@ -131,6 +131,14 @@ class Graph:
         self._ptr = ptr
 
     def set_stream(self, stream) -> None:
+        """Issue the graph's later work on `stream`; work already queued on
+        the old stream (a cold start, an update) is ordered before it by an
+        event, without waiting on the host."""
+        old = getattr(self, "_stream", None)
+        if old is not None and old.cuda_stream != stream.cuda_stream:
+            ev = _torch().cuda.Event()
+            ev.record(old)
+            stream.wait_event(ev)
         N.check(self._lib.apsp_set_stream(self._h, stream.cuda_stream), "apsp_set_stream")
         self._stream = stream
 

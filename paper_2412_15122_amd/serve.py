@@ -10,15 +10,17 @@ Scheduling (one host loop, polled):
   * a graph with queued requests that is not in HBM is admitted when its
     bytes fit the budget, after moving idle graphs (no queued or running
     work, least recently used first) out to host memory if needed;
-  * every resident graph with nothing in flight contributes work: the
-    longest run of light requests at the head of its queue (edge updates and
-    queries) joins the next batched launch (one persistent launch over all
-    such graphs, on a free stream), while a heavy request at the head (node
-    addition or removal, whose O(n^2) sweeps need the whole GPU) runs through
-    the single-update path on the graph's own stream;
-  * launches are asynchronous: requests that arrive while earlier work is on
-    the GPU are taken by the next launch as soon as their graph is free, and
-    launches for disjoint graphs overlap on different streams;
+  * schedule "lockstep" (default): whenever fewer than two batches are on
+    the GPU, every resident graph's queued requests (up to a cap per graph)
+    form the next batch, one lockstep launch in which all graphs' row sweeps
+    share the whole GPU; requests that arrive while a batch runs join the
+    next one, which is already queued behind it on the same stream, so the
+    GPU never waits for the host; at light load (a handful of requests and
+    nothing in flight) the requests run as single calls on that stream;
+  * schedule "hybrid": edge updates and queries of idle graphs go to
+    work-queue batches on free streams, node additions and removals to the
+    single-update path on the graph's own stream, so launches for disjoint
+    graphs overlap;
   * a request completes when the event recorded after its launch has fired;
     latency = completion time - arrival time.
 
@@ -36,7 +38,7 @@ import numpy as np
 
 from . import _native as N
 from .apsp import Graph, _torch
-from .batch import Batch
+from .batch import Batch, QueryResult
 
 LIGHT = ("increase", "decrease", "edge", "query")
 HEAVY = ("add", "remove")
@@ -78,10 +80,24 @@ class GraphSlot:
 class Server:
     def __init__(self, graphs: Sequence, *, undirected: bool = False, budget_bytes: Optional[int] = None,
                  streams: int = 4, max_batch_items: int = 8192, batch_config: Optional[dict] = None,
-                 headroom: int = 64):
+                 headroom: int = 64, schedule: str = "lockstep", per_graph: int = 8, small_batch: int = 8):
         """graphs: adjacency matrices (numpy or torch, n x n int32).  Each is
         created in HBM (cold start) when first admitted.  budget_bytes:
-        HBM the graphs may hold together (default 80% of free HBM)."""
+        HBM the graphs may hold together (default 80% of free HBM).
+        schedule: "lockstep" or "hybrid" (see the module notes); per_graph:
+        requests of one graph a lockstep batch takes at most; small_batch:
+        with no batch and fewer than this many single calls in flight, this
+        many queued requests or fewer run as single calls instead (a
+        lockstep launch has a fixed cost of a few grid barriers that one
+        cheap update does not repay)."""
+        if schedule not in ("lockstep", "hybrid"):
+            raise ValueError("schedule must be 'lockstep' or 'hybrid'")
+        self.schedule = schedule
+        self.per_graph = int(per_graph)
+        self.small_batch = int(small_batch)
+        if schedule == "lockstep":
+            streams = 1
+            batch_config = dict(batch_config or {"variant": 3, "use_graph": True})
         torch = _torch()
         self._torch = torch
         lib_bytes = N.load().apsp_required_bytes
@@ -108,6 +124,10 @@ class Server:
         self.max_batch_items = int(max_batch_items)
         self.stream_busy = [None] * len(self.streams)   # (event, requests, slots) per stream
         self.heavy_inflight: List[tuple] = []           # (event, request, slot)
+        self.lock_inflight: collections.deque = collections.deque()  # lockstep: (event, requests, slots, results, batch)
+        self.lock_depth = 2 if schedule == "lockstep" else 0
+        if schedule == "lockstep":
+            self.batches.append(Batch(len(self.slots), max_batch_items, **cfg))
         self.stats = collections.Counter()
         self.n_done = 0
 
@@ -116,8 +136,14 @@ class Server:
         if s.resident:
             return True
         if self.used + s.nbytes > self.budget:
-            idle = sorted((x for x in self.slots if x.resident and not x.busy and not x.queue),
-                          key=lambda x: x.last_used)
+            # idle graphs first (least recently used first), then graphs with
+            # no work in flight whose oldest queued request is newer than
+            # this graph's, so that a graph under steady traffic cannot keep
+            # its HBM while an older request waits
+            head = s.queue[0].arrival if s.queue else float("inf")
+            idle = sorted((x for x in self.slots if x.resident and not x.busy
+                           and (not x.queue or x.queue[0].arrival > head)),
+                          key=lambda x: (bool(x.queue), x.last_used))
             for x in idle:
                 if self.used + s.nbytes <= self.budget:
                     break
@@ -143,8 +169,8 @@ class Server:
     def _run_heavy(self, s: GraphSlot, r: Request):
         g = s.graph
         torch = self._torch
-        # the graph is idle (its earlier work has completed), so it may move
-        # to any stream; spreading heavy requests lets them overlap
+        # spreading heavy requests over the streams lets them overlap;
+        # set_stream orders the graph's earlier work (a cold start) first
         self._rr = (getattr(self, "_rr", -1) + 1) % len(self.streams)
         g.set_stream(self.streams[self._rr])
         with torch.cuda.stream(g._stream):
@@ -183,6 +209,19 @@ class Server:
         self.stats["batched_items"] += len(items)
 
     def _complete(self, now: float):
+        while self.lock_inflight and self.lock_inflight[0][0].query():
+            _, reqs, slots, res, _bi = self.lock_inflight.popleft()
+            for r, x in zip(reqs, res):
+                if r.kind == "query":
+                    r.result = x.get() if isinstance(x, QueryResult) else x
+                elif r.kind == "add":
+                    r.result = x
+                r.done = now
+                self.n_done += 1
+            for s in slots:
+                s.inflight -= 1
+                s.busy = s.inflight > 0
+                s.last_used = now
         for si, ent in enumerate(self.stream_busy):
             if ent is None or not ent[0].query():
                 continue
@@ -207,11 +246,97 @@ class Server:
                 keep.append((ev, r, s))
         self.heavy_inflight = keep
 
+    def _launch_lockstep(self):
+        """Every resident graph's queued requests (up to per_graph each) as
+        one lockstep batch behind the ones already on the stream, or, at
+        light load, as single calls."""
+        torch = self._torch
+        work, n_items = [], 0
+        # a graph waiting for admission holds back graphs whose queue is
+        # newer, so they drain and one of them can make room
+        waiting = [s.queue[0].arrival for s in self.slots if s.queue and not s.resident]
+        oldest_wait = min(waiting) if waiting else float("inf")
+        ready = sorted((s for s in self.slots if s.queue and s.resident and s.queue[0].arrival <= oldest_wait),
+                       key=lambda s: s.queue[0].arrival)
+        if not ready:
+            return
+        # light load: a few requests go out as single calls while no batch is
+        # in flight and few single calls are; a longer queue (the single
+        # calls fall behind) goes out as a lockstep batch
+        n_batches = sum(1 for e in self.lock_inflight if e[4] is not None)
+        n_single = len(self.lock_inflight) - n_batches
+        queued = sum(min(len(s.queue), self.per_graph) for s in ready)
+        if queued <= self.small_batch and n_batches == 0:
+            if n_single < self.small_batch:
+                self._run_single([(s, [s.queue.popleft() for _ in range(min(len(s.queue), self.per_graph))])
+                                  for s in ready])
+            return
+        if n_batches >= self.lock_depth:
+            return
+        for s in ready:
+            take = []
+            while s.queue and len(take) < self.per_graph and n_items + len(take) < self.max_batch_items:
+                take.append(s.queue.popleft())
+            if take:
+                work.append((s, take))
+                n_items += len(take)
+        graphs = [s.graph for s, _ in work]
+        items, reqs = [], []
+        for gi, (s, rs) in enumerate(work):
+            for r in rs:
+                if r.kind == "query":
+                    items.append(("query", gi, r.args[0], r.args[1]))
+                elif r.kind == "add":
+                    items.append(("add", gi, r.args[0], r.args[1]))
+                elif r.kind == "remove":
+                    items.append(("remove", gi, r.args[0]))
+                else:
+                    items.append(("edge", gi, r.args[0], r.args[1], r.args[2]))
+                reqs.append(r)
+            s.inflight = getattr(s, "inflight", 0) + 1
+            s.busy = True
+        bi = self._next_batch = (getattr(self, "_next_batch", -1) + 1) % len(self.batches)
+        stream = self.streams[0]
+        with torch.cuda.stream(stream):
+            res = self.batches[bi].run(graphs, items, stream=stream)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        self.lock_inflight.append((ev, reqs, [s for s, _ in work], res, bi))
+        self.stats["batches"] += 1
+        self.stats["batched_items"] += len(items)
+
+    def _run_single(self, work: List[tuple]):
+        """A few requests, one library call each on the batch stream (a
+        query waits for its answer), each completed by its own event."""
+        torch = self._torch
+        stream = self.streams[0]
+        with torch.cuda.stream(stream):
+            for s, rs in work:
+                g = s.graph
+                for r in rs:
+                    if r.kind == "add":
+                        x = g.add_node(r.args[0], None if g.undirected else r.args[1])
+                    elif r.kind == "remove":
+                        x = g.remove_node(r.args[0])
+                    elif r.kind == "query":
+                        x = g.query(r.args[0], r.args[1])
+                    else:
+                        x = g.update_edge(r.args[0], r.args[1], r.args[2])
+                    ev = torch.cuda.Event()
+                    ev.record(stream)
+                    s.inflight = getattr(s, "inflight", 0) + 1
+                    s.busy = True
+                    self.lock_inflight.append((ev, [r], [s], [x], None))
+                    self.stats["single"] += 1
+
     def _dispatch(self, now: float):
         # admission, oldest head request first
         waiting = sorted((s for s in self.slots if s.queue and not s.resident), key=lambda s: s.queue[0].arrival)
         for s in waiting:
             self._admit(s, now)
+        if self.schedule == "lockstep":
+            self._launch_lockstep()
+            return
         free = [i for i, e in enumerate(self.stream_busy) if e is None]
         work, n_items = [], 0
         for s in sorted((s for s in self.slots if s.queue and s.resident and not s.busy),

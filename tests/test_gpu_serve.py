@@ -6,8 +6,11 @@ budget that holds only a few graphs at once, so requests queue for
 admission and idle graphs move out to host memory and back.  Each graph's
 final matrix, ids and adjacency, each query answer and each new id must
 equal what the same graph gets when its requests run alone, one library
-call each, in arrival order; a few final states are also checked against
-the oracle's cold Floyd-Warshall.  The tolerance is zero.
+call each, in arrival order.  Both schedules are covered: lockstep batches
+of every request kind (with and without single calls at light load), and
+the hybrid of work-queue batches and single calls.  A few final states are
+also checked against the oracle's cold Floyd-Warshall.  The tolerance is
+zero.
 """
 import os
 
@@ -73,19 +76,24 @@ def check_against_alone(srv, adjs, reqs):
         g.close()
 
 
-def test_mix_equals_alone_under_tiny_budget():
+@pytest.mark.parametrize("schedule,small", [("lockstep", 0), ("lockstep", 8), ("hybrid", 0)])
+def test_mix_equals_alone_under_tiny_budget(schedule, small):
     from paper_2412_15122_amd import serve
     sizes = [60, 200, 33, 150, 90, 250, 120, 75]
     adjs, gen, reqs = graphs_and_requests(sizes, rate=20000.0, count=700, seed=51)
     from paper_2412_15122_amd import _native as N
     nbytes = sorted(int(N.load().apsp_required_bytes(a.shape[0] + HEADROOM, 0)) for a in adjs)
     budget = nbytes[-1] + nbytes[-2] + nbytes[-3]        # about three graphs at a time
-    srv = serve.Server(adjs, budget_bytes=budget, streams=3)
+    log("schedule", schedule, "small_batch", small)
+    srv = serve.Server(adjs, budget_bytes=budget, streams=3, schedule=schedule, small_batch=small)
     summary = srv.run(reqs)
     log("summary", summary, dict(srv.stats))
     assert all(r.done is not None for r in reqs)
     assert srv.stats["evictions"] > 0 and srv.stats["swap_ins"] > 0
-    assert srv.stats["batches"] > 0 and srv.stats["heavy"] > 0
+    if small == 0:                  # every request goes through a batch
+        assert srv.stats["batches"] > 0 and srv.stats["single"] == 0
+    if schedule == "hybrid":
+        assert srv.stats["heavy"] > 0
     # per-graph FIFO: completion times never decrease along a graph's arrivals
     for i in range(len(adjs)):
         done = [r.done for r in sorted(reqs, key=lambda r: r.arrival) if r.graph == i]
@@ -100,14 +108,18 @@ def test_mix_equals_alone_under_tiny_budget():
     srv.close()
 
 
-def test_mix_equals_alone_with_everything_resident_and_slow_arrivals():
+@pytest.mark.parametrize("schedule", ["lockstep", "hybrid"])
+def test_mix_equals_alone_with_everything_resident_and_slow_arrivals(schedule):
     from paper_2412_15122_amd import serve
     sizes = [300, 140, 64, 500]
     adjs, gen, reqs = graphs_and_requests(sizes, rate=3000.0, count=300, seed=52)
-    srv = serve.Server(adjs, streams=4)
+    log("schedule", schedule)
+    srv = serve.Server(adjs, streams=4, schedule=schedule)
     summary = srv.run(reqs)
     log("summary", summary, dict(srv.stats))
     assert srv.stats["evictions"] == 0
+    if schedule == "lockstep":      # light load: single calls on the batch stream
+        assert srv.stats["single"] > 0
     check_against_alone(srv, adjs, reqs)
     srv.close()
 
