@@ -35,34 +35,45 @@ namespace apsp {
 // streaming helpers
 // ---------------------------------------------------------------------------
 
+// Two 4-column slices of the row vectors a sweep tests against.
+struct Vec2 {
+    uint4 a, b;
+};
+
 // Visits the 4-column groups of rows [r0, r1) (columns [0, n)) whose
-// row_ok(i) holds.  Each wavefront takes runs of U 256-column chunks (64
-// lanes x 4 columns, one row per chunk), so every lane has U independent
-// 16-byte loads of D in flight before it uses any; body(i, c0, ok, d) runs
-// on every lane (ok false where the lane has no group), so it may use
-// cross-lane operations.
-template <int U, class RowOk, class Body>
-__device__ inline void stream_chunks(const DevGraph &g, int32_t n, int32_t r0, int32_t r1, RowOk row_ok, Body body) {
+// row_ok(i) holds.  A wavefront takes one 256-column chunk (64 lanes x 4
+// columns) of U consecutive rows at a time: it reads the chunk's slice of the
+// row vectors once (vecs(c0)), then issues the U rows' 16-byte loads of D
+// together before it uses any.  body(i, c0, ok, d, v) runs on every lane (ok
+// false where the lane has no group), so it may use cross-lane operations.
+template <int U, class RowOk, class Vecs, class Body>
+__device__ inline void stream_chunks(const DevGraph &g, int32_t n, int32_t r0, int32_t r1, RowOk row_ok, Vecs vecs,
+                                     Body body) {
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     const int32_t Q = (n + 255) >> 8;
-    const int32_t total = (r1 - r0) * Q;
-    for (int32_t base = wv * U; base < total; base += (BATCH_THREADS / 64) * U) {
-        uint4 d[U];
-        int32_t ri[U], rc[U];
+    const int32_t total = ((r1 - r0 + U - 1) / U) * Q;
+    for (int32_t k = wv; k < total; k += BATCH_THREADS / 64) {
+        const int32_t i0 = r0 + (k / Q) * U;
+        const int32_t c0 = (k % Q) * 256 + lane * 4;
+        const bool col_ok = c0 < n;
         bool ok[U];
+        bool any = false;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t k = base + u;
-            const int32_t i = r0 + k / Q;
-            const int32_t c0 = (k % Q) * 256 + lane * 4;
-            ri[u] = i;
-            rc[u] = c0;
-            ok[u] = k < total && c0 < n && row_ok(i);
+            ok[u] = i0 + u < r1 && row_ok(i0 + u);
+            any = any || ok[u];
+        }
+        if (!any) continue;  // wave-uniform
+        const Vec2 v = vecs(c0);
+        uint4 d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ok[u] = ok[u] && col_ok;
             d[u] = make_uint4(INF, INF, INF, INF);
-            if (ok[u]) d[u] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)i * g.ld + c0);
+            if (ok[u]) d[u] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)(i0 + u) * g.ld + c0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) body(ri[u], rc[u], ok[u], d[u]);
+        for (int u = 0; u < U; ++u) body(i0 + u, c0, ok[u], d[u], v);
     }
 }
 
@@ -77,9 +88,12 @@ __device__ inline void stage_rows(uint32_t *stage, int32_t P, int32_t n, const i
     __syncthreads();
 }
 
-// 4 consecutive entries of a row vector (columns >= n read as INF).
+// 4 consecutive entries of a row vector (16-byte aligned at c0; columns >= n
+// read as INF; one 16-byte load away from the tail).
 __device__ inline uint4 vec4(const uint32_t *v, int32_t c0, int32_t n) {
-    return make_uint4(v[c0], c0 + 1 < n ? v[c0 + 1] : INF, c0 + 2 < n ? v[c0 + 2] : INF, c0 + 3 < n ? v[c0 + 3] : INF);
+    if (c0 + 3 < n) return *reinterpret_cast<const uint4 *>(v + c0);
+    return make_uint4(c0 < n ? v[c0] : INF, c0 + 1 < n ? v[c0 + 1] : INF, c0 + 2 < n ? v[c0 + 2] : INF,
+                      c0 + 3 < n ? v[c0 + 3] : INF);
 }
 
 // D[i][c0..c0+3] := min(D, t), stored only when something changed.
@@ -96,11 +110,11 @@ __device__ inline void store_min4(const DevGraph &g, int32_t i, int32_t c0, uint
 // ---------------------------------------------------------------------------
 // add node
 // ---------------------------------------------------------------------------
-constexpr int PREF = 8;  // index entries whose loads are issued together
 
-// Weights, the new node's light lists, out[] (new row) and in[] (new column).
-__device__ __forceinline__ void add_prologue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
-                             uint32_t *stage) {
+// Weights by slot and the new node's light lists: its in-edges in the index
+// (from wi) and, for a directed graph, its out-edges in plist (from wo).
+__device__ __forceinline__ void add_setup(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
+                                          uint32_t *stage) {
     const int tid = threadIdx.x;
     const int n = g.n_slots;
     const int32_t p = it.a, rank = it.c;
@@ -127,65 +141,105 @@ __device__ __forceinline__ void add_prologue(const DevGraph &g, const BatchGraph
     int2 *pin = g.nin + (int64_t)p * NIN_L;
     select_light(wi, n, p, pin, g.nin_cnt + p, g.nin_beta + p, ssh, stage);
     if (!und) select_light(wo, n, p, bg.plist, bg.plist_cnt, bg.plist_beta, ssh, stage);
-    const int2 *ol = und ? pin : bg.plist;
+    __syncthreads();
+}
+
+// The new row over the 256 columns [cb, cb + 256): out[c] = min_t wo[t] +
+// D[t][c] (Corollary corollary1).  The 4 waves split p's out-list (ascending
+// weight; a wave stops once the next weight reaches every value it holds,
+// distances being >= 0); every unlisted t has wo[t] >= the list bound, so a
+// column at or below it is final, and the others take an exhaustive scan.
+__device__ __forceinline__ void add_out_cols(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, int32_t cb) {
+    __shared__ uint32_t s_part[4][256];
+    __shared__ uint32_t s_red[32];
+    const int n = g.n_slots;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int32_t p = it.a;
+    const bool und = g.undirected != 0;
+    const int2 *ol = und ? g.nin + (int64_t)p * NIN_L : bg.plist;
     const int ocnt = und ? g.nin_cnt[p] : *bg.plist_cnt;
     const uint32_t obeta = (uint32_t)(und ? g.nin_beta[p] : *bg.plist_beta);
-    // new row: out[c] = min_t wo[t] + D[t][c], over p's lightest out-edges first
-    {
-        const int lim = min(ocnt, g.lim);
-        const uint32_t beta_eff = ocnt > g.lim ? (uint32_t)ol[g.lim].y : obeta;
-        for (int32_t c = tid; c < n; c += BATCH_THREADS) {
-            uint32_t acc = INF;
-            if (g.id_of_slot[c] >= 0) {
-                // the first PREF entries' loads are issued together; an entry
-                // never examined weighs at least the last one examined
-                uint32_t pv[PREF];
+    const int lim = min(ocnt, g.lim);
+    const uint32_t beta_eff = ocnt > g.lim ? (uint32_t)ol[g.lim].y : obeta;
+    const int32_t c0 = cb + lane * 4;
+    bool live[4];
 #pragma unroll
-                for (int e = 0; e < PREF; ++e) {
-                    const int2 ent = e < lim ? ol[e] : make_int2(0, (int)INF);
-                    pv[e] = e < lim ? (uint32_t)ent.y + (uint32_t)g.D[(int64_t)ent.x * g.ld + c] : INF;
-                }
+    for (int e = 0; e < 4; ++e) live[e] = c0 + e < n && g.id_of_slot[c0 + e] >= 0;
+    uint32_t acc[4] = {INF, INF, INF, INF};
+    if (c0 < n) {
+        for (int e = wv; e < lim; e += 4) {
+            const int2 ent = ol[e];
+            uint32_t mx = 0;
 #pragma unroll
-                for (int e = 0; e < PREF; ++e) acc = min(acc, pv[e]);
-                for (int e = PREF; e < lim; ++e) {
-                    const int2 ent = ol[e];
-                    if ((uint32_t)ent.y >= acc) break;
-                    acc = min(acc, (uint32_t)ent.y + (uint32_t)g.D[(int64_t)ent.x * g.ld + c]);
-                }
-                if (acc > beta_eff)
-                    for (int32_t t = 0; t < n; ++t) acc = min(acc, (uint32_t)wo[t] + (uint32_t)g.D[(int64_t)t * g.ld + c]);
-            }
-            bg.vout[c] = (int32_t)min(acc, INF);
+            for (int q = 0; q < 4; ++q)
+                if (live[q]) mx = max(mx, acc[q]);
+            if ((uint32_t)ent.y >= mx) break;
+            const uint4 v = vec4(reinterpret_cast<const uint32_t *>(g.D + (int64_t)ent.x * g.ld), c0, n);
+            acc[0] = min(acc[0], (uint32_t)ent.y + v.x);
+            acc[1] = min(acc[1], (uint32_t)ent.y + v.y);
+            acc[2] = min(acc[2], (uint32_t)ent.y + v.z);
+            acc[3] = min(acc[3], (uint32_t)ent.y + v.w);
         }
     }
-    // new column: in[r] = min_x D[r][x] + wi[x] (directed; = out if undirected)
-    if (!und) {
-        const int cnt = g.nin_cnt[p];
-        const int lim = min(cnt, g.lim);
-        const uint32_t beta_eff = cnt > g.lim ? (uint32_t)pin[g.lim].y : (uint32_t)g.nin_beta[p];
-        for (int32_t r = tid; r < n; r += BATCH_THREADS) {
-            uint32_t best = INF;
-            if (g.id_of_slot[r] >= 0) {
-                const int32_t *Dr = g.D + (int64_t)r * g.ld;
-                uint32_t pv[PREF];
 #pragma unroll
-                for (int e = 0; e < PREF; ++e) {
-                    const int2 ent = e < lim ? pin[e] : make_int2(0, (int)INF);
-                    pv[e] = e < lim ? (uint32_t)ent.y + (uint32_t)Dr[ent.x] : INF;
-                }
-#pragma unroll
-                for (int e = 0; e < PREF; ++e) best = min(best, pv[e]);
-                for (int e = PREF; e < lim; ++e) {
-                    const int2 ent = pin[e];
-                    if ((uint32_t)ent.y >= best) break;
-                    best = min(best, (uint32_t)ent.y + (uint32_t)Dr[ent.x]);
-                }
-                if (best > beta_eff)
-                    for (int32_t x = 0; x < n; ++x) best = min(best, (uint32_t)Dr[x] + (uint32_t)wi[x]);
+    for (int q = 0; q < 4; ++q) s_part[wv][lane * 4 + q] = acc[q];
+    __syncthreads();
+    const int32_t c = cb + tid;  // one column per thread from here on
+    uint32_t fin = min(min(s_part[0][tid], s_part[1][tid]), min(s_part[2][tid], s_part[3][tid]));
+    const bool live_c = c < n && g.id_of_slot[c] >= 0;
+    const int need = block_sum<BATCH_THREADS>(live_c && fin > beta_eff, s_red);
+    if (need && live_c && fin > beta_eff)
+        for (int32_t t = 0; t < n; ++t) fin = min(fin, (uint32_t)bg.wo[t] + (uint32_t)g.D[(int64_t)t * g.ld + c]);
+    if (c < n) bg.vout[c] = live_c ? (int32_t)min(fin, INF) : (int32_t)INF;
+    __syncthreads();
+}
+
+// The new column over rows [r0, r1) (directed graphs): in[r] = min_x D[r][x] +
+// wi[x] (Corollary corollary2), one wave per row over p's light in-edges,
+// exhaustive when the row's value exceeds the list bound.
+__device__ __forceinline__ void add_in_rows(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, int32_t r0,
+                                            int32_t r1) {
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int32_t p = it.a;
+    const int2 *L = g.nin + (int64_t)p * NIN_L;
+    const int cnt = g.nin_cnt[p];
+    const int lim = min(cnt, g.lim);
+    const uint32_t beta_eff = cnt > g.lim ? (uint32_t)L[g.lim].y : (uint32_t)g.nin_beta[p];
+    for (int32_t r = r0 + wv; r < r1; r += BATCH_THREADS / 64) {
+        uint32_t best = INF;
+        if (g.id_of_slot[r] >= 0) {
+            const int32_t *Dr = g.D + (int64_t)r * g.ld;
+            if (lane < lim) {
+                const int2 ent = L[lane];
+                best = (uint32_t)ent.y + (uint32_t)Dr[ent.x];
             }
-            bg.vin[r] = (int32_t)min(best, INF);
+            best = wave_min(best);
+            if (best > beta_eff) {
+                for (int32_t x = lane; x < g.n_slots; x += 64) best = min(best, (uint32_t)Dr[x] + (uint32_t)bg.wi[x]);
+                best = wave_min(best);
+            }
         }
+        if (lane == 0) bg.vin[r] = (int32_t)min(best, INF);
     }
+}
+
+// Chunk c of an add's vector phase (add_vec_chunks).
+__device__ __forceinline__ void add_vec_chunk(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, int32_t c) {
+    const int32_t no = add_out_chunks(g.n_slots);
+    if (c < no) {
+        add_out_cols(g, bg, it, c * 256);
+    } else {
+        const int32_t r0 = (c - no) * ADD_IN_ROWS;
+        add_in_rows(g, bg, it, r0, min(r0 + ADD_IN_ROWS, g.n_slots));
+    }
+}
+
+// The whole add prologue by one work-group (work-queue schedule).
+__device__ __forceinline__ void add_prologue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, SelectShared &ssh,
+                                             uint32_t *stage) {
+    add_setup(g, bg, it, ssh, stage);
+    const int32_t nc = add_vec_chunks(g.n_slots, g.undirected != 0);
+    for (int32_t c = 0; c < nc; ++c) add_vec_chunk(g, bg, it, c);
     __syncthreads();
 }
 
@@ -197,10 +251,11 @@ __device__ __forceinline__ void add_relax_rows(const DevGraph &g, const BatchGra
     const int32_t *in = g.undirected ? bg.vout : bg.vin;
     stream_chunks<U>(
         g, n, r0, r1, [&](int32_t i) { return (uint32_t)in[i] < INF; },
-        [&](int32_t i, int32_t c0, bool ok, uint4 d) {
+        [&](int32_t c0) { return Vec2{vec4(outv, c0, n), make_uint4(0, 0, 0, 0)}; },
+        [&](int32_t i, int32_t c0, bool ok, uint4 d, const Vec2 &v) {
             if (!ok) return;
             const uint32_t a = (uint32_t)in[i];
-            const uint4 o = vec4(outv, c0, n);
+            const uint4 o = v.a;
             store_min4(g, i, c0, d, make_uint4(a + o.x, a + o.y, a + o.z, a + o.w));
         });
 }
@@ -291,12 +346,16 @@ __device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph 
             const RowTests rt = row_tests(g, fa, i, w_old);
             return rt.t1 || rt.t2;
         },
-        [&](int32_t i, int32_t c0, bool ok, uint4 d) {
+        [&](int32_t c0) {
+            const uint4 v1 = vec4(S1, c0, n);
+            return Vec2{v1, fa.row2 ? vec4(S2, c0, n) : v1};
+        },
+        [&](int32_t i, int32_t c0, bool ok, uint4 d, const Vec2 &v) {
             uint32_t bits = 0;
             if (ok) {
                 const RowTests rt = row_tests(g, fa, i, w_old);
-                const uint4 v1 = vec4(S1, c0, n);
-                const uint4 v2 = fa.row2 ? vec4(S2, c0, n) : v1;
+                const uint4 v1 = v.a;
+                const uint4 v2 = v.b;
                 const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
                 const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w};
                 const uint32_t w2[4] = {v2.x, v2.y, v2.z, v2.w};
@@ -611,13 +670,16 @@ __device__ __forceinline__ void dec_relax_rows(const DevGraph &g, const BatchGra
             const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
             return du + wn < dv || (und && dv + wn < du);
         },
-        [&](int32_t i, int32_t c0, bool ok, uint4 d) {
+        [&](int32_t c0) {
+            return Vec2{vec4(SV, c0, n), und ? vec4(SU, c0, n) : make_uint4(INF, INF, INF, INF)};
+        },
+        [&](int32_t i, int32_t c0, bool ok, uint4 d, const Vec2 &v) {
             if (!ok) return;
             const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
             const uint32_t x1 = du + wn < dv ? du + wn : INF;
             const uint32_t x2 = und && dv + wn < du ? dv + wn : INF;
-            const uint4 rv = vec4(SV, c0, n);
-            const uint4 ru = und ? vec4(SU, c0, n) : make_uint4(INF, INF, INF, INF);
+            const uint4 rv = v.a;
+            const uint4 ru = v.b;
             store_min4(g, i, c0, d,
                        make_uint4(min(x1 + rv.x, x2 + ru.x), min(x1 + rv.y, x2 + ru.y), min(x1 + rv.z, x2 + ru.z),
                                   min(x1 + rv.w, x2 + ru.w)));
@@ -808,7 +870,7 @@ __device__ __forceinline__ void run_item_alone(const DevGraph &g, const BatchGra
 template <int U>
 __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch(BatchHeader *hdr, const BatchGraph *graphs,
                                                             const int32_t *order, const BatchItem *items) {
-    extern __shared__ uint32_t stage[];  // 2 P words of row vectors / select staging, then 4 wave lists of 2 ROW_CAP
+    extern __shared__ __align__(16) uint32_t stage[];  // 2 P words of row vectors / select staging, then 4 wave lists of 2 ROW_CAP
     __shared__ SelectShared ssh;
     __shared__ int32_t s_next;
     const int32_t num_graphs = hdr->num_graphs;
@@ -888,7 +950,7 @@ __device__ inline int32_t chunk_graph(const int32_t *base, int32_t num_graphs, i
 template <int U>
 __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs,
                                                                      const BatchItem *items, const int32_t *tables) {
-    extern __shared__ uint32_t stage[];  // P words of select staging, then 4 wave lists of 2 ROW_CAP
+    extern __shared__ __align__(16) uint32_t stage[];  // P words of select staging, then 4 wave lists of 2 ROW_CAP
     __shared__ SelectShared ssh;
     __shared__ int32_t s_claim, s_found_g, s_found_j;
     __shared__ int s_flag;
@@ -915,7 +977,7 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
                 const BatchItem it = items[bg.item_begin + s];
                 DevGraph g = bg.g;
                 g.n_slots = it.n_slots;
-                if (it.op == BOP_ADD) add_prologue(g, bg, it, ssh, stage);
+                if (it.op == BOP_ADD) add_setup(g, bg, it, ssh, stage);
                 else if (it.op == BOP_REMOVE) remove_prologue(g, bg, it);
                 else if (it.op == BOP_EDGE) edge_prologue(g, bg, it);
                 else if (it.op == BOP_QUERY) query_block(g, it.a, it.b, it.out, bg.qscratch);
@@ -926,9 +988,23 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
         }
         if (s == steps) break;
         grid_barrier(hdr);
+        // A2: the new row and column of every added node, spread over the grid
+        const int32_t *baseA2 = tables + (int64_t)s * BATCH_TABLES * (G + 1);
+        if (baseA2[G] > 0) {
+            for (int32_t c = blockIdx.x; c < baseA2[G]; c += gridDim.x) {
+                const int32_t gi = chunk_graph(baseA2, G, c);
+                const BatchGraph &bg = graphs[gi];
+                const BatchItem it = items[bg.item_begin + s];
+                DevGraph g = bg.g;
+                g.n_slots = it.n_slots;
+                add_vec_chunk(g, bg, it, c - baseA2[gi]);
+                __syncthreads();
+            }
+            grid_barrier(hdr);
+        }
         if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s < BATCH_PHASE_STAMPS) hdr->phase_ts[3 * s] = wall_clock64();
         // B: row sweeps (relaxation or mask) of every graph, spread over the grid
-        const int32_t *baseB = tables + (int64_t)s * 2 * (G + 1);
+        const int32_t *baseB = baseA2 + (G + 1);
         for (int32_t c = blockIdx.x; c < baseB[G]; c += gridDim.x) {
             const int32_t gi = chunk_graph(baseB, G, c);
             const BatchGraph &bg = graphs[gi];

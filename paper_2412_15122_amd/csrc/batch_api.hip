@@ -32,8 +32,8 @@ BatchLayout batch_layout(int32_t max_graphs, int32_t max_items) {
     off = align256(off + (size_t)max_items * sizeof(BatchItem));
     L.times = off;
     off = align256(off + (size_t)max_graphs * 2 * sizeof(long long));
-    L.tables = off;  // lockstep: per step, sweep and recompute chunk prefixes over the graphs
-    off = align256(off + (size_t)max_items * 2 * ((size_t)max_graphs + 1) * sizeof(int32_t));
+    L.tables = off;  // lockstep: per step, add-vector, sweep and recompute chunk prefixes over the graphs
+    off = align256(off + (size_t)max_items * BATCH_TABLES * ((size_t)max_graphs + 1) * sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -394,32 +394,35 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
     size_t table_words = 0;
     if (b->variant >= 2) {
         // lockstep: step s applies item s of every graph; per step, the chunk
-        // prefixes of the sweep phase (every kind but a query) and of the
-        // recompute phase (removals and edge updates)
+        // prefixes of the add-vector phase (additions), the sweep phase
+        // (every kind but a query) and the recompute phase (removals and
+        // edge updates)
         int32_t steps = 0;
         for (int32_t i : b->active) steps = std::max(steps, b->count[i]);
         auto *tab = reinterpret_cast<int32_t *>(b->stage + b->L.tables);
         const int32_t G1 = n_active + 1;
         for (int32_t st = 0; st < steps; ++st) {
-            int32_t *tb = tab + (size_t)st * 2 * G1, *tc = tb + G1;
-            tb[0] = tc[0] = 0;
+            int32_t *ta = tab + (size_t)st * BATCH_TABLES * G1, *tb = ta + G1, *tc = tb + G1;
+            ta[0] = tb[0] = tc[0] = 0;
             for (int32_t ai = 0; ai < n_active; ++ai) {
                 const int32_t i = b->active[ai];
-                int32_t cb = 0, cc = 0;
+                int32_t ca = 0, cb = 0, cc = 0;
                 if (st < b->count[i]) {
                     const BatchItem &bi = bitems[b->begin[i] + st];
                     const int32_t rpc = batch_rows_per_chunk(bi.n_slots);
+                    if (bi.op == BOP_ADD) ca = add_vec_chunks(bi.n_slots, graphs[i]->kind == APSP_UNDIRECTED);
                     if (bi.op != BOP_QUERY) cb = (bi.n_slots + rpc - 1) / rpc;
                     if (bi.op == BOP_REMOVE || bi.op == BOP_EDGE)
                         cc = (bi.n_slots + BATCH_RECOMPUTE_ROWS - 1) / BATCH_RECOMPUTE_ROWS;
                 }
+                ta[ai + 1] = ta[ai] + ca;
                 tb[ai + 1] = tb[ai] + cb;
                 tc[ai + 1] = tc[ai] + cc;
             }
         }
         hdr->steps = steps;
         b->last_steps = steps;
-        table_words = (size_t)steps * 2 * G1;
+        table_words = (size_t)steps * BATCH_TABLES * G1;
     }
     // order the batch after earlier work of each graph on its own stream
     std::vector<hipStream_t> others;

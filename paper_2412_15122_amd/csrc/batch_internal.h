@@ -61,6 +61,15 @@ struct BatchHeader {
 
 constexpr int BATCH_PHASE_STAMPS = 96;
 constexpr int BATCH_RECOMPUTE_ROWS = 16;  // rows per chunk of the lockstep recompute phase
+constexpr int BATCH_TABLES = 3;           // lockstep chunk tables per step: add vectors, sweeps, recompute
+
+// Work-group chunks of an add's vector phase: 256 columns of the new row,
+// then (directed) ADD_IN_ROWS rows of the new column.
+constexpr int32_t ADD_IN_ROWS = 16;
+__host__ __device__ inline int32_t add_out_chunks(int32_t n) { return (n + 255) / 256; }
+__host__ __device__ inline int32_t add_vec_chunks(int32_t n, bool undirected) {
+    return add_out_chunks(n) + (undirected ? 0 : (n + ADD_IN_ROWS - 1) / ADD_IN_ROWS);
+}
 
 constexpr int BATCH_THREADS = 256;
 constexpr int BATCH_MAX_CAPACITY = APSP_BATCH_MAX_CAPACITY;  // keeps the select stage in LDS
