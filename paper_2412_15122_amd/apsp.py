@@ -87,9 +87,13 @@ class Graph:
         buf = torch.empty(self._nbytes + 256, dtype=torch.uint8, device="cuda")
         ptr = (buf.data_ptr() + 255) & ~255
         stream = torch.cuda.current_stream()
+        if stream.cuda_stream != self._stream.cuda_stream:
+            stream.wait_stream(self._stream)  # the source's queued updates come first
         h = ctypes.c_void_p()
         N.check(self._lib.apsp_graph_clone(self._h, ptr, self._nbytes, stream.cuda_stream, ctypes.byref(h)),
                 "apsp_graph_clone")
+        if stream.cuda_stream != self._stream.cuda_stream:
+            self._stream.wait_stream(stream)  # and the source's later updates after the copy
         return Graph._from_handle(self._lib, h, buf, ptr, self._nbytes, self.capacity, self.kind, stream)
 
     @property
@@ -155,19 +159,32 @@ class Graph:
             pass
 
     # -- updates --------------------------------------------------------------
+    def _join(self):
+        """The current stream, after making the graph's stream wait for it
+        (work the caller queued there, e.g. a tensor it filled, comes first)."""
+        cur = _torch().cuda.current_stream()
+        if cur.cuda_stream != self._stream.cuda_stream:
+            self._stream.wait_stream(cur)
+        return cur
+
     def add_node(self, w_out, w_in=None) -> int:
         """Add a node; w_out[t] / w_in[t] are the weights to / from the t-th
         live node in ascending-id order.  Returns the new id."""
+        torch = _torch()
         n = self.num_nodes()
-        wo = _device_int32(w_out).reshape(-1) if n else None
-        wi = None
-        if n and not self.undirected:
-            if w_in is None:
-                raise ValueError("w_in is required for a directed graph")
-            wi = _device_int32(w_in).reshape(-1)
-        if n and (wo.numel() != n or (wi is not None and wi.numel() != n)):
-            raise ValueError(f"weight vectors must have {n} entries")
-        return self.add_node_device(wo.data_ptr() if n else None, wi.data_ptr() if wi is not None else None)
+        if n and not self.undirected and w_in is None:
+            raise ValueError("w_in is required for a directed graph")
+        self._join()
+        with torch.cuda.stream(self._stream):
+            wo = _device_int32(w_out).reshape(-1) if n else None
+            wi = _device_int32(w_in).reshape(-1) if n and not self.undirected else None
+            if n and (wo.numel() != n or (wi is not None and wi.numel() != n)):
+                raise ValueError(f"weight vectors must have {n} entries")
+            nid = self.add_node_device(wo.data_ptr() if n else None, wi.data_ptr() if wi is not None else None)
+            for t in (wo, wi):
+                if t is not None:
+                    t.record_stream(self._stream)  # not reused before the kernels have read it
+        return nid
 
     def add_node_device(self, w_out_ptr, w_in_ptr) -> int:
         """add_node with device pointers (length = live count)."""
@@ -198,11 +215,17 @@ class Graph:
         return list(buf[: cnt.value])
 
     def matrix_device(self, which: str = "D"):
+        """D (or A) in ascending-id order as a new device tensor, ready for
+        use on the current stream."""
         torch = _torch()
         n = self.num_nodes()
         out = torch.empty((n, n), dtype=torch.int32, device="cuda")
+        cur = self._join()
         fn = self._lib.apsp_read_matrix if which == "D" else self._lib.apsp_read_adjacency
         N.check(fn(self._h, out.data_ptr() if n else None, max(n, 1)), "apsp_read")
+        if cur.cuda_stream != self._stream.cuda_stream:
+            cur.wait_stream(self._stream)
+            out.record_stream(self._stream)
         return out
 
     def matrix(self) -> np.ndarray:

@@ -129,6 +129,7 @@ apsp_status make_handle(int32_t capacity, int32_t kind, void *dev_buf, hipStream
     g->heavy_epoch = (int32_t *)(b + L.heavy_epoch);
     g->flag_bits = (uint32_t *)(b + L.flag_bits);
     g->row_bits = (uint32_t *)(b + L.row_bits);
+    g->marks = (uint8_t *)(b + L.marks);
     g->partials = (int32_t *)(b + L.partials);
     g->prof_impl.stream = g->stream;
     g->prof.impl = &g->prof_impl;
@@ -146,6 +147,8 @@ FusedArgs fused_args(apsp_graph *g, int32_t mode) {
     fa.heavy_epoch = g->heavy_epoch;
     fa.flag_bits = g->flag_bits;
     fa.row_bits = g->row_bits;
+    fa.marks = g->marks;
+    fa.mark_pitch = mark_pitch(g->P);
     fa.partials = g->partials;
     fa.epoch = ++g->epoch;
     return fa;
@@ -212,6 +215,7 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
     launch_fill(d.nin_beta, g->P, (int32_t)INF, s);
     launch_fill(g->heavy_epoch, g->P, 0, s);
     launch_fill((int32_t *)g->row_bits, (g->P + 31) / 32, 0, s);
+    launch_fill((int32_t *)g->flag_bits, (int64_t)g->P * ((g->P + 31) / 32), 0, s);
     launch_fill((int32_t *)d.ctl, sizeof(Ctl) / 4, 0, s);
     apsp_status st = check_launch("cold start fill");
     if (st) {
@@ -335,6 +339,7 @@ apsp_status apsp_graph_relocate(apsp_graph *g, void *dev_buf, size_t dev_buf_byt
     g->heavy_epoch = t->heavy_epoch;
     g->flag_bits = t->flag_bits;
     g->row_bits = t->row_bits;
+    g->marks = t->marks;
     g->partials = t->partials;
     apsp_graph_destroy(t);
     return APSP_OK;

@@ -108,6 +108,10 @@ void launch_add_place(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank
                       hipStream_t s);
 
 // Remove node / edge increase: mask + exact recompute of the masked pairs.
+// Row marks of the mask detection: one byte per group of 8 rows and chunk
+// of 256 columns, bit r set when row 8 g + r has a flag in that chunk.
+__host__ __device__ inline int32_t mark_pitch(int64_t P) { return (int32_t)((P + 255) / 256); }
+
 struct FusedArgs {
     int32_t mode;         // FusedMode
     int32_t k;            // removed slot (FUSED_REMOVE)
@@ -119,8 +123,10 @@ struct FusedArgs {
     int32_t *scratch;     // FUSED_GRID * 2 * P ints
     int32_t *heavy_rows;  // [P] rows deferred to the heavy-row pass
     int32_t *heavy_epoch; // [P] heavy_epoch[i] == epoch marks row i heavy
-    uint32_t *flag_bits;  // [P][P/32] flag bitmap of the tested rows
-    uint32_t *row_bits;   // [P/32] rows holding a flag; zero between updates
+    uint32_t *flag_bits;  // [P][P/32] flag bitmap; zero outside a pending mask (its readers clear it)
+    uint32_t *row_bits;   // [P/32] rows holding a flag (batched launches); zero between updates
+    uint8_t *marks;       // [P/8][mark_pitch(P)] per (8-row group, 256-column chunk): rows with a flag there
+    int32_t mark_pitch;
     int32_t *partials;    // [RECOMPUTE_BLOCKS][4] per-work-group statistics of the recompute
     int32_t epoch;        // distinct for every mask pass
 };

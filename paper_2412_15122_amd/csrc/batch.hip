@@ -370,7 +370,7 @@ __device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph 
             uint32_t word = bits << ((lane & 7) * 4);
 #pragma unroll
             for (int o = 1; o < 8; o <<= 1) word |= (uint32_t)__shfl_xor((int)word, o);
-            if (ok && (lane & 7) == 0) bg.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
+            if (ok && (lane & 7) == 0 && word != 0) bg.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
             if (__ballot(ok && word != 0) != 0 && lane == 0) atomicOr(&bg.row_bits[i >> 5], 1u << (i & 31));
         });
 }
@@ -492,7 +492,7 @@ __device__ __forceinline__ void recompute_rows(const DevGraph &g, const BatchGra
     for (int32_t i = r0 + wv; i < r1; i += BATCH_THREADS / 64) {
         {
             if (((bg.row_bits[i >> 5] >> (i & 31)) & 1u) == 0) continue;
-            const uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
+            uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
             int cnt = 0;
             for (int b = 0; b < nw; b += 512) {  // wave-uniform; 8 words per lane in flight
                 uint32_t wd[8];
@@ -549,6 +549,9 @@ __device__ __forceinline__ void recompute_rows(const DevGraph &g, const BatchGra
             if (cnt <= ROW_CAP) wave_bellman_ford(g, Drow, list, cnt, fsl, sweeps, nfs);
             else if (glist) wave_bellman_ford(g, Drow, glist, cnt, glist + g.P, sweeps, nfs);
             else wave_bellman_ford_words(g, Drow, fw, nw, needs + wv * ((g.P + 31) / 32));
+            // the row's flag words are used up: leave the bitmap clear
+            for (int w = lane; w < nw; w += 64)
+                if (fw[w]) fw[w] = 0u;
         }
     }
 }
@@ -708,7 +711,7 @@ __device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGr
     const int lim = g.lim;
     const int32_t *Min = in_matrix(g);
     int32_t *Drow = g.D + (int64_t)i * g.ld;
-    const uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
+    uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
     for (int32_t c = tid * 4; c < n; c += BATCH_THREADS * 4)
         *reinterpret_cast<uint4 *>(cur + c) = *reinterpret_cast<const uint4 *>(Drow + c);
     __syncthreads();
@@ -807,6 +810,7 @@ __device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGr
     }
     for (int w = tid; w < nw; w += BATCH_THREADS) {
         uint32_t bits = fw[w];
+        if (bits) fw[w] = 0u;  // used up: the bitmap is left clear
         while (bits) {
             const int32_t y = w * 32 + __ffs(bits) - 1;
             bits &= bits - 1;

@@ -10,6 +10,14 @@ namespace apsp {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// A 16-byte load marked non-temporal: a sweep reads each entry of D once per
+// launch, so the line need not stay in the caches.
+__device__ __forceinline__ uint4 load_stream4(const int32_t *p) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    const v4u t = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
+
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));

@@ -28,7 +28,7 @@ inline int32_t padded(int32_t cap) { return ((cap + TILE - 1) / TILE) * TILE; }
 
 struct Layout {
     size_t D, A, AT, nin, nin_cnt, nin_beta, id_of_slot, vec, plist, rank_a, rank_b, qbuf, qscratch, fscratch,
-        nin_queue, heavy_rows, heavy_epoch, flag_bits, row_bits, partials, ctl, total;
+        nin_queue, heavy_rows, heavy_epoch, flag_bits, row_bits, marks, partials, ctl, total;
 };
 
 constexpr int NVEC = 8;  // wo, wi, out, in, colu, colv, rowu, rowv
@@ -62,6 +62,7 @@ inline Layout make_layout(int32_t cap, int32_t kind) {
     L.heavy_epoch = take(P * 4);
     L.flag_bits = take(P * ((P + 31) / 32) * 4);
     L.row_bits = take(((P + 31) / 32) * 4);
+    L.marks = take((P / 8) * mark_pitch(P));
     L.partials = take((size_t)RECOMPUTE_BLOCKS * 4 * 4);
     L.ctl = take(sizeof(Ctl));
     L.total = off;
@@ -124,6 +125,7 @@ struct apsp_graph {
     int32_t *qbuf = nullptr, *qscratch = nullptr, *fscratch = nullptr, *nin_queue = nullptr;
     int32_t *heavy_rows = nullptr, *heavy_epoch = nullptr;
     uint32_t *flag_bits = nullptr, *row_bits = nullptr;
+    uint8_t *marks = nullptr;
     int32_t *partials = nullptr;
     int32_t epoch = 0;
     // host bookkeeping

@@ -242,6 +242,9 @@ void launch_add_in(const DevGraph &g, int32_t p, const int32_t *wi, int32_t *in,
 
 // Theorem theorem3: D[i][j] = min(D[i][j], in[i] + out[j]) over the old
 // slots.  Block = 1024 columns x 8 rows; a row with in[i] = INF cannot change.
+// Every row's 16-byte load is issued (non-temporal: D is streamed once)
+// before any row is tested, so a lane has 8 loads in flight; the few changed
+// groups are stored after.
 constexpr int RELAX_ROWS = 8;
 
 __global__ __launch_bounds__(256) void k_add_relax(DevGraph g, const int32_t *__restrict__ in,
@@ -254,26 +257,28 @@ __global__ __launch_bounds__(256) void k_add_relax(DevGraph g, const int32_t *__
     if (c0 + 1 >= n) o.y = INF;
     if (c0 + 2 >= n) o.z = INF;
     if (c0 + 3 >= n) o.w = INF;
-    int rows = 0;
-#pragma unroll 4
+    uint32_t a[RELAX_ROWS];
+    uint4 d[RELAX_ROWS];
+#pragma unroll
     for (int r = 0; r < RELAX_ROWS; ++r) {
         const int32_t i = r0 + r;
-        if (i >= n) break;
-        const uint32_t a = (uint32_t)in[i];
-        if (a >= INF) continue;
-        ++rows;
-        uint4 *dp = reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0);
-        uint4 d = *dp;
-        uint4 t = make_uint4(a + o.x, a + o.y, a + o.z, a + o.w);
-        if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
-            d.x = min(d.x, t.x);
-            d.y = min(d.y, t.y);
-            d.z = min(d.z, t.z);
-            d.w = min(d.w, t.w);
-            *dp = d;
+        a[r] = i < n ? (uint32_t)in[i] : INF;
+        d[r] = make_uint4(0, 0, 0, 0);
+        if (a[r] < INF) d[r] = load_stream4(g.D + (int64_t)i * g.ld + c0);
+    }
+#pragma unroll
+    for (int r = 0; r < RELAX_ROWS; ++r) {
+        if (a[r] >= INF) continue;
+        const uint4 t = make_uint4(a[r] + o.x, a[r] + o.y, a[r] + o.z, a[r] + o.w);
+        uint4 x = d[r];
+        if (t.x < x.x || t.y < x.y || t.z < x.z || t.w < x.w) {
+            x.x = min(x.x, t.x);
+            x.y = min(x.y, t.y);
+            x.z = min(x.z, t.z);
+            x.w = min(x.w, t.w);
+            *reinterpret_cast<uint4 *>(g.D + (int64_t)(r0 + r) * g.ld + c0) = x;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && rows) atomicAdd(&g.ctl->rows_relaxed, rows);
 }
 
 void launch_add_relax(const DevGraph &g, const int32_t *in, const int32_t *out, hipStream_t s) {
@@ -283,27 +288,34 @@ void launch_add_relax(const DevGraph &g, const int32_t *in, const int32_t *out, 
 }
 
 // Write the new node's row and column of D and A (and A^T) and register it.
-__global__ void k_add_place(DevGraph g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
-                            const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi) {
+// Also counts the rows the relaxation could change (in[s] < INF) for the
+// update statistics, one atomic per block.
+__global__ __launch_bounds__(256) void k_add_place(DevGraph g, int32_t p, int32_t new_id, int32_t rank,
+                                                   int32_t *slot_of_rank, const int32_t *in, const int32_t *out,
+                                                   const int32_t *wo, const int32_t *wi) {
+    __shared__ uint32_t red[8];
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.n_slots) return;
     const int64_t ld = g.ld;
+    int relaxed = 0;
     if (s == p) {
         g.D[(int64_t)p * ld + p] = 0;
         g.A[(int64_t)p * ld + p] = 0;
         if (!g.undirected) g.AT[(int64_t)p * ld + p] = 0;
         g.id_of_slot[p] = new_id;
         slot_of_rank[rank] = p;
-        return;
+    } else if (s < g.n_slots) {
+        relaxed = (uint32_t)in[s] < INF;
+        g.D[(int64_t)p * ld + s] = out[s];
+        g.D[(int64_t)s * ld + p] = in[s];
+        g.A[(int64_t)p * ld + s] = wo[s];
+        g.A[(int64_t)s * ld + p] = wi[s];
+        if (!g.undirected) {
+            g.AT[(int64_t)s * ld + p] = wo[s];
+            g.AT[(int64_t)p * ld + s] = wi[s];
+        }
     }
-    g.D[(int64_t)p * ld + s] = out[s];
-    g.D[(int64_t)s * ld + p] = in[s];
-    g.A[(int64_t)p * ld + s] = wo[s];
-    g.A[(int64_t)s * ld + p] = wi[s];
-    if (!g.undirected) {
-        g.AT[(int64_t)s * ld + p] = wo[s];
-        g.AT[(int64_t)p * ld + s] = wi[s];
-    }
+    relaxed = block_sum256(relaxed, red);
+    if (threadIdx.x == 0 && relaxed) atomicAdd(&g.ctl->rows_relaxed, relaxed);
 }
 
 void launch_add_place(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
@@ -476,20 +488,29 @@ size_t fused_lds_bytes(int32_t P) {
 
 // Pass A, in two kernels.
 //   detect: stream D in tiles of 8 rows x 1024 columns (the pair-test row
-//     slice stays in registers) and write the flags of every tested row into a
-//     bitmap (32 columns per word, assembled by 8 lanes, plain stores: every
-//     word of a tested row is rewritten, so nothing needs clearing).  A row
-//     with a flag sets its bit in row_bits (no return value waited on).
-//   recompute: one wavefront per flagged row.  The row's flagged columns are
-//     read from the bitmap; the row of D itself is `cur`: flagged entries (and
-//     column k of a removal) are set to INF and relaxed in place by
+//     slice stays in registers, the 8 rows' loads are issued together) and
+//     write the nonzero flag words (32 columns per word, assembled by 8 lanes
+//     with DPP moves) into the bitmap, which is zero everywhere else: its
+//     readers clear the words they used.  Each wavefront stores one byte of
+//     row marks for its 8 rows x 256 columns (plain stores: no atomics and
+//     no block barrier).
+//   recompute: one wavefront per row with a mark.  The row's flagged columns
+//     are read from the bitmap; the row of D itself is `cur`: flagged entries
+//     (and column k of a removal) are set to INF and relaxed in place by
 //     Bellman-Ford over the light in-edge index.  Rows with more than ROW_CAP
 //     flags ("heavy") are left untouched and queued for pass B.
 constexpr int DETECT_ROWS = 8;
 
+// OR of the 32-bit values of the 8 lanes of each aligned group of 8.
+__device__ __forceinline__ uint32_t or8(uint32_t v) {
+    v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    return v;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
-    __shared__ uint32_t s_rows;
     const int n = g.n_slots;
     uint32_t w_old = 0;
     if (MODE == FUSED_INCREASE) {
@@ -497,7 +518,6 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
         w_old = (uint32_t)g.ctl->w_old;
     }
     const int lane = lane_id();
-    if (threadIdx.x == 0) s_rows = 0;
     const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
     const int32_t r0 = blockIdx.y * DETECT_ROWS;
     const int64_t nwp = (g.P + 31) / 32;
@@ -509,7 +529,7 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
     const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w};
     const uint32_t w2[4] = {v2.x, v2.y, v2.z, v2.w};
     const int kx = MODE == FUSED_REMOVE ? fa.k : -1;
-    uint32_t row_mask = 0;  // rows of this tile holding a flag (wave-uniform)
+    uint32_t row_mask = 0;  // rows of this wavefront's 8 x 256 tile holding a flag (wave-uniform)
     uint4 d[DETECT_ROWS];
     uint32_t a1[DETECT_ROWS], a2[DETECT_ROWS];
     bool tested[DETECT_ROWS];
@@ -524,7 +544,7 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
             if (rt.t1) a1[r] = rt.a1;
             if (rt.t2) a2[r] = rt.a2;
             tested[r] = rt.t1 || rt.t2;
-            if (tested[r] && c0 < n) d[r] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)i * g.ld + c0);
+            if (tested[r] && c0 < n) d[r] = load_stream4(g.D + (int64_t)i * g.ld + c0);
         }
     }
 #pragma unroll
@@ -541,30 +561,41 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
             f = f && dv[e] < INF && j != i && j != kx;
             bits |= (uint32_t)f << e;
         }
-        uint32_t word = bits << ((lane & 7) * 4);
-        word |= (uint32_t)__shfl_xor((int)word, 1);
-        word |= (uint32_t)__shfl_xor((int)word, 2);
-        word |= (uint32_t)__shfl_xor((int)word, 4);
-        if ((lane & 7) == 0 && c0 < n) fa.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
+        const uint32_t word = or8(bits << ((lane & 7) * 4));
+        if ((lane & 7) == 0 && c0 < n && word != 0) fa.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
         if (__ballot(bits != 0) != 0) row_mask |= 1u << r;
     }
-    // one row-mark update per tile: its 8 rows share a word of row_bits
-    __syncthreads();
-    if (lane == 0 && row_mask) atomicOr(&s_rows, row_mask);
-    __syncthreads();
-    if (threadIdx.x == 0 && s_rows) atomicOr(&fa.row_bits[r0 >> 5], s_rows << (r0 & 31));
+    const int32_t chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (lane == 0 && chunk * 256 < n) fa.marks[(int64_t)blockIdx.y * fa.mark_pitch + chunk] = (uint8_t)row_mask;
+}
+
+// Does row i hold a flag?  (The OR of its group's marks, read by one wave.)
+__device__ __forceinline__ bool row_marked(const FusedArgs &fa, int32_t n, int32_t i) {
+    const uint8_t *m = fa.marks + (int64_t)(i >> 3) * fa.mark_pitch;
+    const int32_t chunks = (n + 255) >> 8;
+    uint32_t v = 0;
+    for (int32_t c = lane_id(); c < chunks; c += 64) v |= m[c];
+    return __ballot((v >> (i & 7)) & 1u) != 0;
 }
 
 // Phi of the pending mask (Algorithm 5's cost needs it before the recompute).
 __global__ __launch_bounds__(256) void k_count_flag_rows(DevGraph g, FusedArgs fa) {
     __shared__ uint32_t red[8];
+    const int32_t chunks = (g.n_slots + 255) >> 8;
     int c = 0;
-    for (int w = threadIdx.x; w < (g.n_slots + 31) / 32; w += 256) c += __popc(fa.row_bits[w]);
+    for (int32_t grp = threadIdx.x; grp < (g.n_slots + 7) / 8; grp += 256) {
+        const uint8_t *m = fa.marks + (int64_t)grp * fa.mark_pitch;
+        uint32_t v = 0;
+        for (int32_t q = 0; q < chunks; ++q) v |= m[q];
+        c += __popc(v);
+    }
     c = block_sum256(c, red);
     if (threadIdx.x == 0) g.ctl->rows = c;
 }
 
-// reset_only: only clear the flagged rows' bits (after a cold fallback).
+// reset_only: only clear the flagged rows' words (after a cold fallback).
+// A row's flag words are cleared once read, except those of an undirected
+// heavy row, which the heavy-row pass reads (and clears) later.
 __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa, int32_t reset_only) {
     __shared__ int32_t lists[4][ROW_CAP];
     __shared__ int32_t fsls[4][ROW_CAP];
@@ -578,13 +609,13 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
     int my_rows = 0, my_fs = 0, my_sweeps = 0, my_flagged = 0;
     const bool active = !(fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE);
     for (int32_t i = blockIdx.x * 4 + wv; active && i < n; i += gridDim.x * 4) {
-        if (((fa.row_bits[i >> 5] >> (i & 31)) & 1u) == 0) continue;
+        if (!row_marked(fa, n, i)) continue;
         ++my_rows;
         // flagged columns of row i -> list (at most ROW_CAP kept)
-        const uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
+        uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
         int cnt = 0;
+        uint32_t wd[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // the row's words when they fit one pass (nw <= 512)
         for (int b = 0; b < nw; b += 512) {  // wave-uniform; 8 words per lane in flight
-            uint32_t wd[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int w = b + q * 64 + lane;
@@ -614,6 +645,16 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
             cnt += __shfl(incl, 63);
         }
         my_flagged += cnt;
+        if (reset_only || cnt <= ROW_CAP || !g.undirected) {
+            if (nw <= 512) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (wd[q]) fw[q * 64 + lane] = 0u;
+            } else {
+                for (int w = lane; w < nw; w += 64)
+                    if (fw[w]) fw[w] = 0u;
+            }
+        }
         if (reset_only) continue;
         if (cnt > ROW_CAP) {
             if (lane == 0) {
@@ -657,7 +698,7 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
 }
 
 // After the recompute: sum the work-groups' statistics into the control
-// block and clear the row marks for the next update.
+// block.
 __global__ __launch_bounds__(256) void k_mask_finish(DevGraph g, FusedArgs fa, int32_t blocks) {
     __shared__ uint32_t red[8];
     if (fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE) return;
@@ -669,7 +710,6 @@ __global__ __launch_bounds__(256) void k_mask_finish(DevGraph g, FusedArgs fa, i
         fs += fa.partials[b * 4 + 2];
         sw = max(sw, (uint32_t)fa.partials[b * 4 + 3]);
     }
-    for (int w = threadIdx.x; w < (g.n_slots + 31) / 32; w += 256) fa.row_bits[w] = 0;
     rows = block_sum256(rows, red);
     flagged = block_sum256(flagged, red);
     fs = block_sum256(fs, red);
@@ -723,8 +763,12 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, Fused
             int32_t *Drow = g.D + (int64_t)i * g.ld;
             for (int32_t c = tid * 4; c < n; c += FUSED_THREADS * 4)
                 *reinterpret_cast<uint4 *>(sh.cur + c) = *reinterpret_cast<const uint4 *>(Drow + c);
-            const uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
-            for (int w = tid; w < nw; w += FUSED_THREADS) sh.fl2[w] = fw[w] & sh.fl[w];
+            uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
+            for (int w = tid; w < nw; w += FUSED_THREADS) {
+                const uint32_t x = fw[w];
+                if (x) fw[w] = 0u;  // read once: the bitmap is left clear
+                sh.fl2[w] = x & sh.fl[w];
+            }
             __syncthreads();
             const int todo = compact_bits(sh.fl2, nw, glist, sh.red);
             for (int e = tid; e < todo; e += FUSED_THREADS) sh.cur[glist[e]] = INF;

@@ -396,3 +396,24 @@ def test_empty_graph_grows():
     g.remove_node(c)
     assert g.num_nodes() == 0
     assert g.add_node([], []) == 3
+
+
+def test_reads_on_another_stream_see_queued_updates():
+    """A graph whose work runs on a side stream: additions (host weight
+    vectors) and removals queued there, then the matrices read from the
+    default stream with no synchronization by the caller."""
+    import torch
+    rng = np.random.default_rng(77)
+    n = 300
+    adj = W.random_graph(n, 1, 1000, seed=77)
+    g = lib_graph(adj, False, capacity=n + 40)
+    side = torch.cuda.Stream()
+    g.set_stream(side)
+    st = W.GraphState(adj, False)
+    A, ids = adj.copy(), list(range(n))
+    for step in range(24):
+        kind = (W.ADD, W.REMOVE, W.INCREASE, W.DECREASE)[step % 4]
+        upd = W.make_update(rng, st, kind, wmin=1, wmax=1000, inc_max=2000)
+        A, ids = apply(g, A, ids, upd, False)
+    expect_equal(g, A, ids, "after queued updates on a side stream")
+    g.sync()
