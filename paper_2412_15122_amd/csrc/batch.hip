@@ -44,11 +44,17 @@ struct Vec2 {
 // row_ok(i) holds.  A wavefront takes one 256-column chunk (64 lanes x 4
 // columns) of U consecutive rows at a time: it reads the chunk's slice of the
 // row vectors once (vecs(c0)), then issues the U rows' 16-byte loads of D
-// together before it uses any.  body(i, c0, ok, d, v) runs on every lane (ok
-// false where the lane has no group), so it may use cross-lane operations.
-template <int U, class RowOk, class Vecs, class Body>
+// (non-temporal: streamed once) together before it uses any.  body(i, c0,
+// ok, d, v) runs on every lane (ok false where the lane has no group), so it
+// may use cross-lane operations; after the U rows, piece_end(i0) runs on
+// every lane of the wavefront.
+struct NoPieceEnd {
+    __device__ void operator()(int32_t) const {}
+};
+
+template <int U, class RowOk, class Vecs, class Body, class PieceEnd = NoPieceEnd>
 __device__ inline void stream_chunks(const DevGraph &g, int32_t n, int32_t r0, int32_t r1, RowOk row_ok, Vecs vecs,
-                                     Body body) {
+                                     Body body, PieceEnd piece_end = PieceEnd()) {
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     const int32_t Q = (n + 255) >> 8;
     const int32_t total = ((r1 - r0 + U - 1) / U) * Q;
@@ -70,10 +76,11 @@ __device__ inline void stream_chunks(const DevGraph &g, int32_t n, int32_t r0, i
         for (int u = 0; u < U; ++u) {
             ok[u] = ok[u] && col_ok;
             d[u] = make_uint4(INF, INF, INF, INF);
-            if (ok[u]) d[u] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)(i0 + u) * g.ld + c0);
+            if (ok[u]) d[u] = load_stream4(g.D + (int64_t)(i0 + u) * g.ld + c0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) body(i0 + u, c0, ok[u], d[u], v);
+        piece_end(i0);
     }
 }
 
@@ -340,6 +347,7 @@ __device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph 
     const int lane = lane_id();
     const int n = g.n_slots;
     const int64_t nwp = (g.P + 31) / 32;
+    uint32_t pmask = 0;  // rows of the current piece holding a flag (wave-uniform)
     stream_chunks<U>(
         g, n, r0, r1,
         [&](int32_t i) {
@@ -371,7 +379,13 @@ __device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph 
 #pragma unroll
             for (int o = 1; o < 8; o <<= 1) word |= (uint32_t)__shfl_xor((int)word, o);
             if (ok && (lane & 7) == 0 && word != 0) bg.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
-            if (__ballot(ok && word != 0) != 0 && lane == 0) atomicOr(&bg.row_bits[i >> 5], 1u << (i & 31));
+            if (__ballot(ok && word != 0) != 0) pmask |= 1u << (i & 31);
+        },
+        [&](int32_t i0) {
+            // the U rows of a piece share a word of row marks (r0 and U
+            // are multiples of 8): one atomic per piece that has a flag
+            if (lane == 0 && pmask) atomicOr(&bg.row_bits[i0 >> 5], pmask);
+            pmask = 0;
         });
 }
 
