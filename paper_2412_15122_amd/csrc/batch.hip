@@ -1021,7 +1021,10 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
             grid_barrier(hdr);
         }
         if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s < BATCH_PHASE_STAMPS) hdr->phase_ts[3 * s] = wall_clock64();
-        // B: row sweeps (relaxation or mask) of every graph, spread over the grid
+        // B: row sweeps (relaxation or mask) of every graph, spread over the
+        // grid round robin (neighbouring work-groups stream neighbouring
+        // rows); the wavefronts of a work-group go on to its next chunk
+        // without waiting for each other (the sweeps share nothing in LDS)
         const int32_t *baseB = baseA2 + (G + 1);
         for (int32_t c = blockIdx.x; c < baseB[G]; c += gridDim.x) {
             const int32_t gi = chunk_graph(baseB, G, c);
@@ -1048,7 +1051,6 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
                                    reinterpret_cast<const uint32_t *>(fa.row2));
                 }
             }
-            __syncthreads();
         }
         // C: recompute of the flagged rows (removal, edge increase)
         const int32_t *baseC = baseB + (G + 1);
@@ -1064,12 +1066,12 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
                 g.n_slots = it.n_slots;
                 const int32_t r0 = (c - baseC[gi]) * BATCH_RECOMPUTE_ROWS;
                 const int32_t r1 = min(r0 + BATCH_RECOMPUTE_ROWS, it.n_slots);
+                // each wavefront uses only its own lists and need bitmap in LDS
                 if (it.op == BOP_REMOVE) {
                     recompute_rows(g, bg, remove_args(bg, it), r0, r1, wlists, nullptr, stage, true);
                 } else if (it.op == BOP_EDGE && g.ctl->edge_mode == EDGE_INCREASE) {
                     recompute_rows(g, bg, increase_args(g, bg), r0, r1, wlists, nullptr, stage, true);
                 }
-                __syncthreads();
             }
             if (threadIdx.x == 0 && s < BATCH_PHASE_STAMPS)
                 atomicMax(reinterpret_cast<unsigned long long *>(&hdr->work_ts[s]), (unsigned long long)wall_clock64());
