@@ -65,9 +65,9 @@ def parse():
 # ---------------------------------------------------------------------------
 # add_relax reads every live row of D once (the new pair distances need every
 # old entry): 4 n^2 bytes per added node, n the live count before the add.
-# mask_detect (a removal; an edge increase is timed separately as
-# mask_detect_inc) reads every live row but k once: 4 (n - 1) n bytes.  Writes
-# (changed entries, the flag bitmap) are not counted.
+# mask_detect (a removal; an edge increase's mask runs in edge_sweep) reads
+# every live row but k once: 4 (n - 1) n bytes.  Writes (changed entries, the
+# flag bitmap) are not counted.
 
 
 KERNEL_SOURCES = ("update.hip", "device_common.h")   # where add_relax and mask_detect live

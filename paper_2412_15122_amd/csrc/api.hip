@@ -171,8 +171,8 @@ int32_t apsp_kernel_count(void) { return KID_COUNT; }
 const char *apsp_kernel_name(int32_t k) {
     static const char *names[KID_COUNT] = {
         "fw_pivot", "fw_panel", "fw_tiles", "nin_build", "nin_update", "add_out", "add_in", "add_relax",
-        "add_place", "gather", "mask_recompute", "tombstone", "edge_begin", "dec_relax", "query", "misc",
-        "mask_detect", "mask_detect_inc"};
+        "add_place", "gather", "mask_recompute", "tombstone", "edge_begin", "edge_sweep", "query", "misc",
+        "mask_detect"};
     if (k < 0 || k >= KID_COUNT) return "";
     return names[k];
 }
@@ -492,16 +492,13 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     g->prof.begin(KID_GATHER);
     launch_gather_rc(d, su, sv, colu(g), colv(g), rowu(g), rowv(g), 1, s);
     g->prof.end();
-    g->prof.begin(KID_DEC_RELAX);
-    launch_dec_relax(d, colu(g), colv(g), rowu(g), rowv(g), w, s);
-    g->prof.end();
     FusedArgs fa = fused_args(g, FUSED_INCREASE);
     fa.col1 = colu(g);
     fa.col2 = colv(g);
     fa.row1 = rowv(g);
     fa.row2 = rowu(g);
-    g->prof.begin(KID_MASK_INC);
-    launch_mask_detect(d, fa, s);
+    g->prof.begin(KID_EDGE_SWEEP);
+    launch_edge_sweep(d, fa, w, s);
     g->prof.end();
     int32_t fallback = 0;
     apsp_status st;
@@ -514,8 +511,7 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     g->prof.end();
     if (fallback && (st = run_cold(g))) return st;
     g->prof.begin(KID_NIN_BUILD);
-    launch_nin_build(d, sv, 1, 1, s);
-    if (g->kind == APSP_UNDIRECTED) launch_nin_build(d, su, 1, 1, s);
+    launch_nin_rebuild_short(d, sv, g->kind == APSP_UNDIRECTED ? su : -1, s);
     g->prof.end();
     if ((st = check_launch("apsp_update_edge"))) return st;
     g->last_n_before = n_before;

@@ -87,6 +87,8 @@ const char *launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof);
 
 // Light in-edge index.
 void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t only_short, hipStream_t s);
+// The lists of y0 and y1 (y1 < 0: y0 only) rebuilt if they have shrunk, one launch.
+void launch_nin_rebuild_short(const DevGraph &g, int32_t y0, int32_t y1, hipStream_t s);
 void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
                        int32_t *beta, hipStream_t s);
 void launch_nin_insert_node(const DevGraph &g, int32_t p, const int32_t *w_row, hipStream_t s);
@@ -144,8 +146,9 @@ void launch_reset_stats(const DevGraph &g, hipStream_t s);
 
 // Edge update.
 void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, hipStream_t s);
-void launch_dec_relax(const DevGraph &g, const int32_t *colu, const int32_t *colv, const int32_t *rowu,
-                      const int32_t *rowv, int32_t w, hipStream_t s);
+// The decrease's relaxation or the tight increase's mask, chosen on the
+// device (fa: the increase's mask arguments; its vectors serve both).
+void launch_edge_sweep(const DevGraph &g, const FusedArgs &fa, int32_t w, hipStream_t s);
 
 // Query / read-out.
 void launch_query(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch, hipStream_t s);
@@ -161,7 +164,7 @@ hipError_t configure_kernels();  // raise dynamic-LDS limits once per process
 enum KernelId : int32_t {
     KID_FW_PIVOT = 0, KID_FW_PANEL, KID_FW_TILE, KID_NIN_BUILD, KID_NIN_UPDATE,
     KID_ADD_OUT, KID_ADD_IN, KID_ADD_RELAX, KID_ADD_PLACE, KID_GATHER, KID_FUSED,
-    KID_TOMBSTONE, KID_EDGE_BEGIN, KID_DEC_RELAX, KID_QUERY, KID_MISC, KID_MASK, KID_MASK_INC, KID_COUNT
+    KID_TOMBSTONE, KID_EDGE_BEGIN, KID_EDGE_SWEEP, KID_QUERY, KID_MISC, KID_MASK, KID_COUNT
 };
 
 // Event-based timing hooks (implemented in the host API unit).

@@ -21,11 +21,9 @@ namespace apsp {
 // Build the index of nodes first .. first+count-1 from row y of the in-edge
 // matrix.  only_short: rebuild only lists that have shrunk below NIN_L/2
 // while unlisted in-edges exist.
-__global__ __launch_bounds__(256) void k_nin_build(DevGraph g, int32_t first, int32_t only_short) {
-    __shared__ SelectShared sh;
-    extern __shared__ uint32_t stage[];
-    const int32_t y = first + blockIdx.x;
-    if (y >= g.n_slots) return;
+__device__ __forceinline__ void nin_build_one(const DevGraph &g, int32_t y, int32_t only_short, SelectShared &sh,
+                                              uint32_t *stage) {
+    if (y < 0 || y >= g.n_slots) return;
     int32_t *cnt = g.nin_cnt + y, *beta = g.nin_beta + y;
     if (only_short && !(*cnt < NIN_L / 2 && (uint32_t)*beta < INF)) return;
     int2 *list = g.nin + (int64_t)y * NIN_L;
@@ -36,11 +34,28 @@ __global__ __launch_bounds__(256) void k_nin_build(DevGraph g, int32_t first, in
     select_light(in_matrix(g) + (int64_t)y * g.ld, g.n_slots, y, list, cnt, beta, sh, stage);
 }
 
+__global__ __launch_bounds__(256) void k_nin_build(DevGraph g, int32_t first, int32_t only_short) {
+    __shared__ SelectShared sh;
+    extern __shared__ uint32_t stage[];
+    nin_build_one(g, first + blockIdx.x, only_short, sh, stage);
+}
+
+// Block 0 rebuilds y0's list, block 1 y1's, each only if it has shrunk.
+__global__ __launch_bounds__(256) void k_nin_rebuild_short(DevGraph g, int32_t y0, int32_t y1) {
+    __shared__ SelectShared sh;
+    extern __shared__ uint32_t stage[];
+    nin_build_one(g, blockIdx.x == 0 ? y0 : y1, 1, sh, stage);
+}
+
 size_t nin_build_lds_bytes(int32_t P) { return (size_t)P * sizeof(uint32_t); }
 
 void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t only_short, hipStream_t s) {
     if (count <= 0) return;
     k_nin_build<<<count, 256, nin_build_lds_bytes(g.P), s>>>(g, first, only_short);
+}
+
+void launch_nin_rebuild_short(const DevGraph &g, int32_t y0, int32_t y1, hipStream_t s) {
+    k_nin_rebuild_short<<<y1 >= 0 ? 2 : 1, 256, nin_build_lds_bytes(g.P), s>>>(g, y0, y1);
 }
 
 // A single list on the critical path of an update: one wide block, so that
@@ -411,10 +426,9 @@ void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, hip
 //   D'[i][j] = min(D[i][j], D[i][u] + w + D[v][j])   (and v -> u if undirected).
 // Only rows with D[i][u] + w < D[i][v] can change.  The column / row vectors
 // were gathered before this launch, so in-place writes do not feed back.
-__global__ __launch_bounds__(256) void k_dec_relax(DevGraph g, const int32_t *__restrict__ colu,
-                                                   const int32_t *__restrict__ colv, const int32_t *__restrict__ rowu,
-                                                   const int32_t *__restrict__ rowv, int32_t w) {
-    if (g.ctl->edge_mode != EDGE_DECREASE) return;
+__device__ __forceinline__ void dec_relax_tile(const DevGraph &g, const int32_t *__restrict__ colu,
+                                               const int32_t *__restrict__ colv, const int32_t *__restrict__ rowu,
+                                               const int32_t *__restrict__ rowv, int32_t w) {
     const int n = g.n_slots;
     const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
     const int32_t r0 = blockIdx.y * RELAX_ROWS;
@@ -426,38 +440,41 @@ __global__ __launch_bounds__(256) void k_dec_relax(DevGraph g, const int32_t *__
     if (c0 + 1 >= n) { bv.y = INF; bu.y = INF; }
     if (c0 + 2 >= n) { bv.z = INF; bu.z = INF; }
     if (c0 + 3 >= n) { bv.w = INF; bu.w = INF; }
+    uint32_t x1[RELAX_ROWS], x2[RELAX_ROWS];
+    uint4 d[RELAX_ROWS];
     int rows = 0;
-    for (int r = 0; r < RELAX_ROWS; ++r) {
+#pragma unroll
+    for (int r = 0; r < RELAX_ROWS; ++r) {  // every changing row's load first
         const int32_t i = r0 + r;
-        if (i >= n) break;
-        const uint32_t du = (uint32_t)colu[i], dv = (uint32_t)colv[i];
-        const uint32_t a1 = du + wn, a2 = dv + wn;
-        const bool t1 = a1 < dv;
-        const bool t2 = g.undirected && a2 < du;
-        if (!t1 && !t2) continue;
-        ++rows;
-        const uint32_t x1 = t1 ? a1 : INF, x2 = t2 ? a2 : INF;
-        uint4 *dp = reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0);
-        uint4 d = *dp;
-        uint4 t = make_uint4(min(x1 + bv.x, x2 + bu.x), min(x1 + bv.y, x2 + bu.y), min(x1 + bv.z, x2 + bu.z),
-                             min(x1 + bv.w, x2 + bu.w));
-        if (t.x < d.x || t.y < d.y || t.z < d.z || t.w < d.w) {
-            d.x = min(d.x, t.x);
-            d.y = min(d.y, t.y);
-            d.z = min(d.z, t.z);
-            d.w = min(d.w, t.w);
-            *dp = d;
+        x1[r] = x2[r] = INF;
+        d[r] = make_uint4(0, 0, 0, 0);
+        if (i < n) {
+            const uint32_t du = (uint32_t)colu[i], dv = (uint32_t)colv[i];
+            if (du + wn < dv) x1[r] = du + wn;
+            if (g.undirected && dv + wn < du) x2[r] = dv + wn;
+            if (x1[r] < INF || x2[r] < INF) {
+                ++rows;
+                d[r] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)i * g.ld + c0);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RELAX_ROWS; ++r) {
+        if (x1[r] >= INF && x2[r] >= INF) continue;
+        const uint4 t = make_uint4(min(x1[r] + bv.x, x2[r] + bu.x), min(x1[r] + bv.y, x2[r] + bu.y),
+                                   min(x1[r] + bv.z, x2[r] + bu.z), min(x1[r] + bv.w, x2[r] + bu.w));
+        uint4 x = d[r];
+        if (t.x < x.x || t.y < x.y || t.z < x.z || t.w < x.w) {
+            x.x = min(x.x, t.x);
+            x.y = min(x.y, t.y);
+            x.z = min(x.z, t.z);
+            x.w = min(x.w, t.w);
+            *reinterpret_cast<uint4 *>(g.D + (int64_t)(r0 + r) * g.ld + c0) = x;
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && rows) atomicAdd(&g.ctl->rows_relaxed, rows);
 }
 
-void launch_dec_relax(const DevGraph &g, const int32_t *colu, const int32_t *colv, const int32_t *rowu,
-                      const int32_t *rowv, int32_t w, hipStream_t s) {
-    if (g.n_slots <= 0) return;
-    dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + RELAX_ROWS - 1) / RELAX_ROWS);
-    k_dec_relax<<<grid, 256, 0, s>>>(g, colu, colv, rowu, rowv, w);
-}
 
 // ---------------------------------------------------------------------------
 // mask + exact recompute (node removal, edge increase)
@@ -510,13 +527,8 @@ __device__ __forceinline__ uint32_t or8(uint32_t v) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
+__device__ __forceinline__ void mask_detect_tile(const DevGraph &g, const FusedArgs &fa, uint32_t w_old) {
     const int n = g.n_slots;
-    uint32_t w_old = 0;
-    if (MODE == FUSED_INCREASE) {
-        if (g.ctl->edge_mode != EDGE_INCREASE) return;
-        w_old = (uint32_t)g.ctl->w_old;
-    }
     const int lane = lane_id();
     const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
     const int32_t r0 = blockIdx.y * DETECT_ROWS;
@@ -567,6 +579,19 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
     }
     const int32_t chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (lane == 0 && chunk * 256 < n) fa.marks[(int64_t)blockIdx.y * fa.mark_pitch + chunk] = (uint8_t)row_mask;
+}
+
+__global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
+    mask_detect_tile<FUSED_REMOVE>(g, fa, 0u);
+}
+
+// The edge update's sweep, chosen on the device: the relaxation of a decrease
+// (colu, colv, rowu, rowv = fa.col1, col2, row2, row1) or the mask of a tight
+// increase; nothing for a no-op.
+__global__ __launch_bounds__(256) void k_edge_sweep(DevGraph g, FusedArgs fa, int32_t w) {
+    const int32_t mode = g.ctl->edge_mode;
+    if (mode == EDGE_DECREASE) dec_relax_tile(g, fa.col1, fa.col2, fa.row2, fa.row1, w);
+    else if (mode == EDGE_INCREASE) mask_detect_tile<FUSED_INCREASE>(g, fa, (uint32_t)g.ctl->w_old);
 }
 
 // Does row i hold a flag?  (The OR of its group's marks, read by one wave.)
@@ -810,8 +835,14 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, Fused
 void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
     if (g.n_slots <= 0) return;
     dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS);
-    if (fa.mode == FUSED_REMOVE) k_mask_detect<FUSED_REMOVE><<<grid, 256, 0, s>>>(g, fa);
-    else k_mask_detect<FUSED_INCREASE><<<grid, 256, 0, s>>>(g, fa);
+    k_mask_detect<<<grid, 256, 0, s>>>(g, fa);
+}
+
+void launch_edge_sweep(const DevGraph &g, const FusedArgs &fa, int32_t w, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    static_assert(RELAX_ROWS == DETECT_ROWS, "one grid serves both sweeps");
+    dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS);
+    k_edge_sweep<<<grid, 256, 0, s>>>(g, fa, w);
 }
 
 void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
