@@ -383,7 +383,6 @@ apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t
     DevGraph &d = g->dg;
     const int32_t n_before = g->n_live;
     d.n_slots = std::max(d.n_slots, p + 1);
-    launch_reset_stats(d, s);
     launch_scatter_weights(d, w_out_dev, w_in_dev, g->rank_cur, n_before, wo(g), und ? wo(g) : wi(g), s);
     int32_t *wi_s = und ? wo(g) : wi(g);
     int2 *pin = d.nin + (int64_t)p * NIN_L;
@@ -408,10 +407,7 @@ apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t
     launch_add_relax(d, in, vout(g), s);
     g->prof.end();
     g->prof.begin(KID_ADD_PLACE);
-    launch_add_place(d, p, nid, n_before, g->rank_cur, in, vout(g), wo(g), wi_s, s);
-    g->prof.end();
-    g->prof.begin(KID_NIN_UPDATE);
-    launch_nin_insert_node(d, p, wo(g), s);
+    launch_add_finish(d, p, nid, n_before, g->rank_cur, in, vout(g), wo(g), wi_s, s);
     g->prof.end();
     apsp_status st = check_launch("apsp_add_node");
     if (st) return st;
@@ -435,9 +431,8 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     hipStream_t s = g->stream;
     DevGraph &d = g->dg;
     const int32_t n_before = g->n_live;
-    launch_reset_stats(d, s);
     g->prof.begin(KID_GATHER);
-    launch_gather_rc(d, k, k, colu(g), nullptr, rowu(g), nullptr, 0, s);
+    launch_gather_rc(d, k, k, colu(g), nullptr, rowu(g), nullptr, 0, s);  // also zeroes the counters
     g->prof.end();
     FusedArgs fa = fused_args(g, FUSED_REMOVE);
     fa.k = k;
@@ -453,10 +448,7 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     launch_mask_recompute(d, fa, fallback, s);
     g->prof.end();
     g->prof.begin(KID_TOMBSTONE);
-    launch_tombstone(d, k, s);
-    g->prof.end();
-    g->prof.begin(KID_NIN_UPDATE);
-    launch_nin_purge(d, k, g->nin_queue, s);
+    launch_remove_finish(d, k, g->nin_queue, g->rank_cur, g->rank_other, r, n_before, s);
     g->prof.end();
     if (fallback) {
         if ((st = run_cold(g))) return st;
@@ -464,7 +456,6 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     g->prof.begin(KID_NIN_BUILD);
     launch_nin_rebuild_queue(d, g->nin_queue, s);
     g->prof.end();
-    launch_rank_remove(g->rank_cur, g->rank_other, r, n_before, s);
     if ((st = check_launch("apsp_remove_node"))) return st;
     std::swap(g->rank_cur, g->rank_other);
     g->live_ids.erase(g->live_ids.begin() + r);

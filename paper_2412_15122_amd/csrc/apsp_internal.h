@@ -91,13 +91,11 @@ void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t o
 void launch_nin_rebuild_short(const DevGraph &g, int32_t y0, int32_t y1, hipStream_t s);
 void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
                        int32_t *beta, hipStream_t s);
-void launch_nin_insert_node(const DevGraph &g, int32_t p, const int32_t *w_row, hipStream_t s);
-// Drop node k from every list; lists that fall below NIN_L/2 while unlisted
-// in-edges exist are queued in `queue` and rebuilt by launch_nin_rebuild_queue.
-void launch_nin_purge(const DevGraph &g, int32_t k, int32_t *queue, hipStream_t s);
+// Rebuild the lists queued by a removal (those that fell below NIN_L/2 while
+// unlisted in-edges exist).
 void launch_nin_rebuild_queue(const DevGraph &g, const int32_t *queue, hipStream_t s);
 
-// Add node.
+// Add node.  The scatter also zeroes the per-update counters.
 void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32_t *w_in,
                             const int32_t *slot_of_rank, int32_t n_live, int32_t *wo, int32_t *wi,
                             hipStream_t s);
@@ -105,9 +103,9 @@ void launch_add_out(const DevGraph &g, const int2 *plist, const int32_t *pcnt, c
                     const int32_t *wo, int32_t *out, hipStream_t s);
 void launch_add_in(const DevGraph &g, int32_t p, const int32_t *wi, int32_t *in, hipStream_t s);
 void launch_add_relax(const DevGraph &g, const int32_t *in, const int32_t *out, hipStream_t s);
-void launch_add_place(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
-                      const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi,
-                      hipStream_t s);
+// Row and column p placed, p registered, p's out-edges entered in the lists.
+void launch_add_finish(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
+                       const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi, hipStream_t s);
 
 // Remove node / edge increase: mask + exact recompute of the masked pairs.
 // Row marks of the mask detection: one byte per group of 8 rows and chunk
@@ -140,9 +138,10 @@ void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, in
 void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s);
 void launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s);
 void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s);  // Phi -> ctl->rows
-void launch_tombstone(const DevGraph &g, int32_t k, hipStream_t s);
-void launch_rank_remove(const int32_t *src, int32_t *dst, int32_t r, int32_t n_live, hipStream_t s);
-void launch_reset_stats(const DevGraph &g, hipStream_t s);
+// After a removal's recompute: tombstone of slot k, k purged from the light
+// lists (short ones queued), rank table shifted (rank_src -> rank_dst).
+void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const int32_t *rank_src, int32_t *rank_dst,
+                          int32_t r, int32_t n_live, hipStream_t s);
 
 // Edge update.
 void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, hipStream_t s);

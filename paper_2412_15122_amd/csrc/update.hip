@@ -10,6 +10,19 @@
 
 namespace apsp {
 
+// Zero the per-update counters (the edge decision is written by k_edge_begin).
+__device__ __forceinline__ void reset_stats(Ctl *c) {
+    c->flagged = 0;
+    c->rows = 0;
+    c->full_scans = 0;
+    c->sweeps = 0;
+    c->rows_relaxed = 0;
+    c->scope_r = 0;
+    c->scope_c = 0;
+    c->short_count = 0;
+    c->heavy_count = 0;
+}
+
 // ---------------------------------------------------------------------------
 // light in-edge index
 // ---------------------------------------------------------------------------
@@ -75,41 +88,7 @@ void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *li
                                                                                     beta);
 }
 
-// New node p: its out-edges p -> y (weights w_row[y]) are in-edges of y.
-__global__ __launch_bounds__(256) void k_nin_insert_node(DevGraph g, int32_t p, const int32_t *w_row) {
-    const int32_t y = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (y >= g.n_slots || y == p || g.id_of_slot[y] < 0) return;
-    wave_list_insert(g, y, p, (uint32_t)w_row[y]);
-}
 
-void launch_nin_insert_node(const DevGraph &g, int32_t p, const int32_t *w_row, hipStream_t s) {
-    if (g.n_slots <= 0) return;
-    k_nin_insert_node<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, p, w_row);
-}
-
-// Node k is gone: drop it from every list; its own list empties.  A list
-// left with fewer than NIN_L/2 entries while unlisted in-edges remain is
-// queued for a rebuild.
-__global__ __launch_bounds__(256) void k_nin_purge(DevGraph g, int32_t k, int32_t *queue) {
-    const int32_t y = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (y >= g.n_slots) return;
-    if (y == k) {
-        g.nin[(int64_t)y * NIN_L + lane_id()] = make_int2(0, (int)INF);
-        if (lane_id() == 0) { g.nin_cnt[y] = 0; g.nin_beta[y] = (int32_t)INF; }
-        return;
-    }
-    const int before = g.nin_cnt[y];
-    wave_list_purge(g, y, k);
-    if (lane_id() == 0 && before >= NIN_L / 2 && before - 1 < NIN_L / 2 && (uint32_t)g.nin_beta[y] < INF &&
-        g.id_of_slot[y] >= 0) {
-        queue[atomicAdd(&g.ctl->short_count, 1)] = y;
-    }
-}
-
-void launch_nin_purge(const DevGraph &g, int32_t k, int32_t *queue, hipStream_t s) {
-    if (g.n_slots <= 0) return;
-    k_nin_purge<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, k, queue);
-}
 
 __global__ __launch_bounds__(SELECT_WIDE) void k_nin_rebuild_queue(DevGraph g, const int32_t *queue) {
     __shared__ SelectShared sh;
@@ -149,11 +128,21 @@ __global__ void k_scatter_weights(DevGraph g, const int32_t *__restrict__ w_out,
     if (bad) atomicOr(&g.ctl->err, (int32_t)ERR_VALUE);
 }
 
+// The start of an addition: the per-update counters zeroed, the weight
+// vectors set to INF (absent edges; dead slots) before the scatter.
+__global__ void k_add_begin(DevGraph g, int32_t *wo, int32_t *wi) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0) reset_stats(g.ctl);
+    if (s < g.n_slots) {
+        wo[s] = (int32_t)INF;
+        wi[s] = (int32_t)INF;
+    }
+}
+
 void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32_t *w_in,
                             const int32_t *slot_of_rank, int32_t n_live, int32_t *wo, int32_t *wi,
                             hipStream_t s) {
-    launch_fill(wo, g.n_slots, (int32_t)INF, s);
-    if (wi != wo) launch_fill(wi, g.n_slots, (int32_t)INF, s);
+    k_add_begin<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, wo, wi);
     if (n_live <= 0) return;
     k_scatter_weights<<<(n_live + 255) / 256, 256, 0, s>>>(g, w_out, g.undirected ? nullptr : w_in,
                                                           slot_of_rank, n_live, wo, wi);
@@ -303,11 +292,14 @@ void launch_add_relax(const DevGraph &g, const int32_t *in, const int32_t *out, 
 }
 
 // Write the new node's row and column of D and A (and A^T) and register it.
-// Also counts the rows the relaxation could change (in[s] < INF) for the
-// update statistics, one atomic per block.
-__global__ __launch_bounds__(256) void k_add_place(DevGraph g, int32_t p, int32_t new_id, int32_t rank,
-                                                   int32_t *slot_of_rank, const int32_t *in, const int32_t *out,
-                                                   const int32_t *wo, const int32_t *wi) {
+// The end of an addition, one launch (its parts are independent):
+//   row and column p of D and A (and A^T) written, p registered (thread
+//   s < n_slots), and the rows the relaxation could change (in[s] < INF)
+//   counted for the update statistics, one atomic per block;
+//   p's out-edge to y entered in y's light in-edge list (one wave per y).
+__global__ __launch_bounds__(256) void k_add_finish(DevGraph g, int32_t p, int32_t new_id, int32_t rank,
+                                                    int32_t *slot_of_rank, const int32_t *in, const int32_t *out,
+                                                    const int32_t *wo, const int32_t *wi) {
     __shared__ uint32_t red[8];
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ld = g.ld;
@@ -331,38 +323,26 @@ __global__ __launch_bounds__(256) void k_add_place(DevGraph g, int32_t p, int32_
     }
     relaxed = block_sum256(relaxed, red);
     if (threadIdx.x == 0 && relaxed) atomicAdd(&g.ctl->rows_relaxed, relaxed);
+    const int32_t y = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (y < g.n_slots && y != p && g.id_of_slot[y] >= 0) wave_list_insert(g, y, p, (uint32_t)wo[y]);
 }
 
-void launch_add_place(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
-                      const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi,
-                      hipStream_t s) {
-    k_add_place<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, p, new_id, rank, slot_of_rank, in, out, wo, wi);
+void launch_add_finish(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
+                       const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi, hipStream_t s) {
+    k_add_finish<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, p, new_id, rank, slot_of_rank, in, out, wo, wi);
 }
 
 // ---------------------------------------------------------------------------
 // gathers, tombstones, bookkeeping
 // ---------------------------------------------------------------------------
 
-// Zero the per-update counters (the edge decision is written by k_edge_begin).
-__global__ void k_reset_stats(DevGraph g) {
-    Ctl *c = g.ctl;
-    c->flagged = 0;
-    c->rows = 0;
-    c->full_scans = 0;
-    c->sweeps = 0;
-    c->rows_relaxed = 0;
-    c->scope_r = 0;
-    c->scope_c = 0;
-    c->short_count = 0;
-    c->heavy_count = 0;
-}
-
-void launch_reset_stats(const DevGraph &g, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(g); }
-
 // cola[i] = D[i][a], colb[i] = D[i][b], rowa[j] = D[a][j], rowb[j] = D[b][j].
+// A removal's gather (gate_on_edge = 0) also zeroes the per-update counters
+// (thread 0 of block 0).
 __global__ void k_gather_rc(DevGraph g, int32_t a, int32_t b, int32_t *cola, int32_t *colb, int32_t *rowa,
                             int32_t *rowb, int32_t gate_on_edge) {
     if (gate_on_edge && g.ctl->edge_mode == EDGE_NOOP) return;
+    if (!gate_on_edge && blockIdx.x == 0 && threadIdx.x == 0) reset_stats(g.ctl);
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n_slots) return;
     const int64_t ld = g.ld;
@@ -378,35 +358,48 @@ void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, in
     k_gather_rc<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, a, b, cola, colb, rowa, rowb, gate_on_edge);
 }
 
-// G - G_k: row and column k of D, A (and A^T) become INF, diagonal included.
-__global__ void k_tombstone(DevGraph g, int32_t k) {
+// The end of a removal, one launch (its parts are independent):
+//   G - G_k: row and column k of D, A (and A^T) become INF, diagonal
+//     included (thread s < n_slots);
+//   k dropped from every light in-edge list, k's own list emptied, lists that
+//     fall below half queued for a rebuild (one wave per list y);
+//   the rank -> slot table without rank r (thread t < n_live - 1).
+__global__ __launch_bounds__(256) void k_remove_finish(DevGraph g, int32_t k, int32_t *queue, const int32_t *rank_src,
+                                                       int32_t *rank_dst, int32_t r, int32_t n_live) {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.n_slots) return;
-    const int64_t ld = g.ld;
-    const int32_t I = (int32_t)INF;
-    g.D[(int64_t)k * ld + s] = I;
-    g.D[(int64_t)s * ld + k] = I;
-    g.A[(int64_t)k * ld + s] = I;
-    g.A[(int64_t)s * ld + k] = I;
-    if (!g.undirected) {
-        g.AT[(int64_t)k * ld + s] = I;
-        g.AT[(int64_t)s * ld + k] = I;
+    if (s < g.n_slots) {
+        const int64_t ld = g.ld;
+        const int32_t I = (int32_t)INF;
+        g.D[(int64_t)k * ld + s] = I;
+        g.D[(int64_t)s * ld + k] = I;
+        g.A[(int64_t)k * ld + s] = I;
+        g.A[(int64_t)s * ld + k] = I;
+        if (!g.undirected) {
+            g.AT[(int64_t)k * ld + s] = I;
+            g.AT[(int64_t)s * ld + k] = I;
+        }
+        if (s == k) g.id_of_slot[k] = -1;
     }
-    if (s == k) g.id_of_slot[k] = -1;
+    if (s < n_live - 1) rank_dst[s] = rank_src[s < r ? s : s + 1];
+    const int32_t y = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (y >= g.n_slots) return;  // wave-uniform
+    if (y == k) {
+        g.nin[(int64_t)y * NIN_L + lane_id()] = make_int2(0, (int)INF);
+        if (lane_id() == 0) { g.nin_cnt[y] = 0; g.nin_beta[y] = (int32_t)INF; }
+        return;
+    }
+    const int before = g.nin_cnt[y];
+    wave_list_purge(g, y, k);
+    if (lane_id() == 0 && before >= NIN_L / 2 && before - 1 < NIN_L / 2 && (uint32_t)g.nin_beta[y] < INF &&
+        g.id_of_slot[y] >= 0) {
+        queue[atomicAdd(&g.ctl->short_count, 1)] = y;
+    }
 }
 
-void launch_tombstone(const DevGraph &g, int32_t k, hipStream_t s) {
-    k_tombstone<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, k);
-}
-
-__global__ void k_rank_remove(const int32_t *src, int32_t *dst, int32_t r, int32_t n_live) {
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n_live - 1) dst[t] = src[t < r ? t : t + 1];
-}
-
-void launch_rank_remove(const int32_t *src, int32_t *dst, int32_t r, int32_t n_live, hipStream_t s) {
-    if (n_live <= 1) return;
-    k_rank_remove<<<(n_live + 255) / 256, 256, 0, s>>>(src, dst, r, n_live);
+void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const int32_t *rank_src, int32_t *rank_dst,
+                          int32_t r, int32_t n_live, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_remove_finish<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, k, queue, rank_src, rank_dst, r, n_live);
 }
 
 // ---------------------------------------------------------------------------
