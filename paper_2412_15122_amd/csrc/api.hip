@@ -432,7 +432,7 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     DevGraph &d = g->dg;
     const int32_t n_before = g->n_live;
     g->prof.begin(KID_GATHER);
-    launch_gather_rc(d, k, k, colu(g), nullptr, rowu(g), nullptr, 0, s);  // also zeroes the counters
+    launch_remove_begin(d, k, colu(g), rowu(g), s);
     g->prof.end();
     FusedArgs fa = fused_args(g, FUSED_REMOVE);
     fa.k = k;
@@ -478,10 +478,7 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     DevGraph &d = g->dg;
     const int32_t n_before = g->n_live;
     g->prof.begin(KID_EDGE_BEGIN);
-    launch_edge_begin(d, su, sv, w, s);
-    g->prof.end();
-    g->prof.begin(KID_GATHER);
-    launch_gather_rc(d, su, sv, colu(g), colv(g), rowu(g), rowv(g), 1, s);
+    launch_edge_begin(d, su, sv, w, colu(g), colv(g), rowu(g), rowv(g), s);
     g->prof.end();
     FusedArgs fa = fused_args(g, FUSED_INCREASE);
     fa.col1 = colu(g);

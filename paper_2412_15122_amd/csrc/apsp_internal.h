@@ -130,8 +130,8 @@ struct FusedArgs {
     int32_t *partials;    // [RECOMPUTE_BLOCKS][4] per-work-group statistics of the recompute
     int32_t epoch;        // distinct for every mask pass
 };
-void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, int32_t *colb,
-                      int32_t *rowa, int32_t *rowb, int32_t gate_on_edge, hipStream_t s);
+// Removal: counters zeroed, colk[i] = D[i][k], rowk[j] = D[k][j].
+void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *rowk, hipStream_t s);
 // Mask + recompute in two steps: detection (|F| lands in ctl->flagged), then
 // the recompute (Phi in ctl->rows) -- or, with reset_only, just the clearing
 // of the row marks when cold Floyd-Warshall replaces the recompute.
@@ -144,7 +144,9 @@ void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const in
                           int32_t r, int32_t n_live, hipStream_t s);
 
 // Edge update.
-void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, hipStream_t s);
+// The edge decision and the gathers of columns / rows u and v of D.
+void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int32_t *colu, int32_t *colv,
+                       int32_t *rowu, int32_t *rowv, hipStream_t s);
 // The decrease's relaxation or the tight increase's mask, chosen on the
 // device (fa: the increase's mask arguments; its vectors serve both).
 void launch_edge_sweep(const DevGraph &g, const FusedArgs &fa, int32_t w, hipStream_t s);

@@ -336,26 +336,19 @@ void launch_add_finish(const DevGraph &g, int32_t p, int32_t new_id, int32_t ran
 // gathers, tombstones, bookkeeping
 // ---------------------------------------------------------------------------
 
-// cola[i] = D[i][a], colb[i] = D[i][b], rowa[j] = D[a][j], rowb[j] = D[b][j].
-// A removal's gather (gate_on_edge = 0) also zeroes the per-update counters
-// (thread 0 of block 0).
-__global__ void k_gather_rc(DevGraph g, int32_t a, int32_t b, int32_t *cola, int32_t *colb, int32_t *rowa,
-                            int32_t *rowb, int32_t gate_on_edge) {
-    if (gate_on_edge && g.ctl->edge_mode == EDGE_NOOP) return;
-    if (!gate_on_edge && blockIdx.x == 0 && threadIdx.x == 0) reset_stats(g.ctl);
+// The start of a removal: the per-update counters zeroed (thread 0 of block
+// 0) and column / row k of D gathered: colk[i] = D[i][k], rowk[j] = D[k][j].
+__global__ void k_remove_begin(DevGraph g, int32_t k, int32_t *colk, int32_t *rowk) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) reset_stats(g.ctl);
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n_slots) return;
-    const int64_t ld = g.ld;
-    cola[i] = g.D[(int64_t)i * ld + a];
-    rowa[i] = g.D[(int64_t)a * ld + i];
-    if (colb) colb[i] = g.D[(int64_t)i * ld + b];
-    if (rowb) rowb[i] = g.D[(int64_t)b * ld + i];
+    colk[i] = g.D[(int64_t)i * g.ld + k];
+    rowk[i] = g.D[(int64_t)k * g.ld + i];
 }
 
-void launch_gather_rc(const DevGraph &g, int32_t a, int32_t b, int32_t *cola, int32_t *colb, int32_t *rowa,
-                      int32_t *rowb, int32_t gate_on_edge, hipStream_t s) {
+void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *rowk, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_gather_rc<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, a, b, cola, colb, rowa, rowb, gate_on_edge);
+    k_remove_begin<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, k, colk, rowk);
 }
 
 // The end of a removal, one launch (its parts are independent):
@@ -406,12 +399,24 @@ void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const in
 // edge update (Section 2.3), decided on the device
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(64) void k_edge_begin(DevGraph g, int32_t su, int32_t sv, int32_t w) {
-    edge_begin_wave(g, su, sv, w);
+// The decision (wave 0 of block 0: mode, old weight, the new weight in A,
+// the index lists) and the gathers of columns u, v and rows u, v of D, which
+// the decision does not touch, in one launch.
+__global__ __launch_bounds__(256) void k_edge_begin(DevGraph g, int32_t su, int32_t sv, int32_t w, int32_t *colu,
+                                                    int32_t *colv, int32_t *rowu, int32_t *rowv) {
+    if (blockIdx.x == 0 && threadIdx.x < 64) edge_begin_wave(g, su, sv, w);
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n_slots) return;
+    const int64_t ld = g.ld;
+    colu[i] = g.D[(int64_t)i * ld + su];
+    colv[i] = g.D[(int64_t)i * ld + sv];
+    rowu[i] = g.D[(int64_t)su * ld + i];
+    rowv[i] = g.D[(int64_t)sv * ld + i];
 }
 
-void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, hipStream_t s) {
-    k_edge_begin<<<1, 64, 0, s>>>(g, su, sv, w);
+void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int32_t *colu, int32_t *colv,
+                       int32_t *rowu, int32_t *rowv, hipStream_t s) {
+    k_edge_begin<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, su, sv, w, colu, colv, rowu, rowv);
 }
 
 // Decrease of u -> v to w (< D[u][v]).  Inserting a relay node on the edge
@@ -715,32 +720,35 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
     }
 }
 
-// After the recompute: sum the work-groups' statistics into the control
-// block.
-__global__ __launch_bounds__(256) void k_mask_finish(DevGraph g, FusedArgs fa, int32_t blocks) {
-    __shared__ uint32_t red[8];
-    if (fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE) return;
+// After the recompute: sum the recompute work-groups' statistics into the
+// control block (one work-group of NT threads).
+template <int NT>
+__device__ __forceinline__ void mask_finish_block(const DevGraph &g, const FusedArgs &fa, int32_t blocks,
+                                                  uint32_t *red) {
     int rows = 0, fs = 0, flagged = 0;
     uint32_t sw = 0;
-    for (int b = threadIdx.x; b < blocks; b += 256) {
+    for (int b = threadIdx.x; b < blocks; b += NT) {
         rows += fa.partials[b * 4 + 0];
         flagged += fa.partials[b * 4 + 1];
         fs += fa.partials[b * 4 + 2];
         sw = max(sw, (uint32_t)fa.partials[b * 4 + 3]);
     }
-    rows = block_sum256(rows, red);
-    flagged = block_sum256(flagged, red);
-    fs = block_sum256(fs, red);
-    sw = wave_max(sw);
-    __syncthreads();
-    if (lane_id() == 0) red[threadIdx.x >> 6] = sw;
-    __syncthreads();
+    rows = block_sum<NT>(rows, red);
+    flagged = block_sum<NT>(flagged, red);
+    fs = block_sum<NT>(fs, red);
+    sw = ~block_min<NT>(~sw, red);
     if (threadIdx.x == 0) {
         g.ctl->rows += rows;
         g.ctl->flagged += (unsigned long long)flagged;
         g.ctl->full_scans += fs;
-        g.ctl->sweeps = max(g.ctl->sweeps, (int32_t)max(max(red[0], red[1]), max(red[2], red[3])));
+        atomicMax(&g.ctl->sweeps, (int32_t)sw);
     }
+}
+
+__global__ __launch_bounds__(256) void k_mask_finish(DevGraph g, FusedArgs fa, int32_t blocks) {
+    __shared__ uint32_t red[8];
+    if (fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE) return;
+    mask_finish_block<256>(g, fa, blocks, red);
 }
 
 // Pass B: the heavy rows, one block each with the row in LDS.
@@ -749,8 +757,7 @@ __global__ __launch_bounds__(256) void k_mask_finish(DevGraph g, FusedArgs fa, i
 //   are recomputed by Bellman-Ford against the now exact remainder of the
 //   row.
 //   directed: every flagged entry is recomputed by Bellman-Ford.
-__global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, FusedArgs fa) {
-    extern __shared__ uint32_t sm[];
+__device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedArgs &fa, uint32_t *sm) {
     FusedShared sh = fused_shared(g, sm);
     const int n = g.n_slots;
     const int nw = (n + 31) >> 5;
@@ -823,6 +830,11 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, Fused
     }
     if (tid == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
     if (tid == 0 && my_sweeps) atomicMax(&g.ctl->sweeps, my_sweeps);
+}
+
+__global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, FusedArgs fa) {
+    extern __shared__ uint32_t sm[];
+    fused_heavy_body(g, fa, sm);
 }
 
 void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
