@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
     ap.add_argument("--schedules", default="lockstep,hybrid",
                     help="serving: server schedules to run (the first is the reported one)")
+    ap.add_argument("--small-batch", type=int, default=None,
+                    help="serving: queued requests the lockstep server sends as single calls (default: the server's)")
     return ap.parse_args()
 
 
@@ -310,7 +312,8 @@ def bench_serving(args):
         for sched in schedules:
             gen = W.Config5Requests(adjs)
             reqs = serve.requests_from_stream(gen, rate, args.requests)
-            srv = serve.Server(adjs, streams=4, schedule=sched)
+            kw = {} if args.small_batch is None else {"small_batch": args.small_batch}
+            srv = serve.Server(adjs, streams=4, schedule=sched, **kw)
             srv.preload()
             r = srv.run(reqs)
             r["stats"] = dict(srv.stats)

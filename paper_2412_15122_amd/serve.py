@@ -15,8 +15,9 @@ Scheduling (one host loop, polled):
     form the next batch, one lockstep launch in which all graphs' row sweeps
     share the whole GPU; requests that arrive while a batch runs join the
     next one, which is already queued behind it on the same stream, so the
-    GPU never waits for the host; at light load (a handful of requests and
-    nothing in flight) the requests run as single calls on that stream;
+    GPU never waits for the host; while the single calls keep up (at most
+    small_batch queued and in flight, no batch in flight) requests run as
+    single calls on that stream instead;
   * schedule "hybrid": edge updates and queries of idle graphs go to
     work-queue batches on free streams, node additions and removals to the
     single-update path on the graph's own stream, so launches for disjoint
@@ -80,7 +81,7 @@ class GraphSlot:
 class Server:
     def __init__(self, graphs: Sequence, *, undirected: bool = False, budget_bytes: Optional[int] = None,
                  streams: int = 4, max_batch_items: int = 8192, batch_config: Optional[dict] = None,
-                 headroom: int = 64, schedule: str = "lockstep", per_graph: int = 8, small_batch: int = 8):
+                 headroom: int = 64, schedule: str = "lockstep", per_graph: int = 8, small_batch: int = 64):
         """graphs: adjacency matrices (numpy or torch, n x n int32).  Each is
         created in HBM (cold start) when first admitted.  budget_bytes:
         HBM the graphs may hold together (default 80% of free HBM).
