@@ -445,10 +445,10 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     apsp_status st = decide_fallback(g, &fa, n_before, &fallback);
     if (st) return st;
     g->prof.begin(KID_FUSED);
-    launch_mask_recompute(d, fa, fallback, s);
+    const int32_t rblocks = launch_mask_recompute(d, fa, fallback, s);
     g->prof.end();
     g->prof.begin(KID_TOMBSTONE);
-    launch_remove_finish(d, k, g->nin_queue, g->rank_cur, g->rank_other, r, n_before, s);
+    launch_remove_finish(d, k, g->nin_queue, g->rank_cur, g->rank_other, r, n_before, g->partials, rblocks, s);
     g->prof.end();
     if (fallback) {
         if ((st = run_cold(g))) return st;
@@ -495,11 +495,11 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
         if (g->ctl_h->edge_mode == EDGE_INCREASE && (st = decide_fallback(g, &fa, n_before, &fallback))) return st;
     }
     g->prof.begin(KID_FUSED);
-    launch_mask_recompute(d, fa, fallback, s);
+    const int32_t rblocks = launch_mask_recompute(d, fa, fallback, s);
     g->prof.end();
     if (fallback && (st = run_cold(g))) return st;
     g->prof.begin(KID_NIN_BUILD);
-    launch_nin_rebuild_short(d, sv, g->kind == APSP_UNDIRECTED ? su : -1, s);
+    launch_edge_finish(d, sv, g->kind == APSP_UNDIRECTED ? su : -1, g->partials, rblocks, s);
     g->prof.end();
     if ((st = check_launch("apsp_update_edge"))) return st;
     g->last_n_before = n_before;

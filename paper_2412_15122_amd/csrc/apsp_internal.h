@@ -87,8 +87,11 @@ const char *launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof);
 
 // Light in-edge index.
 void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t only_short, hipStream_t s);
-// The lists of y0 and y1 (y1 < 0: y0 only) rebuilt if they have shrunk, one launch.
-void launch_nin_rebuild_short(const DevGraph &g, int32_t y0, int32_t y1, hipStream_t s);
+// The end of an edge update, one launch: a tight increase's recompute
+// statistics summed (partials of `blocks` work-groups), then the lists of y0
+// and y1 (y1 < 0: y0 only) rebuilt if they have shrunk.
+void launch_edge_finish(const DevGraph &g, int32_t y0, int32_t y1, const int32_t *partials, int32_t blocks,
+                        hipStream_t s);
 void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
                        int32_t *beta, hipStream_t s);
 // Rebuild the lists queued by a removal (those that fell below NIN_L/2 while
@@ -132,16 +135,18 @@ struct FusedArgs {
 };
 // Removal: counters zeroed, colk[i] = D[i][k], rowk[j] = D[k][j].
 void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *rowk, hipStream_t s);
-// Mask + recompute in two steps: detection (|F| lands in ctl->flagged), then
-// the recompute (Phi in ctl->rows) -- or, with reset_only, just the clearing
-// of the row marks when cold Floyd-Warshall replaces the recompute.
+// Mask + recompute in two steps: detection, then the recompute -- or, with
+// reset_only, just the clearing of the flag words when cold Floyd-Warshall
+// replaces the recompute.  launch_mask_recompute returns the number of
+// work-groups whose statistics (Phi, |F|, ...) the update's next kernel sums
+// into the control block (launch_remove_finish / launch_edge_finish).
 void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s);
-void launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s);
+int32_t launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s);
 void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s);  // Phi -> ctl->rows
 // After a removal's recompute: tombstone of slot k, k purged from the light
 // lists (short ones queued), rank table shifted (rank_src -> rank_dst).
 void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const int32_t *rank_src, int32_t *rank_dst,
-                          int32_t r, int32_t n_live, hipStream_t s);
+                          int32_t r, int32_t n_live, const int32_t *partials, int32_t blocks, hipStream_t s);
 
 // Edge update.
 // The edge decision and the gathers of columns / rows u and v of D.

@@ -53,10 +53,21 @@ __global__ __launch_bounds__(256) void k_nin_build(DevGraph g, int32_t first, in
     nin_build_one(g, first + blockIdx.x, only_short, sh, stage);
 }
 
-// Block 0 rebuilds y0's list, block 1 y1's, each only if it has shrunk.
-__global__ __launch_bounds__(256) void k_nin_rebuild_short(DevGraph g, int32_t y0, int32_t y1) {
+template <int NT>
+__device__ __forceinline__ void mask_finish_block(const DevGraph &g, const int32_t *partials, int32_t blocks,
+                                                  uint32_t *red);
+
+// The end of an edge update: block 0 first sums a tight increase's recompute
+// statistics (partials of `blocks` work-groups; nothing for other edge
+// updates), then block 0 rebuilds y0's list, block 1 y1's, each only if it
+// has shrunk.
+__global__ __launch_bounds__(256) void k_edge_finish(DevGraph g, int32_t y0, int32_t y1, const int32_t *partials,
+                                                     int32_t blocks) {
     __shared__ SelectShared sh;
+    __shared__ uint32_t red[8];
     extern __shared__ uint32_t stage[];
+    if (blockIdx.x == 0 && blocks > 0 && g.ctl->edge_mode == EDGE_INCREASE)
+        mask_finish_block<256>(g, partials, blocks, red);
     nin_build_one(g, blockIdx.x == 0 ? y0 : y1, 1, sh, stage);
 }
 
@@ -67,8 +78,9 @@ void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t o
     k_nin_build<<<count, 256, nin_build_lds_bytes(g.P), s>>>(g, first, only_short);
 }
 
-void launch_nin_rebuild_short(const DevGraph &g, int32_t y0, int32_t y1, hipStream_t s) {
-    k_nin_rebuild_short<<<y1 >= 0 ? 2 : 1, 256, nin_build_lds_bytes(g.P), s>>>(g, y0, y1);
+void launch_edge_finish(const DevGraph &g, int32_t y0, int32_t y1, const int32_t *partials, int32_t blocks,
+                        hipStream_t s) {
+    k_edge_finish<<<y1 >= 0 ? 2 : 1, 256, nin_build_lds_bytes(g.P), s>>>(g, y0, y1, partials, blocks);
 }
 
 // A single list on the critical path of an update: one wide block, so that
@@ -116,6 +128,13 @@ __global__ void k_scatter_weights(DevGraph g, const int32_t *__restrict__ w_out,
                                   const int32_t *__restrict__ slot_of_rank, int32_t n_live, int32_t *wo,
                                   int32_t *wi) {
     int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) reset_stats(g.ctl);  // the start of an addition
+    // dead slots (the new slot among them) have no edges; live slots are
+    // written below by the thread of their rank, so no slot is written twice
+    if (r < g.n_slots && g.id_of_slot[r] < 0) {
+        wo[r] = (int32_t)INF;
+        wi[r] = (int32_t)INF;
+    }
     if (r >= n_live) return;
     int32_t s = slot_of_rank[r];
     int32_t a = w_out[r];
@@ -128,24 +147,12 @@ __global__ void k_scatter_weights(DevGraph g, const int32_t *__restrict__ w_out,
     if (bad) atomicOr(&g.ctl->err, (int32_t)ERR_VALUE);
 }
 
-// The start of an addition: the per-update counters zeroed, the weight
-// vectors set to INF (absent edges; dead slots) before the scatter.
-__global__ void k_add_begin(DevGraph g, int32_t *wo, int32_t *wi) {
-    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s == 0) reset_stats(g.ctl);
-    if (s < g.n_slots) {
-        wo[s] = (int32_t)INF;
-        wi[s] = (int32_t)INF;
-    }
-}
-
 void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32_t *w_in,
                             const int32_t *slot_of_rank, int32_t n_live, int32_t *wo, int32_t *wi,
                             hipStream_t s) {
-    k_add_begin<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, wo, wi);
-    if (n_live <= 0) return;
-    k_scatter_weights<<<(n_live + 255) / 256, 256, 0, s>>>(g, w_out, g.undirected ? nullptr : w_in,
-                                                          slot_of_rank, n_live, wo, wi);
+    const int32_t threads = std::max(g.n_slots, n_live);
+    k_scatter_weights<<<(threads + 255) / 256, 256, 0, s>>>(g, w_out, g.undirected ? nullptr : w_in, slot_of_rank,
+                                                           n_live, wo, wi);
 }
 
 // out[c] = min_t wo[t] (+) D[t][c]  (Corollary corollary1: SPD(p, c)).
@@ -358,7 +365,10 @@ void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *r
 //     fall below half queued for a rebuild (one wave per list y);
 //   the rank -> slot table without rank r (thread t < n_live - 1).
 __global__ __launch_bounds__(256) void k_remove_finish(DevGraph g, int32_t k, int32_t *queue, const int32_t *rank_src,
-                                                       int32_t *rank_dst, int32_t r, int32_t n_live) {
+                                                       int32_t *rank_dst, int32_t r, int32_t n_live,
+                                                       const int32_t *partials, int32_t blocks) {
+    __shared__ uint32_t red[8];
+    if (blockIdx.x == 0) mask_finish_block<256>(g, partials, blocks, red);  // the recompute's statistics
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < g.n_slots) {
         const int64_t ld = g.ld;
@@ -390,9 +400,9 @@ __global__ __launch_bounds__(256) void k_remove_finish(DevGraph g, int32_t k, in
 }
 
 void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const int32_t *rank_src, int32_t *rank_dst,
-                          int32_t r, int32_t n_live, hipStream_t s) {
+                          int32_t r, int32_t n_live, const int32_t *partials, int32_t blocks, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_remove_finish<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, k, queue, rank_src, rank_dst, r, n_live);
+    k_remove_finish<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, k, queue, rank_src, rank_dst, r, n_live, partials, blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -723,15 +733,15 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
 // After the recompute: sum the recompute work-groups' statistics into the
 // control block (one work-group of NT threads).
 template <int NT>
-__device__ __forceinline__ void mask_finish_block(const DevGraph &g, const FusedArgs &fa, int32_t blocks,
+__device__ __forceinline__ void mask_finish_block(const DevGraph &g, const int32_t *partials, int32_t blocks,
                                                   uint32_t *red) {
     int rows = 0, fs = 0, flagged = 0;
     uint32_t sw = 0;
     for (int b = threadIdx.x; b < blocks; b += NT) {
-        rows += fa.partials[b * 4 + 0];
-        flagged += fa.partials[b * 4 + 1];
-        fs += fa.partials[b * 4 + 2];
-        sw = max(sw, (uint32_t)fa.partials[b * 4 + 3]);
+        rows += partials[b * 4 + 0];
+        flagged += partials[b * 4 + 1];
+        fs += partials[b * 4 + 2];
+        sw = max(sw, (uint32_t)partials[b * 4 + 3]);
     }
     rows = block_sum<NT>(rows, red);
     flagged = block_sum<NT>(flagged, red);
@@ -745,11 +755,6 @@ __device__ __forceinline__ void mask_finish_block(const DevGraph &g, const Fused
     }
 }
 
-__global__ __launch_bounds__(256) void k_mask_finish(DevGraph g, FusedArgs fa, int32_t blocks) {
-    __shared__ uint32_t red[8];
-    if (fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE) return;
-    mask_finish_block<256>(g, fa, blocks, red);
-}
 
 // Pass B: the heavy rows, one block each with the row in LDS.
 //   undirected: every flagged (i, j) whose row j was light already holds its
@@ -854,12 +859,12 @@ void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t 
     k_count_flag_rows<<<1, 256, 0, s>>>(g, fa);
 }
 
-void launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s) {
-    if (g.n_slots <= 0) return;
+int32_t launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s) {
+    if (g.n_slots <= 0) return 0;
     const int blocks = std::min(RECOMPUTE_BLOCKS, (g.n_slots + 3) / 4);
     k_recompute_rows<<<blocks, 256, 0, s>>>(g, fa, reset_only);
     if (!reset_only) k_fused_heavy<<<FUSED_GRID, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
-    k_mask_finish<<<1, 256, 0, s>>>(g, fa, blocks);
+    return blocks;
 }
 
 static_assert(APSP_MAX_CAPACITY % TILE == 0, "capacity limit must be a tile multiple");
