@@ -24,7 +24,7 @@ constexpr int TILE = 128;        // Floyd-Warshall block / matrix padding
 constexpr int NIN_L = 64;        // light in-edge index entries per node
 constexpr int FUSED_GRID = 512;  // resident work-groups of the mask+recompute kernel
 constexpr int FUSED_THREADS = 1024;  // threads of a heavy-row work-group
-constexpr int ROW_CAP = 64;      // flagged columns listed per row (more: a "heavy" row)
+constexpr int ROW_CAP = 32;      // flagged columns listed per row (more: a "heavy" row)
 constexpr int RECOMPUTE_BLOCKS = 2048;  // work-groups of the per-row recompute (4 waves each)
 
 enum EdgeMode : int32_t { EDGE_NOOP = 0, EDGE_DECREASE = 1, EDGE_INCREASE = 2 };
