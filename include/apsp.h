@@ -287,11 +287,11 @@ apsp_status apsp_batch_create(void *ws_dev, size_t ws_bytes, int32_t max_graphs,
 apsp_status apsp_batch_destroy(apsp_batch *b);
 /* Two schedules.  Work queue (variants 0, 1): every work-group takes one
  * graph at a time (order: 0 most work first, 1 array order) and runs all of
- * its items alone.  Lockstep (variants 2, 3): step s applies item s of every
- * graph, the row sweeps of all graphs spread over the whole grid between
- * grid barriers (a cooperative launch of the resident grid; the order is
- * irrelevant).  Even variants keep 4, odd ones 8 loads in flight per lane in
- * the streaming loops.  grid: work-groups (0: two per compute unit, at most
+ * its items alone.  Lockstep (variants 2, 3, 4): step s applies item s of
+ * every graph, the row sweeps of all graphs spread over the whole grid
+ * between grid barriers (a cooperative launch of the resident grid; the
+ * order is irrelevant).  Variants 0 and 2 keep 4, 1 and 3 keep 8, 4 keeps
+ * 16 loads in flight per lane in the streaming loops.  grid: work-groups (0: two per compute unit, at most
  * one per graph for the work queue; all resident ones for lockstep; a
  * lockstep grid is capped at the resident count).  use_graph: 1 records the
  * launch once in a HIP graph and replays it. */

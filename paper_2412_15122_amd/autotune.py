@@ -41,14 +41,14 @@ def signature(graphs: Sequence[Graph], items: Sequence[tuple]) -> str:
 
 def candidates(n_cu: int, n_graphs: int) -> List[Dict[str, int]]:
     """Work-queue schedule (variants 0, 1): grid x order; lockstep schedule
-    (variants 2, 3): the resident grid (order does not apply)."""
+    (variants 2, 3, 4): the resident grid (order does not apply)."""
     out = []
     grids = sorted({min(n_graphs, k * n_cu) for k in (1, 2, 4)} | {0})
     for variant in (0, 1):
         for order in (0, 1):
             for grid in grids:
                 out.append({"grid": grid, "order": order, "variant": variant, "use_graph": 1})
-    for variant in (2, 3):
+    for variant in (2, 3, 4):
         out.append({"grid": 0, "order": 0, "variant": variant, "use_graph": 1})
     return out
 

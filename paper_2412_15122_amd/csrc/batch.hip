@@ -382,8 +382,9 @@ __device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph 
             if (__ballot(ok && word != 0) != 0) pmask |= 1u << (i & 31);
         },
         [&](int32_t i0) {
-            // the U rows of a piece share a word of row marks (r0 and U
-            // are multiples of 8): one atomic per piece that has a flag
+            // the U rows of a piece share a word of row marks (r0 is a
+            // multiple of 16, U of 4 up to 16): one atomic per piece that
+            // has a flag
             if (lane == 0 && pmask) atomicOr(&bg.row_bits[i0 >> 5], pmask);
             pmask = 0;
         });
@@ -1149,6 +1150,9 @@ hipError_t configure_batch() {
     if (status == hipSuccess)
         status = hipFuncSetAttribute((const void *)k_batch_lockstep<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      lds2);
+    if (status == hipSuccess)
+        status = hipFuncSetAttribute((const void *)k_batch_lockstep<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     lds2);
     (void)hipGetLastError();
     return status;
 }
@@ -1163,12 +1167,16 @@ hipError_t launch_batch(BatchHeader *hdr, const BatchGraph *graphs, const int32_
     return hipGetLastError();
 }
 
+static const void *lockstep_kernel(int32_t variant) {
+    return variant == 2   ? (const void *)k_batch_lockstep<4>
+           : variant == 3 ? (const void *)k_batch_lockstep<8>
+                          : (const void *)k_batch_lockstep<16>;
+}
+
 hipError_t lockstep_grid(int32_t P_max, int32_t variant, int32_t *grid) {
     const size_t lds = batch_lockstep_lds_bytes(P_max);
     int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, variant == 2 ? (const void *)k_batch_lockstep<4> : (const void *)k_batch_lockstep<8>,
-        BATCH_THREADS, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lockstep_kernel(variant), BATCH_THREADS, lds);
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
@@ -1186,7 +1194,7 @@ hipError_t launch_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs, con
     launch_fill(reinterpret_cast<int32_t *>(hdr->work_ts), 2 * BATCH_PHASE_STAMPS, 0, s);
     const size_t lds = batch_lockstep_lds_bytes(P_max);
     void *args[] = {(void *)&hdr, (void *)&graphs, (void *)&items, (void *)&tables};
-    const void *fn = variant == 2 ? (const void *)k_batch_lockstep<4> : (const void *)k_batch_lockstep<8>;
+    const void *fn = lockstep_kernel(variant);
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BATCH_THREADS), args, (unsigned)lds, s);
 }
 

@@ -220,7 +220,7 @@ apsp_status apsp_batch_destroy(apsp_batch *b) {
 
 apsp_status apsp_batch_set_config(apsp_batch *b, int32_t grid, int32_t order, int32_t variant, int32_t use_graph) {
     if (!b) return fail(APSP_E_INVALID, "apsp_batch_set_config: NULL batch");
-    if (grid < 0 || order < 0 || order > 1 || variant < 0 || variant > 3 || use_graph < 0 || use_graph > 1)
+    if (grid < 0 || order < 0 || order > 1 || variant < 0 || variant > 4 || use_graph < 0 || use_graph > 1)
         return fail(APSP_E_INVALID, "apsp_batch_set_config: value out of range");
     b->grid = grid;
     b->order = order;

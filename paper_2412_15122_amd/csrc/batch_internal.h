@@ -76,8 +76,8 @@ constexpr int BATCH_MAX_CAPACITY = APSP_BATCH_MAX_CAPACITY;  // keeps the select
 
 // Rows per chunk of a lockstep row sweep: about 64K entries (rows of n).
 __host__ __device__ inline int32_t batch_rows_per_chunk(int32_t n) {
-    const int32_t r = n > 0 ? ((1 << 16) / n) & ~7 : 8;
-    return r < 8 ? 8 : r;  // a multiple of 8: a wavefront's rows share a word of row marks
+    const int32_t r = n > 0 ? ((1 << 16) / n) & ~15 : 16;
+    return r < 16 ? 16 : r;  // a multiple of 16: a wavefront's rows share a word of row marks
 }
 
 size_t batch_lds_bytes(int32_t P_max);

@@ -149,6 +149,7 @@ def test_batch_equals_single_calls_graph_replay_both_variants():
 def test_lockstep_schedule_equals_single_calls():
     run_and_compare(SIZES, {"use_graph": False, "variant": 2}, undirected_every=3, seed=13)
     run_and_compare(SIZES, {"use_graph": True, "variant": 3}, undirected_every=2, seed=14)
+    run_and_compare(SIZES, {"use_graph": True, "variant": 4}, undirected_every=3, seed=16)
 
 
 def test_lockstep_with_a_tiny_grid_and_uneven_queues():
