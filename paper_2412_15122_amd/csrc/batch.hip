@@ -174,18 +174,33 @@ __device__ __forceinline__ void add_out_cols(const DevGraph &g, const BatchGraph
     for (int e = 0; e < 4; ++e) live[e] = c0 + e < n && g.id_of_slot[c0 + e] >= 0;
     uint32_t acc[4] = {INF, INF, INF, INF};
     if (c0 < n) {
-        for (int e = wv; e < lim; e += 4) {
-            const int2 ent = ol[e];
+        // the wavefront's entries wv, wv + 4, ... four at a time: their rows'
+        // loads are in flight together; it stops at the first entry that
+        // weighs at least every value it holds
+        for (int e0 = wv; e0 < lim; e0 += 16) {
             uint32_t mx = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (live[q]) mx = max(mx, acc[q]);
-            if ((uint32_t)ent.y >= mx) break;
-            const uint4 v = vec4(reinterpret_cast<const uint32_t *>(g.D + (int64_t)ent.x * g.ld), c0, n);
-            acc[0] = min(acc[0], (uint32_t)ent.y + v.x);
-            acc[1] = min(acc[1], (uint32_t)ent.y + v.y);
-            acc[2] = min(acc[2], (uint32_t)ent.y + v.z);
-            acc[3] = min(acc[3], (uint32_t)ent.y + v.w);
+            int2 ent[4];
+            uint4 v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int e = e0 + 4 * t;
+                ent[t] = e < lim ? ol[e] : make_int2(0, (int)INF);
+                v[t] = make_uint4(INF, INF, INF, INF);
+                if ((uint32_t)ent[t].y < mx)
+                    v[t] = vec4(reinterpret_cast<const uint32_t *>(g.D + (int64_t)ent[t].x * g.ld), c0, n);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t w = (uint32_t)ent[t].y;
+                acc[0] = min(acc[0], w + v[t].x);
+                acc[1] = min(acc[1], w + v[t].y);
+                acc[2] = min(acc[2], w + v[t].z);
+                acc[3] = min(acc[3], w + v[t].w);
+            }
+            if ((uint32_t)ent[3].y >= mx) break;  // every later entry is at least as heavy
         }
     }
 #pragma unroll
@@ -202,31 +217,52 @@ __device__ __forceinline__ void add_out_cols(const DevGraph &g, const BatchGraph
 }
 
 // The new column over rows [r0, r1) (directed graphs): in[r] = min_x D[r][x] +
-// wi[x] (Corollary corollary2), one wave per row over p's light in-edges,
-// exhaustive when the row's value exceeds the list bound.
+// wi[x] (Corollary corollary2), over p's light in-edges (at most 64, read
+// once per wavefront: lane l of a 16-lane group holds entries l, l + 16,
+// l + 32, l + 48).  A wavefront takes 4 rows at a time, one per 16-lane
+// group, each lane's 4 gathers of the row in flight together; a row whose
+// value exceeds the list bound then gets an exhaustive scan by the whole
+// wavefront.
 __device__ __forceinline__ void add_in_rows(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, int32_t r0,
                                             int32_t r1) {
     const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int sub = lane >> 4, l16 = lane & 15;
     const int32_t p = it.a;
     const int2 *L = g.nin + (int64_t)p * NIN_L;
     const int cnt = g.nin_cnt[p];
     const int lim = min(cnt, g.lim);
     const uint32_t beta_eff = cnt > g.lim ? (uint32_t)L[g.lim].y : (uint32_t)g.nin_beta[p];
-    for (int32_t r = r0 + wv; r < r1; r += BATCH_THREADS / 64) {
+    int2 ent[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = l16 + 16 * q;
+        ent[q] = e < lim ? L[e] : make_int2(0, (int)INF);
+    }
+    for (int32_t rb = r0 + wv * 4; rb < r1; rb += BATCH_THREADS / 16) {
+        const int32_t r = rb + sub;
+        const bool live = r < r1 && g.id_of_slot[r] >= 0;
         uint32_t best = INF;
-        if (g.id_of_slot[r] >= 0) {
+        if (live) {
             const int32_t *Dr = g.D + (int64_t)r * g.ld;
-            if (lane < lim) {
-                const int2 ent = L[lane];
-                best = (uint32_t)ent.y + (uint32_t)Dr[ent.x];
-            }
-            best = wave_min(best);
-            if (best > beta_eff) {
-                for (int32_t x = lane; x < g.n_slots; x += 64) best = min(best, (uint32_t)Dr[x] + (uint32_t)bg.wi[x]);
-                best = wave_min(best);
-            }
+            uint32_t v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = (uint32_t)ent[q].y < INF ? (uint32_t)Dr[ent[q].x] : INF;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if ((uint32_t)ent[q].y < INF) best = min(best, (uint32_t)ent[q].y + v[q]);
         }
-        if (lane == 0) bg.vin[r] = (int32_t)min(best, INF);
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) best = min(best, (uint32_t)__shfl_xor((int)best, o, 16));
+        unsigned long long m = __ballot(live && l16 == 0 && best > beta_eff);
+        while (m) {  // wave-uniform
+            const int b = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            // only in-weights below the row's current value can lower it
+            const uint32_t cur = (uint32_t)__shfl((int)best, b);
+            const uint32_t x_best = wave_min_plus_below(g.D + (int64_t)(rb + (b >> 4)) * g.ld, bg.wi, g.n_slots, cur);
+            if (lane == b) best = min(best, x_best);
+        }
+        if (r < r1 && l16 == 0) bg.vin[r] = live ? (int32_t)min(best, INF) : (int32_t)INF;
     }
 }
 
@@ -474,9 +510,7 @@ __device__ __forceinline__ void wave_bellman_ford_words(const DevGraph &g, int32
                 const int32_t y = w * 32 + __ffs(bits) - 1;
                 bits &= bits - 1;
                 const int32_t *col = Min + (int64_t)y * g.ld;
-                uint32_t best = INF;
-                for (int32_t x = lane; x < n; x += 64) best = min(best, (uint32_t)Drow[x] + (uint32_t)col[x]);
-                best = wave_min(best);
+                const uint32_t best = wave_min_plus(Drow, col, n);
                 if (best < (uint32_t)Drow[y]) {
                     changed = true;
                     if (lane == 0) Drow[y] = (int32_t)best;

@@ -65,7 +65,7 @@ constexpr int BATCH_TABLES = 3;           // lockstep chunk tables per step: add
 
 // Work-group chunks of an add's vector phase: 256 columns of the new row,
 // then (directed) ADD_IN_ROWS rows of the new column.
-constexpr int32_t ADD_IN_ROWS = 16;
+constexpr int32_t ADD_IN_ROWS = 64;
 __host__ __device__ inline int32_t add_out_chunks(int32_t n) { return (n + 255) / 256; }
 __host__ __device__ inline int32_t add_vec_chunks(int32_t n, bool undirected) {
     return add_out_chunks(n) + (undirected ? 0 : (n + ADD_IN_ROWS - 1) / ADD_IN_ROWS);

@@ -30,6 +30,64 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
+// min(bound, min over x < n of a[x] + b[x]) (uint32; entries <= INF, a >=
+// 0), by one wavefront: b is read in full (16-byte loads, four per lane in
+// flight), a only where b[x] < bound (no other x can go below bound).
+// a and b 16-byte aligned.
+__device__ inline uint32_t wave_min_plus_below(const int32_t *a, const int32_t *b, int32_t n, uint32_t bound) {
+    const int lane = lane_id();
+    uint32_t best = bound;
+    const int32_t n4 = n & ~3;
+    for (int32_t base = 0; base < n4; base += 1024) {
+        uint4 vb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t x = base + (q * 64 + lane) * 4;
+            vb[q] = make_uint4(INF, INF, INF, INF);
+            if (x < n4) vb[q] = *reinterpret_cast<const uint4 *>(b + x);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t x = base + (q * 64 + lane) * 4;
+            const uint32_t w[4] = {vb[q].x, vb[q].y, vb[q].z, vb[q].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (w[e] < best) best = min(best, (uint32_t)a[x + e] + w[e]);
+        }
+    }
+    if (n4 + lane < n) {
+        const uint32_t w = (uint32_t)b[n4 + lane];
+        if (w < best) best = min(best, (uint32_t)a[n4 + lane] + w);
+    }
+    return wave_min(best);
+}
+
+// min over x < n of a[x] + b[x] (uint32; entries <= INF), by one wavefront:
+// 16-byte loads (a and b 16-byte aligned), four of each per lane in flight.
+__device__ inline uint32_t wave_min_plus(const int32_t *a, const int32_t *b, int32_t n) {
+    const int lane = lane_id();
+    uint32_t best = INF;
+    const int32_t n4 = n & ~3;
+    for (int32_t base = 0; base < n4; base += 1024) {
+        uint4 va[4], vb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t x = base + (q * 64 + lane) * 4;
+            va[q] = make_uint4(INF, INF, INF, INF);
+            vb[q] = va[q];
+            if (x < n4) {
+                va[q] = *reinterpret_cast<const uint4 *>(a + x);
+                vb[q] = *reinterpret_cast<const uint4 *>(b + x);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            best = min(min(best, min(va[q].x + vb[q].x, va[q].y + vb[q].y)), min(va[q].z + vb[q].z, va[q].w + vb[q].w));
+    }
+    if (n4 + lane < n) best = min(best, (uint32_t)a[n4 + lane] + (uint32_t)b[n4 + lane]);
+    return wave_min(best);
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -793,9 +851,7 @@ __device__ inline void wave_bellman_ford(const DevGraph &g, int32_t *Drow, const
         for (int f = 0; f < nfs; ++f) {
             const int32_t y = fsl[f];
             const int32_t *col = Min + (int64_t)y * g.ld;
-            uint32_t best = INF;
-            for (int32_t x = lane; x < n; x += 64) best = min(best, (uint32_t)Drow[x] + (uint32_t)col[x]);
-            best = wave_min(best);
+            const uint32_t best = wave_min_plus(Drow, col, n);
             if (best < (uint32_t)Drow[y]) {
                 changed = true;
                 if (lane == 0) Drow[y] = (int32_t)best;

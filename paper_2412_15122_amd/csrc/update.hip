@@ -239,10 +239,7 @@ __global__ __launch_bounds__(256) void k_add_in(DevGraph g, int32_t p, const int
         best = (uint32_t)ent.y + (uint32_t)Di[ent.x];
     }
     best = wave_min(best);
-    if (best > beta_eff) {
-        for (int32_t r = lane; r < g.n_slots; r += 64) best = min(best, (uint32_t)Di[r] + (uint32_t)wi[r]);
-        best = wave_min(best);
-    }
+    if (best > beta_eff) best = wave_min_plus_below(Di, wi, g.n_slots, best);  // only weights below best matter
     if (lane == 0) in[i] = (int32_t)min(best, INF);
 }
 
