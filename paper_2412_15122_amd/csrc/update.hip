@@ -433,10 +433,10 @@ void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int
 // were gathered before this launch, so in-place writes do not feed back.
 __device__ __forceinline__ void dec_relax_tile(const DevGraph &g, const int32_t *__restrict__ colu,
                                                const int32_t *__restrict__ colv, const int32_t *__restrict__ rowu,
-                                               const int32_t *__restrict__ rowv, int32_t w) {
+                                               const int32_t *__restrict__ rowv, int32_t w, int32_t rg) {
     const int n = g.n_slots;
     const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
-    const int32_t r0 = blockIdx.y * RELAX_ROWS;
+    const int32_t r0 = rg * RELAX_ROWS;
     if (c0 >= n) return;
     const uint32_t wn = (uint32_t)w;
     uint4 bv = *reinterpret_cast<const uint4 *>(rowv + c0);
@@ -522,6 +522,7 @@ size_t fused_lds_bytes(int32_t P) {
 //     Bellman-Ford over the light in-edge index.  Rows with more than ROW_CAP
 //     flags ("heavy") are left untouched and queued for pass B.
 constexpr int DETECT_ROWS = 8;
+constexpr int32_t EDGE_SWEEP_GROUPS = 256;  // work-group rows of the edge sweep's grid
 
 // OR of the 32-bit values of the 8 lanes of each aligned group of 8.
 __device__ __forceinline__ uint32_t or8(uint32_t v) {
@@ -532,11 +533,11 @@ __device__ __forceinline__ uint32_t or8(uint32_t v) {
 }
 
 template <int MODE>
-__device__ __forceinline__ void mask_detect_tile(const DevGraph &g, const FusedArgs &fa, uint32_t w_old) {
+__device__ __forceinline__ void mask_detect_tile(const DevGraph &g, const FusedArgs &fa, uint32_t w_old, int32_t rg) {
     const int n = g.n_slots;
     const int lane = lane_id();
     const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
-    const int32_t r0 = blockIdx.y * DETECT_ROWS;
+    const int32_t r0 = rg * DETECT_ROWS;
     const int64_t nwp = (g.P + 31) / 32;
     uint4 v1 = make_uint4(0, 0, 0, 0), v2 = v1;
     if (c0 < n) {
@@ -583,20 +584,26 @@ __device__ __forceinline__ void mask_detect_tile(const DevGraph &g, const FusedA
         if (__ballot(bits != 0) != 0) row_mask |= 1u << r;
     }
     const int32_t chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (lane == 0 && chunk * 256 < n) fa.marks[(int64_t)blockIdx.y * fa.mark_pitch + chunk] = (uint8_t)row_mask;
+    if (lane == 0 && chunk * 256 < n) fa.marks[(int64_t)rg * fa.mark_pitch + chunk] = (uint8_t)row_mask;
 }
 
 __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
-    mask_detect_tile<FUSED_REMOVE>(g, fa, 0u);
+    mask_detect_tile<FUSED_REMOVE>(g, fa, 0u, blockIdx.y);
 }
 
 // The edge update's sweep, chosen on the device: the relaxation of a decrease
 // (colu, colv, rowu, rowv = fa.col1, col2, row2, row1) or the mask of a tight
 // increase; nothing for a no-op.
+// Each work-group takes every gridDim.y-th group of 8 rows of its 1024
+// columns: a no-op launch (the common case) stays small.
 __global__ __launch_bounds__(256) void k_edge_sweep(DevGraph g, FusedArgs fa, int32_t w) {
     const int32_t mode = g.ctl->edge_mode;
-    if (mode == EDGE_DECREASE) dec_relax_tile(g, fa.col1, fa.col2, fa.row2, fa.row1, w);
-    else if (mode == EDGE_INCREASE) mask_detect_tile<FUSED_INCREASE>(g, fa, (uint32_t)g.ctl->w_old);
+    if (mode == EDGE_NOOP) return;
+    const int32_t groups = (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS;
+    for (int32_t rg = blockIdx.y; rg < groups; rg += gridDim.y) {
+        if (mode == EDGE_DECREASE) dec_relax_tile(g, fa.col1, fa.col2, fa.row2, fa.row1, w, rg);
+        else mask_detect_tile<FUSED_INCREASE>(g, fa, (uint32_t)g.ctl->w_old, rg);
+    }
 }
 
 // Does row i hold a flag?  (The OR of its group's marks, read by one wave.)
@@ -848,7 +855,8 @@ void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
 void launch_edge_sweep(const DevGraph &g, const FusedArgs &fa, int32_t w, hipStream_t s) {
     if (g.n_slots <= 0) return;
     static_assert(RELAX_ROWS == DETECT_ROWS, "one grid serves both sweeps");
-    dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS);
+    const int32_t groups = (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS;
+    dim3 grid((g.n_slots + 1023) / 1024, std::min(groups, EDGE_SWEEP_GROUPS));
     k_edge_sweep<<<grid, 256, 0, s>>>(g, fa, w);
 }
 
