@@ -210,6 +210,9 @@ apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out);
  * (and clears it). */
 apsp_status apsp_sync(apsp_graph *g);
 
+/* Later calls on g enqueue on hip_stream.  Nothing is enqueued: work
+ * already queued on g's previous stream is not ordered before the new
+ * stream's by the library (the caller orders them, e.g. with an event). */
 apsp_status apsp_set_stream(apsp_graph *g, void *hip_stream);
 
 /* Fallback policy of removals and edge increases; delta is Algorithm 5's
@@ -235,8 +238,9 @@ const char *apsp_kernel_name(int32_t kernel);
 
 /* A second handle with the same state as g (matrices, index, ids), in the
  * caller's buffer dev_buf of apsp_required_bytes(capacity of g, kind of g)
- * bytes, enqueued on hip_stream after waiting for g's stream.  The copy is
- * independent of g from then on.  Errors as apsp_cold. */
+ * bytes, enqueued on hip_stream after waiting for g's stream (g's stream
+ * then waits for the copy before g's next call).  The copy is independent
+ * of g from then on.  Errors as apsp_cold. */
 apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes, void *hip_stream,
                              apsp_graph **out);
 

@@ -284,7 +284,10 @@ apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes,
     bool ok = hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event") &&
               hip_ok(hipEventRecord(ev, g->stream), "event record") &&
               hip_ok(hipStreamWaitEvent(c->stream, ev, 0), "stream wait") &&
-              hip_ok(hipMemcpyAsync(c->base, g->base, L.total, hipMemcpyDeviceToDevice, c->stream), "clone copy");
+              hip_ok(hipMemcpyAsync(c->base, g->base, L.total, hipMemcpyDeviceToDevice, c->stream), "clone copy") &&
+              // g's later calls must not overwrite the source while it is copied
+              (c->stream == g->stream || (hip_ok(hipEventRecord(ev, c->stream), "event record") &&
+                                          hip_ok(hipStreamWaitEvent(g->stream, ev, 0), "stream wait")));
     if (ev) (void)hipEventDestroy(ev);
     if (!ok) {
         apsp_graph_destroy(c);
