@@ -487,7 +487,8 @@ def main():
                 ss = [st for k, st in trace if k == kind and not st["noop"]]
                 if not ss:
                     continue
-                keys = ("flagged", "rows", "heavy_rows", "sweeps", "full_scans", "rows_relaxed")
+                keys = ("flagged", "changed", "rows", "rows_changed", "heavy_rows", "sweeps", "full_scans",
+                        "rows_relaxed")
                 log(f"[bench] trace {kind}: {len(ss)} non-noop; " + ", ".join(
                     f"{k} mean {np.mean([st[k] for st in ss]):.1f} max {max(st[k] for st in ss)}" for k in keys))
         if step == 0:

@@ -100,7 +100,15 @@ typedef struct {
     int32_t full_scans;  /* in-edge scans that went past the light-edge index */
     int32_t sweeps;      /* largest number of relaxation sweeps of one row */
     int32_t rows_relaxed;/* rows touched by an add-node / decrease relaxation */
-    int32_t heavy_rows;  /* rows with more than 64 flagged pairs (one work-group each) */
+    int32_t heavy_rows;  /* rows with more than 32 flagged pairs (one work-group each) */
+    int32_t rows_changed;/* Phi': rows with at least one changed pair */
+    int64_t changed;     /* |F'|: flagged pairs whose distance changed -- the
+                          * refined need_update list of Algorithms 11 and 12:
+                          * by Theorem theo_algo12 (and its converse) exactly
+                          * the pairs whose every shortest path uses the
+                          * removed node (or the raised edge).  0 after a cold
+                          * fallback. */
+    double cost_refined; /* Phi' / (N - 1) */
 } apsp_update_stats;
 
 /* ---- sizing ------------------------------------------------------------ */

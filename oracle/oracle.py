@@ -15,6 +15,8 @@ slowly and visibly:
   built with Theorem "theorem_spd_4" / Corollary "corollary3"): pair (i,j)
   is listed when M[i][k] + M[k][j] equals M[i][j].
 * ``remove_cost`` -- Definition "def:cost_defi": Phi / (N - 1).
+* ``refined_set`` -- the refined need_update_list of Algorithms 11-12
+  (Theorem "theo_algo12"): the pairs whose distance changes.
 * ``edge_mask`` -- the same criterion applied to an edge (u,v): the pairs
   whose shortest distance can use the edge (see DESIGN for this reading).
 * ``canonical_path`` -- the lexicographically smallest shortest simple path,
@@ -226,6 +228,16 @@ def edge_mask(D: np.ndarray, u: int, v: int, w_old: int, undirected: bool) -> np
     F &= D < INF
     F[np.arange(n), np.arange(n)] = False
     return F
+
+
+def refined_set(D_before: np.ndarray, D_after: np.ndarray) -> np.ndarray:
+    """The refined need_update_list of Algorithms 11 and 12: the pairs whose
+    shortest distance differs between G and G' (both matrices over the same
+    nodes in the same order; for a removal, pass D_before without row and
+    column k).  By Theorem 'theo_algo12' a pair whose distance goes up had k
+    (or the raised edge) on every shortest path, and a pair with a shortest
+    path avoiding it keeps its distance, so this is the paper's refined list."""
+    return np.asarray(D_before, dtype=np.int64) != np.asarray(D_after, dtype=np.int64)
 
 
 def edge_scope(col_u, col_v, row_u, row_v, w: int) -> Tuple[int, int]:

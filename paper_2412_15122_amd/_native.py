@@ -50,6 +50,9 @@ class UpdateStats(ctypes.Structure):
         ("sweeps", ctypes.c_int32),
         ("rows_relaxed", ctypes.c_int32),
         ("heavy_rows", ctypes.c_int32),
+        ("rows_changed", ctypes.c_int32),
+        ("changed", ctypes.c_int64),
+        ("cost_refined", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -592,6 +592,8 @@ apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
     out->sweeps = c.sweeps;
     out->rows_relaxed = c.rows_relaxed;
     out->heavy_rows = c.heavy_count;
+    out->rows_changed = c.rows_changed;
+    out->changed = (int64_t)c.changed;
     out->fallback = g->last_fallback;
     int32_t kind = g->last_kind;
     if (kind == -1) {  // edge update: the device chose the path
@@ -599,8 +601,10 @@ apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
         out->noop = c.edge_mode == EDGE_NOOP;
     }
     out->kind = kind;
-    if (kind == UK_REMOVE || kind == UK_INCREASE)
+    if (kind == UK_REMOVE || kind == UK_INCREASE) {
         out->cost = g->last_n_before > 1 ? (double)c.rows / (double)(g->last_n_before - 1) : 0.0;
+        out->cost_refined = g->last_n_before > 1 ? (double)c.rows_changed / (double)(g->last_n_before - 1) : 0.0;
+    }
     if (kind == UK_REMOVE) out->noop = c.flagged == 0 && !g->last_fallback;
     return APSP_OK;
 }

@@ -24,6 +24,7 @@ constexpr int TILE = 128;        // Floyd-Warshall block / matrix padding
 constexpr int NIN_L = 64;        // light in-edge index entries per node
 constexpr int FUSED_GRID = 512;  // resident work-groups of the mask+recompute kernel
 constexpr int FUSED_THREADS = 1024;  // threads of a heavy-row work-group
+constexpr int RECOMPUTE_STATS = 6;   // rows, flagged, full scans, sweeps, changed, rows changed
 constexpr int ROW_CAP = 32;      // flagged columns listed per row (more: a "heavy" row)
 constexpr int RECOMPUTE_BLOCKS = 2048;  // work-groups of the per-row recompute (4 waves each)
 
@@ -44,10 +45,11 @@ struct Ctl {
     int32_t rows_relaxed;
     int32_t scope_r;
     int32_t scope_c;
-    int32_t reserved;
+    int32_t rows_changed; // rows with a flagged pair whose distance changed
     int32_t short_count;  // index lists queued for a rebuild
     int32_t heavy_count;  // rows deferred to the heavy-row pass
     int32_t pad[1];
+    unsigned long long changed;  // flagged pairs whose distance changed
 };
 
 // Device view of one graph, passed to kernels by value.
@@ -130,7 +132,7 @@ struct FusedArgs {
     uint32_t *row_bits;   // [P/32] rows holding a flag (batched launches); zero between updates
     uint8_t *marks;       // [P/8][mark_pitch(P)] per (8-row group, 256-column chunk): rows with a flag there
     int32_t mark_pitch;
-    int32_t *partials;    // [RECOMPUTE_BLOCKS][4] per-work-group statistics of the recompute
+    int32_t *partials;    // [RECOMPUTE_BLOCKS][RECOMPUTE_STATS] per-work-group statistics of the recompute
     int32_t epoch;        // distinct for every mask pass
 };
 // Removal: counters zeroed, colk[i] = D[i][k], rowk[j] = D[k][j].
@@ -139,7 +141,8 @@ void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *r
 // reset_only, just the clearing of the flag words when cold Floyd-Warshall
 // replaces the recompute.  launch_mask_recompute returns the number of
 // work-groups whose statistics (Phi, |F|, ...) the update's next kernel sums
-// into the control block (launch_remove_finish / launch_edge_finish).
+// into the control block (launch_remove_finish / launch_edge_finish), negated
+// when the heavy-row pass did not run (its partials are then not summed).
 void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s);
 int32_t launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s);
 void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s);  // Phi -> ctl->rows

@@ -1003,7 +1003,7 @@ __device__ inline int32_t chunk_graph(const int32_t *base, int32_t num_graphs, i
 template <int U>
 __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs,
                                                                      const BatchItem *items, const int32_t *tables) {
-    extern __shared__ __align__(16) uint32_t stage[];  // P words of select staging, then 4 wave lists of 2 ROW_CAP
+    extern __shared__ __align__(16) uint32_t stage[];  // P words of select staging, then the wave lists / need bitmap
     __shared__ SelectShared ssh;
     __shared__ int32_t s_claim, s_found_g, s_found_j;
     __shared__ int s_flag;
@@ -1168,7 +1168,12 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
 
 size_t batch_lds_bytes(int32_t P_max) { return (2 * (size_t)P_max + 4 * 2 * ROW_CAP) * sizeof(uint32_t); }
 
-size_t batch_lockstep_lds_bytes(int32_t P_max) { return ((size_t)P_max + 4 * 2 * ROW_CAP) * sizeof(uint32_t); }
+// The region after the P_max staging words holds the 4 wave lists of the
+// recompute phase, and later the need bitmap of the heavy-row phase (one bit
+// per column): whichever is larger.
+size_t batch_lockstep_lds_bytes(int32_t P_max) {
+    return ((size_t)P_max + std::max<size_t>(4 * 2 * ROW_CAP, ((size_t)P_max + 31) / 32)) * sizeof(uint32_t);
+}
 
 hipError_t configure_batch() {
     static hipError_t status = hipErrorNotReady;

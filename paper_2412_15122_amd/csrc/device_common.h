@@ -423,6 +423,18 @@ __device__ inline RowTests row_tests(const DevGraph &g, const FusedArgs &fa, int
     return r;
 }
 
+// The value D[i][y] had before the update, for a flagged y of row i: the
+// pair test that flagged it holds with equality (removal: D[i][k] + D[k][y];
+// increase: D[i][u] + w_old + D[v][y], or the swapped term when undirected).
+// A recomputed entry can only go up from here, so an entry back at this value
+// is final, and one above it belongs to the refined set (Theorem
+// theo_algo12: every shortest path of that pair used k, or the edge).
+__device__ inline uint32_t flagged_old(const FusedArgs &fa, const RowTests &rt, int32_t y) {
+    const uint32_t o1 = rt.t1 ? rt.a1 + (uint32_t)fa.row1[y] : INF;
+    const uint32_t o2 = rt.t2 ? rt.a2 + (uint32_t)fa.row2[y] : INF;
+    return min(o1, o2);
+}
+
 // Mask pass over row i.  Each lane tests 4 consecutive columns; 8 lanes
 // assemble a 32-bit flag word with shuffles (no clearing, no atomics).
 //   fill == 0: cur[j] = INF for flagged j, D[i][j] otherwise (fl = flags)
@@ -780,7 +792,7 @@ __device__ inline void query_block(const DevGraph &g, int32_t si, int32_t sj, in
 // the current value.  Columns left above their index bound get exhaustive
 // in-edge scans, and the sweeps resume if that changed anything.
 __device__ inline void wave_bellman_ford(const DevGraph &g, int32_t *Drow, const int32_t *list, int cnt, int32_t *fsl,
-                                  int &sweeps, int &nfs_total) {
+                                  int &sweeps, int &nfs_total, const int32_t *olds = nullptr) {
     const int lane = lane_id();
     const int g4 = lane >> 2, l4 = lane & 3;
     const int lim = g.lim;
@@ -792,6 +804,7 @@ __device__ inline void wave_bellman_ford(const DevGraph &g, int32_t *Drow, const
             for (int e = g4; e < cnt; e += 16) {
                 const int32_t y = list[e];
                 uint32_t best = (uint32_t)Drow[y];
+                if (olds && best == (uint32_t)olds[e]) continue;  // back at its old value: final
                 const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
                 for (int c0 = 0; c0 < lim; c0 += 32) {
                     // lane l4 of the group holds entries c0 + 4*l4 .. +3 and
@@ -840,7 +853,7 @@ __device__ inline void wave_bellman_ford(const DevGraph &g, int32_t *Drow, const
                 y = list[e];
                 uint32_t beta_eff = (uint32_t)g.nin_beta[y];
                 if (lim < NIN_L) beta_eff = min(beta_eff, (uint32_t)g.nin[(int64_t)y * NIN_L + lim].y);
-                need = (uint32_t)Drow[y] > beta_eff;
+                need = (uint32_t)Drow[y] > beta_eff && !(olds && Drow[y] == olds[e]);
             }
             const unsigned long long m = __ballot(need);
             if (need) fsl[nfs + __popcll(m & lanes_below())] = y;
@@ -890,6 +903,8 @@ __device__ inline void edge_begin_wave(const DevGraph &g, int32_t su, int32_t sv
         c->sweeps = 0;
         c->rows_relaxed = 0;
         c->heavy_count = 0;
+        c->changed = 0;
+        c->rows_changed = 0;
         g.A[(int64_t)su * ld + sv] = w;
         if (g.undirected) g.A[(int64_t)sv * ld + su] = w;
         else g.AT[(int64_t)sv * ld + su] = w;

@@ -63,7 +63,7 @@ inline Layout make_layout(int32_t cap, int32_t kind) {
     L.flag_bits = take(P * ((P + 31) / 32) * 4);
     L.row_bits = take(((P + 31) / 32) * 4);
     L.marks = take((P / 8) * mark_pitch(P));
-    L.partials = take((size_t)RECOMPUTE_BLOCKS * 4 * 4);
+    L.partials = take(((size_t)RECOMPUTE_BLOCKS * RECOMPUTE_STATS + 2 * (size_t)FUSED_GRID) * 4);
     L.ctl = take(sizeof(Ctl));
     L.total = off;
     return L;

@@ -21,6 +21,8 @@ __device__ __forceinline__ void reset_stats(Ctl *c) {
     c->scope_c = 0;
     c->short_count = 0;
     c->heavy_count = 0;
+    c->changed = 0;
+    c->rows_changed = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_edge_finish(DevGraph g, int32_t y0, int
     __shared__ SelectShared sh;
     __shared__ uint32_t red[8];
     extern __shared__ uint32_t stage[];
-    if (blockIdx.x == 0 && blocks > 0 && g.ctl->edge_mode == EDGE_INCREASE)
+    if (blockIdx.x == 0 && blocks != 0 && g.ctl->edge_mode == EDGE_INCREASE)
         mask_finish_block<256>(g, partials, blocks, red);
     nin_build_one(g, blockIdx.x == 0 ? y0 : y1, 1, sh, stage);
 }
@@ -636,14 +638,16 @@ __global__ __launch_bounds__(256) void k_count_flag_rows(DevGraph g, FusedArgs f
 __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa, int32_t reset_only) {
     __shared__ int32_t lists[4][ROW_CAP];
     __shared__ int32_t fsls[4][ROW_CAP];
-    __shared__ int32_t stat[4][4];
+    __shared__ int32_t olds[4][ROW_CAP];
+    __shared__ int32_t stat[4][RECOMPUTE_STATS];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     int32_t *list = lists[wv];
     int32_t *fsl = fsls[wv];
+    int32_t *old = olds[wv];
     const int n = g.n_slots;
     const int nw = (n + 31) / 32;
     const int64_t nwp = (g.P + 31) / 32;
-    int my_rows = 0, my_fs = 0, my_sweeps = 0, my_flagged = 0;
+    int my_rows = 0, my_fs = 0, my_sweeps = 0, my_flagged = 0, my_changed = 0, my_rows_changed = 0;
     const bool active = !(fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE);
     for (int32_t i = blockIdx.x * 4 + wv; active && i < n; i += gridDim.x * 4) {
         if (!row_marked(fa, n, i)) continue;
@@ -702,12 +706,21 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
         }
         int32_t *Drow = g.D + (int64_t)i * g.ld;
         __threadfence_block();
-        for (int e = lane; e < cnt; e += 64) Drow[list[e]] = (int32_t)INF;
+        for (int e = lane; e < cnt; e += 64) {
+            old[e] = Drow[list[e]];
+            Drow[list[e]] = (int32_t)INF;
+        }
         if (fa.mode == FUSED_REMOVE && lane == 0) Drow[fa.k] = (int32_t)INF;
         __threadfence_block();
         int sweeps = 0;
-        wave_bellman_ford(g, Drow, list, cnt, fsl, sweeps, my_fs);
+        wave_bellman_ford(g, Drow, list, cnt, fsl, sweeps, my_fs, old);
         my_sweeps = max(my_sweeps, sweeps);
+        // the refined set: flagged entries whose distance went up
+        int ch = 0;
+        for (int e = lane; e < cnt; e += 64) ch += Drow[list[e]] != old[e];
+        ch = wave_sum(ch);
+        my_changed += ch;
+        my_rows_changed += ch > 0;
         // undirected: D' is symmetric and so is the mask, so the final
         // entries of row i are also those of column i.  A heavy row j takes
         // its entry (j, i) from here; a light row j computes the same value
@@ -718,19 +731,21 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
                 g.D[(int64_t)y * g.ld + i] = Drow[y];
             }
     }
-    // statistics: one partial per work-group, summed by k_mask_finish
+    // statistics: one partial per work-group, summed by the update's next kernel
     if (lane == 0) {
         stat[wv][0] = my_rows;
         stat[wv][1] = my_flagged;
         stat[wv][2] = my_fs;
         stat[wv][3] = my_sweeps;
+        stat[wv][4] = my_changed;
+        stat[wv][5] = my_rows_changed;
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < RECOMPUTE_STATS) {
         const int q = threadIdx.x;
         int v = q == 3 ? max(max(stat[0][q], stat[1][q]), max(stat[2][q], stat[3][q]))
                        : stat[0][q] + stat[1][q] + stat[2][q] + stat[3][q];
-        fa.partials[blockIdx.x * 4 + q] = v;
+        fa.partials[blockIdx.x * RECOMPUTE_STATS + q] = v;
     }
 }
 
@@ -739,22 +754,39 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
 template <int NT>
 __device__ __forceinline__ void mask_finish_block(const DevGraph &g, const int32_t *partials, int32_t blocks,
                                                   uint32_t *red) {
-    int rows = 0, fs = 0, flagged = 0;
+    int rows = 0, fs = 0, flagged = 0, changed = 0, rows_changed = 0;
     uint32_t sw = 0;
+    // the heavy-row pass's (changed, rows changed) per work-group follow the
+    // recompute's partials; blocks < 0 means it did not run (-blocks groups)
+    const bool heavy = blocks > 0;
+    if (blocks < 0) blocks = -blocks;
+    if (heavy)
+        for (int b = threadIdx.x; b < FUSED_GRID; b += NT) {
+            const int32_t *hb = partials + (int64_t)RECOMPUTE_BLOCKS * RECOMPUTE_STATS + 2 * b;
+            changed += hb[0];
+            rows_changed += hb[1];
+        }
     for (int b = threadIdx.x; b < blocks; b += NT) {
-        rows += partials[b * 4 + 0];
-        flagged += partials[b * 4 + 1];
-        fs += partials[b * 4 + 2];
-        sw = max(sw, (uint32_t)partials[b * 4 + 3]);
+        const int32_t *pb = partials + (int64_t)b * RECOMPUTE_STATS;
+        rows += pb[0];
+        flagged += pb[1];
+        fs += pb[2];
+        sw = max(sw, (uint32_t)pb[3]);
+        changed += pb[4];
+        rows_changed += pb[5];
     }
     rows = block_sum<NT>(rows, red);
     flagged = block_sum<NT>(flagged, red);
     fs = block_sum<NT>(fs, red);
+    changed = block_sum<NT>(changed, red);
+    rows_changed = block_sum<NT>(rows_changed, red);
     sw = ~block_min<NT>(~sw, red);
     if (threadIdx.x == 0) {
         g.ctl->rows += rows;
         g.ctl->flagged += (unsigned long long)flagged;
         g.ctl->full_scans += fs;
+        g.ctl->changed += (unsigned long long)changed;
+        g.ctl->rows_changed += rows_changed;
         atomicMax(&g.ctl->sweeps, (int32_t)sw);
     }
 }
@@ -766,11 +798,37 @@ __device__ __forceinline__ void mask_finish_block(const DevGraph &g, const int32
 //   are recomputed by Bellman-Ford against the now exact remainder of the
 //   row.
 //   directed: every flagged entry is recomputed by Bellman-Ford.
+// Counts the changed pairs among row i's flagged entries (bits of the words
+// fl, read through `word`), whose final values are cur[], and adds them to
+// my_changed / my_rows_changed (block-uniform).
+template <class Word>
+__device__ __forceinline__ void heavy_count_changed(const FusedArgs &fa, const RowTests &rt, const uint32_t *cur,
+                                                    int nw, Word word, uint32_t *red, int &my_changed,
+                                                    int &my_rows_changed) {
+    int ch = 0;
+    for (int w = threadIdx.x; w < nw; w += FUSED_THREADS) {
+        uint32_t bits = word(w);
+        while (bits) {
+            const int32_t y = w * 32 + __ffs(bits) - 1;
+            bits &= bits - 1;
+            ch += cur[y] != flagged_old(fa, rt, y);
+        }
+    }
+    ch = block_sum<FUSED_THREADS>(ch, red);
+    my_changed += ch;
+    my_rows_changed += ch > 0;
+}
+
 __device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedArgs &fa, uint32_t *sm) {
     FusedShared sh = fused_shared(g, sm);
     const int n = g.n_slots;
     const int nw = (n + 31) >> 5;
     const int tid = threadIdx.x;
+    // this work-group's part of the refined-set statistics (summed with the
+    // recompute's partials by the update's next kernel)
+    int32_t *hp = fa.partials + (int64_t)RECOMPUTE_BLOCKS * RECOMPUTE_STATS + 2 * blockIdx.x;
+    int my_changed = 0, my_rows_changed = 0;
+    if (tid == 0) hp[0] = hp[1] = 0;
     uint32_t w_old = 0;
     if (fa.mode == FUSED_INCREASE) {
         if (g.ctl->edge_mode != EDGE_INCREASE) return;
@@ -794,15 +852,12 @@ __device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedA
         __syncthreads();
         for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
             const int32_t i = fa.heavy_rows[idx];
+            const RowTests rt = row_tests(g, fa, i, w_old);
             int32_t *Drow = g.D + (int64_t)i * g.ld;
             for (int32_t c = tid * 4; c < n; c += FUSED_THREADS * 4)
                 *reinterpret_cast<uint4 *>(sh.cur + c) = *reinterpret_cast<const uint4 *>(Drow + c);
             uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
-            for (int w = tid; w < nw; w += FUSED_THREADS) {
-                const uint32_t x = fw[w];
-                if (x) fw[w] = 0u;  // read once: the bitmap is left clear
-                sh.fl2[w] = x & sh.fl[w];
-            }
+            for (int w = tid; w < nw; w += FUSED_THREADS) sh.fl2[w] = fw[w] & sh.fl[w];
             __syncthreads();
             const int todo = compact_bits(sh.fl2, nw, glist, sh.red);
             for (int e = tid; e < todo; e += FUSED_THREADS) sh.cur[glist[e]] = INF;
@@ -816,9 +871,21 @@ __device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedA
             }
             if (tid == 0) my_sweeps = max(my_sweeps, sweeps);
             __syncthreads();
+            // cur holds every final entry of the row (the light-row entries
+            // came in mirrored); count the changed ones over all the row's
+            // flags, then clear its words: the bitmap is left clear
+            heavy_count_changed(fa, rt, sh.cur, nw, [&](int w) { return fw[w]; }, sh.red, my_changed,
+                                my_rows_changed);
+            for (int w = tid; w < nw; w += FUSED_THREADS)
+                if (fw[w]) fw[w] = 0u;
+            __syncthreads();
         }
         if (tid == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
         if (tid == 0 && my_sweeps) atomicMax(&g.ctl->sweeps, my_sweeps);
+        if (tid == 0) {
+            hp[0] = my_changed;
+            hp[1] = my_rows_changed;
+        }
         return;
     }
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
@@ -836,9 +903,15 @@ __device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedA
         }
         if (tid == 0) my_sweeps = max(my_sweeps, sweeps);
         __syncthreads();
+        heavy_count_changed(fa, rt, sh.cur, nw, [&](int w) { return sh.fl[w]; }, sh.red, my_changed, my_rows_changed);
+        __syncthreads();
     }
     if (tid == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
     if (tid == 0 && my_sweeps) atomicMax(&g.ctl->sweeps, my_sweeps);
+    if (tid == 0) {
+        hp[0] = my_changed;
+        hp[1] = my_rows_changed;
+    }
 }
 
 __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, FusedArgs fa) {
@@ -868,7 +941,8 @@ int32_t launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t re
     if (g.n_slots <= 0) return 0;
     const int blocks = std::min(RECOMPUTE_BLOCKS, (g.n_slots + 3) / 4);
     k_recompute_rows<<<blocks, 256, 0, s>>>(g, fa, reset_only);
-    if (!reset_only) k_fused_heavy<<<FUSED_GRID, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
+    if (reset_only) return -blocks;  // no heavy-row pass: its partials are not summed
+    k_fused_heavy<<<FUSED_GRID, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
     return blocks;
 }
 

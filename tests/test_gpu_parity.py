@@ -155,6 +155,47 @@ def test_remove_mask_statistics(undirected):
 
 
 @pytest.mark.parametrize("undirected", [False, True])
+def test_refined_set_statistics(undirected):
+    """|F'| and Phi' (the refined need_update list: pairs whose distance
+    changed) after removals and tight edge increases, against the oracle's
+    matrices before and after; small weights give many ties, so F' is much
+    smaller than F, and rows with more than 32 flags take the heavy-row
+    pass."""
+    rng = np.random.default_rng(91 + undirected)
+    n = 260
+    adj = W.random_graph(n, 1, 12, undirected=undirected, seed=33 + undirected)
+    g = lib_graph(adj, undirected, capacity=n)
+    A, ids = adj.copy(), list(range(n))
+    saw_heavy = False
+    for step in range(8):
+        D = O.fw(A)
+        if step % 2 == 0:
+            k = ids[int(rng.integers(len(ids)))]
+            kc = ids.index(k)
+            g.remove_node(k)
+            A2, ids2 = O.apply_update(A, ids, "remove", u=k, undirected=undirected)
+            keep = [t for t in range(len(ids)) if t != kc]
+            R = O.refined_set(D[np.ix_(keep, keep)], O.fw(A2))
+        else:
+            tight = [(u, v) for u in range(len(ids)) for v in range(len(ids))
+                     if u != v and A[u, v] == D[u, v] and A[u, v] < INF]
+            u, v = tight[int(rng.integers(len(tight)))]
+            w_new = int(A[u, v]) + 7
+            g.update_edge(ids[u], ids[v], w_new)
+            A2, ids2 = O.apply_update(A, ids, "edge", u=ids[u], v=ids[v], w=w_new, undirected=undirected)
+            R = O.refined_set(D, O.fw(A2))
+        s = g.stats()
+        saw_heavy |= s["heavy_rows"] > 0
+        phi = int(np.count_nonzero(R.any(axis=1)))
+        assert s["changed"] == int(R.sum()) and s["rows_changed"] == phi, (step, s, int(R.sum()), phi)
+        assert abs(s["cost_refined"] - phi / (len(ids) - 1)) < 1e-12
+        assert s["changed"] <= s["flagged"] and s["rows_changed"] <= s["rows"]
+        A, ids = A2, ids2
+        expect_equal(g, A, ids, f"step {step}")
+    assert saw_heavy
+
+
+@pytest.mark.parametrize("undirected", [False, True])
 def test_edge_increase_mask_statistics(undirected):
     adj = W.random_graph(150, 1, 8, undirected=undirected, seed=21 + undirected)
     g = lib_graph(adj, undirected, capacity=150)

@@ -328,3 +328,60 @@ def test_apply_update_semantics():
     E, _ = O.apply_update(C, ids3, "decrease", u=9, v=0, w=0, undirected=True)
     assert E[1, 0] == 0 and E[0, 1] == 0
     assert O.apply_update(np.zeros((0, 0), np.int32), [], "add", w_out=[], w_in=[])[1] == [0]
+
+
+# ---------------------------------------------------------------------------
+# the refined need_update list (Algorithms 11-12, Theorem theo_algo12)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_refined_set_is_pairs_whose_every_shortest_path_uses_k(undirected):
+    """Brute force over simple paths (n <= 7, small weights: many ties): the
+    pairs whose distance changes when k is removed are exactly those whose
+    every shortest simple path passes through k, and they lie inside the
+    need_update list."""
+    rng = np.random.default_rng(123 + undirected)
+    for trial in range(25):
+        n = int(rng.integers(3, 8))
+        A = W.random_graph(n, 1, 3, undirected=undirected, density=float(rng.uniform(0.4, 1.0)),
+                           seed=int(rng.integers(1 << 30)))
+        D = O.fw(A)
+        k = int(rng.integers(n))
+        keep = [t for t in range(n) if t != k]
+        A2 = A[np.ix_(keep, keep)]
+        R = O.refined_set(D[np.ix_(keep, keep)], O.fw(A2))
+        F = O.remove_mask(D, k)[np.ix_(keep, keep)]
+        assert not (R & ~F).any(), "a changed pair outside the need_update list"
+        for a, i in enumerate(keep):
+            for b, j in enumerate(keep):
+                if i == j:
+                    continue
+                paths = O.all_shortest_simple_paths(A, i, j)
+                all_use_k = bool(paths) and all(k in p[1:-1] for p in paths)
+                assert R[a, b] == all_use_k, (trial, i, j, k)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_refined_set_of_a_raised_edge_is_pairs_whose_every_shortest_path_uses_it(undirected):
+    rng = np.random.default_rng(321 + undirected)
+    for trial in range(25):
+        n = int(rng.integers(3, 8))
+        A = W.random_graph(n, 1, 3, undirected=undirected, density=1.0, seed=int(rng.integers(1 << 30)))
+        D = O.fw(A)
+        u, v = (int(x) for x in rng.choice(n, 2, replace=False))
+        w_new = int(A[u, v]) + int(rng.integers(1, 4))
+        A2, _ = O.apply_update(A, list(range(n)), "edge", u=u, v=v, w=w_new, undirected=undirected)
+        R = O.refined_set(D, O.fw(A2))
+        F = O.edge_mask(D, u, v, int(A[u, v]), undirected)
+        assert not (R & ~F).any()
+
+        def uses(p):
+            steps = list(zip(p[:-1], p[1:]))
+            return (u, v) in steps or (undirected and (v, u) in steps)
+
+        for i in range(n):
+            for j in range(n):
+                if i == j:
+                    continue
+                paths = O.all_shortest_simple_paths(A, i, j)
+                assert R[i, j] == (bool(paths) and all(uses(p) for p in paths)), (trial, i, j, u, v)
