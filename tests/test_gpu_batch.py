@@ -247,3 +247,48 @@ def test_config4_shape_sample():
     for gi in range(len(ga)):
         assert_same(ga[gi], gb[gi], f"graph {gi} n={wls[gi].adj.shape[0]}")
         assert_same(gc[gi], gb[gi], f"lockstep graph {gi} n={wls[gi].adj.shape[0]}")
+
+
+def test_lockstep_large_pitch_heavy_rows_tiny_index():
+    """A graph whose pitch exceeds 8192 columns (its heavy-row need bitmap is
+    longer than the lockstep wave lists it shares LDS with), small weights
+    (many ties: rows with more than 32 flags) and an index of 2 entries
+    (recomputed entries above the bound take exhaustive scans), beside small
+    graphs: the lockstep batch equals the single calls."""
+    from paper_2412_15122_amd.apsp import Graph
+    from paper_2412_15122_amd.batch import Batch
+    import torch
+    rng = np.random.default_rng(5)
+    sizes = [8300, 40, 300]
+    adjs = [W.random_graph(n, 1, 6, seed=500 + i) for i, n in enumerate(sizes)]
+    ga = [Graph(a, capacity=a.shape[0] + 4) for a in adjs]
+    for g in ga:
+        g.set_index_limit(2)
+    gb = [g.clone() for g in ga]
+    items = []
+    for gi, a in enumerate(adjs):
+        n = a.shape[0]
+        ones = np.argwhere(a == 1)
+        ones = ones[ones[:, 0] != ones[:, 1]]
+        removed = set()
+        for t in range(3):
+            u, v = (int(x) for x in ones[int(rng.integers(len(ones)))])
+            if u not in removed and v not in removed:
+                items.append(("edge", gi, u, v, 4))   # a weight-1 edge is tight: the increase masks
+            k = int(rng.integers(n))
+            while k in removed:
+                k = int(rng.integers(n))
+            removed.add(k)
+            items.append(("remove", gi, k))
+    b = Batch(len(ga), len(items), variant=3, use_graph=True)
+    log("items", len(items))
+    b.run(ga, items)
+    b.status()
+    torch.cuda.synchronize()
+    replay_single(gb, items)
+    for gi in range(len(ga)):
+        assert_same(ga[gi], gb[gi], f"graph {gi} n0={sizes[gi]}")
+        ga[gi].sync()
+    b.close()
+    for g in ga + gb:
+        g.close()
