@@ -19,6 +19,8 @@ slowly and visibly:
   (Theorem "theo_algo12"): the pairs whose distance changes.
 * ``edge_mask`` -- the same criterion applied to an edge (u,v): the pairs
   whose shortest distance can use the edge (see DESIGN for this reading).
+* ``pair_nodes`` -- the nodes on some / on every shortest i -> j path
+  (Algorithms 7, 8 and 10: candidate_node_list and key_node_list).
 * ``canonical_path`` -- the lexicographically smallest shortest simple path,
   taken greedily among Algorithm 7's candidates (correct when w >= 1).
 * ``apply_update`` -- the updated graph G' of the notation table (G + p,
@@ -289,6 +291,50 @@ def canonical_path(A: np.ndarray, D: np.ndarray, i: int, j: int) -> List[int]:
 # ---------------------------------------------------------------------------
 # the updated graph G'
 # ---------------------------------------------------------------------------
+
+def pair_nodes(A: np.ndarray, D: np.ndarray, i: int, j: int) -> Tuple[List[int], List[int]]:
+    """The nodes of the shortest i -> j paths, in compact positions, ascending.
+
+    on  -- Algorithm 7's candidate_node_list (Theorem 'al_correct'), which is
+           the node set of Algorithm 8's paths: every t with
+           D[i][t] (+) D[t][j] == D[i][j], i and j included.
+    key -- Algorithm 10's key_node_list of the pair: the nodes other than i
+           and j that every shortest i -> j walk visits.  Written out by its
+           definition: t is one when j cannot be reached from i over tight
+           edges (x -> y with D[i][x] (+) A[x][y] == D[i][y], both on) once t
+           is taken out -- a walk over tight edges from i to j has length
+           D[i][j], and every shortest walk is one.
+    i == j gives ([i], []); an unreachable pair ([], [])."""
+    A = _check_adj(A).astype(np.int64)
+    D = np.asarray(D, dtype=np.int64)
+    if i == j:
+        return [i], []
+    d = D[i, j]
+    if d >= INF:
+        return [], []
+    n = D.shape[0]
+    on = [t for t in range(n) if oplus(D[i, t], D[t, j]) == d]
+    on_set = set(on)
+
+    def reaches_without(t):
+        seen = {i}
+        stack = [i]
+        while stack:
+            x = stack.pop()
+            if x == j:
+                return True
+            for y in on:
+                if y in seen or y == t or y == x:
+                    continue
+                if A[x, y] < INF and D[i, x] + A[x, y] == D[i, y]:
+                    seen.add(y)
+                    stack.append(y)
+        return False
+
+    key = [t for t in on if t != i and t != j and not reaches_without(t)]
+    assert i in on_set and j in on_set
+    return on, key
+
 
 def apply_update(A: np.ndarray, ids: List[int], kind: str, *, u: int = -1, v: int = -1,
                  w: int = 0, w_out=None, w_in=None, undirected: bool = False):

@@ -385,3 +385,51 @@ def test_refined_set_of_a_raised_edge_is_pairs_whose_every_shortest_path_uses_it
                     continue
                 paths = O.all_shortest_simple_paths(A, i, j)
                 assert R[i, j] == (bool(paths) and all(uses(p) for p in paths)), (trial, i, j, u, v)
+
+
+# ---------------------------------------------------------------------------
+# nodes of the shortest paths of a pair (Algorithms 7, 8, 10)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("undirected", [False, True])
+@pytest.mark.parametrize("zero", [0.0, 0.3])
+def test_pair_nodes_against_all_shortest_simple_paths(undirected, zero):
+    """Brute force over simple paths (n <= 7, small weights: many ties; with
+    and without zero-weight edges): key nodes are the intersection of all
+    shortest simple paths without the endpoints; with positive weights the
+    candidate set is their union, with zero weights it contains it."""
+    rng = np.random.default_rng(7 + undirected + int(10 * zero))
+    for trial in range(40):
+        n = int(rng.integers(2, 8))
+        A = W.random_graph(n, 1, 3, undirected=undirected, density=float(rng.uniform(0.3, 1.0)),
+                           seed=int(rng.integers(1 << 30)), zero_frac=zero)
+        D = O.fw(A)
+        i, j = (int(x) for x in rng.integers(0, n, size=2))
+        on, key = O.pair_nodes(A, D, i, j)
+        if i == j:
+            assert on == [i] and key == []
+            continue
+        paths = O.all_shortest_simple_paths(A, i, j)
+        if not paths:
+            assert on == [] and key == [] and D[i, j] >= INF
+            continue
+        union = sorted(set().union(*map(set, paths)))
+        inter = sorted(set.intersection(*map(set, paths)) - {i, j})
+        assert key == inter, (trial, i, j)
+        if zero == 0.0:
+            assert on == union, (trial, i, j)
+        else:
+            assert set(union) <= set(on)
+
+
+def test_pair_nodes_of_a_path_graph():
+    """A chain with a shortcut: 0-1-2-3-4, plus 1->3 of the same length as
+    1-2-3: every node is on a shortest 0->4 path, 1 and 3 are key nodes, 2
+    is not."""
+    A = np.full((5, 5), INF, dtype=np.int32)
+    for a, b in ((0, 1), (1, 2), (2, 3), (3, 4)):
+        A[a, b] = 1
+    A[1, 3] = 2
+    D = O.fw(A)
+    on, key = O.pair_nodes(A, D, 0, 4)
+    assert on == [0, 1, 2, 3, 4] and key == [1, 3]
