@@ -542,6 +542,26 @@ def main():
             "algorithmic_bytes_per_launch": round(alg / max(c, 1)),
         }
 
+    # synchronous single-pair queries on the final graph (host-observed latency)
+    qrng = np.random.default_rng(4242)
+    live = g.ids()
+    q_path, q_nodes, q_cand, q_key = [], [], [], []
+    for _ in range(64):
+        a, b = (live[int(x)] for x in qrng.integers(0, len(live), size=2))
+        t0 = time.perf_counter()
+        g.query(a, b)
+        t1 = time.perf_counter()
+        _, on, key = g.query_nodes(a, b)
+        t2 = time.perf_counter()
+        q_path.append((t1 - t0) * 1e3)
+        q_nodes.append((t2 - t1) * 1e3)
+        q_cand.append(len(on))
+        q_key.append(len(key))
+    query_ms = {"pairs": len(q_path), "path_p50": round(float(np.median(q_path)), 4),
+                "nodes_p50": round(float(np.median(q_nodes)), 4),
+                "mean_candidates": round(float(np.mean(q_cand)), 2), "mean_key_nodes": round(float(np.mean(q_key)), 2)}
+    log(f"[bench] queries: {query_ms}")
+
     verify = None
     if not args.no_verify:
         # warm result == GPU cold Floyd-Warshall of the final graph
@@ -586,6 +606,7 @@ def main():
         "warm_vs_cold_speedup": round(cold_med / (ms_per_step / per), 1),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
                        "mean_by_kind": by_kind},
+        "query_ms": query_ms,
         "verified_vs_gpu_cold": verify,
         "roofline": roofline,
     }

@@ -15,6 +15,8 @@
  *   apsp_update_edge   one edge raised or lowered (Section 2.3, Algorithm 6;
  *                               done directly, see each call)
  *   apsp_query         warm single-pair shortest path (Section 3, Alg. 7)
+ *   apsp_query_nodes   nodes on some / on every shortest path of a pair
+ *                      (Algorithms 8 and 10)
  *
  * Values.  Weights and distances are int32 in [0, APSP_INF]; APSP_INF
  * (2^30) means "no edge" / "unreachable".  Path lengths saturate at
@@ -188,6 +190,28 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w);
  * path_cap is 0. */
 apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
                        int32_t *path_ids, int32_t path_cap, int32_t *path_len);
+
+/* The nodes of the shortest paths from i to j (Section 3: Algorithm 7's
+ * candidates, Theorem al_correct; Algorithm 8's paths; Algorithm 10's
+ * key_node_list).  *dist = D[i][j].
+ *   on_ids  (host, on_cap entries): every live t with
+ *           D[i][t] + D[t][j] == D[i][j], i and j included -- the nodes that
+ *           lie on some shortest walk from i to j (with positive weights, the
+ *           union of the node sets of all shortest paths).
+ *   key_ids (host, key_cap entries): the nodes other than i and j that every
+ *           shortest walk from i to j visits (the intersection of all
+ *           shortest paths, i and j taken out), computed exactly -- not from
+ *           a subset of the paths.
+ * Both ascending; *on_len / *key_len their lengths.  i == j: on = {i},
+ * key = {}; unreachable: both empty and *dist = APSP_INF.  If a buffer is
+ * too small, returns APSP_E_CAPACITY with *dist and both lengths set.
+ * A buffer may be NULL when its cap is 0.  Work: one pass over row i and
+ * column j, then O(K^2) adjacency reads for K candidates (more only for
+ * levels joined by zero-weight edges).  Uses the graph's update scratch:
+ * ordered on the graph's stream like every call. */
+apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
+                             int32_t *on_ids, int32_t on_cap, int32_t *on_len,
+                             int32_t *key_ids, int32_t key_cap, int32_t *key_len);
 
 /* Copy the live distance matrix (ascending-id order) into out_dev
  * (n x n, leading dimension out_ld >= n).  Asynchronous. */

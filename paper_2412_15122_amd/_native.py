@@ -93,6 +93,7 @@ SIGNATURES = {
     "apsp_remove_node": (_I32, [_P, _I32]),
     "apsp_update_edge": (_I32, [_P, _I32, _I32, _I32]),
     "apsp_query": (_I32, [_P, _I32, _I32, _PI32, _PI32, _I32, _PI32]),
+    "apsp_query_nodes": (_I32, [_P, _I32, _I32, _PI32, _PI32, _I32, _PI32, _PI32, _I32, _PI32]),
     "apsp_read_matrix": (_I32, [_P, _P, _I64]),
     "apsp_read_adjacency": (_I32, [_P, _P, _I64]),
     "apsp_node_count": (_I32, [_P, _PI32]),

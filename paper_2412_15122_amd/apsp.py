@@ -245,6 +245,17 @@ class Graph:
                 "apsp_query")
         return int(dist.value), list(buf[: ln.value])
 
+    def query_nodes(self, i: int, j: int) -> Tuple[int, List[int], List[int]]:
+        """(distance, ids on some shortest i -> j path, ids other than i and j
+        on every shortest i -> j path), both ascending (apsp_query_nodes)."""
+        cap = max(self.num_nodes(), 1)
+        on = (ctypes.c_int32 * cap)()
+        key = (ctypes.c_int32 * cap)()
+        dist, n_on, n_key = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        N.check(self._lib.apsp_query_nodes(self._h, int(i), int(j), ctypes.byref(dist), on, cap, ctypes.byref(n_on),
+                                           key, cap, ctypes.byref(n_key)), "apsp_query_nodes")
+        return int(dist.value), list(on[: n_on.value]), list(key[: n_key.value])
+
     def edge_scope(self, u: int, v: int) -> Tuple[int, int]:
         r = ctypes.c_int32()
         c = ctypes.c_int32()

@@ -96,7 +96,7 @@ apsp_status make_handle(int32_t capacity, int32_t kind, void *dev_buf, hipStream
     g->stream = stream;
     g->base = (char *)dev_buf;
     if (!hip_ok(hipHostMalloc((void **)&g->ctl_h, sizeof(Ctl), 0), "pinned alloc") ||
-        !hip_ok(hipHostMalloc((void **)&g->qbuf_h, (size_t)(g->P + 8) * 4, 0), "pinned alloc")) {
+        !hip_ok(hipHostMalloc((void **)&g->qbuf_h, (size_t)(2 * g->P + 8) * 4, 0), "pinned alloc")) {
         apsp_graph_destroy(g);
         return APSP_E_DEVICE;
     }
@@ -532,6 +532,36 @@ apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32
     *path_len = g->qbuf_h[1];
     if (*path_len > path_cap) return fail(APSP_E_CAPACITY, "apsp_query: path_cap too small");
     for (int32_t t = 0; t < *path_len; ++t) path_ids[t] = g->qbuf_h[3 + t];
+    return APSP_OK;
+}
+
+apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32_t *on_ids, int32_t on_cap,
+                             int32_t *on_len, int32_t *key_ids, int32_t key_cap, int32_t *key_len) {
+    if (!g || !dist || !on_len || !key_len) return fail(APSP_E_INVALID, "apsp_query_nodes: NULL argument");
+    if (on_cap < 0 || (on_cap > 0 && !on_ids) || key_cap < 0 || (key_cap > 0 && !key_ids))
+        return fail(APSP_E_INVALID, "apsp_query_nodes: bad output buffer");
+    int32_t si, sj;
+    if (!lookup(g, i, &si) || !lookup(g, j, &sj)) return fail(APSP_E_NOT_FOUND, "apsp_query_nodes: id is not live");
+    hipStream_t s = g->stream;
+    const int32_t n = g->n_live;
+    // output: 4 + 2 n ints at the start of the heavy-pass scratch; the
+    // per-work-group search space after it (the scratch is idle between updates)
+    int32_t *out = g->fscratch;
+    int32_t *bfs = g->fscratch + (((size_t)2 * g->P + 8 + 63) & ~(size_t)63);
+    g->prof.begin(KID_QUERY);
+    launch_query_nodes(g->dg, si, sj, g->rank_cur, n, out, g->qscratch, bfs, s);
+    g->prof.end();
+    apsp_status st = check_launch("apsp_query_nodes");
+    if (st) return st;
+    if (!hip_ok(hipMemcpyAsync(g->qbuf_h, out, (size_t)(4 + 2 * n) * 4, hipMemcpyDeviceToHost, s), "query copy") ||
+        !hip_ok(hipStreamSynchronize(s), "query sync"))
+        return APSP_E_DEVICE;
+    *dist = g->qbuf_h[0];
+    *on_len = g->qbuf_h[1];
+    *key_len = g->qbuf_h[2];
+    if (*on_len > on_cap || *key_len > key_cap) return fail(APSP_E_CAPACITY, "apsp_query_nodes: buffer too small");
+    std::copy(g->qbuf_h + 4, g->qbuf_h + 4 + *on_len, on_ids);
+    std::copy(g->qbuf_h + 4 + n, g->qbuf_h + 4 + n + *key_len, key_ids);
     return APSP_OK;
 }
 

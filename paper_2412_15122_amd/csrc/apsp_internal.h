@@ -161,6 +161,11 @@ void launch_edge_sweep(const DevGraph &g, const FusedArgs &fa, int32_t w, hipStr
 
 // Query / read-out.
 void launch_query(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch, hipStream_t s);
+// Nodes on some / on every shortest si -> sj path.  rank: the n_live live
+// slots in ascending-id order; out: 4 + 2 n_live ints; scratch: 4 P ints;
+// bfs: 2 P ints for each of 256 work-groups.
+void launch_query_nodes(const DevGraph &g, int32_t si, int32_t sj, const int32_t *rank, int32_t n_live,
+                        int32_t *out, int32_t *scratch, int32_t *bfs, hipStream_t s);
 void launch_gather_compact(const int32_t *src, int64_t ld, int32_t *dst, int64_t dst_ld,
                            const int32_t *slot_of_rank, int32_t n, hipStream_t s);
 void launch_edge_scope(const DevGraph &g, int32_t su, int32_t sv, hipStream_t s);

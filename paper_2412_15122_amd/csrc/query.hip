@@ -13,6 +13,209 @@ void launch_query(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32
     k_query<<<1, 1024, 0, s>>>(g, si, sj, out, scratch);
 }
 
+// ---- nodes on some / on every shortest path of a pair ----------------------
+// (Algorithms 7 and 8 give the candidates and the paths through them,
+// Theorem al_correct; Algorithm 10 intersects the pair's shortest paths.)
+//
+// Levels: L[t] = D[i][t].  Along a tight edge x -> y (both candidates,
+// L[x] + A[x][y] == L[y]) the level does not fall, and the tight walks from
+// i to j are exactly the shortest i -> j walks.  A candidate t other than i
+// and j is on every such walk iff (a) no tight edge jumps over its level
+// (L[x] < L[t] < L[y]) and (b) no walk crosses level L[t] avoiding t: with no
+// zero-weight tight edge inside the level, (b) holds iff t is alone on it;
+// otherwise a search inside the level decides, from the nodes entered from
+// below (or i) to the nodes that leave upward (or j).
+//
+// Scratch (4 P ints): cand[K] slots in ascending-id order, lev[K], reach[K]
+// (highest level a tight out-edge reaches, -1 if none), flags[K].
+// Output (4 + 2 n_live ints): dist, K, number of key nodes, 0, the K
+// candidate ids, then (at 4 + n_live) the key ids, both ascending.
+constexpr int QN_ENTRY = 1;  // a tight in-edge from a lower level
+constexpr int QN_INTRA = 2;  // a zero-weight tight edge to or from the same level
+constexpr int QN_KEY = 4;
+constexpr int QN_GRID = 256;  // work-groups of the per-candidate pass
+// The caller places the output (2 P + 8 ints, rounded up) and QN_GRID search
+// spaces of 2 P ints in the heavy-pass scratch of FUSED_GRID * 2 P ints.
+static_assert(2 * QN_GRID + 3 <= 2 * FUSED_GRID, "query-nodes scratch exceeds the heavy-pass scratch");
+
+__global__ __launch_bounds__(1024) void k_qn_gather(DevGraph g, int32_t si, int32_t sj, const int32_t *__restrict__ rank,
+                                                    int32_t n_live, int32_t *out, int32_t *scratch) {
+    __shared__ uint32_t red[16];
+    __shared__ int s_base;
+    int32_t *cand = scratch, *lev = scratch + g.P, *reach = scratch + 2 * g.P, *flags = scratch + 3 * g.P;
+    const int64_t ld = g.ld;
+    const uint32_t dist = (uint32_t)g.D[(int64_t)si * ld + sj];
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (int32_t r0 = 0; r0 < n_live; r0 += 1024) {
+        const int32_t r = r0 + threadIdx.x;
+        int32_t t = -1;
+        uint32_t lt = 0;
+        if (r < n_live && dist < INF) {
+            t = rank[r];
+            lt = (uint32_t)g.D[(int64_t)si * ld + t];
+            const uint32_t tj = (uint32_t)g.D[(int64_t)t * ld + sj];
+            const bool on = si == sj ? t == si : lt + tj == dist;
+            if (!on) t = -1;
+        }
+        int total;
+        const int off = block_exscan<1024>(t >= 0, red, &total);
+        const int c = s_base + off;
+        if (t >= 0) {
+            cand[c] = t;
+            lev[c] = (int32_t)lt;
+            reach[c] = -1;
+            flags[c] = 0;
+            out[4 + c] = g.id_of_slot[t];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_base += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = (int32_t)dist;
+        out[1] = s_base;
+        out[2] = 0;
+        out[3] = 0;
+    }
+}
+
+// One wave per candidate x: its tight out-edges to other candidates.
+__global__ __launch_bounds__(256) void k_qn_edges(DevGraph g, const int32_t *out, int32_t *scratch) {
+    const int32_t K = out[1];
+    const int32_t x = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (x >= K) return;
+    int32_t *cand = scratch, *lev = scratch + g.P, *reach = scratch + 2 * g.P, *flags = scratch + 3 * g.P;
+    const int32_t *arow = g.A + (int64_t)cand[x] * g.ld;
+    const uint32_t lx = (uint32_t)lev[x];
+    int32_t hi = -1;
+    int intra = 0;
+    for (int32_t y = lane_id(); y < K; y += 64) {
+        const uint32_t a = (uint32_t)arow[cand[y]];
+        const uint32_t ly = (uint32_t)lev[y];
+        if (y == x || a >= INF || lx + a != ly) continue;
+        if (ly > lx) {
+            hi = max(hi, (int32_t)ly);
+            atomicOr(&flags[y], QN_ENTRY);
+        } else {
+            intra = 1;
+            atomicOr(&flags[y], QN_INTRA);
+        }
+    }
+    hi = (int32_t)wave_max((uint32_t)(hi + 1)) - 1;
+    intra = __any(intra);
+    if (lane_id() == 0) {
+        reach[x] = hi;
+        if (intra) atomicOr(&flags[x], QN_INTRA);
+    }
+}
+
+// Is candidate t on every tight i -> j walk?  One work-group per candidate
+// (grid-stride); `bfs` holds 2 P ints per work-group.
+__global__ __launch_bounds__(256) void k_qn_key(DevGraph g, int32_t si, int32_t sj, const int32_t *out,
+                                                int32_t *scratch, int32_t *bfs) {
+    __shared__ uint32_t vis[APSP_MAX_CAPACITY / 32 + 1];
+    __shared__ int s_m, s_tail, s_found;
+    const int32_t K = out[1];
+    int32_t *cand = scratch, *lev = scratch + g.P, *reach = scratch + 2 * g.P, *flags = scratch + 3 * g.P;
+    int32_t *mem = bfs + (int64_t)blockIdx.x * 2 * g.P;  // level members (candidate indices)
+    int32_t *q = mem + g.P;                              // search queue (member indices)
+    const int tid = threadIdx.x;
+    for (int32_t t = blockIdx.x; t < K; t += gridDim.x) {
+        const int32_t st = cand[t];
+        if (st == si || st == sj) continue;
+        const int32_t lt = lev[t];
+        int jumped = 0, same = 0, intra = 0;
+        for (int32_t x = tid; x < K; x += 256) {
+            const int32_t lx = lev[x];
+            jumped |= lx < lt && reach[x] > lt;
+            same |= x != t && lx == lt;
+            intra |= lx == lt && (flags[x] & QN_INTRA);
+        }
+        jumped = __syncthreads_or(jumped);
+        same = __syncthreads_or(same);
+        intra = __syncthreads_or(intra);
+        bool key;
+        if (jumped) {
+            key = false;
+        } else if (!same) {
+            key = true;
+        } else if (!intra) {
+            key = false;
+        } else {
+            // Search inside level lt, without t, from the entries to the exits.
+            if (tid == 0) { s_m = 0; s_tail = 0; s_found = 0; }
+            __syncthreads();
+            for (int32_t x = tid; x < K; x += 256)
+                if (x != t && lev[x] == lt) mem[atomicAdd(&s_m, 1)] = x;
+            __syncthreads();
+            const int M = s_m;
+            for (int w = tid; w < (M + 31) / 32; w += 256) vis[w] = 0;
+            __syncthreads();
+            for (int m = tid; m < M; m += 256) {
+                const int32_t x = mem[m];
+                if (cand[x] == si || (flags[x] & QN_ENTRY)) {
+                    atomicOr(&vis[m >> 5], 1u << (m & 31));
+                    q[atomicAdd(&s_tail, 1)] = m;
+                    if (cand[x] == sj || reach[x] > lt) s_found = 1;
+                }
+            }
+            __syncthreads();
+            int head = 0, tail = s_tail;
+            __syncthreads();
+            while (!s_found && head < tail) {
+                const int64_t pairs = (int64_t)(tail - head) * M;
+                for (int64_t e = tid; e < pairs; e += 256) {
+                    const int a = q[head + (int)(e / M)], b = (int)(e % M);
+                    if ((vis[b >> 5] >> (b & 31)) & 1u) continue;
+                    if (g.A[(int64_t)cand[mem[a]] * g.ld + cand[mem[b]]] != 0) continue;
+                    const uint32_t was = atomicOr(&vis[b >> 5], 1u << (b & 31));
+                    if ((was >> (b & 31)) & 1u) continue;
+                    q[atomicAdd(&s_tail, 1)] = b;
+                    const int32_t y = mem[b];
+                    if (cand[y] == sj || reach[y] > lt) s_found = 1;
+                }
+                __syncthreads();
+                head = tail;
+                tail = s_tail;
+                __syncthreads();
+            }
+            key = !s_found;
+            __syncthreads();
+        }
+        if (key && tid == 0) atomicOr(&flags[t], QN_KEY);
+    }
+}
+
+// The key ids, ascending (candidates are in ascending-id order).
+__global__ __launch_bounds__(1024) void k_qn_emit(DevGraph g, int32_t n_live, int32_t *out, const int32_t *scratch) {
+    __shared__ uint32_t red[16];
+    __shared__ int s_base;
+    const int32_t K = out[1];
+    const int32_t *cand = scratch, *flags = scratch + 3 * g.P;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (int32_t c0 = 0; c0 < K; c0 += 1024) {
+        const int32_t c = c0 + threadIdx.x;
+        const int key = c < K && (flags[c] & QN_KEY);
+        int total;
+        const int off = block_exscan<1024>(key, red, &total);
+        if (key) out[4 + n_live + s_base + off] = g.id_of_slot[cand[c]];
+        __syncthreads();
+        if (threadIdx.x == 0) s_base += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[2] = s_base;
+}
+
+void launch_query_nodes(const DevGraph &g, int32_t si, int32_t sj, const int32_t *rank, int32_t n_live,
+                        int32_t *out, int32_t *scratch, int32_t *bfs, hipStream_t s) {
+    k_qn_gather<<<1, 1024, 0, s>>>(g, si, sj, rank, n_live, out, scratch);
+    k_qn_edges<<<(n_live + 3) / 4, 256, 0, s>>>(g, out, scratch);
+    k_qn_key<<<QN_GRID, 256, 0, s>>>(g, si, sj, out, scratch, bfs);
+    k_qn_emit<<<1, 1024, 0, s>>>(g, n_live, out, scratch);
+}
+
 // dst[a][b] = src[slot[a]][slot[b]] for a, b < n.
 __global__ void k_gather_compact(const int32_t *__restrict__ src, int64_t ld, int32_t *__restrict__ dst,
                                  int64_t dst_ld, const int32_t *__restrict__ slot, int32_t n) {

@@ -433,3 +433,28 @@ def test_pair_nodes_of_a_path_graph():
     D = O.fw(A)
     on, key = O.pair_nodes(A, D, 0, 4)
     assert on == [0, 1, 2, 3, 4] and key == [1, 3]
+
+
+@pytest.mark.parametrize("zero", [0.0, 0.3])
+def test_key_nodes_decide_removals(zero):
+    """What Algorithm 10 uses the key nodes for: removing a key node of (i, j)
+    raises D[i][j]; removing any other node leaves it (checked by a cold
+    Floyd-Warshall of the graph without that node)."""
+    rng = np.random.default_rng(41 + int(10 * zero))
+    for trial in range(25):
+        n = int(rng.integers(3, 12))
+        A = W.random_graph(n, 1, 3, density=float(rng.uniform(0.2, 0.7)), seed=int(rng.integers(1 << 30)),
+                           zero_frac=zero)
+        D = O.fw(A)
+        i, j = (int(x) for x in rng.choice(n, size=2, replace=False))
+        on, key = O.pair_nodes(A, D, i, j)
+        for k in range(n):
+            if k in (i, j):
+                continue
+            keep = [t for t in range(n) if t != k]
+            D2 = O.fw(A[np.ix_(keep, keep)])
+            d2 = D2[keep.index(i), keep.index(j)]
+            if k in key:
+                assert d2 > D[i, j], (trial, k)
+            else:
+                assert d2 == D[i, j], (trial, k)
