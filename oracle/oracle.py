@@ -11,6 +11,10 @@ slowly and visibly:
 * ``brute_force_apsp`` / ``all_shortest_simple_paths`` -- enumeration of
   simple paths, straight from the definition of a path (the notation table's
   loop-free sequence Psi and the set Theta of all i->j paths); tiny n only.
+* ``minimax_apsp`` / ``brute_force_minimax`` / ``minimax_by_thresholds`` --
+  minimax (bottleneck) distances, the (min, max) variant of the discussion
+  section: Floyd-Warshall with max, enumeration of simple paths, and
+  reachability under a weight threshold.
 * ``remove_mask`` -- the need_update_list of a node removal (Section 2.2,
   built with Theorem "theorem_spd_4" / Corollary "corollary3"): pair (i,j)
   is listed when M[i][k] + M[k][j] equals M[i][j].
@@ -193,17 +197,73 @@ def all_shortest_simple_paths(A: np.ndarray, i: int, j: int) -> List[Tuple[int, 
 
 
 # ---------------------------------------------------------------------------
+# minimax (bottleneck) paths: the (min, max) semiring
+# ---------------------------------------------------------------------------
+
+def minimax_apsp(A: np.ndarray) -> np.ndarray:
+    """Minimax distances: MM(i,j) = min over walks i -> j of the largest edge
+    weight on the walk, MM(i,i) = 0, INF if j is unreachable -- the path
+    problem the paper's discussion section names as a variant.  Textbook
+    Floyd-Warshall with max in place of +, one numpy step per pivot."""
+    D = _check_adj(A).astype(np.int64)
+    n = D.shape[0]
+    D[np.arange(n), np.arange(n)] = 0
+    for k in range(n):
+        D = np.minimum(D, np.maximum(D[:, k:k + 1], D[k:k + 1, :]))
+    return D.astype(np.int32)
+
+
+def brute_force_minimax(A: np.ndarray) -> np.ndarray:
+    """MM(i,j) = min over all simple i->j paths of the largest edge weight
+    (a walk's cycles can be cut without raising its largest edge), n <= 8."""
+    A = _check_adj(A)
+    n = A.shape[0]
+    assert n <= 8, "brute force is for tiny graphs"
+    D = np.full((n, n), INF, dtype=np.int64)
+    for i in range(n):
+        for j in range(n):
+            for seq, L in _simple_paths(A, i, j):
+                if L >= INF:
+                    continue
+                D[i, j] = min(D[i, j], max((int(A[a, b]) for a, b in zip(seq[:-1], seq[1:])), default=0))
+    return D.astype(np.int32)
+
+
+def minimax_by_thresholds(A: np.ndarray) -> np.ndarray:
+    """MM(i,j) as the least threshold theta (0 or an edge weight) at which j
+    is reachable from i over edges of weight <= theta: reachability by
+    breadth-first search, one threshold at a time."""
+    A = _check_adj(A).astype(np.int64)
+    n = A.shape[0]
+    D = np.full((n, n), INF, dtype=np.int64)
+    levels = sorted({0} | {int(w) for w in A[A < INF]})
+    for theta in reversed(levels):
+        adj = (A <= theta)
+        for i in range(n):
+            seen = np.zeros(n, dtype=bool)
+            seen[i] = True
+            frontier = [i]
+            while frontier:
+                nxt = np.nonzero(adj[frontier].any(axis=0) & ~seen)[0]
+                seen[nxt] = True
+                frontier = list(nxt)
+            D[i, seen] = theta
+    return D.astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
 # masks, cost, query
 # ---------------------------------------------------------------------------
 
-def remove_mask(D: np.ndarray, k: int) -> np.ndarray:
+def remove_mask(D: np.ndarray, k: int, minimax: bool = False) -> np.ndarray:
     """need_update_list of removing compact node k, as a boolean matrix:
     F[i][j] is True when i != j, k not in {i, j}, D[i][j] < INF and
     D[i][k] (+) D[k][j] == D[i][j]  (equality form of Corollary 'corollary3';
-    for distances '>=' and '==' coincide)."""
+    for distances '>=' and '==' coincide).  minimax: (+) is max."""
     D = np.asarray(D, dtype=np.int64)
     n = D.shape[0]
-    F = (oplus(D[:, k][:, None], D[k, :][None, :]) == D) & (D < INF)
+    cat = np.maximum if minimax else oplus
+    F = (cat(D[:, k][:, None], D[k, :][None, :]) == D) & (D < INF)
     F[np.arange(n), np.arange(n)] = False
     F[k, :] = False
     F[:, k] = False

@@ -458,3 +458,64 @@ def test_key_nodes_decide_removals(zero):
                 assert d2 > D[i, j], (trial, k)
             else:
                 assert d2 == D[i, j], (trial, k)
+
+
+# ---------------------------------------------------------------------------
+# minimax (bottleneck) paths: the (min, max) variant
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_minimax_three_ways(undirected):
+    """Floyd-Warshall with max = brute force over simple paths (n <= 7) =
+    least reachability threshold (n <= 40); zero weights and many ties."""
+    rng = np.random.default_rng(61 + undirected)
+    for trial in range(30):
+        n = int(rng.integers(1, 8)) if trial < 20 else int(rng.integers(8, 40))
+        A = W.random_graph(n, 1, int(rng.integers(1, 20)), undirected=undirected,
+                           density=float(rng.uniform(0.1, 0.9)), seed=int(rng.integers(1 << 30)),
+                           zero_frac=0.15 if trial % 3 == 0 else 0.0)
+        D = O.minimax_apsp(A)
+        assert np.array_equal(D, O.minimax_by_thresholds(A)), trial
+        if n <= 7:
+            assert np.array_equal(D, O.brute_force_minimax(A)), trial
+
+
+def test_minimax_undirected_equals_spanning_tree_bottleneck():
+    """Undirected, positive weights: MM(i,j) is the largest edge on the
+    path between i and j in a minimum spanning forest (scipy's)."""
+    from scipy.sparse.csgraph import minimum_spanning_tree
+    rng = np.random.default_rng(71)
+    for trial in range(8):
+        n = int(rng.integers(5, 60))
+        A = W.random_graph(n, 1, 1000, undirected=True, density=float(rng.uniform(0.05, 0.6)),
+                           seed=int(rng.integers(1 << 30)))
+        dense = np.where(A >= INF, 0, A).astype(np.float64)
+        np.fill_diagonal(dense, 0)
+        T = minimum_spanning_tree(dense).toarray()
+        T = np.maximum(T, T.T)
+        want = np.full((n, n), INF, dtype=np.int64)
+        for s in range(n):           # largest edge on the tree path from s
+            want[s, s] = 0
+            stack = [s]
+            while stack:
+                x = stack.pop()
+                for y in np.nonzero(T[x])[0]:
+                    if want[s, y] == INF:
+                        want[s, y] = max(want[s, x], int(T[x, y]))
+                        stack.append(int(y))
+        assert np.array_equal(O.minimax_apsp(A), want), trial
+
+
+def test_minimax_removal_mask_holds_every_change():
+    """Corollary corollary3 with max: pairs outside the minimax mask of k keep
+    their distance when k is removed."""
+    rng = np.random.default_rng(81)
+    for trial in range(20):
+        n = int(rng.integers(3, 30))
+        A = W.random_graph(n, 1, 6, density=float(rng.uniform(0.1, 0.8)), seed=int(rng.integers(1 << 30)))
+        D = O.minimax_apsp(A)
+        k = int(rng.integers(n))
+        keep = [x for x in range(n) if x != k]
+        D2 = O.minimax_apsp(A[np.ix_(keep, keep)])
+        F = O.remove_mask(D, k, minimax=True)[np.ix_(keep, keep)]
+        assert np.array_equal(D2[~F], D[np.ix_(keep, keep)][~F]), trial
