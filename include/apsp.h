@@ -77,7 +77,16 @@ typedef enum {
     APSP_E_VALUE = -7      /* sticky: a device-resident weight was out of range */
 } apsp_status;
 
-typedef enum { APSP_DIRECTED = 0, APSP_UNDIRECTED = 1 } apsp_kind;
+/* Graph kind: directed or undirected, optionally OR-ed with APSP_MINIMAX.
+ * APSP_MINIMAX selects minimax (bottleneck) paths, the (min, max) semiring:
+ * D[i][j] = the least, over walks from i to j, of the largest edge weight on
+ * the walk (0 when i == j), the variant the paper's discussion section says
+ * its algorithms carry over to.  Every single-graph call then runs the same
+ * steps with max in place of + (Theorems theorem2-theorem3 and Corollary
+ * corollary3 hold with max, which is monotone with 0 as identity on weights
+ * >= 0).  Not available for such graphs: apsp_query_nodes and the batched
+ * calls (both return APSP_E_INVALID). */
+typedef enum { APSP_DIRECTED = 0, APSP_UNDIRECTED = 1, APSP_MINIMAX = 2 } apsp_kind;
 
 /* What apsp_remove_node and an edge increase do after building the mask
  * (Algorithm 5 switches to Floyd-Warshall when Cost exceeds delta). */
@@ -126,7 +135,8 @@ size_t apsp_required_bytes(int32_t capacity, int32_t kind);
  * and compute its APSP matrix by blocked Floyd-Warshall.
  *   kind       APSP_DIRECTED or APSP_UNDIRECTED (adjacency must be
  *              symmetric; asymmetric pairs take the smaller weight and set
- *              the sticky error)
+ *              the sticky error), either OR-ed with APSP_MINIMAX for
+ *              minimax paths
  *   capacity   node slots, n <= capacity <= APSP_MAX_CAPACITY, >= 1
  *   dev_buf    caller-owned device buffer of dev_buf_bytes >=
  *              apsp_required_bytes(capacity, kind), 256-byte aligned
@@ -183,7 +193,9 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w);
  * path is the lexicographically smallest shortest simple path over ids,
  * found among Algorithm 7's candidates {t : D[i][t] + D[t][j] == D[i][j]}
  * (Theorem al_correct).  With zero-weight edges any shortest simple path
- * may be returned.  path_ids (host, path_cap entries) receives the ids from
+ * may be returned; on a minimax graph (APSP_MINIMAX) the path is a simple
+ * path whose largest edge weight is D[i][j], found over the same candidates
+ * with max in place of +.  path_ids (host, path_cap entries) receives the ids from
  * i to j; *path_len its length (1 when i == j, 0 when unreachable, in which
  * case *dist = APSP_INF).  If path_cap < *path_len, returns
  * APSP_E_CAPACITY with *dist and *path_len set.  path_ids may be NULL when

@@ -21,6 +21,7 @@ APSP_E_DEVICE = -5
 APSP_E_VALUE = -7
 APSP_DIRECTED = 0
 APSP_UNDIRECTED = 1
+APSP_MINIMAX = 2      # OR-ed into the kind: minimax (bottleneck) paths
 APSP_FALLBACK_NEVER = 0
 APSP_FALLBACK_COST = 1
 APSP_FALLBACK_ALWAYS = 2

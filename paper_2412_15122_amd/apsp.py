@@ -34,13 +34,14 @@ def _device_int32(x):
 class Graph:
     """A dense weighted graph whose APSP matrix lives on the GPU.
 
-    Graph(adj, undirected=False, capacity=None) runs the cold start
-    (apsp_cold).  `adj` is an n x n int32 matrix (numpy or torch), absent
-    edges APSP_INF, diagonal ignored.  Ids are 0..n-1; added nodes get
-    max_id + 1.
+    Graph(adj, undirected=False, capacity=None, minimax=False) runs the cold
+    start (apsp_cold).  `adj` is an n x n int32 matrix (numpy or torch),
+    absent edges APSP_INF, diagonal ignored.  Ids are 0..n-1; added nodes
+    get max_id + 1.  minimax=True keeps minimax (bottleneck) distances
+    instead of shortest-path ones (APSP_MINIMAX).
     """
 
-    def __init__(self, adj, *, undirected: bool = False, capacity: Optional[int] = None):
+    def __init__(self, adj, *, undirected: bool = False, capacity: Optional[int] = None, minimax: bool = False):
         torch = _torch()
         self._lib = N.load()
         A = _device_int32(adj)
@@ -50,6 +51,7 @@ class Graph:
         cap = int(capacity if capacity is not None else max(n, 1))
         self.kind = N.APSP_UNDIRECTED if undirected else N.APSP_DIRECTED
         self.undirected = bool(undirected)
+        self.minimax = bool(minimax)
         nbytes = int(self._lib.apsp_required_bytes(cap, self.kind))
         if nbytes == 0:
             raise ValueError(f"invalid capacity {cap}")
@@ -60,14 +62,15 @@ class Graph:
         self.capacity = cap
         self._stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
-        st = self._lib.apsp_cold(A.data_ptr() if n else None, n, A.stride(0) if n else 0, self.kind, cap,
+        kind = self.kind | (N.APSP_MINIMAX if self.minimax else 0)
+        st = self._lib.apsp_cold(A.data_ptr() if n else None, n, A.stride(0) if n else 0, kind, cap,
                                  self._ptr, nbytes, self._stream.cuda_stream, ctypes.byref(h))
         N.check(st, "apsp_cold")
         self._h = h
         self._keep = []
 
     @classmethod
-    def _from_handle(cls, lib, h, buf, ptr, nbytes, cap, kind, stream):
+    def _from_handle(cls, lib, h, buf, ptr, nbytes, cap, kind, stream, minimax=False):
         g = cls.__new__(cls)
         g._lib = lib
         g._h = h
@@ -77,6 +80,7 @@ class Graph:
         g.capacity = cap
         g.kind = kind
         g.undirected = kind == N.APSP_UNDIRECTED
+        g.minimax = minimax
         g._stream = stream
         g._keep = []
         return g
@@ -94,7 +98,8 @@ class Graph:
                 "apsp_graph_clone")
         if stream.cuda_stream != self._stream.cuda_stream:
             self._stream.wait_stream(stream)  # and the source's later updates after the copy
-        return Graph._from_handle(self._lib, h, buf, ptr, self._nbytes, self.capacity, self.kind, stream)
+        return Graph._from_handle(self._lib, h, buf, ptr, self._nbytes, self.capacity, self.kind, stream,
+                                  self.minimax)
 
     @property
     def nbytes(self) -> int:

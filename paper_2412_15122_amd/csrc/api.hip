@@ -12,6 +12,9 @@
 #include "apsp_internal.h"
 
 using namespace apsp;
+// The launcher of g's semiring: namespace apsp for shortest paths, apsp::mm
+// for minimax paths (the same kernel sources, compiled once per semiring).
+#define SR(g, fn) ((g)->minimax ? &mm::fn : &fn)
 
 #include "host_graph.h"
 
@@ -60,7 +63,7 @@ apsp_status run_cold(apsp_graph *g) {
     g->prof.end();
     apsp_status st = check_launch("cold start copy");
     if (st) return st;
-    if (const char *bad = launch_fw(g->dg, n, g->stream, &g->prof))
+    if (const char *bad = SR(g, launch_fw)(g->dg, n, g->stream, &g->prof))
         return fail(APSP_E_DEVICE, std::string("Floyd-Warshall launch failed: ") + bad);
     return APSP_OK;
 }
@@ -179,29 +182,34 @@ const char *apsp_kernel_name(int32_t k) {
 
 size_t apsp_required_bytes(int32_t capacity, int32_t kind) {
     if (capacity < 1 || capacity > APSP_MAX_CAPACITY) return 0;
-    if (kind != APSP_DIRECTED && kind != APSP_UNDIRECTED) return 0;
-    return make_layout(capacity, kind).total;
+    const int32_t dir = kind & ~(int32_t)APSP_MINIMAX;
+    if (dir != APSP_DIRECTED && dir != APSP_UNDIRECTED) return 0;
+    return make_layout(capacity, dir).total;
 }
 
 apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t kind, int32_t capacity,
                       void *dev_buf, size_t dev_buf_bytes, void *hip_stream, apsp_graph **out) {
     if (!out) return fail(APSP_E_INVALID, "apsp_cold: out is NULL");
     *out = nullptr;
-    if (kind != APSP_DIRECTED && kind != APSP_UNDIRECTED) return fail(APSP_E_INVALID, "apsp_cold: bad kind");
+    const int32_t dir = kind & ~(int32_t)APSP_MINIMAX;
+    if (dir != APSP_DIRECTED && dir != APSP_UNDIRECTED) return fail(APSP_E_INVALID, "apsp_cold: bad kind");
     if (capacity < 1 || capacity > APSP_MAX_CAPACITY)
         return fail(APSP_E_INVALID, "apsp_cold: capacity must be in [1, APSP_MAX_CAPACITY]");
     if (n < 0 || n > capacity) return fail(APSP_E_INVALID, "apsp_cold: n must be in [0, capacity]");
     if (n > 0 && (!adj_dev || adj_ld < n)) return fail(APSP_E_INVALID, "apsp_cold: bad adjacency pointer or ld");
     if (!dev_buf) return fail(APSP_E_INVALID, "apsp_cold: dev_buf is NULL");
     if (((uintptr_t)dev_buf & 255) != 0) return fail(APSP_E_INVALID, "apsp_cold: dev_buf not 256-byte aligned");
-    const Layout L = make_layout(capacity, kind);
+    const Layout L = make_layout(capacity, dir);
     if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, "apsp_cold: dev_buf smaller than apsp_required_bytes");
 
     apsp_graph *g = nullptr;
-    apsp_status st0 = make_handle(capacity, kind, dev_buf, (hipStream_t)hip_stream, &g);
+    apsp_status st0 = make_handle(capacity, dir, dev_buf, (hipStream_t)hip_stream, &g);
     if (st0) return st0;
+    g->minimax = (kind & APSP_MINIMAX) != 0;
     DevGraph &d = g->dg;
-    if (hipError_t e = configure_kernels(); e != hipSuccess) {
+    hipError_t ce = configure_kernels();
+    if (ce == hipSuccess) ce = mm::configure_kernels();
+    if (hipError_t e = ce; e != hipSuccess) {
         apsp_graph_destroy(g);
         return fail(APSP_E_DEVICE, std::string("configuring kernels: ") + hipGetErrorString(e));
     }
@@ -307,6 +315,7 @@ apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes,
     c->policy = g->policy;
     c->delta = g->delta;
     c->last_kind = g->last_kind;
+    c->minimax = g->minimax;
     c->last_n_before = g->last_n_before;
     c->last_fallback = g->last_fallback;
     *out = c;
@@ -397,17 +406,17 @@ apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t
     const int32_t *oc = und ? d.nin_cnt + p : g->plist_cnt;
     const int32_t *ob = und ? d.nin_beta + p : g->plist_beta;
     g->prof.begin(KID_ADD_OUT);
-    launch_add_out(d, ol, oc, ob, wo(g), vout(g), s);
+    SR(g, launch_add_out)(d, ol, oc, ob, wo(g), vout(g), s);
     g->prof.end();
     int32_t *in = vout(g);
     if (!und) {
         g->prof.begin(KID_ADD_IN);
-        launch_add_in(d, p, wi_s, vin(g), s);
+        SR(g, launch_add_in)(d, p, wi_s, vin(g), s);
         g->prof.end();
         in = vin(g);
     }
     g->prof.begin(KID_ADD_RELAX);
-    launch_add_relax(d, in, vout(g), s);
+    SR(g, launch_add_relax)(d, in, vout(g), s);
     g->prof.end();
     g->prof.begin(KID_ADD_PLACE);
     launch_add_finish(d, p, nid, n_before, g->rank_cur, in, vout(g), wo(g), wi_s, s);
@@ -442,13 +451,13 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     fa.col1 = colu(g);
     fa.row1 = rowu(g);
     g->prof.begin(KID_MASK);
-    launch_mask_detect(d, fa, s);
+    SR(g, launch_mask_detect)(d, fa, s);
     g->prof.end();
     int32_t fallback = 0;
     apsp_status st = decide_fallback(g, &fa, n_before, &fallback);
     if (st) return st;
     g->prof.begin(KID_FUSED);
-    const int32_t rblocks = launch_mask_recompute(d, fa, fallback, s);
+    const int32_t rblocks = SR(g, launch_mask_recompute)(d, fa, fallback, s);
     g->prof.end();
     g->prof.begin(KID_TOMBSTONE);
     launch_remove_finish(d, k, g->nin_queue, g->rank_cur, g->rank_other, r, n_before, g->partials, rblocks, s);
@@ -489,7 +498,7 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     fa.row1 = rowv(g);
     fa.row2 = rowu(g);
     g->prof.begin(KID_EDGE_SWEEP);
-    launch_edge_sweep(d, fa, w, s);
+    SR(g, launch_edge_sweep)(d, fa, w, s);
     g->prof.end();
     int32_t fallback = 0;
     apsp_status st;
@@ -498,7 +507,7 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
         if (g->ctl_h->edge_mode == EDGE_INCREASE && (st = decide_fallback(g, &fa, n_before, &fallback))) return st;
     }
     g->prof.begin(KID_FUSED);
-    const int32_t rblocks = launch_mask_recompute(d, fa, fallback, s);
+    const int32_t rblocks = SR(g, launch_mask_recompute)(d, fa, fallback, s);
     g->prof.end();
     if (fallback && (st = run_cold(g))) return st;
     g->prof.begin(KID_NIN_BUILD);
@@ -519,7 +528,7 @@ apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32
     if (!lookup(g, i, &si) || !lookup(g, j, &sj)) return fail(APSP_E_NOT_FOUND, "apsp_query: id is not live");
     hipStream_t s = g->stream;
     g->prof.begin(KID_QUERY);
-    launch_query(g->dg, si, sj, g->qbuf, g->qscratch, s);
+    SR(g, launch_query)(g->dg, si, sj, g->qbuf, g->qscratch, s);
     g->prof.end();
     apsp_status st = check_launch("apsp_query");
     if (st) return st;
@@ -542,6 +551,7 @@ apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
         return fail(APSP_E_INVALID, "apsp_query_nodes: bad output buffer");
     int32_t si, sj;
     if (!lookup(g, i, &si) || !lookup(g, j, &sj)) return fail(APSP_E_NOT_FOUND, "apsp_query_nodes: id is not live");
+    if (g->minimax) return fail(APSP_E_INVALID, "apsp_query_nodes: shortest-path graphs only (not minimax)");
     hipStream_t s = g->stream;
     const int32_t n = g->n_live;
     // output: 4 + 2 n ints at the start of the heavy-pass scratch; the
@@ -600,7 +610,7 @@ apsp_status apsp_edge_scope(apsp_graph *g, int32_t u, int32_t v, int32_t *r_coun
     int32_t su, sv;
     if (!lookup(g, u, &su) || !lookup(g, v, &sv)) return fail(APSP_E_NOT_FOUND, "apsp_edge_scope: id is not live");
     launch_fill(&g->dg.ctl->scope_r, 2, 0, g->stream);
-    launch_edge_scope(g->dg, su, sv, g->stream);
+    SR(g, launch_edge_scope)(g->dg, su, sv, g->stream);
     apsp_status st = check_launch("apsp_edge_scope");
     if (st) return st;
     if ((st = read_ctl(g))) return st;

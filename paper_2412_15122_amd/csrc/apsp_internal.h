@@ -74,44 +74,6 @@ __host__ __device__ inline const int32_t *in_matrix(const DevGraph &g) {
     return g.undirected ? g.A : g.AT;
 }
 
-// ---- launchers (defined next to their kernels) -----------------------------
-
-void launch_fill(int32_t *p, int64_t count, int32_t v, hipStream_t s);
-void launch_load_adj(const DevGraph &g, const int32_t *adj, int64_t adj_ld, int32_t n, hipStream_t s);
-void launch_transpose(const int32_t *src, int32_t *dst, int64_t ld, int32_t n, hipStream_t s);
-void launch_copy_square(int32_t *dst, const int32_t *src, int64_t ld, int32_t n, hipStream_t s);
-void launch_iota(int32_t *p, int32_t n, hipStream_t s);
-
-// Floyd-Warshall over slots [0, n): three launches per 128-wide round.
-struct Prof;
-// Returns the name of a kernel whose launch failed, or nullptr.
-const char *launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof);
-
-// Light in-edge index.
-void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t only_short, hipStream_t s);
-// The end of an edge update, one launch: a tight increase's recompute
-// statistics summed (partials of `blocks` work-groups), then the lists of y0
-// and y1 (y1 < 0: y0 only) rebuilt if they have shrunk.
-void launch_edge_finish(const DevGraph &g, int32_t y0, int32_t y1, const int32_t *partials, int32_t blocks,
-                        hipStream_t s);
-void launch_select_vec(const int32_t *vals, int32_t n, int32_t exclude, int2 *list, int32_t *cnt,
-                       int32_t *beta, hipStream_t s);
-// Rebuild the lists queued by a removal (those that fell below NIN_L/2 while
-// unlisted in-edges exist).
-void launch_nin_rebuild_queue(const DevGraph &g, const int32_t *queue, hipStream_t s);
-
-// Add node.  The scatter also zeroes the per-update counters.
-void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32_t *w_in,
-                            const int32_t *slot_of_rank, int32_t n_live, int32_t *wo, int32_t *wi,
-                            hipStream_t s);
-void launch_add_out(const DevGraph &g, const int2 *plist, const int32_t *pcnt, const int32_t *pbeta,
-                    const int32_t *wo, int32_t *out, hipStream_t s);
-void launch_add_in(const DevGraph &g, int32_t p, const int32_t *wi, int32_t *in, hipStream_t s);
-void launch_add_relax(const DevGraph &g, const int32_t *in, const int32_t *out, hipStream_t s);
-// Row and column p placed, p registered, p's out-edges entered in the lists.
-void launch_add_finish(const DevGraph &g, int32_t p, int32_t new_id, int32_t rank, int32_t *slot_of_rank,
-                       const int32_t *in, const int32_t *out, const int32_t *wo, const int32_t *wi, hipStream_t s);
-
 // Remove node / edge increase: mask + exact recompute of the masked pairs.
 // Row marks of the mask detection: one byte per group of 8 rows and chunk
 // of 256 columns, bit r set when row 8 g + r has a flag in that chunk.
@@ -135,44 +97,38 @@ struct FusedArgs {
     int32_t *partials;    // [RECOMPUTE_BLOCKS][RECOMPUTE_STATS] per-work-group statistics of the recompute
     int32_t epoch;        // distinct for every mask pass
 };
-// Removal: counters zeroed, colk[i] = D[i][k], rowk[j] = D[k][j].
-void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *rowk, hipStream_t s);
-// Mask + recompute in two steps: detection, then the recompute -- or, with
-// reset_only, just the clearing of the flag words when cold Floyd-Warshall
-// replaces the recompute.  launch_mask_recompute returns the number of
-// work-groups whose statistics (Phi, |F|, ...) the update's next kernel sums
-// into the control block (launch_remove_finish / launch_edge_finish), negated
-// when the heavy-row pass did not run (its partials are then not summed).
-void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s);
-int32_t launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s);
-void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s);  // Phi -> ctl->rows
-// After a removal's recompute: tombstone of slot k, k purged from the light
-// lists (short ones queued), rank table shifted (rank_src -> rank_dst).
-void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const int32_t *rank_src, int32_t *rank_dst,
-                          int32_t r, int32_t n_live, const int32_t *partials, int32_t blocks, hipStream_t s);
+struct Prof;
 
-// Edge update.
-// The edge decision and the gathers of columns / rows u and v of D.
-void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int32_t *colu, int32_t *colv,
-                       int32_t *rowu, int32_t *rowv, hipStream_t s);
-// The decrease's relaxation or the tight increase's mask, chosen on the
-// device (fa: the increase's mask arguments; its vectors serve both).
-void launch_edge_sweep(const DevGraph &g, const FusedArgs &fa, int32_t w, hipStream_t s);
+// ---- semirings -------------------------------------------------------------
+// The kernel sources (fw.hip, update.hip, query.hip and device_common.h) are
+// compiled twice: as they are, for shortest paths -- the (min, +) semiring,
+// a (+) b = a + b -- in namespace apsp, and with APSP_SEMIRING_MINIMAX defined, for
+// minimax (bottleneck) paths -- the (min, max) semiring, a (+) b = max(a, b)
+// -- in namespace apsp::mm.  Every distance concatenation in them goes
+// through cat(); everything else is shared.
+#ifdef APSP_SEMIRING_MINIMAX
+#define APSP_SR_BEGIN namespace mm {
+#define APSP_SR_END }
+#else
+#define APSP_SR_BEGIN
+#define APSP_SR_END
+#endif
 
-// Query / read-out.
-void launch_query(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch, hipStream_t s);
-// Nodes on some / on every shortest si -> sj path.  rank: the n_live live
-// slots in ascending-id order; out: 4 + 2 n_live ints; scratch: 4 P ints;
-// bfs: 2 P ints for each of 256 work-groups.
-void launch_query_nodes(const DevGraph &g, int32_t si, int32_t sj, const int32_t *rank, int32_t n_live,
-                        int32_t *out, int32_t *scratch, int32_t *bfs, hipStream_t s);
-void launch_gather_compact(const int32_t *src, int64_t ld, int32_t *dst, int64_t dst_ld,
-                           const int32_t *slot_of_rank, int32_t n, hipStream_t s);
-void launch_edge_scope(const DevGraph &g, int32_t su, int32_t sv, hipStream_t s);
+APSP_SR_BEGIN
+// Path concatenation a (+) b of this unit's semiring.  Entries are at most
+// INF: a sum stays below 2^31 (no wrap), and a (+) b >= INF whenever either
+// side is INF.
+#ifdef APSP_SEMIRING_MINIMAX
+__device__ __forceinline__ uint32_t cat(uint32_t a, uint32_t b) { return max(a, b); }
+#else
+__device__ __forceinline__ uint32_t cat(uint32_t a, uint32_t b) { return a + b; }
+#endif
+APSP_SR_END
 
-size_t fused_lds_bytes(int32_t P);
-size_t nin_build_lds_bytes(int32_t P);
-hipError_t configure_kernels();  // raise dynamic-LDS limits once per process
+#include "launchers.inc"
+namespace mm {
+#include "launchers.inc"
+}
 
 // Kernel ids for per-kernel timing (apsp_profile).
 enum KernelId : int32_t {

@@ -243,6 +243,7 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
             const apsp_graph *g = graphs[i];
             if (!g) return fail(APSP_E_INVALID, "apsp_batch_run: NULL graph " + std::to_string(i));
             if (!seen.insert(g).second) return fail(APSP_E_INVALID, "apsp_batch_run: graph listed twice");
+            if (g->minimax) return fail(APSP_E_INVALID, "apsp_batch_run: batched launches take shortest-path graphs only");
             if (g->cap > BATCH_MAX_CAPACITY)
                 return fail(APSP_E_INVALID, "apsp_batch_run: graph capacity above APSP_BATCH_MAX_CAPACITY");
         }

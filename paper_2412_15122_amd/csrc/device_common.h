@@ -3,6 +3,7 @@
 #include "apsp_internal.h"
 
 namespace apsp {
+APSP_SR_BEGIN
 
 // ---------------------------------------------------------------------------
 // wave / block helpers (wave64)
@@ -30,7 +31,7 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
-// min(bound, min over x < n of a[x] + b[x]) (uint32; entries <= INF, a >=
+// min(bound, min over x < n of a[x] (+) b[x]) (uint32; entries <= INF, a >=
 // 0), by one wavefront: b is read in full (16-byte loads, four per lane in
 // flight), a only where b[x] < bound (no other x can go below bound).
 // a and b 16-byte aligned.
@@ -52,17 +53,17 @@ __device__ inline uint32_t wave_min_plus_below(const int32_t *a, const int32_t *
             const uint32_t w[4] = {vb[q].x, vb[q].y, vb[q].z, vb[q].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (w[e] < best) best = min(best, (uint32_t)a[x + e] + w[e]);
+                if (w[e] < best) best = min(best, cat((uint32_t)a[x + e], w[e]));
         }
     }
     if (n4 + lane < n) {
         const uint32_t w = (uint32_t)b[n4 + lane];
-        if (w < best) best = min(best, (uint32_t)a[n4 + lane] + w);
+        if (w < best) best = min(best, cat((uint32_t)a[n4 + lane], w));
     }
     return wave_min(best);
 }
 
-// min over x < n of a[x] + b[x] (uint32; entries <= INF), by one wavefront:
+// min over x < n of a[x] (+) b[x] (uint32; entries <= INF), by one wavefront:
 // 16-byte loads (a and b 16-byte aligned), four of each per lane in flight.
 __device__ inline uint32_t wave_min_plus(const int32_t *a, const int32_t *b, int32_t n) {
     const int lane = lane_id();
@@ -82,9 +83,10 @@ __device__ inline uint32_t wave_min_plus(const int32_t *a, const int32_t *b, int
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            best = min(min(best, min(va[q].x + vb[q].x, va[q].y + vb[q].y)), min(va[q].z + vb[q].z, va[q].w + vb[q].w));
+            best = min(min(best, min(cat(va[q].x, vb[q].x), cat(va[q].y, vb[q].y))),
+                       min(cat(va[q].z, vb[q].z), cat(va[q].w, vb[q].w)));
     }
-    if (n4 + lane < n) best = min(best, (uint32_t)a[n4 + lane] + (uint32_t)b[n4 + lane]);
+    if (n4 + lane < n) best = min(best, cat((uint32_t)a[n4 + lane], (uint32_t)b[n4 + lane]));
     return wave_min(best);
 }
 
@@ -413,10 +415,10 @@ __device__ inline RowTests row_tests(const DevGraph &g, const FusedArgs &fa, int
         r.a1 = dik;
     } else {
         const uint32_t cu = (uint32_t)fa.col1[i], cv = (uint32_t)fa.col2[i];
-        r.t1 = cv < INF && cu + w_old == cv;
+        r.t1 = cv < INF && cat(cu, w_old) == cv;
         r.a1 = cv;
         if (g.undirected) {
-            r.t2 = cu < INF && cv + w_old == cu;
+            r.t2 = cu < INF && cat(cv, w_old) == cu;
             r.a2 = cu;
         }
     }
@@ -430,8 +432,8 @@ __device__ inline RowTests row_tests(const DevGraph &g, const FusedArgs &fa, int
 // is final, and one above it belongs to the refined set (Theorem
 // theo_algo12: every shortest path of that pair used k, or the edge).
 __device__ inline uint32_t flagged_old(const FusedArgs &fa, const RowTests &rt, int32_t y) {
-    const uint32_t o1 = rt.t1 ? rt.a1 + (uint32_t)fa.row1[y] : INF;
-    const uint32_t o2 = rt.t2 ? rt.a2 + (uint32_t)fa.row2[y] : INF;
+    const uint32_t o1 = rt.t1 ? cat(rt.a1, (uint32_t)fa.row1[y]) : INF;
+    const uint32_t o2 = rt.t2 ? cat(rt.a2, (uint32_t)fa.row2[y]) : INF;
     return min(o1, o2);
 }
 
@@ -476,7 +478,8 @@ __device__ inline int mask_row(const DevGraph &g, const FusedArgs &fa, int32_t i
                 const int j = j0 + e;
                 uint32_t dj = dv[e];
                 bool f = false;
-                if (j < n && j != i && dj < INF) f = (rt.t1 && rt.a1 + v1[e] == dj) || (rt.t2 && rt.a2 + v2[e] == dj);
+                if (j < n && j != i && dj < INF)
+                    f = (rt.t1 && cat(rt.a1, v1[e]) == dj) || (rt.t2 && cat(rt.a2, v2[e]) == dj);
                 if (fa.mode == FUSED_REMOVE && j == fa.k) {
                     f = false;
                     dj = INF;
@@ -572,14 +575,14 @@ __device__ inline void row_bellman_ford(const DevGraph &g, FusedShared &sh, cons
                     if (e1 + 1 >= lim) pc.w = (int)INF;
                     if (e1 + 3 >= lim) pd.w = (int)INF;
                     uint32_t cm = INF;
-                    if ((uint32_t)pa.y < best) cm = min(cm, cur[pa.x] + (uint32_t)pa.y);
-                    if ((uint32_t)pa.w < best) cm = min(cm, cur[pa.z] + (uint32_t)pa.w);
-                    if ((uint32_t)pb.y < best) cm = min(cm, cur[pb.x] + (uint32_t)pb.y);
-                    if ((uint32_t)pb.w < best) cm = min(cm, cur[pb.z] + (uint32_t)pb.w);
-                    if ((uint32_t)pc.y < best) cm = min(cm, cur[pc.x] + (uint32_t)pc.y);
-                    if ((uint32_t)pc.w < best) cm = min(cm, cur[pc.z] + (uint32_t)pc.w);
-                    if ((uint32_t)pd.y < best) cm = min(cm, cur[pd.x] + (uint32_t)pd.y);
-                    if ((uint32_t)pd.w < best) cm = min(cm, cur[pd.z] + (uint32_t)pd.w);
+                    if ((uint32_t)pa.y < best) cm = min(cm, cat(cur[pa.x], (uint32_t)pa.y));
+                    if ((uint32_t)pa.w < best) cm = min(cm, cat(cur[pa.z], (uint32_t)pa.w));
+                    if ((uint32_t)pb.y < best) cm = min(cm, cat(cur[pb.x], (uint32_t)pb.y));
+                    if ((uint32_t)pb.w < best) cm = min(cm, cat(cur[pb.z], (uint32_t)pb.w));
+                    if ((uint32_t)pc.y < best) cm = min(cm, cat(cur[pc.x], (uint32_t)pc.y));
+                    if ((uint32_t)pc.w < best) cm = min(cm, cat(cur[pc.z], (uint32_t)pc.w));
+                    if ((uint32_t)pd.y < best) cm = min(cm, cat(cur[pd.x], (uint32_t)pd.y));
+                    if ((uint32_t)pd.w < best) cm = min(cm, cat(cur[pd.z], (uint32_t)pd.w));
                     cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
                     cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
                     best = min(best, cm);
@@ -613,7 +616,7 @@ __device__ inline void row_bellman_ford(const DevGraph &g, FusedShared &sh, cons
             const int32_t y = fsl[f];
             const int32_t *col = Min + (int64_t)y * g.ld;
             uint32_t best = INF;
-            for (int32_t x = tid; x < n; x += FUSED_THREADS) best = min(best, cur[x] + (uint32_t)col[x]);
+            for (int32_t x = tid; x < n; x += FUSED_THREADS) best = min(best, cat(cur[x], (uint32_t)col[x]));
             best = block_min<FUSED_THREADS>(best, sh.red);
             if (tid == 0 && best < cur[y]) {
                 cur[y] = best;
@@ -690,7 +693,7 @@ __device__ inline void query_block(const DevGraph &g, int32_t si, int32_t sj, in
         if (g.id_of_slot[t] < 0) continue;
         const uint32_t dit = (uint32_t)g.D[(int64_t)si * ld + t];
         const uint32_t dtj = (uint32_t)g.D[(int64_t)t * ld + sj];
-        if (t == si || t == sj || dit + dtj == dist) {
+        if (t == si || t == sj || cat(dit, dtj) == dist) {
             const int c = atomicAdd(&s_k, 1);
             cand[c] = t;
             candD[c] = (int32_t)dtj;
@@ -716,7 +719,7 @@ __device__ inline void query_block(const DevGraph &g, int32_t si, int32_t sj, in
             if (b == cur || (visited[b >> 5] >> (b & 31)) & 1u) continue;
             const uint32_t a = (uint32_t)g.A[(int64_t)cur * ld + b];
             if (a >= INF) continue;
-            if (a + (uint32_t)candD[c] == dcur) {
+            if (cat(a, (uint32_t)candD[c]) == dcur) {
                 const unsigned long long key = ((unsigned long long)(uint32_t)g.id_of_slot[b] << 32) | (uint32_t)c;
                 best = key < best ? key : best;
             }
@@ -758,7 +761,7 @@ __device__ inline void query_block(const DevGraph &g, int32_t si, int32_t sj, in
                 const int32_t a = cand[c];
                 if (a == b) continue;
                 const uint32_t w = (uint32_t)g.A[(int64_t)a * ld + b];
-                if (w < INF && w + (uint32_t)candD[c2] == (uint32_t)candD[c]) {
+                if (w < INF && cat(w, (uint32_t)candD[c2]) == (uint32_t)candD[c]) {
                     lvl[c2] = level + 1;
                     parent[c2] = c;
                     s_changed = 1;
@@ -821,14 +824,14 @@ __device__ inline void wave_bellman_ford(const DevGraph &g, int32_t *Drow, const
                     if (e1 + 1 >= lim) pc.w = (int)INF;
                     if (e1 + 3 >= lim) pd.w = (int)INF;
                     uint32_t cm = INF;
-                    if ((uint32_t)pa.y < best) cm = min(cm, (uint32_t)Drow[pa.x] + (uint32_t)pa.y);
-                    if ((uint32_t)pa.w < best) cm = min(cm, (uint32_t)Drow[pa.z] + (uint32_t)pa.w);
-                    if ((uint32_t)pb.y < best) cm = min(cm, (uint32_t)Drow[pb.x] + (uint32_t)pb.y);
-                    if ((uint32_t)pb.w < best) cm = min(cm, (uint32_t)Drow[pb.z] + (uint32_t)pb.w);
-                    if ((uint32_t)pc.y < best) cm = min(cm, (uint32_t)Drow[pc.x] + (uint32_t)pc.y);
-                    if ((uint32_t)pc.w < best) cm = min(cm, (uint32_t)Drow[pc.z] + (uint32_t)pc.w);
-                    if ((uint32_t)pd.y < best) cm = min(cm, (uint32_t)Drow[pd.x] + (uint32_t)pd.y);
-                    if ((uint32_t)pd.w < best) cm = min(cm, (uint32_t)Drow[pd.z] + (uint32_t)pd.w);
+                    if ((uint32_t)pa.y < best) cm = min(cm, cat((uint32_t)Drow[pa.x], (uint32_t)pa.y));
+                    if ((uint32_t)pa.w < best) cm = min(cm, cat((uint32_t)Drow[pa.z], (uint32_t)pa.w));
+                    if ((uint32_t)pb.y < best) cm = min(cm, cat((uint32_t)Drow[pb.x], (uint32_t)pb.y));
+                    if ((uint32_t)pb.w < best) cm = min(cm, cat((uint32_t)Drow[pb.z], (uint32_t)pb.w));
+                    if ((uint32_t)pc.y < best) cm = min(cm, cat((uint32_t)Drow[pc.x], (uint32_t)pc.y));
+                    if ((uint32_t)pc.w < best) cm = min(cm, cat((uint32_t)Drow[pc.z], (uint32_t)pc.w));
+                    if ((uint32_t)pd.y < best) cm = min(cm, cat((uint32_t)Drow[pd.x], (uint32_t)pd.y));
+                    if ((uint32_t)pd.w < best) cm = min(cm, cat((uint32_t)Drow[pd.z], (uint32_t)pd.w));
                     cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
                     cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
                     best = min(best, cm);
@@ -913,4 +916,5 @@ __device__ inline void edge_begin_wave(const DevGraph &g, int32_t su, int32_t sv
     if (g.undirected) wave_list_set_edge(g, su, sv, wn);
 }
 
+APSP_SR_END
 }  // namespace apsp

@@ -1,21 +1,24 @@
 // Cold start: adjacency load, transpose, and blocked Floyd-Warshall.
 //
 // Floyd-Warshall (the paper's cold baseline, Section 1) computes, for every
-// pivot k, D[i][j] = min(D[i][j], D[i][k] + D[k][j]).  Blocked by 128-wide
-// rounds it becomes, per round r with pivot block P = D[r][r]:
+// pivot k, D[i][j] = min(D[i][j], D[i][k] (+) D[k][j]), with (+) the unit's
+// semiring concatenation (+ for shortest paths, max for minimax paths).
+// Blocked by 128-wide rounds it becomes, per round r with pivot block
+// P = D[r][r]:
 //   phase 1  P := closure of P (sequential pivots inside one work-group);
 //   phase 2  row panel    D[r][j] := min(D[r][j], P (x) D[r][j]),
 //            column panel D[i][r] := min(D[i][r], D[i][r] (x) P),
-//            where (x) is the min-plus product -- once P is closed, no pivot
-//            order is needed inside a panel;
+//            where (x) is the (min, (+)) product -- once P is closed, no
+//            pivot order is needed inside a panel;
 //   phase 3  every other tile D[i][j] := min(D[i][j], D[i][r] (x) D[r][j]).
-// Integer min-plus is exact and order-free and INF + INF (2^31) fits in
-// uint32, so every schedule gives the same bits as the textbook loop.
-// Min-plus is not a multiply-accumulate, so the tiles run on the vector
-// ALUs, not on the matrix cores.
+// Integer min-plus and min-max are exact and order-free, and INF + INF
+// (2^31) fits in uint32, so every schedule gives the same bits as the
+// textbook loop.  Neither is a multiply-accumulate, so the tiles run on the
+// vector ALUs, not on the matrix cores.
 #include "apsp_internal.h"
 
 namespace apsp {
+APSP_SR_BEGIN
 
 // ---------------------------------------------------------------------------
 // small utilities
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(1024) void k_fw_pivot(int32_t *__restrict__ D, int6
         uint32_t dik = T[row][k];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            uint32_t t = dik + T[k][c0 + c];
+            uint32_t t = cat(dik, T[k][c0 + c]);
             if (t < own[c]) {
                 own[c] = t;
                 T[row][c0 + c] = t;
@@ -231,7 +234,7 @@ __device__ __forceinline__ void minplus_tile(const int32_t *__restrict__ At, con
 #pragma unroll
             for (int m = 0; m < 8; ++m)
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[m][c] = umin3(acc[m][c], a0[m] + b0[c], a1[m] + b1[c]);
+                for (int c = 0; c < 8; ++c) acc[m][c] = umin3(acc[m][c], cat(a0[m], b0[c]), cat(a1[m], b1[c]));
         }
     }
 #pragma unroll
@@ -304,4 +307,5 @@ const char *launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof) {
     return nullptr;
 }
 
+APSP_SR_END
 }  // namespace apsp

@@ -114,7 +114,8 @@ struct ProfImpl {
 
 struct apsp_graph {
     using ProfImpl = apsp_host::ProfImpl;
-    int32_t cap = 0, P = 0, kind = 0;
+    int32_t cap = 0, P = 0, kind = 0;  // kind: APSP_DIRECTED or APSP_UNDIRECTED
+    int32_t minimax = 0;                // the (min, max) semiring (APSP_MINIMAX)
     hipStream_t stream = nullptr;
     char *base = nullptr;
     apsp::DevGraph dg{};

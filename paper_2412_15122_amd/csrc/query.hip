@@ -3,6 +3,7 @@
 #include "device_common.h"
 
 namespace apsp {
+APSP_SR_BEGIN
 
 __global__ __launch_bounds__(1024) void k_query(DevGraph g, int32_t si, int32_t sj, int32_t *out,
                                                 int32_t *scratch) {
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(1024) void k_qn_gather(DevGraph g, int32_t si, int3
             t = rank[r];
             lt = (uint32_t)g.D[(int64_t)si * ld + t];
             const uint32_t tj = (uint32_t)g.D[(int64_t)t * ld + sj];
-            const bool on = si == sj ? t == si : lt + tj == dist;
+            const bool on = si == sj ? t == si : cat(lt, tj) == dist;
             if (!on) t = -1;
         }
         int total;
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(256) void k_qn_edges(DevGraph g, const int32_t *out
     for (int32_t y = lane_id(); y < K; y += 64) {
         const uint32_t a = (uint32_t)arow[cand[y]];
         const uint32_t ly = (uint32_t)lev[y];
-        if (y == x || a >= INF || lx + a != ly) continue;
+        if (y == x || a >= INF || cat(lx, a) != ly) continue;
         if (ly > lx) {
             hi = max(hi, (int32_t)ly);
             atomicOr(&flags[y], QN_ENTRY);
@@ -241,9 +242,9 @@ __global__ void k_edge_scope(DevGraph g, int32_t su, int32_t sv) {
     int r = 0, c = 0;
     if (t < g.n_slots && g.id_of_slot[t] >= 0) {
         const uint32_t du = (uint32_t)g.D[(int64_t)t * ld + su], dv = (uint32_t)g.D[(int64_t)t * ld + sv];
-        r = (dv < INF && du + w == dv);
+        r = (dv < INF && cat(du, w) == dv);
         const uint32_t ru = (uint32_t)g.D[(int64_t)su * ld + t], rv = (uint32_t)g.D[(int64_t)sv * ld + t];
-        c = (ru < INF && w + rv == ru);
+        c = (ru < INF && cat(w, rv) == ru);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -266,4 +267,5 @@ void launch_edge_scope(const DevGraph &g, int32_t su, int32_t sv, hipStream_t s)
     k_edge_scope<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, su, sv);
 }
 
+APSP_SR_END
 }  // namespace apsp

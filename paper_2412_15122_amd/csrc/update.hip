@@ -1,14 +1,16 @@
 // Warm-start updates: add node, remove node, edge decrease / increase, and the
 // light in-edge index they share.
 //
-// Notation: a (+) b = min(a + b, INF), INF = 2^30, evaluated in uint32 (sums
-// of two values <= INF stay below 2^32, and a min against a value <= INF
+// Notation: a (+) b = cat(a, b), the concatenation of the semiring the unit
+// is compiled for (a + b for shortest paths, max(a, b) for minimax paths),
+// INF = 2^30, evaluated in uint32 (no wrap, and a min against a value <= INF
 // needs no clamp).
 #include <algorithm>
 
 #include "device_common.h"
 
 namespace apsp {
+APSP_SR_BEGIN
 
 // Zero the per-update counters (the edge decision is written by k_edge_begin).
 __device__ __forceinline__ void reset_stats(Ctl *c) {
@@ -188,10 +190,10 @@ __global__ __launch_bounds__(256) void k_add_out(DevGraph g, const int2 *__restr
                 if (live[q]) mx = max(mx, acc[q]);
             if ((uint32_t)ent.y >= mx) break;
             int4 v = *reinterpret_cast<const int4 *>(g.D + (int64_t)ent.x * g.ld + c0);
-            acc[0] = min(acc[0], (uint32_t)ent.y + (uint32_t)v.x);
-            acc[1] = min(acc[1], (uint32_t)ent.y + (uint32_t)v.y);
-            acc[2] = min(acc[2], (uint32_t)ent.y + (uint32_t)v.z);
-            acc[3] = min(acc[3], (uint32_t)ent.y + (uint32_t)v.w);
+            acc[0] = min(acc[0], cat((uint32_t)ent.y, (uint32_t)v.x));
+            acc[1] = min(acc[1], cat((uint32_t)ent.y, (uint32_t)v.y));
+            acc[2] = min(acc[2], cat((uint32_t)ent.y, (uint32_t)v.z));
+            acc[3] = min(acc[3], cat((uint32_t)ent.y, (uint32_t)v.w));
         }
     }
 #pragma unroll
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(256) void k_add_out(DevGraph g, const int2 *__restr
     if (need) {
         if (c < n) {
             for (int32_t t = 0; t < n; ++t)
-                fin = min(fin, (uint32_t)wo[t] + (uint32_t)g.D[(int64_t)t * g.ld + c]);
+                fin = min(fin, cat((uint32_t)wo[t], (uint32_t)g.D[(int64_t)t * g.ld + c]));
         }
     }
     if (c < n) out[c] = (int32_t)min(fin, INF);
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(256) void k_add_in(DevGraph g, int32_t p, const int
     uint32_t best = INF;
     if (lane < lim) {
         int2 ent = L[lane];
-        best = (uint32_t)ent.y + (uint32_t)Di[ent.x];
+        best = cat((uint32_t)ent.y, (uint32_t)Di[ent.x]);
     }
     best = wave_min(best);
     if (best > beta_eff) best = wave_min_plus_below(Di, wi, g.n_slots, best);  // only weights below best matter
@@ -250,7 +252,7 @@ void launch_add_in(const DevGraph &g, int32_t p, const int32_t *wi, int32_t *in,
     k_add_in<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, p, wi, in);
 }
 
-// Theorem theorem3: D[i][j] = min(D[i][j], in[i] + out[j]) over the old
+// Theorem theorem3: D[i][j] = min(D[i][j], in[i] (+) out[j]) over the old
 // slots.  Block = 1024 columns x 8 rows; a row with in[i] = INF cannot change.
 // Every row's 16-byte load is issued (non-temporal: D is streamed once)
 // before any row is tested, so a lane has 8 loads in flight; the few changed
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(256) void k_add_relax(DevGraph g, const int32_t *__
 #pragma unroll
     for (int r = 0; r < RELAX_ROWS; ++r) {
         if (a[r] >= INF) continue;
-        const uint4 t = make_uint4(a[r] + o.x, a[r] + o.y, a[r] + o.z, a[r] + o.w);
+        const uint4 t = make_uint4(cat(a[r], o.x), cat(a[r], o.y), cat(a[r], o.z), cat(a[r], o.w));
         uint4 x = d[r];
         if (t.x < x.x || t.y < x.y || t.z < x.z || t.w < x.w) {
             x.x = min(x.x, t.x);
@@ -430,8 +432,8 @@ void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int
 
 // Decrease of u -> v to w (< D[u][v]).  Inserting a relay node on the edge
 // and applying Theorem theorem3 gives
-//   D'[i][j] = min(D[i][j], D[i][u] + w + D[v][j])   (and v -> u if undirected).
-// Only rows with D[i][u] + w < D[i][v] can change.  The column / row vectors
+//   D'[i][j] = min(D[i][j], D[i][u] (+) w (+) D[v][j])   (and v -> u if undirected).
+// Only rows with D[i][u] (+) w < D[i][v] can change.  The column / row vectors
 // were gathered before this launch, so in-place writes do not feed back.
 __device__ __forceinline__ void dec_relax_tile(const DevGraph &g, const int32_t *__restrict__ colu,
                                                const int32_t *__restrict__ colv, const int32_t *__restrict__ rowu,
@@ -457,8 +459,8 @@ __device__ __forceinline__ void dec_relax_tile(const DevGraph &g, const int32_t 
         d[r] = make_uint4(0, 0, 0, 0);
         if (i < n) {
             const uint32_t du = (uint32_t)colu[i], dv = (uint32_t)colv[i];
-            if (du + wn < dv) x1[r] = du + wn;
-            if (g.undirected && dv + wn < du) x2[r] = dv + wn;
+            if (cat(du, wn) < dv) x1[r] = cat(du, wn);
+            if (g.undirected && cat(dv, wn) < du) x2[r] = cat(dv, wn);
             if (x1[r] < INF || x2[r] < INF) {
                 ++rows;
                 d[r] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)i * g.ld + c0);
@@ -468,8 +470,8 @@ __device__ __forceinline__ void dec_relax_tile(const DevGraph &g, const int32_t 
 #pragma unroll
     for (int r = 0; r < RELAX_ROWS; ++r) {
         if (x1[r] >= INF && x2[r] >= INF) continue;
-        const uint4 t = make_uint4(min(x1[r] + bv.x, x2[r] + bu.x), min(x1[r] + bv.y, x2[r] + bu.y),
-                                   min(x1[r] + bv.z, x2[r] + bu.z), min(x1[r] + bv.w, x2[r] + bu.w));
+        const uint4 t = make_uint4(min(cat(x1[r], bv.x), cat(x2[r], bu.x)), min(cat(x1[r], bv.y), cat(x2[r], bu.y)),
+                                   min(cat(x1[r], bv.z), cat(x2[r], bu.z)), min(cat(x1[r], bv.w), cat(x2[r], bu.w)));
         uint4 x = d[r];
         if (t.x < x.x || t.y < x.y || t.z < x.z || t.w < x.w) {
             x.x = min(x.x, t.x);
@@ -488,8 +490,8 @@ __device__ __forceinline__ void dec_relax_tile(const DevGraph &g, const int32_t 
 // ---------------------------------------------------------------------------
 // One block per affected row i (blocks stride over rows).
 //   1. Stream row i once, flag column j when a pair test holds
-//        remove k:   D[i][k] + D[k][j] == D[i][j]          (Corollary corollary3)
-//        increase:   D[i][u] + w_old + D[v][j] == D[i][j]  (and v -> u if undirected)
+//        remove k:   D[i][k] (+) D[k][j] == D[i][j]          (Corollary corollary3)
+//        increase:   D[i][u] (+) w_old (+) D[v][j] == D[i][j]  (and v -> u if undirected)
 //      with j != i, D[i][j] < INF (j != k for a removal).  Unflagged entries
 //      keep their value in G' (Theorem theorem_spd_4); flagged ones start at
 //      INF in an LDS copy `cur` of the row, as does column k.
@@ -557,7 +559,7 @@ __device__ __forceinline__ void mask_detect_tile(const DevGraph &g, const FusedA
     for (int r = 0; r < DETECT_ROWS; ++r) {
         const int32_t i = r0 + r;
         d[r] = make_uint4(INF, INF, INF, INF);
-        a1[r] = a2[r] = 0x80000000u;  // disabled: a + v exceeds every finite entry
+        a1[r] = a2[r] = 0x80000000u;  // disabled: a (+) v exceeds every finite entry
         tested[r] = false;
         if (i < n) {
             const RowTests rt = row_tests(g, fa, i, w_old);
@@ -576,8 +578,8 @@ __device__ __forceinline__ void mask_detect_tile(const DevGraph &g, const FusedA
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int32_t j = c0 + e;
-            bool f = a1[r] + w1[e] == dv[e];
-            if (MODE == FUSED_INCREASE) f = f || (a2[r] + w2[e] == dv[e]);
+            bool f = cat(a1[r], w1[e]) == dv[e];
+            if (MODE == FUSED_INCREASE) f = f || (cat(a2[r], w2[e]) == dv[e]);
             f = f && dv[e] < INF && j != i && j != kx;
             bits |= (uint32_t)f << e;
         }
@@ -966,4 +968,5 @@ hipError_t configure_kernels() {
     return status;
 }
 
+APSP_SR_END
 }  // namespace apsp
