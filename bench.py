@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
     ap.add_argument("--schedules", default="lockstep,hybrid",
                     help="serving: server schedules to run (the first is the reported one)")
+    ap.add_argument("--semiring", default="shortest", choices=["shortest", "minimax"],
+                    help="updates: shortest paths (the benchmark) or minimax (bottleneck) paths")
+    ap.add_argument("--fallback", type=float, default=None,
+                    help="updates: Algorithm 5's cost fallback with this delta (default: never)")
     ap.add_argument("--small-batch", type=int, default=None,
                     help="serving: queued requests the lockstep server sends as single calls (default: the server's)")
     return ap.parse_args()
@@ -395,9 +399,12 @@ def main():
     t = time.perf_counter()
     adj = W.config3_graph(n)
     log(f"[bench] graph n={n} generated in {time.perf_counter() - t:.1f}s")
-    g = Graph(adj, undirected=True, capacity=cap)
+    minimax = args.semiring == "minimax"
+    g = Graph(adj, undirected=True, capacity=cap, minimax=minimax)
+    if args.fallback is not None:
+        g.set_fallback(1, args.fallback)
     torch.cuda.synchronize()
-    log("[bench] cold start done")
+    log(f"[bench] cold start done ({args.semiring} paths)")
     names = kernel_names()
     kid = {nm: i for i, nm in enumerate(names)}
 
@@ -534,7 +541,7 @@ def main():
         c, ms = prof_totals["timed"]
         alg = adds_bytes if prof_kernel == "add_relax" else removes_bytes
         achieved = alg / (ms * 1e-3) / 1e9
-        tb = traffic_from_profiles(prof_kernel)
+        tb = None if minimax else traffic_from_profiles(prof_kernel)   # counters were taken on shortest paths
         roofline = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
@@ -551,14 +558,14 @@ def main():
         t0 = time.perf_counter()
         g.query(a, b)
         t1 = time.perf_counter()
-        _, on, key = g.query_nodes(a, b)
+        _, on, key = g.query_nodes(a, b) if not minimax else (0, [], [])
         t2 = time.perf_counter()
         q_path.append((t1 - t0) * 1e3)
         q_nodes.append((t2 - t1) * 1e3)
         q_cand.append(len(on))
         q_key.append(len(key))
     query_ms = {"pairs": len(q_path), "path_p50": round(float(np.median(q_path)), 4),
-                "nodes_p50": round(float(np.median(q_nodes)), 4),
+                "nodes_p50": None if minimax else round(float(np.median(q_nodes)), 4),
                 "mean_candidates": round(float(np.mean(q_cand)), 2), "mean_key_nodes": round(float(np.mean(q_key)), 2)}
     log(f"[bench] queries: {query_ms}")
 
@@ -567,7 +574,7 @@ def main():
         # warm result == GPU cold Floyd-Warshall of the final graph
         A_final = g.matrix_device("A")
         D_warm = g.matrix_device("D")
-        g2 = Graph(A_final, undirected=True, capacity=A_final.shape[0])
+        g2 = Graph(A_final, undirected=True, capacity=A_final.shape[0], minimax=minimax)
         verify = bool(torch.equal(D_warm, g2.matrix_device("D")))
         g2.close()
         del A_final, D_warm
@@ -583,7 +590,8 @@ def main():
         if sel.any():
             by_kind[k] = round(float(lat[sel].mean()), 4)
     out = {
-        "metric": "warm-start APSP updates/s (n=16384, 1 GPU)",
+        "metric": ("warm-start minimax APSP updates/s (n=16384, 1 GPU)" if minimax
+                   else "warm-start APSP updates/s (n=16384, 1 GPU)"),
         "value": round(value, 2),
         "unit": "updates/s",
         "n_gpus": 1,
@@ -600,6 +608,7 @@ def main():
                          f"{per} sequential updates per step ({counts[W.ADD]} add / {counts[W.REMOVE]} remove / "
                          f"{counts[W.DECREASE]} decrease / {counts[W.INCREASE]} increase incl. one worst-case increase)"),
             "n": n, "updates_per_step": per, "parallelism": "none (1 GPU)",
+            "paths": args.semiring, "fallback_delta": args.fallback,
         },
         "cold_fw_ms": round(cold_med, 2),
         "cold_updates_per_s": round(1e3 / cold_med, 3),
