@@ -528,7 +528,14 @@ apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32
     if (!lookup(g, i, &si) || !lookup(g, j, &sj)) return fail(APSP_E_NOT_FOUND, "apsp_query: id is not live");
     hipStream_t s = g->stream;
     g->prof.begin(KID_QUERY);
-    SR(g, launch_query)(g->dg, si, sj, g->qbuf, g->qscratch, s);
+    if (g->minimax) {
+        if (const char *bad = mm::launch_query_bottleneck(g->dg, si, sj, g->qbuf, g->qscratch, g->qbuf_h, s)) {
+            g->prof.end();
+            return fail(APSP_E_DEVICE, std::string("apsp_query: ") + bad);
+        }
+    } else {
+        launch_query(g->dg, si, sj, g->qbuf, g->qscratch, s);
+    }
     g->prof.end();
     apsp_status st = check_launch("apsp_query");
     if (st) return st;

@@ -128,6 +128,12 @@ APSP_SR_END
 #include "launchers.inc"
 namespace mm {
 #include "launchers.inc"
+// Minimax path query: breadth-first search from si over edges of weight
+// <= D[si][sj], one launch per level, a host sync every few levels through
+// probe_host (pinned, >= 8 ints).  out as for launch_query.  Returns the
+// name of a failed step, or nullptr.
+const char *launch_query_bottleneck(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch,
+                                    int32_t *probe_host, hipStream_t s);
 }
 
 // Kernel ids for per-kernel timing (apsp_profile).

@@ -14,6 +14,154 @@ void launch_query(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32
     k_query<<<1, 1024, 0, s>>>(g, si, sj, out, scratch);
 }
 
+#ifdef APSP_SEMIRING_MINIMAX
+// ---- a minimax path of a pair ------------------------------------------------
+// With max in place of +, Algorithm 7's candidate set keeps most of the graph
+// (ties are the rule: on an undirected graph minimax distances form an
+// ultrametric), so the path is found directly: every walk from i to j over
+// edges of weight <= d = D[i][j] is a minimax path, and a breadth-first
+// search from i over those edges, one launch per level, reaches j.  Its
+// parent tree gives a simple path (fewest edges among them).
+// Scratch (4 P ints): parent[P], two frontiers of P, the visited bitmap
+// (P / 32 words), then QB_CTL control words.
+constexpr int QB_LEVELS_PER_SYNC = 16;
+constexpr int QB_GRID = 1024;
+enum QbCtl { QB_COUNT0 = 0, QB_COUNT1, QB_COUNT2, QB_FOUND, QB_EMPTY, QB_CTL };
+
+struct QbView {
+    int32_t *parent, *f0, *f1;
+    uint32_t *visited;
+    int32_t *ctl;
+};
+
+__host__ __device__ inline QbView qb_view(int32_t *scratch, int32_t P) {
+    QbView v;
+    v.parent = scratch;
+    v.f0 = scratch + P;
+    v.f1 = scratch + 2 * P;
+    v.visited = (uint32_t *)(scratch + 3 * P);
+    v.ctl = scratch + 3 * P + (P + 31) / 32;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_qb_init(DevGraph g, int32_t si, int32_t sj, int32_t *scratch) {
+    const QbView v = qb_view(scratch, g.P);
+    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < (g.P + 31) / 32) v.visited[w] = w == (si >> 5) ? 1u << (si & 31) : 0u;
+    if (w == 0) {
+        v.ctl[QB_COUNT0] = 1;
+        v.ctl[QB_COUNT1] = 0;
+        v.ctl[QB_COUNT2] = 0;
+        v.ctl[QB_FOUND] = si == sj;
+        v.ctl[QB_EMPTY] = 0;
+        v.f0[0] = si;
+        v.parent[si] = -1;
+    }
+}
+
+// Level `level`: every edge a -> b of weight <= d out of the level's frontier
+// to an unvisited b puts b on the next frontier.  One wavefront per (frontier
+// node, 1024-column chunk) work item, grid-stride.  Frontier sizes rotate
+// through three counters: level l reads count l % 3, adds to (l + 1) % 3 and
+// zeroes (l + 2) % 3 for the level after.  Once j is reached, or a frontier
+// is empty (also when j is unreachable), a sticky flag ends every later level.
+__global__ __launch_bounds__(256) void k_qb_level(DevGraph g, int32_t si, int32_t sj, int32_t level, int32_t *scratch) {
+    const QbView v = qb_view(scratch, g.P);
+    if (v.ctl[QB_FOUND] || v.ctl[QB_EMPTY]) return;
+    const uint32_t d = (uint32_t)g.D[(int64_t)si * g.ld + sj];
+    const int32_t cnt_in = v.ctl[QB_COUNT0 + level % 3];
+    if (cnt_in == 0 || d >= INF) {
+        if (threadIdx.x == 0) v.ctl[QB_EMPTY] = 1;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) v.ctl[QB_COUNT0 + (level + 2) % 3] = 0;  // the level after next
+    int32_t *cnt_out = &v.ctl[QB_COUNT0 + (level + 1) % 3];
+    const int32_t *fin = level % 2 ? v.f1 : v.f0;
+    int32_t *fout = level % 2 ? v.f0 : v.f1;
+    const int n = g.n_slots;
+    const int32_t chunks = (n + 1023) / 1024;
+    const int64_t items = (int64_t)cnt_in * chunks;
+    const int lane = lane_id();
+    for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += (int64_t)gridDim.x * 4) {
+        const int32_t a = fin[it / chunks];
+        const int32_t cb = (int32_t)(it % chunks) * 1024;
+        const int32_t *arow = g.A + (int64_t)a * g.ld;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t b0 = cb + q * 256 + lane * 4;
+            uint32_t take = 0;
+            if (b0 < n) {
+                const uint4 wv = *reinterpret_cast<const uint4 *>(arow + b0);
+                const uint32_t ws[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int32_t b = b0 + e;
+                    if (b >= n || b == a || ws[e] > d) continue;
+                    const uint32_t bit = 1u << (b & 31);
+                    if (v.visited[b >> 5] & bit) continue;
+                    if (atomicOr(&v.visited[b >> 5], bit) & bit) continue;
+                    v.parent[b] = a;
+                    take |= 1u << e;
+                    if (b == sj) atomicExch(&v.ctl[QB_FOUND], 1);
+                }
+            }
+            // one counter atomic per wavefront for the nodes it took
+            const int mine = __popc(take);
+            int incl = mine;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(incl, o);
+                if (lane >= o) incl += t;
+            }
+            const int total = __shfl(incl, 63);
+            int base = 0;
+            if (lane == 63 && total) base = atomicAdd(cnt_out, total);
+            base = __shfl(base, 63);
+            int pos = base + incl - mine;
+            for (int e = 0; e < 4; ++e)
+                if (take >> e & 1u) fout[pos++] = b0 + e;
+        }
+    }
+}
+
+// The path from the parent tree: out = dist, length, error, ids from i to j.
+__global__ void k_qb_path(DevGraph g, int32_t si, int32_t sj, int32_t *out, const int32_t *scratch) {
+    const QbView v = qb_view(const_cast<int32_t *>(scratch), g.P);
+    const uint32_t d = (uint32_t)g.D[(int64_t)si * g.ld + sj];
+    if (si == sj) { out[0] = 0; out[1] = 1; out[2] = 0; out[3] = g.id_of_slot[si]; return; }
+    if (d >= INF) { out[0] = (int32_t)INF; out[1] = 0; out[2] = 0; return; }
+    if (!v.ctl[QB_FOUND]) { out[0] = (int32_t)d; out[1] = 0; out[2] = 1; return; }
+    int32_t len = 1;
+    int32_t c0 = sj;
+    for (; c0 >= 0 && c0 != si && len <= g.n_slots; c0 = v.parent[c0]) ++len;
+    if (c0 != si) { out[0] = (int32_t)d; out[1] = 0; out[2] = 1; return; }
+    int32_t c = sj;
+    for (int32_t p = len - 1; p >= 0; --p) {
+        out[3 + p] = g.id_of_slot[c];
+        c = v.parent[c];
+    }
+    out[0] = (int32_t)d;
+    out[1] = len;
+    out[2] = 0;
+}
+
+const char *launch_query_bottleneck(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch,
+                                    int32_t *probe_host, hipStream_t s) {
+    k_qb_init<<<((g.P + 31) / 32 + 255) / 256, 256, 0, s>>>(g, si, sj, scratch);
+    const QbView v = qb_view(scratch, g.P);
+    for (int32_t level = 0; si != sj && level < g.n_slots; level += QB_LEVELS_PER_SYNC) {
+        for (int32_t l = level; l < level + QB_LEVELS_PER_SYNC; ++l)
+            k_qb_level<<<QB_GRID, 256, 0, s>>>(g, si, sj, l, scratch);
+        if (hipMemcpyAsync(probe_host, v.ctl, QB_CTL * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return "query level sync";
+        if (probe_host[QB_FOUND] || probe_host[QB_EMPTY]) break;
+    }
+    k_qb_path<<<1, 1, 0, s>>>(g, si, sj, out, scratch);
+    return nullptr;
+}
+#endif
+
 // ---- nodes on some / on every shortest path of a pair ----------------------
 // (Algorithms 7 and 8 give the candidates and the paths through them,
 // Theorem al_correct; Algorithm 10 intersects the pair's shortest paths.)
