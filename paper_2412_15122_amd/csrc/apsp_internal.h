@@ -26,7 +26,8 @@ constexpr int FUSED_GRID = 512;  // resident work-groups of the mask+recompute k
 constexpr int FUSED_THREADS = 1024;  // threads of a heavy-row work-group
 constexpr int RECOMPUTE_STATS = 6;   // rows, flagged, full scans, sweeps, changed, rows changed
 constexpr int ROW_CAP = 32;      // flagged columns listed per row (more: a "heavy" row)
-constexpr int RECOMPUTE_BLOCKS = 2048;  // work-groups of the per-row recompute (4 waves each)
+constexpr int RECOMPUTE_BLOCKS = 2048;  // work-groups of the per-row recompute
+constexpr int RECOMPUTE_WAVES = 4;      // wavefronts per recompute work-group, one row each at a time
 
 enum EdgeMode : int32_t { EDGE_NOOP = 0, EDGE_DECREASE = 1, EDGE_INCREASE = 2 };
 enum FusedMode : int32_t { FUSED_REMOVE = 0, FUSED_INCREASE = 1 };

@@ -350,8 +350,9 @@ __global__ void k_remove_begin(DevGraph g, int32_t k, int32_t *colk, int32_t *ro
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_stats(g.ctl);
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n_slots) return;
-    colk[i] = g.D[(int64_t)i * g.ld + k];
-    rowk[i] = g.D[(int64_t)k * g.ld + i];
+    const int32_t rk = g.D[(int64_t)k * g.ld + i];
+    rowk[i] = rk;
+    colk[i] = g.undirected ? rk : g.D[(int64_t)i * g.ld + k];  // D symmetric when undirected
 }
 
 void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *rowk, hipStream_t s) {
@@ -419,10 +420,12 @@ __global__ __launch_bounds__(256) void k_edge_begin(DevGraph g, int32_t su, int3
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n_slots) return;
     const int64_t ld = g.ld;
-    colu[i] = g.D[(int64_t)i * ld + su];
-    colv[i] = g.D[(int64_t)i * ld + sv];
-    rowu[i] = g.D[(int64_t)su * ld + i];
-    rowv[i] = g.D[(int64_t)sv * ld + i];
+    const int32_t ru = g.D[(int64_t)su * ld + i], rv = g.D[(int64_t)sv * ld + i];
+    rowu[i] = ru;
+    rowv[i] = rv;
+    // an undirected graph's D is symmetric: its columns are read as rows
+    colu[i] = g.undirected ? ru : g.D[(int64_t)i * ld + su];
+    colv[i] = g.undirected ? rv : g.D[(int64_t)i * ld + sv];
 }
 
 void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int32_t *colu, int32_t *colv,
@@ -637,11 +640,11 @@ __global__ __launch_bounds__(256) void k_count_flag_rows(DevGraph g, FusedArgs f
 // reset_only: only clear the flagged rows' words (after a cold fallback).
 // A row's flag words are cleared once read, except those of an undirected
 // heavy row, which the heavy-row pass reads (and clears) later.
-__global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa, int32_t reset_only) {
-    __shared__ int32_t lists[4][ROW_CAP];
-    __shared__ int32_t fsls[4][ROW_CAP];
-    __shared__ int32_t olds[4][ROW_CAP];
-    __shared__ int32_t stat[4][RECOMPUTE_STATS];
+__global__ __launch_bounds__(64 * RECOMPUTE_WAVES) void k_recompute_rows(DevGraph g, FusedArgs fa, int32_t reset_only) {
+    __shared__ int32_t lists[RECOMPUTE_WAVES][ROW_CAP];
+    __shared__ int32_t fsls[RECOMPUTE_WAVES][ROW_CAP];
+    __shared__ int32_t olds[RECOMPUTE_WAVES][ROW_CAP];
+    __shared__ int32_t stat[RECOMPUTE_WAVES][RECOMPUTE_STATS];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     int32_t *list = lists[wv];
     int32_t *fsl = fsls[wv];
@@ -651,7 +654,7 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
     const int64_t nwp = (g.P + 31) / 32;
     int my_rows = 0, my_fs = 0, my_sweeps = 0, my_flagged = 0, my_changed = 0, my_rows_changed = 0;
     const bool active = !(fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE);
-    for (int32_t i = blockIdx.x * 4 + wv; active && i < n; i += gridDim.x * 4) {
+    for (int32_t i = blockIdx.x * RECOMPUTE_WAVES + wv; active && i < n; i += gridDim.x * RECOMPUTE_WAVES) {
         if (!row_marked(fa, n, i)) continue;
         ++my_rows;
         // flagged columns of row i -> list (at most ROW_CAP kept)
@@ -745,8 +748,9 @@ __global__ __launch_bounds__(256) void k_recompute_rows(DevGraph g, FusedArgs fa
     __syncthreads();
     if (threadIdx.x < RECOMPUTE_STATS) {
         const int q = threadIdx.x;
-        int v = q == 3 ? max(max(stat[0][q], stat[1][q]), max(stat[2][q], stat[3][q]))
-                       : stat[0][q] + stat[1][q] + stat[2][q] + stat[3][q];
+        int v = stat[0][q];
+#pragma unroll
+        for (int w = 1; w < RECOMPUTE_WAVES; ++w) v = q == 3 ? max(v, stat[w][q]) : v + stat[w][q];
         fa.partials[blockIdx.x * RECOMPUTE_STATS + q] = v;
     }
 }
@@ -941,8 +945,8 @@ void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t 
 
 int32_t launch_mask_recompute(const DevGraph &g, const FusedArgs &fa, int32_t reset_only, hipStream_t s) {
     if (g.n_slots <= 0) return 0;
-    const int blocks = std::min(RECOMPUTE_BLOCKS, (g.n_slots + 3) / 4);
-    k_recompute_rows<<<blocks, 256, 0, s>>>(g, fa, reset_only);
+    const int blocks = std::min(RECOMPUTE_BLOCKS, (g.n_slots + RECOMPUTE_WAVES - 1) / RECOMPUTE_WAVES);
+    k_recompute_rows<<<blocks, 64 * RECOMPUTE_WAVES, 0, s>>>(g, fa, reset_only);
     if (reset_only) return -blocks;  // no heavy-row pass: its partials are not summed
     k_fused_heavy<<<FUSED_GRID, FUSED_THREADS, fused_lds_bytes(g.P), s>>>(g, fa);
     return blocks;
