@@ -25,9 +25,10 @@ def lib():
     return N.load()
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_update_and_query_calls():
     names = declared_functions()
-    for required in ("apsp_cold", "apsp_add_node", "apsp_remove_node", "apsp_update_edge", "apsp_query"):
+    for required in ("apsp_cold", "apsp_add_node", "apsp_remove_node", "apsp_update_edge", "apsp_query",
+                     "apsp_query_nodes"):
         assert required in names
 
 
