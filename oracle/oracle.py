@@ -364,16 +364,25 @@ def pair_nodes(A: np.ndarray, D: np.ndarray, i: int, j: int) -> Tuple[List[int],
            edges (x -> y with D[i][x] (+) A[x][y] == D[i][y], both on) once t
            is taken out -- a walk over tight edges from i to j has length
            D[i][j], and every shortest walk is one.
-    i == j gives ([i], []); an unreachable pair ([], [])."""
-    A = _check_adj(A).astype(np.int64)
-    D = np.asarray(D, dtype=np.int64)
+    i == j gives ([i], []); an unreachable pair ([], []).  Only row i and
+    column j of D are read (``pair_nodes_from``)."""
+    D = np.asarray(D)
+    return pair_nodes_from(A, D[i, :], D[:, j], i, j)
+
+
+def pair_nodes_from(A: np.ndarray, di, dj, i: int, j: int) -> Tuple[List[int], List[int]]:
+    """``pair_nodes`` given di[t] = D[i][t] and dj[t] = D[t][j] (e.g. one
+    Dijkstra row from i and one column into j on a large graph); A is read
+    entry by entry."""
+    A = np.asarray(A)
+    di = np.asarray(di, dtype=np.int64)
+    dj = np.asarray(dj, dtype=np.int64)
     if i == j:
         return [i], []
-    d = D[i, j]
+    d = int(di[j])
     if d >= INF:
         return [], []
-    n = D.shape[0]
-    on = [t for t in range(n) if oplus(D[i, t], D[t, j]) == d]
+    on = [int(t) for t in np.nonzero(oplus(di, dj) == d)[0]]
     on_set = set(on)
 
     def reaches_without(t):
@@ -386,7 +395,8 @@ def pair_nodes(A: np.ndarray, D: np.ndarray, i: int, j: int) -> Tuple[List[int],
             for y in on:
                 if y in seen or y == t or y == x:
                     continue
-                if A[x, y] < INF and D[i, x] + A[x, y] == D[i, y]:
+                w = int(A[x, y])
+                if w < INF and int(di[x]) + w == int(di[y]):
                     seen.add(y)
                     stack.append(y)
         return False

@@ -10,7 +10,8 @@ sampled rows against the oracle's Dijkstra; a block of the benchmark's update
 stream, led by the worst-case increase (selected by the oracle), each update
 checked in full against the GPU cold start of the updated graph and, at
 checkpoints, on sampled rows against the oracle.  The light-edge scopes the
-benchmark uses to pick that edge are checked against the oracle too.
+benchmark uses to pick that edge are checked against the oracle too, and so
+are the final graph's pair node sets on sampled pairs.
 """
 import os
 
@@ -136,3 +137,12 @@ def test_undirected_n16384_benchmark_stream():
             sample = touched + [ids[int(x)] for x in rng.integers(0, len(ids), size=4)]
             check_rows(g, A, ids, sample, f"update {t} {upd.kind}")
     g.sync()
+    # the final graph's pair node sets (Algorithms 8 and 10) on sampled pairs:
+    # the oracle needs row i and column j only (undirected: column j = row j)
+    for _ in range(4):
+        a, b = (int(x) for x in rng.integers(0, len(ids), size=2))
+        rows = O.dijkstra_rows(A, [a, b], threads=THREADS)
+        on_o, key_o = O.pair_nodes_from(A, rows[0], rows[1], a, b)
+        dist, on, key = g.query_nodes(ids[a], ids[b])
+        assert dist == int(rows[0][b])
+        assert on == [ids[p] for p in on_o] and key == [ids[p] for p in key_o], (a, b)
