@@ -213,6 +213,28 @@ def minimax_apsp(A: np.ndarray) -> np.ndarray:
     return D.astype(np.int32)
 
 
+def minimax_rows(A: np.ndarray, srcs: Sequence[int]) -> np.ndarray:
+    """Rows srcs of the minimax distance matrix by dense Dijkstra with max in
+    place of + (a node's label is final once it is the least unsettled one,
+    since max never lowers a label), one numpy step per settled node."""
+    A = np.asarray(A)
+    n = A.shape[0]
+    out = np.empty((len(srcs), n), dtype=np.int32)
+    for r, s in enumerate(srcs):
+        dist = np.full(n, INF, dtype=np.int64)
+        done = np.zeros(n, dtype=bool)
+        dist[s] = 0
+        for _ in range(n):
+            cand = np.where(done, np.int64(INF) + 1, dist)
+            u = int(np.argmin(cand))
+            if cand[u] >= INF:
+                break
+            done[u] = True
+            np.minimum(dist, np.maximum(dist[u], A[u].astype(np.int64)), out=dist, where=~done)
+        out[r] = dist
+    return out
+
+
 def brute_force_minimax(A: np.ndarray) -> np.ndarray:
     """MM(i,j) = min over all simple i->j paths of the largest edge weight
     (a walk's cycles can be cut without raising its largest edge), n <= 8."""

@@ -149,3 +149,54 @@ def test_minimax_rejects_pair_nodes_and_batches():
     assert np.array_equal(g.matrix(), O.minimax_apsp(A))
     b.close()
     g.close()
+
+
+def test_minimax_benchmark_graph_n16384():
+    """The benchmark graph (undirected complete, n = 16384) over the minimax
+    semiring with Algorithm 5's cost fallback (delta = 0.5), as the bench
+    runs it: the cold start and a block of the update stream, each state
+    checked on sampled rows against the oracle's minimax Dijkstra, and
+    minimax path queries on the final graph."""
+    from paper_2412_15122_amd.apsp import Graph
+    n = 16384
+    adj = W.config3_graph(n)
+    g = Graph(adj, undirected=True, capacity=n + 16, minimax=True)
+    g.set_fallback(1, 0.5)
+    rng = np.random.default_rng(216)
+    ids = list(range(n))
+
+    def check(A, ids, extra, what):
+        pos = [ids.index(x) for x in extra] + [int(x) for x in rng.integers(0, len(ids), size=2)]
+        got = g.matrix_device("D")[pos].cpu().numpy()
+        assert np.array_equal(got, O.minimax_rows(A, pos)), what
+
+    check(adj, ids, [0, n - 1], "cold")
+    stream = W.Config3Stream(adj, counts={W.ADD: 3, W.REMOVE: 2, W.DECREASE: 3, W.INCREASE: 2})
+    A = adj
+    for t, upd in enumerate(stream.next_block()):
+        log("minimax n=16384 update", t, upd.kind)
+        if upd.kind == W.ADD:
+            g.add_node(upd.w_out)
+            A, ids = O.apply_update(A, ids, "add", w_out=upd.w_out, undirected=True)
+            touched = [ids[-1]]
+        elif upd.kind == W.REMOVE:
+            g.remove_node(upd.u)
+            A, ids = O.apply_update(A, ids, "remove", u=upd.u, undirected=True)
+            touched = []
+        else:
+            g.update_edge(upd.u, upd.v, upd.w)
+            A, ids = O.apply_update(A, ids, "edge", u=upd.u, v=upd.v, w=upd.w, undirected=True)
+            touched = [upd.u]
+        if t % 2 == 0 or upd.kind == W.REMOVE:
+            check(A, ids, touched, f"update {t} {upd.kind}")
+    assert g.ids() == ids
+    pos = [int(x) for x in rng.integers(0, len(ids), size=3)]
+    rows = O.minimax_rows(A, pos)
+    for r, a in enumerate(pos):
+        b = int(rng.integers(0, len(ids)))
+        dist, path = g.query(ids[a], ids[b])
+        assert dist == int(rows[r][b])
+        p = [ids.index(v) for v in path]
+        assert p[0] == a and p[-1] == b and len(set(p)) == len(p)
+        assert max((int(A[x, y]) for x, y in zip(p, p[1:])), default=0) == dist
+    g.close()

@@ -519,3 +519,15 @@ def test_minimax_removal_mask_holds_every_change():
         D2 = O.minimax_apsp(A[np.ix_(keep, keep)])
         F = O.remove_mask(D, k, minimax=True)[np.ix_(keep, keep)]
         assert np.array_equal(D2[~F], D[np.ix_(keep, keep)][~F]), trial
+
+
+def test_minimax_rows_equal_floyd_warshall():
+    rng = np.random.default_rng(91)
+    for trial in range(12):
+        n = int(rng.integers(1, 70))
+        A = W.random_graph(n, 1, int(rng.integers(1, 30)), undirected=bool(trial % 2),
+                           density=float(rng.uniform(0.05, 0.9)), seed=int(rng.integers(1 << 30)),
+                           zero_frac=0.1 if trial % 3 == 0 else 0.0)
+        D = O.minimax_apsp(A)
+        srcs = [int(x) for x in rng.integers(0, n, size=min(n, 5))]
+        assert np.array_equal(O.minimax_rows(A, srcs), D[srcs]), trial
