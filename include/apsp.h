@@ -84,8 +84,8 @@ typedef enum {
  * its algorithms carry over to.  Every single-graph call then runs the same
  * steps with max in place of + (Theorems theorem2-theorem3 and Corollary
  * corollary3 hold with max, which is monotone with 0 as identity on weights
- * >= 0).  Not available for such graphs: apsp_query_nodes and the batched
- * calls (both return APSP_E_INVALID). */
+ * >= 0).  apsp_query_nodes takes shortest-path graphs only; a batch
+ * (apsp_batch_run) takes graphs of one kind: all minimax or none. */
 typedef enum { APSP_DIRECTED = 0, APSP_UNDIRECTED = 1, APSP_MINIMAX = 2 } apsp_kind;
 
 /* What apsp_remove_node and an edge increase do after building the mask
@@ -346,7 +346,9 @@ apsp_status apsp_batch_destroy(apsp_batch *b);
 apsp_status apsp_batch_set_config(apsp_batch *b, int32_t grid, int32_t order, int32_t variant,
                                   int32_t use_graph);
 /* Runs items[0..num_items) on graphs[0..num_graphs) (distinct handles) on
- * hip_stream.  Work queued earlier for a graph on another stream must have
+ * hip_stream.  The graphs are all shortest-path graphs or all minimax ones
+ * (APSP_MINIMAX; else APSP_E_INVALID): the launch runs the kernels of that
+ * semiring.  Work queued earlier for a graph on another stream must have
  * completed.  Every item is checked first; if one is invalid, nothing runs,
  * no graph changes, and the status names the first bad item.  new_ids
  * (host, num_items, may be NULL) receives the id of each added node and -1

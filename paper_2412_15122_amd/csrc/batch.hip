@@ -30,6 +30,7 @@
 #include "device_common.h"
 
 namespace apsp {
+APSP_SR_BEGIN
 
 // ---------------------------------------------------------------------------
 // streaming helpers
@@ -195,10 +196,10 @@ __device__ __forceinline__ void add_out_cols(const DevGraph &g, const BatchGraph
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const uint32_t w = (uint32_t)ent[t].y;
-                acc[0] = min(acc[0], w + v[t].x);
-                acc[1] = min(acc[1], w + v[t].y);
-                acc[2] = min(acc[2], w + v[t].z);
-                acc[3] = min(acc[3], w + v[t].w);
+                acc[0] = min(acc[0], cat(w, v[t].x));
+                acc[1] = min(acc[1], cat(w, v[t].y));
+                acc[2] = min(acc[2], cat(w, v[t].z));
+                acc[3] = min(acc[3], cat(w, v[t].w));
             }
             if ((uint32_t)ent[3].y >= mx) break;  // every later entry is at least as heavy
         }
@@ -211,12 +212,12 @@ __device__ __forceinline__ void add_out_cols(const DevGraph &g, const BatchGraph
     const bool live_c = c < n && g.id_of_slot[c] >= 0;
     const int need = block_sum<BATCH_THREADS>(live_c && fin > beta_eff, s_red);
     if (need && live_c && fin > beta_eff)
-        for (int32_t t = 0; t < n; ++t) fin = min(fin, (uint32_t)bg.wo[t] + (uint32_t)g.D[(int64_t)t * g.ld + c]);
+        for (int32_t t = 0; t < n; ++t) fin = min(fin, cat((uint32_t)bg.wo[t], (uint32_t)g.D[(int64_t)t * g.ld + c]));
     if (c < n) bg.vout[c] = live_c ? (int32_t)min(fin, INF) : (int32_t)INF;
     __syncthreads();
 }
 
-// The new column over rows [r0, r1) (directed graphs): in[r] = min_x D[r][x] +
+// The new column over rows [r0, r1) (directed graphs): in[r] = min_x D[r][x] (+)
 // wi[x] (Corollary corollary2), over p's light in-edges (at most 64, read
 // once per wavefront: lane l of a 16-lane group holds entries l, l + 16,
 // l + 32, l + 48).  A wavefront takes 4 rows at a time, one per 16-lane
@@ -249,7 +250,7 @@ __device__ __forceinline__ void add_in_rows(const DevGraph &g, const BatchGraph 
             for (int q = 0; q < 4; ++q) v[q] = (uint32_t)ent[q].y < INF ? (uint32_t)Dr[ent[q].x] : INF;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if ((uint32_t)ent[q].y < INF) best = min(best, (uint32_t)ent[q].y + v[q]);
+                if ((uint32_t)ent[q].y < INF) best = min(best, cat((uint32_t)ent[q].y, v[q]));
         }
 #pragma unroll
         for (int o = 1; o < 16; o <<= 1) best = min(best, (uint32_t)__shfl_xor((int)best, o, 16));
@@ -286,7 +287,7 @@ __device__ __forceinline__ void add_prologue(const DevGraph &g, const BatchGraph
     __syncthreads();
 }
 
-// Theorem theorem3 over rows [r0, r1): D[i][j] = min(D[i][j], in[i] + out[j]).
+// Theorem theorem3 over rows [r0, r1): D[i][j] = min(D[i][j], in[i] (+) out[j]).
 // outv: the new row (LDS stage or global).
 template <int U>
 __device__ __forceinline__ void add_relax_rows(const DevGraph &g, const BatchGraph &bg, int32_t r0, int32_t r1, const uint32_t *outv) {
@@ -299,7 +300,7 @@ __device__ __forceinline__ void add_relax_rows(const DevGraph &g, const BatchGra
             if (!ok) return;
             const uint32_t a = (uint32_t)in[i];
             const uint4 o = v.a;
-            store_min4(g, i, c0, d, make_uint4(a + o.x, a + o.y, a + o.z, a + o.w));
+            store_min4(g, i, c0, d, make_uint4(cat(a, o.x), cat(a, o.y), cat(a, o.z), cat(a, o.w)));
         });
 }
 
@@ -407,7 +408,7 @@ __device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph 
                 for (int e = 0; e < 4; ++e) {
                     const int32_t j = c0 + e;
                     const bool f = j < n && j != i && !(fa.mode == FUSED_REMOVE && j == fa.k) && dv[e] < INF &&
-                                   ((rt.t1 && rt.a1 + w1[e] == dv[e]) || (rt.t2 && rt.a2 + w2[e] == dv[e]));
+                                   ((rt.t1 && cat(rt.a1, w1[e]) == dv[e]) || (rt.t2 && cat(rt.a2, w2[e]) == dv[e]));
                     bits |= (uint32_t)f << e;
                 }
             }
@@ -463,14 +464,14 @@ __device__ __forceinline__ void wave_bellman_ford_words(const DevGraph &g, int32
                         if (e1 + 1 >= lim) pc.w = (int)INF;
                         if (e1 + 3 >= lim) pd.w = (int)INF;
                         uint32_t cm = INF;
-                        if ((uint32_t)pa.y < best) cm = min(cm, (uint32_t)Drow[pa.x] + (uint32_t)pa.y);
-                        if ((uint32_t)pa.w < best) cm = min(cm, (uint32_t)Drow[pa.z] + (uint32_t)pa.w);
-                        if ((uint32_t)pb.y < best) cm = min(cm, (uint32_t)Drow[pb.x] + (uint32_t)pb.y);
-                        if ((uint32_t)pb.w < best) cm = min(cm, (uint32_t)Drow[pb.z] + (uint32_t)pb.w);
-                        if ((uint32_t)pc.y < best) cm = min(cm, (uint32_t)Drow[pc.x] + (uint32_t)pc.y);
-                        if ((uint32_t)pc.w < best) cm = min(cm, (uint32_t)Drow[pc.z] + (uint32_t)pc.w);
-                        if ((uint32_t)pd.y < best) cm = min(cm, (uint32_t)Drow[pd.x] + (uint32_t)pd.y);
-                        if ((uint32_t)pd.w < best) cm = min(cm, (uint32_t)Drow[pd.z] + (uint32_t)pd.w);
+                        if ((uint32_t)pa.y < best) cm = min(cm, cat((uint32_t)Drow[pa.x], (uint32_t)pa.y));
+                        if ((uint32_t)pa.w < best) cm = min(cm, cat((uint32_t)Drow[pa.z], (uint32_t)pa.w));
+                        if ((uint32_t)pb.y < best) cm = min(cm, cat((uint32_t)Drow[pb.x], (uint32_t)pb.y));
+                        if ((uint32_t)pb.w < best) cm = min(cm, cat((uint32_t)Drow[pb.z], (uint32_t)pb.w));
+                        if ((uint32_t)pc.y < best) cm = min(cm, cat((uint32_t)Drow[pc.x], (uint32_t)pc.y));
+                        if ((uint32_t)pc.w < best) cm = min(cm, cat((uint32_t)Drow[pc.z], (uint32_t)pc.w));
+                        if ((uint32_t)pd.y < best) cm = min(cm, cat((uint32_t)Drow[pd.x], (uint32_t)pd.y));
+                        if ((uint32_t)pd.w < best) cm = min(cm, cat((uint32_t)Drow[pd.z], (uint32_t)pd.w));
                         cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
                         cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
                         best = min(best, cm);
@@ -720,7 +721,7 @@ __device__ __forceinline__ void dec_relax_rows(const DevGraph &g, const BatchGra
         g, n, r0, r1,
         [&](int32_t i) {
             const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
-            return du + wn < dv || (und && dv + wn < du);
+            return cat(du, wn) < dv || (und && cat(dv, wn) < du);
         },
         [&](int32_t c0) {
             return Vec2{vec4(SV, c0, n), und ? vec4(SU, c0, n) : make_uint4(INF, INF, INF, INF)};
@@ -728,13 +729,13 @@ __device__ __forceinline__ void dec_relax_rows(const DevGraph &g, const BatchGra
         [&](int32_t i, int32_t c0, bool ok, uint4 d, const Vec2 &v) {
             if (!ok) return;
             const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
-            const uint32_t x1 = du + wn < dv ? du + wn : INF;
-            const uint32_t x2 = und && dv + wn < du ? dv + wn : INF;
+            const uint32_t x1 = cat(du, wn) < dv ? cat(du, wn) : INF;
+            const uint32_t x2 = und && cat(dv, wn) < du ? cat(dv, wn) : INF;
             const uint4 rv = v.a;
             const uint4 ru = v.b;
             store_min4(g, i, c0, d,
-                       make_uint4(min(x1 + rv.x, x2 + ru.x), min(x1 + rv.y, x2 + ru.y), min(x1 + rv.z, x2 + ru.z),
-                                  min(x1 + rv.w, x2 + ru.w)));
+                       make_uint4(min(cat(x1, rv.x), cat(x2, ru.x)), min(cat(x1, rv.y), cat(x2, ru.y)),
+                                  min(cat(x1, rv.z), cat(x2, ru.z)), min(cat(x1, rv.w), cat(x2, ru.w))));
         });
 }
 
@@ -798,14 +799,14 @@ __device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGr
                         if (e1 + 1 >= lim) pc.w = (int)INF;
                         if (e1 + 3 >= lim) pd.w = (int)INF;
                         uint32_t cm = INF;
-                        if ((uint32_t)pa.y < best) cm = min(cm, cur[pa.x] + (uint32_t)pa.y);
-                        if ((uint32_t)pa.w < best) cm = min(cm, cur[pa.z] + (uint32_t)pa.w);
-                        if ((uint32_t)pb.y < best) cm = min(cm, cur[pb.x] + (uint32_t)pb.y);
-                        if ((uint32_t)pb.w < best) cm = min(cm, cur[pb.z] + (uint32_t)pb.w);
-                        if ((uint32_t)pc.y < best) cm = min(cm, cur[pc.x] + (uint32_t)pc.y);
-                        if ((uint32_t)pc.w < best) cm = min(cm, cur[pc.z] + (uint32_t)pc.w);
-                        if ((uint32_t)pd.y < best) cm = min(cm, cur[pd.x] + (uint32_t)pd.y);
-                        if ((uint32_t)pd.w < best) cm = min(cm, cur[pd.z] + (uint32_t)pd.w);
+                        if ((uint32_t)pa.y < best) cm = min(cm, cat(cur[pa.x], (uint32_t)pa.y));
+                        if ((uint32_t)pa.w < best) cm = min(cm, cat(cur[pa.z], (uint32_t)pa.w));
+                        if ((uint32_t)pb.y < best) cm = min(cm, cat(cur[pb.x], (uint32_t)pb.y));
+                        if ((uint32_t)pb.w < best) cm = min(cm, cat(cur[pb.z], (uint32_t)pb.w));
+                        if ((uint32_t)pc.y < best) cm = min(cm, cat(cur[pc.x], (uint32_t)pc.y));
+                        if ((uint32_t)pc.w < best) cm = min(cm, cat(cur[pc.z], (uint32_t)pc.w));
+                        if ((uint32_t)pd.y < best) cm = min(cm, cat(cur[pd.x], (uint32_t)pd.y));
+                        if ((uint32_t)pd.w < best) cm = min(cm, cat(cur[pd.z], (uint32_t)pd.w));
                         cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
                         cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
                         best = min(best, cm);
@@ -845,7 +846,7 @@ __device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGr
                 bits &= bits - 1;
                 const int32_t *col = Min + (int64_t)y * g.ld;
                 uint32_t best = INF;
-                for (int32_t x = tid; x < n; x += BATCH_THREADS) best = min(best, cur[x] + (uint32_t)col[x]);
+                for (int32_t x = tid; x < n; x += BATCH_THREADS) best = min(best, cat(cur[x], (uint32_t)col[x]));
                 best = block_min<BATCH_THREADS>(best, red);
                 if (tid == 0 && best < cur[y]) {
                     cur[y] = best;
@@ -1237,4 +1238,5 @@ hipError_t launch_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs, con
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BATCH_THREADS), args, (unsigned)lds, s);
 }
 
+APSP_SR_END
 }  // namespace apsp

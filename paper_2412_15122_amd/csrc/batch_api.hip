@@ -41,6 +41,7 @@ BatchLayout batch_layout(int32_t max_graphs, int32_t max_items) {
 struct ExecKey {
     int32_t grid, variant;
     size_t lds;
+    bool minimax;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -102,12 +103,15 @@ struct apsp_batch {
 
 namespace {
 
-apsp_status launch(apsp_batch *b, int32_t n_active, int32_t P_max, hipStream_t s) {
+// The batch's graphs share one semiring: minimax picks the apsp::mm build of
+// the batched kernels.
+apsp_status launch(apsp_batch *b, int32_t n_active, int32_t P_max, bool minimax, hipStream_t s) {
     const bool lockstep = b->variant >= 2;
     int32_t grid = b->grid > 0 ? b->grid : std::max(1, std::min(n_active, 2 * b->n_cu));
     if (lockstep) {
         int32_t cap = 0;
-        if (!hip_ok(lockstep_grid(P_max, b->variant, &cap), "lockstep occupancy")) return APSP_E_DEVICE;
+        const hipError_t oc = minimax ? mm::lockstep_grid(P_max, b->variant, &cap) : lockstep_grid(P_max, b->variant, &cap);
+        if (!hip_ok(oc, "lockstep occupancy")) return APSP_E_DEVICE;
         grid = b->grid > 0 ? std::min(b->grid, cap) : cap;
     }
     auto *hdr = reinterpret_cast<BatchHeader *>(b->ws);
@@ -116,6 +120,9 @@ apsp_status launch(apsp_batch *b, int32_t n_active, int32_t P_max, hipStream_t s
     auto *items = reinterpret_cast<const BatchItem *>(b->ws + b->L.items);
     auto *tables = reinterpret_cast<const int32_t *>(b->ws + b->L.tables);
     auto go = [&](hipStream_t st) {
+        if (minimax)
+            return lockstep ? mm::launch_batch_lockstep(hdr, graphs, items, tables, P_max, grid, b->variant, st)
+                            : mm::launch_batch(hdr, graphs, order, items, P_max, grid, b->variant, st);
         return lockstep ? launch_batch_lockstep(hdr, graphs, items, tables, P_max, grid, b->variant, st)
                         : launch_batch(hdr, graphs, order, items, P_max, grid, b->variant, st);
     };
@@ -126,12 +133,12 @@ apsp_status launch(apsp_batch *b, int32_t n_active, int32_t P_max, hipStream_t s
     }
     const size_t lds = lockstep ? batch_lockstep_lds_bytes(P_max) : batch_lds_bytes(P_max);
     for (auto &x : b->execs) {
-        if (x.grid == grid && x.variant == b->variant && x.lds == lds) {
+        if (x.grid == grid && x.variant == b->variant && x.lds == lds && x.minimax == minimax) {
             if (!hip_ok(hipGraphLaunch(x.exec, s), "graph launch")) return APSP_E_DEVICE;
             return APSP_OK;
         }
     }
-    ExecKey k{grid, b->variant, lds, nullptr, nullptr};
+    ExecKey k{grid, b->variant, lds, minimax, nullptr, nullptr};
     hipStream_t cs = b->cap_stream;
     if (!hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) return APSP_E_DEVICE;
     hipError_t e = go(cs);
@@ -190,7 +197,8 @@ apsp_status apsp_batch_create(void *ws_dev, size_t ws_bytes, int32_t max_graphs,
         !hip_ok(hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev), "device attribute") ||
         !hip_ok(hipHostMalloc((void **)&b->times_h, (size_t)max_graphs * 2 * sizeof(long long), 0), "pinned alloc") ||
         !hip_ok(hipHostMalloc((void **)&b->err_h, sizeof(int32_t), 0), "pinned alloc") ||
-        !hip_ok(configure_batch(), "configuring the batched kernel")) {
+        !hip_ok(configure_batch(), "configuring the batched kernel") ||
+        !hip_ok(mm::configure_batch(), "configuring the batched kernel")) {
         apsp_batch_destroy(b);
         return APSP_E_DEVICE;
     }
@@ -243,7 +251,8 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
             const apsp_graph *g = graphs[i];
             if (!g) return fail(APSP_E_INVALID, "apsp_batch_run: NULL graph " + std::to_string(i));
             if (!seen.insert(g).second) return fail(APSP_E_INVALID, "apsp_batch_run: graph listed twice");
-            if (g->minimax) return fail(APSP_E_INVALID, "apsp_batch_run: batched launches take shortest-path graphs only");
+            if (g->minimax != graphs[0]->minimax)
+                return fail(APSP_E_INVALID, "apsp_batch_run: the graphs of one batch must share the path kind");
             if (g->cap > BATCH_MAX_CAPACITY)
                 return fail(APSP_E_INVALID, "apsp_batch_run: graph capacity above APSP_BATCH_MAX_CAPACITY");
         }
@@ -447,7 +456,7 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
         !hip_ok(hipEventRecord(b->staged, s), "event record"))
         return undo_all(log), APSP_E_DEVICE;
     b->stage_busy = true;
-    apsp_status st = launch(b, n_active, P_max, s);
+    apsp_status st = launch(b, n_active, P_max, num_graphs > 0 && graphs[0]->minimax, s);
     if (st) return undo_all(log), st;
     // later single calls on a graph's own stream run after the batch
     if (!others.empty()) {

@@ -80,18 +80,9 @@ __host__ __device__ inline int32_t batch_rows_per_chunk(int32_t n) {
     return r < 16 ? 16 : r;  // a multiple of 16: a wavefront's rows share a word of row marks
 }
 
-size_t batch_lds_bytes(int32_t P_max);
-size_t batch_lockstep_lds_bytes(int32_t P_max);
-hipError_t configure_batch();  // raise the dynamic-LDS limit once per process
-// Persistent launch of `grid` work-groups over the graphs listed in `order`.
-hipError_t launch_batch(BatchHeader *hdr, const BatchGraph *graphs, const int32_t *order, const BatchItem *items,
-                        int32_t P_max, int32_t grid, int32_t variant, hipStream_t s);
-// Lockstep schedule (variants 2 and 3): the grid that is resident all at
-// once (cooperative launch), and the launch.  tables: per step, two prefix
-// arrays over the graphs (chunks of the sweep phase, chunks of the recompute
-// phase).
-hipError_t lockstep_grid(int32_t P_max, int32_t variant, int32_t *grid);
-hipError_t launch_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs, const BatchItem *items,
-                                 const int32_t *tables, int32_t P_max, int32_t grid, int32_t variant, hipStream_t s);
+#include "batch_launchers.inc"
+namespace mm {
+#include "batch_launchers.inc"
+}
 
 }  // namespace apsp

@@ -8,7 +8,8 @@ every update kind -- add, remove, edge decrease, tight and loose increase,
 deletion -- on directed and undirected graphs, with the cost fallback, with
 an index of 2 entries (exhaustive scans), and with heavy rows (ties: rows
 with more than 32 flags).  Removal statistics equal the oracle's minimax
-mask; queries return a simple path whose largest edge is the distance.
+mask; queries return a simple path whose largest edge is the distance; a
+batch of minimax graphs equals the single calls.
 """
 import numpy as np
 import pytest
@@ -135,20 +136,90 @@ def test_minimax_heavy_rows_and_clone():
     c.close()
 
 
-def test_minimax_rejects_pair_nodes_and_batches():
+def test_minimax_rejects_pair_nodes_and_mixed_batches():
     from paper_2412_15122_amd.apsp import Graph
     from paper_2412_15122_amd.batch import Batch
     from paper_2412_15122_amd._native import ApspError
     A = W.random_graph(20, 1, 9, seed=2)
     g = Graph(A, capacity=24, minimax=True)
+    h = Graph(A, capacity=24)
     with pytest.raises(ApspError):
         g.query_nodes(0, 5)
-    b = Batch(1, 4)
-    with pytest.raises(ApspError):
-        b.run([g], [("edge", 0, 1, 2, 3)])
+    b = Batch(2, 4)
+    with pytest.raises(ApspError):                 # one batch, one path kind
+        b.run([g, h], [("edge", 0, 1, 2, 3), ("edge", 1, 1, 2, 3)])
     assert np.array_equal(g.matrix(), O.minimax_apsp(A))
+    assert np.array_equal(h.matrix(), O.fw(A))
     b.close()
     g.close()
+    h.close()
+
+
+@pytest.mark.parametrize("config", [{"use_graph": False, "variant": 1}, {"use_graph": True, "variant": 3}])
+def test_minimax_batch_equals_single_calls(config):
+    """Minimax graphs in one batched launch (the kernels' minimax build):
+    every graph's matrices and ids equal the one-call-per-update path on a
+    clone, each final matrix equals the oracle's, and query distances equal
+    the single calls' (the paths may differ: both are minimax paths)."""
+    from paper_2412_15122_amd.apsp import Graph
+    from paper_2412_15122_amd.batch import Batch
+    import torch
+    rng = np.random.default_rng(31 + config["variant"])
+    sizes = [1, 3, 40, 143, 300, 129, 700]
+    ga, states, per = [], [], []
+    for gi, n in enumerate(sizes):
+        und = gi % 2 == 1
+        wmax = (6, 5000)[gi % 3 == 0]
+        A = W.random_graph(n, 1, wmax, undirected=und, density=0.4, seed=900 + gi)
+        ga.append(Graph(A, undirected=und, capacity=n + 8, minimax=True))
+        st = W.GraphState(A, und)
+        seq = []
+        for t in range(6):
+            kinds = [W.ADD] + ([W.REMOVE] if len(st.live) >= 1 else []) + \
+                    ([W.DECREASE, W.INCREASE] if len(st.live) >= 2 else [])
+            k = kinds[int(rng.integers(len(kinds)))]
+            try:
+                up = W.make_update(rng, st, k, wmin=1, wmax=wmax, inc_max=2 * wmax, density=0.4)
+            except RuntimeError:
+                up = W.make_update(rng, st, W.ADD, wmin=1, wmax=wmax, inc_max=2 * wmax, density=0.4)
+            if up.kind == W.ADD:
+                seq.append(("add", gi, up.w_out, up.w_in))
+            elif up.kind == W.REMOVE:
+                seq.append(("remove", gi, up.u))
+            else:
+                seq.append(("edge", gi, up.u, up.v, up.w))
+            if len(st.live) >= 2 and t % 2 == 1:
+                a, c = rng.choice(len(st.live), size=2, replace=False)
+                seq.append(("query", gi, st.live[int(a)], st.live[int(c)]))
+        states.append(st)
+        per.append(seq)
+    items = [it for t in range(max(map(len, per))) for seq in per if t < len(seq) for it in [seq[t]]]
+    gb = [g.clone() for g in ga]
+    b = Batch(len(ga), len(items), **config)
+    res = b.run(ga, items)
+    b.status()
+    torch.cuda.synchronize()
+    answers = {}
+    for t, it in enumerate(items):
+        g = gb[it[1]]
+        if it[0] == "add":
+            g.add_node(it[2], None if g.undirected else it[3])
+        elif it[0] == "remove":
+            g.remove_node(it[2])
+        elif it[0] == "edge":
+            g.update_edge(it[2], it[3], it[4])
+        else:
+            answers[t] = g.query(it[2], it[3])[0]
+    for gi in range(len(ga)):
+        assert ga[gi].ids() == gb[gi].ids() == states[gi].live
+        assert torch.equal(ga[gi].matrix_device("D"), gb[gi].matrix_device("D")), gi
+        assert torch.equal(ga[gi].matrix_device("A"), gb[gi].matrix_device("A")), gi
+        assert np.array_equal(ga[gi].matrix(), O.minimax_apsp(states[gi].dense())), gi
+    for t, d in answers.items():
+        assert res[t].get()[0] == d, t
+    b.close()
+    for g in ga + gb:
+        g.close()
 
 
 def test_minimax_benchmark_graph_n16384():
