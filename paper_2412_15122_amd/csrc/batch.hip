@@ -709,7 +709,7 @@ __device__ __forceinline__ void edge_prologue(const DevGraph &g, const BatchGrap
 }
 
 // Relaxation through the lowered edge over rows [r0, r1): D[i][j] vs
-// D[i][u] + w + D[v][j] (and D[i][v] + w + D[u][j] when undirected), rows
+// D[i][u] (+) w (+) D[v][j] (and D[i][v] (+) w (+) D[u][j] when undirected), rows
 // that cannot change filtered first.  SV / SU: rows v and u (LDS or global).
 template <int U>
 __device__ __forceinline__ void dec_relax_rows(const DevGraph &g, const BatchGraph &bg, int32_t w, int32_t r0, int32_t r1,
