@@ -261,6 +261,26 @@ class Graph:
                                            key, cap, ctypes.byref(n_key)), "apsp_query_nodes")
         return int(dist.value), list(on[: n_on.value]), list(key[: n_key.value])
 
+    def query_paths(self, i: int, j: int) -> List[List[int]]:
+        """Algorithm 8's list of shortest i -> j paths: the query's path,
+        then for every other node t on some shortest path (query_nodes) the
+        path i -> t followed by t -> j, each new path once.  Every path is
+        shortest; the list need not hold them all.  [[i]] when i == j, []
+        when j is unreachable."""
+        dist, on, _ = self.query_nodes(i, j)
+        if not on:
+            return []
+        first = self.query(i, j)[1]
+        paths, seen = [first], {tuple(first)}
+        for t in on:
+            if t in (i, j) or t in first:
+                continue
+            p = self.query(i, t)[1] + self.query(t, j)[1][1:]
+            if tuple(p) not in seen:
+                seen.add(tuple(p))
+                paths.append(p)
+        return paths
+
     def edge_scope(self, u: int, v: int) -> Tuple[int, int]:
         r = ctypes.c_int32()
         c = ctypes.c_int32()

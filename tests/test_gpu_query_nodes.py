@@ -149,3 +149,33 @@ def test_query_nodes_long_chain_and_capacity():
     with pytest.raises(ApspError):
         g.query_nodes(0, n + 5)
     g.close()
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_query_paths_are_algorithm_8s_list(undirected):
+    """Graph.query_paths: every listed path is a shortest path (its length
+    is D[i][j]); with positive weights its node sets cover the candidate
+    set, and the nodes on every listed path include the key nodes."""
+    from paper_2412_15122_amd.apsp import Graph
+    rng = np.random.default_rng(77 + undirected)
+    n = 80
+    A = W.random_graph(n, 1, 3, undirected=undirected, density=0.12, seed=5 + undirected)
+    g = Graph(A, undirected=undirected, capacity=n)
+    D = O.fw(A)
+    for _ in range(25):
+        a, b = (int(x) for x in rng.integers(0, n, size=2))
+        paths = g.query_paths(a, b)
+        on, key = O.pair_nodes(A, D, a, b)
+        if a == b:
+            assert paths == [[a]]
+            continue
+        if D[a, b] >= INF:
+            assert paths == []
+            continue
+        for p in paths:
+            assert p[0] == a and p[-1] == b
+            assert sum(int(A[x, y]) for x, y in zip(p, p[1:])) == D[a, b]
+        assert sorted(set().union(*map(set, paths))) == on
+        common = set.intersection(*map(set, paths)) - {a, b}
+        assert set(key) <= common
+    g.close()
