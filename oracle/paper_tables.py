@@ -39,8 +39,11 @@ def one_size(n: int, repeats: int, queries: int, seed: int, wmax: int) -> dict:
         k = int(rng.integers(n))
         keep = [x for x in range(n) if x != k]
         Dk_cold, t_cold = PC.fw(np.ascontiguousarray(A[np.ix_(keep, keep)]))
+        print(f"n={n} rep={rep}: cold Floyd-Warshall of G - G_k {t_cold:.2f} s", flush=True)
         Dk, s5 = PC.remove(A, D, k, 1.0)
+        print(f"n={n} rep={rep}: Algorithm 5 {s5['seconds']:.2f} s", flush=True)
         Dk11, s11 = PC.remove_key(A, D, k, 1.0)
+        print(f"n={n} rep={rep}: Algorithm 11 {s11['seconds']:.2f} s", flush=True)
         assert np.array_equal(Dk, Dk_cold) and np.array_equal(Dk11, Dk_cold)
         r_rm.append(s5["seconds"] / t_cold)
         r_key.append(s11["seconds"] / t_cold)
@@ -52,6 +55,7 @@ def one_size(n: int, repeats: int, queries: int, seed: int, wmax: int) -> dict:
         A2 = A.copy()
         A2[u, v] = A2[v, u] = w
         De_cold, t_cold_e = PC.fw(A2)
+        print(f"n={n} rep={rep}: cold Floyd-Warshall of G' {t_cold_e:.2f} s", flush=True)
         De, se = PC.edge(A, D, u, v, w, 1.0, True)
         assert np.array_equal(De, De_cold)
         r_ed.append(se["seconds"] / t_cold_e)
