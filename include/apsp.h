@@ -220,7 +220,9 @@ apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
  * A buffer may be NULL when its cap is 0.  Work: one pass over row i and
  * column j, then O(K^2) adjacency reads for K candidates (more only for
  * levels joined by zero-weight edges).  Uses the graph's update scratch:
- * ordered on the graph's stream like every call. */
+ * ordered on the graph's stream like every call.  Errors: APSP_E_INVALID
+ * for NULL outputs or a minimax graph, APSP_E_NOT_FOUND for an id that is
+ * not live. */
 apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
                              int32_t *on_ids, int32_t on_cap, int32_t *on_len,
                              int32_t *key_ids, int32_t key_cap, int32_t *key_len);
