@@ -179,3 +179,19 @@ def test_query_paths_are_algorithm_8s_list(undirected):
         common = set.intersection(*map(set, paths)) - {a, b}
         assert set(key) <= common
     g.close()
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_query_nodes_mostly_zero_weights(undirected):
+    """Weights mostly 0 (zero-weight cycles, levels holding most candidates,
+    the in-level search for nearly every candidate)."""
+    from paper_2412_15122_amd.apsp import Graph
+    rng = np.random.default_rng(123 + undirected)
+    n = 120
+    A = W.random_graph(n, 1, 2, undirected=undirected, density=0.06, seed=31 + undirected, zero_frac=0.7)
+    g = Graph(A, undirected=undirected, capacity=n)
+    D = O.fw(A)
+    pairs = [(int(a), int(b)) for a, b in rng.integers(0, n, size=(6, 2))]
+    searched = check_pairs(g, A, list(range(n)), pairs, "zero-heavy")
+    log("candidates decided by the in-level search:", searched)
+    g.close()
