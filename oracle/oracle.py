@@ -24,7 +24,8 @@ slowly and visibly:
 * ``edge_mask`` -- the same criterion applied to an edge (u,v): the pairs
   whose shortest distance can use the edge (see DESIGN for this reading).
 * ``pair_nodes`` -- the nodes on some / on every shortest i -> j path
-  (Algorithms 7, 8 and 10: candidate_node_list and key_node_list).
+  (Algorithms 7, 8 and 10: candidate_node_list and key_node_list);
+  ``minimax_pair_nodes`` the same over minimax paths.
 * ``canonical_path`` -- the lexicographically smallest shortest simple path,
   taken greedily among Algorithm 7's candidates (correct when w >= 1).
 * ``apply_update`` -- the updated graph G' of the notation table (G + p,
@@ -425,6 +426,39 @@ def pair_nodes_from(A: np.ndarray, di, dj, i: int, j: int) -> Tuple[List[int], L
 
     key = [t for t in on if t != i and t != j and not reaches_without(t)]
     assert i in on_set and j in on_set
+    return on, key
+
+
+def minimax_pair_nodes(A: np.ndarray, D: np.ndarray, i: int, j: int) -> Tuple[List[int], List[int]]:
+    """``pair_nodes`` over minimax paths (D the minimax matrix): the nodes on
+    some optimal i -> j walk, t with max(D[i][t], D[t][j]) == D[i][j], and
+    the nodes other than i and j on every one.  An optimal walk is any walk
+    whose edges all weigh at most d = D[i][j] (its largest edge is then d),
+    so t is a key node when j cannot be reached from i over edges <= d once
+    t is taken out."""
+    A = np.asarray(A)
+    D = np.asarray(D, dtype=np.int64)
+    if i == j:
+        return [i], []
+    d = int(D[i, j])
+    if d >= INF:
+        return [], []
+    on = [int(t) for t in np.nonzero(np.maximum(D[i, :], D[:, j]) == d)[0]]
+    light = A <= d
+
+    def reaches_without(t):
+        seen = np.zeros(A.shape[0], dtype=bool)
+        seen[i] = seen[t] = True
+        frontier = [i]
+        while frontier:
+            if seen[j] and j != t:
+                return True
+            nxt = np.nonzero(light[frontier].any(axis=0) & ~seen)[0]
+            seen[nxt] = True
+            frontier = list(nxt)
+        return bool(seen[j])
+
+    key = [t for t in on if t != i and t != j and not reaches_without(t)]
     return on, key
 
 

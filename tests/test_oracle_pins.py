@@ -531,3 +531,36 @@ def test_minimax_rows_equal_floyd_warshall():
         D = O.minimax_apsp(A)
         srcs = [int(x) for x in rng.integers(0, n, size=min(n, 5))]
         assert np.array_equal(O.minimax_rows(A, srcs), D[srcs]), trial
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_minimax_pair_nodes_against_brute_force(undirected):
+    """Minimax pairs (n <= 7, small weights, zero weights too): the key nodes
+    are the intersection of all simple paths whose largest edge is the
+    minimax distance, those paths lie inside the node set, and removing a
+    node raises the distance exactly when it is a key node."""
+    rng = np.random.default_rng(101 + undirected)
+    for trial in range(60):
+        n = int(rng.integers(2, 8))
+        A = W.random_graph(n, 1, 4, undirected=undirected, density=float(rng.uniform(0.3, 1.0)),
+                           seed=int(rng.integers(1 << 30)), zero_frac=0.2 if trial % 2 else 0.0)
+        D = O.minimax_apsp(A)
+        i, j = (int(x) for x in rng.integers(0, n, size=2))
+        on, key = O.minimax_pair_nodes(A, D, i, j)
+        if i == j:
+            assert on == [i] and key == []
+            continue
+        if D[i, j] >= INF:
+            assert on == [] and key == []
+            continue
+        paths = [p for p, L in O._simple_paths(A, i, j)
+                 if L < INF and max((int(A[a, b]) for a, b in zip(p, p[1:])), default=0) == D[i, j]]
+        assert paths
+        assert key == sorted(set.intersection(*map(set, paths)) - {i, j}), trial
+        assert set().union(*map(set, paths)) <= set(on)
+        for k in range(n):
+            if k in (i, j):
+                continue
+            keep = [t for t in range(n) if t != k]
+            d2 = O.minimax_apsp(A[np.ix_(keep, keep)])[keep.index(i), keep.index(j)]
+            assert (d2 > D[i, j]) == (k in key), (trial, k)
