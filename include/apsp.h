@@ -84,8 +84,8 @@ typedef enum {
  * its algorithms carry over to.  Every single-graph call then runs the same
  * steps with max in place of + (Theorems theorem2-theorem3 and Corollary
  * corollary3 hold with max, which is monotone with 0 as identity on weights
- * >= 0).  apsp_query_nodes takes shortest-path graphs only; a batch
- * (apsp_batch_run) takes graphs of one kind: all minimax or none. */
+ * >= 0).  A batch (apsp_batch_run) takes graphs of one kind: all minimax
+ * or none. */
 typedef enum { APSP_DIRECTED = 0, APSP_UNDIRECTED = 1, APSP_MINIMAX = 2 } apsp_kind;
 
 /* What apsp_remove_node and an edge increase do after building the mask
@@ -220,9 +220,13 @@ apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
  * A buffer may be NULL when its cap is 0.  Work: one pass over row i and
  * column j, then O(K^2) adjacency reads for K candidates (more only for
  * levels joined by zero-weight edges).  Uses the graph's update scratch:
- * ordered on the graph's stream like every call.  Errors: APSP_E_INVALID
- * for NULL outputs or a minimax graph, APSP_E_NOT_FOUND for an id that is
- * not live. */
+ * ordered on the graph's stream like every call.  On a minimax graph
+ * (APSP_MINIMAX) the sets are over optimal walks -- those whose edges all
+ * weigh at most D[i][j]: on = {t : max(D[i][t], D[t][j]) == D[i][j]}, key =
+ * the nodes on every such walk, found as the interior nodes t of one such
+ * path for which a search from i over edges <= D[i][j] that avoids t does
+ * not reach j (one search per interior node).  Errors: APSP_E_INVALID for
+ * NULL outputs, APSP_E_NOT_FOUND for an id that is not live. */
 apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
                              int32_t *on_ids, int32_t on_cap, int32_t *on_len,
                              int32_t *key_ids, int32_t key_cap, int32_t *key_len);

@@ -436,14 +436,34 @@ def minimax_pair_nodes(A: np.ndarray, D: np.ndarray, i: int, j: int) -> Tuple[Li
     whose edges all weigh at most d = D[i][j] (its largest edge is then d),
     so t is a key node when j cannot be reached from i over edges <= d once
     t is taken out."""
+    D = np.asarray(D)
+    return minimax_pair_nodes_from(A, D[i, :], D[:, j], i, j)
+
+
+def minimax_key_test(A: np.ndarray, i: int, j: int, d: int, t: int) -> bool:
+    """Is t on every walk from i to j over edges of weight <= d?"""
+    light = np.asarray(A) <= d
+    seen = np.zeros(light.shape[0], dtype=bool)
+    seen[i] = seen[t] = True
+    frontier = [i]
+    while frontier and not seen[j]:
+        nxt = np.nonzero(light[frontier].any(axis=0) & ~seen)[0]
+        seen[nxt] = True
+        frontier = list(nxt)
+    return not bool(seen[j])
+
+
+def minimax_pair_nodes_from(A: np.ndarray, di, dj, i: int, j: int) -> Tuple[List[int], List[int]]:
+    """``minimax_pair_nodes`` given di[t] = D[i][t] and dj[t] = D[t][j]."""
     A = np.asarray(A)
-    D = np.asarray(D, dtype=np.int64)
+    di = np.asarray(di, dtype=np.int64)
+    dj = np.asarray(dj, dtype=np.int64)
     if i == j:
         return [i], []
-    d = int(D[i, j])
+    d = int(di[j])
     if d >= INF:
         return [], []
-    on = [int(t) for t in np.nonzero(np.maximum(D[i, :], D[:, j]) == d)[0]]
+    on = [int(t) for t in np.nonzero(np.maximum(di, dj) == d)[0]]
     light = A <= d
 
     def reaches_without(t):

@@ -558,7 +558,6 @@ apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
         return fail(APSP_E_INVALID, "apsp_query_nodes: bad output buffer");
     int32_t si, sj;
     if (!lookup(g, i, &si) || !lookup(g, j, &sj)) return fail(APSP_E_NOT_FOUND, "apsp_query_nodes: id is not live");
-    if (g->minimax) return fail(APSP_E_INVALID, "apsp_query_nodes: shortest-path graphs only (not minimax)");
     hipStream_t s = g->stream;
     const int32_t n = g->n_live;
     // output: 4 + 2 n ints at the start of the heavy-pass scratch; the
@@ -566,7 +565,17 @@ apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
     int32_t *out = g->fscratch;
     int32_t *bfs = g->fscratch + (((size_t)2 * g->P + 8 + 63) & ~(size_t)63);
     g->prof.begin(KID_QUERY);
-    launch_query_nodes(g->dg, si, sj, g->rank_cur, n, out, g->qscratch, bfs, s);
+    if (g->minimax) {
+        // output, then n_slots marks; the candidate arrays and the path after them
+        int32_t *work = g->fscratch + (((size_t)3 * g->P + 72 + 63) & ~(size_t)63);
+        if (const char *bad = mm::launch_query_nodes_bottleneck(g->dg, si, sj, g->rank_cur, n, out, g->qscratch, work,
+                                                                g->qbuf_h, s)) {
+            g->prof.end();
+            return fail(APSP_E_DEVICE, std::string("apsp_query_nodes: ") + bad);
+        }
+    } else {
+        launch_query_nodes(g->dg, si, sj, g->rank_cur, n, out, g->qscratch, bfs, s);
+    }
     g->prof.end();
     apsp_status st = check_launch("apsp_query_nodes");
     if (st) return st;

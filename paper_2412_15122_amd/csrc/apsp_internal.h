@@ -135,6 +135,12 @@ namespace mm {
 // name of a failed step, or nullptr.
 const char *launch_query_bottleneck(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch,
                                     int32_t *probe_host, hipStream_t s);
+// Minimax pair node sets (output as launch_query_nodes, plus n_slots marks
+// after it: 4 + 2 n_live + n_slots ints); scratch: 4 P ints for the search;
+// work: 5 P + 1 ints.  Synchronous.
+const char *launch_query_nodes_bottleneck(const DevGraph &g, int32_t si, int32_t sj, const int32_t *rank,
+                                          int32_t n_live, int32_t *out, int32_t *scratch, int32_t *work,
+                                          int32_t *probe_host, hipStream_t s);
 }
 
 // Kernel ids for per-kernel timing (apsp_profile).

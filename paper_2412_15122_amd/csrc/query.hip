@@ -1,5 +1,7 @@
 // Warm single-pair query (Section 3, Algorithm 7), matrix read-out, and the
 // edge scope count.
+#include <vector>
+
 #include "device_common.h"
 
 namespace apsp {
@@ -65,7 +67,8 @@ __global__ __launch_bounds__(256) void k_qb_init(DevGraph g, int32_t si, int32_t
 // through three counters: level l reads count l % 3, adds to (l + 1) % 3 and
 // zeroes (l + 2) % 3 for the level after.  Once j is reached, or a frontier
 // is empty (also when j is unreachable), a sticky flag ends every later level.
-__global__ __launch_bounds__(256) void k_qb_level(DevGraph g, int32_t si, int32_t sj, int32_t level, int32_t *scratch) {
+__global__ __launch_bounds__(256) void k_qb_level(DevGraph g, int32_t si, int32_t sj, int32_t skip, int32_t level,
+                                                  int32_t *scratch) {
     const QbView v = qb_view(scratch, g.P);
     if (v.ctl[QB_FOUND] || v.ctl[QB_EMPTY]) return;
     const uint32_t d = (uint32_t)g.D[(int64_t)si * g.ld + sj];
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(256) void k_qb_level(DevGraph g, int32_t si, int32_
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int32_t b = b0 + e;
-                    if (b >= n || b == a || ws[e] > d) continue;
+                    if (b >= n || b == a || b == skip || ws[e] > d) continue;
                     const uint32_t bit = 1u << (b & 31);
                     if (v.visited[b >> 5] & bit) continue;
                     if (atomicOr(&v.visited[b >> 5], bit) & bit) continue;
@@ -145,21 +148,68 @@ __global__ void k_qb_path(DevGraph g, int32_t si, int32_t sj, int32_t *out, cons
     out[2] = 0;
 }
 
-const char *launch_query_bottleneck(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch,
-                                    int32_t *probe_host, hipStream_t s) {
+// The search from si, not entering slot `skip` (-1: none); on return the
+// probe holds the control words (QB_FOUND: sj reached).
+static const char *qb_search(const DevGraph &g, int32_t si, int32_t sj, int32_t skip, int32_t *scratch,
+                             int32_t *probe_host, hipStream_t s) {
     k_qb_init<<<((g.P + 31) / 32 + 255) / 256, 256, 0, s>>>(g, si, sj, scratch);
     const QbView v = qb_view(scratch, g.P);
+    probe_host[QB_FOUND] = si == sj;
     for (int32_t level = 0; si != sj && level < g.n_slots; level += QB_LEVELS_PER_SYNC) {
         for (int32_t l = level; l < level + QB_LEVELS_PER_SYNC; ++l)
-            k_qb_level<<<QB_GRID, 256, 0, s>>>(g, si, sj, l, scratch);
+            k_qb_level<<<QB_GRID, 256, 0, s>>>(g, si, sj, skip, l, scratch);
         if (hipMemcpyAsync(probe_host, v.ctl, QB_CTL * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return "query level sync";
         if (probe_host[QB_FOUND] || probe_host[QB_EMPTY]) break;
     }
+    return nullptr;
+}
+
+const char *launch_query_bottleneck(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32_t *scratch,
+                                    int32_t *probe_host, hipStream_t s) {
+    if (const char *bad = qb_search(g, si, sj, -1, scratch, probe_host, s)) return bad;
     k_qb_path<<<1, 1, 0, s>>>(g, si, sj, out, scratch);
     return nullptr;
 }
+
+// The slots of the found path, sj first: path[0] = length, path[1..] slots
+// (length 0 when sj was not reached).
+__global__ void k_qb_path_slots(DevGraph g, int32_t si, int32_t sj, int32_t *path, const int32_t *scratch) {
+    const QbView v = qb_view(const_cast<int32_t *>(scratch), g.P);
+    int32_t len = 0;
+    if (v.ctl[QB_FOUND]) {
+        int32_t c = sj;
+        for (; c >= 0 && len < g.n_slots; c = c == si ? -1 : v.parent[c]) path[1 + len++] = c;
+        if (path[len] != si) len = 0;
+    }
+    path[0] = len;
+}
+
+__global__ void k_qb_mark(int32_t *mark, int32_t slot) { mark[slot] = 1; }
+
+// The ids of the marked slots in ascending-id order (rank table), at
+// out[4 + n_live ...], their count at out[2].
+__global__ __launch_bounds__(1024) void k_qb_emit_marked(DevGraph g, const int32_t *__restrict__ rank, int32_t n_live,
+                                                         const int32_t *mark, int32_t *out) {
+    __shared__ uint32_t red[16];
+    __shared__ int s_base;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (int32_t r0 = 0; r0 < n_live; r0 += 1024) {
+        const int32_t r = r0 + threadIdx.x;
+        const int32_t slot = r < n_live ? rank[r] : -1;
+        const int key = slot >= 0 && mark[slot];
+        int total;
+        const int off = block_exscan<1024>(key, red, &total);
+        if (key) out[4 + n_live + s_base + off] = g.id_of_slot[slot];
+        __syncthreads();
+        if (threadIdx.x == 0) s_base += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[2] = s_base;
+}
+
 #endif
 
 // ---- nodes on some / on every shortest path of a pair ----------------------
@@ -364,6 +414,41 @@ void launch_query_nodes(const DevGraph &g, int32_t si, int32_t sj, const int32_t
     k_qn_key<<<QN_GRID, 256, 0, s>>>(g, si, sj, out, scratch, bfs);
     k_qn_emit<<<1, 1024, 0, s>>>(g, n_live, out, scratch);
 }
+
+#ifdef APSP_SEMIRING_MINIMAX
+// Node sets of a minimax pair.  The set on optimal walks is the gather of
+// k_qn_gather (max in place of +); the nodes on every optimal walk all lie
+// on the one path the search finds, and such a node t is one of them when
+// the search without t does not reach sj.  work: 5 P + 64 ints (the
+// gather's candidate arrays, the path, the marks).
+const char *launch_query_nodes_bottleneck(const DevGraph &g, int32_t si, int32_t sj, const int32_t *rank,
+                                          int32_t n_live, int32_t *out, int32_t *scratch, int32_t *work,
+                                          int32_t *probe_host, hipStream_t s) {
+    int32_t *cand = work;                  // 4 P: the gather's candidate arrays
+    int32_t *path = work + 4 * g.P;        // P + 1
+    int32_t *mark = out + 4 + 2 * (int64_t)n_live;  // n_slots marks after the output lists
+    k_qn_gather<<<1, 1024, 0, s>>>(g, si, sj, rank, n_live, out, cand);
+    launch_fill(mark, g.n_slots, 0, s);
+    if (si != sj) {
+        if (const char *bad = qb_search(g, si, sj, -1, scratch, probe_host, s)) return bad;
+        k_qb_path_slots<<<1, 1, 0, s>>>(g, si, sj, path, scratch);
+        if (hipMemcpyAsync(probe_host, path, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return "query path length";
+        const int32_t len = probe_host[0];
+        std::vector<int32_t> slots(len > 0 ? len : 0);
+        if (len > 0 && (hipMemcpyAsync(slots.data(), path + 1, (size_t)len * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
+            return "query path";
+        for (int32_t q = 1; q + 1 < len; ++q) {  // interior nodes of the path
+            if (const char *bad = qb_search(g, si, sj, slots[q], scratch, probe_host, s)) return bad;
+            if (!probe_host[QB_FOUND]) k_qb_mark<<<1, 1, 0, s>>>(mark, slots[q]);
+        }
+    }
+    k_qb_emit_marked<<<1, 1024, 0, s>>>(g, rank, n_live, mark, out);
+    return nullptr;
+}
+#endif
 
 // dst[a][b] = src[slot[a]][slot[b]] for a, b < n.
 __global__ void k_gather_compact(const int32_t *__restrict__ src, int64_t ld, int32_t *__restrict__ dst,

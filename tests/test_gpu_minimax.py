@@ -8,8 +8,9 @@ every update kind -- add, remove, edge decrease, tight and loose increase,
 deletion -- on directed and undirected graphs, with the cost fallback, with
 an index of 2 entries (exhaustive scans), and with heavy rows (ties: rows
 with more than 32 flags).  Removal statistics equal the oracle's minimax
-mask; queries return a simple path whose largest edge is the distance; a
-batch of minimax graphs equals the single calls.
+mask; queries return a simple path whose largest edge is the distance, and
+pair node sets equal the oracle's; a batch of minimax graphs equals the
+single calls.
 """
 import numpy as np
 import pytest
@@ -136,15 +137,45 @@ def test_minimax_heavy_rows_and_clone():
     c.close()
 
 
-def test_minimax_rejects_pair_nodes_and_mixed_batches():
+@pytest.mark.parametrize("undirected", [False, True])
+def test_minimax_pair_nodes_equal_oracle(undirected):
+    """Node sets of minimax pairs (on some / on every optimal walk) against
+    the oracle's, on graphs with many ties and zero weights, cold and after
+    updates (ids out of slot order)."""
+    from paper_2412_15122_amd.apsp import Graph
+    rng = np.random.default_rng(41 + undirected)
+    for n, wmax, dens, zero in ((9, 3, 0.5, 0.2), (90, 4, 0.08, 0.1), (200, 30, 0.03, 0.0), (143, 10000, 0.05, 0.0)):
+        A = W.random_graph(n, 1, wmax, undirected=undirected, density=dens, seed=int(rng.integers(1 << 30)),
+                           zero_frac=zero)
+        g = Graph(A, undirected=undirected, capacity=n + 8, minimax=True)
+        st = W.GraphState(A, undirected)
+        for kind in (W.REMOVE, W.ADD):
+            up = W.make_update(rng, st, kind, wmin=1, wmax=wmax, inc_max=2 * wmax, density=dens)
+            if up.kind == W.ADD:
+                g.add_node(up.w_out, None if undirected else up.w_in)
+            else:
+                g.remove_node(up.u)
+        Ad = st.dense()
+        D = O.minimax_apsp(Ad)
+        ids = st.live
+        assert g.ids() == ids
+        m = len(ids)
+        pairs = [(int(a), int(b)) for a, b in rng.integers(0, m, size=(20, 2))] + [(0, 0), (m - 1, 0)]
+        for a, b in pairs:
+            on_o, key_o = O.minimax_pair_nodes(Ad, D, a, b)
+            dist, on, key = g.query_nodes(ids[a], ids[b])
+            assert dist == int(D[a, b]), (n, a, b)
+            assert on == [ids[p] for p in on_o] and key == [ids[p] for p in key_o], (n, a, b)
+        g.close()
+
+
+def test_minimax_rejects_mixed_batches():
     from paper_2412_15122_amd.apsp import Graph
     from paper_2412_15122_amd.batch import Batch
     from paper_2412_15122_amd._native import ApspError
     A = W.random_graph(20, 1, 9, seed=2)
     g = Graph(A, capacity=24, minimax=True)
     h = Graph(A, capacity=24)
-    with pytest.raises(ApspError):
-        g.query_nodes(0, 5)
     b = Batch(2, 4)
     with pytest.raises(ApspError):                 # one batch, one path kind
         b.run([g, h], [("edge", 0, 1, 2, 3), ("edge", 1, 1, 2, 3)])
@@ -261,6 +292,20 @@ def test_minimax_benchmark_graph_n16384():
         if t % 2 == 0 or upd.kind == W.REMOVE:
             check(A, ids, touched, f"update {t} {upd.kind}")
     assert g.ids() == ids
+    # pair node sets on sampled pairs: the set on optimal walks exactly; the
+    # reported key nodes pass the oracle's test, and so do no sampled others
+    for _ in range(2):
+        a, b = (int(x) for x in rng.integers(0, len(ids), size=2))
+        rows = O.minimax_rows(A, [a, b])
+        d = int(rows[0][b])
+        dist, on, key = g.query_nodes(ids[a], ids[b])
+        on_o = [int(t) for t in np.nonzero(np.maximum(rows[0].astype(np.int64), rows[1]) == d)[0]] if a != b else [a]
+        assert dist == d and on == [ids[p] for p in on_o], (a, b)
+        for t in key:
+            assert O.minimax_key_test(A, a, b, d, ids.index(t)), (a, b, t)
+        others = [p for p in on_o if p not in (a, b) and ids[p] not in key]
+        for p in [others[int(x)] for x in rng.integers(0, len(others), size=3)] if others else []:
+            assert not O.minimax_key_test(A, a, b, d, p), (a, b, p)
     pos = [int(x) for x in rng.integers(0, len(ids), size=3)]
     rows = O.minimax_rows(A, pos)
     for r, a in enumerate(pos):

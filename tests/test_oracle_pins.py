@@ -558,6 +558,7 @@ def test_minimax_pair_nodes_against_brute_force(undirected):
         assert paths
         assert key == sorted(set.intersection(*map(set, paths)) - {i, j}), trial
         assert set().union(*map(set, paths)) <= set(on)
+        assert key == [t for t in on if t not in (i, j) and O.minimax_key_test(A, i, j, int(D[i, j]), t)]
         for k in range(n):
             if k in (i, j):
                 continue
