@@ -558,14 +558,14 @@ def main():
         t0 = time.perf_counter()
         g.query(a, b)
         t1 = time.perf_counter()
-        _, on, key = g.query_nodes(a, b) if not minimax else (0, [], [])
+        _, on, key = g.query_nodes(a, b)
         t2 = time.perf_counter()
         q_path.append((t1 - t0) * 1e3)
         q_nodes.append((t2 - t1) * 1e3)
         q_cand.append(len(on))
         q_key.append(len(key))
     query_ms = {"pairs": len(q_path), "path_p50": round(float(np.median(q_path)), 4),
-                "nodes_p50": None if minimax else round(float(np.median(q_nodes)), 4),
+                "nodes_p50": round(float(np.median(q_nodes)), 4),
                 "mean_candidates": round(float(np.mean(q_cand)), 2), "mean_key_nodes": round(float(np.mean(q_key)), 2)}
     log(f"[bench] queries: {query_ms}")
 
