@@ -63,10 +63,11 @@ class Request:
 
 
 class GraphSlot:
-    def __init__(self, index: int, adj, undirected: bool, capacity: int):
+    def __init__(self, index: int, adj, undirected: bool, capacity: int, minimax: bool = False):
         self.index = index
         self.adj = adj
         self.undirected = undirected
+        self.minimax = minimax
         self.capacity = capacity
         self.graph: Optional[Graph] = None
         self.queue: collections.deque = collections.deque()
@@ -81,7 +82,8 @@ class GraphSlot:
 class Server:
     def __init__(self, graphs: Sequence, *, undirected: bool = False, budget_bytes: Optional[int] = None,
                  streams: int = 4, max_batch_items: int = 8192, batch_config: Optional[dict] = None,
-                 headroom: int = 64, schedule: str = "lockstep", per_graph: int = 8, small_batch: int = 64):
+                 headroom: int = 64, schedule: str = "lockstep", per_graph: int = 8, small_batch: int = 64,
+                 minimax: bool = False):
         """graphs: adjacency matrices (numpy or torch, n x n int32).  Each is
         created in HBM (cold start) when first admitted.  budget_bytes:
         HBM the graphs may hold together (default 80% of free HBM).
@@ -90,7 +92,10 @@ class Server:
         with no batch and fewer than this many single calls in flight, this
         many queued requests or fewer run as single calls instead (a
         lockstep launch has a fixed cost of a few grid barriers that one
-        cheap update does not repay)."""
+        cheap update does not repay).  minimax: serve minimax (bottleneck)
+        distances instead of shortest-path ones (a query's path is then a
+        minimax path, found by the batch's candidate walk or by a single
+        call's search, which may pick different ones)."""
         if schedule not in ("lockstep", "hybrid"):
             raise ValueError("schedule must be 'lockstep' or 'hybrid'")
         self.schedule = schedule
@@ -106,7 +111,7 @@ class Server:
         self.slots: List[GraphSlot] = []
         for i, a in enumerate(graphs):
             n = int(a.shape[0])
-            s = GraphSlot(i, a, undirected, n + headroom)
+            s = GraphSlot(i, a, undirected, n + headroom, minimax)
             s.nbytes = int(lib_bytes(s.capacity, kind))
             if s.nbytes == 0:
                 raise ValueError(f"graph {i}: capacity {s.capacity} is out of range")
@@ -156,7 +161,7 @@ class Server:
         stream = self.streams[s.index % len(self.streams)]
         with self._torch.cuda.stream(stream):
             if s.graph is None:
-                s.graph = Graph(s.adj, undirected=s.undirected, capacity=s.capacity)
+                s.graph = Graph(s.adj, undirected=s.undirected, capacity=s.capacity, minimax=s.minimax)
                 self.stats["cold_starts"] += 1
             else:
                 s.graph.swap_in()
