@@ -1,5 +1,7 @@
-// Warm single-pair query (Section 3, Algorithm 7), matrix read-out, and the
-// edge scope count.
+// Warm single-pair queries: the path (Section 3, Algorithm 7; for minimax
+// graphs a search over edges no heavier than the distance), the nodes on
+// some / on every shortest path (Algorithms 8 and 10), matrix read-out, and
+// the edge scope count.
 #include <vector>
 
 #include "device_common.h"
