@@ -542,9 +542,16 @@ def main():
         alg = adds_bytes if prof_kernel == "add_relax" else removes_bytes
         achieved = alg / (ms * 1e-3) / 1e9
         tb = None if minimax else traffic_from_profiles(prof_kernel)   # counters were taken on shortest paths
+        # the counter runs launch at n = 16384 exactly; this run's launches at
+        # the growing live count: the measured traffic over its algorithmic
+        # bytes at that n is the comparable figure
+        n_pmc = 16384
+        alg_pmc = 4 * n_pmc * n_pmc if prof_kernel == "add_relax" else 4 * (n_pmc - 1) * n_pmc
         roofline = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
+            "traffic_at_n": n_pmc if tb else None,
+            "traffic_vs_algorithmic": round(tb / alg_pmc, 4) if tb else None,
             "kernel": prof_kernel, "launches": c, "avg_launch_ms": round(ms / max(c, 1), 4),
             "algorithmic_bytes_per_launch": round(alg / max(c, 1)),
         }
