@@ -97,6 +97,12 @@ typedef enum {
     APSP_FALLBACK_ALWAYS = 2  /* always cold FW on G' */
 } apsp_fallback;
 
+/* How apsp_import checks the matrix it is given. */
+typedef enum {
+    APSP_IMPORT_TRUSTED = 0,  /* only the O(n^2) checks of a distance matrix */
+    APSP_IMPORT_EXACT = 1     /* also a cold recompute, compared entry by entry */
+} apsp_import_check;
+
 typedef struct apsp_graph apsp_graph;
 
 /* Per-update statistics of the last update (apsp_last_stats). */
@@ -147,6 +153,33 @@ size_t apsp_required_bytes(int32_t capacity, int32_t kind);
 apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t kind,
                       int32_t capacity, void *dev_buf, size_t dev_buf_bytes,
                       void *hip_stream, apsp_graph **out);
+
+/* Warm start from a distance matrix that is already known: the premise of
+ * the paper's problem statement (Section 2: the old graph's all-pairs
+ * shortest-path matrix is given, and only the update is to be paid for).
+ * Builds a graph as apsp_cold does from adj_dev, but takes D from apsp_dev
+ * (n x n int32, row-major, leading dimension apsp_ld >= n, row i = distances
+ * from node i) instead of running Floyd-Warshall: O(n^2) work.
+ *   ids      host array of n strictly ascending ids in [0, INT32_MAX) for
+ *            rows 0..n-1 (NULL = 0..n-1); read during the call only.
+ *   next_id  the id the next apsp_add_node returns (later ones count up
+ *            from it), above every id; -1 = the largest id + 1.  Lets a
+ *            copy keep a graph's id sequence (apsp_next_id) when its largest
+ *            ids were removed.
+ *   verify   APSP_IMPORT_TRUSTED: the checks below only;
+ *            APSP_IMPORT_EXACT: also a cold Floyd-Warshall of the adjacency,
+ *            compared with apsp_dev entry by entry (a cold start's cost).
+ * The checks, always made: every entry in [0, APSP_INF], a zero diagonal,
+ * D[i][j] <= adj[i][j], and symmetry for an undirected graph.  A matrix that
+ * passes them but is not the distance matrix of adj (possible only under
+ * APSP_IMPORT_TRUSTED) makes every later result undefined.
+ * The call waits for hip_stream (it reads the check's count back); adj_dev
+ * and apsp_dev may be freed when it returns.
+ * Errors: as apsp_cold, and APSP_E_INVALID for a bad verify value, bad ids
+ * or next_id, or a matrix that fails a check (no handle is made). */
+apsp_status apsp_import(const int32_t *adj_dev, int64_t adj_ld, const int32_t *apsp_dev, int64_t apsp_ld,
+                        int32_t n, const int32_t *ids, int32_t next_id, int32_t kind, int32_t capacity,
+                        void *dev_buf, size_t dev_buf_bytes, void *hip_stream, int32_t verify, apsp_graph **out);
 
 /* Recompute D from the current adjacency by cold Floyd-Warshall (the
  * fallback of Algorithm 5, and recovery).  Asynchronous. */
@@ -237,6 +270,10 @@ apsp_status apsp_read_matrix(apsp_graph *g, int32_t *out_dev, int64_t out_ld);
 
 /* Same for the adjacency matrix (diagonal 0). */
 apsp_status apsp_read_adjacency(apsp_graph *g, int32_t *out_dev, int64_t out_ld);
+
+/* The id the next apsp_add_node will return: one above the largest id the
+ * graph has ever held (ids of removed nodes are not reused).  Host only. */
+apsp_status apsp_next_id(const apsp_graph *g, int32_t *id);
 
 /* Live node count (host bookkeeping; never waits). */
 apsp_status apsp_node_count(const apsp_graph *g, int32_t *n);

@@ -22,6 +22,8 @@ APSP_E_VALUE = -7
 APSP_DIRECTED = 0
 APSP_UNDIRECTED = 1
 APSP_MINIMAX = 2      # OR-ed into the kind: minimax (bottleneck) paths
+APSP_IMPORT_TRUSTED = 0  # apsp_import: O(n^2) checks only
+APSP_IMPORT_EXACT = 1    # apsp_import: also a cold recompute, compared
 APSP_FALLBACK_NEVER = 0
 APSP_FALLBACK_COST = 1
 APSP_FALLBACK_ALWAYS = 2
@@ -88,6 +90,9 @@ SIGNATURES = {
     "apsp_kernel_name": (ctypes.c_char_p, [_I32]),
     "apsp_required_bytes": (ctypes.c_size_t, [_I32, _I32]),
     "apsp_cold": (_I32, [_P, _I32, _I64, _I32, _I32, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "apsp_import": (_I32, [_P, _I64, _P, _I64, _I32, _PI32, _I32, _I32, _I32, _P, ctypes.c_size_t, _P, _I32,
+                           ctypes.POINTER(_P)]),
+    "apsp_next_id": (_I32, [_P, _PI32]),
     "apsp_recompute_cold": (_I32, [_P]),
     "apsp_graph_destroy": (_I32, [_P]),
     "apsp_add_node": (_I32, [_P, _P, _P, _PI32]),

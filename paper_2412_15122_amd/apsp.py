@@ -70,6 +70,58 @@ class Graph:
         self._keep = []
 
     @classmethod
+    def from_matrix(cls, adj, dist, *, undirected: bool = False, capacity: Optional[int] = None,
+                    minimax: bool = False, ids: Optional[Sequence[int]] = None, next_id: Optional[int] = None,
+                    exact: bool = False) -> "Graph":
+        """A graph whose distance matrix is already known (apsp_import): the
+        paper's starting point, where the old matrix is given and only the
+        updates are paid for.  `dist` is n x n in the order of `adj`'s rows;
+        `ids` (ascending) name those rows (default 0..n-1); `next_id` is the
+        id the next add_node returns (default: the largest id + 1).  exact=True also
+        recomputes cold and compares; otherwise only the O(n^2) checks of a
+        distance matrix are made.  Raises ApspError if a check fails."""
+        torch = _torch()
+        lib = N.load()
+        A = _device_int32(adj)
+        Dm = _device_int32(dist)
+        if A.dim() != 2 or A.shape[0] != A.shape[1] or tuple(Dm.shape) != tuple(A.shape):
+            raise ValueError("adjacency and distance matrix must be square and of one size")
+        n = int(A.shape[0])
+        if ids is not None and len(ids) != n:
+            raise ValueError(f"ids must have {n} entries")
+        cap = int(capacity if capacity is not None else max(n, 1))
+        kind = N.APSP_UNDIRECTED if undirected else N.APSP_DIRECTED
+        nbytes = int(lib.apsp_required_bytes(cap, kind))
+        if nbytes == 0:
+            raise ValueError(f"invalid capacity {cap}")
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        ptr = (buf.data_ptr() + 255) & ~255
+        stream = torch.cuda.current_stream()
+        id_arr = None
+        if ids is not None and n:
+            id_arr = (ctypes.c_int32 * n)(*[int(x) for x in ids])
+        h = ctypes.c_void_p()
+        st = lib.apsp_import(A.data_ptr() if n else None, A.stride(0) if n else 0,
+                             Dm.data_ptr() if n else None, Dm.stride(0) if n else 0, n, id_arr,
+                             -1 if next_id is None else int(next_id),
+                             kind | (N.APSP_MINIMAX if minimax else 0), cap, ptr, nbytes, stream.cuda_stream,
+                             N.APSP_IMPORT_EXACT if exact else N.APSP_IMPORT_TRUSTED, ctypes.byref(h))
+        N.check(st, "apsp_import")
+        return cls._from_handle(lib, h, buf, ptr, nbytes, cap, kind, stream, bool(minimax))
+
+    def grow(self, capacity: int) -> "Graph":
+        """A copy of this graph with `capacity` node slots (at least the live
+        count), built from its matrices by apsp_import: same ids, same next
+        id, same distances, O(n^2) work.  This graph is left unchanged."""
+        n = self.num_nodes()
+        if capacity < n:
+            raise ValueError(f"capacity {capacity} is below the live count {n}")
+        A = self.matrix_device("A")
+        Dm = self.matrix_device("D")
+        return Graph.from_matrix(A, Dm, undirected=self.undirected, capacity=capacity, minimax=self.minimax,
+                                 ids=self.ids(), next_id=self.next_id())
+
+    @classmethod
     def _from_handle(cls, lib, h, buf, ptr, nbytes, cap, kind, stream, minimax=False):
         g = cls.__new__(cls)
         g._lib = lib
@@ -211,6 +263,12 @@ class Graph:
         n = ctypes.c_int32()
         N.check(self._lib.apsp_node_count(self._h, ctypes.byref(n)), "apsp_node_count")
         return int(n.value)
+
+    def next_id(self) -> int:
+        """The id the next add_node returns (ids are never reused)."""
+        x = ctypes.c_int32()
+        N.check(self._lib.apsp_next_id(self._h, ctypes.byref(x)), "apsp_next_id")
+        return int(x.value)
 
     def ids(self) -> List[int]:
         n = self.num_nodes()

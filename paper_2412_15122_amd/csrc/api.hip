@@ -157,50 +157,25 @@ FusedArgs fused_args(apsp_graph *g, int32_t mode) {
     return fa;
 }
 
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// C ABI
-// ---------------------------------------------------------------------------
-
-extern "C" {
-
-int32_t apsp_abi_version(void) { return APSP_ABI_VERSION; }
-
-const char *apsp_last_error(void) { return g_err.c_str(); }
-
-int32_t apsp_kernel_count(void) { return KID_COUNT; }
-
-const char *apsp_kernel_name(int32_t k) {
-    static const char *names[KID_COUNT] = {
-        "fw_pivot", "fw_panel", "fw_tiles", "nin_build", "nin_update", "add_out", "add_in", "add_relax",
-        "add_place", "gather", "mask_recompute", "tombstone", "edge_begin", "edge_sweep", "query", "misc",
-        "mask_detect"};
-    if (k < 0 || k >= KID_COUNT) return "";
-    return names[k];
-}
-
-size_t apsp_required_bytes(int32_t capacity, int32_t kind) {
-    if (capacity < 1 || capacity > APSP_MAX_CAPACITY) return 0;
-    const int32_t dir = kind & ~(int32_t)APSP_MINIMAX;
-    if (dir != APSP_DIRECTED && dir != APSP_UNDIRECTED) return 0;
-    return make_layout(capacity, dir).total;
-}
-
-apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t kind, int32_t capacity,
-                      void *dev_buf, size_t dev_buf_bytes, void *hip_stream, apsp_graph **out) {
-    if (!out) return fail(APSP_E_INVALID, "apsp_cold: out is NULL");
+// The part of a new graph that precedes its distance matrix: argument
+// checks, the handle, every buffer in its initial state, the adjacency (and
+// its transpose) loaded, slots 0..n-1 in use.  Messages start with `who`.
+apsp_status new_graph(const char *who, const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t kind,
+                      int32_t capacity, void *dev_buf, size_t dev_buf_bytes, void *hip_stream, apsp_graph **out,
+                      apsp_graph **made) {
+    const std::string w(who);
+    if (!out) return fail(APSP_E_INVALID, w + ": out is NULL");
     *out = nullptr;
     const int32_t dir = kind & ~(int32_t)APSP_MINIMAX;
-    if (dir != APSP_DIRECTED && dir != APSP_UNDIRECTED) return fail(APSP_E_INVALID, "apsp_cold: bad kind");
+    if (dir != APSP_DIRECTED && dir != APSP_UNDIRECTED) return fail(APSP_E_INVALID, w + ": bad kind");
     if (capacity < 1 || capacity > APSP_MAX_CAPACITY)
-        return fail(APSP_E_INVALID, "apsp_cold: capacity must be in [1, APSP_MAX_CAPACITY]");
-    if (n < 0 || n > capacity) return fail(APSP_E_INVALID, "apsp_cold: n must be in [0, capacity]");
-    if (n > 0 && (!adj_dev || adj_ld < n)) return fail(APSP_E_INVALID, "apsp_cold: bad adjacency pointer or ld");
-    if (!dev_buf) return fail(APSP_E_INVALID, "apsp_cold: dev_buf is NULL");
-    if (((uintptr_t)dev_buf & 255) != 0) return fail(APSP_E_INVALID, "apsp_cold: dev_buf not 256-byte aligned");
+        return fail(APSP_E_INVALID, w + ": capacity must be in [1, APSP_MAX_CAPACITY]");
+    if (n < 0 || n > capacity) return fail(APSP_E_INVALID, w + ": n must be in [0, capacity]");
+    if (n > 0 && (!adj_dev || adj_ld < n)) return fail(APSP_E_INVALID, w + ": bad adjacency pointer or ld");
+    if (!dev_buf) return fail(APSP_E_INVALID, w + ": dev_buf is NULL");
+    if (((uintptr_t)dev_buf & 255) != 0) return fail(APSP_E_INVALID, w + ": dev_buf not 256-byte aligned");
     const Layout L = make_layout(capacity, dir);
-    if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, "apsp_cold: dev_buf smaller than apsp_required_bytes");
+    if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, w + ": dev_buf smaller than apsp_required_bytes");
 
     apsp_graph *g = nullptr;
     apsp_status st0 = make_handle(capacity, dir, dev_buf, (hipStream_t)hip_stream, &g);
@@ -239,22 +214,114 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
         apsp_graph_destroy(g);
         return st;
     }
-    st = run_cold(g);
+    *made = g;
+    return APSP_OK;
+}
+
+// The part that follows D: the light in-edge index and the host's id map
+// (ids[r] for slot r, or 0..n-1 when ids is NULL).
+apsp_status finish_graph(apsp_graph *g, int32_t n, const int32_t *ids) {
+    launch_nin_build(g->dg, 0, n, 0, g->stream);
+    apsp_status st = check_launch("index build");
+    if (st) return st;
+    g->n_live = n;
+    g->live_ids.resize(n);
+    for (int32_t i = 0; i < n; ++i) {
+        g->live_ids[i] = ids ? ids[i] : i;
+        g->slot_of_id[g->live_ids[i]] = i;
+    }
+    g->max_id = n > 0 ? g->live_ids[n - 1] : -1;
+    return APSP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int32_t apsp_abi_version(void) { return APSP_ABI_VERSION; }
+
+const char *apsp_last_error(void) { return g_err.c_str(); }
+
+int32_t apsp_kernel_count(void) { return KID_COUNT; }
+
+const char *apsp_kernel_name(int32_t k) {
+    static const char *names[KID_COUNT] = {
+        "fw_pivot", "fw_panel", "fw_tiles", "nin_build", "nin_update", "add_out", "add_in", "add_relax",
+        "add_place", "gather", "mask_recompute", "tombstone", "edge_begin", "edge_sweep", "query", "misc",
+        "mask_detect"};
+    if (k < 0 || k >= KID_COUNT) return "";
+    return names[k];
+}
+
+size_t apsp_required_bytes(int32_t capacity, int32_t kind) {
+    if (capacity < 1 || capacity > APSP_MAX_CAPACITY) return 0;
+    const int32_t dir = kind & ~(int32_t)APSP_MINIMAX;
+    if (dir != APSP_DIRECTED && dir != APSP_UNDIRECTED) return 0;
+    return make_layout(capacity, dir).total;
+}
+
+apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t kind, int32_t capacity,
+                      void *dev_buf, size_t dev_buf_bytes, void *hip_stream, apsp_graph **out) {
+    apsp_graph *g = nullptr;
+    apsp_status st = new_graph("apsp_cold", adj_dev, n, adj_ld, kind, capacity, dev_buf, dev_buf_bytes, hip_stream,
+                               out, &g);
+    if (st) return st;
+    if ((st = run_cold(g)) || (st = finish_graph(g, n, nullptr))) {
+        apsp_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return APSP_OK;
+}
+
+apsp_status apsp_import(const int32_t *adj_dev, int64_t adj_ld, const int32_t *apsp_dev, int64_t apsp_ld,
+                        int32_t n, const int32_t *ids, int32_t next_id, int32_t kind, int32_t capacity,
+                        void *dev_buf, size_t dev_buf_bytes, void *hip_stream, int32_t verify, apsp_graph **out) {
+    if (out) *out = nullptr;
+    if (verify != APSP_IMPORT_TRUSTED && verify != APSP_IMPORT_EXACT)
+        return fail(APSP_E_INVALID, "apsp_import: verify must be APSP_IMPORT_TRUSTED or APSP_IMPORT_EXACT");
+    if (n > 0 && (!apsp_dev || apsp_ld < n)) return fail(APSP_E_INVALID, "apsp_import: bad matrix pointer or ld");
+    if (ids) {
+        for (int32_t i = 0; i < n; ++i)
+            if (ids[i] < 0 || ids[i] == INT32_MAX || (i > 0 && ids[i] <= ids[i - 1]))
+                return fail(APSP_E_INVALID, "apsp_import: ids must be non-negative and strictly ascending");
+    }
+    const int32_t top = n == 0 ? -1 : ids ? ids[n - 1] : n - 1;
+    if (next_id != -1 && next_id <= top)
+        return fail(APSP_E_INVALID, "apsp_import: next_id must exceed every id (or be -1)");
+    apsp_graph *g = nullptr;
+    apsp_status st = new_graph("apsp_import", adj_dev, n, adj_ld, kind, capacity, dev_buf, dev_buf_bytes, hip_stream,
+                               out, &g);
+    if (st) return st;
+    hipStream_t s = g->stream;
+    int32_t *bad = g->qscratch;  // free until the first query
+    launch_fill(bad, 1, 0, s);
+    launch_import_d(g->dg, apsp_dev, apsp_ld, n, bad, s);
+    if (verify == APSP_IMPORT_EXACT) {
+        st = run_cold(g);
+        if (!st) launch_count_diff(g->dg.D, g->dg.ld, apsp_dev, apsp_ld, n, bad, s);
+    }
+    if (!st && ids && n > 0 &&
+        !hip_ok(hipMemcpyAsync(g->dg.id_of_slot, ids, (size_t)n * 4, hipMemcpyHostToDevice, s), "ids copy"))
+        st = APSP_E_DEVICE;
+    if (!st) st = check_launch("apsp_import");
+    if (!st && (!hip_ok(hipMemcpyAsync(g->qbuf_h, bad, 4, hipMemcpyDeviceToHost, s), "check copy") ||
+                !hip_ok(hipStreamSynchronize(s), "stream sync")))
+        st = APSP_E_DEVICE;
+    if (!st && g->qbuf_h[0] != 0)
+        st = fail(APSP_E_INVALID, "apsp_import: " + std::to_string(g->qbuf_h[0]) +
+                                      (verify == APSP_IMPORT_EXACT
+                                           ? " entries fail the checks or differ from the cold recompute"
+                                           : " entries fail the checks of a distance matrix"));
+    if (!st) st = finish_graph(g, n, ids);
+    if (!st && next_id != -1) g->max_id = next_id - 1;
     if (st) {
         apsp_graph_destroy(g);
         return st;
-    }
-    launch_nin_build(d, 0, n, 0, s);
-    if ((st = check_launch("index build"))) {
-        apsp_graph_destroy(g);
-        return st;
-    }
-    g->n_live = n;
-    g->max_id = n - 1;
-    g->live_ids.resize(n);
-    for (int32_t i = 0; i < n; ++i) {
-        g->live_ids[i] = i;
-        g->slot_of_id[i] = i;
     }
     *out = g;
     return APSP_OK;
@@ -604,6 +671,12 @@ apsp_status apsp_read_adjacency(apsp_graph *g, int32_t *out_dev, int64_t out_ld)
         return fail(APSP_E_INVALID, "apsp_read_adjacency: bad output");
     launch_gather_compact(g->dg.A, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->stream);
     return check_launch("apsp_read_adjacency");
+}
+
+apsp_status apsp_next_id(const apsp_graph *g, int32_t *id) {
+    if (!g || !id) return fail(APSP_E_INVALID, "apsp_next_id: NULL argument");
+    *id = g->max_id + 1;
+    return APSP_OK;
 }
 
 apsp_status apsp_node_count(const apsp_graph *g, int32_t *n) {

@@ -109,6 +109,55 @@ void launch_copy_square(int32_t *dst, const int32_t *src, int64_t ld, int32_t n,
     k_copy_square<<<grid, 256, 0, s>>>(dst, src, ld, n);
 }
 
+// Import of a known distance matrix: D[i][j] := src[i][j] for i, j < n,
+// checked against what the distance matrix of the loaded adjacency must
+// satisfy (Section 2): every entry in [0, INF], a zero diagonal, no entry
+// above its edge's weight (the edge alone is a path), and symmetry for an
+// undirected graph.  Each failing entry adds one to *bad (one atomic per
+// wave); an entry outside [0, INF] is stored as INF.
+__global__ __launch_bounds__(256) void k_import_d(DevGraph g, const int32_t *__restrict__ src, int64_t src_ld,
+                                                  int32_t n, int32_t *bad) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = blockIdx.y;
+    int b = 0;
+    if (j < n) {
+        const int32_t raw = src[(int64_t)i * src_ld + j];
+        int32_t w = raw;
+        if (w < 0 || (uint32_t)w > INF) { w = (int32_t)INF; b = 1; }
+        if (i == j && w != 0) b = 1;
+        if ((uint32_t)w > (uint32_t)g.A[(int64_t)i * g.ld + j]) b = 1;
+        if (g.undirected && src[(int64_t)j * src_ld + i] != raw) b = 1;
+        g.D[(int64_t)i * g.ld + j] = w;
+    }
+    const unsigned long long m = __ballot(b);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(bad, (int32_t)__popcll(m));
+}
+
+void launch_import_d(const DevGraph &g, const int32_t *src, int64_t src_ld, int32_t n, int32_t *bad, hipStream_t s) {
+    if (n <= 0) return;
+    dim3 grid((n + 255) / 256, n);
+    k_import_d<<<grid, 256, 0, s>>>(g, src, src_ld, n, bad);
+}
+
+// *bad += #{(i, j) in [0, n)^2 : a[i][j] != b[i][j]} (one atomic per wave).
+__global__ __launch_bounds__(256) void k_count_diff(const int32_t *__restrict__ a, int64_t lda,
+                                                    const int32_t *__restrict__ b, int64_t ldb, int32_t n,
+                                                    int32_t *bad) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = blockIdx.y;
+    const int d = j < n && a[(int64_t)i * lda + j] != b[(int64_t)i * ldb + j];
+    const unsigned long long m = __ballot(d);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(bad, (int32_t)__popcll(m));
+}
+
+void launch_count_diff(const int32_t *a, int64_t lda, const int32_t *b, int64_t ldb, int32_t n, int32_t *bad,
+                       hipStream_t s) {
+    if (n <= 0) return;
+    dim3 grid((n + 255) / 256, n);
+    k_count_diff<<<grid, 256, 0, s>>>(a, lda, b, ldb, n, bad);
+}
+
+
 // ---------------------------------------------------------------------------
 // phase 1: closure of the 128 x 128 pivot block in LDS
 // ---------------------------------------------------------------------------

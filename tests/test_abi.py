@@ -114,3 +114,42 @@ def test_batch_and_clone_host_checks(lib):
     for name in ("APSP_OP_ADD_NODE", "APSP_OP_REMOVE_NODE", "APSP_OP_UPDATE_EDGE", "APSP_OP_QUERY"):
         assert int(re.search(name + r"\s*=\s*(\d+)", text).group(1)) == getattr(N, name)
     assert ctypes.sizeof(N.BatchItem) == 48
+
+
+def test_import_argument_checks_fail_before_device_work(lib):
+    from paper_2412_15122_amd import _native as N
+    h = ctypes.c_void_p()
+    text = open(HEADER).read()
+    for name in ("APSP_IMPORT_TRUSTED", "APSP_IMPORT_EXACT"):
+        assert int(re.search(name + r"\s*=\s*(\d+)", text).group(1)) == getattr(N, name)
+    fake = ctypes.c_void_p(256)
+    # verify outside the two modes
+    assert lib.apsp_import(fake, 4, fake, 4, 4, None, -1, 0, 8, fake, 1 << 30, None, 7, ctypes.byref(h)) \
+        == N.APSP_E_INVALID
+    assert b"verify" in lib.apsp_last_error()
+    # no matrix, or a leading dimension below n
+    assert lib.apsp_import(fake, 4, None, 4, 4, None, -1, 0, 8, fake, 1 << 30, None, 0, ctypes.byref(h)) \
+        == N.APSP_E_INVALID
+    assert lib.apsp_import(fake, 4, fake, 3, 4, None, -1, 0, 8, fake, 1 << 30, None, 0, ctypes.byref(h)) \
+        == N.APSP_E_INVALID
+    # ids not strictly ascending, negative, or the largest int32 (its successor would overflow)
+    for ids in ([0, 2, 2, 5], [-1, 0, 1, 2], [0, 1, 2, 2**31 - 1]):
+        arr = (ctypes.c_int32 * 4)(*ids)
+        assert lib.apsp_import(fake, 4, fake, 4, 4, arr, -1, 0, 8, fake, 1 << 30, None, 0, ctypes.byref(h)) \
+            == N.APSP_E_INVALID
+        assert b"ids" in lib.apsp_last_error()
+    # the checks apsp_cold makes, with the import's name
+    assert lib.apsp_import(fake, 4, fake, 4, 9, None, -1, 0, 8, fake, 1 << 30, None, 0, ctypes.byref(h)) \
+        == N.APSP_E_INVALID
+    assert lib.apsp_last_error().startswith(b"apsp_import")
+    assert lib.apsp_import(fake, 4, fake, 4, 4, None, -1, 0, 8, fake, 16, None, 0, ctypes.byref(h)) \
+        == N.APSP_E_CAPACITY
+    assert lib.apsp_import(fake, 4, fake, 4, 4, None, -1, 0, 8, fake, 1 << 30, None, 0, None) == N.APSP_E_INVALID
+    # next_id not above every id
+    assert lib.apsp_import(fake, 4, fake, 4, 4, None, 3, 0, 8, fake, 1 << 30, None, 0, ctypes.byref(h)) \
+        == N.APSP_E_INVALID
+    assert b"next_id" in lib.apsp_last_error()
+    assert lib.apsp_import(fake, 4, fake, 4, 4, None, -2, 0, 8, fake, 1 << 30, None, 0, ctypes.byref(h)) \
+        == N.APSP_E_INVALID
+    assert lib.apsp_next_id(None, None) == N.APSP_E_INVALID
+    assert h.value is None
