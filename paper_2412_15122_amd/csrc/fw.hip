@@ -157,49 +157,72 @@ void launch_count_diff(const int32_t *a, int64_t lda, const int32_t *b, int64_t 
     k_count_diff<<<grid, 256, 0, s>>>(a, lda, b, ldb, n, bad);
 }
 
-
 // ---------------------------------------------------------------------------
-// phase 1: closure of the 128 x 128 pivot block in LDS
+// phase 1: closure of the 128 x 128 pivot block
 // ---------------------------------------------------------------------------
-// Thread t owns row (t & 127) and the 16 columns 16 * (t >> 7) + c.  During
-// pivot k neither row k nor column k changes (D[k][k] is 0, or INF for a
-// dead slot), so one barrier per pivot suffices.
+// Thread t keeps row (t & 127), columns 16 * (t >> 7) + c, c < 16, of the
+// block in registers for all 128 pivots.  Pivot k needs D[i][k] of every row
+// and D[k][j] of every column; at the end of pivot k - 1 the owners of
+// column k and of row k publish those values (already updated by pivot
+// k - 1) to a two-deep LDS buffer, so one barrier per pivot suffices: pivot
+// k reads buffer k & 1 while the next values go to the other.  During pivot
+// k neither row k nor column k changes (D[k][k] is 0, or INF for a dead
+// slot), so the published values are the ones the textbook loop reads.
 
 __global__ __launch_bounds__(1024) void k_fw_pivot(int32_t *__restrict__ D, int64_t ld, int32_t r) {
-    __shared__ uint32_t T[TILE][TILE + 1];
+    __shared__ __align__(16) uint32_t rowbuf[2][TILE];  // rowbuf[k & 1][j] = D[k][j]
+    __shared__ uint32_t colbuf[2][TILE];                // colbuf[k & 1][i] = D[i][k]
     const int tid = threadIdx.x;
-    int32_t *base = D + (int64_t)r * TILE * ld + (int64_t)r * TILE;
-    for (int idx = tid; idx < TILE * TILE / 4; idx += 1024) {
-        int row = idx >> 5, c4 = idx & 31;
-        int4 v = *reinterpret_cast<const int4 *>(base + (int64_t)row * ld + c4 * 4);
-        T[row][c4 * 4 + 0] = (uint32_t)v.x;
-        T[row][c4 * 4 + 1] = (uint32_t)v.y;
-        T[row][c4 * 4 + 2] = (uint32_t)v.z;
-        T[row][c4 * 4 + 3] = (uint32_t)v.w;
-    }
-    __syncthreads();
     const int row = tid & (TILE - 1);
     const int c0 = (tid >> 7) * 16;
+    int32_t *src = D + ((int64_t)r * TILE + row) * ld + (int64_t)r * TILE + c0;
     uint32_t own[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) own[c] = T[row][c0 + c];
-    for (int k = 0; k < TILE; ++k) {
-        uint32_t dik = T[row][k];
+    for (int q = 0; q < 4; ++q) {
+        const int4 v = *reinterpret_cast<const int4 *>(src + 4 * q);
+        own[4 * q + 0] = (uint32_t)v.x;
+        own[4 * q + 1] = (uint32_t)v.y;
+        own[4 * q + 2] = (uint32_t)v.z;
+        own[4 * q + 3] = (uint32_t)v.w;
+    }
+    if (c0 == 0) colbuf[0][row] = own[0];
+    if (row == 0) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            uint32_t t = cat(dik, T[k][c0 + c]);
-            if (t < own[c]) {
-                own[c] = t;
-                T[row][c0 + c] = t;
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<uint4 *>(&rowbuf[0][c0 + 4 * q]) =
+                make_uint4(own[4 * q], own[4 * q + 1], own[4 * q + 2], own[4 * q + 3]);
+    }
+    __syncthreads();
+    for (int kb = 0; kb < TILE; kb += 16) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = kb + kk;
+            const int p = kk & 1;  // == k & 1: kb is even
+            const uint32_t dik = colbuf[p][row];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 rk = *reinterpret_cast<const uint4 *>(&rowbuf[p][c0 + 4 * q]);
+                own[4 * q + 0] = min(own[4 * q + 0], cat(dik, rk.x));
+                own[4 * q + 1] = min(own[4 * q + 1], cat(dik, rk.y));
+                own[4 * q + 2] = min(own[4 * q + 2], cat(dik, rk.z));
+                own[4 * q + 3] = min(own[4 * q + 3], cat(dik, rk.w));
             }
+            if (k + 1 < TILE) {
+                if (c0 == ((k + 1) & ~15)) colbuf[p ^ 1][row] = own[(kk + 1) & 15];
+                if (row == k + 1) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *reinterpret_cast<uint4 *>(&rowbuf[p ^ 1][c0 + 4 * q]) =
+                            make_uint4(own[4 * q], own[4 * q + 1], own[4 * q + 2], own[4 * q + 3]);
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int c = 0; c < 16; c += 4) {
-        int4 v = make_int4((int)own[c], (int)own[c + 1], (int)own[c + 2], (int)own[c + 3]);
-        *reinterpret_cast<int4 *>(base + (int64_t)row * ld + c0 + c) = v;
-    }
+    for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<int4 *>(src + 4 * q) =
+            make_int4((int)own[4 * q], (int)own[4 * q + 1], (int)own[4 * q + 2], (int)own[4 * q + 3]);
 }
 
 // ---------------------------------------------------------------------------
