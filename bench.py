@@ -46,9 +46,12 @@ def parse():
                     help="update kinds of a step (profiling runs of one kind); 'all' is the benchmark mix")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (counter calibration)")
-    ap.add_argument("--workload", default="updates", choices=["updates", "batched", "serving"],
+    ap.add_argument("--workload", default="updates", choices=["updates", "batched", "serving", "kernels"],
                     help="updates: the n=16384 update stream (default); batched: 512 graphs with 8 queued "
-                         "updates each, one persistent launch vs one call per update")
+                         "updates each, one persistent launch vs one call per update; kernels: standalone "
+                         "medians of single updates on the n=16384 graph (add, remove, a forced wide edge "
+                         "decrease and the worst-case increase that undoes it)")
+    ap.add_argument("--reps", type=int, default=20, help="kernels: repetitions per update kind")
     ap.add_argument("--graphs", type=int, default=None, help="batched / serving: number of graphs (512 / 64)")
     ap.add_argument("--batch-config", default=None,
                     help="batched: grid,order,variant to use instead of autotuning")
@@ -363,6 +366,94 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_kernels(args):
+    """Standalone medians of single updates on the undirected complete graph
+    n = 16384 (every repetition starts from the same distances):
+      decrease the most used of the 64 lightest edges lowered to 0: the
+               relaxation sweeps nearly every row in one of the two
+               directions (a forced wide K1 sweep), then
+      increase the same edge back to its weight: the worst-case tight
+               increase (mask over R x C, then the recompute);
+      remove   a random live node, then
+      add      the same node back (its original weights, now the newest id).
+    Times are HIP events on the graph's stream around each call."""
+    import torch
+    from paper_2412_15122_amd import workloads as W
+    from paper_2412_15122_amd.apsp import Graph
+    n = args.n
+    adj = W.config3_graph(n)
+    g = Graph(adj, undirected=True, capacity=n + 8)
+    torch.cuda.synchronize()
+    log(f"[bench] cold start done (n={n})")
+    rng = np.random.default_rng(2412151223)
+    orig = {i: i for i in range(n)}          # id -> row of adj (weights of the node)
+    live = list(range(n))
+    times = {"remove": [], "add": [], "decrease": [], "increase": []}
+    stats = {"remove": [], "add": [], "decrease": [], "increase": []}
+
+    def timed(kind, fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times[kind].append(e0.elapsed_time(e1))
+        stats[kind].append(g.stats())
+        return out
+
+    cands = W.lightest_edges(adj, 64, True)
+    best, best_key = None, None
+    for (u, v, wt) in cands:
+        r, c = g.edge_scope(u, v)
+        key = (-(r * c), u, v)
+        if best_key is None or key < best_key:
+            best, best_key = (u, v, wt, r, c), key
+    u, v, wt, r0, c0 = best
+    log(f"[bench] worst-case edge ({u},{v}) weight {wt}: |R|={r0} |C|={c0}")
+    for rep in range(args.reps):
+        timed("decrease", lambda: g.update_edge(u, v, 0))
+        timed("increase", lambda: g.update_edge(u, v, wt))
+    for rep in range(args.reps):
+        k = live[int(rng.integers(len(live)))]
+        timed("remove", lambda: g.remove_node(k))
+        live.remove(k)
+        w = torch.from_numpy(np.ascontiguousarray(adj[orig[k], [orig[x] for x in live]], dtype=np.int32)).cuda()
+        torch.cuda.synchronize()
+        nid = timed("add", lambda: g.add_node_device(w.data_ptr(), w.data_ptr()))
+        orig[nid] = orig.pop(k)
+        live.append(nid)
+    out = {"n": n, "reps": args.reps, "edge": [int(u), int(v), int(wt)], "edge_scope": [int(r0), int(c0)]}
+    for kind in times:
+        t = np.array(times[kind])
+        st = stats[kind]
+        row = {"median_ms": round(float(np.median(t)), 4), "p90_ms": round(float(np.percentile(t, 90)), 4),
+               "min_ms": round(float(t.min()), 4)}
+        if kind in ("decrease", "add"):
+            rr = float(np.median([s_["rows_relaxed"] for s_ in st]))
+            row["rows_relaxed"] = rr
+            # rows swept by the relaxation, 4 n bytes each, over the median time of the whole call
+            row["swept_GBps_whole_call"] = round(rr * 4 * n / (float(np.median(t)) * 1e-3) / 1e9, 1)
+        if kind in ("remove", "increase"):
+            row["flagged"] = float(np.median([s_["flagged"] for s_ in st]))
+            row["rows"] = float(np.median([s_["rows"] for s_ in st]))
+            row["changed"] = float(np.median([s_["changed"] for s_ in st]))
+        out[kind] = row
+        log(f"[bench] {kind}: {row}")
+    ok = None if args.no_verify else bool(np.array_equal(g.matrix(), _cold_matrix(g)))
+    log(f"[bench] final matrix equals a cold recompute: {ok}")
+    out["verified_vs_gpu_cold"] = ok
+    print(json.dumps({"workload": "kernels", **out}), flush=True)
+    return 0 if ok is not False else 1
+
+
+def _cold_matrix(g):
+    c = g.clone()
+    c.recompute_cold()
+    m = c.matrix()
+    c.close()
+    return m
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -371,6 +462,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "kernels":
+        return bench_kernels(args)
     if args.workload == "serving":
         return bench_serving(args)
     import torch

@@ -83,7 +83,7 @@ def mixed_updates(g, A, ids, rng, steps, undirected, wmax, cap, what, minimax=Fa
 
 
 @pytest.mark.parametrize("undirected", [False, True])
-@pytest.mark.parametrize("n,wmax,density", [(1, 10, 1.0), (130, 1000, 1.0), (257, 5, 0.6)])
+@pytest.mark.parametrize("n,wmax,density", [(0, 10, 1.0), (1, 10, 1.0), (130, 1000, 1.0), (257, 5, 0.6)])
 @pytest.mark.parametrize("exact", [False, True])
 def test_import_then_updates(n, wmax, density, undirected, exact):
     rng = np.random.default_rng(7 * n + 2 * undirected + exact)
