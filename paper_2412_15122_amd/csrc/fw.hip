@@ -244,7 +244,7 @@ __device__ __forceinline__ uint32_t umin3(uint32_t a, uint32_t b, uint32_t c) {
 
 __device__ __forceinline__ void minplus_tile(const int32_t *__restrict__ At, const int32_t *__restrict__ Bt,
                                              int32_t *Ct, int64_t ld, uint32_t (*As)[LDS_W],
-                                             uint32_t (*Bs)[LDS_W]) {
+                                             uint32_t (*Bs)[LDS_W], bool close = false) {
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
     uint32_t acc[8][8];
@@ -309,6 +309,47 @@ __device__ __forceinline__ void minplus_tile(const int32_t *__restrict__ At, con
                 for (int c = 0; c < 8; ++c) acc[m][c] = umin3(acc[m][c], cat(a0[m], b0[c]), cat(a1[m], b1[c]));
         }
     }
+    if (close) {
+        // C := closure of C (the next round's pivot block, phase 1), on the
+        // micro-tiles in registers.  Pivot k = 64 h + 4 g + e is row m = 4 h + e
+        // of the threads with ty == g and column c = 4 h + e of those with
+        // tx == g; they publish it to LDS, then every thread relaxes through
+        // it.  Row k and column k do not change during pivot k.
+        uint32_t *rowbuf = &As[0][0];  // rowbuf[j] = C[k][j]
+        uint32_t *colbuf = &As[1][0];  // colbuf[i] = C[i][k]
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            for (int g = 0; g < 16; ++g) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    __syncthreads();  // the previous pivot's reads are done
+                    if (ty == g) {
+                        *reinterpret_cast<uint4 *>(&rowbuf[tx * 4]) = make_uint4(
+                            acc[4 * h + e][0], acc[4 * h + e][1], acc[4 * h + e][2], acc[4 * h + e][3]);
+                        *reinterpret_cast<uint4 *>(&rowbuf[64 + tx * 4]) = make_uint4(
+                            acc[4 * h + e][4], acc[4 * h + e][5], acc[4 * h + e][6], acc[4 * h + e][7]);
+                    }
+                    if (tx == g) {
+                        *reinterpret_cast<uint4 *>(&colbuf[ty * 4]) = make_uint4(
+                            acc[0][4 * h + e], acc[1][4 * h + e], acc[2][4 * h + e], acc[3][4 * h + e]);
+                        *reinterpret_cast<uint4 *>(&colbuf[64 + ty * 4]) = make_uint4(
+                            acc[4][4 * h + e], acc[5][4 * h + e], acc[6][4 * h + e], acc[7][4 * h + e]);
+                    }
+                    __syncthreads();
+                    const uint4 rl = *reinterpret_cast<const uint4 *>(&rowbuf[tx * 4]);
+                    const uint4 rh = *reinterpret_cast<const uint4 *>(&rowbuf[64 + tx * 4]);
+                    const uint4 cl = *reinterpret_cast<const uint4 *>(&colbuf[ty * 4]);
+                    const uint4 ch = *reinterpret_cast<const uint4 *>(&colbuf[64 + ty * 4]);
+                    const uint32_t rk[8] = {rl.x, rl.y, rl.z, rl.w, rh.x, rh.y, rh.z, rh.w};
+                    const uint32_t ck[8] = {cl.x, cl.y, cl.z, cl.w, ch.x, ch.y, ch.z, ch.w};
+#pragma unroll
+                    for (int m = 0; m < 8; ++m)
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) acc[m][c] = min(acc[m][c], cat(ck[m], rk[c]));
+                }
+            }
+        }
+    }
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         int row = (m < 4) ? (ty * 4 + m) : (64 + ty * 4 + (m - 4));
@@ -341,7 +382,12 @@ __global__ __launch_bounds__(256) void k_fw_panel(int32_t *D, int64_t ld, int32_
 // Phase 3: (nb-1)^2 tiles.  Work-groups are dealt round-robin to the 8 XCDs;
 // the remap gives each XCD a contiguous run of tiles (same tile row i), so
 // the column-panel tile D[i][r] is reused from that XCD's L2.
-__global__ __launch_bounds__(256) void k_fw_tiles(int32_t *D, int64_t ld, int32_t r, int32_t nb) {
+// With close_next, tile (r+1, r+1) -- the next round's pivot block, which no
+// other work-group of this round reads -- goes to work-group 0 (dispatched
+// first) and is closed there right after its update: the next round's
+// phase 1 then runs under this round's phase 3 instead of as a launch of its
+// own.
+__global__ __launch_bounds__(256, 3) void k_fw_tiles(int32_t *D, int64_t ld, int32_t r, int32_t nb, int32_t close_next) {
     __shared__ uint32_t As[KC][LDS_W];
     __shared__ uint32_t Bs[KC][LDS_W];
     const int32_t m = nb - 1;
@@ -349,29 +395,33 @@ __global__ __launch_bounds__(256) void k_fw_tiles(int32_t *D, int64_t ld, int32_
     int32_t b = blockIdx.x;
     const int32_t per = total / 8;
     if (b < per * 8) b = (b & 7) * per + (b >> 3);
+    const int32_t next = r * m + r;  // tile (r+1, r+1) with row and column r skipped
+    if (close_next) b = b == next ? 0 : b == 0 ? next : b;
     int32_t ii = b / m, jj = b - ii * m;
     int32_t i = ii + (ii >= r), j = jj + (jj >= r);
     const int32_t *Ap = D + (int64_t)i * TILE * ld + (int64_t)r * TILE;
     const int32_t *Bp = D + (int64_t)r * TILE * ld + (int64_t)j * TILE;
     int32_t *C = D + (int64_t)i * TILE * ld + (int64_t)j * TILE;
-    minplus_tile(Ap, Bp, C, ld, As, Bs);
+    minplus_tile(Ap, Bp, C, ld, As, Bs, close_next && b == next);
 }
 
 const char *launch_fw(const DevGraph &g, int32_t n, hipStream_t s, Prof *prof) {
     if (n <= 0) return nullptr;
     const int32_t nb = (n + TILE - 1) / TILE;
+    // round 0's pivot block on its own; every later one inside the previous
+    // round's phase 3
+    if (prof) prof->begin(KID_FW_PIVOT);
+    k_fw_pivot<<<1, 1024, 0, s>>>(g.D, g.ld, 0);
+    if (prof) prof->end();
+    if (hipGetLastError() != hipSuccess) return "fw_pivot";
     for (int32_t r = 0; r < nb; ++r) {
-        if (prof) prof->begin(KID_FW_PIVOT);
-        k_fw_pivot<<<1, 1024, 0, s>>>(g.D, g.ld, r);
-        if (prof) prof->end();
-        if (hipGetLastError() != hipSuccess) return "fw_pivot";
         if (nb > 1) {
             if (prof) prof->begin(KID_FW_PANEL);
             k_fw_panel<<<2 * (nb - 1), 256, 0, s>>>(g.D, g.ld, r, nb);
             if (prof) prof->end();
             if (hipGetLastError() != hipSuccess) return "fw_panel";
             if (prof) prof->begin(KID_FW_TILE);
-            k_fw_tiles<<<(nb - 1) * (nb - 1), 256, 0, s>>>(g.D, g.ld, r, nb);
+            k_fw_tiles<<<(nb - 1) * (nb - 1), 256, 0, s>>>(g.D, g.ld, r, nb, r + 1 < nb ? 1 : 0);
             if (prof) prof->end();
             if (hipGetLastError() != hipSuccess) return "fw_tiles";
         }
