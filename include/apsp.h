@@ -331,6 +331,18 @@ const char *apsp_kernel_name(int32_t kernel);
 apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes, void *hip_stream,
                              apsp_graph **out);
 
+/* A copy of g with `capacity` node slots (at least the slots g has in use,
+ * e.g. to add nodes to a full graph), in the caller's buffer dev_buf of
+ * apsp_required_bytes(capacity, kind of g) bytes: every used slot keeps its
+ * place, its ids, distances, weights and index list, so the copy behaves as
+ * g would with more room (same ids, same next id).  O(n^2) device copies,
+ * enqueued on hip_stream after g's stream; g's stream then waits for the
+ * copy.  g is unchanged.  Errors: APSP_E_INVALID (NULL arguments, capacity
+ * below the slots in use or above APSP_MAX_CAPACITY, a misaligned or
+ * overlapping buffer), APSP_E_CAPACITY (buffer too small), APSP_E_DEVICE. */
+apsp_status apsp_grow(apsp_graph *g, int32_t capacity, void *dev_buf, size_t dev_buf_bytes, void *hip_stream,
+                      apsp_graph **out);
+
 /* The caller has copied g's whole buffer (apsp_required_bytes bytes, e.g.
  * out to host memory and back) into dev_buf; from now on g uses dev_buf and
  * the old buffer may be freed.  Nothing is enqueued: the caller orders the

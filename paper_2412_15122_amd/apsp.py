@@ -110,16 +110,21 @@ class Graph:
         return cls._from_handle(lib, h, buf, ptr, nbytes, cap, kind, stream, bool(minimax))
 
     def grow(self, capacity: int) -> "Graph":
-        """A copy of this graph with `capacity` node slots (at least the live
-        count), built from its matrices by apsp_import: same ids, same next
-        id, same distances, O(n^2) work.  This graph is left unchanged."""
-        n = self.num_nodes()
-        if capacity < n:
-            raise ValueError(f"capacity {capacity} is below the live count {n}")
-        A = self.matrix_device("A")
-        Dm = self.matrix_device("D")
-        return Graph.from_matrix(A, Dm, undirected=self.undirected, capacity=capacity, minimax=self.minimax,
-                                 ids=self.ids(), next_id=self.next_id())
+        """A copy of this graph with `capacity` node slots (apsp_grow): every
+        used slot keeps its place, ids, distances and weights, so the copy
+        behaves as this graph would with more room.  O(n^2) device copies;
+        this graph is left unchanged."""
+        torch = _torch()
+        nbytes = int(self._lib.apsp_required_bytes(int(capacity), self.kind))
+        if nbytes == 0:
+            raise ValueError(f"invalid capacity {capacity}")
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        ptr = (buf.data_ptr() + 255) & ~255
+        stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        N.check(self._lib.apsp_grow(self._h, int(capacity), ptr, nbytes, stream.cuda_stream, ctypes.byref(h)),
+                "apsp_grow")
+        return Graph._from_handle(self._lib, h, buf, ptr, nbytes, int(capacity), self.kind, stream, self.minimax)
 
     @classmethod
     def _from_handle(cls, lib, h, buf, ptr, nbytes, cap, kind, stream, minimax=False):

@@ -157,6 +157,25 @@ FusedArgs fused_args(apsp_graph *g, int32_t mode) {
     return fa;
 }
 
+// Every buffer of a new handle in its initial state: no edges, no
+// distances (INF), no ids, empty index lists, clear flags and counters.
+apsp_status init_buffers(apsp_graph *g) {
+    DevGraph &d = g->dg;
+    hipStream_t s = g->stream;
+    const int64_t PP = (int64_t)g->P * g->P;
+    launch_fill(d.D, PP, (int32_t)INF, s);
+    launch_fill(d.A, PP, (int32_t)INF, s);
+    if (d.AT) launch_fill(d.AT, PP, (int32_t)INF, s);
+    launch_fill(d.id_of_slot, g->P, -1, s);
+    launch_fill(d.nin_cnt, g->P, 0, s);
+    launch_fill(d.nin_beta, g->P, (int32_t)INF, s);
+    launch_fill(g->heavy_epoch, g->P, 0, s);
+    launch_fill((int32_t *)g->row_bits, (g->P + 31) / 32, 0, s);
+    launch_fill((int32_t *)g->flag_bits, (int64_t)g->P * ((g->P + 31) / 32), 0, s);
+    launch_fill((int32_t *)d.ctl, sizeof(Ctl) / 4, 0, s);
+    return check_launch("initial fill");
+}
+
 // The part of a new graph that precedes its distance matrix: argument
 // checks, the handle, every buffer in its initial state, the adjacency (and
 // its transpose) loaded, slots 0..n-1 in use.  Messages start with `who`.
@@ -189,18 +208,7 @@ apsp_status new_graph(const char *who, const int32_t *adj_dev, int32_t n, int64_
         return fail(APSP_E_DEVICE, std::string("configuring kernels: ") + hipGetErrorString(e));
     }
     hipStream_t s = g->stream;
-    const int64_t PP = (int64_t)g->P * g->P;
-    launch_fill(d.D, PP, (int32_t)INF, s);
-    launch_fill(d.A, PP, (int32_t)INF, s);
-    if (d.AT) launch_fill(d.AT, PP, (int32_t)INF, s);
-    launch_fill(d.id_of_slot, g->P, -1, s);
-    launch_fill(d.nin_cnt, g->P, 0, s);
-    launch_fill(d.nin_beta, g->P, (int32_t)INF, s);
-    launch_fill(g->heavy_epoch, g->P, 0, s);
-    launch_fill((int32_t *)g->row_bits, (g->P + 31) / 32, 0, s);
-    launch_fill((int32_t *)g->flag_bits, (int64_t)g->P * ((g->P + 31) / 32), 0, s);
-    launch_fill((int32_t *)d.ctl, sizeof(Ctl) / 4, 0, s);
-    apsp_status st = check_launch("cold start fill");
+    apsp_status st = init_buffers(g);
     if (st) {
         apsp_graph_destroy(g);
         return st;
@@ -383,6 +391,71 @@ apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes,
     c->delta = g->delta;
     c->last_kind = g->last_kind;
     c->minimax = g->minimax;
+    c->last_n_before = g->last_n_before;
+    c->last_fallback = g->last_fallback;
+    *out = c;
+    return APSP_OK;
+}
+
+apsp_status apsp_grow(apsp_graph *g, int32_t capacity, void *dev_buf, size_t dev_buf_bytes, void *hip_stream,
+                      apsp_graph **out) {
+    if (!out) return fail(APSP_E_INVALID, "apsp_grow: out is NULL");
+    *out = nullptr;
+    if (!g) return fail(APSP_E_INVALID, "apsp_grow: NULL graph");
+    if (capacity < g->dg.n_slots || capacity < 1 || capacity > APSP_MAX_CAPACITY)
+        return fail(APSP_E_INVALID, "apsp_grow: capacity must be in [slots in use, APSP_MAX_CAPACITY]");
+    if (!dev_buf || ((uintptr_t)dev_buf & 255) != 0)
+        return fail(APSP_E_INVALID, "apsp_grow: dev_buf NULL or not 256-byte aligned");
+    const Layout L = make_layout(capacity, g->kind);
+    if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, "apsp_grow: dev_buf smaller than apsp_required_bytes");
+    const size_t src_total = make_layout(g->cap, g->kind).total;
+    if ((char *)dev_buf < g->base + src_total && g->base < (char *)dev_buf + L.total)
+        return fail(APSP_E_INVALID, "apsp_grow: dev_buf overlaps the source graph");
+    apsp_graph *c = nullptr;
+    apsp_status st = make_handle(capacity, g->kind, dev_buf, (hipStream_t)hip_stream, &c);
+    if (st) return st;
+    c->minimax = g->minimax;
+    hipStream_t cs = c->stream;
+    const int32_t ns = g->dg.n_slots;
+    const DevGraph &gd = g->dg;
+    DevGraph &cd = c->dg;
+    hipEvent_t ev = nullptr;
+    bool ok = hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event") &&
+              hip_ok(hipEventRecord(ev, g->stream), "event record") &&
+              hip_ok(hipStreamWaitEvent(cs, ev, 0), "stream wait") && init_buffers(c) == APSP_OK;
+    // slot s keeps its place: rows and columns [0, ns) of each matrix move to
+    // the wider pitch, the per-slot tables and the rank table are copied
+    auto copy2d = [&](int32_t *dst, const int32_t *src) {
+        return ns == 0 || hip_ok(hipMemcpy2DAsync(dst, (size_t)c->P * 4, src, (size_t)g->P * 4, (size_t)ns * 4, ns,
+                                                  hipMemcpyDeviceToDevice, cs),
+                                 "grow copy");
+    };
+    auto copy1d = [&](void *dst, const void *src, size_t bytes) {
+        return bytes == 0 || hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, cs), "grow copy");
+    };
+    ok = ok && copy2d(cd.D, gd.D) && copy2d(cd.A, gd.A) && (!gd.AT || copy2d(cd.AT, gd.AT)) &&
+         copy1d(cd.nin, gd.nin, (size_t)ns * NIN_L * sizeof(int2)) && copy1d(cd.nin_cnt, gd.nin_cnt, (size_t)ns * 4) &&
+         copy1d(cd.nin_beta, gd.nin_beta, (size_t)ns * 4) && copy1d(cd.id_of_slot, gd.id_of_slot, (size_t)ns * 4) &&
+         copy1d(c->rank_cur, g->rank_cur, (size_t)g->n_live * 4) && copy1d(cd.ctl, gd.ctl, sizeof(Ctl)) &&
+         // g's later calls must not overwrite the source while it is copied
+         (cs == g->stream ||
+          (hip_ok(hipEventRecord(ev, cs), "event record") && hip_ok(hipStreamWaitEvent(g->stream, ev, 0), "stream wait")));
+    if (ev) (void)hipEventDestroy(ev);
+    if (!ok) {
+        apsp_graph_destroy(c);
+        return APSP_E_DEVICE;
+    }
+    cd.n_slots = ns;
+    cd.lim = gd.lim;
+    c->epoch = g->epoch;
+    c->n_live = g->n_live;
+    c->max_id = g->max_id;
+    c->live_ids = g->live_ids;
+    c->slot_of_id = g->slot_of_id;
+    c->free_slots = g->free_slots;
+    c->policy = g->policy;
+    c->delta = g->delta;
+    c->last_kind = g->last_kind;
     c->last_n_before = g->last_n_before;
     c->last_fallback = g->last_fallback;
     *out = c;

@@ -153,3 +153,11 @@ def test_import_argument_checks_fail_before_device_work(lib):
         == N.APSP_E_INVALID
     assert lib.apsp_next_id(None, None) == N.APSP_E_INVALID
     assert h.value is None
+
+
+def test_grow_host_checks(lib):
+    from paper_2412_15122_amd import _native as N
+    h = ctypes.c_void_p()
+    assert lib.apsp_grow(None, 8, ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h)) == N.APSP_E_INVALID
+    assert lib.apsp_grow(None, 8, ctypes.c_void_p(256), 1 << 30, None, None) == N.APSP_E_INVALID
+    assert h.value is None

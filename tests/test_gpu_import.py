@@ -1,5 +1,5 @@
 """GPU parity of the warm start from a known distance matrix (apsp_import) and
-of growing a graph's capacity through it (Graph.grow).
+of growing a graph's capacity (apsp_grow).
 
 The paper's problem statement (Section 2) starts from a graph whose
 all-pairs shortest-path matrix is already known; apsp_import takes that
@@ -188,10 +188,22 @@ def test_grow_keeps_ids_and_distances(undirected):
         g.add_node(np.ones(len(ids), np.int32), None if undirected else np.ones(len(ids), np.int32))
     g.remove_node(ids[-1])                 # the largest id leaves: no copy may hand it out again
     A, ids = O.apply_update(A, ids, "remove", u=ids[-1], undirected=undirected)
+    with pytest.raises(ApspError()):       # fewer slots than the graph uses
+        g.grow(n - 1)
     big = g.grow(n + 40)
     assert big.capacity == n + 40
     assert big.next_id() == g.next_id() > max(ids) + 1
     expect_equal(big, A, ids, "grown")
     expect_equal(g, A, ids, "source unchanged")
-    mixed_updates(big, A, ids, rng, 14, undirected, 500, n + 40, "after grow")
+    # the same copy by way of the import of its matrices
+    imp = Graph().from_matrix(g.adjacency(), g.matrix(), undirected=undirected, capacity=n + 40, ids=ids,
+                              next_id=g.next_id(), exact=True)
+    assert imp.next_id() == big.next_id()
+    A2, ids2 = A.copy(), list(ids)
+    state = rng.bit_generator.state
+    A, ids = mixed_updates(big, A, ids, rng, 14, undirected, 500, n + 40, "after grow")
+    rng.bit_generator.state = state
+    A2, ids2 = mixed_updates(imp, A2, ids2, rng, 14, undirected, 500, n + 40, "after import")
+    assert ids2 == ids and np.array_equal(big.matrix(), imp.matrix())
     big.sync()
+    imp.sync()
