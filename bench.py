@@ -138,6 +138,45 @@ def cpu_baseline(adj, budget_s=12.0):
     }
 
 
+def cpu_context(adj):
+    """Further oracle timings on the host, context beside the baseline (a few
+    seconds): cold Floyd-Warshall of the n = 256 directed complete graph on
+    one thread (median of 5); of a directed n = 4096 graph of 95% density on
+    one thread and on all, sampled by pivots and extrapolated; one dense
+    Dijkstra row of the n = 16384 graph on one thread."""
+    from oracle import oracle as O
+    from paper_2412_15122_amd import workloads as W
+    out = {"host_cpu": "unknown", "logical_cpus": os.cpu_count(), "threads": O.max_threads()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    out["host_cpu"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    a256 = W.random_graph(256, 1, 1000, undirected=False, density=1.0, seed=W.seed_for(1))
+    ts = []
+    for _ in range(5):
+        t = time.perf_counter()
+        O.fw(a256, threads=1)
+        ts.append(time.perf_counter() - t)
+    out["fw_n256_1thread_ms"] = round(1e3 * float(np.median(ts)), 2)
+    a4096 = W.random_graph(4096, 1, 10000, undirected=False, density=0.95, seed=W.seed_for(2))
+    for label, threads, pivots in (("1thread", 1, 32), ("all_threads", O.max_threads(), 128)):
+        D = O.fw_init(a4096)
+        t = time.perf_counter()
+        O.fw_pivots(D, 0, pivots, threads)
+        el = time.perf_counter() - t
+        out[f"fw_n4096_{label}_s"] = round(el / pivots * 4096, 2)
+    t = time.perf_counter()
+    O.dijkstra_rows(adj, [0, 1], threads=1)
+    out["dijkstra_row_n16384_1thread_ms"] = round(1e3 * (time.perf_counter() - t) / 2, 1)
+    out["note"] = ("n=4096 figures extrapolated from 32 (one thread) and 128 (all threads) timed pivots; "
+                   "context only, not the baseline")
+    return out
+
+
 # ---------------------------------------------------------------------------
 # main
 # ---------------------------------------------------------------------------
@@ -722,6 +761,10 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle Floyd-Warshall, sampled)")
         out["cpu_baseline"] = cpu_baseline(adj)
+        try:  # context only: a failure here must not cost the benchmark line
+            out["cpu_context"] = cpu_context(adj)
+        except Exception as e:  # noqa: BLE001
+            out["cpu_context"] = {"error": f"{type(e).__name__}: {e}"}
     g.close()
     print(json.dumps(out), flush=True)
 
