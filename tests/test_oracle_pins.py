@@ -565,3 +565,25 @@ def test_minimax_pair_nodes_against_brute_force(undirected):
             keep = [t for t in range(n) if t != k]
             d2 = O.minimax_apsp(A[np.ix_(keep, keep)])[keep.index(i), keep.index(j)]
             assert (d2 > D[i, j]) == (k in key), (trial, k)
+
+
+@pytest.mark.parametrize("minimax", [False, True])
+@pytest.mark.parametrize("undirected", [False, True])
+def test_true_distance_matrices_pass_the_import_checks(undirected, minimax):
+    """The O(n^2) conditions apsp_import checks hold for every true distance
+    matrix (so a correct matrix is never refused): entries in [0, INF], a zero
+    diagonal, no entry above its edge, symmetry when undirected -- here on
+    graphs with absent edges, zero weights and unreachable pairs."""
+    INF = W.INF
+    rng = np.random.default_rng(5 + 2 * undirected + minimax)
+    for n, density, zero in ((1, 1.0, 0.0), (9, 0.3, 0.3), (40, 0.1, 0.2), (60, 1.0, 0.0)):
+        adj = W.random_graph(n, 1, 50, undirected=undirected, density=density,
+                             seed=int(rng.integers(1 << 30)), zero_frac=zero)
+        D = O.minimax_apsp(adj) if minimax else O.fw(adj)
+        A = adj.astype(np.int64).copy()
+        np.fill_diagonal(A, 0)
+        assert D.min() >= 0 and D.max() <= INF
+        assert np.all(np.diag(D) == 0)
+        assert np.all(D.astype(np.int64) <= A)
+        if undirected:
+            assert np.array_equal(D, D.T)
