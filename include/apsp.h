@@ -7,14 +7,14 @@
  * large dense graph" (Liu, arXiv 2412.15122):
  *
  *   apsp_cold          cold APSP (Floyd-Warshall; Section 1)
- *   apsp_add_node      G + p   (Theorems theorem2, theo_2_back, theorem3 and
- *                               Corollaries corollary1, corollary2; Sec. 2.1)
- *   apsp_remove_node   G - G_k (need_update_list by Theorem theorem_spd_4 /
- *                               Corollary corollary3, then recompute of the
- *                               listed pairs; Section 2.2, Algorithm 5)
- *   apsp_update_edge   one edge raised or lowered (Section 2.3, Algorithm 6;
+ *   apsp_add_node      G + p   (Theorems 1, 2 and 3 and
+ *                               Corollaries 1 and 2; Sec. 3.1)
+ *   apsp_remove_node   G - G_k (need_update_list by Theorem 4 /
+ *                               Corollary 3, then recompute of the
+ *                               listed pairs; Section 3.2, Algorithm 5)
+ *   apsp_update_edge   one edge raised or lowered (Section 3.3, Algorithm 6;
  *                               done directly, see each call)
- *   apsp_query         warm single-pair shortest path (Section 3, Alg. 7)
+ *   apsp_query         warm single-pair shortest path (Section 4, Alg. 7)
  *   apsp_query_nodes   nodes on some / on every shortest path of a pair
  *                      (Algorithms 8 and 10)
  *
@@ -82,8 +82,8 @@ typedef enum {
  * D[i][j] = the least, over walks from i to j, of the largest edge weight on
  * the walk (0 when i == j), the variant the paper's discussion section says
  * its algorithms carry over to.  Every single-graph call then runs the same
- * steps with max in place of + (Theorems theorem2-theorem3 and Corollary
- * corollary3 hold with max, which is monotone with 0 as identity on weights
+ * steps with max in place of + (Theorems 1–3 and Corollary
+ * 3 hold with max, which is monotone with 0 as identity on weights
  * >= 0).  A batch (apsp_batch_run) takes graphs of one kind: all minimax
  * or none. */
 typedef enum { APSP_DIRECTED = 0, APSP_UNDIRECTED = 1, APSP_MINIMAX = 2 } apsp_kind;
@@ -110,7 +110,7 @@ typedef struct {
     int64_t flagged;     /* |F|: pairs in the need_update mask */
     int32_t rows;        /* Phi: rows with at least one flagged pair */
     int32_t n_before;    /* live node count before the update */
-    double cost;         /* Definition def:cost_defi: Phi / (N - 1) */
+    double cost;         /* Definition 1: Phi / (N - 1) */
     int32_t kind;        /* 0 none, 1 add, 2 remove, 3 decrease, 4 increase */
     int32_t noop;        /* 1 when D provably did not change (O(1) path) */
     int32_t fallback;    /* 1 when cold Floyd-Warshall ran instead */
@@ -121,7 +121,7 @@ typedef struct {
     int32_t rows_changed;/* Phi': rows with at least one changed pair */
     int64_t changed;     /* |F'|: flagged pairs whose distance changed -- the
                           * refined need_update list of Algorithms 11 and 12:
-                          * by Theorem theo_algo12 (and its converse) exactly
+                          * by Theorem 6 (and its converse) exactly
                           * the pairs whose every shortest path uses the
                           * removed node (or the raised edge).  0 after a cold
                           * fallback. */
@@ -155,7 +155,7 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
                       void *hip_stream, apsp_graph **out);
 
 /* Warm start from a distance matrix that is already known: the premise of
- * the paper's problem statement (Section 2: the old graph's all-pairs
+ * the paper's problem statement (Section 1: the old graph's all-pairs
  * shortest-path matrix is given, and only the update is to be paid for).
  * Builds a graph as apsp_cold does from adj_dev, but takes D from apsp_dev
  * (n x n int32, row-major, leading dimension apsp_ld >= n, row i = distances
@@ -163,7 +163,8 @@ apsp_status apsp_cold(const int32_t *adj_dev, int32_t n, int64_t adj_ld, int32_t
  *   ids      host array of n strictly ascending ids in [0, INT32_MAX) for
  *            rows 0..n-1 (NULL = 0..n-1); read during the call only.
  *   next_id  the id the next apsp_add_node returns (later ones count up
- *            from it), above every id; -1 = the largest id + 1.  Lets a
+ *            from it), above every id and below INT32_MAX; -1 = the
+ *            largest id + 1.  Lets a
  *            copy keep a graph's id sequence (apsp_next_id) when its largest
  *            ids were removed.
  *   verify   APSP_IMPORT_TRUSTED: the checks below only;
@@ -191,20 +192,21 @@ apsp_status apsp_graph_destroy(apsp_graph *g);
 
 /* ---- updates (asynchronous) ---------------------------------------------- */
 
-/* Add node p (paper: G + p, Section 2.1).  w_out_dev[t] is the weight of
+/* Add node p (paper: G + p, Section 3.1).  w_out_dev[t] is the weight of
  * p -> t and w_in_dev[t] the weight of t -> p, for the t-th live node in
  * ascending-id order (length = live count before the call).  For an
  * undirected graph w_in_dev may be NULL (it equals w_out_dev).  New row:
- * SPD(p, r) = min_t d(p,t) + SPD(t,r) (Corollary corollary1); new column:
- * SPD(r, p) = min_t SPD(r,t) + d(t,p) (Corollary corollary2); old pairs:
- * min(SPD(i,j), SPD(i,p) + SPD(p,j)) (Theorem theorem3).  *new_id (host)
- * receives max_id + 1.  Returns APSP_E_CAPACITY when every slot is used. */
+ * SPD(p, r) = min_t d(p,t) + SPD(t,r) (Corollary 1); new column:
+ * SPD(r, p) = min_t SPD(r,t) + d(t,p) (Corollary 2); old pairs:
+ * min(SPD(i,j), SPD(i,p) + SPD(p,j)) (Theorem 3).  *new_id (host)
+ * receives max_id + 1.  Returns APSP_E_CAPACITY when every slot is used, or
+ * when max_id + 1 would reach INT32_MAX (ids stay below it). */
 apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t *w_in_dev,
                           int32_t *new_id);
 
-/* Remove node `id` (paper: G - G_k, Section 2.2, Algorithm 5).  Pairs (i,j)
+/* Remove node `id` (paper: G - G_k, Section 3.2, Algorithm 5).  Pairs (i,j)
  * with D[i][k] + D[k][j] == D[i][j] form the need_update mask (Corollary
- * corollary3: all others keep their distance); the masked pairs are
+ * 3: all others keep their distance); the masked pairs are
  * recomputed exactly on G - G_k, or cold Floyd-Warshall runs, per the
  * fallback policy.  The id is retired. */
 apsp_status apsp_remove_node(apsp_graph *g, int32_t id);
@@ -213,19 +215,19 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id);
  * 0 <= w <= APSP_INF (APSP_INF deletes the edge).  u != v, both live.
  * The paper (Algorithm 6) removes one endpoint and adds it back; this call
  * gets the same D directly: a decrease below D[u][v] relaxes every pair
- * through the new edge (Theorem theorem3 with a relay node on the edge), an
+ * through the new edge (Theorem 3 with a relay node on the edge), an
  * increase of an edge with D[u][v] == w_old recomputes the pairs whose
- * shortest distance can use it (Corollary corollary3 applied to that relay
+ * shortest distance can use it (Corollary 3 applied to that relay
  * node); any other change leaves D as it is.  The choice is made on the
  * device: the call never waits. */
 apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w);
 
 /* ---- queries (synchronous) ------------------------------------------------ */
 
-/* Shortest path from i to j (Algorithm 7, Section 3): *dist = D[i][j]; the
+/* Shortest path from i to j (Algorithm 7, Section 4): *dist = D[i][j]; the
  * path is the lexicographically smallest shortest simple path over ids,
  * found among Algorithm 7's candidates {t : D[i][t] + D[t][j] == D[i][j]}
- * (Theorem al_correct).  With zero-weight edges any shortest simple path
+ * (Theorem 5).  With zero-weight edges any shortest simple path
  * may be returned; on a minimax graph (APSP_MINIMAX) the path is a simple
  * path whose largest edge weight is D[i][j], found over the same candidates
  * with max in place of +.  path_ids (host, path_cap entries) receives the ids from
@@ -236,8 +238,8 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w);
 apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
                        int32_t *path_ids, int32_t path_cap, int32_t *path_len);
 
-/* The nodes of the shortest paths from i to j (Section 3: Algorithm 7's
- * candidates, Theorem al_correct; Algorithm 8's paths; Algorithm 10's
+/* The nodes of the shortest paths from i to j (Section 4: Algorithm 7's
+ * candidates, Theorem 5; Algorithm 8's paths; Algorithm 10's
  * key_node_list).  *dist = D[i][j].
  *   on_ids  (host, on_cap entries): every live t with
  *           D[i][t] + D[t][j] == D[i][j], i and j included -- the nodes that
@@ -347,8 +349,19 @@ apsp_status apsp_grow(apsp_graph *g, int32_t capacity, void *dev_buf, size_t dev
  * out to host memory and back) into dev_buf; from now on g uses dev_buf and
  * the old buffer may be freed.  Nothing is enqueued: the caller orders the
  * copy before g's next call (e.g. on g's stream).  Lets a server move idle
- * graphs out of HBM and back without a cold start. */
+ * graphs out of HBM and back without a cold start.  A graph detached with
+ * apsp_graph_detach (below) is usable again after this call. */
 apsp_status apsp_graph_relocate(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes);
+
+/* The caller is about to free or reuse g's device buffer, e.g. after copying
+ * it to host memory: waits for g's stream, then every call that would touch
+ * device memory through g (updates, queries, read-outs, statistics, sync,
+ * clone, grow, batches) returns APSP_E_INVALID and enqueues nothing, until
+ * apsp_graph_relocate gives g a buffer again.  Host-only calls (ids, counts,
+ * apsp_next_id, settings, apsp_graph_destroy) keep working.  Errors:
+ * APSP_E_INVALID (NULL), APSP_E_DEVICE (the stream wait failed; g stays
+ * attached). */
+apsp_status apsp_graph_detach(apsp_graph *g);
 
 /* ---- batched updates --------------------------------------------------- */
 

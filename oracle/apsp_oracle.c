@@ -9,7 +9,7 @@
  * exactly (paper, Section 1: the shortest-path problem and APSP; notation
  * table: SPD(i,j|G) with SPD(i,i) = 0 and the APSP matrix M_G): the cold APSP
  * matrix of the graph, by two textbook routines the paper names as the cold
- * baselines (Section 1 and Section 2.1: Floyd-Warshall and Dijkstra):
+ * baselines (Section 1 and Section 3.1: Floyd-Warshall and Dijkstra):
  *
  *   oracle_fw_init / oracle_fw_pivots   Floyd-Warshall, k outermost
  *   oracle_dijkstra_rows                dense O(n^2) Dijkstra per source

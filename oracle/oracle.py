@@ -15,12 +15,12 @@ slowly and visibly:
   minimax (bottleneck) distances, the (min, max) variant of the discussion
   section: Floyd-Warshall with max, enumeration of simple paths, and
   reachability under a weight threshold.
-* ``remove_mask`` -- the need_update_list of a node removal (Section 2.2,
-  built with Theorem "theorem_spd_4" / Corollary "corollary3"): pair (i,j)
+* ``remove_mask`` -- the need_update_list of a node removal (Section 3.2,
+  built with Theorem 4 / Corollary 3): pair (i,j)
   is listed when M[i][k] + M[k][j] equals M[i][j].
-* ``remove_cost`` -- Definition "def:cost_defi": Phi / (N - 1).
+* ``remove_cost`` -- Definition 1: Phi / (N - 1).
 * ``refined_set`` -- the refined need_update_list of Algorithms 11-12
-  (Theorem "theo_algo12"): the pairs whose distance changes.
+  (Theorem 6): the pairs whose distance changes.
 * ``edge_mask`` -- the same criterion applied to an edge (u,v): the pairs
   whose shortest distance can use the edge (see DESIGN for this reading).
 * ``pair_nodes`` -- the nodes on some / on every shortest i -> j path
@@ -281,7 +281,7 @@ def minimax_by_thresholds(A: np.ndarray) -> np.ndarray:
 def remove_mask(D: np.ndarray, k: int, minimax: bool = False) -> np.ndarray:
     """need_update_list of removing compact node k, as a boolean matrix:
     F[i][j] is True when i != j, k not in {i, j}, D[i][j] < INF and
-    D[i][k] (+) D[k][j] == D[i][j]  (equality form of Corollary 'corollary3';
+    D[i][k] (+) D[k][j] == D[i][j]  (equality form of Corollary 3;
     for distances '>=' and '==' coincide).  minimax: (+) is max."""
     D = np.asarray(D, dtype=np.int64)
     n = D.shape[0]
@@ -294,7 +294,7 @@ def remove_mask(D: np.ndarray, k: int, minimax: bool = False) -> np.ndarray:
 
 
 def remove_cost(F: np.ndarray, n_before: int) -> Tuple[int, float]:
-    """Definition 'def:cost_defi': Phi = number of non-empty need_update_list
+    """Definition 1: Phi = number of non-empty need_update_list
     rows, Cost = Phi / (N - 1) with N the node count before the removal."""
     phi = int(np.count_nonzero(F.any(axis=1)))
     cost = 0.0 if n_before <= 1 else phi / (n_before - 1)
@@ -319,7 +319,7 @@ def refined_set(D_before: np.ndarray, D_after: np.ndarray) -> np.ndarray:
     """The refined need_update_list of Algorithms 11 and 12: the pairs whose
     shortest distance differs between G and G' (both matrices over the same
     nodes in the same order; for a removal, pass D_before without row and
-    column k).  By Theorem 'theo_algo12' a pair whose distance goes up had k
+    column k).  By Theorem 6 a pair whose distance goes up had k
     (or the raised edge) on every shortest path, and a pair with a shortest
     path avoiding it keeps its distance, so this is the paper's refined list."""
     return np.asarray(D_before, dtype=np.int64) != np.asarray(D_after, dtype=np.int64)
@@ -341,7 +341,7 @@ def canonical_path(A: np.ndarray, D: np.ndarray, i: int, j: int) -> List[int]:
     """Lexicographically smallest shortest simple i->j path (compact indices).
 
     Candidates are Algorithm 7's: t with D[i][t] (+) D[t][j] == D[i][j]
-    (Theorem 'al_correct': they contain every shortest path).  From cur, the
+    (Theorem 5: they contain every shortest path).  From cur, the
     next node is the smallest b != cur with A[cur][b] < INF and
     A[cur][b] (+) D[b][j] == D[cur][j].  With w >= 1 each step lowers
     D[.][j], so the walk is simple and ends at j.  Returns [] if unreachable.
@@ -378,7 +378,7 @@ def canonical_path(A: np.ndarray, D: np.ndarray, i: int, j: int) -> List[int]:
 def pair_nodes(A: np.ndarray, D: np.ndarray, i: int, j: int) -> Tuple[List[int], List[int]]:
     """The nodes of the shortest i -> j paths, in compact positions, ascending.
 
-    on  -- Algorithm 7's candidate_node_list (Theorem 'al_correct'), which is
+    on  -- Algorithm 7's candidate_node_list (Theorem 5), which is
            the node set of Algorithm 8's paths: every t with
            D[i][t] (+) D[t][j] == D[i][j], i and j included.
     key -- Algorithm 10's key_node_list of the pair: the nodes other than i

@@ -8,8 +8,8 @@
  * warm/cold time ratios can be set beside the paper's Tables 1-4:
  *
  *   pc_fw             the cold start: textbook Floyd-Warshall (Section 1).
- *   pc_remove         Algorithm 5: need_update_list by Corollary corollary3,
- *                     Cost (Definition def:cost_defi), Floyd-Warshall on
+ *   pc_remove         Algorithm 5: need_update_list by Corollary 3,
+ *                     Cost (Definition 1), Floyd-Warshall on
  *                     G - G_k when Cost > delta, else copy M_G and run one
  *                     dense Dijkstra on G - G_k from every row with a
  *                     non-empty list, stopping once the row's listed nodes
@@ -22,8 +22,8 @@
  *                     intersected; then Algorithm 5 from its Cost step.
  *   pc_edge           Algorithm 6: the endpoint whose removal costs less is
  *                     removed (Algorithm 5), then added back with the new
- *                     weight by the add-node theorems of Section 2.1
- *                     (Theorems theorem2, theo_2_back, theorem3).
+ *                     weight by the add-node theorems of Section 3.1
+ *                     (Theorems 1, 2 and 3).
  *   pc_query          Algorithm 7: candidates, small graph, Dijkstra on it.
  *   pc_dijkstra_path  the cold single-pair query (Dijkstra on G).
  *   pc_remove_sample  a bounded timing sample of Algorithm 5 (benchmark).
@@ -32,7 +32,7 @@
  * saturating sums.  Matrices are row-major n x n int32; results of a removal
  * are (n-1) x (n-1) in the order of the remaining nodes.  `st` receives
  * (Phi, listed pairs, fell back to Floyd-Warshall, Dijkstra runs, and --
- * pc_remove_key -- the pairs Corollary corollary3 flagged, or -- pc_edge --
+ * pc_remove_key -- the pairs Corollary 3 flagged, or -- pc_edge --
  * the removed endpoint): 5 entries.  Every routine returns 0, or -1 when it
  * cannot allocate its work space.
  */
@@ -326,7 +326,7 @@ int pc_remove_key(int32_t n, const int32_t *A, const int32_t *D, int32_t k, doub
         free(need); free(cnt); key_work_free(&w);
         return -1;
     }
-    need_lists(n, (const uint32_t *)D, k, need, cnt);  /* the pairs Corollary corollary3 flags */
+    need_lists(n, (const uint32_t *)D, k, need, cnt);  /* the pairs Corollary 3 flags */
     int64_t flagged = 0;
     for (int32_t i = 0; i < n; ++i) {
         if (!cnt[i]) continue;
@@ -377,7 +377,7 @@ int pc_edge(int32_t n, const int32_t *A, const int32_t *D, int32_t undirected, i
     int rc = remove_from_lists(n, (const uint32_t *)A, Du, k, delta, need, cnt, D2, st, NULL);
     st[4] = k;
     if (rc) goto done;
-    /* G': the edge re-weighted; k added back (Section 2.1). */
+    /* G': the edge re-weighted; k added back (Section 3.1). */
     memcpy(Ap, A, (size_t)n * n * 4);
     Ap[(size_t)u * n + v] = (uint32_t)w;
     if (undirected) Ap[(size_t)v * n + u] = (uint32_t)w;

@@ -114,6 +114,7 @@ SIGNATURES = {
     "apsp_profile_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     "apsp_graph_clone": (_I32, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
     "apsp_graph_relocate": (_I32, [_P, _P, ctypes.c_size_t]),
+    "apsp_graph_detach": (_I32, [_P]),
     "apsp_grow": (_I32, [_P, _I32, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
     "apsp_batch_workspace_bytes": (ctypes.c_size_t, [_I32, _I32]),
     "apsp_batch_create": (_I32, [_P, ctypes.c_size_t, _I32, _I32, ctypes.POINTER(_P)]),

@@ -7,6 +7,7 @@ buffer and the stream only.
 from __future__ import annotations
 
 import ctypes
+import sys
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -178,6 +179,9 @@ class Graph:
         with torch.cuda.stream(self._stream):
             host.copy_(self._buf[off:off + self._nbytes], non_blocking=True)
         self._stream.synchronize()
+        # from here on the library refuses every call that would touch the
+        # old buffer, until swap_in relocates the graph
+        N.check(self._lib.apsp_graph_detach(self._h), "apsp_graph_detach")
         self._buf = host
         self._ptr = None
 
@@ -215,6 +219,10 @@ class Graph:
             self._h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be torn down: make
+        # no HIP call then (the process releases everything anyway)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -15,6 +15,7 @@ ids at that point of the graph's queue).
 from __future__ import annotations
 
 import ctypes
+import sys
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -71,6 +72,10 @@ class Batch:
             self._h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be torn down: make
+        # no HIP call then (the process releases everything anyway)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

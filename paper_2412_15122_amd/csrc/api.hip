@@ -299,8 +299,8 @@ apsp_status apsp_import(const int32_t *adj_dev, int64_t adj_ld, const int32_t *a
                 return fail(APSP_E_INVALID, "apsp_import: ids must be non-negative and strictly ascending");
     }
     const int32_t top = n == 0 ? -1 : ids ? ids[n - 1] : n - 1;
-    if (next_id != -1 && next_id <= top)
-        return fail(APSP_E_INVALID, "apsp_import: next_id must exceed every id (or be -1)");
+    if (next_id != -1 && (next_id <= top || next_id == INT32_MAX))
+        return fail(APSP_E_INVALID, "apsp_import: next_id must exceed every id and be below INT32_MAX (or be -1)");
     apsp_graph *g = nullptr;
     apsp_status st = new_graph("apsp_import", adj_dev, n, adj_ld, kind, capacity, dev_buf, dev_buf_bytes, hip_stream,
                                out, &g);
@@ -337,6 +337,7 @@ apsp_status apsp_import(const int32_t *adj_dev, int64_t adj_ld, const int32_t *a
 
 apsp_status apsp_recompute_cold(apsp_graph *g) {
     if (!g) return fail(APSP_E_INVALID, "apsp_recompute_cold: NULL graph");
+    if (g->detached) return detached_error("apsp_recompute_cold");
     return run_cold(g);
 }
 
@@ -354,6 +355,7 @@ apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes,
     if (!out) return fail(APSP_E_INVALID, "apsp_graph_clone: out is NULL");
     *out = nullptr;
     if (!g) return fail(APSP_E_INVALID, "apsp_graph_clone: NULL graph");
+    if (g->detached) return detached_error("apsp_graph_clone");
     if (!dev_buf) return fail(APSP_E_INVALID, "apsp_graph_clone: dev_buf is NULL");
     if (((uintptr_t)dev_buf & 255) != 0) return fail(APSP_E_INVALID, "apsp_graph_clone: dev_buf not 256-byte aligned");
     const Layout L = make_layout(g->cap, g->kind);
@@ -402,6 +404,7 @@ apsp_status apsp_grow(apsp_graph *g, int32_t capacity, void *dev_buf, size_t dev
     if (!out) return fail(APSP_E_INVALID, "apsp_grow: out is NULL");
     *out = nullptr;
     if (!g) return fail(APSP_E_INVALID, "apsp_grow: NULL graph");
+    if (g->detached) return detached_error("apsp_grow");
     if (capacity < g->dg.n_slots || capacity < 1 || capacity > APSP_MAX_CAPACITY)
         return fail(APSP_E_INVALID, "apsp_grow: capacity must be in [slots in use, APSP_MAX_CAPACITY]");
     if (!dev_buf || ((uintptr_t)dev_buf & 255) != 0)
@@ -493,7 +496,15 @@ apsp_status apsp_graph_relocate(apsp_graph *g, void *dev_buf, size_t dev_buf_byt
     g->row_bits = t->row_bits;
     g->marks = t->marks;
     g->partials = t->partials;
+    g->detached = 0;
     apsp_graph_destroy(t);
+    return APSP_OK;
+}
+
+apsp_status apsp_graph_detach(apsp_graph *g) {
+    if (!g) return fail(APSP_E_INVALID, "apsp_graph_detach: NULL graph");
+    if (!hip_ok(hipStreamSynchronize(g->stream), "stream sync")) return APSP_E_DEVICE;
+    g->detached = 1;
     return APSP_OK;
 }
 
@@ -523,9 +534,12 @@ apsp_status apsp_set_index_limit(apsp_graph *g, int32_t limit) {
 
 apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t *w_in_dev, int32_t *new_id) {
     if (!g || !new_id) return fail(APSP_E_INVALID, "apsp_add_node: NULL argument");
+    if (g->detached) return detached_error("apsp_add_node");
     const bool und = g->kind == APSP_UNDIRECTED;
     if (g->n_live > 0 && (!w_out_dev || (!und && !w_in_dev)))
         return fail(APSP_E_INVALID, "apsp_add_node: weight vector is NULL");
+    // ids stay below INT32_MAX, as apsp_import requires of the ids it takes
+    if (g->max_id >= INT32_MAX - 1) return fail(APSP_E_CAPACITY, "apsp_add_node: the id range is used up");
     int32_t p;
     if (!g->free_slots.empty()) p = *g->free_slots.begin();
     else if (g->dg.n_slots < g->cap) p = g->dg.n_slots;
@@ -577,6 +591,7 @@ apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t
 
 apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     if (!g) return fail(APSP_E_INVALID, "apsp_remove_node: NULL graph");
+    if (g->detached) return detached_error("apsp_remove_node");
     int32_t k;
     if (!lookup(g, id, &k)) return fail(APSP_E_NOT_FOUND, "apsp_remove_node: id is not live");
     const int32_t r = rank_of(g, id);
@@ -622,6 +637,7 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
 
 apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     if (!g) return fail(APSP_E_INVALID, "apsp_update_edge: NULL graph");
+    if (g->detached) return detached_error("apsp_update_edge");
     if (w < 0 || (uint32_t)w > INF) return fail(APSP_E_INVALID, "apsp_update_edge: weight outside [0, APSP_INF]");
     if (u == v) return fail(APSP_E_INVALID, "apsp_update_edge: u == v");
     int32_t su, sv;
@@ -663,6 +679,7 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
 apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32_t *path_ids, int32_t path_cap,
                        int32_t *path_len) {
     if (!g || !dist || !path_len) return fail(APSP_E_INVALID, "apsp_query: NULL argument");
+    if (g->detached) return detached_error("apsp_query");
     if (path_cap < 0 || (path_cap > 0 && !path_ids)) return fail(APSP_E_INVALID, "apsp_query: bad path buffer");
     int32_t si, sj;
     if (!lookup(g, i, &si) || !lookup(g, j, &sj)) return fail(APSP_E_NOT_FOUND, "apsp_query: id is not live");
@@ -694,6 +711,7 @@ apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32
 apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32_t *on_ids, int32_t on_cap,
                              int32_t *on_len, int32_t *key_ids, int32_t key_cap, int32_t *key_len) {
     if (!g || !dist || !on_len || !key_len) return fail(APSP_E_INVALID, "apsp_query_nodes: NULL argument");
+    if (g->detached) return detached_error("apsp_query_nodes");
     if (on_cap < 0 || (on_cap > 0 && !on_ids) || key_cap < 0 || (key_cap > 0 && !key_ids))
         return fail(APSP_E_INVALID, "apsp_query_nodes: bad output buffer");
     int32_t si, sj;
@@ -733,6 +751,7 @@ apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
 
 apsp_status apsp_read_matrix(apsp_graph *g, int32_t *out_dev, int64_t out_ld) {
     if (!g) return fail(APSP_E_INVALID, "apsp_read_matrix: NULL graph");
+    if (g->detached) return detached_error("apsp_read_matrix");
     if (g->n_live > 0 && (!out_dev || out_ld < g->n_live)) return fail(APSP_E_INVALID, "apsp_read_matrix: bad output");
     launch_gather_compact(g->dg.D, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->stream);
     return check_launch("apsp_read_matrix");
@@ -740,6 +759,7 @@ apsp_status apsp_read_matrix(apsp_graph *g, int32_t *out_dev, int64_t out_ld) {
 
 apsp_status apsp_read_adjacency(apsp_graph *g, int32_t *out_dev, int64_t out_ld) {
     if (!g) return fail(APSP_E_INVALID, "apsp_read_adjacency: NULL graph");
+    if (g->detached) return detached_error("apsp_read_adjacency");
     if (g->n_live > 0 && (!out_dev || out_ld < g->n_live))
         return fail(APSP_E_INVALID, "apsp_read_adjacency: bad output");
     launch_gather_compact(g->dg.A, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->stream);
@@ -768,6 +788,7 @@ apsp_status apsp_node_ids(const apsp_graph *g, int32_t *ids, int32_t cap, int32_
 
 apsp_status apsp_edge_scope(apsp_graph *g, int32_t u, int32_t v, int32_t *r_count, int32_t *c_count) {
     if (!g || !r_count || !c_count) return fail(APSP_E_INVALID, "apsp_edge_scope: NULL argument");
+    if (g->detached) return detached_error("apsp_edge_scope");
     if (u == v) return fail(APSP_E_INVALID, "apsp_edge_scope: u == v");
     int32_t su, sv;
     if (!lookup(g, u, &su) || !lookup(g, v, &sv)) return fail(APSP_E_NOT_FOUND, "apsp_edge_scope: id is not live");
@@ -783,6 +804,7 @@ apsp_status apsp_edge_scope(apsp_graph *g, int32_t u, int32_t v, int32_t *r_coun
 
 apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
     if (!g || !out) return fail(APSP_E_INVALID, "apsp_last_stats: NULL argument");
+    if (g->detached) return detached_error("apsp_last_stats");
     apsp_status st = read_ctl(g);
     if (st) return st;
     const Ctl &c = *g->ctl_h;
@@ -813,6 +835,7 @@ apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
 
 apsp_status apsp_sync(apsp_graph *g) {
     if (!g) return fail(APSP_E_INVALID, "apsp_sync: NULL graph");
+    if (g->detached) return detached_error("apsp_sync");
     apsp_status st = read_ctl(g);
     if (st) return st;
     if (g->ctl_h->err) {

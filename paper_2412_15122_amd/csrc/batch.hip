@@ -1,9 +1,9 @@
 // Batched updates over many graphs.
 //
 // Each update runs the same method as the single-graph kernels:
-//   add node     Corollaries corollary1 / corollary2 (new row / column over
-//                the new node's light edges) and Theorem theorem3 (relaxation)
-//   remove node  Corollary corollary3 mask, then Bellman-Ford recompute of
+//   add node     Corollaries 1 / 2 (new row / column over
+//                the new node's light edges) and Theorem 3 (relaxation)
+//   remove node  Corollary 3 mask, then Bellman-Ford recompute of
 //                the flagged entries of each row (one wavefront per row)
 //   edge update  decrease: relaxation through the new edge; increase: mask
 //                of the pairs that can use the edge, then the same recompute
@@ -153,7 +153,7 @@ __device__ __forceinline__ void add_setup(const DevGraph &g, const BatchGraph &b
 }
 
 // The new row over the 256 columns [cb, cb + 256): out[c] = min_t wo[t] +
-// D[t][c] (Corollary corollary1).  The 4 waves split p's out-list (ascending
+// D[t][c] (Corollary 1).  The 4 waves split p's out-list (ascending
 // weight; a wave stops once the next weight reaches every value it holds,
 // distances being >= 0); every unlisted t has wo[t] >= the list bound, so a
 // column at or below it is final, and the others take an exhaustive scan.
@@ -218,7 +218,7 @@ __device__ __forceinline__ void add_out_cols(const DevGraph &g, const BatchGraph
 }
 
 // The new column over rows [r0, r1) (directed graphs): in[r] = min_x D[r][x] (+)
-// wi[x] (Corollary corollary2), over p's light in-edges (at most 64, read
+// wi[x] (Corollary 2), over p's light in-edges (at most 64, read
 // once per wavefront: lane l of a 16-lane group holds entries l, l + 16,
 // l + 32, l + 48).  A wavefront takes 4 rows at a time, one per 16-lane
 // group, each lane's 4 gathers of the row in flight together; a row whose
@@ -287,7 +287,7 @@ __device__ __forceinline__ void add_prologue(const DevGraph &g, const BatchGraph
     __syncthreads();
 }
 
-// Theorem theorem3 over rows [r0, r1): D[i][j] = min(D[i][j], in[i] (+) out[j]).
+// Theorem 3 over rows [r0, r1): D[i][j] = min(D[i][j], in[i] (+) out[j]).
 // outv: the new row (LDS stage or global).
 template <int U>
 __device__ __forceinline__ void add_relax_rows(const DevGraph &g, const BatchGraph &bg, int32_t r0, int32_t r1, const uint32_t *outv) {

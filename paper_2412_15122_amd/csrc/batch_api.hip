@@ -251,6 +251,7 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
             const apsp_graph *g = graphs[i];
             if (!g) return fail(APSP_E_INVALID, "apsp_batch_run: NULL graph " + std::to_string(i));
             if (!seen.insert(g).second) return fail(APSP_E_INVALID, "apsp_batch_run: graph listed twice");
+            if (g->detached) return detached_error("apsp_batch_run");
             if (g->minimax != graphs[0]->minimax)
                 return fail(APSP_E_INVALID, "apsp_batch_run: the graphs of one batch must share the path kind");
             if (g->cap > BATCH_MAX_CAPACITY)
@@ -285,6 +286,7 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
         if (x.op == APSP_OP_ADD_NODE) {
             if (g->n_live > 0 && (!x.w_out_dev || (!und && !x.w_in_dev)))
                 return bad_item(log, t, APSP_E_INVALID, "weight vector is NULL");
+            if (g->max_id >= INT32_MAX - 1) return bad_item(log, t, APSP_E_CAPACITY, "the id range is used up");
             int32_t p;
             bool was_free = false;
             if (!g->free_slots.empty()) {

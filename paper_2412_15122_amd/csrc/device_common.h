@@ -430,7 +430,7 @@ __device__ inline RowTests row_tests(const DevGraph &g, const FusedArgs &fa, int
 // increase: D[i][u] + w_old + D[v][y], or the swapped term when undirected).
 // A recomputed entry can only go up from here, so an entry back at this value
 // is final, and one above it belongs to the refined set (Theorem
-// theo_algo12: every shortest path of that pair used k, or the edge).
+// Theorem 6: every shortest path of that pair used k, or the edge).
 __device__ inline uint32_t flagged_old(const FusedArgs &fa, const RowTests &rt, int32_t y) {
     const uint32_t o1 = rt.t1 ? cat(rt.a1, (uint32_t)fa.row1[y]) : INF;
     const uint32_t o2 = rt.t2 ? cat(rt.a2, (uint32_t)fa.row2[y]) : INF;
@@ -657,7 +657,7 @@ __device__ inline unsigned long long block_min_key(unsigned long long v, unsigne
 // found), out[3..] = path ids.  scratch holds 4 * P ints.
 //
 // Candidates (Algorithm 7): t with D[i][t] + D[t][j] == D[i][j], plus i
-// and j; by Theorem al_correct they contain every shortest i -> j path.
+// and j; by Theorem 5 they contain every shortest i -> j path.
 // The walk takes, from cur, the candidate b with the smallest id such that
 // A[cur][b] + D[b][j] == D[cur][j] (the edge starts a shortest path to j).
 // With weights >= 1 this yields the lexicographically smallest shortest

@@ -111,7 +111,7 @@ void launch_copy_square(int32_t *dst, const int32_t *src, int64_t ld, int32_t n,
 
 // Import of a known distance matrix: D[i][j] := src[i][j] for i, j < n,
 // checked against what the distance matrix of the loaded adjacency must
-// satisfy (Section 2): every entry in [0, INF], a zero diagonal, no entry
+// satisfy (Section 1): every entry in [0, INF], a zero diagonal, no entry
 // above its edge's weight (the edge alone is a path), and symmetry for an
 // undirected graph.  Each failing entry adds one to *bad (one atomic per
 // wave); an entry outside [0, INF] is stored as INF.

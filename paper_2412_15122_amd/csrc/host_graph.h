@@ -129,6 +129,10 @@ struct apsp_graph {
     uint8_t *marks = nullptr;
     int32_t *partials = nullptr;
     int32_t epoch = 0;
+    // set by apsp_graph_detach (the device buffer is no longer the graph's),
+    // cleared by apsp_graph_relocate; every call that would touch device
+    // memory refuses a detached graph
+    int32_t detached = 0;
     // host bookkeeping
     int32_t n_live = 0, max_id = -1;
     std::vector<int32_t> live_ids;  // ascending
@@ -170,6 +174,13 @@ inline int32_t rank_of(const apsp_graph *g, int32_t id) {
     auto it = std::lower_bound(g->live_ids.begin(), g->live_ids.end(), id);
     if (it == g->live_ids.end() || *it != id) return -1;
     return (int32_t)(it - g->live_ids.begin());
+}
+
+// The error every device-touching call returns for a detached graph.
+inline apsp_status detached_error(const char *who) {
+    return fail(APSP_E_INVALID, std::string(who) +
+                                    ": the graph is detached from device memory (apsp_graph_detach); "
+                                    "apsp_graph_relocate gives it a buffer again");
 }
 
 inline bool lookup(const apsp_graph *g, int32_t id, int32_t *slot) {

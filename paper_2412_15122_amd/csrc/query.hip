@@ -1,4 +1,4 @@
-// Warm single-pair queries: the path (Section 3, Algorithm 7; for minimax
+// Warm single-pair queries: the path (Section 4, Algorithm 7; for minimax
 // graphs a search over edges no heavier than the distance), the nodes on
 // some / on every shortest path (Algorithms 8 and 10), matrix read-out, and
 // the edge scope count.
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(1024) void k_qb_emit_marked(DevGraph g, const int32
 
 // ---- nodes on some / on every shortest path of a pair ----------------------
 // (Algorithms 7 and 8 give the candidates and the paths through them,
-// Theorem al_correct; Algorithm 10 intersects the pair's shortest paths.)
+// Theorem 5; Algorithm 10 intersects the pair's shortest paths.)
 //
 // Levels: L[t] = D[i][t].  Along a tight edge x -> y (both candidates,
 // L[x] + A[x][y] == L[y]) the level does not fall, and the tight walks from

@@ -123,7 +123,7 @@ void launch_nin_rebuild_queue(const DevGraph &g, const int32_t *queue, hipStream
 }
 
 // ---------------------------------------------------------------------------
-// add node (Section 2.1)
+// add node (Section 3.1)
 // ---------------------------------------------------------------------------
 
 // wo[s] / wi[s]: the new node's out- / in-weight towards slot s (INF for
@@ -159,7 +159,7 @@ void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32
                                                            n_live, wo, wi);
 }
 
-// out[c] = min_t wo[t] (+) D[t][c]  (Corollary corollary1: SPD(p, c)).
+// out[c] = min_t wo[t] (+) D[t][c]  (Corollary 1: SPD(p, c)).
 // The new node's lightest out-edges come first (plist, ascending weight): a
 // column stops once the next weight reaches its current value (distances
 // are >= 0), and every unlisted t has wo[t] >= beta, so a column whose
@@ -219,7 +219,7 @@ void launch_add_out(const DevGraph &g, const int2 *plist, const int32_t *pcnt, c
     k_add_out<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, plist, pcnt, pbeta, wo, out);
 }
 
-// in[i] = min_r D[i][r] (+) wi[r]  (Corollary corollary2: SPD(i, p)), one wave
+// in[i] = min_r D[i][r] (+) wi[r]  (Corollary 2: SPD(i, p)), one wave
 // per row over the new node's light in-edges (its own index list, built
 // from wi), exhaustive when the row's value exceeds beta.  Directed only;
 // for an undirected graph in = out.
@@ -252,7 +252,7 @@ void launch_add_in(const DevGraph &g, int32_t p, const int32_t *wi, int32_t *in,
     k_add_in<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, p, wi, in);
 }
 
-// Theorem theorem3: D[i][j] = min(D[i][j], in[i] (+) out[j]) over the old
+// Theorem 3: D[i][j] = min(D[i][j], in[i] (+) out[j]) over the old
 // slots.  Block = 1024 columns x 8 rows; a row with in[i] = INF cannot change.
 // Every row's 16-byte load is issued (non-temporal: D is streamed once)
 // before any row is tested, so a lane has 8 loads in flight; the few changed
@@ -408,7 +408,7 @@ void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const in
 }
 
 // ---------------------------------------------------------------------------
-// edge update (Section 2.3), decided on the device
+// edge update (Section 3.3), decided on the device
 // ---------------------------------------------------------------------------
 
 // The decision (wave 0 of block 0: mode, old weight, the new weight in A,
@@ -434,7 +434,7 @@ void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int
 }
 
 // Decrease of u -> v to w (< D[u][v]).  Inserting a relay node on the edge
-// and applying Theorem theorem3 gives
+// and applying Theorem 3 gives
 //   D'[i][j] = min(D[i][j], D[i][u] (+) w (+) D[v][j])   (and v -> u if undirected).
 // Only rows with D[i][u] (+) w < D[i][v] can change.  The column / row vectors
 // were gathered before this launch, so in-place writes do not feed back.
@@ -493,10 +493,10 @@ __device__ __forceinline__ void dec_relax_tile(const DevGraph &g, const int32_t 
 // ---------------------------------------------------------------------------
 // One block per affected row i (blocks stride over rows).
 //   1. Stream row i once, flag column j when a pair test holds
-//        remove k:   D[i][k] (+) D[k][j] == D[i][j]          (Corollary corollary3)
+//        remove k:   D[i][k] (+) D[k][j] == D[i][j]          (Corollary 3)
 //        increase:   D[i][u] (+) w_old (+) D[v][j] == D[i][j]  (and v -> u if undirected)
 //      with j != i, D[i][j] < INF (j != k for a removal).  Unflagged entries
-//      keep their value in G' (Theorem theorem_spd_4); flagged ones start at
+//      keep their value in G' (Theorem 4); flagged ones start at
 //      INF in an LDS copy `cur` of the row, as does column k.
 //   2. Recompute the flagged entries on G' by Bellman-Ford relaxation
 //        cur[y] = min_x cur[x] (+) A'[x][y]

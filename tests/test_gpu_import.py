@@ -1,7 +1,7 @@
 """GPU parity of the warm start from a known distance matrix (apsp_import) and
 of growing a graph's capacity (apsp_grow).
 
-The paper's problem statement (Section 2) starts from a graph whose
+The paper's problem statement (Section 1) starts from a graph whose
 all-pairs shortest-path matrix is already known; apsp_import takes that
 matrix, here the oracle's, instead of running a cold start.  Every later
 result must equal the oracle run cold on the updated graph, bit for bit.

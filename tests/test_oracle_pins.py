@@ -133,8 +133,8 @@ def test_fw_invariants_bellman_unique(undirected):
 
 def apsp_by_repeated_add(A):
     """Cold APSP by adding nodes one at a time (the recursion the paper's
-    Algorithm 1 rests on): the new row by Theorem 'theorem2', the new column
-    by Theorem 'theo_2_back', old pairs by Theorem 'theorem3'.  Plain loops,
+    Algorithm 1 rests on): the new row by Theorem 1, the new column
+    by Theorem 2, old pairs by Theorem 3.  Plain loops,
     no shared code with the oracle."""
     n = A.shape[0]
     M = [[0]]
@@ -252,7 +252,7 @@ def test_edge_mask_is_edge_on_some_shortest_path(undirected):
 
 @pytest.mark.parametrize("undirected", [False, True])
 def test_masks_cover_every_changed_pair(undirected):
-    """Corollary 'corollary3' (soundness): pairs outside the mask keep their
+    """Corollary 3 (soundness): pairs outside the mask keep their
     distance.  Checked against a cold recompute, with ties and zero weights."""
     rng = np.random.default_rng(51)
     for trial in range(12):
@@ -331,7 +331,7 @@ def test_apply_update_semantics():
 
 
 # ---------------------------------------------------------------------------
-# the refined need_update list (Algorithms 11-12, Theorem theo_algo12)
+# the refined need_update list (Algorithms 11-12, Theorem 6)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("undirected", [False, True])
@@ -507,7 +507,7 @@ def test_minimax_undirected_equals_spanning_tree_bottleneck():
 
 
 def test_minimax_removal_mask_holds_every_change():
-    """Corollary corollary3 with max: pairs outside the minimax mask of k keep
+    """Corollary 3 with max: pairs outside the minimax mask of k keep
     their distance when k is removed."""
     rng = np.random.default_rng(81)
     for trial in range(20):
