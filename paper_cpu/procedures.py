@@ -1,7 +1,7 @@
 """The paper's own warm-start procedures on the CPU -- TEST AND BENCHMARK
 INFRASTRUCTURE ONLY.
 
-Thin ctypes wrappers over ``paper_cpu.c`` (one thread, the steps of
+Thin ctypes wrappers over ``procedures.c`` (one thread, the steps of
 Algorithms 5, 6, 7 and 11 in the paper's order, with textbook Floyd-Warshall
 and dense Dijkstra as the cold starts they are compared with).  Only `tests/`
 and the benchmark's CPU baseline leg use it; it shares no code with the HIP
@@ -20,7 +20,7 @@ import numpy as np
 INF = 1 << 30
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "paper_cpu.c")
+_SRC = os.path.join(_HERE, "procedures.c")
 _LIB = os.path.join(_HERE, "libpaper_cpu.so")
 _lib = None
 

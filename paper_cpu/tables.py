@@ -1,6 +1,7 @@
 """Re-run of the paper's warm/cold time ratios (its Experiments I-IV, Tables
-1-4) with the CPU procedures of paper_cpu.c, one thread each, on the host
-that runs it.  Test and benchmark infrastructure, like the rest of oracle/.
+1-4) with the CPU procedures of procedures.c, one thread each, on the host
+that runs it.  Benchmark infrastructure: it shares no code with the HIP
+library and does not use the oracle (its cold starts are procedures.c's own).
 
 Workload: undirected complete graphs with symmetric weights uniform on
 [1, wmax] (10000 by default; the paper does not state its weights), a random node removed
@@ -11,7 +12,7 @@ warm branch always; the paper's delta is not stated), so the ratio measures
 the warm procedure itself; the mean Cost is reported beside it.  Every warm
 result is checked against its cold counterpart.
 
-    python -m oracle.paper_tables --sizes 1000,2000,3000 --repeats 5
+    python -m paper_cpu.tables --sizes 1000,2000,3000 --repeats 5
 """
 from __future__ import annotations
 
@@ -22,8 +23,7 @@ import sys
 
 import numpy as np
 
-from . import oracle as O
-from . import paper_cpu as PC
+from . import procedures as PC
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 from paper_2412_15122_amd import workloads as W  # noqa: E402  (seeded generators only)
@@ -34,7 +34,7 @@ def one_size(n: int, repeats: int, queries: int, seed: int, wmax: int) -> dict:
     r_rm, r_ed, r_q, r_key, costs, refined = [], [], [], [], [], []
     for rep in range(repeats):
         A = W.symmetric_complete_graph(n, 1, wmax, seed=int(rng.integers(1 << 30)))
-        D = O.fw(A)
+        D, _ = PC.fw(A)
         # Experiment I and IV: remove a random node
         k = int(rng.integers(n))
         keep = [x for x in range(n) if x != k]

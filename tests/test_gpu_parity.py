@@ -236,13 +236,16 @@ def test_edge_decrease_noop_and_rows():
     expect_equal(g, A, ids)
 
 
-def test_edge_scope_matches_oracle():
-    adj = W.random_graph(130, 1, 6, undirected=True, seed=41)
-    g = lib_graph(adj, True)
+@pytest.mark.parametrize("undirected", [True, False])
+def test_edge_scope_matches_oracle(undirected):
+    adj = W.random_graph(130, 1, 6, undirected=undirected, seed=41)
+    g = lib_graph(adj, undirected)
     D = O.fw(adj)
-    for (u, v) in ((0, 1), (5, 99), (64, 65), (127, 128)):
+    if not undirected:
+        assert not np.array_equal(D, D.T)
+    for (u, v) in ((0, 1), (1, 0), (5, 99), (99, 5), (64, 65), (127, 128)):
         w = int(adj[u, v])
-        assert g.edge_scope(u, v) == O.edge_scope(D[:, u], D[:, v], D[u, :], D[v, :], w)
+        assert g.edge_scope(u, v) == O.edge_scope(D[:, u], D[:, v], D[u, :], D[v, :], w), (u, v)
 
 
 # ---------------------------------------------------------------------------

@@ -312,6 +312,33 @@ def test_edge_scope_counts():
         assert Fe.sum() <= R * C
 
 
+@pytest.mark.parametrize("undirected", [False, True])
+def test_edge_scope_by_brute_force(undirected):
+    """|R| and |C| against their meaning, by enumerating every shortest simple
+    path on small graphs: R = the sources i with some shortest i->v path whose
+    last edge is u->v, C = the targets j with some shortest u->j path whose
+    first edge is u->v.  On a directed graph D is not symmetric, so a row read
+    where a column belongs (or the reverse) changes the counts."""
+    rng = np.random.default_rng(72 + undirected)
+    checked = 0
+    for trial in range(14):
+        n = 5 + trial % 3
+        A = rand_graph(rng, n, [2, 4, 9][trial % 3], undirected=undirected, density=0.75)
+        D = O.fw(A)
+        for u in range(n):
+            for v in range(n):
+                if u == v or A[u, v] >= INF:
+                    continue
+                w = int(A[u, v])
+                R = sum(1 for i in range(n)
+                        if any(p[-2:] == (u, v) for p in O.all_shortest_simple_paths(A, i, v)))
+                C = sum(1 for j in range(n)
+                        if any(p[:2] == (u, v) for p in O.all_shortest_simple_paths(A, u, j)))
+                assert O.edge_scope(D[:, u], D[:, v], D[u, :], D[v, :], w) == (R, C), (trial, u, v)
+                checked += 1
+    assert checked > 100
+
+
 # ---------------------------------------------------------------------------
 # the updated graph G'
 # ---------------------------------------------------------------------------

@@ -1,5 +1,5 @@
 """The paper's own warm-start procedures on the CPU (Algorithms 5, 6, 7, 11;
-oracle/paper_cpu.c), pinned to the oracle: every result equals the oracle's
+paper_cpu/procedures.c), pinned to the oracle: every result equals the oracle's
 cold Floyd-Warshall of the updated graph, on both branches of the delta test;
 Phi and Cost equal the need_update_list's by definition; Algorithm 11's list
 lies inside Algorithm 5's and still holds every pair whose distance changes;
@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from oracle import paper_cpu as PC
+from paper_cpu import procedures as PC
 from paper_2412_15122_amd import workloads as W
 
 INF = W.INF
