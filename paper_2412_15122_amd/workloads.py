@@ -27,6 +27,9 @@ import numpy as np
 INF = 1 << 30
 
 ADD, REMOVE, DECREASE, INCREASE = "add", "remove", "decrease", "increase"
+# edge updates that cross INF: an existing edge removed (its weight set to INF)
+# and an absent edge inserted with a finite weight
+DELETE, INSERT = "delete", "insert"
 
 _SEED_BASE = 2412151220
 
@@ -90,7 +93,7 @@ def symmetric_complete_graph(n: int, wmin: int, wmax: int, seed) -> np.ndarray:
 class Update:
     """One update of the stream.
 
-    kind      ADD | REMOVE | DECREASE | INCREASE
+    kind      ADD | REMOVE | DECREASE | INCREASE | DELETE | INSERT
     u, v      edge endpoints (ids) for edge updates; u = id for REMOVE
     w         new edge weight for edge updates
     old       weight of the edge before the update (edge updates)
@@ -188,6 +191,16 @@ def _pick_edge(rng, st: GraphState) -> Tuple[int, int, int]:
     raise RuntimeError("no edge found")
 
 
+def _pick_absent_edge(rng, st: GraphState) -> Tuple[int, int]:
+    """A random absent edge u->v (u != v, weight INF) between live nodes."""
+    for _ in range(10000):
+        u, v = rng.choice(len(st.live), size=2, replace=False)
+        u, v = st.live[int(u)], st.live[int(v)]
+        if st.weight(u, v) >= INF:
+            return u, v
+    raise RuntimeError("no absent edge found")
+
+
 def _draw_weights(rng, m: int, wmin: int, wmax: int, density: float) -> np.ndarray:
     w = rng.integers(wmin, wmax + 1, size=m, dtype=np.int32)
     if density < 1.0:
@@ -199,7 +212,8 @@ def make_update(rng, st: GraphState, kind: str, *, wmin: int, wmax: int,
                 inc_max: int, density: float = 1.0) -> Update:
     """Draw one update of `kind` against the current state and apply it to the
     bookkeeping.  Decrease: new weight uniform on [1, old] (0 stays 0); increase: uniform on
-    [old, max(old, inc_max)]."""
+    [old, max(old, inc_max)]; delete: an existing edge set to INF; insert: an
+    absent edge given a weight uniform on [wmin, wmax]."""
     if kind == ADD:
         m = len(st.live)
         w_out = _draw_weights(rng, m, wmin, wmax, density)
@@ -210,8 +224,15 @@ def make_update(rng, st: GraphState, kind: str, *, wmin: int, wmax: int,
         k = st.live[int(rng.integers(0, len(st.live)))]
         st.remove(k)
         return Update(REMOVE, u=k)
+    if kind == INSERT:
+        u, v = _pick_absent_edge(rng, st)
+        w = int(rng.integers(wmin, wmax + 1))
+        st.set_weight(u, v, w)
+        return Update(kind, u=u, v=v, w=w, old=INF)
     u, v, old = _pick_edge(rng, st)
-    if kind == DECREASE:
+    if kind == DELETE:
+        w = INF
+    elif kind == DECREASE:
         w = int(rng.integers(min(1, old), old + 1))   # a zero-weight edge stays 0
     elif kind == INCREASE:
         w = int(rng.integers(old, max(old, inc_max) + 1))

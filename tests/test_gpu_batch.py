@@ -3,8 +3,9 @@
 Every graph's state after its queued items equals the one-call-per-update
 path on a clone of the same graph (D, adjacency and ids, bit-exact); the
 query answers equal the single-call query at the same point of the queue;
-graphs of up to 400 nodes are also checked against the oracle's cold
-Floyd-Warshall of their final adjacency.  Sizes are uneven and include tiny
+every graph's final state is also checked against the oracle's cold
+Floyd-Warshall of its final adjacency (the 8300-node graph on one row per
+128-row band, by the oracle's Dijkstra).  Sizes are uneven and include tiny
 graphs (1 node, empty after a removal), n <= 143 and n just above a
 128-slot pitch.  A rejected batch changes no graph.
 """
@@ -74,6 +75,20 @@ def make_case(sizes, undirected_every=0, seed=7, updates=8, queries=True):
     return graphs, states, items
 
 
+def final_adjacency(adj, items, undirected):
+    """The oracle's adjacency and ids after one graph's queued items."""
+    A, ids = adj, list(range(adj.shape[0]))
+    for it in items:
+        if it[0] == "add":
+            A, ids = O.apply_update(A, ids, "add", w_out=it[2], w_in=it[2] if undirected else it[3],
+                                    undirected=undirected)
+        elif it[0] == "remove":
+            A, ids = O.apply_update(A, ids, "remove", u=it[2], undirected=undirected)
+        elif it[0] == "edge":
+            A, ids = O.apply_update(A, ids, "edge", u=it[2], v=it[3], w=it[4], undirected=undirected)
+    return A, ids
+
+
 def build(graphs):
     from paper_2412_15122_amd.apsp import Graph
     out = []
@@ -125,10 +140,9 @@ def run_and_compare(sizes, config, undirected_every=0, seed=7, check_oracle=True
         assert res[t].get() == ans, f"query item {t}"
     if check_oracle:
         for gi, st in enumerate(states):
-            if sizes[gi] <= 400:
-                A = st.dense()
-                assert ga[gi].ids() == st.live
-                assert np.array_equal(ga[gi].matrix(), O.fw(A, threads=THREADS)), f"oracle graph {gi}"
+            A = st.dense()
+            assert ga[gi].ids() == st.live
+            assert np.array_equal(ga[gi].matrix(), O.fw(A, threads=THREADS)), f"oracle graph {gi}"
     b.close()
     for g in ga + gb:
         g.close()
@@ -247,6 +261,9 @@ def test_config4_shape_sample():
     for gi in range(len(ga)):
         assert_same(ga[gi], gb[gi], f"graph {gi} n={wls[gi].adj.shape[0]}")
         assert_same(gc[gi], gb[gi], f"lockstep graph {gi} n={wls[gi].adj.shape[0]}")
+        A, ids = final_adjacency(wls[gi].adj, [it for it in items if it[1] == gi], False)
+        assert gc[gi].ids() == ids
+        assert np.array_equal(gc[gi].matrix(), O.fw(A, threads=THREADS)), f"oracle graph {gi}"
 
 
 def test_lockstep_large_pitch_heavy_rows_tiny_index():
@@ -289,6 +306,14 @@ def test_lockstep_large_pitch_heavy_rows_tiny_index():
     for gi in range(len(ga)):
         assert_same(ga[gi], gb[gi], f"graph {gi} n0={sizes[gi]}")
         ga[gi].sync()
+        A, ids = final_adjacency(adjs[gi], [it for it in items if it[1] == gi], False)
+        assert ga[gi].ids() == ids
+        if sizes[gi] <= 2048:
+            assert np.array_equal(ga[gi].matrix(), O.fw(A, threads=THREADS)), f"oracle graph {gi}"
+        else:
+            pos = [min(len(ids) - 1, b + int(rng.integers(128))) for b in range(0, len(ids), 128)]
+            ref = O.dijkstra_rows(A, pos, threads=THREADS)
+            assert np.array_equal(ga[gi].matrix_device("D")[pos].cpu().numpy(), ref), f"oracle graph {gi}"
     b.close()
     for g in ga + gb:
         g.close()

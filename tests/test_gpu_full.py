@@ -5,11 +5,12 @@ against the GPU cold blocked Floyd-Warshall of the updated graph and on
 sampled rows against the oracle's Dijkstra; the cold start is checked in full
 against the oracle's Floyd-Warshall.
 
-n = 16384 (undirected complete, the benchmark graph): the cold start on
-sampled rows against the oracle's Dijkstra; a block of the benchmark's update
+n = 16384 (undirected complete, the benchmark graph): the cold start on one
+row of every 128-row band against the oracle's Dijkstra; a block of the benchmark's update
 stream, led by the worst-case increase (selected by the oracle), each update
-checked in full against the GPU cold start of the updated graph and, at
-checkpoints, on sampled rows against the oracle.  The light-edge scopes the
+checked in full against the GPU cold start of the updated graph and on
+sampled rows against the oracle (at two checkpoints, one row per 128-row
+band).  The light-edge scopes the
 benchmark uses to pick that edge are checked against the oracle too, and so
 are the final graph's pair node sets on sampled pairs.
 """
@@ -50,6 +51,12 @@ def check_rows(g, A, ids, rows, what):
     D = g.matrix_device("D")
     got = D[pos].cpu().numpy()
     assert np.array_equal(got, ref), what
+
+
+def band_rows(rng, ids, band=128):
+    """One id from every band of `band` consecutive live positions."""
+    n = len(ids)
+    return [ids[min(n - 1, b + int(rng.integers(band)))] for b in range(0, n, band)]
 
 
 def test_directed_n4096_every_update_kind():
@@ -104,7 +111,9 @@ def test_undirected_n16384_benchmark_stream():
     log("cold start n=16384")
     rng = np.random.default_rng(16384)
     ids = list(range(n))
-    check_rows(g, adj, ids, [int(x) for x in rng.integers(0, n, size=12)] + [0, n - 1], "cold")
+    # one row in every 128-row band (the cold start's tile bands), at a seeded
+    # offset, plus the first and last rows; undirected, so rows are columns too
+    check_rows(g, adj, ids, band_rows(rng, ids) + [0, n - 1], "cold")
 
     cands = W.lightest_edges(adj, 64, True)
     (wu, wv), scopes = oracle_worst_edge(adj, cands)
@@ -133,7 +142,10 @@ def test_undirected_n16384_benchmark_stream():
             s = g.stats()
             assert s["kind"] == 4 and s["flagged"] > 0  # the worst-case edge was tight
         assert gpu_cold_equal(g, True), (t, upd.kind)
-        if t % 10 == 0 or upd.kind == W.REMOVE:
+        if t in (len(block) // 2, len(block) - 1):
+            # checkpoints: one row per 128-row band of the live order
+            check_rows(g, A, ids, touched + band_rows(rng, ids), f"checkpoint {t} {upd.kind}")
+        elif t % 10 == 0 or upd.kind == W.REMOVE:
             sample = touched + [ids[int(x)] for x in rng.integers(0, len(ids), size=4)]
             check_rows(g, A, ids, sample, f"update {t} {upd.kind}")
     g.sync()

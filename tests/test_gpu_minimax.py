@@ -197,7 +197,7 @@ def test_minimax_batch_equals_single_calls(config):
     import torch
     rng = np.random.default_rng(31 + config["variant"])
     sizes = [1, 3, 40, 143, 300, 129, 700]
-    ga, states, per = [], [], []
+    ga, states, per, snap = [], [], [], {}
     for gi, n in enumerate(sizes):
         und = gi % 2 == 1
         wmax = (6, 5000)[gi % 3 == 0]
@@ -222,6 +222,7 @@ def test_minimax_batch_equals_single_calls(config):
             if len(st.live) >= 2 and t % 2 == 1:
                 a, c = rng.choice(len(st.live), size=2, replace=False)
                 seq.append(("query", gi, st.live[int(a)], st.live[int(c)]))
+                snap[(gi, len(seq) - 1)] = (st.dense(), list(st.live))
         states.append(st)
         per.append(seq)
     items = [it for t in range(max(map(len, per))) for seq in per if t < len(seq) for it in [seq[t]]]
@@ -248,6 +249,24 @@ def test_minimax_batch_equals_single_calls(config):
         assert np.array_equal(ga[gi].matrix(), O.minimax_apsp(states[gi].dense())), gi
     for t, d in answers.items():
         assert res[t].get()[0] == d, t
+    # every batched path, by property on the oracle's graph when it was asked
+    at = {}
+    for t, it in enumerate(items):
+        k = at.get(it[1], 0)
+        at[it[1]] = k + 1
+        if it[0] != "query":
+            continue
+        A, ids = snap[(it[1], k)]
+        a, c = ids.index(it[2]), ids.index(it[3])
+        d = int(O.minimax_rows(A, [a])[0][c])
+        dist, path = res[t].get()
+        assert dist == d, t
+        if d >= INF:
+            assert path == [], t
+            continue
+        pos = [ids.index(x) for x in path]
+        assert pos[0] == a and pos[-1] == c and len(set(pos)) == len(pos), t
+        assert max((int(A[x, y]) for x, y in zip(pos, pos[1:])), default=0) == d, t
     b.close()
     for g in ga + gb:
         g.close()

@@ -84,7 +84,8 @@ def test_config1_sequence():
 # random update sequences
 # ---------------------------------------------------------------------------
 
-def random_sequence(seed, n, undirected, steps, wmax, density=1.0, zero=0.0, limit=None, cap_extra=12):
+def random_sequence(seed, n, undirected, steps, wmax, density=1.0, zero=0.0, limit=None, cap_extra=12,
+                    inf_edges=False):
     rng = np.random.default_rng(seed)
     adj = W.random_graph(n, 1, wmax, undirected=undirected, density=density,
                          seed=int(rng.integers(1 << 30)), zero_frac=zero)
@@ -95,8 +96,8 @@ def random_sequence(seed, n, undirected, steps, wmax, density=1.0, zero=0.0, lim
     A, ids = adj.copy(), list(range(n))
     expect_equal(g, A, ids, "cold")
     for step in range(steps):
-        kinds = [W.ADD, W.REMOVE, W.DECREASE, W.INCREASE]
-        kind = kinds[int(rng.integers(4))]
+        kinds = [W.ADD, W.REMOVE, W.DECREASE, W.INCREASE] + ([W.DELETE, W.INSERT] * 2 if inf_edges else [])
+        kind = kinds[int(rng.integers(len(kinds)))]
         if len(st.live) <= 2 and kind == W.REMOVE:
             kind = W.ADD
         if len(ids) >= n + cap_extra and kind == W.ADD:
@@ -111,6 +112,15 @@ def random_sequence(seed, n, undirected, steps, wmax, density=1.0, zero=0.0, lim
 @pytest.mark.parametrize("n,wmax,density", [(40, 20, 1.0), (150, 1000, 1.0), (200, 5, 0.5), (331, 10000, 0.95)])
 def test_random_sequences(n, wmax, density, undirected):
     random_sequence(1000 + n + undirected, n, undirected, 14, wmax, density)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+@pytest.mark.parametrize("density", [0.95, 0.5])
+def test_random_sequences_delete_and_insert_edges(density, undirected):
+    """Edge updates that cross INF: an existing edge deleted (set to INF) and
+    an absent edge inserted, mixed with every other kind."""
+    random_sequence(5000 + int(100 * density) + undirected, 170, undirected, 24, 200, density,
+                    inf_edges=True)
 
 
 @pytest.mark.parametrize("undirected", [False, True])

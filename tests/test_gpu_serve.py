@@ -74,8 +74,41 @@ def check_against_alone(srv, adjs, reqs, minimax=False):
             assert r.result == results[r.rid], (r.rid, r.kind)
         elif r.kind == "query":     # minimax: a batch and a single call may pick different optimal paths
             assert r.result[0] == results[r.rid][0], r.rid
+    if minimax:
+        check_minimax_paths(adjs, reqs)
     for g in alone:
         g.close()
+
+
+def check_minimax_paths(adjs, reqs):
+    """Every served minimax path, by property on the oracle's graph at the
+    time of the query (each graph's requests replayed in arrival order): it
+    runs from i to j over existing edges without repeating a node, and its
+    largest edge weight is the oracle's minimax distance."""
+    state = [(a, list(range(a.shape[0]))) for a in adjs]
+    checked = 0
+    for r in sorted(reqs, key=lambda r: r.arrival):
+        A, ids = state[r.graph]
+        if r.kind == "add":
+            state[r.graph] = O.apply_update(A, ids, "add", w_out=r.args[0], w_in=r.args[1])
+        elif r.kind == "remove":
+            state[r.graph] = O.apply_update(A, ids, "remove", u=r.args[0])
+        elif r.kind == "query":
+            a, b = ids.index(r.args[0]), ids.index(r.args[1])
+            d = int(O.minimax_rows(A, [a])[0][b])
+            dist, path = r.result
+            assert dist == d, r.rid
+            if d >= W.INF:
+                assert path == [], r.rid
+                continue
+            pos = [ids.index(x) for x in path]
+            assert pos[0] == a and pos[-1] == b and len(set(pos)) == len(pos), r.rid
+            assert all(A[x, y] < W.INF for x, y in zip(pos, pos[1:])), r.rid
+            assert max((int(A[x, y]) for x, y in zip(pos, pos[1:])), default=0) == d, r.rid
+            checked += 1
+        else:
+            state[r.graph] = O.apply_update(A, ids, "edge", u=r.args[0], v=r.args[1], w=r.args[2])
+    assert checked > 0
 
 
 @pytest.mark.parametrize("schedule,small", [("lockstep", 0), ("lockstep", 8), ("hybrid", 0)])
@@ -146,7 +179,9 @@ def test_plain_server_matches_too():
 def test_minimax_graphs_served_equal_alone():
     """The server over minimax graphs (lockstep batches of the minimax
     kernels): matrices, ids and new ids equal the single calls exactly,
-    query distances too; final states equal the oracle's minimax matrices."""
+    query distances too, and every served path is a minimax path of the
+    graph at its time (by property); final states equal the oracle's minimax
+    matrices."""
     from paper_2412_15122_amd import serve
     sizes = [60, 200, 33, 150]
     adjs, gen, reqs = graphs_and_requests(sizes, rate=20000.0, count=300, seed=53)
