@@ -222,6 +222,26 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id);
  * device: the call never waits. */
 apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * update as apsp_update_edge, with the same kernels and bit for bit the
+ * same results, but its working memory (the gathered columns and rows, the
+ * flag bitmap, row marks, heavy-row scratch and recompute partials, which
+ * apsp_update_edge keeps in the graph's buffer) is a static array inside
+ * the library, apsp_noalloc_scratch_bytes() bytes on every device the
+ * library runs on, held until the process ends.  The call allocates
+ * nothing (no hipMalloc, hipHostMalloc or event creation; profiling is off
+ * for it) and clears the parts that must start at zero with fill kernels.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (another stream, another thread) race and give undefined
+ * results; calls ordered on one stream are safe.  Graphs of capacity above
+ * APSP_NOALLOC_MAX_CAPACITY get APSP_E_CAPACITY (nothing enqueued); other
+ * errors as apsp_update_edge. */
+#define APSP_NOALLOC_MAX_CAPACITY 4224
+apsp_status apsp_update_edge_noalloc(apsp_graph *g, int32_t u, int32_t v, int32_t w);
+/* Bytes of the static working-memory array of apsp_update_edge_noalloc (per device). */
+size_t apsp_noalloc_scratch_bytes(void);
+
 /* ---- queries (synchronous) ------------------------------------------------ */
 
 /* Shortest path from i to j (Algorithm 7, Section 4): *dist = D[i][j]; the

@@ -29,6 +29,7 @@ APSP_FALLBACK_COST = 1
 APSP_FALLBACK_ALWAYS = 2
 APSP_MAX_CAPACITY = 38272
 APSP_BATCH_MAX_CAPACITY = 16384
+APSP_NOALLOC_MAX_CAPACITY = 4224
 APSP_OP_ADD_NODE = 1
 APSP_OP_REMOVE_NODE = 2
 APSP_OP_UPDATE_EDGE = 3
@@ -98,6 +99,8 @@ SIGNATURES = {
     "apsp_add_node": (_I32, [_P, _P, _P, _PI32]),
     "apsp_remove_node": (_I32, [_P, _I32]),
     "apsp_update_edge": (_I32, [_P, _I32, _I32, _I32]),
+    "apsp_update_edge_noalloc": (_I32, [_P, _I32, _I32, _I32]),
+    "apsp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "apsp_query": (_I32, [_P, _I32, _I32, _PI32, _PI32, _I32, _PI32]),
     "apsp_query_nodes": (_I32, [_P, _I32, _I32, _PI32, _PI32, _I32, _PI32, _PI32, _I32, _PI32]),
     "apsp_read_matrix": (_I32, [_P, _P, _I64]),

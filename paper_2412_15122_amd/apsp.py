@@ -268,6 +268,11 @@ class Graph:
     def update_edge(self, u: int, v: int, w: int) -> None:
         N.check(self._lib.apsp_update_edge(self._h, int(u), int(v), int(w)), "apsp_update_edge")
 
+    def update_edge_noalloc(self, u: int, v: int, w: int) -> None:
+        """update_edge with the library's static working memory (no device
+        allocation; capacity <= APSP_NOALLOC_MAX_CAPACITY)."""
+        N.check(self._lib.apsp_update_edge_noalloc(self._h, int(u), int(v), int(w)), "apsp_update_edge_noalloc")
+
     def recompute_cold(self) -> None:
         N.check(self._lib.apsp_recompute_cold(self._h), "apsp_recompute_cold")
 

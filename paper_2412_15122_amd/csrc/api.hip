@@ -248,6 +248,67 @@ apsp_status finish_graph(apsp_graph *g, int32_t n, const int32_t *ids) {
 // C ABI
 // ---------------------------------------------------------------------------
 
+// The edge update over given working memory (the public entry points below
+// pass the graph's own or the library's static array).
+apsp_status apsp_host::check_edge_args(apsp_graph *g, const char *who, int32_t u, int32_t v, int32_t w, int32_t *su,
+                                       int32_t *sv) {
+    if (!g) return fail(APSP_E_INVALID, std::string(who) + ": NULL graph");
+    if (g->detached) return detached_error(who);
+    if (w < 0 || (uint32_t)w > INF) return fail(APSP_E_INVALID, std::string(who) + ": weight outside [0, APSP_INF]");
+    if (u == v) return fail(APSP_E_INVALID, std::string(who) + ": u == v");
+    if (!lookup(g, u, su) || !lookup(g, v, sv)) return fail(APSP_E_NOT_FOUND, std::string(who) + ": id is not live");
+    return APSP_OK;
+}
+
+apsp_status apsp_host::update_edge_with(apsp_graph *g, const char *who, int32_t u, int32_t v, int32_t w,
+                                        const EdgeScratch &sc) {
+    int32_t su, sv;
+    if (apsp_status bad = check_edge_args(g, who, u, v, w, &su, &sv)) return bad;
+    hipStream_t s = g->stream;
+    DevGraph &d = g->dg;
+    const int32_t n_before = g->n_live;
+    g->prof.begin(KID_EDGE_BEGIN);
+    launch_edge_begin(d, su, sv, w, sc.colu, sc.colv, sc.rowu, sc.rowv, s);
+    g->prof.end();
+    FusedArgs fa{};
+    fa.mode = FUSED_INCREASE;
+    fa.k = -1;
+    fa.scratch = sc.fscratch;
+    fa.heavy_rows = sc.heavy_rows;
+    fa.heavy_epoch = sc.heavy_epoch;
+    fa.flag_bits = sc.flag_bits;
+    fa.row_bits = sc.row_bits;
+    fa.marks = sc.marks;
+    fa.mark_pitch = mark_pitch(g->P);
+    fa.partials = sc.partials;
+    fa.epoch = sc.epoch;
+    fa.col1 = sc.colu;
+    fa.col2 = sc.colv;
+    fa.row1 = sc.rowv;
+    fa.row2 = sc.rowu;
+    g->prof.begin(KID_EDGE_SWEEP);
+    SR(g, launch_edge_sweep)(d, fa, w, s);
+    g->prof.end();
+    int32_t fallback = 0;
+    apsp_status st;
+    if (g->policy != APSP_FALLBACK_NEVER) {
+        if ((st = read_ctl(g))) return st;
+        if (g->ctl_h->edge_mode == EDGE_INCREASE && (st = decide_fallback(g, &fa, n_before, &fallback))) return st;
+    }
+    g->prof.begin(KID_FUSED);
+    const int32_t rblocks = SR(g, launch_mask_recompute)(d, fa, fallback, s);
+    g->prof.end();
+    if (fallback && (st = run_cold(g))) return st;
+    g->prof.begin(KID_NIN_BUILD);
+    launch_edge_finish(d, sv, g->kind == APSP_UNDIRECTED ? su : -1, sc.partials, rblocks, s);
+    g->prof.end();
+    if ((st = check_launch(who))) return st;
+    g->last_n_before = n_before;
+    g->last_fallback = fallback;
+    g->last_kind = -1;  // the device picked the path; apsp_last_stats reads it back
+    return APSP_OK;
+}
+
 extern "C" {
 
 int32_t apsp_abi_version(void) { return APSP_ABI_VERSION; }
@@ -636,44 +697,23 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
 }
 
 apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
-    if (!g) return fail(APSP_E_INVALID, "apsp_update_edge: NULL graph");
-    if (g->detached) return detached_error("apsp_update_edge");
-    if (w < 0 || (uint32_t)w > INF) return fail(APSP_E_INVALID, "apsp_update_edge: weight outside [0, APSP_INF]");
-    if (u == v) return fail(APSP_E_INVALID, "apsp_update_edge: u == v");
     int32_t su, sv;
-    if (!lookup(g, u, &su) || !lookup(g, v, &sv)) return fail(APSP_E_NOT_FOUND, "apsp_update_edge: id is not live");
-    hipStream_t s = g->stream;
-    DevGraph &d = g->dg;
-    const int32_t n_before = g->n_live;
-    g->prof.begin(KID_EDGE_BEGIN);
-    launch_edge_begin(d, su, sv, w, colu(g), colv(g), rowu(g), rowv(g), s);
-    g->prof.end();
-    FusedArgs fa = fused_args(g, FUSED_INCREASE);
-    fa.col1 = colu(g);
-    fa.col2 = colv(g);
-    fa.row1 = rowv(g);
-    fa.row2 = rowu(g);
-    g->prof.begin(KID_EDGE_SWEEP);
-    SR(g, launch_edge_sweep)(d, fa, w, s);
-    g->prof.end();
-    int32_t fallback = 0;
-    apsp_status st;
-    if (g->policy != APSP_FALLBACK_NEVER) {
-        if ((st = read_ctl(g))) return st;
-        if (g->ctl_h->edge_mode == EDGE_INCREASE && (st = decide_fallback(g, &fa, n_before, &fallback))) return st;
-    }
-    g->prof.begin(KID_FUSED);
-    const int32_t rblocks = SR(g, launch_mask_recompute)(d, fa, fallback, s);
-    g->prof.end();
-    if (fallback && (st = run_cold(g))) return st;
-    g->prof.begin(KID_NIN_BUILD);
-    launch_edge_finish(d, sv, g->kind == APSP_UNDIRECTED ? su : -1, g->partials, rblocks, s);
-    g->prof.end();
-    if ((st = check_launch("apsp_update_edge"))) return st;
-    g->last_n_before = n_before;
-    g->last_fallback = fallback;
-    g->last_kind = -1;  // the device picked the path; apsp_last_stats reads it back
-    return APSP_OK;
+    if (apsp_status bad = check_edge_args(g, "apsp_update_edge", u, v, w, &su, &sv)) return bad;
+    // the graph's own working memory, carved from its buffer
+    EdgeScratch sc{};
+    sc.colu = colu(g);
+    sc.colv = colv(g);
+    sc.rowu = rowu(g);
+    sc.rowv = rowv(g);
+    sc.fscratch = g->fscratch;
+    sc.heavy_rows = g->heavy_rows;
+    sc.heavy_epoch = g->heavy_epoch;
+    sc.flag_bits = g->flag_bits;
+    sc.row_bits = g->row_bits;
+    sc.marks = g->marks;
+    sc.partials = g->partials;
+    sc.epoch = ++g->epoch;
+    return update_edge_with(g, "apsp_update_edge", u, v, w, sc);
 }
 
 apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32_t *path_ids, int32_t path_cap,

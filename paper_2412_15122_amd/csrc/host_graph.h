@@ -190,4 +190,28 @@ inline bool lookup(const apsp_graph *g, int32_t id, int32_t *slot) {
     return true;
 }
 
+// The working memory of one edge update (device pointers): gathered columns
+// and rows of u and v, the heavy-row pass scratch (FUSED_GRID * 2 * P ints),
+// its row list and epoch marks (P ints each; heavy_epoch[i] == epoch marks a
+// heavy row, so epochs must not repeat on one array), the flag bitmap
+// (P * ceil(P/32) words, zero on entry), row bits (ceil(P/32) words, zero on
+// entry), row marks ((P/8) * mark_pitch(P) bytes) and the recompute's
+// per-work-group statistics.
+struct EdgeScratch {
+    int32_t *colu, *colv, *rowu, *rowv;
+    int32_t *fscratch, *heavy_rows, *heavy_epoch;
+    uint32_t *flag_bits, *row_bits;
+    uint8_t *marks;
+    int32_t *partials;
+    int32_t epoch;
+};
+
+// Argument checks of an edge update (nothing enqueued); slots of u and v.
+apsp_status check_edge_args(apsp_graph *g, const char *who, int32_t u, int32_t v, int32_t w, int32_t *su,
+                            int32_t *sv);
+// An edge update over the given working memory (apsp_update_edge passes the
+// graph's own; the no-allocation variant passes the library's static array).
+apsp_status update_edge_with(apsp_graph *g, const char *who, int32_t u, int32_t v, int32_t w,
+                             const EdgeScratch &sc);
+
 }  // namespace apsp_host

@@ -44,6 +44,11 @@ def test_constants_match_header(lib):
     text = open(HEADER).read()
     assert int(re.search(r"#define APSP_INF (\d+)", text).group(1)) == N.APSP_INF == 1 << 30
     assert int(re.search(r"#define APSP_MAX_CAPACITY (\d+)", text).group(1)) == N.APSP_MAX_CAPACITY
+    assert int(re.search(r"#define APSP_NOALLOC_MAX_CAPACITY (\d+)", text).group(1)) == N.APSP_NOALLOC_MAX_CAPACITY
+    # the static working memory of the no-allocation edge update holds a graph
+    # of the largest capacity it accepts, and stays modest
+    P = N.APSP_NOALLOC_MAX_CAPACITY
+    assert P * P // 8 + 1024 * P * 4 <= lib.apsp_noalloc_scratch_bytes() <= 32 << 20
     assert lib.apsp_abi_version() == int(re.search(r"#define APSP_ABI_VERSION (\d+)", text).group(1))
     for name in ("APSP_OK", "APSP_E_INVALID", "APSP_E_NOT_FOUND", "APSP_E_CAPACITY", "APSP_E_DEVICE", "APSP_E_VALUE"):
         m = re.search(name + r"\s*=\s*(-?\d+)", text)
@@ -80,6 +85,7 @@ def test_null_handle_checks(lib):
     from paper_2412_15122_amd import _native as N
     assert lib.apsp_remove_node(None, 0) == N.APSP_E_INVALID
     assert lib.apsp_update_edge(None, 0, 1, 5) == N.APSP_E_INVALID
+    assert lib.apsp_update_edge_noalloc(None, 0, 1, 5) == N.APSP_E_INVALID
     assert lib.apsp_add_node(None, None, None, None) == N.APSP_E_INVALID
     assert lib.apsp_graph_destroy(None) == N.APSP_OK
 
