@@ -3,13 +3,18 @@
 Workload: undirected complete graph, n = 16384, symmetric int32 weights
 U[1, 10000] (D = 1 GiB).  One step = 1000 updates applied in sequence
 (300 add-node / 200 remove-node / 250 edge decrease / 250 edge increase,
-seeded shuffle; the first is the worst-case increase of the step: among the
-64 lightest edges, the one with the largest |R| * |C|, raised to 20000).
-Every input (graph, add-node weight vectors) is resident in HBM before the
-timed region.  Prints one JSON line.
+seeded shuffle; the first is the worst-case increase: among the 64 lightest
+edges, the one with the largest |R| * |C|, raised to 20000) to the n-node
+graph, which is restored from a device snapshot before every step, outside
+the timed region.  Every input (graph, add-node weight vectors) is resident
+in HBM before the timed region.  The same line also carries the batched
+workload (512 graphs x 8 updates in one persistent launch against one call
+per update) and the served one (64 resident graphs, Poisson requests, p50 /
+p99 against the plain path).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384]
-                  [--no-cpu-baseline] [--no-verify]
+                  [--no-cpu-baseline] [--no-verify] [--legs batched,serving]
+  python bench.py --workload batched | serving | kernels   (one workload alone)
 """
 import argparse
 import hashlib
@@ -57,7 +62,10 @@ def parse():
                     help="batched: grid,order,variant to use instead of autotuning")
     ap.add_argument("--rates", default="1000,3000,10000,30000,100000",
                     help="serving: Poisson arrival rates (requests/s) to sweep")
-    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
+    ap.add_argument("--requests", type=int, default=20000, help="serving: requests per rate")
+    ap.add_argument("--legs", default="batched,serving",
+                    help="updates workload: further legs reported in the same line ('' for none)")
+    ap.add_argument("--leg-rates", default="10000,100000", help="serving leg: arrival rates (req/s)")
     ap.add_argument("--schedules", default="lockstep,hybrid",
                     help="serving: server schedules to run (the first is the reported one)")
     ap.add_argument("--semiring", default="shortest", choices=["shortest", "minimax"],
@@ -195,6 +203,13 @@ def batch_items(wls, W):
 
 
 def bench_batched(args):
+    import torch
+    torch.cuda.set_device(0)
+    out = batched_leg(args.graphs or 512, args.warmup, args.steps, args.batch_config)
+    print(json.dumps(out), flush=True)
+
+
+def batched_leg(graphs, warmup, steps, batch_config=None):
     """512 directed complete graphs (n log-uniform in [128, 2048]), 8 queued
     updates each: one autotuned, graph-replayed persistent launch against the
     plain path (one library call, i.e. one set of kernel launches, per
@@ -205,9 +220,8 @@ def bench_batched(args):
     from paper_2412_15122_amd.apsp import Graph
     from paper_2412_15122_amd.batch import Batch
     from paper_2412_15122_amd import autotune
-    torch.cuda.set_device(0)
     t = time.perf_counter()
-    wls = W.config4(graphs=args.graphs or 512)
+    wls = W.config4(graphs=graphs)
     log(f"[bench] {len(wls)} graphs generated in {time.perf_counter() - t:.1f}s")
     base = [Graph(w.adj, undirected=False, capacity=w.adj.shape[0] + 8) for w in wls]
     torch.cuda.synchronize()
@@ -215,8 +229,8 @@ def bench_batched(args):
     n_upd = len(items)
     ns = np.array([w.adj.shape[0] for w in wls])
     log(f"[bench] cold starts done; {n_upd} updates; sum n^2 = {int((ns.astype(np.int64) ** 2).sum())}")
-    if args.batch_config:
-        gr, od, va = (int(x) for x in args.batch_config.split(","))
+    if batch_config:
+        gr, od, va = (int(x) for x in batch_config.split(","))
         tuned = {"config": {"grid": gr, "order": od, "variant": va, "use_graph": 1}, "ms": None, "table": [],
                  "key": "fixed"}
     else:
@@ -247,7 +261,7 @@ def bench_batched(args):
                 g.update_edge(it[2], it[3], it[4])
 
     batched_ms, plain_ms, verify = [], [], True
-    for rep in range(args.warmup + args.steps):
+    for rep in range(warmup + steps):
         ga = [g.clone() for g in base]
         gb = [g.clone() for g in base]
         torch.cuda.synchronize()
@@ -288,7 +302,7 @@ def bench_batched(args):
         verify = verify and same
         log(f"[bench] rep {rep}: batched {tb:.2f} ms wall ({e0.elapsed_time(e1):.2f} ms events), "
             f"plain {tp:.1f} ms wall ({e2.elapsed_time(e3):.1f} ms events), equal={same}")
-        if rep >= args.warmup:
+        if rep >= warmup:
             batched_ms.append(tb)
             plain_ms.append(tp)
         for x in ga + gb:
@@ -311,7 +325,7 @@ def bench_batched(args):
         "metric": "batched warm-start APSP updates/s (512 graphs x 8 updates, 1 GPU)",
         "value": round(n_upd / (bt * 1e-3), 1),
         "unit": "updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": round(bt, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
         "config": {"workload": (f"{len(wls)} directed complete graphs, n log-uniform in [128, 2048], weights "
@@ -331,10 +345,18 @@ def bench_batched(args):
     b.close()
     for g in base:
         g.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_serving(args):
+    import torch
+    torch.cuda.set_device(0)
+    out = serving_leg(args.graphs or 64, [float(x) for x in args.rates.split(",")], args.requests,
+                      args.schedules.split(","), args.small_batch)
+    print(json.dumps(out), flush=True)
+
+
+def serving_leg(graphs, rates, requests, schedules, small_batch=None):
     """64 resident directed complete graphs (n uniform in [1024, 8192]),
     Poisson requests (45% increase, 45% decrease, 2.5% add, 2.5% remove, 5%
     query) swept over arrival rates: the continuous-batching server against
@@ -345,20 +367,17 @@ def bench_serving(args):
     from paper_2412_15122_amd import workloads as W
     from paper_2412_15122_amd import serve
     from paper_2412_15122_amd.apsp import Graph
-    torch.cuda.set_device(0)
     t = time.perf_counter()
-    adjs = W.config5_graphs(graphs=args.graphs or 64)
+    adjs = W.config5_graphs(graphs=graphs)
     ns = [a.shape[0] for a in adjs]
     log(f"[bench] {len(adjs)} graphs generated in {time.perf_counter() - t:.1f}s; n {min(ns)}..{max(ns)}")
-    rates = [float(x) for x in args.rates.split(",")]
-    schedules = args.schedules.split(",")
     rows = []
     for rate in rates:
         per = {}
         for sched in schedules:
             gen = W.Config5Requests(adjs)
-            reqs = serve.requests_from_stream(gen, rate, args.requests)
-            kw = {} if args.small_batch is None else {"small_batch": args.small_batch}
+            reqs = serve.requests_from_stream(gen, rate, requests)
+            kw = {} if small_batch is None else {"small_batch": small_batch}
             srv = serve.Server(adjs, streams=4, schedule=sched, **kw)
             srv.preload()
             r = srv.run(reqs)
@@ -393,7 +412,7 @@ def bench_serving(args):
         "ms_per_step": round(top["served"]["wall_s"] * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
         "config": {"workload": (f"{len(adjs)} directed complete graphs, n uniform in [1024, 8192], weights U[1,10000]; "
-                                f"Poisson requests, {args.requests} per rate: 45% increase, 45% decrease, 2.5% add, "
+                                f"Poisson requests, {requests} per rate: 45% increase, 45% decrease, 2.5% add, "
                                 f"2.5% remove, 5% single-pair query"),
                    "graphs": len(adjs), "parallelism": "none (1 GPU)", "rates": rates,
                    "schedule": schedules[0]},
@@ -402,7 +421,7 @@ def bench_serving(args):
                        "p99_ms": top["plain"]["p99_ms"]},
         "sweep": rows,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_kernels(args):
@@ -526,15 +545,16 @@ def main():
     if args.mix != "all":
         counts = {k: (per if k == args.mix else 0) for k in counts}
     growth = counts[W.ADD] - counts[W.REMOVE]
-    cap = n + max(growth, 0) * steps_total + 256
+    cap = n + counts[W.ADD] + 256      # every step starts again from the n-node graph
 
     t = time.perf_counter()
     adj = W.config3_graph(n)
     log(f"[bench] graph n={n} generated in {time.perf_counter() - t:.1f}s")
     minimax = args.semiring == "minimax"
-    g = Graph(adj, undirected=True, capacity=cap, minimax=minimax)
+    base = Graph(adj, undirected=True, capacity=cap, minimax=minimax)
     if args.fallback is not None:
-        g.set_fallback(1, args.fallback)
+        base.set_fallback(1, args.fallback)
+    g = base
     torch.cuda.synchronize()
     log(f"[bench] cold start done ({args.semiring} paths)")
     names = kernel_names()
@@ -556,12 +576,11 @@ def main():
     cand_base = W.lightest_edges(adj, 64, True)
 
     def worst_case_edge():
-        live = set(g.ids())
+        """Among the 64 lightest edges of the n-node graph every step starts
+        from, the one with the largest |R| * |C| (ties: lowest (u, v))."""
         best, best_key = None, None
         for (u, v, _) in cand_base:
-            if u not in live or v not in live:
-                continue
-            r, c = g.edge_scope(u, v)
+            r, c = base.edge_scope(u, v)
             key = (-(r * c), u, v)
             if best_key is None or key < best_key:
                 best, best_key = (u, v), key
@@ -582,7 +601,7 @@ def main():
                 ptrs.append(None)
         return dev, ptrs
 
-    def run_block(block, ptrs, events, trace=None):
+    def run_block(g, block, ptrs, events, trace=None):
         for i, u in enumerate(block):
             if u.kind == W.ADD:
                 g.add_node_device(ptrs[i], ptrs[i])
@@ -602,11 +621,21 @@ def main():
     prof_totals = {}
     alg_bytes_total = 0
     stats_all = []
+    # one block of updates, drawn once against the n-node graph; every step
+    # restores that graph (a device copy of the cold-started snapshot, outside
+    # the timed region) and applies the whole block to it
+    worst = worst_case_edge() if counts[W.INCREASE] > 0 else None
+    block = stream.next_block(worst=worst)
+    dev, ptrs = stage(block)
+    live, live_lo, live_hi = n, n, n
+    for u in block:
+        live += 1 if u.kind == W.ADD else (-1 if u.kind == W.REMOVE else 0)
+        live_lo, live_hi = min(live_lo, live), max(live_hi, live)
     for step in range(steps_total):
         timed = step >= args.warmup
-        worst = worst_case_edge() if counts[W.INCREASE] > 0 else None
-        block = stream.next_block(worst=worst)
-        dev, ptrs = stage(block)
+        if g is not base:
+            g.close()
+        g = base.clone()
         torch.cuda.synchronize()
         if step == 0:
             g.profile(-1)          # every kernel: find the dominant one
@@ -618,7 +647,7 @@ def main():
         t0 = time.perf_counter()
         start.record()
         trace = [] if (args.trace and not timed) else None
-        run_block(block, ptrs, events, trace)
+        run_block(g, block, ptrs, events, trace)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if trace:
@@ -652,14 +681,15 @@ def main():
                 prof_totals["timed"][0] += c
                 prof_totals["timed"][1] += ms
                 g.profile(0)
-        del dev
+    del dev
 
     # algorithmic bytes of the dominant kernel over the timed steps: replay the
-    # live counts (every add / remove changes n by one)
-    live = n + growth * args.warmup
+    # live counts (every add / remove changes n by one; each step starts at n)
     removes_bytes = adds_bytes = 0
     launches = {"add_relax": 0, "mask_detect": 0}
-    for k in kinds_all:
+    for t, k in enumerate(kinds_all):
+        if t % len(block) == 0:
+            live = n
         if k == W.ADD:
             adds_bytes += 4 * live * live
             launches["add_relax"] += 1
@@ -675,8 +705,8 @@ def main():
         achieved = alg / (ms * 1e-3) / 1e9
         tb = None if minimax else traffic_from_profiles(prof_kernel)   # counters were taken on shortest paths
         # the counter runs launch at n = 16384 exactly; this run's launches at
-        # the growing live count: the measured traffic over its algorithmic
-        # bytes at that n is the comparable figure
+        # the live count of the step: the measured traffic over its
+        # algorithmic bytes at that n is the comparable figure
         n_pmc = 16384
         alg_pmc = 4 * n_pmc * n_pmc if prof_kernel == "add_relax" else 4 * (n_pmc - 1) * n_pmc
         roofline = {
@@ -746,7 +776,9 @@ def main():
             "workload": (f"undirected complete graph n={n}, symmetric weights U[1,10000], "
                          f"{per} sequential updates per step ({counts[W.ADD]} add / {counts[W.REMOVE]} remove / "
                          f"{counts[W.DECREASE]} decrease / {counts[W.INCREASE]} increase incl. one worst-case increase)"),
-            "n": n, "updates_per_step": per, "parallelism": "none (1 GPU)",
+            "n": n, "live_nodes_range": [live_lo, live_hi],
+            "step": "the n-node graph restored from a snapshot before each step (untimed), then the same block",
+            "updates_per_step": per, "parallelism": "none (1 GPU)",
             "paths": args.semiring, "fallback_delta": args.fallback,
         },
         "cold_fw_ms": round(cold_med, 2),
@@ -758,6 +790,28 @@ def main():
         "verified_vs_gpu_cold": verify,
         "roofline": roofline,
     }
+    g.close()
+    base.close()
+    del g, base
+    torch.cuda.empty_cache()
+    legs = [x for x in args.legs.split(",") if x]
+    if "batched" in legs and not minimax:
+        log("[bench] batched leg: 512 graphs x 8 updates, one persistent launch vs one call per update")
+        b = batched_leg(512, 1, 3)
+        out["batched"] = {k: b[k] for k in ("metric", "value", "unit", "ms_per_step", "steps", "warmup", "config",
+                                            "plain_path", "batched_vs_plain_speedup", "verified_vs_plain",
+                                            "roofline")}
+        torch.cuda.empty_cache()
+    if "serving" in legs and not minimax:
+        rates = [float(x) for x in args.leg_rates.split(",")]
+        log(f"[bench] serving leg: 64 resident graphs, {args.requests} requests per rate at {rates} req/s")
+        sv = serving_leg(64, rates, args.requests, ["lockstep"])
+        out["serving"] = {"metric": sv["metric"], "unit": "updates/s", "config": sv["config"],
+                          "rates": [{"rate": r["rate"],
+                                     "served": {k: r["served"][k] for k in ("updates_per_s", "p50_ms", "p99_ms")},
+                                     "plain": {k: r["plain"][k] for k in ("updates_per_s", "p50_ms", "p99_ms")}}
+                                    for r in sv["sweep"]]}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle Floyd-Warshall, sampled)")
         out["cpu_baseline"] = cpu_baseline(adj)
@@ -765,7 +819,6 @@ def main():
             out["cpu_context"] = cpu_context(adj)
         except Exception as e:  # noqa: BLE001
             out["cpu_context"] = {"error": f"{type(e).__name__}: {e}"}
-    g.close()
     print(json.dumps(out), flush=True)
 
 
