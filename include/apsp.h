@@ -85,8 +85,23 @@ typedef enum {
  * steps with max in place of + (Theorems 1–3 and Corollary
  * 3 hold with max, which is monotone with 0 as identity on weights
  * >= 0).  A batch (apsp_batch_run) takes graphs of one kind: all minimax
- * or none. */
-typedef enum { APSP_DIRECTED = 0, APSP_UNDIRECTED = 1, APSP_MINIMAX = 2 } apsp_kind;
+ * (widest graphs included) or none.
+ *
+ * APSP_WIDEST (instead of APSP_MINIMAX) selects widest paths, the (max, min)
+ * semiring the discussion section names beside minimax paths: weights are
+ * capacities c in [0, APSP_INF - 1] (APSP_INF: no edge), and
+ * W[i][j] = the largest, over walks from i to j, of the smallest capacity
+ * on the walk; W[i][i] = APSP_INF - 1, and W[i][j] = APSP_INF when j is
+ * unreachable.  The library stores each capacity c as the weight
+ * (APSP_INF - 1) - c and runs the minimax kernels: a walk's smallest
+ * capacity is APSP_INF - 1 minus its largest stored weight, so
+ * W[i][j] = (APSP_INF - 1) - D[i][j] for the minimax matrix D of the stored
+ * weights, exactly.  Every value crossing the boundary is converted: the
+ * adjacency and add-node capacities on the way in, edge-update capacities,
+ * and matrices, adjacency read-outs and query distances (single or batched)
+ * on the way out.  Paths and node sets are those of the minimax problem,
+ * which are the widest paths. */
+typedef enum { APSP_DIRECTED = 0, APSP_UNDIRECTED = 1, APSP_MINIMAX = 2, APSP_WIDEST = 4 } apsp_kind;
 
 /* What apsp_remove_node and an edge increase do after building the mask
  * (Algorithm 5 switches to Floyd-Warshall when Cost exceeds delta). */
@@ -126,6 +141,11 @@ typedef struct {
                           * removed node (or the raised edge).  0 after a cold
                           * fallback. */
     double cost_refined; /* Phi' / (N - 1) */
+    int32_t route;       /* removals: 0 mask + recompute; 1 the minimum-spanning-forest
+                          * route of an undirected minimax graph (only the pairs
+                          * whose distance changes are written; see
+                          * apsp_remove_node) */
+    int32_t pad;
 } apsp_update_stats;
 
 /* ---- sizing ------------------------------------------------------------ */
@@ -208,7 +228,17 @@ apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t
  * with D[i][k] + D[k][j] == D[i][j] form the need_update mask (Corollary
  * 3: all others keep their distance); the masked pairs are
  * recomputed exactly on G - G_k, or cold Floyd-Warshall runs, per the
- * fallback policy.  The id is retired. */
+ * fallback policy.  The id is retired.
+ * On an undirected minimax (or widest) graph the call first tries the
+ * refined set of Algorithms 11-12 (Theorem 6) directly: a minimum spanning
+ * forest of G over the light in-edge index, certified against every
+ * unlisted edge; only pairs whose forest path crossed k can change, and
+ * their new distances follow from the lightest edges joining the pieces the
+ * forest falls into.  This writes only the changed pairs.  When the
+ * certificate or a size limit (capacity above 32768, k joining more than
+ * 64 pieces) rejects it, the mask route runs; both give the same matrix.
+ * The route taken is in apsp_update_stats.route.  This call waits once for
+ * the device (the certificate's read-back) on such graphs. */
 apsp_status apsp_remove_node(apsp_graph *g, int32_t id);
 
 /* Set the weight of edge u -> v (and v -> u for an undirected graph) to w,
@@ -285,6 +315,23 @@ apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
 apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
                              int32_t *on_ids, int32_t on_cap, int32_t *on_len,
                              int32_t *key_ids, int32_t key_cap, int32_t *key_len);
+
+/* Algorithm 8's list of shortest i -> j paths (Section 4): the query's own
+ * path (apsp_query), then, for every other node t on some shortest i -> j
+ * path (the candidate set of apsp_query_nodes) in ascending id order and not
+ * on a path already listed through it, the path i -> t followed by
+ * t -> j, each distinct path once.  Every listed path is a shortest simple
+ * walk (on minimax / widest graphs: an optimal one); the list need not hold
+ * every shortest path.  Output (host memory): path q is
+ * ids[offsets[q] .. offsets[q + 1]); *npaths paths, *ids_len ids in all;
+ * *dist as apsp_query.  i == j gives [[i]]; an unreachable j gives no path
+ * (offsets[0] = 0).  The paths run on the device, one work-group per
+ * candidate (chunks of up to 128), then one read-back per chunk;
+ * synchronous.  APSP_E_CAPACITY when offsets_cap < *npaths + 1 or
+ * ids_cap < *ids_len (both sizes are set, nothing else written);
+ * APSP_E_NOT_FOUND for a dead id. */
+apsp_status apsp_query_paths(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32_t *ids, int64_t ids_cap,
+                             int64_t *ids_len, int32_t *offsets, int32_t offsets_cap, int32_t *npaths);
 
 /* Copy the live distance matrix (ascending-id order) into out_dev
  * (n x n, leading dimension out_ld >= n).  Asynchronous. */

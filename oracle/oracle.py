@@ -15,6 +15,12 @@ slowly and visibly:
   minimax (bottleneck) distances, the (min, max) variant of the discussion
   section: Floyd-Warshall with max, enumeration of simple paths, and
   reachability under a weight threshold.
+* ``widest_apsp`` / ``brute_force_widest`` / ``widest_by_thresholds`` --
+  widest (maximum-capacity) paths, the (max, min) variant the discussion
+  section names beside minimax paths: Floyd-Warshall with min and max
+  swapped, enumeration of simple paths, and reachability over edges of at
+  least a given capacity.  W(i,i) = WIDEST_TOP (an empty walk is not
+  limited), INF when j is unreachable.
 * ``remove_mask`` -- the need_update_list of a node removal (Section 3.2,
   built with Theorem 4 / Corollary 3): pair (i,j)
   is listed when M[i][k] + M[k][j] equals M[i][j].
@@ -272,6 +278,70 @@ def minimax_by_thresholds(A: np.ndarray) -> np.ndarray:
                 frontier = list(nxt)
             D[i, seen] = theta
     return D.astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# widest (maximum-capacity) paths: the (max, min) semiring
+# ---------------------------------------------------------------------------
+
+WIDEST_TOP = INF - 1   # the largest capacity; the width of the empty walk i -> i
+
+
+def widest_apsp(C: np.ndarray) -> np.ndarray:
+    """Widest-path widths: W(i,j) = max over walks i -> j of the smallest
+    edge capacity on the walk, W(i,i) = WIDEST_TOP, INF if j is unreachable.
+    Capacities in [0, WIDEST_TOP], INF = no edge.  Textbook Floyd-Warshall
+    with (max, min) in place of (min, +); 'no path' is -1 inside."""
+    C = _check_adj(C).astype(np.int64)
+    n = C.shape[0]
+    W = np.where(C >= INF, -1, C)
+    W[np.arange(n), np.arange(n)] = WIDEST_TOP
+    for k in range(n):
+        W = np.maximum(W, np.minimum(W[:, k:k + 1], W[k:k + 1, :]))
+    return np.where(W < 0, INF, W).astype(np.int32)
+
+
+def brute_force_widest(C: np.ndarray) -> np.ndarray:
+    """W(i,j) = max over all simple i -> j paths of the smallest capacity
+    (cutting a cycle out of a walk never lowers its smallest capacity),
+    n <= 8."""
+    C = _check_adj(C)
+    n = C.shape[0]
+    assert n <= 8, "brute force is for tiny graphs"
+    W = np.full((n, n), -1, dtype=np.int64)
+    for i in range(n):
+        W[i, i] = WIDEST_TOP
+        for j in range(n):
+            if i == j:
+                continue
+            for seq, _ in _simple_paths(C, i, j):   # every edge of seq is present
+                W[i, j] = max(W[i, j], min(int(C[a, b]) for a, b in zip(seq[:-1], seq[1:])))
+    return np.where(W < 0, INF, W).astype(np.int32)
+
+
+def widest_by_thresholds(C: np.ndarray) -> np.ndarray:
+    """W(i,j) as the largest threshold t (an edge capacity) at which j is
+    reachable from i over edges of capacity >= t: breadth-first search, one
+    threshold at a time from the largest down."""
+    C = _check_adj(C).astype(np.int64)
+    n = C.shape[0]
+    W = np.full((n, n), INF, dtype=np.int64)
+    done = np.eye(n, dtype=bool)
+    W[np.arange(n), np.arange(n)] = WIDEST_TOP
+    for t in sorted({int(c) for c in C[C < INF]}, reverse=True):
+        adj = (C >= t) & (C < INF)
+        for i in range(n):
+            seen = np.zeros(n, dtype=bool)
+            seen[i] = True
+            frontier = [i]
+            while frontier:
+                nxt = np.nonzero(adj[frontier].any(axis=0) & ~seen)[0]
+                seen[nxt] = True
+                frontier = list(nxt)
+            new = seen & ~done[i]
+            W[i, new] = t
+            done[i] |= seen
+    return W.astype(np.int32)
 
 
 # ---------------------------------------------------------------------------

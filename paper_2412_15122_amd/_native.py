@@ -22,6 +22,7 @@ APSP_E_VALUE = -7
 APSP_DIRECTED = 0
 APSP_UNDIRECTED = 1
 APSP_MINIMAX = 2      # OR-ed into the kind: minimax (bottleneck) paths
+APSP_WIDEST = 4       # OR-ed into the kind: widest (maximum-capacity) paths
 APSP_IMPORT_TRUSTED = 0  # apsp_import: O(n^2) checks only
 APSP_IMPORT_EXACT = 1    # apsp_import: also a cold recompute, compared
 APSP_FALLBACK_NEVER = 0
@@ -57,6 +58,8 @@ class UpdateStats(ctypes.Structure):
         ("rows_changed", ctypes.c_int32),
         ("changed", ctypes.c_int64),
         ("cost_refined", ctypes.c_double),
+        ("route", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -108,6 +111,7 @@ SIGNATURES = {
     "apsp_node_count": (_I32, [_P, _PI32]),
     "apsp_node_ids": (_I32, [_P, _PI32, _I32, _PI32]),
     "apsp_edge_scope": (_I32, [_P, _I32, _I32, _PI32, _PI32]),
+    "apsp_query_paths": (_I32, [_P, _I32, _I32, _PI32, _PI32, _I64, ctypes.POINTER(_I64), _PI32, _I32, _PI32]),
     "apsp_last_stats": (_I32, [_P, ctypes.POINTER(UpdateStats)]),
     "apsp_sync": (_I32, [_P]),
     "apsp_set_stream": (_I32, [_P, _P]),

@@ -32,6 +32,11 @@ def _device_int32(x):
     return t.to(device="cuda", dtype=torch.int32).contiguous()
 
 
+def _path_bits(minimax: bool, widest: bool) -> int:
+    """The kind bits of a graph's path problem."""
+    return N.APSP_WIDEST if widest else (N.APSP_MINIMAX if minimax else 0)
+
+
 class Graph:
     """A dense weighted graph whose APSP matrix lives on the GPU.
 
@@ -39,10 +44,14 @@ class Graph:
     start (apsp_cold).  `adj` is an n x n int32 matrix (numpy or torch),
     absent edges APSP_INF, diagonal ignored.  Ids are 0..n-1; added nodes
     get max_id + 1.  minimax=True keeps minimax (bottleneck) distances
-    instead of shortest-path ones (APSP_MINIMAX).
+    instead of shortest-path ones (APSP_MINIMAX); widest=True keeps widest
+    (maximum-capacity) paths: `adj` then holds capacities in
+    [0, APSP_INF - 1] (APSP_INF: no edge), and every matrix, distance and
+    weight read back is a width (APSP_WIDEST).
     """
 
-    def __init__(self, adj, *, undirected: bool = False, capacity: Optional[int] = None, minimax: bool = False):
+    def __init__(self, adj, *, undirected: bool = False, capacity: Optional[int] = None, minimax: bool = False,
+                 widest: bool = False):
         torch = _torch()
         self._lib = N.load()
         A = _device_int32(adj)
@@ -52,7 +61,8 @@ class Graph:
         cap = int(capacity if capacity is not None else max(n, 1))
         self.kind = N.APSP_UNDIRECTED if undirected else N.APSP_DIRECTED
         self.undirected = bool(undirected)
-        self.minimax = bool(minimax)
+        self.widest = bool(widest)
+        self.minimax = bool(minimax) or self.widest
         nbytes = int(self._lib.apsp_required_bytes(cap, self.kind))
         if nbytes == 0:
             raise ValueError(f"invalid capacity {cap}")
@@ -63,7 +73,7 @@ class Graph:
         self.capacity = cap
         self._stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
-        kind = self.kind | (N.APSP_MINIMAX if self.minimax else 0)
+        kind = self.kind | _path_bits(self.minimax, self.widest)
         st = self._lib.apsp_cold(A.data_ptr() if n else None, n, A.stride(0) if n else 0, kind, cap,
                                  self._ptr, nbytes, self._stream.cuda_stream, ctypes.byref(h))
         N.check(st, "apsp_cold")
@@ -73,7 +83,7 @@ class Graph:
     @classmethod
     def from_matrix(cls, adj, dist, *, undirected: bool = False, capacity: Optional[int] = None,
                     minimax: bool = False, ids: Optional[Sequence[int]] = None, next_id: Optional[int] = None,
-                    exact: bool = False) -> "Graph":
+                    exact: bool = False, widest: bool = False) -> "Graph":
         """A graph whose distance matrix is already known (apsp_import): the
         paper's starting point, where the old matrix is given and only the
         updates are paid for.  `dist` is n x n in the order of `adj`'s rows;
@@ -105,10 +115,11 @@ class Graph:
         st = lib.apsp_import(A.data_ptr() if n else None, A.stride(0) if n else 0,
                              Dm.data_ptr() if n else None, Dm.stride(0) if n else 0, n, id_arr,
                              -1 if next_id is None else int(next_id),
-                             kind | (N.APSP_MINIMAX if minimax else 0), cap, ptr, nbytes, stream.cuda_stream,
+                             kind | _path_bits(minimax, widest), cap, ptr, nbytes, stream.cuda_stream,
                              N.APSP_IMPORT_EXACT if exact else N.APSP_IMPORT_TRUSTED, ctypes.byref(h))
         N.check(st, "apsp_import")
-        return cls._from_handle(lib, h, buf, ptr, nbytes, cap, kind, stream, bool(minimax))
+        return cls._from_handle(lib, h, buf, ptr, nbytes, cap, kind, stream, bool(minimax) or bool(widest),
+                                bool(widest))
 
     def grow(self, capacity: int) -> "Graph":
         """A copy of this graph with `capacity` node slots (apsp_grow): every
@@ -125,10 +136,11 @@ class Graph:
         h = ctypes.c_void_p()
         N.check(self._lib.apsp_grow(self._h, int(capacity), ptr, nbytes, stream.cuda_stream, ctypes.byref(h)),
                 "apsp_grow")
-        return Graph._from_handle(self._lib, h, buf, ptr, nbytes, int(capacity), self.kind, stream, self.minimax)
+        return Graph._from_handle(self._lib, h, buf, ptr, nbytes, int(capacity), self.kind, stream, self.minimax,
+                                  self.widest)
 
     @classmethod
-    def _from_handle(cls, lib, h, buf, ptr, nbytes, cap, kind, stream, minimax=False):
+    def _from_handle(cls, lib, h, buf, ptr, nbytes, cap, kind, stream, minimax=False, widest=False):
         g = cls.__new__(cls)
         g._lib = lib
         g._h = h
@@ -139,6 +151,7 @@ class Graph:
         g.kind = kind
         g.undirected = kind == N.APSP_UNDIRECTED
         g.minimax = minimax
+        g.widest = widest
         g._stream = stream
         g._keep = []
         return g
@@ -157,7 +170,7 @@ class Graph:
         if stream.cuda_stream != self._stream.cuda_stream:
             self._stream.wait_stream(stream)  # and the source's later updates after the copy
         return Graph._from_handle(self._lib, h, buf, ptr, self._nbytes, self.capacity, self.kind, stream,
-                                  self.minimax)
+                                  self.minimax, self.widest)
 
     @property
     def nbytes(self) -> int:
@@ -338,24 +351,25 @@ class Graph:
         return int(dist.value), list(on[: n_on.value]), list(key[: n_key.value])
 
     def query_paths(self, i: int, j: int) -> List[List[int]]:
-        """Algorithm 8's list of shortest i -> j paths: the query's path,
-        then for every other node t on some shortest path (query_nodes) the
-        path i -> t followed by t -> j, each new path once.  Every path is
-        shortest; the list need not hold them all.  [[i]] when i == j, []
+        """Algorithm 8's list of shortest i -> j paths (apsp_query_paths): the
+        query's path, then for every other node t on some shortest path the
+        path i -> t followed by t -> j, each distinct path once.  Every path
+        is shortest; the list need not hold them all.  [[i]] when i == j, []
         when j is unreachable."""
-        dist, on, _ = self.query_nodes(i, j)
-        if not on:
-            return []
-        first = self.query(i, j)[1]
-        paths, seen = [first], {tuple(first)}
-        for t in on:
-            if t in (i, j) or t in first:
+        n = max(self.num_nodes(), 1)
+        ids_cap, off_cap = 8 * n, n + 1
+        for _ in range(2):
+            ids = (ctypes.c_int32 * ids_cap)()
+            offs = (ctypes.c_int32 * off_cap)()
+            dist, npaths, ids_len = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+            st = self._lib.apsp_query_paths(self._h, int(i), int(j), ctypes.byref(dist), ids, ids_cap,
+                                            ctypes.byref(ids_len), offs, off_cap, ctypes.byref(npaths))
+            if st == N.APSP_E_CAPACITY:  # sizes reported: once more with room
+                ids_cap, off_cap = int(ids_len.value), int(npaths.value) + 1
                 continue
-            p = self.query(i, t)[1] + self.query(t, j)[1][1:]
-            if tuple(p) not in seen:
-                seen.add(tuple(p))
-                paths.append(p)
-        return paths
+            N.check(st, "apsp_query_paths")
+            return [list(ids[offs[q]:offs[q + 1]]) for q in range(npaths.value)]
+        raise N.ApspError(N.APSP_E_CAPACITY, "apsp_query_paths")
 
     def edge_scope(self, u: int, v: int) -> Tuple[int, int]:
         r = ctypes.c_int32()

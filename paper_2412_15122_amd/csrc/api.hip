@@ -17,6 +17,7 @@ using namespace apsp;
 #define SR(g, fn) ((g)->minimax ? &mm::fn : &fn)
 
 #include "host_graph.h"
+#include "msf.h"
 
 using namespace apsp_host;
 
@@ -85,6 +86,58 @@ apsp_status decide_fallback(apsp_graph *g, const FusedArgs *fa, int32_t n_before
     *fallback = cost > g->delta;
     launch_fill(&g->dg.ctl->rows, 1, 0, g->stream);  // the recompute counts Phi again
     return check_launch("cost decision");
+}
+
+// Removal of slot k from an undirected minimax graph through its minimum
+// spanning forest (msf.hip): the forest over the light index, its
+// certificate and the pieces of T - k, one read-back, then -- when the
+// certificate holds -- the mask's counts and the new entries of the pairs
+// across pieces.  *used is false when the certificate or a size limit
+// rejects the forest (nothing written: the caller runs the mask route);
+// *fallback is 1 when Algorithm 5's cost test picks cold Floyd-Warshall
+// (no entry written either).
+apsp_status remove_by_forest(apsp_graph *g, int32_t k, int32_t n_before, bool *used, int32_t *fallback) {
+    *used = false;
+    *fallback = 0;
+    if (msf_configure() != hipSuccess) {
+        (void)hipGetLastError();
+        return APSP_OK;
+    }
+    DevGraph &d = g->dg;
+    hipStream_t s = g->stream;
+    const MsfWork w = msf_work(g->fscratch, g->P);
+    if (w.ints > (int64_t)FUSED_GRID * 2 * g->P) return APSP_OK;  // the heavy-row scratch holds it (P >= 128)
+    int32_t rounds = 2;
+    while ((1 << (rounds - 2)) < std::max(n_before, 2)) ++rounds;
+    launch_msf_forest(d, w, k, rounds, s);
+    apsp_status st = check_launch("apsp_remove_node: spanning forest");
+    if (st) return st;
+    if (!hip_ok(hipMemcpyAsync(g->qbuf_h, w.info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "forest read") ||
+        !hip_ok(hipStreamSynchronize(s), "stream sync"))
+        return APSP_E_DEVICE;
+    const int32_t *info = g->qbuf_h;
+    if (info[MI_ACTIVE] != 0 || info[MI_FAIL] != 0) return APSP_OK;
+    FusedArgs fa{};
+    fa.mode = FUSED_REMOVE;
+    fa.k = k;
+    fa.col1 = colu(g);
+    fa.row1 = rowu(g);
+    g->prof.begin(KID_MASK);
+    mm::launch_mask_count(d, fa, s);
+    g->prof.end();
+    *used = true;
+    if (g->policy == APSP_FALLBACK_COST) {
+        if ((st = read_ctl(g))) return st;
+        const double cost = n_before > 1 ? (double)g->ctl_h->rows / (double)(n_before - 1) : 0.0;
+        if (cost > g->delta) {
+            *fallback = 1;
+            return check_launch("apsp_remove_node: mask counts");
+        }
+    }
+    g->prof.begin(KID_FUSED);
+    launch_msf_update(d, w, info[MI_SMALL], s);
+    g->prof.end();
+    return check_launch("apsp_remove_node: spanning-forest update");
 }
 
 // A handle over the caller's buffer: pinned host mirrors and the carving of
@@ -185,8 +238,10 @@ apsp_status new_graph(const char *who, const int32_t *adj_dev, int32_t n, int64_
     const std::string w(who);
     if (!out) return fail(APSP_E_INVALID, w + ": out is NULL");
     *out = nullptr;
-    const int32_t dir = kind & ~(int32_t)APSP_MINIMAX;
+    const int32_t dir = kind & ~(int32_t)(APSP_MINIMAX | APSP_WIDEST);
     if (dir != APSP_DIRECTED && dir != APSP_UNDIRECTED) return fail(APSP_E_INVALID, w + ": bad kind");
+    if ((kind & APSP_MINIMAX) && (kind & APSP_WIDEST))
+        return fail(APSP_E_INVALID, w + ": APSP_MINIMAX and APSP_WIDEST exclude each other");
     if (capacity < 1 || capacity > APSP_MAX_CAPACITY)
         return fail(APSP_E_INVALID, w + ": capacity must be in [1, APSP_MAX_CAPACITY]");
     if (n < 0 || n > capacity) return fail(APSP_E_INVALID, w + ": n must be in [0, capacity]");
@@ -199,8 +254,10 @@ apsp_status new_graph(const char *who, const int32_t *adj_dev, int32_t n, int64_
     apsp_graph *g = nullptr;
     apsp_status st0 = make_handle(capacity, dir, dev_buf, (hipStream_t)hip_stream, &g);
     if (st0) return st0;
-    g->minimax = (kind & APSP_MINIMAX) != 0;
+    // widest paths are minimax paths over transformed weights (widest_xf)
+    g->minimax = (kind & (APSP_MINIMAX | APSP_WIDEST)) != 0;
     DevGraph &d = g->dg;
+    d.widest = (kind & APSP_WIDEST) != 0;
     hipError_t ce = configure_kernels();
     if (ce == hipSuccess) ce = mm::configure_kernels();
     if (hipError_t e = ce; e != hipSuccess) {
@@ -264,6 +321,7 @@ apsp_status apsp_host::update_edge_with(apsp_graph *g, const char *who, int32_t 
                                         const EdgeScratch &sc) {
     int32_t su, sv;
     if (apsp_status bad = check_edge_args(g, who, u, v, w, &su, &sv)) return bad;
+    if (g->dg.widest) w = widest_xf(w);  // a capacity, stored as its transform
     hipStream_t s = g->stream;
     DevGraph &d = g->dg;
     const int32_t n_before = g->n_live;
@@ -328,8 +386,9 @@ const char *apsp_kernel_name(int32_t k) {
 
 size_t apsp_required_bytes(int32_t capacity, int32_t kind) {
     if (capacity < 1 || capacity > APSP_MAX_CAPACITY) return 0;
-    const int32_t dir = kind & ~(int32_t)APSP_MINIMAX;
+    const int32_t dir = kind & ~(int32_t)(APSP_MINIMAX | APSP_WIDEST);
     if (dir != APSP_DIRECTED && dir != APSP_UNDIRECTED) return 0;
+    if ((kind & APSP_MINIMAX) && (kind & APSP_WIDEST)) return 0;
     return make_layout(capacity, dir).total;
 }
 
@@ -372,7 +431,7 @@ apsp_status apsp_import(const int32_t *adj_dev, int64_t adj_ld, const int32_t *a
     launch_import_d(g->dg, apsp_dev, apsp_ld, n, bad, s);
     if (verify == APSP_IMPORT_EXACT) {
         st = run_cold(g);
-        if (!st) launch_count_diff(g->dg.D, g->dg.ld, apsp_dev, apsp_ld, n, bad, s);
+        if (!st) launch_count_diff(g->dg.D, g->dg.ld, apsp_dev, apsp_ld, n, bad, g->dg.widest, s);
     }
     if (!st && ids && n > 0 &&
         !hip_ok(hipMemcpyAsync(g->dg.id_of_slot, ids, (size_t)n * 4, hipMemcpyHostToDevice, s), "ids copy"))
@@ -444,6 +503,7 @@ apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes,
     c->rank_other = (int32_t *)(c->base + ((char *)g->rank_other - g->base));
     c->dg.n_slots = g->dg.n_slots;
     c->dg.lim = g->dg.lim;
+    c->dg.widest = g->dg.widest;
     c->epoch = g->epoch;
     c->n_live = g->n_live;
     c->max_id = g->max_id;
@@ -511,6 +571,7 @@ apsp_status apsp_grow(apsp_graph *g, int32_t capacity, void *dev_buf, size_t dev
     }
     cd.n_slots = ns;
     cd.lim = gd.lim;
+    cd.widest = gd.widest;
     c->epoch = g->epoch;
     c->n_live = g->n_live;
     c->max_id = g->max_id;
@@ -536,11 +597,12 @@ apsp_status apsp_graph_relocate(apsp_graph *g, void *dev_buf, size_t dev_buf_byt
     apsp_status st = make_handle(g->cap, g->kind, dev_buf, g->stream, &t);
     if (st) return st;
     const int64_t rc = (char *)g->rank_cur - g->base, ro = (char *)g->rank_other - g->base;
-    const int32_t n_slots = g->dg.n_slots, lim = g->dg.lim;
+    const int32_t n_slots = g->dg.n_slots, lim = g->dg.lim, widest = g->dg.widest;
     g->base = t->base;
     g->dg = t->dg;
     g->dg.n_slots = n_slots;
     g->dg.lim = lim;
+    g->dg.widest = widest;
     for (int v = 0; v < NVEC; ++v) g->vec[v] = t->vec[v];
     g->plist = t->plist;
     g->plist_cnt = t->plist_cnt;
@@ -662,19 +724,28 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     g->prof.begin(KID_GATHER);
     launch_remove_begin(d, k, colu(g), rowu(g), s);
     g->prof.end();
-    FusedArgs fa = fused_args(g, FUSED_REMOVE);
-    fa.k = k;
-    fa.col1 = colu(g);
-    fa.row1 = rowu(g);
-    g->prof.begin(KID_MASK);
-    SR(g, launch_mask_detect)(d, fa, s);
-    g->prof.end();
     int32_t fallback = 0;
-    apsp_status st = decide_fallback(g, &fa, n_before, &fallback);
-    if (st) return st;
-    g->prof.begin(KID_FUSED);
-    const int32_t rblocks = SR(g, launch_mask_recompute)(d, fa, fallback, s);
-    g->prof.end();
+    apsp_status st;
+    // undirected minimax graphs: the spanning-forest route when its
+    // certificate holds (exact, and it writes only the changed pairs)
+    bool forest = false;
+    if (g->minimax && g->kind == APSP_UNDIRECTED && g->P <= MSF_MAX_PITCH && g->policy != APSP_FALLBACK_ALWAYS &&
+        (st = remove_by_forest(g, k, n_before, &forest, &fallback)))
+        return st;
+    int32_t rblocks = 0;
+    if (!forest) {
+        FusedArgs fa = fused_args(g, FUSED_REMOVE);
+        fa.k = k;
+        fa.col1 = colu(g);
+        fa.row1 = rowu(g);
+        g->prof.begin(KID_MASK);
+        SR(g, launch_mask_detect)(d, fa, s);
+        g->prof.end();
+        if ((st = decide_fallback(g, &fa, n_before, &fallback))) return st;
+        g->prof.begin(KID_FUSED);
+        rblocks = SR(g, launch_mask_recompute)(d, fa, fallback, s);
+        g->prof.end();
+    }
     g->prof.begin(KID_TOMBSTONE);
     launch_remove_finish(d, k, g->nin_queue, g->rank_cur, g->rank_other, r, n_before, g->partials, rblocks, s);
     g->prof.end();
@@ -693,6 +764,7 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     g->last_kind = UK_REMOVE;
     g->last_n_before = n_before;
     g->last_fallback = fallback;
+    g->last_route = forest ? 1 : 0;
     return APSP_OK;
 }
 
@@ -741,7 +813,7 @@ apsp_status apsp_query(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32
         !hip_ok(hipStreamSynchronize(s), "query sync"))
         return APSP_E_DEVICE;
     if (g->qbuf_h[2] != 0) return fail(APSP_E_DEVICE, "apsp_query: no shortest path found on the device");
-    *dist = g->qbuf_h[0];
+    *dist = g->dg.widest ? widest_xf(g->qbuf_h[0]) : g->qbuf_h[0];
     *path_len = g->qbuf_h[1];
     if (*path_len > path_cap) return fail(APSP_E_CAPACITY, "apsp_query: path_cap too small");
     for (int32_t t = 0; t < *path_len; ++t) path_ids[t] = g->qbuf_h[3 + t];
@@ -780,7 +852,7 @@ apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
     if (!hip_ok(hipMemcpyAsync(g->qbuf_h, out, (size_t)(4 + 2 * n) * 4, hipMemcpyDeviceToHost, s), "query copy") ||
         !hip_ok(hipStreamSynchronize(s), "query sync"))
         return APSP_E_DEVICE;
-    *dist = g->qbuf_h[0];
+    *dist = g->dg.widest ? widest_xf(g->qbuf_h[0]) : g->qbuf_h[0];
     *on_len = g->qbuf_h[1];
     *key_len = g->qbuf_h[2];
     if (*on_len > on_cap || *key_len > key_cap) return fail(APSP_E_CAPACITY, "apsp_query_nodes: buffer too small");
@@ -789,11 +861,103 @@ apsp_status apsp_query_nodes(apsp_graph *g, int32_t i, int32_t j, int32_t *dist,
     return APSP_OK;
 }
 
+apsp_status apsp_query_paths(apsp_graph *g, int32_t i, int32_t j, int32_t *dist, int32_t *ids, int64_t ids_cap,
+                             int64_t *ids_len, int32_t *offsets, int32_t offsets_cap, int32_t *npaths) {
+    if (!g || !dist || !ids_len || !npaths) return fail(APSP_E_INVALID, "apsp_query_paths: NULL argument");
+    if (g->detached) return detached_error("apsp_query_paths");
+    if (ids_cap < 0 || (ids_cap > 0 && !ids) || offsets_cap < 0 || (offsets_cap > 0 && !offsets))
+        return fail(APSP_E_INVALID, "apsp_query_paths: bad output buffer");
+    int32_t si, sj;
+    if (!lookup(g, i, &si) || !lookup(g, j, &sj)) return fail(APSP_E_NOT_FOUND, "apsp_query_paths: id is not live");
+    const int32_t n = g->n_live;
+    // the nodes on some shortest path (the candidates), and the query's own path
+    std::vector<int32_t> on(std::max(n, 1)), key(std::max(n, 1)), first(std::max(n, 1));
+    int32_t d = 0, on_len = 0, key_len = 0, first_len = 0;
+    apsp_status st = apsp_query_nodes(g, i, j, &d, on.data(), n, &on_len, key.data(), n, &key_len);
+    if (st) return st;
+    *dist = d;
+    if (on_len == 0) {  // unreachable
+        *npaths = 0;
+        *ids_len = 0;
+        if (offsets_cap >= 1) offsets[0] = 0;
+        return offsets_cap >= 1 ? APSP_OK : fail(APSP_E_CAPACITY, "apsp_query_paths: offsets_cap too small");
+    }
+    if ((st = apsp_query(g, i, j, &d, first.data(), n, &first_len))) return st;
+    first.resize(first_len);
+    std::set<int32_t> on_first(first.begin(), first.end());
+    std::vector<int32_t> cand;  // slots of the candidates off the first path, ascending id
+    for (int32_t x = 0; x < on_len; ++x) {
+        const int32_t t = on[x];
+        if (t == i || t == j || on_first.count(t)) continue;
+        int32_t st_ = 0;
+        lookup(g, t, &st_);
+        cand.push_back(st_);
+    }
+    std::vector<std::vector<int32_t>> paths{first};
+    std::set<std::vector<int32_t>> seen{first};
+    // chunks of candidates, one work-group each, over the heavy-row scratch
+    // (idle between updates): candidate slots, 4 P words of query scratch
+    // per work-group, two query outputs of P + 3 words per work-group
+    const int64_t P = g->P, room = (int64_t)FUSED_GRID * 2 * P - 256;
+    const int32_t chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(128, room / (4 * P + 2 * (P + 3))));
+    int32_t *cslots = g->fscratch;
+    int32_t *qsc = g->fscratch + 256;
+    int32_t *qout = qsc + (int64_t)chunk * 4 * P;
+    hipStream_t s = g->stream;
+    std::vector<int32_t> hdr, buf;
+    for (size_t c0 = 0; c0 < cand.size(); c0 += chunk) {
+        const int32_t cnt = (int32_t)std::min<size_t>(chunk, cand.size() - c0);
+        if (!hip_ok(hipMemcpyAsync(cslots, cand.data() + c0, (size_t)cnt * 4, hipMemcpyHostToDevice, s), "paths copy"))
+            return APSP_E_DEVICE;
+        g->prof.begin(KID_QUERY);
+        SR(g, launch_query_paths)(g->dg, si, sj, cslots, cnt, qout, qsc, s);
+        g->prof.end();
+        if ((st = check_launch("apsp_query_paths"))) return st;
+        // the 2 cnt headers (dist, length, status), then the paths up to the longest
+        const size_t pitch = (size_t)(P + 3) * 4;
+        hdr.resize((size_t)2 * cnt * 3);
+        if (!hip_ok(hipMemcpy2DAsync(hdr.data(), 12, qout, pitch, 12, 2 * cnt, hipMemcpyDeviceToHost, s), "paths read") ||
+            !hip_ok(hipStreamSynchronize(s), "paths sync"))
+            return APSP_E_DEVICE;
+        int32_t longest = 0;
+        for (int32_t q = 0; q < 2 * cnt; ++q) {
+            if (hdr[3 * q + 2] != 0) return fail(APSP_E_DEVICE, "apsp_query_paths: no shortest path found on the device");
+            longest = std::max(longest, hdr[3 * q + 1]);
+        }
+        const size_t w = (size_t)(3 + longest) * 4;
+        buf.resize((size_t)2 * cnt * (3 + longest));
+        if (!hip_ok(hipMemcpy2DAsync(buf.data(), w, qout, pitch, w, 2 * cnt, hipMemcpyDeviceToHost, s), "paths read") ||
+            !hip_ok(hipStreamSynchronize(s), "paths sync"))
+            return APSP_E_DEVICE;
+        for (int32_t c = 0; c < cnt; ++c) {
+            const int32_t *a = buf.data() + (size_t)(2 * c) * (3 + longest);
+            const int32_t *b = buf.data() + (size_t)(2 * c + 1) * (3 + longest);
+            std::vector<int32_t> p(a + 3, a + 3 + a[1]);   // i -> t
+            p.insert(p.end(), b + 4, b + 3 + b[1]);         // t -> j without t
+            if (seen.insert(p).second) paths.push_back(std::move(p));
+        }
+    }
+    int64_t total = 0;
+    for (const auto &p : paths) total += (int64_t)p.size();
+    *npaths = (int32_t)paths.size();
+    *ids_len = total;
+    if (offsets_cap < (int32_t)paths.size() + 1 || ids_cap < total)
+        return fail(APSP_E_CAPACITY, "apsp_query_paths: output too small (npaths and ids_len give the sizes)");
+    int64_t off = 0;
+    for (size_t q = 0; q < paths.size(); ++q) {
+        offsets[q] = (int32_t)off;
+        std::copy(paths[q].begin(), paths[q].end(), ids + off);
+        off += (int64_t)paths[q].size();
+    }
+    offsets[paths.size()] = (int32_t)off;
+    return APSP_OK;
+}
+
 apsp_status apsp_read_matrix(apsp_graph *g, int32_t *out_dev, int64_t out_ld) {
     if (!g) return fail(APSP_E_INVALID, "apsp_read_matrix: NULL graph");
     if (g->detached) return detached_error("apsp_read_matrix");
     if (g->n_live > 0 && (!out_dev || out_ld < g->n_live)) return fail(APSP_E_INVALID, "apsp_read_matrix: bad output");
-    launch_gather_compact(g->dg.D, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->stream);
+    launch_gather_compact(g->dg.D, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->dg.widest, g->stream);
     return check_launch("apsp_read_matrix");
 }
 
@@ -802,7 +966,7 @@ apsp_status apsp_read_adjacency(apsp_graph *g, int32_t *out_dev, int64_t out_ld)
     if (g->detached) return detached_error("apsp_read_adjacency");
     if (g->n_live > 0 && (!out_dev || out_ld < g->n_live))
         return fail(APSP_E_INVALID, "apsp_read_adjacency: bad output");
-    launch_gather_compact(g->dg.A, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->stream);
+    launch_gather_compact(g->dg.A, g->dg.ld, out_dev, out_ld, g->rank_cur, g->n_live, g->dg.widest, g->stream);
     return check_launch("apsp_read_adjacency");
 }
 
@@ -870,6 +1034,7 @@ apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
         out->cost_refined = g->last_n_before > 1 ? (double)c.rows_changed / (double)(g->last_n_before - 1) : 0.0;
     }
     if (kind == UK_REMOVE) out->noop = c.flagged == 0 && !g->last_fallback;
+    out->route = kind == UK_REMOVE ? g->last_route : 0;
     return APSP_OK;
 }
 

@@ -68,7 +68,18 @@ struct DevGraph {
     int32_t n_slots;      // slots [0, n_slots) may be live
     int32_t undirected;
     int32_t lim;          // usable index entries (1..NIN_L)
+    int32_t widest;       // widest-path graph: weights stored as WIDEST_TOP - capacity (see widest_xf)
 };
+
+// Widest (maximum-capacity) paths run as minimax paths over transformed
+// weights: a capacity c in [0, WIDEST_TOP] is stored as WIDEST_TOP - c, so
+// the largest over paths of the smallest capacity is WIDEST_TOP minus the
+// least over paths of the largest stored weight.  INF (no edge / no path)
+// maps to itself; the map is its own inverse on [0, WIDEST_TOP].
+constexpr uint32_t WIDEST_TOP = INF - 1;
+__host__ __device__ inline int32_t widest_xf(int32_t v) {
+    return (uint32_t)v <= WIDEST_TOP ? (int32_t)(WIDEST_TOP - (uint32_t)v) : v;
+}
 
 // Row y of the in-edge matrix: Min[y][x] = A[x][y].
 __host__ __device__ inline const int32_t *in_matrix(const DevGraph &g) {

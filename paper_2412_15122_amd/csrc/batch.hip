@@ -141,6 +141,10 @@ __device__ __forceinline__ void add_setup(const DevGraph &g, const BatchGraph &b
         int bad = 0;
         if (a < 0 || (uint32_t)a > INF) { a = (int32_t)INF; bad = 1; }
         if (b < 0 || (uint32_t)b > INF) { b = (int32_t)INF; bad = 1; }
+        if (g.widest) {
+            a = widest_xf(a);
+            b = widest_xf(b);
+        }
         wo[s] = a;
         wi[s] = b;
         if (bad) atomicOr(&g.ctl->err, (int32_t)ERR_VALUE);
@@ -288,17 +292,18 @@ __device__ __forceinline__ void add_prologue(const DevGraph &g, const BatchGraph
 }
 
 // Theorem 3 over rows [r0, r1): D[i][j] = min(D[i][j], in[i] (+) out[j]).
-// outv: the new row (LDS stage or global).
-template <int U>
-__device__ __forceinline__ void add_relax_rows(const DevGraph &g, const BatchGraph &bg, int32_t r0, int32_t r1, const uint32_t *outv) {
+// outv: the new row (LDS stage or global); in_of(i): in[i] (from the graph's
+// vector or an LDS copy of the chunk's rows).
+template <int U, class InOf>
+__device__ __forceinline__ void add_relax_rows(const DevGraph &g, const BatchGraph &bg, int32_t r0, int32_t r1, const uint32_t *outv,
+                                               InOf in_of) {
     const int n = g.n_slots;
-    const int32_t *in = g.undirected ? bg.vout : bg.vin;
     stream_chunks<U>(
-        g, n, r0, r1, [&](int32_t i) { return (uint32_t)in[i] < INF; },
+        g, n, r0, r1, [&](int32_t i) { return in_of(i) < INF; },
         [&](int32_t c0) { return Vec2{vec4(outv, c0, n), make_uint4(0, 0, 0, 0)}; },
         [&](int32_t i, int32_t c0, bool ok, uint4 d, const Vec2 &v) {
             if (!ok) return;
-            const uint32_t a = (uint32_t)in[i];
+            const uint32_t a = in_of(i);
             const uint4 o = v.a;
             store_min4(g, i, c0, d, make_uint4(cat(a, o.x), cat(a, o.y), cat(a, o.z), cat(a, o.w)));
         });
@@ -378,9 +383,11 @@ __device__ inline FusedArgs increase_args(const DevGraph &g, const BatchGraph &b
 // Flags of rows [r0, r1) into the graph's bitmap (8 lanes assemble each
 // 32-column word with shuffles) and the row marks.  S1 / S2: the pair test's
 // row vectors (LDS stage or global; S2 used only when fa.row2 is set).
-template <int U>
-__device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa, uint32_t w_old, int32_t r0,
-                            int32_t r1, const uint32_t *S1, const uint32_t *S2) {
+// tests(i): the row's pair tests (row_tests over the graph's vectors, or an
+// LDS copy of the chunk's rows).
+template <int U, class Tests>
+__device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa, int32_t r0,
+                            int32_t r1, const uint32_t *S1, const uint32_t *S2, Tests tests) {
     const int lane = lane_id();
     const int n = g.n_slots;
     const int64_t nwp = (g.P + 31) / 32;
@@ -388,7 +395,7 @@ __device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph 
     stream_chunks<U>(
         g, n, r0, r1,
         [&](int32_t i) {
-            const RowTests rt = row_tests(g, fa, i, w_old);
+            const RowTests rt = tests(i);
             return rt.t1 || rt.t2;
         },
         [&](int32_t c0) {
@@ -398,7 +405,7 @@ __device__ __forceinline__ void detect_rows(const DevGraph &g, const BatchGraph 
         [&](int32_t i, int32_t c0, bool ok, uint4 d, const Vec2 &v) {
             uint32_t bits = 0;
             if (ok) {
-                const RowTests rt = row_tests(g, fa, i, w_old);
+                const RowTests rt = tests(i);
                 const uint4 v1 = v.a;
                 const uint4 v2 = v.b;
                 const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
@@ -711,16 +718,18 @@ __device__ __forceinline__ void edge_prologue(const DevGraph &g, const BatchGrap
 // Relaxation through the lowered edge over rows [r0, r1): D[i][j] vs
 // D[i][u] (+) w (+) D[v][j] (and D[i][v] (+) w (+) D[u][j] when undirected), rows
 // that cannot change filtered first.  SV / SU: rows v and u (LDS or global).
-template <int U>
+// cu(i), cv(i): D[i][u] and D[i][v] (the graph's vectors or an LDS copy of
+// the chunk's rows).
+template <int U, class ColU, class ColV>
 __device__ __forceinline__ void dec_relax_rows(const DevGraph &g, const BatchGraph &bg, int32_t w, int32_t r0, int32_t r1,
-                               const uint32_t *SV, const uint32_t *SU) {
+                               const uint32_t *SV, const uint32_t *SU, ColU cu, ColV cv) {
     const bool und = g.undirected != 0;
     const uint32_t wn = (uint32_t)w;
     const int n = g.n_slots;
     stream_chunks<U>(
         g, n, r0, r1,
         [&](int32_t i) {
-            const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
+            const uint32_t du = cu(i), dv = cv(i);
             return cat(du, wn) < dv || (und && cat(dv, wn) < du);
         },
         [&](int32_t c0) {
@@ -728,7 +737,7 @@ __device__ __forceinline__ void dec_relax_rows(const DevGraph &g, const BatchGra
         },
         [&](int32_t i, int32_t c0, bool ok, uint4 d, const Vec2 &v) {
             if (!ok) return;
-            const uint32_t du = (uint32_t)bg.colu[i], dv = (uint32_t)bg.colv[i];
+            const uint32_t du = cu(i), dv = cv(i);
             const uint32_t x1 = cat(du, wn) < dv ? cat(du, wn) : INF;
             const uint32_t x2 = und && cat(dv, wn) < du ? cat(dv, wn) : INF;
             const uint4 rv = v.a;
@@ -870,6 +879,13 @@ __device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGr
     __syncthreads();
 }
 
+// Algorithm 7's query; a widest graph's distance goes out as a width.
+__device__ __forceinline__ void batch_query(const DevGraph &g, const BatchGraph &bg, const BatchItem &it) {
+    query_block(g, it.a, it.b, it.out, bg.qscratch);
+    if (g.widest && threadIdx.x == 0) it.out[0] = widest_xf(it.out[0]);  // the thread that wrote it
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // schedule 1: work queue (one work-group per graph, all phases)
 // ---------------------------------------------------------------------------
@@ -882,7 +898,7 @@ __device__ __forceinline__ void run_item_alone(const DevGraph &g, const BatchGra
     case BOP_ADD:
         add_prologue(g, bg, it, ssh, stage);
         stage_rows(stage, g.P, n, bg.vout, nullptr);
-        add_relax_rows<U>(g, bg, 0, n, stage);
+        add_relax_rows<U>(g, bg, 0, n, stage, [&](int32_t i) { return (uint32_t)(g.undirected ? bg.vout : bg.vin)[i]; });
         __syncthreads();
         add_epilogue(g, bg, it);
         break;
@@ -890,7 +906,7 @@ __device__ __forceinline__ void run_item_alone(const DevGraph &g, const BatchGra
         remove_prologue(g, bg, it);
         const FusedArgs fa = remove_args(bg, it);
         stage_rows(stage, g.P, n, fa.row1, nullptr);
-        detect_rows<U>(g, bg, fa, 0, 0, n, stage, stage + g.P);
+        detect_rows<U>(g, bg, fa, 0, n, stage, stage + g.P, [&](int32_t i) { return row_tests(g, fa, i, 0u); });
         __syncthreads();
         recompute_rows(g, bg, fa, 0, n, wlists, bg.scratch, stage);
         __syncthreads();
@@ -902,12 +918,14 @@ __device__ __forceinline__ void run_item_alone(const DevGraph &g, const BatchGra
         const int32_t mode = g.ctl->edge_mode;
         if (mode == EDGE_DECREASE) {
             stage_rows(stage, g.P, n, bg.rowv, g.undirected ? bg.rowu : nullptr);
-            dec_relax_rows<U>(g, bg, it.c, 0, n, stage, stage + g.P);
+            dec_relax_rows<U>(g, bg, it.c, 0, n, stage, stage + g.P, [&](int32_t i) { return (uint32_t)bg.colu[i]; },
+                              [&](int32_t i) { return (uint32_t)bg.colv[i]; });
             __syncthreads();
         } else if (mode == EDGE_INCREASE) {
             const FusedArgs fa = increase_args(g, bg);
             stage_rows(stage, g.P, n, fa.row1, fa.row2);
-            detect_rows<U>(g, bg, fa, (uint32_t)g.ctl->w_old, 0, n, stage, stage + g.P);
+            const uint32_t w_old = (uint32_t)g.ctl->w_old;
+            detect_rows<U>(g, bg, fa, 0, n, stage, stage + g.P, [&](int32_t i) { return row_tests(g, fa, i, w_old); });
             __syncthreads();
             recompute_rows(g, bg, fa, 0, n, wlists, bg.scratch, stage);
             __syncthreads();
@@ -915,7 +933,7 @@ __device__ __forceinline__ void run_item_alone(const DevGraph &g, const BatchGra
         edge_epilogue(g, bg, it, ssh, stage);
         break;
     }
-    case BOP_QUERY: query_block(g, it.a, it.b, it.out, bg.qscratch); break;
+    case BOP_QUERY: batch_query(g, bg, it); break;
     default: break;
     }
     __syncthreads();
@@ -991,8 +1009,15 @@ __device__ __forceinline__ void grid_barrier(BatchHeader *hdr) {
 }
 
 // Chunk c of a step's sweep table -> graph (base: prefix of chunk counts).
-__device__ inline int32_t chunk_graph(const int32_t *base, int32_t num_graphs, int32_t c) {
-    int32_t lo = 0, hi = num_graphs;  // base[lo] <= c < base[hi]
+// lo: a graph at or before the answer (the previous chunk's graph: a
+// work-group's chunks only move forward); the search gallops from there.
+__device__ inline int32_t chunk_graph(const int32_t *base, int32_t num_graphs, int32_t c, int32_t lo = 0) {
+    int32_t hi = lo + 1, step = 1;  // base[lo] <= c
+    while (hi < num_graphs && base[hi] <= c) {
+        lo = hi;
+        step <<= 1;
+        hi = min(num_graphs, lo + step);
+    }
     while (hi - lo > 1) {
         const int32_t mid = (lo + hi) >> 1;
         if (base[mid] <= c) lo = mid;
@@ -1002,7 +1027,7 @@ __device__ inline int32_t chunk_graph(const int32_t *base, int32_t num_graphs, i
 }
 
 template <int U>
-__global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs,
+__global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs,
                                                                      const BatchItem *items, const int32_t *tables) {
     extern __shared__ __align__(16) uint32_t stage[];  // P words of select staging, then the wave lists / need bitmap
     __shared__ SelectShared ssh;
@@ -1034,7 +1059,7 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
                 if (it.op == BOP_ADD) add_setup(g, bg, it, ssh, stage);
                 else if (it.op == BOP_REMOVE) remove_prologue(g, bg, it);
                 else if (it.op == BOP_EDGE) edge_prologue(g, bg, it);
-                else if (it.op == BOP_QUERY) query_block(g, it.a, it.b, it.out, bg.qscratch);
+                else if (it.op == BOP_QUERY) batch_query(g, bg, it);
                 if (s == cnt - 1 && it.op == BOP_QUERY && threadIdx.x == 0)
                     hdr->times[2 * bg.index + 1] = wall_clock64();
             }
@@ -1045,8 +1070,8 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
         // A2: the new row and column of every added node, spread over the grid
         const int32_t *baseA2 = tables + (int64_t)s * BATCH_TABLES * (G + 1);
         if (baseA2[G] > 0) {
-            for (int32_t c = blockIdx.x; c < baseA2[G]; c += gridDim.x) {
-                const int32_t gi = chunk_graph(baseA2, G, c);
+            for (int32_t c = blockIdx.x, gi = 0; c < baseA2[G]; c += gridDim.x) {
+                gi = chunk_graph(baseA2, G, c, gi);
                 const BatchGraph &bg = graphs[gi];
                 const BatchItem it = items[bg.item_begin + s];
                 DevGraph g = bg.g;
@@ -1062,30 +1087,83 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
         // rows); the wavefronts of a work-group go on to its next chunk
         // without waiting for each other (the sweeps share nothing in LDS)
         const int32_t *baseB = baseA2 + (G + 1);
-        for (int32_t c = blockIdx.x; c < baseB[G]; c += gridDim.x) {
-            const int32_t gi = chunk_graph(baseB, G, c);
+        const bool staged = lockstep_stages_sweeps(P_max);
+        for (int32_t c = blockIdx.x, gi = 0; c < baseB[G]; c += gridDim.x) {
+            gi = chunk_graph(baseB, G, c, gi);
             const BatchGraph &bg = graphs[gi];
             const BatchItem it = items[bg.item_begin + s];
             DevGraph g = bg.g;
             g.n_slots = it.n_slots;
             const int32_t rpc = batch_rows_per_chunk(it.n_slots);
             const int32_t r0 = (c - baseB[gi]) * rpc, r1 = min(r0 + rpc, it.n_slots);
+            const int32_t mode = it.op == BOP_EDGE ? g.ctl->edge_mode : EDGE_NOOP;
+            // the chunk's inputs besides D: one or two row vectors (the
+            // columns' side of the pair test or relaxation) and one or two
+            // values per row (its side); with `staged`, copied to LDS once
+            // per chunk so that a wavefront's pieces wait only for D
+            const int32_t *vsrc1 = nullptr, *vsrc2 = nullptr, *rsrc1 = nullptr, *rsrc2 = nullptr;
             if (it.op == BOP_ADD) {
-                add_relax_rows<U>(g, bg, r0, r1, reinterpret_cast<const uint32_t *>(bg.vout));
+                vsrc1 = bg.vout;
+                rsrc1 = g.undirected ? bg.vout : bg.vin;
+            } else if (it.op == BOP_REMOVE) {
+                vsrc1 = bg.rowu;
+                rsrc1 = bg.colu;
+            } else if (mode == EDGE_DECREASE || mode == EDGE_INCREASE) {
+                vsrc1 = bg.rowv;
+                vsrc2 = g.undirected ? bg.rowu : nullptr;
+                rsrc1 = bg.colu;
+                rsrc2 = bg.colv;
+            } else {
+                continue;  // block-uniform: a no-op edge update or a query sweeps nothing
+            }
+            const uint32_t *S1 = reinterpret_cast<const uint32_t *>(vsrc1);
+            const uint32_t *S2 = reinterpret_cast<const uint32_t *>(vsrc2);
+            const uint32_t *T1 = reinterpret_cast<const uint32_t *>(rsrc1) + r0;
+            const uint32_t *T2 = reinterpret_cast<const uint32_t *>(rsrc2 ? rsrc2 + r0 : nullptr);
+            if (staged) {
+                uint32_t *v1 = stage, *v2 = stage + P_max, *t1 = stage + 2 * P_max, *t2 = t1 + LOCKSTEP_STAGE_ROWS;
+                __syncthreads();  // the previous chunk's readers are done
+                const int32_t n4 = (it.n_slots + 3) & ~3;
+                for (int32_t x = threadIdx.x; x < n4; x += BATCH_THREADS) {
+                    v1[x] = x < it.n_slots ? (uint32_t)vsrc1[x] : INF;
+                    if (vsrc2) v2[x] = x < it.n_slots ? (uint32_t)vsrc2[x] : INF;
+                }
+                for (int32_t r = threadIdx.x; r < r1 - r0; r += BATCH_THREADS) {
+                    t1[r] = (uint32_t)rsrc1[r0 + r];
+                    if (rsrc2) t2[r] = (uint32_t)rsrc2[r0 + r];
+                }
+                __syncthreads();
+                S1 = v1;
+                S2 = vsrc2 ? v2 : nullptr;
+                T1 = t1;
+                T2 = rsrc2 ? t2 : nullptr;
+            }
+            if (it.op == BOP_ADD) {
+                add_relax_rows<U>(g, bg, r0, r1, S1, [&](int32_t i) { return T1[i - r0]; });
             } else if (it.op == BOP_REMOVE) {
                 const FusedArgs fa = remove_args(bg, it);
-                detect_rows<U>(g, bg, fa, 0, r0, r1, reinterpret_cast<const uint32_t *>(fa.row1), nullptr);
-            } else if (it.op == BOP_EDGE) {
-                const int32_t mode = g.ctl->edge_mode;
-                if (mode == EDGE_DECREASE) {
-                    dec_relax_rows<U>(g, bg, it.c, r0, r1, reinterpret_cast<const uint32_t *>(bg.rowv),
-                                      reinterpret_cast<const uint32_t *>(bg.rowu));
-                } else if (mode == EDGE_INCREASE) {
-                    const FusedArgs fa = increase_args(g, bg);
-                    detect_rows<U>(g, bg, fa, (uint32_t)g.ctl->w_old, r0, r1,
-                                   reinterpret_cast<const uint32_t *>(fa.row1),
-                                   reinterpret_cast<const uint32_t *>(fa.row2));
-                }
+                const int32_t k = it.a;
+                detect_rows<U>(g, bg, fa, r0, r1, S1, nullptr, [&](int32_t i) {
+                    const uint32_t dik = T1[i - r0];
+                    return RowTests{i != k && dik < INF, false, dik, 0u};
+                });
+            } else if (mode == EDGE_DECREASE) {
+                dec_relax_rows<U>(g, bg, it.c, r0, r1, S1, S2, [&](int32_t i) { return T1[i - r0]; },
+                                  [&](int32_t i) { return T2[i - r0]; });
+            } else {
+                const FusedArgs fa = increase_args(g, bg);
+                const uint32_t w_old = (uint32_t)g.ctl->w_old;
+                const bool und = g.undirected != 0;
+                detect_rows<U>(g, bg, fa, r0, r1, S1, S2, [&](int32_t i) {
+                    // the pair tests of row_tests for an increase, from the copies
+                    const uint32_t cu = T1[i - r0], cv = T2[i - r0];
+                    RowTests r{cv < INF && cat(cu, w_old) == cv, false, cv, 0u};
+                    if (und) {
+                        r.t2 = cu < INF && cat(cv, w_old) == cu;
+                        r.a2 = cu;
+                    }
+                    return r;
+                });
             }
         }
         // C: recompute of the flagged rows (removal, edge increase)
@@ -1094,8 +1172,8 @@ __global__ __launch_bounds__(BATCH_THREADS, 2) void k_batch_lockstep(BatchHeader
             grid_barrier(hdr);
             if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s + 1 < BATCH_PHASE_STAMPS)
                 hdr->phase_ts[3 * s + 1] = wall_clock64();
-            for (int32_t c = blockIdx.x; c < baseC[G]; c += gridDim.x) {
-                const int32_t gi = chunk_graph(baseC, G, c);
+            for (int32_t c = blockIdx.x, gi = 0; c < baseC[G]; c += gridDim.x) {
+                gi = chunk_graph(baseC, G, c, gi);
                 const BatchGraph &bg = graphs[gi];
                 const BatchItem it = items[bg.item_begin + s];
                 DevGraph g = bg.g;
@@ -1173,7 +1251,9 @@ size_t batch_lds_bytes(int32_t P_max) { return (2 * (size_t)P_max + 4 * 2 * ROW_
 // recompute phase, and later the need bitmap of the heavy-row phase (one bit
 // per column): whichever is larger.
 size_t batch_lockstep_lds_bytes(int32_t P_max) {
-    return ((size_t)P_max + std::max<size_t>(4 * 2 * ROW_CAP, ((size_t)P_max + 31) / 32)) * sizeof(uint32_t);
+    size_t words = (size_t)P_max + std::max<size_t>(4 * 2 * ROW_CAP, ((size_t)P_max + 31) / 32);
+    if (lockstep_stages_sweeps(P_max)) words = std::max<size_t>(words, 2 * (size_t)P_max + 2 * LOCKSTEP_STAGE_ROWS);
+    return words * sizeof(uint32_t);
 }
 
 hipError_t configure_batch() {

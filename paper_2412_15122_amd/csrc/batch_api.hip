@@ -339,7 +339,7 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
             bi.op = BOP_EDGE;
             bi.a = su;
             bi.b = sv;
-            bi.c = x.w;
+            bi.c = g->dg.widest ? widest_xf(x.w) : x.w;
             last_kind[x.graph] = -1;
             last_n[x.graph] = g->n_live;
         } else if (x.op == APSP_OP_QUERY) {

@@ -80,6 +80,14 @@ __host__ __device__ inline int32_t batch_rows_per_chunk(int32_t n) {
     return r < 16 ? 16 : r;  // a multiple of 16: a wavefront's rows share a word of row marks
 }
 
+// Lockstep row sweeps copy a chunk's row vectors (2 x P_max words) and its
+// rows' test values (2 x LOCKSTEP_STAGE_ROWS words) to LDS when the batch's
+// largest pitch keeps that small; a chunk holds at most min(rows per chunk,
+// n) <= 256 rows (rows per chunk <= 65536 / n).
+constexpr int32_t LOCKSTEP_STAGE_ROWS = 256;
+constexpr int32_t LOCKSTEP_STAGE_MAX_PITCH = 4608;
+__host__ __device__ inline bool lockstep_stages_sweeps(int32_t P_max) { return P_max <= LOCKSTEP_STAGE_MAX_PITCH; }
+
 #include "batch_launchers.inc"
 namespace mm {
 #include "batch_launchers.inc"

@@ -63,6 +63,7 @@ __global__ void k_load_adj(DevGraph g, const int32_t *__restrict__ adj, int64_t 
         if (w2 != w) bad = 1;
         w = min(w, w2);
     }
+    if (g.widest) w = widest_xf(w);
     if (i == j) { w = 0; bad = 0; }
     g.A[(int64_t)i * g.ld + j] = w;
     if (bad) atomicOr(&g.ctl->err, (int32_t)ERR_VALUE);
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(256) void k_import_d(DevGraph g, const int32_t *__r
         const int32_t raw = src[(int64_t)i * src_ld + j];
         int32_t w = raw;
         if (w < 0 || (uint32_t)w > INF) { w = (int32_t)INF; b = 1; }
+        if (g.widest) w = widest_xf(w);  // the checks below hold for the stored form
         if (i == j && w != 0) b = 1;
         if ((uint32_t)w > (uint32_t)g.A[(int64_t)i * g.ld + j]) b = 1;
         if (g.undirected && src[(int64_t)j * src_ld + i] != raw) b = 1;
@@ -142,19 +144,21 @@ void launch_import_d(const DevGraph &g, const int32_t *src, int64_t src_ld, int3
 // *bad += #{(i, j) in [0, n)^2 : a[i][j] != b[i][j]} (one atomic per wave).
 __global__ __launch_bounds__(256) void k_count_diff(const int32_t *__restrict__ a, int64_t lda,
                                                     const int32_t *__restrict__ b, int64_t ldb, int32_t n,
-                                                    int32_t *bad) {
+                                                    int32_t *bad, int32_t widest) {
     const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t i = blockIdx.y;
-    const int d = j < n && a[(int64_t)i * lda + j] != b[(int64_t)i * ldb + j];
+    int32_t bv = j < n ? b[(int64_t)i * ldb + j] : 0;
+    if (widest) bv = widest_xf(bv);
+    const int d = j < n && a[(int64_t)i * lda + j] != bv;
     const unsigned long long m = __ballot(d);
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(bad, (int32_t)__popcll(m));
 }
 
 void launch_count_diff(const int32_t *a, int64_t lda, const int32_t *b, int64_t ldb, int32_t n, int32_t *bad,
-                       hipStream_t s) {
+                       int32_t widest, hipStream_t s) {
     if (n <= 0) return;
     dim3 grid((n + 255) / 256, n);
-    k_count_diff<<<grid, 256, 0, s>>>(a, lda, b, ldb, n, bad);
+    k_count_diff<<<grid, 256, 0, s>>>(a, lda, b, ldb, n, bad, widest);
 }
 
 // ---------------------------------------------------------------------------

@@ -141,6 +141,7 @@ struct apsp_graph {
     int32_t policy = APSP_FALLBACK_NEVER;
     double delta = 0.5;
     int32_t last_kind = apsp_host::UK_NONE, last_n_before = 0, last_fallback = 0;
+    int32_t last_route = 0;  // 1: the last removal took the spanning-forest route
     apsp::Ctl *ctl_h = nullptr;   // pinned
     int32_t *qbuf_h = nullptr;  // pinned
     ProfImpl prof_impl;

@@ -18,6 +18,26 @@ void launch_query(const DevGraph &g, int32_t si, int32_t sj, int32_t *out, int32
     k_query<<<1, 1024, 0, s>>>(g, si, sj, out, scratch);
 }
 
+// Algorithm 8's paths through the candidates cand[0..count): work-group c
+// writes the path si -> cand[c] and then cand[c] -> sj, each as query_block
+// does (3 + P words from out + 2 c (P + 3)), over its own 4 P words of
+// scratch.
+__global__ __launch_bounds__(1024) void k_query_paths(DevGraph g, int32_t si, int32_t sj, const int32_t *cand,
+                                                      int32_t *out, int32_t *scratch) {
+    const int32_t c = blockIdx.x;
+    const int32_t t = cand[c];
+    int32_t *sc = scratch + (int64_t)c * 4 * g.P;
+    int32_t *o = out + (int64_t)c * 2 * (g.P + 3);
+    query_block(g, si, t, o, sc);
+    __syncthreads();
+    query_block(g, t, sj, o + g.P + 3, sc);
+}
+
+void launch_query_paths(const DevGraph &g, int32_t si, int32_t sj, const int32_t *cand, int32_t count, int32_t *out,
+                        int32_t *scratch, hipStream_t s) {
+    if (count > 0) k_query_paths<<<count, 1024, 0, s>>>(g, si, sj, cand, out, scratch);
+}
+
 #ifdef APSP_SEMIRING_MINIMAX
 // ---- a minimax path of a pair ------------------------------------------------
 // With max in place of +, Algorithm 7's candidate set keeps most of the graph
@@ -454,18 +474,19 @@ const char *launch_query_nodes_bottleneck(const DevGraph &g, int32_t si, int32_t
 
 // dst[a][b] = src[slot[a]][slot[b]] for a, b < n.
 __global__ void k_gather_compact(const int32_t *__restrict__ src, int64_t ld, int32_t *__restrict__ dst,
-                                 int64_t dst_ld, const int32_t *__restrict__ slot, int32_t n) {
+                                 int64_t dst_ld, const int32_t *__restrict__ slot, int32_t n, int32_t widest) {
     const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t a = blockIdx.y;
     if (b >= n) return;
-    dst[(int64_t)a * dst_ld + b] = src[(int64_t)slot[a] * ld + slot[b]];
+    const int32_t v = src[(int64_t)slot[a] * ld + slot[b]];
+    dst[(int64_t)a * dst_ld + b] = widest ? widest_xf(v) : v;
 }
 
 void launch_gather_compact(const int32_t *src, int64_t ld, int32_t *dst, int64_t dst_ld,
-                           const int32_t *slot_of_rank, int32_t n, hipStream_t s) {
+                           const int32_t *slot_of_rank, int32_t n, int32_t widest, hipStream_t s) {
     if (n <= 0) return;
     dim3 grid((n + 255) / 256, n);
-    k_gather_compact<<<grid, 256, 0, s>>>(src, ld, dst, dst_ld, slot_of_rank, n);
+    k_gather_compact<<<grid, 256, 0, s>>>(src, ld, dst, dst_ld, slot_of_rank, n, widest);
 }
 
 // |R| and |C| of edge su -> sv at its current weight.

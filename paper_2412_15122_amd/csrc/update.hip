@@ -146,6 +146,10 @@ __global__ void k_scatter_weights(DevGraph g, const int32_t *__restrict__ w_out,
     int bad = 0;
     if (a < 0 || (uint32_t)a > INF) { a = (int32_t)INF; bad = 1; }
     if (b < 0 || (uint32_t)b > INF) { b = (int32_t)INF; bad = 1; }
+    if (g.widest) {
+        a = widest_xf(a);
+        b = widest_xf(b);
+    }
     wo[s] = a;
     wi[s] = b;
     if (bad) atomicOr(&g.ctl->err, (int32_t)ERR_VALUE);
@@ -250,6 +254,72 @@ __global__ __launch_bounds__(256) void k_add_in(DevGraph g, int32_t p, const int
 void launch_add_in(const DevGraph &g, int32_t p, const int32_t *wi, int32_t *in, hipStream_t s) {
     if (g.n_slots <= 0) return;
     k_add_in<<<(g.n_slots + 3) / 4, 256, 0, s>>>(g, p, wi, in);
+}
+
+// Row-stationary streaming, for the edge update's sweep and the count-only
+// removal mask: a work-group owns SWEEP_ROWS consecutive rows, evaluates
+// their row-side values once, then walks the rows' columns in tiles of 1024
+// (256 lanes x 4 columns), loading each tile's rows of D (non-temporal: D is
+// streamed once) together with the slices of the row vectors, so a tile
+// waits on one round trip.  (The add relaxation and the removal mask, which
+// sweep every row, keep one tile per work-group: over the whole matrix
+// that order streams D faster on this part.)  The tile count is the same for
+// every lane of a wavefront (lanes past n load nothing), so the cross-lane
+// steps of a tile body see every lane.
+constexpr int SWEEP_ROWS = 8;
+
+template <int R>
+struct SweepTile {
+    uint4 d[R];
+    uint4 v1, v2;
+};
+
+// 4 consecutive entries of a row vector at c0 (INF from column n on).
+__device__ __forceinline__ uint4 vec_slice(const int32_t *v, int32_t c0, int32_t n) {
+    if (c0 + 3 < n) return *reinterpret_cast<const uint4 *>(v + c0);
+    return make_uint4(c0 < n ? (uint32_t)v[c0] : INF, c0 + 1 < n ? (uint32_t)v[c0 + 1] : INF,
+                      c0 + 2 < n ? (uint32_t)v[c0 + 2] : INF, c0 + 3 < n ? (uint32_t)v[c0 + 3] : INF);
+}
+
+// Loads of one tile: rows r0 + r with bit r of `act`, and the slices of v1
+// (and v2 when given) at column c0.
+template <int R>
+__device__ __forceinline__ void sweep_load(SweepTile<R> &t, const DevGraph &g, int32_t r0, uint32_t act, int32_t c0,
+                                           int32_t n, const int32_t *v1, const int32_t *v2) {
+    const bool ok = c0 < n;
+    t.v1 = ok ? vec_slice(v1, c0, n) : make_uint4(INF, INF, INF, INF);
+    t.v2 = ok && v2 ? vec_slice(v2, c0, n) : make_uint4(INF, INF, INF, INF);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        t.d[r] = make_uint4(INF, INF, INF, INF);
+        if (ok && ((act >> r) & 1u)) t.d[r] = load_stream4(g.D + (int64_t)(r0 + r) * g.ld + c0);
+    }
+}
+
+// Calls body(tile, c0, t) for every tile t of the rows' columns [0, n),
+// c0 = 1024 t + 4 lane-in-block.
+template <int R, class Body>
+__device__ __forceinline__ void sweep_rows(const DevGraph &g, int32_t r0, uint32_t act, int32_t n, const int32_t *v1,
+                                           const int32_t *v2, Body body) {
+    const int32_t tiles = (n + 1023) >> 10;
+    int32_t c0 = threadIdx.x * 4;
+    SweepTile<R> T;
+    for (int32_t t = 0; t < tiles; ++t, c0 += 1024) {
+        sweep_load<R>(T, g, r0, act, c0, n, v1, v2);
+        body(T, c0, t);
+    }
+}
+
+// D[i][c0..c0+3] := min(D, t) over columns below n, stored only when
+// something changed.
+__device__ __forceinline__ void store_min_if_lower(const DevGraph &g, int32_t i, int32_t c0, uint4 x, uint4 t) {
+    if (t.x < x.x || t.y < x.y || t.z < x.z || t.w < x.w) {
+        x.x = min(x.x, t.x);
+        x.y = min(x.y, t.y);
+        x.z = min(x.z, t.z);
+        x.w = min(x.w, t.w);
+        *reinterpret_cast<uint4 *>(g.D + (int64_t)i * g.ld + c0) = x;
+    }
 }
 
 // Theorem 3: D[i][j] = min(D[i][j], in[i] (+) out[j]) over the old
@@ -438,53 +508,39 @@ void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int
 //   D'[i][j] = min(D[i][j], D[i][u] (+) w (+) D[v][j])   (and v -> u if undirected).
 // Only rows with D[i][u] (+) w < D[i][v] can change.  The column / row vectors
 // were gathered before this launch, so in-place writes do not feed back.
-__device__ __forceinline__ void dec_relax_tile(const DevGraph &g, const int32_t *__restrict__ colu,
+// The rows r0 .. r0 + SWEEP_ROWS - 1 of one work-group.
+__device__ __forceinline__ void dec_relax_rows(const DevGraph &g, const int32_t *__restrict__ colu,
                                                const int32_t *__restrict__ colv, const int32_t *__restrict__ rowu,
-                                               const int32_t *__restrict__ rowv, int32_t w, int32_t rg) {
+                                               const int32_t *__restrict__ rowv, int32_t w, int32_t r0) {
     const int n = g.n_slots;
-    const int32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
-    const int32_t r0 = rg * RELAX_ROWS;
-    if (c0 >= n) return;
     const uint32_t wn = (uint32_t)w;
-    uint4 bv = *reinterpret_cast<const uint4 *>(rowv + c0);
-    uint4 bu = make_uint4(INF, INF, INF, INF);
-    if (g.undirected) bu = *reinterpret_cast<const uint4 *>(rowu + c0);
-    if (c0 + 1 >= n) { bv.y = INF; bu.y = INF; }
-    if (c0 + 2 >= n) { bv.z = INF; bu.z = INF; }
-    if (c0 + 3 >= n) { bv.w = INF; bu.w = INF; }
-    uint32_t x1[RELAX_ROWS], x2[RELAX_ROWS];
-    uint4 d[RELAX_ROWS];
-    int rows = 0;
+    uint32_t x1[SWEEP_ROWS], x2[SWEEP_ROWS];
+    uint32_t act = 0;
 #pragma unroll
-    for (int r = 0; r < RELAX_ROWS; ++r) {  // every changing row's load first
+    for (int r = 0; r < SWEEP_ROWS; ++r) {
         const int32_t i = r0 + r;
         x1[r] = x2[r] = INF;
-        d[r] = make_uint4(0, 0, 0, 0);
         if (i < n) {
             const uint32_t du = (uint32_t)colu[i], dv = (uint32_t)colv[i];
             if (cat(du, wn) < dv) x1[r] = cat(du, wn);
             if (g.undirected && cat(dv, wn) < du) x2[r] = cat(dv, wn);
-            if (x1[r] < INF || x2[r] < INF) {
-                ++rows;
-                d[r] = *reinterpret_cast<const uint4 *>(g.D + (int64_t)i * g.ld + c0);
-            }
+            if (x1[r] < INF || x2[r] < INF) act |= 1u << r;
         }
     }
+    if (act == 0) return;  // block-uniform
+    if (threadIdx.x == 0) atomicAdd(&g.ctl->rows_relaxed, __popc(act));
+    sweep_rows<SWEEP_ROWS>(g, r0, act, n, rowv, g.undirected ? rowu : nullptr,
+                           [&](const SweepTile<SWEEP_ROWS> &T, int32_t c0, int32_t) {
+        if (c0 >= n) return;
+        const uint4 bv = T.v1, bu = T.v2;  // INF where absent or past n
 #pragma unroll
-    for (int r = 0; r < RELAX_ROWS; ++r) {
-        if (x1[r] >= INF && x2[r] >= INF) continue;
-        const uint4 t = make_uint4(min(cat(x1[r], bv.x), cat(x2[r], bu.x)), min(cat(x1[r], bv.y), cat(x2[r], bu.y)),
-                                   min(cat(x1[r], bv.z), cat(x2[r], bu.z)), min(cat(x1[r], bv.w), cat(x2[r], bu.w)));
-        uint4 x = d[r];
-        if (t.x < x.x || t.y < x.y || t.z < x.z || t.w < x.w) {
-            x.x = min(x.x, t.x);
-            x.y = min(x.y, t.y);
-            x.z = min(x.z, t.z);
-            x.w = min(x.w, t.w);
-            *reinterpret_cast<uint4 *>(g.D + (int64_t)(r0 + r) * g.ld + c0) = x;
+        for (int r = 0; r < SWEEP_ROWS; ++r) {
+            if (!((act >> r) & 1u)) continue;
+            store_min_if_lower(g, r0 + r, c0, T.d[r],
+                               make_uint4(min(cat(x1[r], bv.x), cat(x2[r], bu.x)), min(cat(x1[r], bv.y), cat(x2[r], bu.y)),
+                                          min(cat(x1[r], bv.z), cat(x2[r], bu.z)), min(cat(x1[r], bv.w), cat(x2[r], bu.w))));
         }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && rows) atomicAdd(&g.ctl->rows_relaxed, rows);
+    });
 }
 
 
@@ -528,9 +584,6 @@ size_t fused_lds_bytes(int32_t P) {
 //     (and column k of a removal) are set to INF and relaxed in place by
 //     Bellman-Ford over the light in-edge index.  Rows with more than ROW_CAP
 //     flags ("heavy") are left untouched and queued for pass B.
-constexpr int DETECT_ROWS = 8;
-constexpr int32_t EDGE_SWEEP_GROUPS = 256;  // work-group rows of the edge sweep's grid
-
 // OR of the 32-bit values of the 8 lanes of each aligned group of 8.
 __device__ __forceinline__ uint32_t or8(uint32_t v) {
     v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
@@ -539,6 +592,62 @@ __device__ __forceinline__ uint32_t or8(uint32_t v) {
     return v;
 }
 
+// The mask of rows r0 .. r0 + SWEEP_ROWS - 1 (one work-group).  Each tile
+// writes its nonzero flag words and, per wavefront, the byte of row marks of
+// its 8 rows x 256 columns -- also when nothing is flagged, since the marks
+// are rewritten by every detection.
+template <int MODE>
+__device__ __forceinline__ void mask_detect_rows(const DevGraph &g, const FusedArgs &fa, uint32_t w_old, int32_t r0) {
+    static_assert(SWEEP_ROWS == 8, "a byte of row marks covers 8 rows");
+    const int n = g.n_slots;
+    const int lane = lane_id();
+    const int64_t nwp = (g.P + 31) / 32;
+    const int32_t rg = r0 / SWEEP_ROWS;
+    const int kx = MODE == FUSED_REMOVE ? fa.k : -1;
+    uint32_t a1[SWEEP_ROWS], a2[SWEEP_ROWS];
+    uint32_t act = 0;
+#pragma unroll
+    for (int r = 0; r < SWEEP_ROWS; ++r) {
+        const int32_t i = r0 + r;
+        a1[r] = a2[r] = 0x80000000u;  // disabled: a (+) v exceeds every finite entry
+        if (i < n) {
+            const RowTests rt = row_tests(g, fa, i, w_old);
+            if (rt.t1) a1[r] = rt.a1;
+            if (rt.t2) a2[r] = rt.a2;
+            if (rt.t1 || rt.t2) act |= 1u << r;
+        }
+    }
+    sweep_rows<SWEEP_ROWS>(g, r0, act, n, fa.row1, MODE == FUSED_INCREASE ? fa.row2 : nullptr,
+                           [&](const SweepTile<SWEEP_ROWS> &T, int32_t c0, int32_t t) {
+        const uint32_t w1[4] = {T.v1.x, T.v1.y, T.v1.z, T.v1.w};
+        const uint32_t w2[4] = {T.v2.x, T.v2.y, T.v2.z, T.v2.w};
+        uint32_t row_mask = 0;  // rows of this wavefront's 8 x 256 tile holding a flag (wave-uniform)
+#pragma unroll
+        for (int r = 0; r < SWEEP_ROWS; ++r) {
+            if (!((act >> r) & 1u)) continue;  // block-uniform
+            const int32_t i = r0 + r;
+            const uint32_t dv[4] = {T.d[r].x, T.d[r].y, T.d[r].z, T.d[r].w};
+            uint32_t bits = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int32_t j = c0 + e;
+                bool f = cat(a1[r], w1[e]) == dv[e];
+                if (MODE == FUSED_INCREASE) f = f || (cat(a2[r], w2[e]) == dv[e]);
+                f = f && dv[e] < INF && j != i && j != kx && j < n;
+                bits |= (uint32_t)f << e;
+            }
+            const uint32_t word = or8(bits << ((lane & 7) * 4));
+            if ((lane & 7) == 0 && c0 < n && word != 0) fa.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
+            if (__ballot(bits != 0) != 0) row_mask |= 1u << r;
+        }
+        const int32_t chunk = t * 4 + (threadIdx.x >> 6);
+        if (lane == 0 && chunk * 256 < n) fa.marks[(int64_t)rg * fa.mark_pitch + chunk] = (uint8_t)row_mask;
+    });
+}
+
+// The removal mask over one tile of 8 rows x 1024 columns (one work-group per
+// tile): the 8 rows' loads issued together before any test.
+constexpr int DETECT_ROWS = 8;
 template <int MODE>
 __device__ __forceinline__ void mask_detect_tile(const DevGraph &g, const FusedArgs &fa, uint32_t w_old, int32_t rg) {
     const int n = g.n_slots;
@@ -598,19 +707,63 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
     mask_detect_tile<FUSED_REMOVE>(g, fa, 0u, blockIdx.y);
 }
 
+// |F| and Phi of a removal's mask, counted without writing it (a route that
+// needs no flags still reports them, and Algorithm 5's cost test reads Phi).
+__global__ __launch_bounds__(256) void k_mask_count(DevGraph g, FusedArgs fa) {
+    __shared__ uint32_t s_cnt, s_rows;
+    const int n = g.n_slots;
+    const int32_t r0 = blockIdx.x * SWEEP_ROWS;
+    uint32_t a1[SWEEP_ROWS];
+    uint32_t act = 0;
+#pragma unroll
+    for (int r = 0; r < SWEEP_ROWS; ++r) {
+        a1[r] = 0x80000000u;
+        if (r0 + r < n) {
+            const RowTests rt = row_tests(g, fa, r0 + r, 0u);
+            if (rt.t1) {
+                a1[r] = rt.a1;
+                act |= 1u << r;
+            }
+        }
+    }
+    if (act == 0) return;  // block-uniform
+    if (threadIdx.x == 0) s_cnt = s_rows = 0;
+    __syncthreads();
+    uint32_t cnt = 0, rows = 0;
+    sweep_rows<SWEEP_ROWS>(g, r0, act, n, fa.row1, nullptr, [&](const SweepTile<SWEEP_ROWS> &T, int32_t c0, int32_t) {
+        const uint32_t w1[4] = {T.v1.x, T.v1.y, T.v1.z, T.v1.w};
+#pragma unroll
+        for (int r = 0; r < SWEEP_ROWS; ++r) {
+            if (!((act >> r) & 1u)) continue;
+            const uint32_t dv[4] = {T.d[r].x, T.d[r].y, T.d[r].z, T.d[r].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int32_t j = c0 + e;
+                const bool f = cat(a1[r], w1[e]) == dv[e] && dv[e] < INF && j != r0 + r && j != fa.k && j < n;
+                cnt += f;
+                rows |= (uint32_t)f << r;
+            }
+        }
+    });
+    if (cnt) atomicAdd(&s_cnt, cnt);
+    if (rows) atomicOr(&s_rows, rows);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) {
+        atomicAdd(&g.ctl->flagged, (unsigned long long)s_cnt);
+        atomicAdd(&g.ctl->rows, __popc(s_rows));
+    }
+}
+
 // The edge update's sweep, chosen on the device: the relaxation of a decrease
 // (colu, colv, rowu, rowv = fa.col1, col2, row2, row1) or the mask of a tight
-// increase; nothing for a no-op.
-// Each work-group takes every gridDim.y-th group of 8 rows of its 1024
-// columns: a no-op launch (the common case) stays small.
+// increase; nothing for a no-op.  One work-group per SWEEP_ROWS rows (the
+// grid of a no-op launch is n / SWEEP_ROWS work-groups that return at once).
 __global__ __launch_bounds__(256) void k_edge_sweep(DevGraph g, FusedArgs fa, int32_t w) {
     const int32_t mode = g.ctl->edge_mode;
     if (mode == EDGE_NOOP) return;
-    const int32_t groups = (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS;
-    for (int32_t rg = blockIdx.y; rg < groups; rg += gridDim.y) {
-        if (mode == EDGE_DECREASE) dec_relax_tile(g, fa.col1, fa.col2, fa.row2, fa.row1, w, rg);
-        else mask_detect_tile<FUSED_INCREASE>(g, fa, (uint32_t)g.ctl->w_old, rg);
-    }
+    const int32_t r0 = blockIdx.x * SWEEP_ROWS;
+    if (mode == EDGE_DECREASE) dec_relax_rows(g, fa.col1, fa.col2, fa.row2, fa.row1, w, r0);
+    else mask_detect_rows<FUSED_INCREASE>(g, fa, (uint32_t)g.ctl->w_old, r0);
 }
 
 // Does row i hold a flag?  (The OR of its group's marks, read by one wave.)
@@ -931,12 +1084,14 @@ void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
     k_mask_detect<<<grid, 256, 0, s>>>(g, fa);
 }
 
+void launch_mask_count(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
+    if (g.n_slots <= 0) return;
+    k_mask_count<<<(g.n_slots + SWEEP_ROWS - 1) / SWEEP_ROWS, 256, 0, s>>>(g, fa);
+}
+
 void launch_edge_sweep(const DevGraph &g, const FusedArgs &fa, int32_t w, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    static_assert(RELAX_ROWS == DETECT_ROWS, "one grid serves both sweeps");
-    const int32_t groups = (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS;
-    dim3 grid((g.n_slots + 1023) / 1024, std::min(groups, EDGE_SWEEP_GROUPS));
-    k_edge_sweep<<<grid, 256, 0, s>>>(g, fa, w);
+    k_edge_sweep<<<(g.n_slots + SWEEP_ROWS - 1) / SWEEP_ROWS, 256, 0, s>>>(g, fa, w);
 }
 
 void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {

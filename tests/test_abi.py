@@ -59,7 +59,9 @@ def test_required_bytes(lib):
     from paper_2412_15122_amd import _native as N
     assert lib.apsp_required_bytes(0, 0) == 0
     assert lib.apsp_required_bytes(N.APSP_MAX_CAPACITY + 1, 0) == 0
-    assert lib.apsp_required_bytes(10, 7) == 0
+    assert lib.apsp_required_bytes(10, 7) == 0    # minimax and widest together
+    assert lib.apsp_required_bytes(10, 8) == 0    # an unknown bit
+    assert lib.apsp_required_bytes(10, N.APSP_WIDEST | N.APSP_UNDIRECTED) == lib.apsp_required_bytes(10, 1)
     und = lib.apsp_required_bytes(16384, N.APSP_UNDIRECTED)
     dire = lib.apsp_required_bytes(16384, N.APSP_DIRECTED)
     mat = 16384 * 16384 * 4

@@ -114,22 +114,28 @@ def test_minimax_updates(undirected, setup):
     g.close()
 
 
-def test_minimax_heavy_rows_and_clone():
-    """Weights 1..2 on a dense graph: huge ties, so removals flag rows with
-    far more than 32 entries (the block-per-row pass); a clone keeps the
-    semiring."""
+@pytest.mark.parametrize("undirected", [True, False])
+def test_minimax_heavy_rows_and_clone(undirected):
+    """Weights 1..2 on a sparse graph: huge ties.  Directed, removals flag
+    rows with far more than 32 entries (the block-per-row pass of the mask
+    route); undirected, they take the spanning-forest route.  A clone keeps
+    the semiring."""
     from paper_2412_15122_amd.apsp import Graph
     rng = np.random.default_rng(5)
     n = 600
-    A0 = W.random_graph(n, 1, 2, undirected=True, density=0.02, seed=8)
-    g = Graph(A0, undirected=True, capacity=n + 2, minimax=True)
+    A0 = W.random_graph(n, 1, 2, undirected=undirected, density=0.02, seed=8)
+    g = Graph(A0, undirected=undirected, capacity=n + 2, minimax=True)
     c = g.clone()
-    st = W.GraphState(A0, True)
+    st = W.GraphState(A0, undirected)
     for t in range(3):
         up = W.make_update(rng, st, W.REMOVE, wmin=1, wmax=2, inc_max=4)
         g.remove_node(up.u)
         c.remove_node(up.u)
-        assert g.stats()["heavy_rows"] > 0
+        s = g.stats()
+        if undirected:
+            assert s["route"] == 1 and s["heavy_rows"] == 0
+        else:
+            assert s["route"] == 0 and s["heavy_rows"] > 0
     D = O.minimax_apsp(st.dense())
     assert np.array_equal(g.matrix(), D)
     assert np.array_equal(c.matrix(), D)
@@ -335,3 +341,59 @@ def test_minimax_benchmark_graph_n16384():
         assert p[0] == a and p[-1] == b and len(set(p)) == len(p)
         assert max((int(A[x, y]) for x, y in zip(p, p[1:])), default=0) == dist
     g.close()
+
+
+@pytest.mark.parametrize("wmax,limit", [(10000, None), (6, None), (10000, 2)])
+def test_minimax_removal_by_spanning_forest(wmax, limit):
+    """Removals on undirected minimax graphs take the spanning-forest route
+    when its certificate holds (route 1): every state equals the oracle's
+    minimax Floyd-Warshall, the changed-pair count equals the oracle's
+    refined set (Theorem 6), and the mask's |F| and Phi equal the oracle's.
+    With a 2-entry index the certificate cannot cover the graph and the mask
+    route runs instead (route 0), with the same results."""
+    from paper_2412_15122_amd.apsp import Graph
+    rng = np.random.default_rng(91 + wmax + (limit or 0))
+    n = 420
+    A = W.random_graph(n, 1, wmax, undirected=True, seed=int(rng.integers(1 << 30)))
+    g = Graph(A, undirected=True, capacity=n + 4, minimax=True)
+    if limit:
+        g.set_index_limit(limit)
+    ids = list(range(n))
+    D = O.minimax_apsp(A)
+    routes = []
+    for t in range(10):
+        k = ids[int(rng.integers(len(ids)))]
+        a = ids.index(k)
+        F = O.remove_mask(D, a, minimax=True)
+        g.remove_node(k)
+        s = g.stats()
+        A, ids = O.apply_update(A, ids, "remove", u=k, undirected=True)
+        D2 = O.minimax_apsp(A)
+        assert np.array_equal(g.matrix(), D2), (t, k)
+        keep = [x for x in range(len(ids) + 1) if x != a]
+        changed = O.refined_set(D[np.ix_(keep, keep)], D2)
+        assert s["changed"] == int(changed.sum()), (t, s["changed"], int(changed.sum()))
+        assert s["rows_changed"] == int(changed.any(axis=1).sum()), t
+        assert s["flagged"] == int(F.sum()) and s["rows"] == int(F.any(axis=1).sum()), t
+        routes.append(s["route"])
+        D = D2
+    if limit:
+        assert set(routes) == {0}, routes
+    else:
+        assert routes.count(1) >= 8, routes
+
+
+def test_widest_removal_by_spanning_forest():
+    """The same route on an undirected widest graph (stored as a minimax one)."""
+    from paper_2412_15122_amd.apsp import Graph
+    rng = np.random.default_rng(97)
+    n = 300
+    C = W.random_graph(n, 1, 500, undirected=True, density=0.3, seed=98)
+    g = Graph(C, undirected=True, capacity=n, widest=True)
+    ids = list(range(n))
+    for t in range(6):
+        k = ids[int(rng.integers(len(ids)))]
+        g.remove_node(k)
+        C, ids = O.apply_update(C, ids, "remove", u=k, undirected=True)
+        assert g.stats()["route"] == 1, t
+        assert np.array_equal(g.matrix(), O.widest_apsp(C)), t

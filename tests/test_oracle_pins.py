@@ -614,3 +614,65 @@ def test_true_distance_matrices_pass_the_import_checks(undirected, minimax):
         assert np.all(D.astype(np.int64) <= A)
         if undirected:
             assert np.array_equal(D, D.T)
+
+
+# ---------------------------------------------------------------------------
+# widest (maximum-capacity) paths
+# ---------------------------------------------------------------------------
+
+def rand_caps(rng, n, cmax, *, undirected=False, density=1.0, zero=0.0):
+    """Capacities U[1, cmax] (some 0 with `zero`), absent edges INF."""
+    return W.random_graph(n, 1, cmax, undirected=undirected, density=density,
+                          seed=int(rng.integers(1 << 31)), zero_frac=zero)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_widest_equals_brute_force_and_thresholds(undirected):
+    rng = np.random.default_rng(301 + undirected)
+    for trial in range(18):
+        n = [0, 1, 2, 4, 6, 7][trial % 6]
+        C = rand_caps(rng, n, [3, 50, O.WIDEST_TOP][trial % 3], undirected=undirected,
+                      density=[1.0, 0.5, 0.25][trial % 3], zero=0.2 if trial % 4 == 1 else 0.0)
+        Wf = O.widest_apsp(C)
+        assert np.array_equal(Wf, O.brute_force_widest(C)), trial
+        assert np.array_equal(Wf, O.widest_by_thresholds(C)), trial
+
+
+def test_widest_by_maximum_spanning_tree():
+    """Undirected: the width of a pair is the smallest capacity on its path
+    in a maximum spanning forest (scipy's minimum spanning tree of
+    (WIDEST_TOP + 1) - c, so every present edge stays positive)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import minimum_spanning_tree, breadth_first_order
+    rng = np.random.default_rng(305)
+    for n, cmax, dens in ((40, 30, 1.0), (60, 1000, 0.15), (25, 4, 0.5)):
+        C = rand_caps(rng, n, cmax, undirected=True, density=dens)
+        M = np.where(C < INF, (O.WIDEST_TOP + 1) - C.astype(np.int64), 0).astype(np.float64)
+        np.fill_diagonal(M, 0)
+        T = minimum_spanning_tree(csr_matrix(M)).toarray()
+        T = np.maximum(T, T.T)
+        Wf = O.widest_apsp(C)
+        for i in range(n):
+            order, pred = breadth_first_order(csr_matrix(T), i, directed=False, return_predecessors=True)
+            for j in range(n):
+                if i == j:
+                    assert Wf[i, j] == O.WIDEST_TOP
+                elif j not in set(order.tolist()):
+                    assert Wf[i, j] == INF
+                else:
+                    x, m = j, O.WIDEST_TOP
+                    while x != i:
+                        m = min(m, int(C[pred[x], x]))
+                        x = pred[x]
+                    assert Wf[i, j] == m, (i, j)
+
+
+def test_widest_is_a_minimax_problem_on_flipped_capacities():
+    """The reading the library takes: W = TOP - MM(TOP - C) entrywise
+    (INF kept), checked here between two independent oracle routines."""
+    rng = np.random.default_rng(309)
+    for undirected in (False, True):
+        C = rand_caps(rng, 30, 500, undirected=undirected, density=0.4, zero=0.1)
+        F = np.where(C < INF, O.WIDEST_TOP - C.astype(np.int64), INF).astype(np.int32)
+        MM = O.minimax_apsp(F).astype(np.int64)
+        assert np.array_equal(O.widest_apsp(C), np.where(MM < INF, O.WIDEST_TOP - MM, INF))
