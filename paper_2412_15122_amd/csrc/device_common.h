@@ -536,6 +536,30 @@ __device__ inline int compact_bits(const uint32_t *bm, int nw, int32_t *list, ui
     return tot;
 }
 
+// Index entries e and e+1 of a node's light in-edge list as (x, w, x', w');
+// entries at or past lim read as weight INF.
+__device__ __forceinline__ int4 index_pair(const int4 *L4, int lim, int e) {
+    int4 p = make_int4(0, (int)INF, 0, (int)INF);
+    if (e < lim) p = L4[e >> 1];
+    if (e + 1 >= lim) p.w = (int)INF;
+    return p;
+}
+
+// cm lowered by row[x] (+) w for the pair's edges lighter than best (row:
+// a row of D in global memory, or its copy in LDS).
+template <class T>
+__device__ __forceinline__ uint32_t pull_pair(const T *row, int4 p, uint32_t best, uint32_t cm) {
+    if ((uint32_t)p.y < best) cm = min(cm, cat((uint32_t)row[p.x], (uint32_t)p.y));
+    if ((uint32_t)p.w < best) cm = min(cm, cat((uint32_t)row[p.z], (uint32_t)p.w));
+    return cm;
+}
+
+// Minimum over an aligned group of four lanes.
+__device__ __forceinline__ uint32_t group4_min(uint32_t v) {
+    v = min(v, (uint32_t)__shfl_xor((int)v, 1, 4));
+    return min(v, (uint32_t)__shfl_xor((int)v, 2, 4));
+}
+
 // Bellman-Ford relaxation of the columns list[0..total) of the LDS row cur:
 //   cur[y] = min_x cur[x] (+) A'[x][y]
 // Sweeps scan each y's light in-edges (4 lanes per y, 32 entries per round
@@ -552,13 +576,42 @@ __device__ inline void row_bellman_ford(const DevGraph &g, FusedShared &sh, cons
     const int lim = g.lim;
     const int32_t *Min = in_matrix(g);
     uint32_t *cur = sh.cur;
+    // each group's first column and its 32 lightest in-edges stay in
+    // registers for all sweeps: a sweep over at most NG columns reads only LDS
+    const bool has0 = grp < total;
+    const int32_t y0 = has0 ? list[grp] : 0;
+    const int4 *Y4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y0 * NIN_L);
+    const int4 none4 = make_int4(0, (int)INF, 0, (int)INF);
+    const int4 q0 = has0 ? index_pair(Y4, lim, 2 * l4) : none4, q1 = has0 ? index_pair(Y4, lim, 8 + 2 * l4) : none4;
+    const int4 q2 = has0 ? index_pair(Y4, lim, 16 + 2 * l4) : none4, q3 = has0 ? index_pair(Y4, lim, 24 + 2 * l4) : none4;
+    const uint32_t wl0 = (uint32_t)__shfl(q3.w, 3, 4);  // entry 31 (INF past lim)
     for (;;) {
         for (;;) {
             __syncthreads();
             if (tid == 0) *sh.flag_changed = 0;
             __syncthreads();
             bool changed = false;
-            for (int e = grp; e < total; e += NG) {
+            if (has0) {
+                uint32_t best = cur[y0];
+                uint32_t cm = pull_pair(cur, q0, best, INF);
+                cm = pull_pair(cur, q1, best, cm);
+                cm = pull_pair(cur, q2, best, cm);
+                cm = pull_pair(cur, q3, best, cm);
+                best = min(best, group4_min(cm));
+                for (int c0 = 32; c0 < lim && wl0 < best; c0 += 32) {  // rare: the rest from the index
+                    uint32_t cr = INF;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cr = pull_pair(cur, index_pair(Y4, lim, c0 + 8 * q + 2 * l4), best, cr);
+                    best = min(best, group4_min(cr));
+                    const uint32_t wl = (uint32_t)__shfl(index_pair(Y4, lim, c0 + 24 + 2 * l4).w, 3, 4);
+                    if (wl >= best) break;
+                }
+                if (l4 == 0 && best < cur[y0]) {
+                    cur[y0] = best;
+                    changed = true;
+                }
+            }
+            for (int e = grp + NG; e < total; e += NG) {
                 const int32_t y = list[e];
                 uint32_t best = cur[y];
                 const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
@@ -789,6 +842,18 @@ __device__ inline void query_block(const DevGraph &g, int32_t si, int32_t sj, in
     __syncthreads();
 }
 
+// Smallest 64-bit key over a wavefront.
+__device__ __forceinline__ unsigned long long wave_min_key(unsigned long long v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
+        const unsigned long long u = ((unsigned long long)hi << 32) | lo;
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
 // Bellman-Ford over the flagged columns list[0..cnt) of row Drow (in place),
 // one wavefront: 16 groups of 4 lanes, each group one column at a time,
 // reading 16 index entries per load and stopping once an entry is at least
@@ -807,36 +872,32 @@ __device__ inline void wave_bellman_ford(const DevGraph &g, int32_t *Drow, const
             for (int e = g4; e < cnt; e += 16) {
                 const int32_t y = list[e];
                 uint32_t best = (uint32_t)Drow[y];
-                if (olds && best == (uint32_t)olds[e]) continue;  // back at its old value: final
+                // a lower bound: the old value when distances only go up
+                // (an entry back at it is final), else 0
+                const uint32_t floor = olds ? (uint32_t)olds[e] : 0u;
+                if (best <= floor) continue;
                 const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
-                for (int c0 = 0; c0 < lim; c0 += 32) {
-                    // lane l4 of the group holds entries c0 + 4*l4 .. +3 and
-                    // c0 + 16 + 4*l4 .. +3: 32 entries per round trip
-                    const int e0 = c0 + 4 * l4, e1 = e0 + 16;
-                    const int4 none = make_int4(0, (int)INF, 0, (int)INF);
-                    int4 pa = none, pb = none, pc = none, pd = none;
-                    if (e0 < lim) pa = L4[e0 >> 1];
-                    if (e0 + 2 < lim) pb = L4[(e0 >> 1) + 1];
-                    if (e1 < lim) pc = L4[e1 >> 1];
-                    if (e1 + 2 < lim) pd = L4[(e1 >> 1) + 1];
-                    if (e0 + 1 >= lim) pa.w = (int)INF;
-                    if (e0 + 3 >= lim) pb.w = (int)INF;
-                    if (e1 + 1 >= lim) pc.w = (int)INF;
-                    if (e1 + 3 >= lim) pd.w = (int)INF;
-                    uint32_t cm = INF;
-                    if ((uint32_t)pa.y < best) cm = min(cm, cat((uint32_t)Drow[pa.x], (uint32_t)pa.y));
-                    if ((uint32_t)pa.w < best) cm = min(cm, cat((uint32_t)Drow[pa.z], (uint32_t)pa.w));
-                    if ((uint32_t)pb.y < best) cm = min(cm, cat((uint32_t)Drow[pb.x], (uint32_t)pb.y));
-                    if ((uint32_t)pb.w < best) cm = min(cm, cat((uint32_t)Drow[pb.z], (uint32_t)pb.w));
-                    if ((uint32_t)pc.y < best) cm = min(cm, cat((uint32_t)Drow[pc.x], (uint32_t)pc.y));
-                    if ((uint32_t)pc.w < best) cm = min(cm, cat((uint32_t)Drow[pc.z], (uint32_t)pc.w));
-                    if ((uint32_t)pd.y < best) cm = min(cm, cat((uint32_t)Drow[pd.x], (uint32_t)pd.y));
-                    if ((uint32_t)pd.w < best) cm = min(cm, cat((uint32_t)Drow[pd.z], (uint32_t)pd.w));
-                    cm = min(cm, (uint32_t)__shfl_xor((int)cm, 1, 4));
-                    cm = min(cm, (uint32_t)__shfl_xor((int)cm, 2, 4));
-                    best = min(best, cm);
-                    const uint32_t wlast = (uint32_t)__shfl(pd.w, 3, 4);
-                    if (wlast >= best) break;  // every later entry is at least as heavy
+                // lane l4 of the group holds entries 2*l4 + 8*q and the next,
+                // q = 0..3: the lightest eight are gathered first, and the
+                // rest only below the bound they give.  Most of the cost is
+                // the random reads of D, so a scan gathers as few as it can.
+                int4 p0 = index_pair(L4, lim, 2 * l4), p1 = index_pair(L4, lim, 8 + 2 * l4);
+                int4 p2 = index_pair(L4, lim, 16 + 2 * l4), p3 = index_pair(L4, lim, 24 + 2 * l4);
+                best = min(best, group4_min(pull_pair(Drow, p0, best, INF)));
+                uint32_t wl = (uint32_t)__shfl(p0.w, 3, 4);  // the eighth entry
+                for (int c0 = 32; best > floor && wl < best; c0 += 32) {
+                    uint32_t cm = pull_pair(Drow, p1, best, INF);
+                    cm = pull_pair(Drow, p2, best, cm);
+                    cm = pull_pair(Drow, p3, best, cm);
+                    best = min(best, group4_min(cm));
+                    wl = (uint32_t)__shfl(p3.w, 3, 4);  // the last entry of this block of 32
+                    if (c0 >= lim || best <= floor || wl >= best) break;
+                    p0 = index_pair(L4, lim, c0 + 2 * l4);
+                    p1 = index_pair(L4, lim, c0 + 8 + 2 * l4);
+                    p2 = index_pair(L4, lim, c0 + 16 + 2 * l4);
+                    p3 = index_pair(L4, lim, c0 + 24 + 2 * l4);
+                    best = min(best, group4_min(pull_pair(Drow, p0, best, INF)));
+                    wl = (uint32_t)__shfl(p0.w, 3, 4);
                 }
                 if (l4 == 0 && best < (uint32_t)Drow[y]) {
                     Drow[y] = (int32_t)best;

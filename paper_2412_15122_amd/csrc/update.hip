@@ -790,14 +790,159 @@ __global__ __launch_bounds__(256) void k_count_flag_rows(DevGraph g, FusedArgs f
     if (threadIdx.x == 0) g.ctl->rows = c;
 }
 
+// The flagged columns of a light row as a set: open addressing over FSET
+// slots (at most ROW_CAP keys, so half stay empty and every probe ends),
+// key -1 = empty, with each key's position in the row's list.
+constexpr int FSET_BITS = 6;
+constexpr int FSET = 1 << FSET_BITS;
+static_assert(FSET == 64 && 2 * ROW_CAP <= FSET, "one set slot per lane, at most half of them used");
+__device__ __forceinline__ uint32_t fset_slot(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - FSET_BITS); }
+__device__ __forceinline__ int fset_find(const int32_t *keys, const int32_t *pos, int32_t x) {
+    for (uint32_t h = fset_slot(x);; h = (h + 1) & (FSET - 1)) {
+        const int32_t key = keys[h];
+        if (key == x) return pos[h];
+        if (key < 0) return -1;
+    }
+}
+
+// One light-in-edge pair of a flagged entry e of row i: an edge from an
+// unflagged x lowers cm by D[i][x] (+) w, one from a flagged x (its list
+// position a) is kept as W[a][e] for the closure; edges at least as heavy
+// as best cannot lower the entry and are skipped, and so are those of the
+// removed slot.
+__device__ __forceinline__ uint32_t light_pull_pair(const int32_t *Drow, int4 p, uint32_t best, uint32_t cm, int e,
+                                                    int cnt, int32_t kx, const int32_t *keys, const int32_t *pos,
+                                                    uint32_t *W) {
+    if ((uint32_t)p.y < best && p.x != kx) {
+        const int a = fset_find(keys, pos, p.x);
+        if (a >= 0) W[a * cnt + e] = (uint32_t)p.y;
+        else cm = min(cm, cat((uint32_t)Drow[p.x], (uint32_t)p.y));
+    }
+    if ((uint32_t)p.w < best && p.z != kx) {
+        const int a = fset_find(keys, pos, p.z);
+        if (a >= 0) W[a * cnt + e] = (uint32_t)p.w;
+        else cm = min(cm, cat((uint32_t)Drow[p.z], (uint32_t)p.w));
+    }
+    return cm;
+}
+
+// The new entries of a light row (cnt <= ROW_CAP flagged columns list[]),
+// one wavefront, every value kept in LDS until the end:
+//  1. each flagged entry starts from its best walk whose last edge leaves an
+//     unflagged column -- a pull over its light in-edges, lightest eight
+//     first, the rest only below the bound they give, stopping at the old
+//     value (distances only go up, so an entry back at it is final) -- and
+//     the pull keeps the in-edges that come from flagged columns;
+//  2. Dijkstra over the flagged columns with those edges closes the set;
+//  3. an entry left above its beta_eff could still take an edge missing from
+//     the index: a full scan of its column lowers it, and 2-3 repeat until
+//     no scan lowers anything.
+// Flagged columns are never read from D: their old values may be stale.
+// Returns the entry of list position `lane` (INF past cnt).
+__device__ inline uint32_t light_row(const DevGraph &g, const FusedArgs &fa, const RowTests &rt, int32_t *Drow,
+                                     const int32_t *list, int cnt, int32_t *fsl, int32_t *old, uint32_t *val,
+                                     int32_t *keys, int32_t *pos, uint32_t *W, int &sweeps, int &nfs_total) {
+    const int lane = lane_id();
+    const int g4 = lane >> 2, l4 = lane & 3;
+    const int lim = g.lim;
+    const int32_t kx = fa.mode == FUSED_REMOVE ? fa.k : -1;
+    keys[lane] = -1;
+    for (int q = lane; q < cnt * cnt; q += 64) W[q] = INF;
+    __threadfence_block();
+    int32_t ye = 0;
+    uint32_t olde = INF, beta = INF;
+    if (lane < cnt) {
+        ye = list[lane];
+        uint32_t h = fset_slot(ye);
+        while (atomicCAS(&keys[h], -1, ye) != -1) h = (h + 1) & (FSET - 1);
+        pos[h] = lane;
+        olde = flagged_old(fa, rt, ye);
+        old[lane] = (int32_t)olde;
+        beta = (uint32_t)g.nin_beta[ye];
+        if (lim < NIN_L) beta = min(beta, (uint32_t)g.nin[(int64_t)ye * NIN_L + lim].y);
+    }
+    __threadfence_block();
+    for (int e = g4; e < cnt; e += 16) {
+        const int32_t y = list[e];
+        const uint32_t floor = (uint32_t)old[e];
+        const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
+        int4 p0 = index_pair(L4, lim, 2 * l4), p1 = index_pair(L4, lim, 8 + 2 * l4);
+        int4 p2 = index_pair(L4, lim, 16 + 2 * l4), p3 = index_pair(L4, lim, 24 + 2 * l4);
+        uint32_t best = group4_min(light_pull_pair(Drow, p0, INF, INF, e, cnt, kx, keys, pos, W));
+        uint32_t wl = (uint32_t)__shfl(p0.w, 3, 4);  // the eighth entry
+        for (int c0 = 32; best > floor && wl < best; c0 += 32) {
+            uint32_t cm = light_pull_pair(Drow, p1, best, INF, e, cnt, kx, keys, pos, W);
+            cm = light_pull_pair(Drow, p2, best, cm, e, cnt, kx, keys, pos, W);
+            cm = light_pull_pair(Drow, p3, best, cm, e, cnt, kx, keys, pos, W);
+            best = min(best, group4_min(cm));
+            wl = (uint32_t)__shfl(p3.w, 3, 4);
+            if (c0 >= lim || best <= floor || wl >= best) break;
+            p0 = index_pair(L4, lim, c0 + 2 * l4);
+            p1 = index_pair(L4, lim, c0 + 8 + 2 * l4);
+            p2 = index_pair(L4, lim, c0 + 16 + 2 * l4);
+            p3 = index_pair(L4, lim, c0 + 24 + 2 * l4);
+            best = min(best, group4_min(light_pull_pair(Drow, p0, best, INF, e, cnt, kx, keys, pos, W)));
+            wl = (uint32_t)__shfl(p0.w, 3, 4);
+        }
+        if (l4 == 0) val[e] = best;
+    }
+    __threadfence_block();
+    ++sweeps;
+    // Dijkstra: weights >= 0 and cat is monotone, so the unsettled entry of
+    // smallest value is final
+    uint32_t dist = lane < cnt ? val[lane] : INF;
+    const int32_t *Min = in_matrix(g);
+    for (;;) {
+        bool done = lane >= cnt;
+        for (int it = 0; it < cnt; ++it) {
+            const unsigned long long key =
+                wave_min_key(done ? ~0ull : (((unsigned long long)dist << 32) | (uint32_t)lane));
+            const uint32_t da = (uint32_t)(key >> 32);
+            if (key == ~0ull || da >= INF) break;  // wave-uniform
+            const int a = (int)(key & 63u);
+            if (lane == a) done = true;
+            if (!done) dist = min(dist, cat(da, W[a * cnt + lane]));
+        }
+        // entries that an edge missing from the index could still lower:
+        // full scans of their columns against the row as it stands
+        unsigned long long need = __ballot(lane < cnt && dist > beta && dist > olde);
+        if (!need) break;
+        if (lane < cnt) Drow[ye] = (int32_t)dist;
+        __threadfence_block();
+        nfs_total += __popcll(need);
+        bool lowered = false;
+        while (need) {
+            const int f = __ffsll((long long)need) - 1;
+            need &= need - 1;
+            const uint32_t df = (uint32_t)__shfl((int)dist, f);
+            const uint32_t b = wave_min_plus_below(Drow, Min + (int64_t)list[f] * g.ld, g.n_slots, df);
+            if (b < df) {
+                lowered = true;
+                if (lane == f) {
+                    dist = b;
+                    Drow[ye] = (int32_t)b;
+                }
+            }
+            __threadfence_block();
+        }
+        ++sweeps;
+        if (!lowered) break;
+    }
+    return dist;
+}
+
 // reset_only: only clear the flagged rows' words (after a cold fallback).
 // A row's flag words are cleared once read, except those of an undirected
 // heavy row, which the heavy-row pass reads (and clears) later.
-__global__ __launch_bounds__(64 * RECOMPUTE_WAVES) void k_recompute_rows(DevGraph g, FusedArgs fa, int32_t reset_only) {
+__global__ __launch_bounds__(64 * RECOMPUTE_WAVES, 5) void k_recompute_rows(DevGraph g, FusedArgs fa, int32_t reset_only) {
     __shared__ int32_t lists[RECOMPUTE_WAVES][ROW_CAP];
     __shared__ int32_t fsls[RECOMPUTE_WAVES][ROW_CAP];
     __shared__ int32_t olds[RECOMPUTE_WAVES][ROW_CAP];
     __shared__ int32_t stat[RECOMPUTE_WAVES][RECOMPUTE_STATS];
+    __shared__ uint32_t dense[RECOMPUTE_WAVES][ROW_CAP * ROW_CAP];  // light in-edges among a row's flagged columns
+    __shared__ uint32_t vals[RECOMPUTE_WAVES][ROW_CAP];
+    __shared__ int32_t fkeys[RECOMPUTE_WAVES][FSET];
+    __shared__ int32_t fpos[RECOMPUTE_WAVES][FSET];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     int32_t *list = lists[wv];
     int32_t *fsl = fsls[wv];
@@ -807,6 +952,7 @@ __global__ __launch_bounds__(64 * RECOMPUTE_WAVES) void k_recompute_rows(DevGrap
     const int64_t nwp = (g.P + 31) / 32;
     int my_rows = 0, my_fs = 0, my_sweeps = 0, my_flagged = 0, my_changed = 0, my_rows_changed = 0;
     const bool active = !(fa.mode == FUSED_INCREASE && g.ctl->edge_mode != EDGE_INCREASE);
+    const uint32_t w_old = active && fa.mode == FUSED_INCREASE ? (uint32_t)g.ctl->w_old : 0u;
     for (int32_t i = blockIdx.x * RECOMPUTE_WAVES + wv; active && i < n; i += gridDim.x * RECOMPUTE_WAVES) {
         if (!row_marked(fa, n, i)) continue;
         ++my_rows;
@@ -863,31 +1009,26 @@ __global__ __launch_bounds__(64 * RECOMPUTE_WAVES) void k_recompute_rows(DevGrap
             continue;
         }
         int32_t *Drow = g.D + (int64_t)i * g.ld;
-        __threadfence_block();
-        for (int e = lane; e < cnt; e += 64) {
-            old[e] = Drow[list[e]];
-            Drow[list[e]] = (int32_t)INF;
-        }
         if (fa.mode == FUSED_REMOVE && lane == 0) Drow[fa.k] = (int32_t)INF;
         __threadfence_block();
         int sweeps = 0;
-        wave_bellman_ford(g, Drow, list, cnt, fsl, sweeps, my_fs, old);
+        const RowTests rt = row_tests(g, fa, i, w_old);
+        const uint32_t v = light_row(g, fa, rt, Drow, list, cnt, fsl, old, vals[wv], fkeys[wv], fpos[wv], dense[wv],
+                                     sweeps, my_fs);
         my_sweeps = max(my_sweeps, sweeps);
         // the refined set: flagged entries whose distance went up
-        int ch = 0;
-        for (int e = lane; e < cnt; e += 64) ch += Drow[list[e]] != old[e];
-        ch = wave_sum(ch);
+        const int ch = wave_sum(lane < cnt && v != (uint32_t)old[lane]);
         my_changed += ch;
         my_rows_changed += ch > 0;
         // undirected: D' is symmetric and so is the mask, so the final
         // entries of row i are also those of column i.  A heavy row j takes
         // its entry (j, i) from here; a light row j computes the same value
         // itself, and any interleaving of the two exact writes is harmless.
-        if (g.undirected)
-            for (int e = lane; e < cnt; e += 64) {
-                const int32_t y = list[e];
-                g.D[(int64_t)y * g.ld + i] = Drow[y];
-            }
+        if (lane < cnt) {
+            const int32_t y = list[lane];
+            Drow[y] = (int32_t)v;
+            if (g.undirected) g.D[(int64_t)y * g.ld + i] = (int32_t)v;
+        }
     }
     // statistics: one partial per work-group, summed by the update's next kernel
     if (lane == 0) {
@@ -1013,8 +1154,17 @@ __device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedA
             const int32_t i = fa.heavy_rows[idx];
             const RowTests rt = row_tests(g, fa, i, w_old);
             int32_t *Drow = g.D + (int64_t)i * g.ld;
-            for (int32_t c = tid * 4; c < n; c += FUSED_THREADS * 4)
-                *reinterpret_cast<uint4 *>(sh.cur + c) = *reinterpret_cast<const uint4 *>(Drow + c);
+            // the row into LDS, four 16-byte loads per thread in flight
+            for (int32_t c = tid * 4; c < n; c += FUSED_THREADS * 16) {
+                uint4 v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (c + q * FUSED_THREADS * 4 < n)
+                        v[q] = *reinterpret_cast<const uint4 *>(Drow + c + q * FUSED_THREADS * 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (c + q * FUSED_THREADS * 4 < n) *reinterpret_cast<uint4 *>(sh.cur + c + q * FUSED_THREADS * 4) = v[q];
+            }
             uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
             for (int w = tid; w < nw; w += FUSED_THREADS) sh.fl2[w] = fw[w] & sh.fl[w];
             __syncthreads();
