@@ -196,7 +196,37 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
                              int32_t *cnt_out, int32_t *beta_out, SelectShared &sh, uint32_t *stage) {
     const int tid = threadIdx.x;
     int valid = 0;
-    for (int32_t x = tid; x < n; x += NT) {
+    // stage the values: 16-byte loads, four per thread in flight (scalar
+    // loads for a misaligned vector and the tail)
+    const int32_t n4 = ((uintptr_t)vals & 15) ? 0 : (n & ~3);
+    for (int32_t base = 0; base < n4; base += NT * 16) {
+        uint4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t x = base + (q * NT + tid) * 4;
+            if (x < n4) v[q] = *reinterpret_cast<const uint4 *>(vals + x);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t x = base + (q * NT + tid) * 4;
+            if (x < n4) {
+                uint4 u = v[q];
+                if ((uint32_t)(excl - x) < 4u) {
+                    const int e = excl - x;
+                    if (e == 0) u.x = INF;
+                    if (e == 1) u.y = INF;
+                    if (e == 2) u.z = INF;
+                    if (e == 3) u.w = INF;
+                }
+                stage[x] = u.x;  // (the LDS stage is only 4-byte aligned)
+                stage[x + 1] = u.y;
+                stage[x + 2] = u.z;
+                stage[x + 3] = u.w;
+                valid += (u.x < INF) + (u.y < INF) + (u.z < INF) + (u.w < INF);
+            }
+        }
+    }
+    for (int32_t x = n4 + tid; x < n; x += NT) {
         uint32_t v = (uint32_t)vals[x];
         if (x == excl) v = INF;
         stage[x] = v;

@@ -164,63 +164,70 @@ void launch_scatter_weights(const DevGraph &g, const int32_t *w_out, const int32
 }
 
 // out[c] = min_t wo[t] (+) D[t][c]  (Corollary 1: SPD(p, c)).
-// The new node's lightest out-edges come first (plist, ascending weight): a
-// column stops once the next weight reaches its current value (distances
-// are >= 0), and every unlisted t has wo[t] >= beta, so a column whose
-// value is <= beta is final.  Columns above beta (or unreachable) take an
-// exhaustive scan.  One block = 256 columns; its 4 waves split the list.
-__global__ __launch_bounds__(256) void k_add_out(DevGraph g, const int2 *__restrict__ plist,
-                                                 const int32_t *__restrict__ pcnt, const int32_t *__restrict__ pbeta,
-                                                 const int32_t *__restrict__ wo, int32_t *__restrict__ out) {
-    __shared__ uint32_t part[4][256];
-    __shared__ uint32_t red[8];
+// The new node's lightest out-edges (plist, ascending weight) are split over
+// the block's 16 waves, each reading its (at most four) rows' chunks at once
+// -- one round trip, at most 64 rows of 1 KB per block.  Every unlisted t
+// has wo[t] >= beta, so a column whose value is <= beta is final; columns
+// above beta (or unreachable) take an exhaustive scan.  One block = 256
+// columns, a lane 4 of them.
+constexpr int ADD_OUT_THREADS = 1024;
+constexpr int ADD_OUT_WAVES = ADD_OUT_THREADS / 64;
+static_assert(ADD_OUT_WAVES * 4 >= NIN_L, "four list entries per wave cover the list");
+__global__ __launch_bounds__(ADD_OUT_THREADS) void k_add_out(DevGraph g, const int2 *__restrict__ plist,
+                                                             const int32_t *__restrict__ pcnt,
+                                                             const int32_t *__restrict__ pbeta,
+                                                             const int32_t *__restrict__ wo, int32_t *__restrict__ out) {
+    __shared__ uint32_t part[ADD_OUT_WAVES][256];
+    __shared__ uint32_t red[ADD_OUT_WAVES];
     const int n = g.n_slots;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int32_t cbase = blockIdx.x * 256;
     const int32_t c0 = cbase + lane * 4;
-    bool live[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) live[e] = (c0 + e < n) && g.id_of_slot[c0 + e] >= 0;
-    uint32_t acc[4] = {INF, INF, INF, INF};
     const int cnt = *pcnt;
     const int lim = min(cnt, g.lim);
     const uint32_t beta_eff = cnt > g.lim ? (uint32_t)plist[g.lim].y : (uint32_t)*pbeta;
+    uint32_t acc[4] = {INF, INF, INF, INF};
     if (c0 < n) {
-        for (int e = wv; e < lim; e += 4) {
-            int2 ent = plist[e];
-            uint32_t mx = 0;
+        int2 ent[4];
+        int4 v[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (live[q]) mx = max(mx, acc[q]);
-            if ((uint32_t)ent.y >= mx) break;
-            int4 v = *reinterpret_cast<const int4 *>(g.D + (int64_t)ent.x * g.ld + c0);
-            acc[0] = min(acc[0], cat((uint32_t)ent.y, (uint32_t)v.x));
-            acc[1] = min(acc[1], cat((uint32_t)ent.y, (uint32_t)v.y));
-            acc[2] = min(acc[2], cat((uint32_t)ent.y, (uint32_t)v.z));
-            acc[3] = min(acc[3], cat((uint32_t)ent.y, (uint32_t)v.w));
+        for (int q = 0; q < 4; ++q) {
+            const int e = wv + q * ADD_OUT_WAVES;
+            ent[q] = e < lim ? plist[e] : make_int2(0, (int)INF);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if ((uint32_t)ent[q].y < INF) v[q] = *reinterpret_cast<const int4 *>(g.D + (int64_t)ent[q].x * g.ld + c0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if ((uint32_t)ent[q].y >= INF) continue;
+            const uint32_t w = (uint32_t)ent[q].y;
+            acc[0] = min(acc[0], cat(w, (uint32_t)v[q].x));
+            acc[1] = min(acc[1], cat(w, (uint32_t)v[q].y));
+            acc[2] = min(acc[2], cat(w, (uint32_t)v[q].z));
+            acc[3] = min(acc[3], cat(w, (uint32_t)v[q].w));
         }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) part[wv][lane * 4 + q] = acc[q];
     __syncthreads();
-    const int32_t c = cbase + tid;  // one column per thread from here on
-    uint32_t fin = min(min(part[0][tid], part[1][tid]), min(part[2][tid], part[3][tid]));
-    const bool live_c = c < n && g.id_of_slot[c] >= 0;
-    int need = live_c && fin > beta_eff;
-    need = block_sum256(need, red);
-    if (need) {
-        if (c < n) {
-            for (int32_t t = 0; t < n; ++t)
-                fin = min(fin, cat((uint32_t)wo[t], (uint32_t)g.D[(int64_t)t * g.ld + c]));
-        }
+    const int32_t c = cbase + tid;  // one column per thread of the first 256 from here on
+    uint32_t fin = INF;
+    if (tid < 256) {
+#pragma unroll
+        for (int w = 0; w < ADD_OUT_WAVES; ++w) fin = min(fin, part[w][tid]);
     }
-    if (c < n) out[c] = (int32_t)min(fin, INF);
+    const bool live_c = tid < 256 && c < n && g.id_of_slot[c] >= 0;
+    const int need = block_sum<ADD_OUT_THREADS>(live_c && fin > beta_eff, red);
+    if (need && tid < 256 && c < n)
+        for (int32_t t = 0; t < n; ++t) fin = min(fin, cat((uint32_t)wo[t], (uint32_t)g.D[(int64_t)t * g.ld + c]));
+    if (tid < 256 && c < n) out[c] = (int32_t)min(fin, INF);
 }
 
 void launch_add_out(const DevGraph &g, const int2 *plist, const int32_t *pcnt, const int32_t *pbeta,
                     const int32_t *wo, int32_t *out, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_add_out<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, plist, pcnt, pbeta, wo, out);
+    k_add_out<<<(g.n_slots + 255) / 256, ADD_OUT_THREADS, 0, s>>>(g, plist, pcnt, pbeta, wo, out);
 }
 
 // in[i] = min_r D[i][r] (+) wi[r]  (Corollary 2: SPD(i, p)), one wave
