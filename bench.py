@@ -57,6 +57,8 @@ def parse():
                          "medians of single updates on the n=16384 graph (add, remove, a forced wide edge "
                          "decrease and the worst-case increase that undoes it)")
     ap.add_argument("--reps", type=int, default=20, help="kernels: repetitions per update kind")
+    ap.add_argument("--reps-sweep", type=int, default=5,
+                    help="updates: repetitions of the edge-sweep roofline probe (forced decrease, worst increase)")
     ap.add_argument("--graphs", type=int, default=None, help="batched / serving: number of graphs (512 / 64)")
     ap.add_argument("--batch-config", default=None,
                     help="batched: grid,order,variant to use instead of autotuning")
@@ -504,6 +506,48 @@ def bench_kernels(args):
     return 0 if ok is not False else 1
 
 
+def edge_sweep_roofline(base, worst, adj, kid, reps):
+    """The edge update's sweep kernel against HBM, on a copy of the n-node
+    graph: the stream's worst-case edge lowered to 0 (a forced wide
+    decrease: rows_relaxed rows are read, 4n bytes each) and raised back to
+    its weight (the tight increase's mask: with the edge at 0, u and v are
+    equally far from every node, so both pair tests hold on every row and
+    all n rows are read).  Average kernel time per launch by HIP events on
+    the graph's stream."""
+    import torch
+    u, v = int(worst[0]), int(worst[1])
+    wt = int(adj[u, v])
+    h = base.clone()
+    n = len(h.ids())
+    out = {}
+    for kind, w in (("decrease", 0), ("increase", wt)):
+        out[kind] = {"ms": [], "rows": []}
+    for _ in range(reps):
+        for kind, w in (("decrease", 0), ("increase", wt)):
+            if kind == "increase":
+                D = h.matrix_device("D")
+                rows_read = int(((D[:n, u] == D[:n, v])).sum().item())
+                del D
+            h.profile(1 << kid["edge_sweep"])
+            h.update_edge(u, v, w)
+            torch.cuda.synchronize()
+            c, ms = h.profile_read(kid["edge_sweep"])
+            h.profile(0)
+            st = h.stats()
+            out[kind]["ms"].append(ms / max(c, 1))
+            out[kind]["rows"].append(st["rows_relaxed"] if kind == "decrease" else rows_read)
+    h.close()
+    res = {"edge": [u, v, wt], "n": n}
+    for kind, d in out.items():
+        ms = float(np.median(d["ms"]))
+        rows = float(np.median(d["rows"]))
+        gbs = 4.0 * n * rows / (ms * 1e-3) / 1e9
+        res[kind] = {"avg_launch_ms": round(ms, 4), "rows_read": rows, "achieved": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"[bench] edge sweep: {res}")
+    return res
+
+
 def _cold_matrix(g):
     c = g.clone()
     c.recompute_cold()
@@ -717,6 +761,9 @@ def main():
             "kernel": prof_kernel, "launches": c, "avg_launch_ms": round(ms / max(c, 1), 4),
             "algorithmic_bytes_per_launch": round(alg / max(c, 1)),
         }
+
+    if roofline is not None and worst is not None and not minimax:
+        roofline["edge_sweep"] = edge_sweep_roofline(base, worst, adj, kid, args.reps_sweep)
 
     # synchronous single-pair queries on the final graph (host-observed latency)
     qrng = np.random.default_rng(4242)

@@ -304,14 +304,16 @@ __device__ __forceinline__ void sweep_load(SweepTile<R> &t, const DevGraph &g, i
 }
 
 // Calls body(tile, c0, t) for every tile t of the rows' columns [0, n),
-// c0 = 1024 t + 4 lane-in-block.
+// c0 = 4 SWEEP_THREADS t + 4 thread-in-block: a work-group of SWEEP_THREADS
+// threads spans SWEEP_THREADS / 64 column chunks of 256 per tile.
+constexpr int SWEEP_THREADS = 512;
 template <int R, class Body>
 __device__ __forceinline__ void sweep_rows(const DevGraph &g, int32_t r0, uint32_t act, int32_t n, const int32_t *v1,
                                            const int32_t *v2, Body body) {
-    const int32_t tiles = (n + 1023) >> 10;
+    const int32_t tiles = (n + 4 * SWEEP_THREADS - 1) / (4 * SWEEP_THREADS);
     int32_t c0 = threadIdx.x * 4;
     SweepTile<R> T;
-    for (int32_t t = 0; t < tiles; ++t, c0 += 1024) {
+    for (int32_t t = 0; t < tiles; ++t, c0 += 4 * SWEEP_THREADS) {
         sweep_load<R>(T, g, r0, act, c0, n, v1, v2);
         body(T, c0, t);
     }
@@ -647,7 +649,7 @@ __device__ __forceinline__ void mask_detect_rows(const DevGraph &g, const FusedA
             if ((lane & 7) == 0 && c0 < n && word != 0) fa.flag_bits[(int64_t)i * nwp + (c0 >> 5)] = word;
             if (__ballot(bits != 0) != 0) row_mask |= 1u << r;
         }
-        const int32_t chunk = t * 4 + (threadIdx.x >> 6);
+        const int32_t chunk = c0 >> 8;  // this wavefront's 256 columns
         if (lane == 0 && chunk * 256 < n) fa.marks[(int64_t)rg * fa.mark_pitch + chunk] = (uint8_t)row_mask;
     });
 }
@@ -716,7 +718,7 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
 
 // |F| and Phi of a removal's mask, counted without writing it (a route that
 // needs no flags still reports them, and Algorithm 5's cost test reads Phi).
-__global__ __launch_bounds__(256) void k_mask_count(DevGraph g, FusedArgs fa) {
+__global__ __launch_bounds__(SWEEP_THREADS) void k_mask_count(DevGraph g, FusedArgs fa) {
     __shared__ uint32_t s_cnt, s_rows;
     const int n = g.n_slots;
     const int32_t r0 = blockIdx.x * SWEEP_ROWS;
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(256) void k_mask_count(DevGraph g, FusedArgs fa) {
 // (colu, colv, rowu, rowv = fa.col1, col2, row2, row1) or the mask of a tight
 // increase; nothing for a no-op.  One work-group per SWEEP_ROWS rows (the
 // grid of a no-op launch is n / SWEEP_ROWS work-groups that return at once).
-__global__ __launch_bounds__(256) void k_edge_sweep(DevGraph g, FusedArgs fa, int32_t w) {
+__global__ __launch_bounds__(SWEEP_THREADS) void k_edge_sweep(DevGraph g, FusedArgs fa, int32_t w) {
     const int32_t mode = g.ctl->edge_mode;
     if (mode == EDGE_NOOP) return;
     const int32_t r0 = blockIdx.x * SWEEP_ROWS;
@@ -1243,12 +1245,12 @@ void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
 
 void launch_mask_count(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_mask_count<<<(g.n_slots + SWEEP_ROWS - 1) / SWEEP_ROWS, 256, 0, s>>>(g, fa);
+    k_mask_count<<<(g.n_slots + SWEEP_ROWS - 1) / SWEEP_ROWS, SWEEP_THREADS, 0, s>>>(g, fa);
 }
 
 void launch_edge_sweep(const DevGraph &g, const FusedArgs &fa, int32_t w, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_edge_sweep<<<(g.n_slots + SWEEP_ROWS - 1) / SWEEP_ROWS, 256, 0, s>>>(g, fa, w);
+    k_edge_sweep<<<(g.n_slots + SWEEP_ROWS - 1) / SWEEP_ROWS, SWEEP_THREADS, 0, s>>>(g, fa, w);
 }
 
 void launch_count_flag_rows(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
