@@ -131,6 +131,47 @@ def test_random_sequences_tiny_index(limit, undirected):
 
 
 @pytest.mark.parametrize("undirected", [False, True])
+def test_largest_capacity(undirected):
+    """A graph at the largest capacity (pitch APSP_MAX_CAPACITY): every update
+    kind against the oracle, with weights 1..3 so that removals and tight
+    increases flag many pairs and rows go to the heavy-row pass, whose LDS
+    row then spans the whole pitch (close to the 160 KiB limit)."""
+    from paper_2412_15122_amd import _native as N
+    from paper_2412_15122_amd.apsp import Graph
+    rng = np.random.default_rng(7100 + undirected)
+    n = 260
+    adj = W.random_graph(n, 1, 3, undirected=undirected, density=1.0, seed=int(rng.integers(1 << 30)))
+    g = Graph(adj, undirected=undirected, capacity=N.APSP_MAX_CAPACITY)
+    st = W.GraphState(adj, undirected)
+    A, ids = adj.copy(), list(range(n))
+    expect_equal(g, A, ids, "cold")
+    heavy = 0
+    kinds = [W.REMOVE, W.ADD, W.INCREASE, W.DECREASE] * 3
+    for step, kind in enumerate(kinds):
+        if kind == W.INCREASE:
+            # the lightest edge on the most shortest paths: a tight increase
+            u, v = 0, 1
+            best = -1
+            Dm = O.fw(A)
+            for _ in range(40):
+                a, b = (int(x) for x in rng.choice(len(ids), size=2, replace=False))
+                if A[a, b] >= INF:
+                    continue
+                c = int(((Dm[:, a:a + 1] + A[a, b] + Dm[b:b + 1, :]) == Dm).sum())
+                if c > best:
+                    best, u, v = c, a, b
+            upd = W.Update(W.INCREASE, u=ids[u], v=ids[v], w=int(A[u, v]) + 3, old=int(A[u, v]))
+            st.set_weight(ids[u], ids[v], upd.w)
+        else:
+            upd = W.make_update(rng, st, kind, wmin=1, wmax=3, inc_max=6, density=1.0)
+        A, ids = apply(g, A, ids, upd, undirected)
+        heavy += g.stats()["heavy_rows"]
+        expect_equal(g, A, ids, f"step {step} {upd.kind}")
+    assert heavy > 0, "no update reached the heavy-row pass"
+    g.close()
+
+
+@pytest.mark.parametrize("undirected", [False, True])
 def test_random_sequences_zero_weights_sparse(undirected):
     random_sequence(3000 + undirected, 120, undirected, 14, 4, density=0.08, zero=0.3)
 
