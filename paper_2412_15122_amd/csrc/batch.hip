@@ -788,10 +788,12 @@ __device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGr
             if (tid == 0) *s_flag = 0;
             __syncthreads();
             bool changed = false;
-            for (int w = grp; w < nw; w += BATCH_THREADS / 4) {
-                uint32_t bits = fw[w];
+            // a group takes 8 columns (a quarter of a flag word) at a time, so
+            // that a dense word is shared by four groups
+            for (int u = grp; u < 4 * nw; u += BATCH_THREADS / 4) {
+                uint32_t bits = (fw[u >> 2] >> (8 * (u & 3))) & 0xFFu;
                 while (bits) {
-                    const int32_t y = w * 32 + __ffs(bits) - 1;
+                    const int32_t y = (u >> 2) * 32 + 8 * (u & 3) + __ffs(bits) - 1;
                     bits &= bits - 1;
                     uint32_t best = cur[y];
                     const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
@@ -834,17 +836,18 @@ __device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGr
         }
         for (int w = tid; w < nw; w += BATCH_THREADS) need[w] = 0;
         __syncthreads();
-        for (int w = grp; w < nw; w += BATCH_THREADS / 4) {
-            uint32_t bits = fw[w], mark = 0;
+        for (int u = grp; u < 4 * nw; u += BATCH_THREADS / 4) {  // quarter words, as in the sweeps
+            const int sh8 = 8 * (u & 3);
+            uint32_t bits = (fw[u >> 2] >> sh8) & 0xFFu, mark = 0;
             while (bits) {
                 const int b = __ffs(bits) - 1;
                 bits &= bits - 1;
-                const int32_t y = w * 32 + b;
+                const int32_t y = (u >> 2) * 32 + sh8 + b;
                 uint32_t beta_eff = (uint32_t)g.nin_beta[y];
                 if (lim < NIN_L) beta_eff = min(beta_eff, (uint32_t)g.nin[(int64_t)y * NIN_L + lim].y);
-                if (cur[y] > beta_eff) mark |= 1u << b;
+                if (cur[y] > beta_eff) mark |= 1u << (sh8 + b);
             }
-            if (l4 == 0 && mark) need[w] = mark;
+            if (l4 == 0 && mark) atomicOr(&need[u >> 2], mark);
         }
         __syncthreads();
         if (tid == 0) *s_flag = 0;

@@ -1107,21 +1107,17 @@ __device__ __forceinline__ void mask_finish_block(const DevGraph &g, const int32
 //   are recomputed by Bellman-Ford against the now exact remainder of the
 //   row.
 //   directed: every flagged entry is recomputed by Bellman-Ford.
-// Counts the changed pairs among row i's flagged entries (bits of the words
-// fl, read through `word`), whose final values are cur[], and adds them to
-// my_changed / my_rows_changed (block-uniform).
-template <class Word>
+// Counts the changed pairs among row i's flagged entries (list[0..cnt)),
+// whose final values are cur[], and adds them to my_changed /
+// my_rows_changed (block-uniform).  One entry per thread at a time, so that
+// the old values' loads of a dense flag word are not one thread's chain.
 __device__ __forceinline__ void heavy_count_changed(const FusedArgs &fa, const RowTests &rt, const uint32_t *cur,
-                                                    int nw, Word word, uint32_t *red, int &my_changed,
+                                                    const int32_t *list, int cnt, uint32_t *red, int &my_changed,
                                                     int &my_rows_changed) {
     int ch = 0;
-    for (int w = threadIdx.x; w < nw; w += FUSED_THREADS) {
-        uint32_t bits = word(w);
-        while (bits) {
-            const int32_t y = w * 32 + __ffs(bits) - 1;
-            bits &= bits - 1;
-            ch += cur[y] != flagged_old(fa, rt, y);
-        }
+    for (int e = threadIdx.x; e < cnt; e += FUSED_THREADS) {
+        const int32_t y = list[e];
+        ch += cur[y] != flagged_old(fa, rt, y);
     }
     ch = block_sum<FUSED_THREADS>(ch, red);
     my_changed += ch;
@@ -1163,17 +1159,8 @@ __device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedA
             const int32_t i = fa.heavy_rows[idx];
             const RowTests rt = row_tests(g, fa, i, w_old);
             int32_t *Drow = g.D + (int64_t)i * g.ld;
-            // the row into LDS, four 16-byte loads per thread in flight
-            for (int32_t c = tid * 4; c < n; c += FUSED_THREADS * 16) {
-                uint4 v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (c + q * FUSED_THREADS * 4 < n)
-                        v[q] = *reinterpret_cast<const uint4 *>(Drow + c + q * FUSED_THREADS * 4);
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (c + q * FUSED_THREADS * 4 < n) *reinterpret_cast<uint4 *>(sh.cur + c + q * FUSED_THREADS * 4) = v[q];
-            }
+            for (int32_t c = tid * 4; c < n; c += FUSED_THREADS * 4)
+                *reinterpret_cast<uint4 *>(sh.cur + c) = *reinterpret_cast<const uint4 *>(Drow + c);
             uint32_t *fw = fa.flag_bits + (int64_t)i * nwp;
             for (int w = tid; w < nw; w += FUSED_THREADS) sh.fl2[w] = fw[w] & sh.fl[w];
             __syncthreads();
@@ -1192,10 +1179,12 @@ __device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedA
             // cur holds every final entry of the row (the light-row entries
             // came in mirrored); count the changed ones over all the row's
             // flags, then clear its words: the bitmap is left clear
-            heavy_count_changed(fa, rt, sh.cur, nw, [&](int w) { return fw[w]; }, sh.red, my_changed,
-                                my_rows_changed);
+            for (int w = tid; w < nw; w += FUSED_THREADS) sh.fl2[w] = fw[w];
+            __syncthreads();
+            const int all = compact_bits(sh.fl2, nw, glist, sh.red);
+            heavy_count_changed(fa, rt, sh.cur, glist, all, sh.red, my_changed, my_rows_changed);
             for (int w = tid; w < nw; w += FUSED_THREADS)
-                if (fw[w]) fw[w] = 0u;
+                if (sh.fl2[w]) fw[w] = 0u;
             __syncthreads();
         }
         if (tid == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
@@ -1221,7 +1210,7 @@ __device__ __forceinline__ void fused_heavy_body(const DevGraph &g, const FusedA
         }
         if (tid == 0) my_sweeps = max(my_sweeps, sweeps);
         __syncthreads();
-        heavy_count_changed(fa, rt, sh.cur, nw, [&](int w) { return sh.fl[w]; }, sh.red, my_changed, my_rows_changed);
+        heavy_count_changed(fa, rt, sh.cur, glist, all, sh.red, my_changed, my_rows_changed);
         __syncthreads();
     }
     if (tid == 0 && my_fs) atomicAdd(&g.ctl->full_scans, my_fs);
