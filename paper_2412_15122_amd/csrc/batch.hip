@@ -984,11 +984,15 @@ __device__ __forceinline__ void grid_barrier(BatchHeader *hdr) {
         const unsigned grp = blockIdx.x & 7u;
         const unsigned ngroups = nb < 8 ? nb : 8;
         const unsigned gsize = nb / 8 + (grp < nb % 8 ? 1u : 0u);
-        __threadfence();
-        const unsigned gen = __hip_atomic_load(&hdr->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned a = __hip_atomic_fetch_add(&hdr->bar_group[grp * 32], 1u, __ATOMIC_ACQ_REL,
+        // one release per work-group (its writes, in L2 after the block
+        // barrier, written back for the other XCDs) and one acquire on the
+        // way out: each device-scope fence costs an L2 walk, and a barrier
+        // with four of them per work-group cost ~40 us more
+        const unsigned gen = __hip_atomic_load(&hdr->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned a = __hip_atomic_fetch_add(&hdr->bar_group[grp * 32], 1u, __ATOMIC_RELEASE,
                                                   __HIP_MEMORY_SCOPE_AGENT);
         if (a == gsize - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the group's releases, before passing them on
             __hip_atomic_store(&hdr->bar_group[grp * 32], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned b = __hip_atomic_fetch_add(&hdr->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
             if (b == ngroups - 1) {
@@ -1005,8 +1009,7 @@ __device__ __forceinline__ void grid_barrier(BatchHeader *hdr) {
             ++it;
         }
         if (it >= BARRIER_SPIN_LIMIT) atomicOr(&hdr->err, 1);
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
