@@ -882,6 +882,128 @@ __device__ __forceinline__ void heavy_row_block(const DevGraph &g, const BatchGr
     __syncthreads();
 }
 
+// heavy_row_block with the row's flagged columns compacted once into an LDS
+// list (`list`: room for n entries): the sweeps hand out entries, not flag
+// words, so a dense word does not become one group's chain, and each group
+// keeps its first entry's 32 lightest in-edges in registers across the
+// sweeps.  Same fixed point, same writes.
+__device__ __forceinline__ void heavy_row_block_listed(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa,
+                                                       int32_t i, uint32_t *cur, int32_t *list, uint32_t *need,
+                                                       int *s_flag, uint32_t *red) {
+    const int tid = threadIdx.x, grp = tid >> 2, l4 = tid & 3;
+    constexpr int NG = BATCH_THREADS / 4;
+    const int n = g.n_slots;
+    const int nw = (n + 31) / 32;
+    const int64_t nwp = (g.P + 31) / 32;
+    const int lim = g.lim;
+    const int32_t *Min = in_matrix(g);
+    int32_t *Drow = g.D + (int64_t)i * g.ld;
+    uint32_t *fw = bg.flag_bits + (int64_t)i * nwp;
+    for (int32_t c = tid * 4; c < n; c += BATCH_THREADS * 4)
+        *reinterpret_cast<uint4 *>(cur + c) = *reinterpret_cast<const uint4 *>(Drow + c);
+    // compact the flagged columns: a thread per word, then a block scan
+    int total = 0;
+    for (int w0 = 0; w0 < nw; w0 += BATCH_THREADS) {
+        const int w = w0 + tid;
+        const uint32_t bits0 = w < nw ? fw[w] : 0u;
+        int tot;
+        int pos = total + block_exscan<BATCH_THREADS>(__popc(bits0), red, &tot);
+        for (uint32_t bits = bits0; bits; bits &= bits - 1) list[pos++] = w * 32 + __ffs(bits) - 1;
+        total += tot;
+        __syncthreads();
+    }
+    for (int e = tid; e < total; e += BATCH_THREADS) cur[list[e]] = INF;
+    if (fa.mode == FUSED_REMOVE && tid == 0) cur[fa.k] = INF;
+    __syncthreads();
+    const bool has0 = grp < total;
+    const int32_t y0 = has0 ? list[grp] : 0;
+    const int4 *Y4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y0 * NIN_L);
+    const int4 none4 = make_int4(0, (int)INF, 0, (int)INF);
+    const int4 q0 = has0 ? index_pair(Y4, lim, 2 * l4) : none4, q1 = has0 ? index_pair(Y4, lim, 8 + 2 * l4) : none4;
+    const int4 q2 = has0 ? index_pair(Y4, lim, 16 + 2 * l4) : none4, q3 = has0 ? index_pair(Y4, lim, 24 + 2 * l4) : none4;
+    const uint32_t wl0 = (uint32_t)__shfl(q3.w, 3, 4);  // entry 31 (INF past lim)
+    for (;;) {
+        for (;;) {
+            __syncthreads();
+            if (tid == 0) *s_flag = 0;
+            __syncthreads();
+            bool changed = false;
+            for (int e = grp; e < total; e += NG) {
+                const int32_t y = e == grp ? y0 : list[e];
+                const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
+                uint32_t best = cur[y];
+                uint32_t cm;
+                uint32_t wl;
+                if (e == grp) {
+                    cm = pull_pair(cur, q0, best, INF);
+                    cm = pull_pair(cur, q1, best, cm);
+                    cm = pull_pair(cur, q2, best, cm);
+                    cm = pull_pair(cur, q3, best, cm);
+                    wl = wl0;
+                } else {
+                    const int4 r0 = index_pair(L4, lim, 2 * l4), r1 = index_pair(L4, lim, 8 + 2 * l4);
+                    const int4 r2 = index_pair(L4, lim, 16 + 2 * l4), r3 = index_pair(L4, lim, 24 + 2 * l4);
+                    cm = pull_pair(cur, r0, best, INF);
+                    cm = pull_pair(cur, r1, best, cm);
+                    cm = pull_pair(cur, r2, best, cm);
+                    cm = pull_pair(cur, r3, best, cm);
+                    wl = (uint32_t)__shfl(r3.w, 3, 4);
+                }
+                best = min(best, group4_min(cm));
+                for (int c0 = 32; c0 < lim && wl < best; c0 += 32) {  // rare: the rest of the list
+                    uint32_t cr = INF;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cr = pull_pair(cur, index_pair(L4, lim, c0 + 8 * q + 2 * l4), best, cr);
+                    best = min(best, group4_min(cr));
+                    wl = (uint32_t)__shfl(index_pair(L4, lim, c0 + 24 + 2 * l4).w, 3, 4);
+                }
+                if (l4 == 0 && best < cur[y]) {
+                    cur[y] = best;
+                    changed = true;
+                }
+            }
+            if (changed) *s_flag = 1;
+            __syncthreads();
+            if (*s_flag == 0) break;
+        }
+        for (int w = tid; w < nw; w += BATCH_THREADS) need[w] = 0;
+        __syncthreads();
+        for (int e = tid; e < total; e += BATCH_THREADS) {
+            const int32_t y = list[e];
+            uint32_t beta_eff = (uint32_t)g.nin_beta[y];
+            if (lim < NIN_L) beta_eff = min(beta_eff, (uint32_t)g.nin[(int64_t)y * NIN_L + lim].y);
+            if (cur[y] > beta_eff) atomicOr(&need[y >> 5], 1u << (y & 31));
+        }
+        __syncthreads();
+        if (tid == 0) *s_flag = 0;
+        for (int w = 0; w < nw; ++w) {  // block-uniform: every thread reads the same LDS word
+            uint32_t bits = need[w];
+            while (bits) {
+                const int32_t y = w * 32 + __ffs(bits) - 1;
+                bits &= bits - 1;
+                const int32_t *col = Min + (int64_t)y * g.ld;
+                uint32_t best = INF;
+                for (int32_t x = tid; x < n; x += BATCH_THREADS) best = min(best, cat(cur[x], (uint32_t)col[x]));
+                best = block_min<BATCH_THREADS>(best, red);
+                if (tid == 0 && best < cur[y]) {
+                    cur[y] = best;
+                    *s_flag = 1;
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        if (*s_flag == 0) break;
+    }
+    for (int e = tid; e < total; e += BATCH_THREADS) {
+        const int32_t y = list[e];
+        Drow[y] = (int32_t)cur[y];
+    }
+    for (int w = tid; w < nw; w += BATCH_THREADS)
+        if (fw[w]) fw[w] = 0u;  // used up: the bitmap is left clear
+    __syncthreads();
+}
+
 // Algorithm 7's query; a widest graph's distance goes out as a width.
 __device__ __forceinline__ void batch_query(const DevGraph &g, const BatchGraph &bg, const BatchItem &it) {
     query_block(g, it.a, it.b, it.out, bg.qscratch);
@@ -1236,8 +1358,13 @@ __global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch_lockstep(BatchHeader
                 DevGraph g = bg.g;
                 g.n_slots = it.n_slots;
                 const FusedArgs fa = it.op == BOP_REMOVE ? remove_args(bg, it) : increase_args(g, bg);
-                heavy_row_block(g, bg, fa, bg.heavy_rows[found_j], stage, reinterpret_cast<uint32_t *>(wlists),
-                                &s_flag, ssh.red);
+                if (lockstep_stages_sweeps(P_max))  // the sweeps' staging area past the need bitmap holds the list
+                    heavy_row_block_listed(g, bg, fa, bg.heavy_rows[found_j], stage,
+                                           wlists + std::max(4 * 2 * ROW_CAP, (P_max + 31) / 32),
+                                           reinterpret_cast<uint32_t *>(wlists), &s_flag, ssh.red);
+                else
+                    heavy_row_block(g, bg, fa, bg.heavy_rows[found_j], stage, reinterpret_cast<uint32_t *>(wlists),
+                                    &s_flag, ssh.red);
             }
         }
         grid_barrier(hdr);
@@ -1256,6 +1383,12 @@ size_t batch_lds_bytes(int32_t P_max) { return (2 * (size_t)P_max + 4 * 2 * ROW_
 // The region after the P_max staging words holds the 4 wave lists of the
 // recompute phase, and later the need bitmap of the heavy-row phase (one bit
 // per column): whichever is larger.
+// A heavy row's list (room for P_max entries) sits past the need bitmap in
+// the sweeps' staging area: P_max + max(wave lists, bitmap) + P_max words fit
+// in the 2 P_max + 2 LOCKSTEP_STAGE_ROWS words of a staged launch.
+static_assert(4 * 2 * ROW_CAP <= 2 * LOCKSTEP_STAGE_ROWS &&
+                  (LOCKSTEP_STAGE_MAX_PITCH + 31) / 32 <= 2 * LOCKSTEP_STAGE_ROWS,
+              "the heavy-row list fits in the staging area");
 size_t batch_lockstep_lds_bytes(int32_t P_max) {
     size_t words = (size_t)P_max + std::max<size_t>(4 * 2 * ROW_CAP, ((size_t)P_max + 31) / 32);
     if (lockstep_stages_sweeps(P_max)) words = std::max<size_t>(words, 2 * (size_t)P_max + 2 * LOCKSTEP_STAGE_ROWS);
