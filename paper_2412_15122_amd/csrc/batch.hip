@@ -538,7 +538,8 @@ __device__ __forceinline__ void wave_bellman_ford_words(const DevGraph &g, int32
 // without one, read their flag words directly (needs: 4 * ceil(P / 32)
 // words of LDS).
 __device__ __forceinline__ void recompute_rows(const DevGraph &g, const BatchGraph &bg, const FusedArgs &fa, int32_t r0, int32_t r1,
-                               int32_t *wlists, int32_t *glists, uint32_t *needs, bool defer_heavy = false) {
+                               int32_t *wlists, int32_t *glists, uint32_t *needs, bool defer_heavy = false,
+                               uint32_t *light = nullptr) {
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     const int nw = (g.n_slots + 31) / 32;
     const int64_t nwp = (g.P + 31) / 32;
@@ -588,6 +589,21 @@ __device__ __forceinline__ void recompute_rows(const DevGraph &g, const BatchGra
             }
             __threadfence_block();
             int32_t *Drow = g.D + (int64_t)i * g.ld;
+            if (light && cnt <= ROW_CAP) {
+                // the values stay in LDS: one pull per entry and a closure
+                // (light_row); flagged entries of D are neither reset nor read
+                const LightRowLds L = light_row_lds(light + wv * LIGHT_ROW_WORDS);
+                if (fa.mode == FUSED_REMOVE && lane == 0) Drow[fa.k] = (int32_t)INF;
+                __threadfence_block();
+                const uint32_t w_old = fa.mode == FUSED_INCREASE ? (uint32_t)g.ctl->w_old : 0u;
+                int sweeps = 0;
+                const uint32_t v = light_row(g, fa, row_tests(g, fa, i, w_old), Drow, list, cnt, L.fsl, L.old, L.val,
+                                             L.keys, L.pos, L.W, sweeps, nfs);
+                if (lane < cnt) Drow[list[lane]] = (int32_t)v;
+                for (int w = lane; w < nw; w += 64)
+                    if (fw[w]) fw[w] = 0u;
+                continue;
+            }
             if (cnt <= ROW_CAP || glist) {
                 const int32_t *L = cnt <= ROW_CAP ? list : glist;
                 for (int e = lane; e < cnt; e += 64) Drow[L[e]] = (int32_t)INF;
@@ -1309,10 +1325,11 @@ __global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch_lockstep(BatchHeader
                 const int32_t r0 = (c - baseC[gi]) * BATCH_RECOMPUTE_ROWS;
                 const int32_t r1 = min(r0 + BATCH_RECOMPUTE_ROWS, it.n_slots);
                 // each wavefront uses only its own lists and need bitmap in LDS
+                uint32_t *light = lockstep_light_rows(P_max) ? stage + lockstep_light_offset(P_max) : nullptr;
                 if (it.op == BOP_REMOVE) {
-                    recompute_rows(g, bg, remove_args(bg, it), r0, r1, wlists, nullptr, stage, true);
+                    recompute_rows(g, bg, remove_args(bg, it), r0, r1, wlists, nullptr, stage, true, light);
                 } else if (it.op == BOP_EDGE && g.ctl->edge_mode == EDGE_INCREASE) {
-                    recompute_rows(g, bg, increase_args(g, bg), r0, r1, wlists, nullptr, stage, true);
+                    recompute_rows(g, bg, increase_args(g, bg), r0, r1, wlists, nullptr, stage, true, light);
                 }
             }
             if (threadIdx.x == 0 && s < BATCH_PHASE_STAMPS)
@@ -1392,6 +1409,8 @@ static_assert(4 * 2 * ROW_CAP <= 2 * LOCKSTEP_STAGE_ROWS &&
 size_t batch_lockstep_lds_bytes(int32_t P_max) {
     size_t words = (size_t)P_max + std::max<size_t>(4 * 2 * ROW_CAP, ((size_t)P_max + 31) / 32);
     if (lockstep_stages_sweeps(P_max)) words = std::max<size_t>(words, 2 * (size_t)P_max + 2 * LOCKSTEP_STAGE_ROWS);
+    if (lockstep_light_rows(P_max)) words = lockstep_light_offset(P_max) + (BATCH_THREADS / 64) * LIGHT_ROW_WORDS;
+    static_assert(LIGHT_ROW_WORDS == LOCKSTEP_LIGHT_WORDS && BATCH_THREADS / 64 == 4, "light-row LDS sizing");
     return words * sizeof(uint32_t);
 }
 
@@ -1399,7 +1418,11 @@ hipError_t configure_batch() {
     static hipError_t status = hipErrorNotReady;
     if (status != hipErrorNotReady) return status;
     const int lds = (int)batch_lds_bytes(BATCH_MAX_CAPACITY);
-    const int lds2 = (int)batch_lockstep_lds_bytes(BATCH_MAX_CAPACITY);
+    // the largest launch: the largest pitch, or the largest one with the
+    // light rows' LDS
+    int32_t p_light = LOCKSTEP_STAGE_MAX_PITCH;
+    while (p_light > 0 && !lockstep_light_rows(p_light)) --p_light;
+    const int lds2 = (int)std::max(batch_lockstep_lds_bytes(BATCH_MAX_CAPACITY), batch_lockstep_lds_bytes(p_light));
     status = hipFuncSetAttribute((const void *)k_batch<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (status == hipSuccess)
         status = hipFuncSetAttribute((const void *)k_batch<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);

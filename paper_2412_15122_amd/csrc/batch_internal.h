@@ -87,6 +87,17 @@ __host__ __device__ inline int32_t batch_rows_per_chunk(int32_t n) {
 constexpr int32_t LOCKSTEP_STAGE_ROWS = 256;
 constexpr int32_t LOCKSTEP_STAGE_MAX_PITCH = 4608;
 __host__ __device__ inline bool lockstep_stages_sweeps(int32_t P_max) { return P_max <= LOCKSTEP_STAGE_MAX_PITCH; }
+constexpr int LOCKSTEP_LIGHT_WORDS = ROW_CAP * ROW_CAP + 2 * 64 + 3 * ROW_CAP;  // light_row's per-wave LDS
+// The recompute phase's light rows keep their values in LDS (light_row)
+// when the launch can hold each wavefront's LIGHT_ROW_WORDS past the
+// staging area and still fit three work-groups in a CU's 160 KiB.
+__host__ __device__ inline int32_t lockstep_light_offset(int32_t P_max) {
+    return 2 * P_max + 2 * LOCKSTEP_STAGE_ROWS;
+}
+__host__ __device__ inline bool lockstep_light_rows(int32_t P_max) {
+    return lockstep_stages_sweeps(P_max) &&
+           ((size_t)lockstep_light_offset(P_max) + 4 * (size_t)LOCKSTEP_LIGHT_WORDS) * 4 <= 163840 / 3;
+}
 
 #include "batch_launchers.inc"
 namespace mm {

@@ -799,147 +799,6 @@ __global__ __launch_bounds__(256) void k_count_flag_rows(DevGraph g, FusedArgs f
     if (threadIdx.x == 0) g.ctl->rows = c;
 }
 
-// The flagged columns of a light row as a set: open addressing over FSET
-// slots (at most ROW_CAP keys, so half stay empty and every probe ends),
-// key -1 = empty, with each key's position in the row's list.
-constexpr int FSET_BITS = 6;
-constexpr int FSET = 1 << FSET_BITS;
-static_assert(FSET == 64 && 2 * ROW_CAP <= FSET, "one set slot per lane, at most half of them used");
-__device__ __forceinline__ uint32_t fset_slot(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - FSET_BITS); }
-__device__ __forceinline__ int fset_find(const int32_t *keys, const int32_t *pos, int32_t x) {
-    for (uint32_t h = fset_slot(x);; h = (h + 1) & (FSET - 1)) {
-        const int32_t key = keys[h];
-        if (key == x) return pos[h];
-        if (key < 0) return -1;
-    }
-}
-
-// One light-in-edge pair of a flagged entry e of row i: an edge from an
-// unflagged x lowers cm by D[i][x] (+) w, one from a flagged x (its list
-// position a) is kept as W[a][e] for the closure; edges at least as heavy
-// as best cannot lower the entry and are skipped, and so are those of the
-// removed slot.
-__device__ __forceinline__ uint32_t light_pull_pair(const int32_t *Drow, int4 p, uint32_t best, uint32_t cm, int e,
-                                                    int cnt, int32_t kx, const int32_t *keys, const int32_t *pos,
-                                                    uint32_t *W) {
-    if ((uint32_t)p.y < best && p.x != kx) {
-        const int a = fset_find(keys, pos, p.x);
-        if (a >= 0) W[a * cnt + e] = (uint32_t)p.y;
-        else cm = min(cm, cat((uint32_t)Drow[p.x], (uint32_t)p.y));
-    }
-    if ((uint32_t)p.w < best && p.z != kx) {
-        const int a = fset_find(keys, pos, p.z);
-        if (a >= 0) W[a * cnt + e] = (uint32_t)p.w;
-        else cm = min(cm, cat((uint32_t)Drow[p.z], (uint32_t)p.w));
-    }
-    return cm;
-}
-
-// The new entries of a light row (cnt <= ROW_CAP flagged columns list[]),
-// one wavefront, every value kept in LDS until the end:
-//  1. each flagged entry starts from its best walk whose last edge leaves an
-//     unflagged column -- a pull over its light in-edges, lightest eight
-//     first, the rest only below the bound they give, stopping at the old
-//     value (distances only go up, so an entry back at it is final) -- and
-//     the pull keeps the in-edges that come from flagged columns;
-//  2. Dijkstra over the flagged columns with those edges closes the set;
-//  3. an entry left above its beta_eff could still take an edge missing from
-//     the index: a full scan of its column lowers it, and 2-3 repeat until
-//     no scan lowers anything.
-// Flagged columns are never read from D: their old values may be stale.
-// Returns the entry of list position `lane` (INF past cnt).
-__device__ inline uint32_t light_row(const DevGraph &g, const FusedArgs &fa, const RowTests &rt, int32_t *Drow,
-                                     const int32_t *list, int cnt, int32_t *fsl, int32_t *old, uint32_t *val,
-                                     int32_t *keys, int32_t *pos, uint32_t *W, int &sweeps, int &nfs_total) {
-    const int lane = lane_id();
-    const int g4 = lane >> 2, l4 = lane & 3;
-    const int lim = g.lim;
-    const int32_t kx = fa.mode == FUSED_REMOVE ? fa.k : -1;
-    keys[lane] = -1;
-    for (int q = lane; q < cnt * cnt; q += 64) W[q] = INF;
-    __threadfence_block();
-    int32_t ye = 0;
-    uint32_t olde = INF, beta = INF;
-    if (lane < cnt) {
-        ye = list[lane];
-        uint32_t h = fset_slot(ye);
-        while (atomicCAS(&keys[h], -1, ye) != -1) h = (h + 1) & (FSET - 1);
-        pos[h] = lane;
-        olde = flagged_old(fa, rt, ye);
-        old[lane] = (int32_t)olde;
-        beta = (uint32_t)g.nin_beta[ye];
-        if (lim < NIN_L) beta = min(beta, (uint32_t)g.nin[(int64_t)ye * NIN_L + lim].y);
-    }
-    __threadfence_block();
-    for (int e = g4; e < cnt; e += 16) {
-        const int32_t y = list[e];
-        const uint32_t floor = (uint32_t)old[e];
-        const int4 *L4 = reinterpret_cast<const int4 *>(g.nin + (int64_t)y * NIN_L);
-        int4 p0 = index_pair(L4, lim, 2 * l4), p1 = index_pair(L4, lim, 8 + 2 * l4);
-        int4 p2 = index_pair(L4, lim, 16 + 2 * l4), p3 = index_pair(L4, lim, 24 + 2 * l4);
-        uint32_t best = group4_min(light_pull_pair(Drow, p0, INF, INF, e, cnt, kx, keys, pos, W));
-        uint32_t wl = (uint32_t)__shfl(p0.w, 3, 4);  // the eighth entry
-        for (int c0 = 32; best > floor && wl < best; c0 += 32) {
-            uint32_t cm = light_pull_pair(Drow, p1, best, INF, e, cnt, kx, keys, pos, W);
-            cm = light_pull_pair(Drow, p2, best, cm, e, cnt, kx, keys, pos, W);
-            cm = light_pull_pair(Drow, p3, best, cm, e, cnt, kx, keys, pos, W);
-            best = min(best, group4_min(cm));
-            wl = (uint32_t)__shfl(p3.w, 3, 4);
-            if (c0 >= lim || best <= floor || wl >= best) break;
-            p0 = index_pair(L4, lim, c0 + 2 * l4);
-            p1 = index_pair(L4, lim, c0 + 8 + 2 * l4);
-            p2 = index_pair(L4, lim, c0 + 16 + 2 * l4);
-            p3 = index_pair(L4, lim, c0 + 24 + 2 * l4);
-            best = min(best, group4_min(light_pull_pair(Drow, p0, best, INF, e, cnt, kx, keys, pos, W)));
-            wl = (uint32_t)__shfl(p0.w, 3, 4);
-        }
-        if (l4 == 0) val[e] = best;
-    }
-    __threadfence_block();
-    ++sweeps;
-    // Dijkstra: weights >= 0 and cat is monotone, so the unsettled entry of
-    // smallest value is final
-    uint32_t dist = lane < cnt ? val[lane] : INF;
-    const int32_t *Min = in_matrix(g);
-    for (;;) {
-        bool done = lane >= cnt;
-        for (int it = 0; it < cnt; ++it) {
-            const unsigned long long key =
-                wave_min_key(done ? ~0ull : (((unsigned long long)dist << 32) | (uint32_t)lane));
-            const uint32_t da = (uint32_t)(key >> 32);
-            if (key == ~0ull || da >= INF) break;  // wave-uniform
-            const int a = (int)(key & 63u);
-            if (lane == a) done = true;
-            if (!done) dist = min(dist, cat(da, W[a * cnt + lane]));
-        }
-        // entries that an edge missing from the index could still lower:
-        // full scans of their columns against the row as it stands
-        unsigned long long need = __ballot(lane < cnt && dist > beta && dist > olde);
-        if (!need) break;
-        if (lane < cnt) Drow[ye] = (int32_t)dist;
-        __threadfence_block();
-        nfs_total += __popcll(need);
-        bool lowered = false;
-        while (need) {
-            const int f = __ffsll((long long)need) - 1;
-            need &= need - 1;
-            const uint32_t df = (uint32_t)__shfl((int)dist, f);
-            const uint32_t b = wave_min_plus_below(Drow, Min + (int64_t)list[f] * g.ld, g.n_slots, df);
-            if (b < df) {
-                lowered = true;
-                if (lane == f) {
-                    dist = b;
-                    Drow[ye] = (int32_t)b;
-                }
-            }
-            __threadfence_block();
-        }
-        ++sweeps;
-        if (!lowered) break;
-    }
-    return dist;
-}
-
 // reset_only: only clear the flagged rows' words (after a cold fallback).
 // A row's flag words are cleared once read, except those of an undirected
 // heavy row, which the heavy-row pass reads (and clears) later.
