@@ -57,6 +57,9 @@ def parse():
                          "medians of single updates on the n=16384 graph (add, remove, a forced wide edge "
                          "decrease and the worst-case increase that undoes it)")
     ap.add_argument("--reps", type=int, default=20, help="kernels: repetitions per update kind")
+    ap.add_argument("--prof-every", type=int, default=10,
+                    help="updates: HIP events bracket launches 0, k, 2k, ... of the dominant kernel in each timed "
+                         "step (two event records cost ~11 us of stream time; the launches between carry none)")
     ap.add_argument("--reps-sweep", type=int, default=5,
                     help="updates: repetitions of the edge-sweep roofline probe (forced decrease, worst increase)")
     ap.add_argument("--graphs", type=int, default=None, help="batched / serving: number of graphs (512 / 64)")
@@ -82,11 +85,13 @@ def parse():
 # ---------------------------------------------------------------------------
 # algorithmic bytes per launch of the sweep kernels
 # ---------------------------------------------------------------------------
-# add_relax reads every live row of D once (the new pair distances need every
-# old entry): 4 n^2 bytes per added node, n the live count before the add.
-# mask_detect (a removal; an edge increase's mask runs in edge_sweep) reads
-# every live row but k once: 4 (n - 1) n bytes.  Writes (changed entries, the
-# flag bitmap) are not counted.
+# The benchmark graph is undirected, so D is symmetric and each sweep needs
+# one entry per unordered pair (see sweep_bytes): add_relax reads every pair
+# of old nodes once, 4 n (n - 1) / 2 bytes per added node, n the live count
+# before the add; mask_detect (a removal; an edge increase's mask runs in
+# edge_sweep) every pair of the other n - 1 nodes, 4 (n - 1)(n - 2) / 2
+# bytes.  Writes (changed entries and their mirrors, the flag bitmap) are not
+# counted.
 
 
 KERNEL_SOURCES = ("update.hip", "device_common.h")   # where add_relax and mask_detect live
@@ -100,6 +105,17 @@ def source_hash():
         with open(os.path.join(ROOT, "paper_2412_15122_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def sweep_bytes(kind, live):
+    """Algorithmic bytes of one full sweep of D on the undirected graph of
+    `live` nodes.  D is symmetric, so an addition's relaxation (Theorem 3,
+    in = out) reads each unordered pair of the old nodes once, 4 n (n-1) / 2
+    bytes, and a removal's mask (Corollary 3) each unordered pair of the
+    other n - 1 nodes, 4 (n-1)(n-2) / 2."""
+    if kind == "add":
+        return 2 * live * (live - 1)
+    return 2 * (live - 1) * (live - 2)
 
 
 def traffic_from_profiles(kernel):
@@ -491,8 +507,11 @@ def bench_kernels(args):
         if kind in ("decrease", "add"):
             rr = float(np.median([s_["rows_relaxed"] for s_ in st]))
             row["rows_relaxed"] = rr
-            # rows swept by the relaxation, 4 n bytes each, over the median time of the whole call
-            row["swept_GBps_whole_call"] = round(rr * 4 * n / (float(np.median(t)) * 1e-3) / 1e9, 1)
+            # bytes swept over the median time of the whole call: a decrease reads its rows
+            # (4 n bytes each); an addition to the undirected graph reads each unordered
+            # pair of the old nodes once (D is symmetric)
+            swept = rr * 4 * n if kind == "decrease" else sweep_bytes("add", n)
+            row["swept_GBps_whole_call"] = round(swept / (float(np.median(t)) * 1e-3) / 1e9, 1)
         if kind in ("remove", "increase"):
             row["flagged"] = float(np.median([s_["flagged"] for s_ in st]))
             row["rows"] = float(np.median([s_["rows"] for s_ in st]))
@@ -688,7 +707,7 @@ def main():
         if step == 0:
             g.profile(-1)          # every kernel: find the dominant one
         elif timed and prof_kernel is not None:
-            g.profile(1 << kid[prof_kernel])
+            g.profile(1 << kid[prof_kernel], every=args.prof_every)
         events = [torch.cuda.Event(enable_timing=True) for _ in block] if latency_step else None
         start = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -736,22 +755,31 @@ def main():
 
     # algorithmic bytes of the dominant kernel over the timed steps: replay the
     # live counts (every add / remove changes n by one; each step starts at n)
+    # (only the launches the events timed: 0, every, 2 every, ... of each step)
     removes_bytes = adds_bytes = 0
     launches = {"add_relax": 0, "mask_detect": 0}
+    seen = {"add_relax": 0, "mask_detect": 0}
     for t, k in enumerate(kinds_all):
         if t % len(block) == 0:
             live = n
+            seen = {"add_relax": 0, "mask_detect": 0}
         if k == W.ADD:
-            adds_bytes += 4 * live * live
-            launches["add_relax"] += 1
+            if seen["add_relax"] % args.prof_every == 0:
+                adds_bytes += sweep_bytes("add", live)
+                launches["add_relax"] += 1
+            seen["add_relax"] += 1
             live += 1
         elif k == W.REMOVE:
-            removes_bytes += 4 * (live - 1) * live
-            launches["mask_detect"] += 1
+            if seen["mask_detect"] % args.prof_every == 0:
+                removes_bytes += sweep_bytes("remove", live)
+                launches["mask_detect"] += 1
+            seen["mask_detect"] += 1
             live -= 1
     roofline = None
     if prof_kernel and "timed" in prof_totals and prof_totals["timed"][1] > 0:
         c, ms = prof_totals["timed"]
+        if c != launches[prof_kernel]:
+            raise RuntimeError(f"{prof_kernel}: {c} timed launches, expected {launches[prof_kernel]}")
         alg = adds_bytes if prof_kernel == "add_relax" else removes_bytes
         achieved = alg / (ms * 1e-3) / 1e9
         tb = None if minimax else traffic_from_profiles(prof_kernel)   # counters were taken on shortest paths
@@ -759,13 +787,14 @@ def main():
         # the live count of the step: the measured traffic over its
         # algorithmic bytes at that n is the comparable figure
         n_pmc = 16384
-        alg_pmc = 4 * n_pmc * n_pmc if prof_kernel == "add_relax" else 4 * (n_pmc - 1) * n_pmc
+        alg_pmc = sweep_bytes("add" if prof_kernel == "add_relax" else "remove", n_pmc)
         roofline = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
             "traffic_at_n": n_pmc if tb else None,
             "traffic_vs_algorithmic": round(tb / alg_pmc, 4) if tb else None,
-            "kernel": prof_kernel, "launches": c, "avg_launch_ms": round(ms / max(c, 1), 4),
+            "kernel": prof_kernel, "launches": c, "timed_every": args.prof_every,
+            "avg_launch_ms": round(ms / max(c, 1), 4),
             "algorithmic_bytes_per_launch": round(alg / max(c, 1)),
         }
 

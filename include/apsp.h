@@ -387,6 +387,11 @@ apsp_status apsp_set_index_limit(apsp_graph *g, int32_t limit);
  * the number of timed launches and their summed duration in ms. */
 apsp_status apsp_profile(apsp_graph *g, int64_t kernel_mask);
 apsp_status apsp_profile_read(apsp_graph *g, int32_t kernel, int64_t *launches, double *total_ms);
+/* As apsp_profile, but only launches 0, every, 2 every, ... of each kernel in
+ * kernel_mask are timed (each timed launch costs two event records on the
+ * stream; sampling keeps that cost out of the launches in between).  every
+ * >= 1, else APSP_E_INVALID. */
+apsp_status apsp_profile_every(apsp_graph *g, int64_t kernel_mask, int32_t every);
 int32_t apsp_kernel_count(void);
 const char *apsp_kernel_name(int32_t kernel);
 

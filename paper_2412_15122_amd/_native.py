@@ -118,6 +118,7 @@ SIGNATURES = {
     "apsp_set_fallback": (_I32, [_P, _I32, ctypes.c_double]),
     "apsp_set_index_limit": (_I32, [_P, _I32]),
     "apsp_profile": (_I32, [_P, _I64]),
+    "apsp_profile_every": (_I32, [_P, _I64, _I32]),
     "apsp_profile_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     "apsp_graph_clone": (_I32, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
     "apsp_graph_relocate": (_I32, [_P, _P, ctypes.c_size_t]),

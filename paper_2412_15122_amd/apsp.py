@@ -393,8 +393,8 @@ class Graph:
     def set_index_limit(self, limit: int) -> None:
         N.check(self._lib.apsp_set_index_limit(self._h, int(limit)), "apsp_set_index_limit")
 
-    def profile(self, mask: int) -> None:
-        N.check(self._lib.apsp_profile(self._h, int(mask)), "apsp_profile")
+    def profile(self, mask: int, every: int = 1) -> None:
+        N.check(self._lib.apsp_profile_every(self._h, int(mask), int(every)), "apsp_profile_every")
 
     def profile_read(self, kernel: int) -> Tuple[int, float]:
         c = ctypes.c_int64()

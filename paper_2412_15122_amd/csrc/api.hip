@@ -26,7 +26,8 @@ thread_local std::string apsp_host::g_err;
 namespace apsp {
 void Prof::begin(int32_t kid) {
     auto *p = static_cast<apsp_host::ProfImpl *>(impl);
-    if (!on || !p || !((p->mask >> kid) & 1)) {
+    // launches 0, every, 2 every, ... of each enabled kernel are timed
+    if (!on || !p || !((p->mask >> kid) & 1) || p->seen[kid]++ % p->every != 0) {
         if (p) p->cur_kid = -1;
         return;
     }
@@ -48,6 +49,15 @@ void Prof::end() {
 }  // namespace apsp
 
 namespace {
+
+// The statistics an edge update left as partials (see update_edge_with),
+// summed into the control block.
+apsp_status flush_stats(apsp_graph *g) {
+    if (!g->stats_pending) return APSP_OK;
+    launch_edge_stats(g->dg, g->partials, g->stats_pending, g->stream);
+    g->stats_pending = 0;
+    return check_launch("edge update statistics");
+}
 
 apsp_status read_ctl(apsp_graph *g) {
     if (!hip_ok(hipMemcpyAsync(g->ctl_h, g->dg.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream), "read ctl"))
@@ -357,9 +367,15 @@ apsp_status apsp_host::update_edge_with(apsp_graph *g, const char *who, int32_t 
     const int32_t rblocks = SR(g, launch_mask_recompute)(d, fa, fallback, s);
     g->prof.end();
     if (fallback && (st = run_cold(g))) return st;
-    g->prof.begin(KID_NIN_BUILD);
-    launch_edge_finish(d, sv, g->kind == APSP_UNDIRECTED ? su : -1, sc.partials, rblocks, s);
-    g->prof.end();
+    // the recompute's statistics stay as per-work-group partials in the
+    // graph's own memory until they are read; memory shared with other calls
+    // is summed at once
+    if (sc.lazy_stats) {
+        g->stats_pending = rblocks;
+    } else {
+        launch_edge_stats(d, sc.partials, rblocks, s);
+        g->stats_pending = 0;
+    }
     if ((st = check_launch(who))) return st;
     g->last_n_before = n_before;
     g->last_fallback = fallback;
@@ -482,8 +498,10 @@ apsp_status apsp_graph_clone(apsp_graph *g, void *dev_buf, size_t dev_buf_bytes,
     if (dev_buf_bytes < L.total) return fail(APSP_E_CAPACITY, "apsp_graph_clone: dev_buf smaller than apsp_required_bytes");
     if ((char *)dev_buf < g->base + L.total && g->base < (char *)dev_buf + L.total)
         return fail(APSP_E_INVALID, "apsp_graph_clone: dev_buf overlaps the source graph");
+    apsp_status st = flush_stats(g);  // the copy carries the summed statistics
+    if (st) return st;
     apsp_graph *c = nullptr;
-    apsp_status st = make_handle(g->cap, g->kind, dev_buf, (hipStream_t)hip_stream, &c);
+    st = make_handle(g->cap, g->kind, dev_buf, (hipStream_t)hip_stream, &c);
     if (st) return st;
     hipEvent_t ev = nullptr;
     bool ok = hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event") &&
@@ -535,6 +553,7 @@ apsp_status apsp_grow(apsp_graph *g, int32_t capacity, void *dev_buf, size_t dev
     const size_t src_total = make_layout(g->cap, g->kind).total;
     if ((char *)dev_buf < g->base + src_total && g->base < (char *)dev_buf + L.total)
         return fail(APSP_E_INVALID, "apsp_grow: dev_buf overlaps the source graph");
+    if (apsp_status fs = flush_stats(g)) return fs;  // the copy carries the summed statistics
     apsp_graph *c = nullptr;
     apsp_status st = make_handle(capacity, g->kind, dev_buf, (hipStream_t)hip_stream, &c);
     if (st) return st;
@@ -626,6 +645,8 @@ apsp_status apsp_graph_relocate(apsp_graph *g, void *dev_buf, size_t dev_buf_byt
 
 apsp_status apsp_graph_detach(apsp_graph *g) {
     if (!g) return fail(APSP_E_INVALID, "apsp_graph_detach: NULL graph");
+    if (!g->detached)
+        if (apsp_status st = flush_stats(g)) return st;
     if (!hip_ok(hipStreamSynchronize(g->stream), "stream sync")) return APSP_E_DEVICE;
     g->detached = 1;
     return APSP_OK;
@@ -706,6 +727,7 @@ apsp_status apsp_add_node(apsp_graph *g, const int32_t *w_out_dev, const int32_t
     g->slot_of_id[nid] = p;
     g->n_live += 1;
     g->last_kind = UK_ADD;
+    g->stats_pending = 0;
     g->last_n_before = n_before;
     g->last_fallback = 0;
     *new_id = nid;
@@ -722,7 +744,7 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     DevGraph &d = g->dg;
     const int32_t n_before = g->n_live;
     g->prof.begin(KID_GATHER);
-    launch_remove_begin(d, k, colu(g), rowu(g), s);
+    launch_remove_begin(d, k, colu(g), rowu(g), g->marks, s);
     g->prof.end();
     int32_t fallback = 0;
     apsp_status st;
@@ -762,6 +784,7 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id) {
     g->free_slots.insert(k);
     g->n_live -= 1;
     g->last_kind = UK_REMOVE;
+    g->stats_pending = 0;
     g->last_n_before = n_before;
     g->last_fallback = fallback;
     g->last_route = forest ? 1 : 0;
@@ -784,6 +807,7 @@ apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w) {
     sc.row_bits = g->row_bits;
     sc.marks = g->marks;
     sc.partials = g->partials;
+    sc.lazy_stats = true;
     sc.epoch = ++g->epoch;
     return update_edge_with(g, "apsp_update_edge", u, v, w, sc);
 }
@@ -1009,7 +1033,8 @@ apsp_status apsp_edge_scope(apsp_graph *g, int32_t u, int32_t v, int32_t *r_coun
 apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
     if (!g || !out) return fail(APSP_E_INVALID, "apsp_last_stats: NULL argument");
     if (g->detached) return detached_error("apsp_last_stats");
-    apsp_status st = read_ctl(g);
+    apsp_status st = flush_stats(g);
+    if (!st) st = read_ctl(g);
     if (st) return st;
     const Ctl &c = *g->ctl_h;
     std::memset(out, 0, sizeof(*out));
@@ -1051,18 +1076,23 @@ apsp_status apsp_sync(apsp_graph *g) {
     return APSP_OK;
 }
 
-apsp_status apsp_profile(apsp_graph *g, int64_t kernel_mask) {
+apsp_status apsp_profile_every(apsp_graph *g, int64_t kernel_mask, int32_t every) {
     if (!g) return fail(APSP_E_INVALID, "apsp_profile: NULL graph");
+    if (every < 1) return fail(APSP_E_INVALID, "apsp_profile_every: every must be at least 1");
     if (!hip_ok(hipStreamSynchronize(g->stream), "stream sync")) return APSP_E_DEVICE;
     g->prof_impl.collect();
     for (int k = 0; k < KID_COUNT; ++k) {
         g->prof_impl.count[k] = 0;
         g->prof_impl.ms[k] = 0.0;
+        g->prof_impl.seen[k] = 0;
     }
     g->prof_impl.mask = kernel_mask;
+    g->prof_impl.every = every;
     g->prof.on = kernel_mask != 0;
     return APSP_OK;
 }
+
+apsp_status apsp_profile(apsp_graph *g, int64_t kernel_mask) { return apsp_profile_every(g, kernel_mask, 1); }
 
 apsp_status apsp_profile_read(apsp_graph *g, int32_t kernel, int64_t *launches, double *total_ms) {
     if (!g || !launches || !total_ms) return fail(APSP_E_INVALID, "apsp_profile_read: NULL argument");

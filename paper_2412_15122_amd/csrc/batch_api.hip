@@ -472,6 +472,7 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
         apsp_graph *g = graphs[i];
         if (last_kind[i] != 0) {
             g->last_kind = last_kind[i];
+            g->stats_pending = 0;  // the batch sums its own statistics
             g->last_n_before = last_n[i];
             g->last_fallback = 0;
         }

@@ -85,6 +85,8 @@ struct ProfImpl {
     hipEvent_t cur_a = nullptr;
     int64_t count[KID_COUNT] = {};
     double ms[KID_COUNT] = {};
+    int64_t seen[KID_COUNT] = {};  // launches of each kernel since apsp_profile_every
+    int32_t every = 1;
 
     hipEvent_t take() {
         if (used == pool.size()) {
@@ -142,6 +144,10 @@ struct apsp_graph {
     double delta = 0.5;
     int32_t last_kind = apsp_host::UK_NONE, last_n_before = 0, last_fallback = 0;
     int32_t last_route = 0;  // 1: the last removal took the spanning-forest route
+    // nonzero: the last update was an edge update whose recompute statistics
+    // are still per-work-group partials (this many work-groups, as
+    // launch_mask_recompute returned); summed into ctl before ctl is read
+    int32_t stats_pending = 0;
     apsp::Ctl *ctl_h = nullptr;   // pinned
     int32_t *qbuf_h = nullptr;  // pinned
     ProfImpl prof_impl;
@@ -205,6 +211,8 @@ struct EdgeScratch {
     uint8_t *marks;
     int32_t *partials;
     int32_t epoch;
+    // partials in the graph's own memory: summed when the statistics are read
+    bool lazy_stats = false;
 };
 
 // Argument checks of an edge update (nothing enqueued); slots of u and v.

@@ -61,18 +61,12 @@ template <int NT>
 __device__ __forceinline__ void mask_finish_block(const DevGraph &g, const int32_t *partials, int32_t blocks,
                                                   uint32_t *red);
 
-// The end of an edge update: block 0 first sums a tight increase's recompute
-// statistics (partials of `blocks` work-groups; nothing for other edge
-// updates), then block 0 rebuilds y0's list, block 1 y1's, each only if it
-// has shrunk.
-__global__ __launch_bounds__(256) void k_edge_finish(DevGraph g, int32_t y0, int32_t y1, const int32_t *partials,
-                                                     int32_t blocks) {
-    __shared__ SelectShared sh;
+// The statistics of an edge update's recompute: a tight increase's partials
+// of `blocks` work-groups summed into the control block (nothing for other
+// edge updates).  One work-group, launched only when the statistics are read.
+__global__ __launch_bounds__(256) void k_edge_stats(DevGraph g, const int32_t *partials, int32_t blocks) {
     __shared__ uint32_t red[8];
-    extern __shared__ uint32_t stage[];
-    if (blockIdx.x == 0 && blocks != 0 && g.ctl->edge_mode == EDGE_INCREASE)
-        mask_finish_block<256>(g, partials, blocks, red);
-    nin_build_one(g, blockIdx.x == 0 ? y0 : y1, 1, sh, stage);
+    if (blocks != 0 && g.ctl->edge_mode == EDGE_INCREASE) mask_finish_block<256>(g, partials, blocks, red);
 }
 
 size_t nin_build_lds_bytes(int32_t P) { return (size_t)P * sizeof(uint32_t); }
@@ -82,9 +76,8 @@ void launch_nin_build(const DevGraph &g, int32_t first, int32_t count, int32_t o
     k_nin_build<<<count, 256, nin_build_lds_bytes(g.P), s>>>(g, first, only_short);
 }
 
-void launch_edge_finish(const DevGraph &g, int32_t y0, int32_t y1, const int32_t *partials, int32_t blocks,
-                        hipStream_t s) {
-    k_edge_finish<<<y1 >= 0 ? 2 : 1, 256, nin_build_lds_bytes(g.P), s>>>(g, y0, y1, partials, blocks);
+void launch_edge_stats(const DevGraph &g, const int32_t *partials, int32_t blocks, hipStream_t s) {
+    k_edge_stats<<<1, 256, 0, s>>>(g, partials, blocks);
 }
 
 // A single list on the critical path of an update: one wide block, so that
@@ -372,8 +365,101 @@ __global__ __launch_bounds__(256) void k_add_relax(DevGraph g, const int32_t *__
     }
 }
 
+// ---- undirected graphs: sweeps over the upper triangle ----
+// D of an undirected graph is symmetric, and so are an addition's
+// relaxation (in = out) and a removal's mask: such a sweep reads only the
+// tiles of 8 rows x 1024 columns that reach the diagonal or lie above it, and
+// whatever it changes or flags at (i, j), j > i, it also changes or flags at
+// (j, i).  Tiles in order of row group rg, then column tile bx from rg / 128
+// (the tile holding column 8 rg) on.
+constexpr int32_t UPPER_GROUPS_PER_TILE = 1024 / 8;
+
+__host__ __device__ inline int64_t upper_tile_count(int32_t n) {
+    const int32_t nbx = (n + 1023) >> 10, groups = (n + 7) >> 3;
+    int64_t t = 0;
+    for (int32_t q = 0; q < nbx; ++q) {
+        const int32_t g0 = q * UPPER_GROUPS_PER_TILE, g1 = min(groups, g0 + UPPER_GROUPS_PER_TILE);
+        if (g1 > g0) t += (int64_t)(g1 - g0) * (nbx - q);
+    }
+    return t;
+}
+
+__device__ __forceinline__ void upper_tile_of(int32_t n, int64_t b, int32_t &rg, int32_t &bx) {
+    const int32_t nbx = (n + 1023) >> 10, groups = (n + 7) >> 3;
+    rg = bx = 0;
+    for (int32_t q = 0; q < nbx; ++q) {
+        const int32_t g0 = q * UPPER_GROUPS_PER_TILE, g1 = min(groups, g0 + UPPER_GROUPS_PER_TILE);
+        const int64_t cnt = g1 > g0 ? (int64_t)(g1 - g0) * (nbx - q) : 0;
+        if (b < cnt) {
+            rg = g0 + (int32_t)(b / (nbx - q));
+            bx = q + (int32_t)(b % (nbx - q));
+            return;
+        }
+        b -= cnt;
+    }
+}
+
+// An undirected addition's relaxation over the upper triangle: (i, j), j > i,
+// and its mirror (j, i) take min(D[i][j], out[i] (+) out[j]).  A lane's 4
+// columns wholly above the diagonal are stored as one 16-byte store when they
+// changed; a group that meets the diagonal stores its changed entries one by
+// one, since its entries at or below the diagonal take mirrored values from
+// other lanes.  Row and column p are rewritten by the next kernel.
+__global__ __launch_bounds__(256) void k_add_relax_sym(DevGraph g, const int32_t *__restrict__ out) {
+    const int n = g.n_slots;
+    int32_t rg, bx;
+    upper_tile_of(n, blockIdx.x, rg, bx);
+    const int32_t c0 = bx * 1024 + threadIdx.x * 4;
+    const int32_t r0 = rg * RELAX_ROWS;
+    if (c0 >= n || c0 + 3 <= r0) return;  // no column of this lane lies above a row of the group
+    const int64_t ld = g.ld;
+    uint4 o = *reinterpret_cast<const uint4 *>(out + c0);
+    if (c0 + 1 >= n) o.y = INF;
+    if (c0 + 2 >= n) o.z = INF;
+    if (c0 + 3 >= n) o.w = INF;
+    uint32_t a[RELAX_ROWS];
+    uint4 d[RELAX_ROWS];
+#pragma unroll
+    for (int r = 0; r < RELAX_ROWS; ++r) {
+        const int32_t i = r0 + r;
+        a[r] = i < n && c0 + 3 > i ? (uint32_t)out[i] : INF;
+        d[r] = make_uint4(0, 0, 0, 0);
+        if (a[r] < INF) d[r] = load_stream4(g.D + (int64_t)i * ld + c0);
+    }
+#pragma unroll
+    for (int r = 0; r < RELAX_ROWS; ++r) {
+        if (a[r] >= INF) continue;
+        const int32_t i = r0 + r;
+        const uint32_t t[4] = {cat(a[r], o.x), cat(a[r], o.y), cat(a[r], o.z), cat(a[r], o.w)};
+        uint32_t x[4] = {d[r].x, d[r].y, d[r].z, d[r].w};
+        uint32_t ch = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (c0 + e > i && t[e] < x[e]) {
+                x[e] = t[e];
+                ch |= 1u << e;
+            }
+        }
+        if (!ch) continue;
+        if (c0 > i) {
+            *reinterpret_cast<uint4 *>(g.D + (int64_t)i * ld + c0) = make_uint4(x[0], x[1], x[2], x[3]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if ((ch >> e) & 1u) g.D[(int64_t)i * ld + c0 + e] = (int32_t)x[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if ((ch >> e) & 1u) g.D[(int64_t)(c0 + e) * ld + i] = (int32_t)x[e];
+    }
+}
+
 void launch_add_relax(const DevGraph &g, const int32_t *in, const int32_t *out, hipStream_t s) {
     if (g.n_slots <= 0) return;
+    if (g.undirected) {  // in == out
+        k_add_relax_sym<<<(unsigned)upper_tile_count(g.n_slots), 256, 0, s>>>(g, out);
+        return;
+    }
     dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + RELAX_ROWS - 1) / RELAX_ROWS);
     k_add_relax<<<grid, 256, 0, s>>>(g, in, out);
 }
@@ -424,19 +510,26 @@ void launch_add_finish(const DevGraph &g, int32_t p, int32_t new_id, int32_t ran
 // ---------------------------------------------------------------------------
 
 // The start of a removal: the per-update counters zeroed (thread 0 of block
-// 0) and column / row k of D gathered: colk[i] = D[i][k], rowk[j] = D[k][j].
-__global__ void k_remove_begin(DevGraph g, int32_t k, int32_t *colk, int32_t *rowk) {
+// 0), column / row k of D gathered: colk[i] = D[i][k], rowk[j] = D[k][j],
+// and the first mark_words words of the row marks zeroed (an undirected
+// mask ORs its marks in).
+__global__ void k_remove_begin(DevGraph g, int32_t k, int32_t *colk, int32_t *rowk, uint32_t *marks,
+                               int32_t mark_words) {
     if (blockIdx.x == 0 && threadIdx.x == 0) reset_stats(g.ctl);
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int32_t w = i; w < mark_words; w += gridDim.x * blockDim.x) marks[w] = 0u;
     if (i >= g.n_slots) return;
     const int32_t rk = g.D[(int64_t)k * g.ld + i];
     rowk[i] = rk;
     colk[i] = g.undirected ? rk : g.D[(int64_t)i * g.ld + k];  // D symmetric when undirected
 }
 
-void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *rowk, hipStream_t s) {
+void launch_remove_begin(const DevGraph &g, int32_t k, int32_t *colk, int32_t *rowk, uint8_t *marks, hipStream_t s) {
     if (g.n_slots <= 0) return;
-    k_remove_begin<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, k, colk, rowk);
+    // marks: 256-byte aligned, (P / 8) rows of mark_pitch bytes, padded to 256
+    const int32_t words = g.undirected ? (int32_t)(((int64_t)(g.n_slots + 7) / 8 * mark_pitch(g.P) + 3) / 4) : 0;
+    k_remove_begin<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, k, colk, rowk, reinterpret_cast<uint32_t *>(marks),
+                                                           words);
 }
 
 // The end of a removal, one launch (its parts are independent):
@@ -491,11 +584,24 @@ void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const in
 // ---------------------------------------------------------------------------
 
 // The decision (wave 0 of block 0: mode, old weight, the new weight in A,
-// the index lists) and the gathers of columns u, v and rows u, v of D, which
-// the decision does not touch, in one launch.
+// the index lists of v and u patched), after which block 0 rebuilds either
+// list from the new weights if the patch left it short; and the gathers of
+// columns u, v and rows u, v of D, which the decision does not touch, in one
+// launch.  Every later step of the update sees the patched (or rebuilt)
+// lists; any list that keeps the index invariant serves the recompute.
 __global__ __launch_bounds__(256) void k_edge_begin(DevGraph g, int32_t su, int32_t sv, int32_t w, int32_t *colu,
                                                     int32_t *colv, int32_t *rowu, int32_t *rowv) {
-    if (blockIdx.x == 0 && threadIdx.x < 64) edge_begin_wave(g, su, sv, w);
+    __shared__ SelectShared sh;
+    extern __shared__ uint32_t stage[];
+    if (blockIdx.x == 0) {  // block-uniform
+        if (threadIdx.x < 64) edge_begin_wave(g, su, sv, w);
+        __syncthreads();
+        nin_build_one(g, sv, 1, sh, stage);
+        if (g.undirected) {
+            __syncthreads();
+            nin_build_one(g, su, 1, sh, stage);
+        }
+    }
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n_slots) return;
     const int64_t ld = g.ld;
@@ -509,7 +615,8 @@ __global__ __launch_bounds__(256) void k_edge_begin(DevGraph g, int32_t su, int3
 
 void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int32_t *colu, int32_t *colv,
                        int32_t *rowu, int32_t *rowv, hipStream_t s) {
-    k_edge_begin<<<(g.n_slots + 255) / 256, 256, 0, s>>>(g, su, sv, w, colu, colv, rowu, rowv);
+    k_edge_begin<<<(g.n_slots + 255) / 256, 256, nin_build_lds_bytes(g.P), s>>>(g, su, sv, w, colu, colv, rowu,
+                                                                                 rowv);
 }
 
 // Decrease of u -> v to w (< D[u][v]).  Inserting a relay node on the edge
@@ -714,6 +821,80 @@ __device__ __forceinline__ void mask_detect_tile(const DevGraph &g, const FusedA
 
 __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
     mask_detect_tile<FUSED_REMOVE>(g, fa, 0u, blockIdx.y);
+}
+
+// OR bits into the row-mark byte of row group grp and chunk (the marks are
+// zeroed by the removal's first kernel).
+__device__ __forceinline__ void mark_or(const FusedArgs &fa, int32_t grp, int32_t chunk, uint32_t bits) {
+    const int64_t off = (int64_t)grp * fa.mark_pitch + chunk;
+    atomicOr(reinterpret_cast<uint32_t *>(fa.marks + (off & ~(int64_t)3)), bits << (8 * (off & 3)));
+}
+
+// An undirected removal's mask over one upper tile (see upper_tile_of): the
+// pairs (i, j), j > i, tested as in mask_detect_tile, each flag also set at
+// (j, i).  A row's flag word that holds its diagonal also takes mirrored bits
+// and is ORed in; its words further right take none and are stored.  Each
+// lane ORs its columns' mirrored bits (8 rows: a byte of row j's word that
+// holds columns r0 .. r0 + 7) and their marks in.
+__global__ __launch_bounds__(256) void k_mask_detect_sym(DevGraph g, FusedArgs fa) {
+    const int n = g.n_slots;
+    const int lane = lane_id();
+    int32_t rg, bx;
+    upper_tile_of(n, blockIdx.x, rg, bx);
+    const int32_t c0 = bx * 1024 + threadIdx.x * 4;
+    const int32_t r0 = rg * DETECT_ROWS;
+    const int64_t nwp = (g.P + 31) / 32;
+    uint4 v1 = make_uint4(0, 0, 0, 0);
+    if (c0 < n) v1 = *reinterpret_cast<const uint4 *>(fa.row1 + c0);
+    const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w};
+    const int kx = fa.k;
+    uint32_t row_mask = 0;         // rows of this wavefront's 8 x 256 tile holding a flag (wave-uniform)
+    uint32_t mir[4] = {0, 0, 0, 0};  // per column of the lane: bit r = flag of row r0 + r
+    uint4 d[DETECT_ROWS];
+    uint32_t a1[DETECT_ROWS];
+    bool tested[DETECT_ROWS];
+#pragma unroll
+    for (int r = 0; r < DETECT_ROWS; ++r) {
+        const int32_t i = r0 + r;
+        d[r] = make_uint4(INF, INF, INF, INF);
+        a1[r] = 0x80000000u;  // disabled: a (+) v exceeds every finite entry
+        tested[r] = false;
+        if (i < n) {
+            const RowTests rt = row_tests(g, fa, i, 0u);
+            if (rt.t1) a1[r] = rt.a1;
+            tested[r] = rt.t1;
+            if (tested[r] && c0 < n && c0 + 3 > i) d[r] = load_stream4(g.D + (int64_t)i * g.ld + c0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < DETECT_ROWS; ++r) {
+        if (!tested[r]) continue;  // block-uniform
+        const int32_t i = r0 + r;
+        const uint32_t dv[4] = {d[r].x, d[r].y, d[r].z, d[r].w};
+        uint32_t bits = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int32_t j = c0 + e;
+            const bool f = cat(a1[r], w1[e]) == dv[e] && dv[e] < INF && j > i && j != kx;
+            bits |= (uint32_t)f << e;
+            mir[e] |= (uint32_t)f << r;
+        }
+        const uint32_t word = or8(bits << ((lane & 7) * 4));
+        if ((lane & 7) == 0 && c0 < n && word != 0) {
+            uint32_t *wp = fa.flag_bits + (int64_t)i * nwp + (c0 >> 5);
+            if ((c0 >> 5) == (i >> 5)) atomicOr(wp, word);
+            else *wp = word;
+        }
+        if (__ballot(bits != 0) != 0) row_mask |= 1u << r;
+    }
+    if (lane == 0 && row_mask) mark_or(fa, rg, bx * 4 + (threadIdx.x >> 6), row_mask);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (!mir[e]) continue;
+        const int32_t j = c0 + e;
+        atomicOr(fa.flag_bits + (int64_t)j * nwp + (r0 >> 5), mir[e] << (r0 & 31));
+        mark_or(fa, j >> 3, r0 >> 8, 1u << (j & 7));
+    }
 }
 
 // |F| and Phi of a removal's mask, counted without writing it (a route that
@@ -1087,6 +1268,10 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_fused_heavy(DevGraph g, Fused
 
 void launch_mask_detect(const DevGraph &g, const FusedArgs &fa, hipStream_t s) {
     if (g.n_slots <= 0) return;
+    if (g.undirected) {
+        k_mask_detect_sym<<<(unsigned)upper_tile_count(g.n_slots), 256, 0, s>>>(g, fa);
+        return;
+    }
     dim3 grid((g.n_slots + 1023) / 1024, (g.n_slots + DETECT_ROWS - 1) / DETECT_ROWS);
     k_mask_detect<<<grid, 256, 0, s>>>(g, fa);
 }
@@ -1130,6 +1315,8 @@ hipError_t configure_kernels() {
         status = hipFuncSetAttribute((const void *)k_select_vec, hipFuncAttributeMaxDynamicSharedMemorySize, sel);
     if (status == hipSuccess)
         status = hipFuncSetAttribute((const void *)k_nin_rebuild_queue, hipFuncAttributeMaxDynamicSharedMemorySize, sel);
+    if (status == hipSuccess)
+        status = hipFuncSetAttribute((const void *)k_edge_begin, hipFuncAttributeMaxDynamicSharedMemorySize, sel);
     (void)hipGetLastError();  // do not leave the status for an unrelated launch check
     return status;
 }

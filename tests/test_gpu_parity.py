@@ -247,6 +247,51 @@ def test_refined_set_statistics(undirected):
 
 
 @pytest.mark.parametrize("undirected", [False, True])
+def test_increase_statistics_read_after_copies(undirected):
+    """A tight increase leaves its recompute statistics as per-work-group
+    partials that are summed when first read: a clone and a grown copy made
+    before that read, and the graph read after them, all report the refined
+    set the oracle's matrices give; a removal that follows reports its own
+    figures only."""
+    n = 200
+    rng = np.random.default_rng(61 + undirected)
+    adj = W.random_graph(n, 1, 12, undirected=undirected, seed=61 + undirected)
+    g = lib_graph(adj, undirected, capacity=n)
+    A, ids = adj.copy(), list(range(n))
+    D = O.fw(A)
+    tight = [(u, v) for u in range(n) for v in range(n) if u != v and A[u, v] == D[u, v] and A[u, v] < INF]
+    for _ in range(40):
+        u, v = tight[int(rng.integers(len(tight)))]
+        A2, ids2 = O.apply_update(A, ids, "edge", u=u, v=v, w=int(A[u, v]) + 7, undirected=undirected)
+        R = O.refined_set(D, O.fw(A2))
+        if R.sum() > 0:
+            break
+    assert R.sum() > 0
+    g.update_edge(u, v, int(A[u, v]) + 7)
+    c = g.clone()
+    h = g.grow(n + 16)
+    phi = int(np.count_nonzero(R.any(axis=1)))
+    for x in (c, h, g):
+        s = x.stats()
+        assert s["kind"] == 4 and s["changed"] == int(R.sum()) and s["rows_changed"] == phi, s
+    A, ids = A2, ids2
+    expect_equal(c, A, ids, "clone")
+    expect_equal(h, A, ids, "grown copy")
+    c.close()
+    h.close()
+    D = O.fw(A)
+    k = ids[int(rng.integers(len(ids)))]
+    F = O.remove_mask(D, ids.index(k))
+    g.remove_node(k)
+    A2, ids2 = O.apply_update(A, ids, "remove", u=k, undirected=undirected)
+    keep = [t for t in range(len(ids)) if t != ids.index(k)]
+    R = O.refined_set(D[np.ix_(keep, keep)], O.fw(A2))
+    s = g.stats()
+    assert s["kind"] == 2 and s["flagged"] == F.sum() and s["changed"] == int(R.sum()), s
+    expect_equal(g, A2, ids2, "removal")
+
+
+@pytest.mark.parametrize("undirected", [False, True])
 def test_edge_increase_mask_statistics(undirected):
     adj = W.random_graph(150, 1, 8, undirected=undirected, seed=21 + undirected)
     g = lib_graph(adj, undirected, capacity=150)
