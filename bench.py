@@ -530,9 +530,10 @@ def edge_sweep_roofline(base, worst, adj, kid, reps):
     graph: the stream's worst-case edge lowered to 0 (a forced wide
     decrease: rows_relaxed rows are read, 4n bytes each) and raised back to
     its weight (the tight increase's mask: with the edge at 0, u and v are
-    equally far from every node, so both pair tests hold on every row and
-    all n rows are read).  Average kernel time per launch by HIP events on
-    the graph's stream."""
+    equally far from every node, so both pair tests hold on every row; the
+    mask of an undirected graph is symmetric, so a tested row i reads its
+    columns j > i, 4 (n - 1 - i) bytes).  Average kernel time per launch by
+    HIP events on the graph's stream."""
     import torch
     u, v = int(worst[0]), int(worst[1])
     wt = int(adj[u, v])
@@ -540,13 +541,15 @@ def edge_sweep_roofline(base, worst, adj, kid, reps):
     n = len(h.ids())
     out = {}
     for kind, w in (("decrease", 0), ("increase", wt)):
-        out[kind] = {"ms": [], "rows": []}
+        out[kind] = {"ms": [], "rows": [], "bytes": []}
     for _ in range(reps):
         for kind, w in (("decrease", 0), ("increase", wt)):
             if kind == "increase":
                 D = h.matrix_device("D")
-                rows_read = int(((D[:n, u] == D[:n, v])).sum().item())
-                del D
+                tested = torch.nonzero(D[:n, u] == D[:n, v]).flatten().to(torch.int64)
+                rows_read = int(tested.numel())
+                upper_bytes = int((4 * (n - 1 - tested)).sum().item())
+                del D, tested
             h.profile(1 << kid["edge_sweep"])
             h.update_edge(u, v, w)
             torch.cuda.synchronize()
@@ -555,14 +558,16 @@ def edge_sweep_roofline(base, worst, adj, kid, reps):
             st = h.stats()
             out[kind]["ms"].append(ms / max(c, 1))
             out[kind]["rows"].append(st["rows_relaxed"] if kind == "decrease" else rows_read)
+            out[kind]["bytes"].append(4 * n * st["rows_relaxed"] if kind == "decrease" else upper_bytes)
     h.close()
     res = {"edge": [u, v, wt], "n": n}
     for kind, d in out.items():
         ms = float(np.median(d["ms"]))
         rows = float(np.median(d["rows"]))
-        gbs = 4.0 * n * rows / (ms * 1e-3) / 1e9
-        res[kind] = {"avg_launch_ms": round(ms, 4), "rows_read": rows, "achieved": round(gbs, 1),
-                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        nbytes = float(np.median(d["bytes"]))
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[kind] = {"avg_launch_ms": round(ms, 4), "rows_read": rows, "bytes": int(nbytes),
+                     "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     log(f"[bench] edge sweep: {res}")
     return res
 

@@ -336,7 +336,7 @@ apsp_status apsp_host::update_edge_with(apsp_graph *g, const char *who, int32_t 
     DevGraph &d = g->dg;
     const int32_t n_before = g->n_live;
     g->prof.begin(KID_EDGE_BEGIN);
-    launch_edge_begin(d, su, sv, w, sc.colu, sc.colv, sc.rowu, sc.rowv, s);
+    launch_edge_begin(d, su, sv, w, sc.colu, sc.colv, sc.rowu, sc.rowv, sc.marks, s);
     g->prof.end();
     FusedArgs fa{};
     fa.mode = FUSED_INCREASE;

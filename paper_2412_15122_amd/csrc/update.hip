@@ -590,9 +590,12 @@ void launch_remove_finish(const DevGraph &g, int32_t k, int32_t *queue, const in
 // launch.  Every later step of the update sees the patched (or rebuilt)
 // lists; any list that keeps the index invariant serves the recompute.
 __global__ __launch_bounds__(256) void k_edge_begin(DevGraph g, int32_t su, int32_t sv, int32_t w, int32_t *colu,
-                                                    int32_t *colv, int32_t *rowu, int32_t *rowv) {
+                                                    int32_t *colv, int32_t *rowu, int32_t *rowv, uint32_t *marks,
+                                                    int32_t mark_words) {
     __shared__ SelectShared sh;
     extern __shared__ uint32_t stage[];
+    // an undirected increase's mask ORs its row marks in
+    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < mark_words; q += gridDim.x * blockDim.x) marks[q] = 0u;
     if (blockIdx.x == 0) {  // block-uniform
         if (threadIdx.x < 64) edge_begin_wave(g, su, sv, w);
         __syncthreads();
@@ -614,9 +617,10 @@ __global__ __launch_bounds__(256) void k_edge_begin(DevGraph g, int32_t su, int3
 }
 
 void launch_edge_begin(const DevGraph &g, int32_t su, int32_t sv, int32_t w, int32_t *colu, int32_t *colv,
-                       int32_t *rowu, int32_t *rowv, hipStream_t s) {
-    k_edge_begin<<<(g.n_slots + 255) / 256, 256, nin_build_lds_bytes(g.P), s>>>(g, su, sv, w, colu, colv, rowu,
-                                                                                 rowv);
+                       int32_t *rowu, int32_t *rowv, uint8_t *marks, hipStream_t s) {
+    const int32_t words = g.undirected ? (int32_t)(((int64_t)(g.n_slots + 7) / 8 * mark_pitch(g.P) + 3) / 4) : 0;
+    k_edge_begin<<<(g.n_slots + 255) / 256, 256, nin_build_lds_bytes(g.P), s>>>(
+        g, su, sv, w, colu, colv, rowu, rowv, reinterpret_cast<uint32_t *>(marks), words);
 }
 
 // Decrease of u -> v to w (< D[u][v]).  Inserting a relay node on the edge
@@ -824,7 +828,7 @@ __global__ __launch_bounds__(256) void k_mask_detect(DevGraph g, FusedArgs fa) {
 }
 
 // OR bits into the row-mark byte of row group grp and chunk (the marks are
-// zeroed by the removal's first kernel).
+// zeroed by the update's first kernel).
 __device__ __forceinline__ void mark_or(const FusedArgs &fa, int32_t grp, int32_t chunk, uint32_t bits) {
     const int64_t off = (int64_t)grp * fa.mark_pitch + chunk;
     atomicOr(reinterpret_cast<uint32_t *>(fa.marks + (off & ~(int64_t)3)), bits << (8 * (off & 3)));
@@ -888,13 +892,15 @@ __global__ __launch_bounds__(256) void k_mask_detect_sym(DevGraph g, FusedArgs f
         if (__ballot(bits != 0) != 0) row_mask |= 1u << r;
     }
     if (lane == 0 && row_mask) mark_or(fa, rg, bx * 4 + (threadIdx.x >> 6), row_mask);
+    uint32_t mbits = 0;  // the lane's 4 columns share a row group
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         if (!mir[e]) continue;
         const int32_t j = c0 + e;
         atomicOr(fa.flag_bits + (int64_t)j * nwp + (r0 >> 5), mir[e] << (r0 & 31));
-        mark_or(fa, j >> 3, r0 >> 8, 1u << (j & 7));
+        mbits |= 1u << (j & 7);
     }
+    if (mbits) mark_or(fa, c0 >> 3, r0 >> 8, mbits);
 }
 
 // |F| and Phi of a removal's mask, counted without writing it (a route that
@@ -944,6 +950,76 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_mask_count(DevGraph g, FusedA
     }
 }
 
+// A tight increase's mask on an undirected graph (the rows r0 .. r0 + 7 of
+// one work-group): both pair tests of mask_detect_rows on the pairs (i, j),
+// j > i, each flag also set at (j, i) -- the mask is symmetric, its second
+// test being the first read from the other end.  The walk starts at the tile
+// that holds column r0; flag words and marks as in k_mask_detect_sym (the
+// marks were zeroed by k_edge_begin).
+__device__ __forceinline__ void inc_mask_rows_sym(const DevGraph &g, const FusedArgs &fa, uint32_t w_old, int32_t r0) {
+    const int n = g.n_slots;
+    const int lane = lane_id();
+    const int64_t nwp = (g.P + 31) / 32;
+    const int32_t rg = r0 / SWEEP_ROWS;
+    uint32_t a1[SWEEP_ROWS], a2[SWEEP_ROWS];
+    uint32_t act = 0;
+#pragma unroll
+    for (int r = 0; r < SWEEP_ROWS; ++r) {
+        const int32_t i = r0 + r;
+        a1[r] = a2[r] = 0x80000000u;  // disabled: a (+) v exceeds every finite entry
+        if (i < n) {
+            const RowTests rt = row_tests(g, fa, i, w_old);
+            if (rt.t1) a1[r] = rt.a1;
+            if (rt.t2) a2[r] = rt.a2;
+            if (rt.t1 || rt.t2) act |= 1u << r;
+        }
+    }
+    if (act == 0) return;  // block-uniform
+    constexpr int32_t span = 4 * SWEEP_THREADS;
+    const int32_t tiles = (n + span - 1) / span;
+    int32_t c0 = (r0 / span) * span + threadIdx.x * 4;
+    SweepTile<SWEEP_ROWS> T;
+    for (int32_t t = r0 / span; t < tiles; ++t, c0 += span) {
+        sweep_load<SWEEP_ROWS>(T, g, r0, act, c0, n, fa.row1, fa.row2);
+        const uint32_t w1[4] = {T.v1.x, T.v1.y, T.v1.z, T.v1.w};
+        const uint32_t w2[4] = {T.v2.x, T.v2.y, T.v2.z, T.v2.w};
+        uint32_t row_mask = 0;           // rows of this wavefront's 8 x 256 tile holding a flag (wave-uniform)
+        uint32_t mir[4] = {0, 0, 0, 0};  // per column of the lane: bit r = flag of row r0 + r
+#pragma unroll
+        for (int r = 0; r < SWEEP_ROWS; ++r) {
+            if (!((act >> r) & 1u)) continue;  // block-uniform
+            const int32_t i = r0 + r;
+            const uint32_t dv[4] = {T.d[r].x, T.d[r].y, T.d[r].z, T.d[r].w};
+            uint32_t bits = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int32_t j = c0 + e;
+                const bool f = (cat(a1[r], w1[e]) == dv[e] || cat(a2[r], w2[e]) == dv[e]) && dv[e] < INF && j > i &&
+                               j < n;
+                bits |= (uint32_t)f << e;
+                mir[e] |= (uint32_t)f << r;
+            }
+            const uint32_t word = or8(bits << ((lane & 7) * 4));
+            if ((lane & 7) == 0 && c0 < n && word != 0) {
+                uint32_t *wp = fa.flag_bits + (int64_t)i * nwp + (c0 >> 5);
+                if ((c0 >> 5) == (i >> 5)) atomicOr(wp, word);
+                else *wp = word;
+            }
+            if (__ballot(bits != 0) != 0) row_mask |= 1u << r;
+        }
+        if (lane == 0 && row_mask) mark_or(fa, rg, c0 >> 8, row_mask);
+        uint32_t mbits = 0;  // the lane's 4 columns share a row group
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (!mir[e]) continue;
+            const int32_t j = c0 + e;
+            atomicOr(fa.flag_bits + (int64_t)j * nwp + (r0 >> 5), mir[e] << (r0 & 31));
+            mbits |= 1u << (j & 7);
+        }
+        if (mbits) mark_or(fa, c0 >> 3, r0 >> 8, mbits);
+    }
+}
+
 // The edge update's sweep, chosen on the device: the relaxation of a decrease
 // (colu, colv, rowu, rowv = fa.col1, col2, row2, row1) or the mask of a tight
 // increase; nothing for a no-op.  One work-group per SWEEP_ROWS rows (the
@@ -953,6 +1029,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_edge_sweep(DevGraph g, FusedA
     if (mode == EDGE_NOOP) return;
     const int32_t r0 = blockIdx.x * SWEEP_ROWS;
     if (mode == EDGE_DECREASE) dec_relax_rows(g, fa.col1, fa.col2, fa.row2, fa.row1, w, r0);
+    else if (g.undirected) inc_mask_rows_sym(g, fa, (uint32_t)g.ctl->w_old, r0);
     else mask_detect_rows<FUSED_INCREASE>(g, fa, (uint32_t)g.ctl->w_old, r0);
 }
 
