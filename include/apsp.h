@@ -141,10 +141,10 @@ typedef struct {
                           * removed node (or the raised edge).  0 after a cold
                           * fallback. */
     double cost_refined; /* Phi' / (N - 1) */
-    int32_t route;       /* removals: 0 mask + recompute; 1 the minimum-spanning-forest
-                          * route of an undirected minimax graph (only the pairs
-                          * whose distance changes are written; see
-                          * apsp_remove_node) */
+    int32_t route;       /* removals and tight increases: 0 mask + recompute; 1 the
+                          * minimum-spanning-forest route of an undirected minimax
+                          * graph (only the pairs whose distance changes are
+                          * written; see apsp_remove_node, apsp_update_edge) */
     int32_t pad;
 } apsp_update_stats;
 
@@ -249,13 +249,23 @@ apsp_status apsp_remove_node(apsp_graph *g, int32_t id);
  * increase of an edge with D[u][v] == w_old recomputes the pairs whose
  * shortest distance can use it (Corollary 3 applied to that relay
  * node); any other change leaves D as it is.  The choice is made on the
- * device: the call never waits. */
+ * device: the call never waits, except on an undirected minimax (or widest)
+ * graph, where it reads the device's choice back: a tight increase there
+ * first tries the spanning-forest route of apsp_remove_node with the raised
+ * edge in place of the removed node (the forest of the graph before the
+ * change; if the edge is not in it no distance changes, otherwise only the
+ * pairs across the two pieces it separates can, and they take their values
+ * from the lightest edge now joining the pieces), and waits once more for
+ * its certificate; when the certificate or a size limit rejects it, the
+ * mask route runs, with the same matrix.  The route taken is in
+ * apsp_update_stats.route. */
 apsp_status apsp_update_edge(apsp_graph *g, int32_t u, int32_t v, int32_t w);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * update as apsp_update_edge, with the same kernels and bit for bit the
- * same results, but its working memory (the gathered columns and rows, the
+ * same results (on an undirected minimax graph always by the mask route),
+ * but its working memory (the gathered columns and rows, the
  * flag bitmap, row marks, heavy-row scratch and recompute partials, which
  * apsp_update_edge keeps in the graph's buffer) is a static array inside
  * the library, apsp_noalloc_scratch_bytes() bytes on every device the

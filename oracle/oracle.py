@@ -371,15 +371,16 @@ def remove_cost(F: np.ndarray, n_before: int) -> Tuple[int, float]:
     return phi, cost
 
 
-def edge_mask(D: np.ndarray, u: int, v: int, w_old: int, undirected: bool) -> np.ndarray:
+def edge_mask(D: np.ndarray, u: int, v: int, w_old: int, undirected: bool, minimax: bool = False) -> np.ndarray:
     """Pairs whose shortest distance can use edge u->v of weight w_old:
     i != j, D[i][j] < INF and D[i][u] (+) w_old (+) D[v][j] == D[i][j]; for an
-    undirected graph also the v->u direction."""
+    undirected graph also the v->u direction.  minimax: (+) is max."""
     D = np.asarray(D, dtype=np.int64)
     n = D.shape[0]
-    F = oplus(oplus(D[:, u][:, None], w_old), D[v, :][None, :]) == D
+    cat = np.maximum if minimax else oplus
+    F = cat(cat(D[:, u][:, None], w_old), D[v, :][None, :]) == D
     if undirected:
-        F |= oplus(oplus(D[:, v][:, None], w_old), D[u, :][None, :]) == D
+        F |= cat(cat(D[:, v][:, None], w_old), D[u, :][None, :]) == D
     F &= D < INF
     F[np.arange(n), np.arange(n)] = False
     return F

@@ -119,7 +119,7 @@ apsp_status remove_by_forest(apsp_graph *g, int32_t k, int32_t n_before, bool *u
     if (w.ints > (int64_t)FUSED_GRID * 2 * g->P) return APSP_OK;  // the heavy-row scratch holds it (P >= 128)
     int32_t rounds = 2;
     while ((1 << (rounds - 2)) < std::max(n_before, 2)) ++rounds;
-    launch_msf_forest(d, w, k, rounds, s);
+    launch_msf_forest(d, w, k, -1, -1, 0, rounds, s);
     apsp_status st = check_launch("apsp_remove_node: spanning forest");
     if (st) return st;
     if (!hip_ok(hipMemcpyAsync(g->qbuf_h, w.info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "forest read") ||
@@ -148,6 +148,56 @@ apsp_status remove_by_forest(apsp_graph *g, int32_t k, int32_t n_before, bool *u
     launch_msf_update(d, w, info[MI_SMALL], s);
     g->prof.end();
     return check_launch("apsp_remove_node: spanning-forest update");
+}
+
+// A tight increase of edge (su, sv) from w_old on an undirected minimax graph
+// through its minimum spanning forest (msf.hip), after k_edge_begin has
+// written the new weight: the forest of the graph before the change, its
+// certificate and the two pieces of T - e, one read-back, then -- when the
+// certificate holds -- the mask's counts and the new entries of the pairs
+// across the pieces (none when e is not in T).  *used and *fallback as in
+// remove_by_forest.
+apsp_status increase_by_forest(apsp_graph *g, int32_t su, int32_t sv, int32_t w_old, int32_t n_before, bool *used,
+                               int32_t *fallback, const FusedArgs &fa) {
+    *used = false;
+    *fallback = 0;
+    if (msf_configure() != hipSuccess) {
+        (void)hipGetLastError();
+        return APSP_OK;
+    }
+    DevGraph &d = g->dg;
+    hipStream_t s = g->stream;
+    const MsfWork w = msf_work(g->fscratch, g->P);
+    if (w.ints > (int64_t)FUSED_GRID * 2 * g->P) return APSP_OK;
+    int32_t rounds = 2;
+    while ((1 << (rounds - 2)) < std::max(n_before, 2)) ++rounds;
+    launch_msf_forest(d, w, -1, su, sv, w_old, rounds, s);
+    apsp_status st = check_launch("apsp_update_edge: spanning forest");
+    if (st) return st;
+    if (!hip_ok(hipMemcpyAsync(g->qbuf_h, w.info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "forest read") ||
+        !hip_ok(hipStreamSynchronize(s), "stream sync"))
+        return APSP_E_DEVICE;
+    const int32_t *info = g->qbuf_h;
+    if (info[MI_ACTIVE] != 0 || info[MI_FAIL] != 0) return APSP_OK;
+    const int32_t pieces = info[MI_D], small = info[MI_SMALL];
+    g->prof.begin(KID_MASK);
+    mm::launch_mask_count(d, fa, s);
+    g->prof.end();
+    *used = true;
+    if (g->policy == APSP_FALLBACK_COST) {
+        if ((st = read_ctl(g))) return st;
+        const double cost = n_before > 1 ? (double)g->ctl_h->rows / (double)(n_before - 1) : 0.0;
+        if (cost > g->delta) {
+            *fallback = 1;
+            return check_launch("apsp_update_edge: mask counts");
+        }
+    }
+    if (pieces == 2) {
+        g->prof.begin(KID_FUSED);
+        launch_msf_update(d, w, small, s);
+        g->prof.end();
+    }
+    return check_launch("apsp_update_edge: spanning-forest update");
 }
 
 // A handle over the caller's buffer: pinned host mirrors and the carving of
@@ -354,11 +404,34 @@ apsp_status apsp_host::update_edge_with(apsp_graph *g, const char *who, int32_t 
     fa.col2 = sc.colv;
     fa.row1 = sc.rowv;
     fa.row2 = sc.rowu;
+    apsp_status st;
+    // undirected minimax graphs: a tight increase takes the spanning-forest
+    // route when its certificate holds (it works in the graph's own memory,
+    // so not for the no-allocation entry point); the device's decision is
+    // read back first
+    if (g->minimax && g->kind == APSP_UNDIRECTED && g->P <= MSF_MAX_PITCH && sc.lazy_stats &&
+        g->policy != APSP_FALLBACK_ALWAYS) {
+        if ((st = read_ctl(g))) return st;
+        if (g->ctl_h->edge_mode == EDGE_INCREASE) {
+            bool forest = false;
+            int32_t fb = 0;
+            if ((st = increase_by_forest(g, su, sv, g->ctl_h->w_old, n_before, &forest, &fb, fa))) return st;
+            if (forest) {
+                if (fb && (st = run_cold(g))) return st;
+                if ((st = check_launch(who))) return st;
+                g->stats_pending = 0;
+                g->last_n_before = n_before;
+                g->last_fallback = fb;
+                g->last_kind = -1;
+                g->last_route = 1;
+                return APSP_OK;
+            }
+        }
+    }
     g->prof.begin(KID_EDGE_SWEEP);
     SR(g, launch_edge_sweep)(d, fa, w, s);
     g->prof.end();
     int32_t fallback = 0;
-    apsp_status st;
     if (g->policy != APSP_FALLBACK_NEVER) {
         if ((st = read_ctl(g))) return st;
         if (g->ctl_h->edge_mode == EDGE_INCREASE && (st = decide_fallback(g, &fa, n_before, &fallback))) return st;
@@ -380,6 +453,7 @@ apsp_status apsp_host::update_edge_with(apsp_graph *g, const char *who, int32_t 
     g->last_n_before = n_before;
     g->last_fallback = fallback;
     g->last_kind = -1;  // the device picked the path; apsp_last_stats reads it back
+    g->last_route = 0;
     return APSP_OK;
 }
 
@@ -1059,7 +1133,7 @@ apsp_status apsp_last_stats(apsp_graph *g, apsp_update_stats *out) {
         out->cost_refined = g->last_n_before > 1 ? (double)c.rows_changed / (double)(g->last_n_before - 1) : 0.0;
     }
     if (kind == UK_REMOVE) out->noop = c.flagged == 0 && !g->last_fallback;
-    out->route = kind == UK_REMOVE ? g->last_route : 0;
+    out->route = (kind == UK_REMOVE || kind == UK_INCREASE) ? g->last_route : 0;
     return APSP_OK;
 }
 

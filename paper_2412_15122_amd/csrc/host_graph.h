@@ -143,7 +143,7 @@ struct apsp_graph {
     int32_t policy = APSP_FALLBACK_NEVER;
     double delta = 0.5;
     int32_t last_kind = apsp_host::UK_NONE, last_n_before = 0, last_fallback = 0;
-    int32_t last_route = 0;  // 1: the last removal took the spanning-forest route
+    int32_t last_route = 0;  // 1: the last removal or tight increase took the spanning-forest route
     // nonzero: the last update was an edge update whose recompute statistics
     // are still per-work-group partials (this many work-groups, as
     // launch_mask_recompute returned); summed into ctl before ctl is read

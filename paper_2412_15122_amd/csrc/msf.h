@@ -1,6 +1,7 @@
-// The spanning-forest route of a node removal on an undirected minimax graph
-// (msf.hip): working memory, carved from the heavy-row scratch of the graph
-// (idle during a removal until the mask path would use it), and launchers.
+// The spanning-forest route of a node removal or a tight edge increase on an
+// undirected minimax graph (msf.hip): working memory, carved from the
+// heavy-row scratch of the graph (idle until the mask route would use it),
+// and launchers.
 #pragma once
 #include "apsp_internal.h"
 
@@ -17,7 +18,7 @@ enum MsfInfo : int32_t {
     MI_HOOKS = 1,   // hooks in the current round
     MI_ACTIVE = 2,  // rounds still running
     MI_FAIL = 3,    // MSF_FAIL_* bits
-    MI_D = 4,       // pieces of T - k
+    MI_D = 4,       // pieces of T - k (T - e for a raised edge e: 2, or 0 when e is not in T)
     MI_SMALL = 5,   // nodes outside the largest piece
     MI_GIANT = 6,   // index of the largest piece
     MI_COMP = 7,    // nodes of k's component other than k
@@ -47,8 +48,11 @@ struct MsfWork {
 
 MsfWork msf_work(int32_t *scratch, int32_t P);
 hipError_t msf_configure();
-// Boruvka rounds over the light index, the certificate, the pieces of T - k.
-void launch_msf_forest(const DevGraph &g, const MsfWork &w, int32_t k, int32_t rounds, hipStream_t s);
+// Boruvka rounds over the light index, the certificate, the pieces of T - k;
+// with k < 0, of T - (eu, ev) for an edge raised from weight ew (the forest is
+// the one of the graph before the change).  eu < 0: no such edge.
+void launch_msf_forest(const DevGraph &g, const MsfWork &w, int32_t k, int32_t eu, int32_t ev, int32_t ew,
+                       int32_t rounds, hipStream_t s);
 // Replacement edges, the pieces' forest, the new entries of the small pieces'
 // rows (and their mirrors), Phi'.
 void launch_msf_update(const DevGraph &g, const MsfWork &w, int32_t small_count, hipStream_t s);

@@ -1,7 +1,7 @@
-// Node removal on an undirected minimax graph by its minimum spanning forest:
-// the refined need_update list of Algorithms 11 and 12 (Theorem 6) computed
-// directly, with work that follows the pairs whose distance can change
-// rather than the need_update mask.
+// Node removal (and tight edge increase) on an undirected minimax graph by
+// its minimum spanning forest: the refined need_update list of Algorithms 11
+// and 12 (Theorem 6) computed directly, with work that follows the pairs
+// whose distance can change rather than the need_update mask.
 //
 // With max in place of +, ties are structural (minimax distances of an
 // undirected graph form an ultrametric), and the mask of Corollary 3 covers
@@ -20,6 +20,13 @@
 //     y_ab, and W_ab is the largest of its edge weights and of the distances
 //     inside the pieces it crosses (all unchanged: same-piece pairs keep
 //     their T-path).
+// A tight increase of edge e = (u, v) is the same argument with one piece
+// boundary: T is taken as a forest of the graph before the change (e at its
+// old weight).  If e is not in T, T is still a minimum spanning forest after
+// the change and no distance moves; otherwise T - e has two pieces, pairs
+// inside a piece keep their T-path, and a pair across them takes
+// max(D[i][x], W, D[y][j]) with (x, y) the lightest edge that now joins the
+// pieces (e at its new weight among the candidates).
 // T is built by Boruvka rounds over the light in-edge index (each node's
 // lightest edges, ties broken by slot pair), and trusted only with a
 // certificate: every edge left out of the index weighs at least its
@@ -79,8 +86,11 @@ __global__ void k_msf_init(DevGraph g, MsfWork w) {
 }
 
 // Each live node's lightest index edge to another component, folded into its
-// component's best edge (one wavefront per node, one lane per entry).
-__global__ __launch_bounds__(256) void k_msf_min(DevGraph g, MsfWork w) {
+// component's best edge (one wavefront per node, one lane per entry).  For a
+// raised edge (eu, ev) the forest is the one of the graph before the change:
+// the edge also counts at its old weight ew (its index entries, if any, hold
+// the new weight, which is heavier and loses).
+__global__ __launch_bounds__(256) void k_msf_min(DevGraph g, MsfWork w, int32_t eu, int32_t ev, uint32_t ew) {
     if (!w.info[MI_ACTIVE]) return;
     const int32_t x = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (x >= g.n_slots) return;  // wave-uniform
@@ -93,6 +103,11 @@ __global__ __launch_bounds__(256) void k_msf_min(DevGraph g, MsfWork w) {
         const int2 e = g.nin[(int64_t)x * NIN_L + lane];
         const int32_t ly = e.x >= 0 && e.x < g.n_slots ? w.label[e.x] : -1;
         if (ly >= 0 && ly != lx) key = edge_key((uint32_t)e.y, x, e.x);
+    }
+    if (lane == 0 && (x == eu || x == ev)) {
+        const int32_t y = x == eu ? ev : eu;
+        const int32_t ly = w.label[y];
+        if (ly >= 0 && ly != lx && ew < INF) key = min(key, edge_key(ew, x, y));
     }
     key = wave_min64(key);
     if (lane == 0 && key != NO_EDGE) atomicMin(&w.best[lx], key);
@@ -181,6 +196,8 @@ __global__ __launch_bounds__(256) void k_msf_certify(DevGraph g, MsfWork w) {
 }
 
 // ---- pieces of T - k (one work-group, union-find in LDS) --------------------
+// For a raised edge (k < 0): the pieces of T - (eu, ev), two when the edge is
+// in T, none when it is not (then no distance changes).
 
 __device__ __forceinline__ int32_t uf_find(int32_t *par, int32_t x) {
     int32_t p = par[x];
@@ -193,7 +210,7 @@ __device__ __forceinline__ int32_t uf_find(int32_t *par, int32_t x) {
     return x;
 }
 
-__global__ __launch_bounds__(1024) void k_msf_pieces(DevGraph g, MsfWork w, int32_t k) {
+__global__ __launch_bounds__(1024) void k_msf_pieces(DevGraph g, MsfWork w, int32_t k, int32_t eu, int32_t ev) {
     extern __shared__ int32_t par[];  // n_slots words
     __shared__ int32_t s_root[MSF_DMAX], s_size[MSF_DMAX];
     __shared__ int32_t s_d, s_fail, s_small, s_comp;
@@ -206,9 +223,15 @@ __global__ __launch_bounds__(1024) void k_msf_pieces(DevGraph g, MsfWork w, int3
     __syncthreads();
     for (int32_t e = tid; e < trees; e += blockDim.x) {
         const int32_t a = w.tree_a[e], b = w.tree_b[e];
-        if (a == k || b == k) {
+        if (k >= 0 && (a == k || b == k)) {
             const int32_t slot = atomicAdd(&s_d, 1);
             if (slot < MSF_DMAX) s_root[slot] = a == k ? b : a;
+            continue;
+        }
+        if (k < 0 && ((a == eu && b == ev) || (a == ev && b == eu))) {  // one tree edge at most (distinct keys)
+            s_root[0] = eu;
+            s_root[1] = ev;
+            s_d = 2;
             continue;
         }
         for (int tries = 0;; ++tries) {
@@ -230,7 +253,15 @@ __global__ __launch_bounds__(1024) void k_msf_pieces(DevGraph g, MsfWork w, int3
     __syncthreads();
     if (tid < d) s_root[tid] = uf_find(par, s_root[tid]);
     __syncthreads();
-    const int32_t lk = w.label[k];
+    if (k < 0 && d == 0) {  // a raised edge outside T: nothing changes
+        if (tid == 0) {
+            w.info[MI_FAIL] |= s_fail;
+            w.info[MI_D] = 0;
+            w.info[MI_SMALL] = 0;
+        }
+        return;
+    }
+    const int32_t lk = w.label[k >= 0 ? k : eu];
     for (int32_t x = tid; x < n; x += blockDim.x) {
         if (x == k || w.label[x] != lk || lk < 0) continue;
         atomicAdd(&s_comp, 1);
@@ -454,18 +485,19 @@ hipError_t msf_configure() {
     return status;
 }
 
-void launch_msf_forest(const DevGraph &g, const MsfWork &w, int32_t k, int32_t rounds, hipStream_t s) {
+void launch_msf_forest(const DevGraph &g, const MsfWork &w, int32_t k, int32_t eu, int32_t ev, int32_t ew,
+                       int32_t rounds, hipStream_t s) {
     const int32_t n = g.n_slots;
     const int32_t init = std::max<int32_t>(g.P, MSF_DMAX * MSF_DMAX);
     k_msf_init<<<(init + 255) / 256, 256, 0, s>>>(g, w);
     for (int32_t r = 0; r < rounds; ++r) {
-        k_msf_min<<<(n + 3) / 4, 256, 0, s>>>(g, w);
+        k_msf_min<<<(n + 3) / 4, 256, 0, s>>>(g, w, eu, ev, (uint32_t)ew);
         k_msf_hook<<<(n + 255) / 256, 256, 0, s>>>(g, w);
         k_msf_relabel<<<(n + 255) / 256, 256, 0, s>>>(g, w);
     }
     k_msf_comp_stats<<<(g.P + 255) / 256, 256, 0, s>>>(g, w);
     k_msf_certify<<<(n + 3) / 4, 256, 0, s>>>(g, w);
-    k_msf_pieces<<<1, 1024, (size_t)n * sizeof(int32_t), s>>>(g, w, k);
+    k_msf_pieces<<<1, 1024, (size_t)n * sizeof(int32_t), s>>>(g, w, k, eu, ev);
 }
 
 void launch_msf_update(const DevGraph &g, const MsfWork &w, int32_t small_count, hipStream_t s) {

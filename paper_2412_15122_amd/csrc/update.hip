@@ -903,31 +903,36 @@ __global__ __launch_bounds__(256) void k_mask_detect_sym(DevGraph g, FusedArgs f
     if (mbits) mark_or(fa, c0 >> 3, r0 >> 8, mbits);
 }
 
-// |F| and Phi of a removal's mask, counted without writing it (a route that
-// needs no flags still reports them, and Algorithm 5's cost test reads Phi).
+// |F| and Phi of a removal's (or a tight increase's) mask, counted without
+// writing it (a route that needs no flags still reports them, and Algorithm
+// 5's cost test reads Phi).
 __global__ __launch_bounds__(SWEEP_THREADS) void k_mask_count(DevGraph g, FusedArgs fa) {
     __shared__ uint32_t s_cnt, s_rows;
     const int n = g.n_slots;
     const int32_t r0 = blockIdx.x * SWEEP_ROWS;
-    uint32_t a1[SWEEP_ROWS];
+    const bool inc = fa.mode == FUSED_INCREASE;
+    const uint32_t w_old = inc ? (uint32_t)g.ctl->w_old : 0u;
+    const int32_t kx = inc ? -1 : fa.k;
+    uint32_t a1[SWEEP_ROWS], a2[SWEEP_ROWS];
     uint32_t act = 0;
 #pragma unroll
     for (int r = 0; r < SWEEP_ROWS; ++r) {
-        a1[r] = 0x80000000u;
+        a1[r] = a2[r] = 0x80000000u;
         if (r0 + r < n) {
-            const RowTests rt = row_tests(g, fa, r0 + r, 0u);
-            if (rt.t1) {
-                a1[r] = rt.a1;
-                act |= 1u << r;
-            }
+            const RowTests rt = row_tests(g, fa, r0 + r, w_old);
+            if (rt.t1) a1[r] = rt.a1;
+            if (rt.t2) a2[r] = rt.a2;
+            if (rt.t1 || rt.t2) act |= 1u << r;
         }
     }
     if (act == 0) return;  // block-uniform
     if (threadIdx.x == 0) s_cnt = s_rows = 0;
     __syncthreads();
     uint32_t cnt = 0, rows = 0;
-    sweep_rows<SWEEP_ROWS>(g, r0, act, n, fa.row1, nullptr, [&](const SweepTile<SWEEP_ROWS> &T, int32_t c0, int32_t) {
+    sweep_rows<SWEEP_ROWS>(g, r0, act, n, fa.row1, inc ? fa.row2 : nullptr,
+                           [&](const SweepTile<SWEEP_ROWS> &T, int32_t c0, int32_t) {
         const uint32_t w1[4] = {T.v1.x, T.v1.y, T.v1.z, T.v1.w};
+        const uint32_t w2[4] = {T.v2.x, T.v2.y, T.v2.z, T.v2.w};
 #pragma unroll
         for (int r = 0; r < SWEEP_ROWS; ++r) {
             if (!((act >> r) & 1u)) continue;
@@ -935,7 +940,8 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_mask_count(DevGraph g, FusedA
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int32_t j = c0 + e;
-                const bool f = cat(a1[r], w1[e]) == dv[e] && dv[e] < INF && j != r0 + r && j != fa.k && j < n;
+                const bool f = (cat(a1[r], w1[e]) == dv[e] || cat(a2[r], w2[e]) == dv[e]) && dv[e] < INF &&
+                               j != r0 + r && j != kx && j < n;
                 cnt += f;
                 rows |= (uint32_t)f << r;
             }

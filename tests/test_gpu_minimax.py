@@ -383,6 +383,50 @@ def test_minimax_removal_by_spanning_forest(wmax, limit):
         assert routes.count(1) >= 8, routes
 
 
+@pytest.mark.parametrize("wmax,density", [(30, 0.05), (10000, 1.0)])
+def test_minimax_tight_increase_by_spanning_forest(wmax, density):
+    """Tight increases (and deletions) of edges on undirected minimax graphs
+    take the spanning-forest route (route 1): the forest of the graph before
+    the change, and only the pairs across the two pieces the raised edge
+    separates in it (none when it is not a forest edge).  Every state equals
+    the oracle's minimax Floyd-Warshall, the changed-pair count equals the
+    oracle's refined set, and the mask's |F| and Phi equal the oracle's."""
+    from paper_2412_15122_amd.apsp import Graph
+    rng = np.random.default_rng(131 + wmax)
+    n = 360
+    A = W.random_graph(n, 1, wmax, undirected=True, density=density, seed=int(rng.integers(1 << 30)))
+    g = Graph(A, undirected=True, capacity=n + 4, minimax=True)
+    ids = list(range(n))
+    D = O.minimax_apsp(A)
+    routes, moved = [], 0
+    for t in range(12):
+        tight = np.argwhere((A == D) & (A < INF) & ~np.eye(n, dtype=bool))
+        # every other step, a raise that moves some distance (the edge
+        # separates two pieces of the forest), found by trying candidates
+        for _ in range(12 if t % 2 else 1):
+            u, v = (int(x) for x in tight[int(rng.integers(len(tight)))])
+            w_new = INF if t % 4 == 3 else int(A[u, v]) + int(rng.integers(1, wmax + 1))
+            A2, ids2 = O.apply_update(A, ids, "edge", u=u, v=v, w=w_new, undirected=True)
+            D2 = O.minimax_apsp(A2)
+            if not np.array_equal(D2, D):
+                break
+        F = O.edge_mask(D, u, v, int(A[u, v]), True, minimax=True)
+        g.update_edge(u, v, w_new)
+        s = g.stats()
+        A, ids = A2, ids2
+        assert np.array_equal(g.matrix(), D2), (t, u, v, w_new)
+        changed = O.refined_set(D, D2)
+        assert s["kind"] == 4, (t, s)
+        assert s["changed"] == int(changed.sum()), (t, s["changed"], int(changed.sum()))
+        assert s["rows_changed"] == int(changed.any(axis=1).sum()), t
+        assert s["flagged"] == int(F.sum()) and s["rows"] == int(F.any(axis=1).sum()), t
+        routes.append(s["route"])
+        moved += int(changed.sum()) > 0
+        D = D2
+    assert routes.count(1) >= 10, routes
+    assert moved >= 3, moved
+
+
 def test_widest_removal_by_spanning_forest():
     """The same route on an undirected widest graph (stored as a minimax one)."""
     from paper_2412_15122_amd.apsp import Graph

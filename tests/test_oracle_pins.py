@@ -548,6 +548,33 @@ def test_minimax_removal_mask_holds_every_change():
         assert np.array_equal(D2[~F], D[np.ix_(keep, keep)][~F]), trial
 
 
+def test_minimax_edge_mask_holds_every_change():
+    """Corollary 3 with max, applied to the relay node of an edge: when an
+    edge is raised, pairs outside its minimax mask keep their distance; and
+    raising an edge heavier than its endpoints' minimax distance changes no
+    distance at all (the rule that skips such an increase)."""
+    rng = np.random.default_rng(83)
+    for trial in range(20):
+        n = int(rng.integers(3, 30))
+        und = bool(trial % 2)
+        A = W.random_graph(n, 1, 6, undirected=und, density=float(rng.uniform(0.2, 0.9)),
+                           seed=int(rng.integers(1 << 30)))
+        D = O.minimax_apsp(A)
+        edges = np.argwhere((A < INF) & ~np.eye(n, dtype=bool))
+        if len(edges) == 0:
+            continue
+        u, v = (int(x) for x in edges[int(rng.integers(len(edges)))])
+        F = O.edge_mask(D, u, v, int(A[u, v]), und, minimax=True)
+        A2 = A.copy()
+        A2[u, v] = int(A[u, v]) + int(rng.integers(1, 8))
+        if und:
+            A2[v, u] = A2[u, v]
+        D2 = O.minimax_apsp(A2)
+        assert np.array_equal(D2[~F], D[~F]), trial
+        if A[u, v] > D[u, v]:
+            assert np.array_equal(D2, D), trial
+
+
 def test_minimax_rows_equal_floyd_warshall():
     rng = np.random.default_rng(91)
     for trial in range(12):
