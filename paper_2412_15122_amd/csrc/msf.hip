@@ -166,11 +166,39 @@ __global__ void k_msf_relabel(DevGraph g, MsfWork w) {
 
 // ---- certificate -----------------------------------------------------------
 
+// Component sizes and heaviest forest edges.  Most slots share one
+// component: the lanes of a wavefront that agree with its first valid lane
+// combine into one atomic (one counter hit by every slot would serialize),
+// the others add their own.
 __global__ void k_msf_comp_stats(DevGraph g, MsfWork w) {
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
     const int32_t trees = min(w.info[MI_TREE], g.P);
-    if (t < trees) atomicMax(&w.comp_max[w.label[w.tree_a[t]]], w.tree_w[t]);
-    if (t < g.n_slots && w.label[t] >= 0) atomicAdd(&w.comp_size[w.label[t]], 1);
+    // heaviest forest edge per component
+    const int32_t le = t < trees ? w.label[w.tree_a[t]] : -1;
+    const int32_t we = t < trees ? w.tree_w[t] : 0;
+    unsigned long long m = __ballot(le >= 0);
+    if (m) {
+        const int first = __ffsll((long long)m) - 1;
+        const int32_t lf = __shfl(le, first);
+        const bool same = le >= 0 && le == lf;
+        uint32_t v = same ? (uint32_t)we : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+        if (lane == first) atomicMax(&w.comp_max[lf], (int32_t)v);
+        if (le >= 0 && !same) atomicMax(&w.comp_max[le], we);
+    }
+    // size per component
+    const int32_t ls = t < g.n_slots ? w.label[t] : -1;
+    m = __ballot(ls >= 0);
+    if (m) {
+        const int first = __ffsll((long long)m) - 1;
+        const int32_t lf = __shfl(ls, first);
+        const bool same = ls >= 0 && ls == lf;
+        const int cnt = __popcll(__ballot(same));
+        if (lane == first) atomicAdd(&w.comp_size[lf], cnt);
+        if (ls >= 0 && !same) atomicAdd(&w.comp_size[ls], 1);
+    }
 }
 
 // Per live node: its component's heaviest forest edge is no heavier than the
