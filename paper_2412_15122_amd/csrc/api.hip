@@ -98,6 +98,28 @@ apsp_status decide_fallback(apsp_graph *g, const FusedArgs *fa, int32_t n_before
     return check_launch("cost decision");
 }
 
+// The spanning forest, its certificate and the pieces of T - k (or of T - e
+// for a raised edge eu-ev of old weight ew), read back into g->qbuf_h.
+// Boruvka needs at most about log2(n) rounds but usually far fewer: a first
+// try runs 10 (the rounds after convergence are launches that do nothing),
+// and only a forest still growing after them is built again with all.
+apsp_status build_forest(apsp_graph *g, const MsfWork &w, int32_t k, int32_t eu, int32_t ev, int32_t ew,
+                         int32_t n_before, const char *who) {
+    int32_t rounds = 2;
+    while ((1 << (rounds - 2)) < std::max(n_before, 2)) ++rounds;
+    const int32_t first = std::min<int32_t>(rounds, 10);
+    for (int32_t r : {first, rounds}) {
+        launch_msf_forest(g->dg, w, k, eu, ev, ew, r, g->stream);
+        if (apsp_status st = check_launch(who)) return st;
+        if (!hip_ok(hipMemcpyAsync(g->qbuf_h, w.info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, g->stream),
+                    "forest read") ||
+            !hip_ok(hipStreamSynchronize(g->stream), "stream sync"))
+            return APSP_E_DEVICE;
+        if (g->qbuf_h[MI_ACTIVE] == 0 || r == rounds) break;
+    }
+    return APSP_OK;
+}
+
 // Removal of slot k from an undirected minimax graph through its minimum
 // spanning forest (msf.hip): the forest over the light index, its
 // certificate and the pieces of T - k, one read-back, then -- when the
@@ -117,14 +139,8 @@ apsp_status remove_by_forest(apsp_graph *g, int32_t k, int32_t n_before, bool *u
     hipStream_t s = g->stream;
     const MsfWork w = msf_work(g->fscratch, g->P);
     if (w.ints > (int64_t)FUSED_GRID * 2 * g->P) return APSP_OK;  // the heavy-row scratch holds it (P >= 128)
-    int32_t rounds = 2;
-    while ((1 << (rounds - 2)) < std::max(n_before, 2)) ++rounds;
-    launch_msf_forest(d, w, k, -1, -1, 0, rounds, s);
-    apsp_status st = check_launch("apsp_remove_node: spanning forest");
+    apsp_status st = build_forest(g, w, k, -1, -1, 0, n_before, "apsp_remove_node: spanning forest");
     if (st) return st;
-    if (!hip_ok(hipMemcpyAsync(g->qbuf_h, w.info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "forest read") ||
-        !hip_ok(hipStreamSynchronize(s), "stream sync"))
-        return APSP_E_DEVICE;
     const int32_t *info = g->qbuf_h;
     if (info[MI_ACTIVE] != 0 || info[MI_FAIL] != 0) return APSP_OK;
     FusedArgs fa{};
@@ -169,14 +185,8 @@ apsp_status increase_by_forest(apsp_graph *g, int32_t su, int32_t sv, int32_t w_
     hipStream_t s = g->stream;
     const MsfWork w = msf_work(g->fscratch, g->P);
     if (w.ints > (int64_t)FUSED_GRID * 2 * g->P) return APSP_OK;
-    int32_t rounds = 2;
-    while ((1 << (rounds - 2)) < std::max(n_before, 2)) ++rounds;
-    launch_msf_forest(d, w, -1, su, sv, w_old, rounds, s);
-    apsp_status st = check_launch("apsp_update_edge: spanning forest");
+    apsp_status st = build_forest(g, w, -1, su, sv, w_old, n_before, "apsp_update_edge: spanning forest");
     if (st) return st;
-    if (!hip_ok(hipMemcpyAsync(g->qbuf_h, w.info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "forest read") ||
-        !hip_ok(hipStreamSynchronize(s), "stream sync"))
-        return APSP_E_DEVICE;
     const int32_t *info = g->qbuf_h;
     if (info[MI_ACTIVE] != 0 || info[MI_FAIL] != 0) return APSP_OK;
     const int32_t pieces = info[MI_D], small = info[MI_SMALL];

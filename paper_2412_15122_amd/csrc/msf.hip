@@ -110,7 +110,10 @@ __global__ __launch_bounds__(256) void k_msf_min(DevGraph g, MsfWork w, int32_t 
         if (ly >= 0 && ly != lx && ew < INF) key = min(key, edge_key(ew, x, y));
     }
     key = wave_min64(key);
-    if (lane == 0 && key != NO_EDGE) atomicMin(&w.best[lx], key);
+    // the best edge only falls: a read at or below the key (stale reads are
+    // higher, never lower) makes the atomic useless -- and the nodes of a
+    // large component would all queue on its one word
+    if (lane == 0 && key != NO_EDGE && key < w.best[lx]) atomicMin(&w.best[lx], key);
 }
 
 // Every component root hooks to the component across its best edge and
@@ -216,9 +219,32 @@ __global__ __launch_bounds__(256) void k_msf_certify(DevGraph g, MsfWork w) {
         if ((uint32_t)w.comp_max[lx] > beta) atomicOr(&w.info[MI_FAIL], MSF_FAIL_CERT);
     }
     if (lx != x) return;
+    // the root's row: 16-byte loads, four per lane in flight (rows are padded
+    // to a multiple of 128 entries; slots past n_slots are dead)
     const int32_t *Dr = g.D + (int64_t)x * g.ld;
+    const int32_t n4 = (g.n_slots + 3) & ~3;
     int reach = 0;
-    for (int32_t y = lane; y < g.n_slots; y += 64) reach += (uint32_t)Dr[y] < INF && g.id_of_slot[y] >= 0;
+    for (int32_t y0 = lane * 4; y0 < n4; y0 += 64 * 4 * 4) {
+        uint4 dv[4], iv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t y = y0 + q * 256;
+            dv[q] = make_uint4(INF, INF, INF, INF);
+            iv[q] = make_uint4(0, 0, 0, 0);
+            if (y < n4) {
+                dv[q] = *reinterpret_cast<const uint4 *>(Dr + y);
+                iv[q] = *reinterpret_cast<const uint4 *>(g.id_of_slot + y);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t y = y0 + q * 256;
+            reach += (dv[q].x < INF && (int32_t)iv[q].x >= 0 && y < g.n_slots) +
+                     (dv[q].y < INF && (int32_t)iv[q].y >= 0 && y + 1 < g.n_slots) +
+                     (dv[q].z < INF && (int32_t)iv[q].z >= 0 && y + 2 < g.n_slots) +
+                     (dv[q].w < INF && (int32_t)iv[q].w >= 0 && y + 3 < g.n_slots);
+        }
+    }
     reach = wave_sum(reach);
     if (lane == 0 && reach != w.comp_size[x]) atomicOr(&w.info[MI_FAIL], MSF_FAIL_SPAN);
 }
