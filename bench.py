@@ -107,14 +107,18 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def sweep_bytes(kind, live):
+def sweep_bytes(kind, live, count_only=False):
     """Algorithmic bytes of one full sweep of D on the undirected graph of
     `live` nodes.  D is symmetric, so an addition's relaxation (Theorem 3,
     in = out) reads each unordered pair of the old nodes once, 4 n (n-1) / 2
     bytes, and a removal's mask (Corollary 3) each unordered pair of the
-    other n - 1 nodes, 4 (n-1)(n-2) / 2."""
+    other n - 1 nodes, 4 (n-1)(n-2) / 2.  count_only: the count-only mask of
+    a minimax removal's spanning-forest route, which reads the rows of the
+    other n - 1 nodes in full, 4 (n-1) n."""
     if kind == "add":
         return 2 * live * (live - 1)
+    if count_only:
+        return 4 * (live - 1) * live
     return 2 * (live - 1) * (live - 2)
 
 
@@ -776,7 +780,7 @@ def main():
             live += 1
         elif k == W.REMOVE:
             if seen["mask_detect"] % args.prof_every == 0:
-                removes_bytes += sweep_bytes("remove", live)
+                removes_bytes += sweep_bytes("remove", live, count_only=minimax)
                 launches["mask_detect"] += 1
             seen["mask_detect"] += 1
             live -= 1
