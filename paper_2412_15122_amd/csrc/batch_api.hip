@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <unordered_set>
 #include <vector>
 
@@ -54,6 +55,18 @@ struct Undo {
     bool slot_was_free;
 };
 
+// The first item of a graph that failed its checks (t < 0: none).
+struct ItemFail {
+    int32_t t = -1;
+    apsp_status st = APSP_OK;
+    const char *what = "";
+};
+
+// Host threads that check a batch's items (graphs split between them), from
+// this many items on.
+constexpr int32_t BATCH_HOST_THREADS = 8;
+constexpr int32_t BATCH_HOST_PARALLEL_ITEMS = 512;
+
 void undo_all(std::vector<Undo> &log) {
     for (auto it = log.rbegin(); it != log.rend(); ++it) {
         apsp_graph *g = it->g;
@@ -98,7 +111,8 @@ struct apsp_batch {
     // per-run scratch (host)
     std::vector<int32_t> count, begin, fill, active;
     std::vector<int64_t> work;
-    std::vector<Undo> log;
+    std::vector<int32_t> order_items, cursor;  // items grouped by graph; fill cursor
+    std::vector<std::vector<Undo>> logs;       // per host thread
 };
 
 namespace {
@@ -158,9 +172,9 @@ apsp_status launch(apsp_batch *b, int32_t n_active, int32_t P_max, bool minimax,
     return APSP_OK;
 }
 
-apsp_status bad_item(std::vector<Undo> &log, int32_t t, apsp_status st, const char *what) {
-    undo_all(log);
-    return fail(st, "apsp_batch_run: item " + std::to_string(t) + ": " + what);
+// Every host change of the last checks, undone (a later step failed).
+void undo_logs(apsp_batch *b) {
+    for (auto &l : b->logs) undo_all(l);
 }
 
 }  // namespace
@@ -273,89 +287,133 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
     b->fill.assign(b->begin.begin(), b->begin.end() - 1);
     b->work.assign(num_graphs, 0);
     auto *bitems = reinterpret_cast<BatchItem *>(b->stage + b->L.items);
-    std::vector<Undo> &log = b->log;
-    log.clear();
     std::vector<int32_t> last_kind(num_graphs, 0), last_n(num_graphs, 0);
-    for (int32_t t = 0; t < num_items; ++t) {
-        const apsp_batch_item &x = items[t];
-        apsp_graph *g = graphs[x.graph];
-        BatchItem bi{};
-        bi.rank_src = g->rank_cur;
-        if (new_ids) new_ids[t] = -1;
-        const bool und = g->kind == APSP_UNDIRECTED;
-        if (x.op == APSP_OP_ADD_NODE) {
-            if (g->n_live > 0 && (!x.w_out_dev || (!und && !x.w_in_dev)))
-                return bad_item(log, t, APSP_E_INVALID, "weight vector is NULL");
-            if (g->max_id >= INT32_MAX - 1) return bad_item(log, t, APSP_E_CAPACITY, "the id range is used up");
-            int32_t p;
-            bool was_free = false;
-            if (!g->free_slots.empty()) {
-                p = *g->free_slots.begin();
-                was_free = true;
-            } else if (g->dg.n_slots < g->cap) {
-                p = g->dg.n_slots;
+    // Each graph's items apply in their order; different graphs' host
+    // bookkeeping is independent, so the graphs are split over a few host
+    // threads (the per-item checks miss the caches of 512 graphs' id maps).
+    // Items grouped by graph, in order:
+    b->order_items.resize(num_items);
+    b->cursor.assign(b->begin.begin(), b->begin.end() - 1);
+    for (int32_t t = 0; t < num_items; ++t) b->order_items[b->cursor[items[t].graph]++] = t;
+    // one graph's items; the first failing item stops it (nothing undone here)
+    auto run_graph = [&](int32_t gi, std::vector<Undo> &log) -> ItemFail {
+        for (int32_t q = b->begin[gi]; q < b->begin[gi + 1]; ++q) {
+            const int32_t t = b->order_items[q];
+            const apsp_batch_item &x = items[t];
+            apsp_graph *g = graphs[x.graph];
+            BatchItem bi{};
+            bi.rank_src = g->rank_cur;
+            if (new_ids) new_ids[t] = -1;
+            const bool und = g->kind == APSP_UNDIRECTED;
+            if (x.op == APSP_OP_ADD_NODE) {
+                if (g->n_live > 0 && (!x.w_out_dev || (!und && !x.w_in_dev)))
+                    return ItemFail{t, APSP_E_INVALID, "weight vector is NULL"};
+                if (g->max_id >= INT32_MAX - 1) return ItemFail{t, APSP_E_CAPACITY, "the id range is used up"};
+                int32_t p;
+                bool was_free = false;
+                if (!g->free_slots.empty()) {
+                    p = *g->free_slots.begin();
+                    was_free = true;
+                } else if (g->dg.n_slots < g->cap) {
+                    p = g->dg.n_slots;
+                } else {
+                    return ItemFail{t, APSP_E_CAPACITY, "every slot is in use"};
+                }
+                const int32_t nid = g->max_id + 1;
+                log.push_back({g, BOP_ADD, nid, p, 0, g->dg.n_slots, g->max_id, was_free});
+                g->dg.n_slots = std::max(g->dg.n_slots, p + 1);
+                bi.op = BOP_ADD;
+                bi.a = p;
+                bi.b = nid;
+                bi.c = g->n_live;
+                bi.w_out = x.w_out_dev;
+                bi.w_in = und ? x.w_out_dev : x.w_in_dev;
+                last_kind[x.graph] = UK_ADD;
+                last_n[x.graph] = g->n_live;
+                g->free_slots.erase(p);
+                g->max_id = nid;
+                g->live_ids.push_back(nid);
+                g->slot_of_id[nid] = p;
+                g->n_live += 1;
+                if (new_ids) new_ids[t] = nid;
+            } else if (x.op == APSP_OP_REMOVE_NODE) {
+                int32_t k;
+                if (!lookup(g, x.u, &k)) return ItemFail{t, APSP_E_NOT_FOUND, "id is not live"};
+                const int32_t r = rank_of(g, x.u);
+                log.push_back({g, BOP_REMOVE, x.u, k, r, g->dg.n_slots, g->max_id, false});
+                bi.op = BOP_REMOVE;
+                bi.a = k;
+                bi.b = r;
+                bi.c = g->n_live;
+                bi.rank_dst = g->rank_other;
+                last_kind[x.graph] = UK_REMOVE;
+                last_n[x.graph] = g->n_live;
+                std::swap(g->rank_cur, g->rank_other);
+                g->live_ids.erase(g->live_ids.begin() + r);
+                g->slot_of_id.erase(x.u);
+                g->free_slots.insert(k);
+                g->n_live -= 1;
+            } else if (x.op == APSP_OP_UPDATE_EDGE) {
+                if (x.w < 0 || (uint32_t)x.w > INF) return ItemFail{t, APSP_E_INVALID, "weight outside [0, APSP_INF]"};
+                if (x.u == x.v) return ItemFail{t, APSP_E_INVALID, "u == v"};
+                int32_t su, sv;
+                if (!lookup(g, x.u, &su) || !lookup(g, x.v, &sv)) return ItemFail{t, APSP_E_NOT_FOUND, "id is not live"};
+                bi.op = BOP_EDGE;
+                bi.a = su;
+                bi.b = sv;
+                bi.c = g->dg.widest ? widest_xf(x.w) : x.w;
+                last_kind[x.graph] = -1;
+                last_n[x.graph] = g->n_live;
+            } else if (x.op == APSP_OP_QUERY) {
+                int32_t si, sj;
+                if (!lookup(g, x.u, &si) || !lookup(g, x.v, &sj)) return ItemFail{t, APSP_E_NOT_FOUND, "id is not live"};
+                if (!x.out_dev || x.out_cap < 3 + g->n_live) return ItemFail{t, APSP_E_CAPACITY, "query output too short"};
+                bi.op = BOP_QUERY;
+                bi.a = si;
+                bi.b = sj;
+                bi.out = x.out_dev;
             } else {
-                return bad_item(log, t, APSP_E_CAPACITY, "every slot is in use");
+                return ItemFail{t, APSP_E_INVALID, "unknown op"};
             }
-            const int32_t nid = g->max_id + 1;
-            log.push_back({g, BOP_ADD, nid, p, 0, g->dg.n_slots, g->max_id, was_free});
-            g->dg.n_slots = std::max(g->dg.n_slots, p + 1);
-            bi.op = BOP_ADD;
-            bi.a = p;
-            bi.b = nid;
-            bi.c = g->n_live;
-            bi.w_out = x.w_out_dev;
-            bi.w_in = und ? x.w_out_dev : x.w_in_dev;
-            last_kind[x.graph] = UK_ADD;
-            last_n[x.graph] = g->n_live;
-            g->free_slots.erase(p);
-            g->max_id = nid;
-            g->live_ids.push_back(nid);
-            g->slot_of_id[nid] = p;
-            g->n_live += 1;
-            if (new_ids) new_ids[t] = nid;
-        } else if (x.op == APSP_OP_REMOVE_NODE) {
-            int32_t k;
-            if (!lookup(g, x.u, &k)) return bad_item(log, t, APSP_E_NOT_FOUND, "id is not live");
-            const int32_t r = rank_of(g, x.u);
-            log.push_back({g, BOP_REMOVE, x.u, k, r, g->dg.n_slots, g->max_id, false});
-            bi.op = BOP_REMOVE;
-            bi.a = k;
-            bi.b = r;
-            bi.c = g->n_live;
-            bi.rank_dst = g->rank_other;
-            last_kind[x.graph] = UK_REMOVE;
-            last_n[x.graph] = g->n_live;
-            std::swap(g->rank_cur, g->rank_other);
-            g->live_ids.erase(g->live_ids.begin() + r);
-            g->slot_of_id.erase(x.u);
-            g->free_slots.insert(k);
-            g->n_live -= 1;
-        } else if (x.op == APSP_OP_UPDATE_EDGE) {
-            if (x.w < 0 || (uint32_t)x.w > INF) return bad_item(log, t, APSP_E_INVALID, "weight outside [0, APSP_INF]");
-            if (x.u == x.v) return bad_item(log, t, APSP_E_INVALID, "u == v");
-            int32_t su, sv;
-            if (!lookup(g, x.u, &su) || !lookup(g, x.v, &sv)) return bad_item(log, t, APSP_E_NOT_FOUND, "id is not live");
-            bi.op = BOP_EDGE;
-            bi.a = su;
-            bi.b = sv;
-            bi.c = g->dg.widest ? widest_xf(x.w) : x.w;
-            last_kind[x.graph] = -1;
-            last_n[x.graph] = g->n_live;
-        } else if (x.op == APSP_OP_QUERY) {
-            int32_t si, sj;
-            if (!lookup(g, x.u, &si) || !lookup(g, x.v, &sj)) return bad_item(log, t, APSP_E_NOT_FOUND, "id is not live");
-            if (!x.out_dev || x.out_cap < 3 + g->n_live) return bad_item(log, t, APSP_E_CAPACITY, "query output too short");
-            bi.op = BOP_QUERY;
-            bi.a = si;
-            bi.b = sj;
-            bi.out = x.out_dev;
-        } else {
-            return bad_item(log, t, APSP_E_INVALID, "unknown op");
+            bi.n_slots = g->dg.n_slots;
+            b->work[x.graph] += (int64_t)bi.n_slots * bi.n_slots;
+            bitems[b->fill[x.graph]++] = bi;
         }
-        bi.n_slots = g->dg.n_slots;
-        b->work[x.graph] += (int64_t)bi.n_slots * bi.n_slots;
-        bitems[b->fill[x.graph]++] = bi;
+        return ItemFail{};
+    };
+    const int32_t nthreads = num_items >= BATCH_HOST_PARALLEL_ITEMS
+                                 ? std::max(1, std::min<int32_t>(BATCH_HOST_THREADS, num_graphs))
+                                 : 1;
+    b->logs.resize(nthreads);
+    std::vector<ItemFail> fails(nthreads);
+    // contiguous ranges of graphs with about equal item counts
+    auto run_range = [&](int32_t w) {
+        b->logs[w].clear();
+        const int64_t lo = (int64_t)num_items * w / nthreads, hi = (int64_t)num_items * (w + 1) / nthreads;
+        for (int32_t gi = 0; gi < num_graphs; ++gi) {
+            if (b->begin[gi] < lo || b->begin[gi] >= hi || b->count[gi] == 0) continue;
+            const ItemFail f = run_graph(gi, b->logs[w]);
+            if (f.t >= 0) {
+                fails[w] = f;
+                return;
+            }
+        }
+    };
+    if (nthreads == 1) {
+        run_range(0);
+    } else {
+        std::vector<std::thread> pool;
+        pool.reserve(nthreads - 1);
+        for (int32_t w = 1; w < nthreads; ++w) pool.emplace_back(run_range, w);
+        run_range(0);
+        for (auto &th : pool) th.join();
+    }
+    const ItemFail *first = nullptr;
+    for (const ItemFail &f : fails)
+        if (f.t >= 0 && (!first || f.t < first->t)) first = &f;
+    if (first) {
+        undo_logs(b);
+        return fail(first->st, "apsp_batch_run: item " + std::to_string(first->t) + ": " + first->what);
     }
     // launch records: graphs with items, most work first unless asked otherwise
     auto *hdr = reinterpret_cast<BatchHeader *>(b->stage);
@@ -443,23 +501,23 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
             others.push_back(graphs[i]->stream);
     while (b->waits.size() < others.size()) {
         hipEvent_t e;
-        if (!hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) return undo_all(log), APSP_E_DEVICE;
+        if (!hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) return undo_logs(b), APSP_E_DEVICE;
         b->waits.push_back(e);
     }
     for (size_t q = 0; q < others.size(); ++q)
         if (!hip_ok(hipEventRecord(b->waits[q], others[q]), "event record") ||
             !hip_ok(hipStreamWaitEvent(s, b->waits[q], 0), "stream wait"))
-            return undo_all(log), APSP_E_DEVICE;
+            return undo_logs(b), APSP_E_DEVICE;
     const size_t bytes = b->L.items + (size_t)num_items * sizeof(BatchItem);
     if (!hip_ok(hipMemcpyAsync(b->ws, b->stage, bytes, hipMemcpyHostToDevice, s), "batch upload") ||
         (table_words && !hip_ok(hipMemcpyAsync(b->ws + b->L.tables, b->stage + b->L.tables,
                                                table_words * sizeof(int32_t), hipMemcpyHostToDevice, s),
                                 "batch upload")) ||
         !hip_ok(hipEventRecord(b->staged, s), "event record"))
-        return undo_all(log), APSP_E_DEVICE;
+        return undo_logs(b), APSP_E_DEVICE;
     b->stage_busy = true;
     apsp_status st = launch(b, n_active, P_max, num_graphs > 0 && graphs[0]->minimax, s);
-    if (st) return undo_all(log), st;
+    if (st) return undo_logs(b), st;
     // later single calls on a graph's own stream run after the batch
     if (!others.empty()) {
         if (!hip_ok(hipEventRecord(b->done, s), "event record")) return APSP_E_DEVICE;
@@ -477,7 +535,7 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
             g->last_fallback = 0;
         }
     }
-    log.clear();
+    for (auto &l : b->logs) l.clear();
     return APSP_OK;
 }
 

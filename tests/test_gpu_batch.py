@@ -232,6 +232,46 @@ def test_rejected_batch_changes_nothing():
     b.close()
 
 
+def test_large_batch_checked_on_host_threads():
+    """From 512 items on, the host checks split the graphs over threads: a
+    batch with bad items in two graphs is rejected naming the earlier one,
+    with every graph unchanged, and the valid batch still equals the single
+    calls and the oracle."""
+    from paper_2412_15122_amd.batch import Batch
+    from paper_2412_15122_amd._native import ApspError
+    import torch
+    sizes = [20 + (7 * i) % 41 for i in range(80)]
+    graphs, states, items = make_case(sizes, undirected_every=4, seed=41)
+    assert len(items) >= 512
+    ga = build(graphs)
+    before = [(g.ids(), g.matrix_device("D").clone(), g.matrix_device("A").clone()) for g in ga]
+    bad = list(items)
+    bad.insert(len(bad) * 3 // 4, ("edge", 70, 10 ** 6, 0, 5))  # 10**6 is not a live id
+    early = len(bad) // 4
+    bad.insert(early, ("remove", 5, 10 ** 6))
+    b = Batch(len(ga), len(bad), use_graph=True, variant=3)
+    with pytest.raises(ApspError, match=rf"item {early}: id is not live"):
+        b.run(ga, bad)
+    for g, (ids, D, A) in zip(ga, before):
+        assert g.ids() == ids
+        assert torch.equal(g.matrix_device("D"), D) and torch.equal(g.matrix_device("A"), A)
+    gb = [g.clone() for g in ga]
+    res = b.run(ga, items)
+    b.status()
+    torch.cuda.synchronize()
+    answers = replay_single(gb, items)
+    for gi in range(len(ga)):
+        assert_same(ga[gi], gb[gi], f"graph {gi}")
+    for t, ans in answers.items():
+        assert res[t].get() == ans, f"query item {t}"
+    for gi in (0, 1, 37, 79):
+        assert ga[gi].ids() == states[gi].live
+        assert np.array_equal(ga[gi].matrix(), O.fw(states[gi].dense(), threads=THREADS)), f"oracle graph {gi}"
+    b.close()
+    for g in ga + gb:
+        g.close()
+
+
 def test_config4_shape_sample():
     """A slice of the batched workload (directed complete graphs, n
     log-uniform in [128, 2048], 8 queued updates each)."""
