@@ -196,6 +196,7 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
                              int32_t *cnt_out, int32_t *beta_out, SelectShared &sh, uint32_t *stage) {
     const int tid = threadIdx.x;
     int valid = 0;
+    uint32_t tmin = INF;  // this thread's smallest staged value
     // stage the values: 16-byte loads, four per thread in flight (scalar
     // loads for a misaligned vector and the tail)
     const int32_t n4 = ((uintptr_t)vals & 15) ? 0 : (n & ~3);
@@ -223,6 +224,7 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
                 stage[x + 2] = u.z;
                 stage[x + 3] = u.w;
                 valid += (u.x < INF) + (u.y < INF) + (u.z < INF) + (u.w < INF);
+                tmin = min(tmin, min(min(u.x, u.y), min(u.z, u.w)));
             }
         }
     }
@@ -231,6 +233,7 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
         if (x == excl) v = INF;
         stage[x] = v;
         valid += v < INF;
+        tmin = min(tmin, v);
     }
     int total = block_sum<NT>(valid, sh.red);
     uint32_t tau = INF;  // entries < tau are all taken
@@ -265,9 +268,7 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
     if (total > NIN_L) {
         // light weights are usually packed near the minimum: try the 256
         // values [vmin, vmin + 256) first (one histogram, few collisions)
-        uint32_t vmin = INF;
-        for (int32_t x = tid; x < n; x += NT) vmin = min(vmin, stage[x]);
-        vmin = block_min<NT>(vmin, sh.red);
+        const uint32_t vmin = block_min<NT>(tmin, sh.red);
         if (tid < 256) sh.hist[tid] = 0;
         __syncthreads();
         for (int32_t x = tid; x < n; x += NT) {
@@ -301,27 +302,49 @@ __device__ inline void select_light(const int32_t *__restrict__ vals, int32_t n,
         }
         __syncthreads();
     }
-    // ordered collection over contiguous segments of the staged values
-    const int32_t seg = (n + NT - 1) / NT;
-    const int32_t x0 = min(n, tid * seg), x1 = min(n, x0 + seg);
-    int c_less = 0, c_eq = 0;
-    for (int32_t x = x0; x < x1; ++x) {
-        const uint32_t v = stage[x];
-        c_less += (v < tau);
-        c_eq += (v == tau && v < INF);
+    // ordered collection: wavefront w takes the contiguous range [w span,
+    // (w + 1) span) and reads it 64 consecutive values at a time (no LDS bank
+    // conflicts); ballots rank the kept entries in index order
+    constexpr int NWAVES = NT / 64;
+    const int wid = tid >> 6, lane = tid & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int32_t span = (((n + NWAVES - 1) / NWAVES) + 63) & ~63;
+    const int32_t xa = min(n, wid * span), xb = min(n, xa + span);
+    int c_less = 0, c_eq = 0;  // this wavefront's counts
+    for (int32_t b = xa; b < xb; b += 64) {  // wave-uniform
+        const int32_t x = b + lane;
+        const uint32_t v = x < xb ? stage[x] : INF;
+        c_less += __popcll(__ballot(v < tau));
+        c_eq += __popcll(__ballot(v == tau && v < INF));
     }
-    int tot_less, tot_eq;
-    int off_less = block_exscan<NT>(c_less, sh.red, &tot_less);
-    int off_eq = block_exscan<NT>(c_eq, sh.red + 16, &tot_eq);
-    for (int32_t x = x0; x < x1; ++x) {
-        const uint32_t v = stage[x];
-        if (v >= INF) continue;
-        if (v < tau) {
-            sh.keys[off_less++] = ((unsigned long long)v << 32) | (uint32_t)x;
-        } else if (v == tau) {
-            if (off_eq < need_eq) sh.keys[tot_less + off_eq] = ((unsigned long long)v << 32) | (uint32_t)x;
-            ++off_eq;
+    __syncthreads();
+    if (lane == 0) {
+        sh.red[wid] = (uint32_t)c_less;
+        sh.red[16 + wid] = (uint32_t)c_eq;
+    }
+    __syncthreads();
+    int off_less = 0, off_eq = 0, tot_less = 0;
+#pragma unroll
+    for (int w = 0; w < NWAVES; ++w) {
+        const int a = (int)sh.red[w], e = (int)sh.red[16 + w];
+        if (w < wid) {
+            off_less += a;
+            off_eq += e;
         }
+        tot_less += a;
+    }
+    for (int32_t b = xa; b < xb; b += 64) {  // wave-uniform
+        const int32_t x = b + lane;
+        const uint32_t v = x < xb ? stage[x] : INF;
+        const unsigned long long ml = __ballot(v < tau), me = __ballot(v == tau && v < INF);
+        if (v < tau) {
+            sh.keys[off_less + __popcll(ml & below)] = ((unsigned long long)v << 32) | (uint32_t)x;
+        } else if (v == tau && v < INF) {
+            const int r = off_eq + __popcll(me & below);
+            if (r < need_eq) sh.keys[tot_less + r] = ((unsigned long long)v << 32) | (uint32_t)x;
+        }
+        off_less += __popcll(ml);
+        off_eq += __popcll(me);
     }
     __syncthreads();
     const int m = min(total, NIN_L);
