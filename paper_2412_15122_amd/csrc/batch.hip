@@ -1170,12 +1170,93 @@ __device__ inline int32_t chunk_graph(const int32_t *base, int32_t num_graphs, i
     return lo;
 }
 
+// One chunk of step s's row sweeps: rows [cg * rpc, (cg + 1) * rpc) of
+// graph bg's item s (rpc = batch_rows_per_chunk).  The caller separates
+// chunks with a block barrier, so the staging area is free on entry.
+template <int U>
+__device__ inline void sweep_chunk(const BatchGraph &bg, const BatchItem *items, int32_t s, int32_t cg, bool staged,
+                                   int32_t P_max, uint32_t *stage) {
+    const BatchItem it = items[bg.item_begin + s];
+    DevGraph g = bg.g;
+    g.n_slots = it.n_slots;
+    const int32_t rpc = batch_rows_per_chunk(it.n_slots);
+    const int32_t r0 = cg * rpc, r1 = min(r0 + rpc, it.n_slots);
+    const int32_t mode = it.op == BOP_EDGE ? g.ctl->edge_mode : EDGE_NOOP;
+    // the chunk's inputs besides D: one or two row vectors (the
+    // columns' side of the pair test or relaxation) and one or two
+    // values per row (its side); with `staged`, copied to LDS once
+    // per chunk so that a wavefront's pieces wait only for D
+    const int32_t *vsrc1 = nullptr, *vsrc2 = nullptr, *rsrc1 = nullptr, *rsrc2 = nullptr;
+    if (it.op == BOP_ADD) {
+        vsrc1 = bg.vout;
+        rsrc1 = g.undirected ? bg.vout : bg.vin;
+    } else if (it.op == BOP_REMOVE) {
+        vsrc1 = bg.rowu;
+        rsrc1 = bg.colu;
+    } else if (mode == EDGE_DECREASE || mode == EDGE_INCREASE) {
+        vsrc1 = bg.rowv;
+        vsrc2 = g.undirected ? bg.rowu : nullptr;
+        rsrc1 = bg.colu;
+        rsrc2 = bg.colv;
+    } else {
+        return;  // block-uniform: a no-op edge update or a query sweeps nothing
+    }
+    const uint32_t *S1 = reinterpret_cast<const uint32_t *>(vsrc1);
+    const uint32_t *S2 = reinterpret_cast<const uint32_t *>(vsrc2);
+    const uint32_t *T1 = reinterpret_cast<const uint32_t *>(rsrc1) + r0;
+    const uint32_t *T2 = reinterpret_cast<const uint32_t *>(rsrc2 ? rsrc2 + r0 : nullptr);
+    if (staged) {
+        uint32_t *v1 = stage, *v2 = stage + P_max, *t1 = stage + 2 * P_max, *t2 = t1 + LOCKSTEP_STAGE_ROWS;
+        const int32_t n4 = (it.n_slots + 3) & ~3;
+        for (int32_t x = threadIdx.x; x < n4; x += BATCH_THREADS) {
+            v1[x] = x < it.n_slots ? (uint32_t)vsrc1[x] : INF;
+            if (vsrc2) v2[x] = x < it.n_slots ? (uint32_t)vsrc2[x] : INF;
+        }
+        for (int32_t r = threadIdx.x; r < r1 - r0; r += BATCH_THREADS) {
+            t1[r] = (uint32_t)rsrc1[r0 + r];
+            if (rsrc2) t2[r] = (uint32_t)rsrc2[r0 + r];
+        }
+        __syncthreads();
+        S1 = v1;
+        S2 = vsrc2 ? v2 : nullptr;
+        T1 = t1;
+        T2 = rsrc2 ? t2 : nullptr;
+    }
+    if (it.op == BOP_ADD) {
+        add_relax_rows<U>(g, bg, r0, r1, S1, [&](int32_t i) { return T1[i - r0]; });
+    } else if (it.op == BOP_REMOVE) {
+        const FusedArgs fa = remove_args(bg, it);
+        const int32_t k = it.a;
+        detect_rows<U>(g, bg, fa, r0, r1, S1, nullptr, [&](int32_t i) {
+            const uint32_t dik = T1[i - r0];
+            return RowTests{i != k && dik < INF, false, dik, 0u};
+        });
+    } else if (mode == EDGE_DECREASE) {
+        dec_relax_rows<U>(g, bg, it.c, r0, r1, S1, S2, [&](int32_t i) { return T1[i - r0]; },
+                          [&](int32_t i) { return T2[i - r0]; });
+    } else {
+        const FusedArgs fa = increase_args(g, bg);
+        const uint32_t w_old = (uint32_t)g.ctl->w_old;
+        const bool und = g.undirected != 0;
+        detect_rows<U>(g, bg, fa, r0, r1, S1, S2, [&](int32_t i) {
+            // the pair tests of row_tests for an increase, from the copies
+            const uint32_t cu = T1[i - r0], cv = T2[i - r0];
+            RowTests r{cv < INF && cat(cu, w_old) == cv, false, cv, 0u};
+            if (und) {
+                r.t2 = cu < INF && cat(cv, w_old) == cu;
+                r.a2 = cu;
+            }
+            return r;
+        });
+    }
+}
+
 template <int U>
 __global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs,
                                                                      const BatchItem *items, const int32_t *tables) {
     extern __shared__ __align__(16) uint32_t stage[];  // P words of select staging, then the wave lists / need bitmap
     __shared__ SelectShared ssh;
-    __shared__ int32_t s_claim, s_found_g, s_found_j;
+    __shared__ int32_t s_claim, s_found_g, s_found_j, s_sweep;
     __shared__ int s_flag;
     const int32_t G = hdr->num_graphs;
     const int32_t steps = hdr->steps;
@@ -1226,89 +1307,29 @@ __global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch_lockstep(BatchHeader
             grid_barrier(hdr);
         }
         if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s < BATCH_PHASE_STAMPS) hdr->phase_ts[3 * s] = wall_clock64();
-        // B: row sweeps (relaxation or mask) of every graph, spread over the
-        // grid round robin (neighbouring work-groups stream neighbouring
-        // rows); the wavefronts of a work-group go on to its next chunk
-        // without waiting for each other (the sweeps share nothing in LDS)
+        // B: row sweeps (relaxation or mask) of every graph.  Chunks are
+        // claimed from a counter (the next claim is in flight while the
+        // current chunk streams), in the table's order: additions and
+        // removals first, largest graph first, then the edge updates, most of
+        // which turn out to sweep nothing (decided in phase A), so they fill
+        // the tail.  A static round robin left the busiest work-group about
+        // twice the mean bytes.
         const int32_t *baseB = baseA2 + (G + 1);
+        const int32_t *orderB = baseB + 2 * (G + 1);
         const bool staged = lockstep_stages_sweeps(P_max);
-        for (int32_t c = blockIdx.x, gi = 0; c < baseB[G]; c += gridDim.x) {
-            gi = chunk_graph(baseB, G, c, gi);
-            const BatchGraph &bg = graphs[gi];
-            const BatchItem it = items[bg.item_begin + s];
-            DevGraph g = bg.g;
-            g.n_slots = it.n_slots;
-            const int32_t rpc = batch_rows_per_chunk(it.n_slots);
-            const int32_t r0 = (c - baseB[gi]) * rpc, r1 = min(r0 + rpc, it.n_slots);
-            const int32_t mode = it.op == BOP_EDGE ? g.ctl->edge_mode : EDGE_NOOP;
-            // the chunk's inputs besides D: one or two row vectors (the
-            // columns' side of the pair test or relaxation) and one or two
-            // values per row (its side); with `staged`, copied to LDS once
-            // per chunk so that a wavefront's pieces wait only for D
-            const int32_t *vsrc1 = nullptr, *vsrc2 = nullptr, *rsrc1 = nullptr, *rsrc2 = nullptr;
-            if (it.op == BOP_ADD) {
-                vsrc1 = bg.vout;
-                rsrc1 = g.undirected ? bg.vout : bg.vin;
-            } else if (it.op == BOP_REMOVE) {
-                vsrc1 = bg.rowu;
-                rsrc1 = bg.colu;
-            } else if (mode == EDGE_DECREASE || mode == EDGE_INCREASE) {
-                vsrc1 = bg.rowv;
-                vsrc2 = g.undirected ? bg.rowu : nullptr;
-                rsrc1 = bg.colu;
-                rsrc2 = bg.colv;
-            } else {
-                continue;  // block-uniform: a no-op edge update or a query sweeps nothing
-            }
-            const uint32_t *S1 = reinterpret_cast<const uint32_t *>(vsrc1);
-            const uint32_t *S2 = reinterpret_cast<const uint32_t *>(vsrc2);
-            const uint32_t *T1 = reinterpret_cast<const uint32_t *>(rsrc1) + r0;
-            const uint32_t *T2 = reinterpret_cast<const uint32_t *>(rsrc2 ? rsrc2 + r0 : nullptr);
-            if (staged) {
-                uint32_t *v1 = stage, *v2 = stage + P_max, *t1 = stage + 2 * P_max, *t2 = t1 + LOCKSTEP_STAGE_ROWS;
-                __syncthreads();  // the previous chunk's readers are done
-                const int32_t n4 = (it.n_slots + 3) & ~3;
-                for (int32_t x = threadIdx.x; x < n4; x += BATCH_THREADS) {
-                    v1[x] = x < it.n_slots ? (uint32_t)vsrc1[x] : INF;
-                    if (vsrc2) v2[x] = x < it.n_slots ? (uint32_t)vsrc2[x] : INF;
-                }
-                for (int32_t r = threadIdx.x; r < r1 - r0; r += BATCH_THREADS) {
-                    t1[r] = (uint32_t)rsrc1[r0 + r];
-                    if (rsrc2) t2[r] = (uint32_t)rsrc2[r0 + r];
-                }
-                __syncthreads();
-                S1 = v1;
-                S2 = vsrc2 ? v2 : nullptr;
-                T1 = t1;
-                T2 = rsrc2 ? t2 : nullptr;
-            }
-            if (it.op == BOP_ADD) {
-                add_relax_rows<U>(g, bg, r0, r1, S1, [&](int32_t i) { return T1[i - r0]; });
-            } else if (it.op == BOP_REMOVE) {
-                const FusedArgs fa = remove_args(bg, it);
-                const int32_t k = it.a;
-                detect_rows<U>(g, bg, fa, r0, r1, S1, nullptr, [&](int32_t i) {
-                    const uint32_t dik = T1[i - r0];
-                    return RowTests{i != k && dik < INF, false, dik, 0u};
-                });
-            } else if (mode == EDGE_DECREASE) {
-                dec_relax_rows<U>(g, bg, it.c, r0, r1, S1, S2, [&](int32_t i) { return T1[i - r0]; },
-                                  [&](int32_t i) { return T2[i - r0]; });
-            } else {
-                const FusedArgs fa = increase_args(g, bg);
-                const uint32_t w_old = (uint32_t)g.ctl->w_old;
-                const bool und = g.undirected != 0;
-                detect_rows<U>(g, bg, fa, r0, r1, S1, S2, [&](int32_t i) {
-                    // the pair tests of row_tests for an increase, from the copies
-                    const uint32_t cu = T1[i - r0], cv = T2[i - r0];
-                    RowTests r{cv < INF && cat(cu, w_old) == cv, false, cv, 0u};
-                    if (und) {
-                        r.t2 = cu < INF && cat(cv, w_old) == cu;
-                        r.a2 = cu;
-                    }
-                    return r;
-                });
-            }
+        if (threadIdx.x == 0) s_sweep = atomicAdd(&hdr->sweep_claim, 1);
+        __syncthreads();
+        for (int32_t c = s_sweep, pos = 0; c < baseB[G];) {
+            int32_t next = 0;
+            if (threadIdx.x == 0) next = atomicAdd(&hdr->sweep_claim, 1);
+            pos = chunk_graph(baseB, G, c, pos);  // claims only grow, so the search moves forward
+            const int32_t gi = orderB[pos];
+            const int32_t cg = c - baseB[pos];
+            sweep_chunk<U>(graphs[gi], items, s, cg, staged, P_max, stage);
+            __syncthreads();  // every thread has read s_sweep, and the staged vectors are done with
+            if (threadIdx.x == 0) s_sweep = next;
+            __syncthreads();
+            c = s_sweep;
         }
         // C: recompute of the flagged rows (removal, edge increase)
         const int32_t *baseC = baseB + (G + 1);
@@ -1385,7 +1406,10 @@ __global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch_lockstep(BatchHeader
             }
         }
         grid_barrier(hdr);
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(&hdr->heavy_claim, 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            atomicExch(&hdr->heavy_claim, 0);
+            atomicExch(&hdr->sweep_claim, 0);
+        }
         if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s + 2 < BATCH_PHASE_STAMPS)
             hdr->phase_ts[3 * s + 2] = wall_clock64();
     }
@@ -1472,7 +1496,7 @@ hipError_t launch_batch_lockstep(BatchHeader *hdr, const BatchGraph *graphs, con
     launch_fill(reinterpret_cast<int32_t *>(&hdr->bar_count), 1, 0, s);
     launch_fill(reinterpret_cast<int32_t *>(hdr->bar_group), 8 * 32, 0, s);
     launch_fill(&hdr->err, 1, 0, s);
-    launch_fill(&hdr->heavy_claim, 1, 0, s);
+    launch_fill(&hdr->heavy_claim, 2, 0, s);  // heavy_claim, sweep_claim
     launch_fill(reinterpret_cast<int32_t *>(hdr->work_ts), 2 * BATCH_PHASE_STAMPS, 0, s);
     const size_t lds = batch_lockstep_lds_bytes(P_max);
     void *args[] = {(void *)&hdr, (void *)&graphs, (void *)&items, (void *)&tables};

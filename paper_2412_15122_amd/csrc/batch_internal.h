@@ -49,7 +49,8 @@ struct BatchHeader {
     int32_t p_max;       // lockstep: largest pitch of the batch
     int32_t err;         // lockstep: set when a grid barrier wait timed out
     int32_t heavy_claim; // lockstep: next deferred heavy row to take (zero between steps)
-    int32_t pad0[24];
+    int32_t sweep_claim; // lockstep: next chunk of the row sweeps to take (zero between steps)
+    int32_t pad0[23];
     unsigned bar_count;  // lockstep grid barrier (each counter on its own 128-byte line)
     unsigned pad1[31];
     unsigned bar_gen;
@@ -61,7 +62,10 @@ struct BatchHeader {
 
 constexpr int BATCH_PHASE_STAMPS = 96;
 constexpr int BATCH_RECOMPUTE_ROWS = 16;  // rows per chunk of the lockstep recompute phase
-constexpr int BATCH_TABLES = 3;           // lockstep chunk tables per step: add vectors, sweeps, recompute
+// lockstep tables per step, G + 1 words each: chunk prefixes of the add
+// vectors, the sweeps and the recompute, then the graph order of the sweep
+// prefix (its position k -> graph index)
+constexpr int BATCH_TABLES = 4;
 
 // Work-group chunks of an add's vector phase: 256 columns of the new row,
 // then (directed) ADD_IN_ROWS rows of the new column.
