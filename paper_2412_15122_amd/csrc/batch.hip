@@ -227,9 +227,10 @@ __device__ __forceinline__ void add_out_cols(const DevGraph &g, const BatchGraph
 // l + 32, l + 48).  A wavefront takes 4 rows at a time, one per 16-lane
 // group, each lane's 4 gathers of the row in flight together; a row whose
 // value exceeds the list bound then gets an exhaustive scan by the whole
-// wavefront.
+// wavefront.  Values go to bg.vin and, when rows_out is set, to
+// rows_out[r - r0] as well.
 __device__ __forceinline__ void add_in_rows(const DevGraph &g, const BatchGraph &bg, const BatchItem &it, int32_t r0,
-                                            int32_t r1) {
+                                            int32_t r1, uint32_t *rows_out = nullptr) {
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     const int sub = lane >> 4, l16 = lane & 15;
     const int32_t p = it.a;
@@ -267,7 +268,11 @@ __device__ __forceinline__ void add_in_rows(const DevGraph &g, const BatchGraph 
             const uint32_t x_best = wave_min_plus_below(g.D + (int64_t)(rb + (b >> 4)) * g.ld, bg.wi, g.n_slots, cur);
             if (lane == b) best = min(best, x_best);
         }
-        if (r < r1 && l16 == 0) bg.vin[r] = live ? (int32_t)min(best, INF) : (int32_t)INF;
+        if (r < r1 && l16 == 0) {
+            const int32_t val = live ? (int32_t)min(best, INF) : (int32_t)INF;
+            bg.vin[r] = val;
+            if (rows_out) rows_out[r - r0] = (uint32_t)val;
+        }
     }
 }
 
@@ -1212,9 +1217,16 @@ __device__ inline void sweep_chunk(const BatchGraph &bg, const BatchItem *items,
             v1[x] = x < it.n_slots ? (uint32_t)vsrc1[x] : INF;
             if (vsrc2) v2[x] = x < it.n_slots ? (uint32_t)vsrc2[x] : INF;
         }
-        for (int32_t r = threadIdx.x; r < r1 - r0; r += BATCH_THREADS) {
-            t1[r] = (uint32_t)rsrc1[r0 + r];
-            if (rsrc2) t2[r] = (uint32_t)rsrc2[r0 + r];
+        if (it.op == BOP_ADD && !g.undirected) {
+            // a directed add's new column is computed here, for the chunk's
+            // rows, instead of in the add-vector phase: it reads the same
+            // rows' old values that the relaxation then streams
+            add_in_rows(g, bg, it, r0, r1, t1);
+        } else {
+            for (int32_t r = threadIdx.x; r < r1 - r0; r += BATCH_THREADS) {
+                t1[r] = (uint32_t)rsrc1[r0 + r];
+                if (rsrc2) t2[r] = (uint32_t)rsrc2[r0 + r];
+            }
         }
         __syncthreads();
         S1 = v1;

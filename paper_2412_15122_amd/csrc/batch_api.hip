@@ -485,7 +485,11 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
                 if (st < b->count[i]) {
                     const BatchItem &bi = bitems[b->begin[i] + st];
                     const int32_t rpc = batch_rows_per_chunk(bi.n_slots);
-                    if (bi.op == BOP_ADD) ca = add_vec_chunks(bi.n_slots, graphs[i]->kind == APSP_UNDIRECTED);
+                    // with staged sweeps the sweep chunks compute a directed
+                    // add's new column themselves (batch.hip, sweep_chunk)
+                    if (bi.op == BOP_ADD)
+                        ca = lockstep_stages_sweeps(P_max) ? add_out_chunks(bi.n_slots)
+                                                           : add_vec_chunks(bi.n_slots, graphs[i]->kind == APSP_UNDIRECTED);
                     if (bi.op != BOP_QUERY) cb = (bi.n_slots + rpc - 1) / rpc;
                     if (bi.op == BOP_REMOVE || bi.op == BOP_EDGE)
                         cc = (bi.n_slots + BATCH_RECOMPUTE_ROWS - 1) / BATCH_RECOMPUTE_ROWS;
