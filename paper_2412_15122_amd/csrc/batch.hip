@@ -314,6 +314,71 @@ __device__ __forceinline__ void add_relax_rows(const DevGraph &g, const BatchGra
         });
 }
 
+// Index-list edits four lists at a time (an epilogue edits up to a few
+// percent of all lists, each a round trip when done one by one): the
+// lists' entries, counts and bounds are read together, then each list is
+// edited from the registers with the single-list logic of
+// wave_list_insert / wave_list_purge.  The lists must differ.
+struct ListRegs {
+    int2 ent;  // entry `lane` (every list has NIN_L slots)
+    int cnt;
+    uint32_t beta;
+};
+
+__device__ __forceinline__ ListRegs list_load(const DevGraph &g, int32_t y) {
+    ListRegs r;
+    r.ent = g.nin[(int64_t)y * NIN_L + lane_id()];
+    r.cnt = g.nin_cnt[y];
+    r.beta = (uint32_t)g.nin_beta[y];
+    return r;
+}
+
+__device__ __forceinline__ void list_insert_regs(const DevGraph &g, int32_t y, const ListRegs &r, int32_t x,
+                                                 uint32_t w) {
+    const int lane = lane_id();
+    if (w >= INF || w >= r.beta) return;
+    const int cnt = r.cnt;
+    const int2 ent = lane < cnt ? r.ent : make_int2(0, (int)INF);
+    const int pos = __popcll(__ballot(lane < cnt && (uint32_t)ent.y <= w));
+    const int px = __shfl_up(ent.x, 1), py = __shfl_up(ent.y, 1);
+    const int ncnt = min(cnt + 1, NIN_L);
+    uint32_t dropped = INF;
+    if (cnt == NIN_L) dropped = (pos < NIN_L) ? (uint32_t)__shfl(ent.y, NIN_L - 1) : w;
+    const int2 ne = lane < pos ? ent : (lane == pos ? make_int2(x, (int)w) : make_int2(px, py));
+    if (lane < ncnt) g.nin[(int64_t)y * NIN_L + lane] = ne;
+    if (lane == 0) {
+        g.nin_cnt[y] = ncnt;
+        if (cnt == NIN_L) g.nin_beta[y] = (int32_t)min(r.beta, dropped);
+    }
+}
+
+__device__ __forceinline__ void list_purge_regs(const DevGraph &g, int32_t y, const ListRegs &r, int32_t x) {
+    const int lane = lane_id();
+    const int cnt = r.cnt;
+    const int2 ent = lane < cnt ? r.ent : make_int2(0, (int)INF);
+    const unsigned long long m = __ballot(lane < cnt && ent.x == x);
+    if (m == 0) return;
+    const int pos = __ffsll((long long)m) - 1;
+    const int nx = __shfl_down(ent.x, 1), ny = __shfl_down(ent.y, 1);
+    int2 *L = g.nin + (int64_t)y * NIN_L;
+    if (lane >= pos && lane < cnt - 1) L[lane] = make_int2(nx, ny);
+    if (lane == cnt - 1) L[lane] = make_int2(0, (int)INF);
+    if (lane == 0) g.nin_cnt[y] = cnt - 1;
+}
+
+// The next (up to) four set bits of the wave-uniform mask m as lists
+// y0 + bit (-1 where none is left).
+__device__ __forceinline__ void take4(unsigned long long &m, int32_t y0, int32_t (&yq)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        yq[q] = -1;
+        if (m) {
+            yq[q] = y0 + __ffsll((long long)m) - 1;
+            m &= m - 1;
+        }
+    }
+}
+
 // Row and column p of D, A (and A^T), the id, the rank, and p's out-edges in
 // every other node's light list.
 __device__ __forceinline__ void add_epilogue(const DevGraph &g, const BatchGraph &bg, const BatchItem &it) {
@@ -351,10 +416,20 @@ __device__ __forceinline__ void add_epilogue(const DevGraph &g, const BatchGraph
         const int32_t y = y0 + lane_id();
         const bool cand = y < n && y != p && g.id_of_slot[y] >= 0 && (uint32_t)wo[y] < (uint32_t)g.nin_beta[y];
         unsigned long long m = __ballot(cand);
-        while (m) {
-            const int b = __ffsll((long long)m) - 1;
-            m &= m - 1;
-            wave_list_insert(g, y0 + b, p, (uint32_t)wo[y0 + b]);
+        while (m) {  // wave-uniform
+            int32_t yq[4];
+            take4(m, y0, yq);
+            ListRegs r[4];
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (yq[q] >= 0) {
+                    r[q] = list_load(g, yq[q]);
+                    w[q] = (uint32_t)wo[yq[q]];
+                }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (yq[q] >= 0) list_insert_regs(g, yq[q], r[q], p, w[q]);
         }
     }
     __syncthreads();
@@ -674,10 +749,16 @@ __device__ __forceinline__ void remove_epilogue(const DevGraph &g, const BatchGr
             cand = c > 0 && wk < INF && wk <= (uint32_t)g.nin[(int64_t)y * NIN_L + c - 1].y;
         }
         unsigned long long m = __ballot(cand);
-        while (m) {
-            const int b = __ffsll((long long)m) - 1;
-            m &= m - 1;
-            wave_list_purge(g, y0 + b, k);
+        while (m) {  // wave-uniform
+            int32_t yq[4];
+            take4(m, y0, yq);
+            ListRegs r[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (yq[q] >= 0) r[q] = list_load(g, yq[q]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (yq[q] >= 0) list_purge_regs(g, yq[q], r[q], k);
         }
     }
     if (tid < 64) {
