@@ -1430,13 +1430,16 @@ __global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch_lockstep(BatchHeader
             grid_barrier(hdr);
             if (blockIdx.x == 0 && threadIdx.x == 0 && 3 * s + 1 < BATCH_PHASE_STAMPS)
                 hdr->phase_ts[3 * s + 1] = wall_clock64();
-            for (int32_t c = blockIdx.x, gi = 0; c < baseC[G]; c += gridDim.x) {
-                gi = chunk_graph(baseC, G, c, gi);
-                const BatchGraph &bg = graphs[gi];
+            // chunks round robin in the sweep phase's graph order (removals
+            // largest first, then the edge updates)
+            const int32_t *orderC = baseB + 2 * (G + 1);
+            for (int32_t c = blockIdx.x, pos = 0; c < baseC[G]; c += gridDim.x) {
+                pos = chunk_graph(baseC, G, c, pos);
+                const BatchGraph &bg = graphs[orderC[pos]];
                 const BatchItem it = items[bg.item_begin + s];
                 DevGraph g = bg.g;
                 g.n_slots = it.n_slots;
-                const int32_t r0 = (c - baseC[gi]) * BATCH_RECOMPUTE_ROWS;
+                const int32_t r0 = (c - baseC[pos]) * BATCH_RECOMPUTE_ROWS;
                 const int32_t r1 = min(r0 + BATCH_RECOMPUTE_ROWS, it.n_slots);
                 // each wavefront uses only its own lists and need bitmap in LDS
                 uint32_t *light = lockstep_light_rows(P_max) ? stage + lockstep_light_offset(P_max) : nullptr;

@@ -466,15 +466,16 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
         // lockstep: step s applies item s of every graph; per step, the chunk
         // prefixes of the add-vector phase (additions), the sweep phase
         // (every kind but a query) and the recompute phase (removals and
-        // edge updates), and the order of the sweep prefix: additions and
-        // removals (which always sweep) by falling byte count, then the edge
-        // updates (which sweep only when phase A finds the edge matters)
+        // edge updates), and the order of the sweep and recompute prefixes:
+        // additions and removals (which always sweep) by falling byte count,
+        // then the edge updates (which sweep only when phase A finds the edge
+        // matters)
         int32_t steps = 0;
         for (int32_t i : b->active) steps = std::max(steps, b->count[i]);
         auto *tab = reinterpret_cast<int32_t *>(b->stage + b->L.tables);
         const int32_t G1 = n_active + 1;
         std::vector<int64_t> sweep_key(n_active);
-        std::vector<int32_t> sweep_cb(n_active);
+        std::vector<int32_t> sweep_cb(n_active), sweep_cc(n_active);
         for (int32_t st = 0; st < steps; ++st) {
             int32_t *ta = tab + (size_t)st * BATCH_TABLES * G1, *tb = ta + G1, *tc = tb + G1, *td = tc + G1;
             ta[0] = tb[0] = tc[0] = 0;
@@ -496,14 +497,17 @@ apsp_status apsp_batch_run(apsp_batch *b, apsp_graph *const *graphs, int32_t num
                     if (bi.op == BOP_ADD || bi.op == BOP_REMOVE) key = (int64_t)bi.n_slots * bi.n_slots;
                 }
                 ta[ai + 1] = ta[ai] + ca;
-                tc[ai + 1] = tc[ai] + cc;
                 sweep_cb[ai] = cb;
+                sweep_cc[ai] = cc;
                 sweep_key[ai] = key;
                 td[ai] = ai;
             }
             td[n_active] = 0;
             std::stable_sort(td, td + n_active, [&](int32_t x, int32_t y) { return sweep_key[x] > sweep_key[y]; });
-            for (int32_t k = 0; k < n_active; ++k) tb[k + 1] = tb[k] + sweep_cb[td[k]];
+            for (int32_t k = 0; k < n_active; ++k) {
+                tb[k + 1] = tb[k] + sweep_cb[td[k]];
+                tc[k + 1] = tc[k] + sweep_cc[td[k]];
+            }
         }
         hdr->steps = steps;
         b->last_steps = steps;

@@ -64,7 +64,7 @@ constexpr int BATCH_PHASE_STAMPS = 96;
 constexpr int BATCH_RECOMPUTE_ROWS = 16;  // rows per chunk of the lockstep recompute phase
 // lockstep tables per step, G + 1 words each: chunk prefixes of the add
 // vectors, the sweeps and the recompute, then the graph order of the sweep
-// prefix (its position k -> graph index)
+// and recompute prefixes (their position k -> graph index)
 constexpr int BATCH_TABLES = 4;
 
 // Work-group chunks of an add's vector phase: 256 columns of the new row,
