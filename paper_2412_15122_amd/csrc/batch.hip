@@ -1454,14 +1454,15 @@ __global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch_lockstep(BatchHeader
             grid_barrier(hdr);
             // C2: the deferred heavy rows, one work-group each, taken from a
             // shared counter; a claim maps to (graph, row) through a
-            // block-wide scan of the graphs' heavy-row counts
+            // block-wide scan of the graphs' heavy-row counts, in the same
+            // graph order (the largest removals' rows are taken first)
             for (;;) {
                 if (threadIdx.x == 0) s_claim = atomicAdd(&hdr->heavy_claim, 1);
                 __syncthreads();
                 const int32_t t = s_claim;
                 int32_t found_g = -1, found_j = 0, base = 0;
                 for (int32_t g0 = 0; g0 < G && found_g < 0; g0 += BATCH_THREADS) {
-                    const int32_t gi = g0 + threadIdx.x;
+                    const int32_t gi = g0 + threadIdx.x < G ? orderC[g0 + threadIdx.x] : G;
                     int32_t hc = 0;
                     if (gi < G) {
                         const BatchGraph &bq = graphs[gi];
